@@ -1,0 +1,277 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these retypes the oracle's formulas: each compares it with a
+printed value, a closed form, a library routine on an equivalent problem,
+an invariant, or a brute force written independently in Python.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.spatial.distance as ssd
+
+import workloads
+from tests import bruteforce as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------- ranks ----
+
+def test_sortperm_matches_paper_example(orc):
+    """Section 4.5 prints sortperm([7,3,8,4,2]) = [5,2,4,1,3] (1-based)."""
+    rows = dict((r[0], [int(x) for x in r[1:]]) for r in _golden_rows("sortperm_example.txt"))
+    got = orc.sortperm(rows["v"])
+    assert [int(x) + 1 for x in got] == rows["sortperm"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_edge_order_equals_stable_library_sort(orc, seed):
+    """Ranks = stable sort on q, ties by pair index (lexsort on (q, i, j))."""
+    c = workloads.lattice_cloud(seed, 20 + seed, side=3)  # many exact ties
+    q = orc.sqdist(c.points)
+    i, j = orc.pair_lists(c.n)
+    ref = np.lexsort((j, i, q))
+    assert np.array_equal(orc.sortperm(q), ref)
+    assert np.array_equal(orc.sortperm(q), np.argsort(q, kind="stable"))
+
+
+# ------------------------------------------------------------ distances ----
+
+@pytest.mark.parametrize("dtype,lo,hi", [(np.int8, -128, 127), (np.int16, -3000, 3000), (np.int32, 0, 1023)])
+def test_sqdist_three_ways(orc, dtype, lo, hi):
+    """Direct sum, the Gram identity |x|^2+|y|^2-2<x,y>, and scipy agree."""
+    rng = np.random.default_rng(7)
+    pts = rng.integers(lo, hi + 1, (23, 5)).astype(dtype)
+    q = orc.sqdist(pts)
+    x = pts.astype(np.int64)
+    g = x @ x.T
+    nrm = np.diag(g)
+    i, j = orc.pair_lists(len(pts))
+    gram = nrm[i] + nrm[j] - 2 * g[i, j]
+    assert np.array_equal(q, gram)
+    sp = ssd.pdist(x.astype(np.float64), "sqeuclidean")
+    assert np.array_equal(q, sp.astype(np.int64))
+    bd = bf.sqdist_pairs(pts)
+    assert [bd[(a, b)] for a, b in zip(i, j)] == list(q)
+
+
+def test_sqdist_extreme_int8(orc):
+    """-128 against 127 in every coordinate: q = d * 255^2 exactly."""
+    d = 64
+    pts = np.array([[-128] * d, [127] * d], np.int8)
+    assert orc.sqdist(pts).tolist() == [d * 255 * 255]
+
+
+# ------------------------------------------------------------ threshold ----
+
+def test_num_kept_closed_forms(orc):
+    """K = floor(num * E / den): 20% of C(1000,2) and 10% of C(4000,2)."""
+    assert orc.num_kept(("fraction", 20, 100), np.zeros(499500, np.int64)) == 99900
+    assert orc.num_kept(("fraction", 10, 100), np.zeros(7998000, np.int64)) == 799800
+    assert orc.num_kept(("full", 0, 1), np.zeros(2016, np.int64)) == 2016
+    assert orc.num_kept(("fraction", 1, 3), np.zeros(10, np.int64)) == 3  # floor(10/3)
+    assert orc.num_kept(("count", 7, 1), np.zeros(10, np.int64)) == 7
+    with pytest.raises(ValueError):
+        orc.num_kept(("count", 11, 1), np.zeros(10, np.int64))
+    with pytest.raises(ValueError):
+        orc.num_kept(("fraction", 101, 100), np.zeros(10, np.int64))
+
+
+def test_sqdist_threshold_is_strict(orc):
+    """Edges join points closer than the threshold (Section 2.1): q < tau."""
+    q = np.array([4, 1, 4, 9, 0, 4], np.int64)
+    assert orc.num_kept(("sqdist", 4, 0), q) == 2
+    assert orc.num_kept(("sqdist", 5, 0), q) == 5
+    assert orc.num_kept(("sqdist", 0, 0), q) == 0
+
+
+# ------------------------------------------------------------ triangles ----
+
+def _K_of(thr):
+    kind, num, den = thr
+
+    def f(qs):
+        E = len(qs)
+        if kind == "full":
+            return E
+        if kind == "count":
+            return num
+        if kind == "fraction":
+            return (num * E) // den
+        return sum(1 for v in qs if v < num)
+
+    return f
+
+
+CASES = [
+    workloads.uniform_cloud(1, 9, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(2, 11, 3, thr=("fraction", 40, 100)),
+    workloads.lattice_cloud(3, 12, side=3, thr=("fraction", 50, 100)),   # duplicates and ties
+    workloads.lattice_cloud(4, 10, side=2, thr=("count", 17, 1)),
+    workloads.uniform_cloud(5, 12, 4, thr=("sqdist", 20000, 0)),
+    workloads.uniform_cloud(6, 3, 1, thr=("full", 0, 1)),
+    workloads.uniform_cloud(7, 2, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(8, 1, 2, thr=("full", 0, 1)),
+    workloads.lattice_cloud(9, 8, side=1, thr=("fraction", 60, 100)),    # all points equal
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c.name + "_" + c.thr[0])
+def test_filtration_matches_bruteforce(orc, case):
+    kept, rank, tris, _ = bf.filtration(case.points, _K_of(case.thr))
+    f = orc.build(case.points, case.thr)
+    assert f.K == len(kept)
+    assert list(zip(f.ei.tolist(), f.ej.tolist())) == kept
+    assert [tuple(r) for r in f.tris.tolist()] == tris
+
+
+@pytest.mark.parametrize("n", [3, 4, 10, 64])
+def test_full_threshold_counts_are_binomials(orc, n):
+    """At the infinite threshold every pair and triple is a simplex."""
+    c = workloads.uniform_cloud(n, n, 2, dtype=np.int32, lo=0, hi=1023)
+    f = orc.build(c.points, ("full", 0, 1))
+    assert (f.K, f.T) == (math.comb(n, 2), math.comb(n, 3))
+
+
+def test_plain64_counts(orc):
+    f = orc.build(*_cloud_args(workloads.plain64()))
+    assert f.counts == (64, 2016, 41664)
+
+
+def _cloud_args(c):
+    return c.points, c.thr
+
+
+@pytest.mark.parametrize("row", _golden_rows("complex_sizes.txt"), ids=lambda r: r[0])
+def test_paper_complex_sizes(orc, row):
+    """Table 5's size of complex = n + C(n,2) + C(n,3) at the infinite threshold,
+    to the paper's two significant figures; counts come from the oracle's own
+    triangle test on a random cloud of that many points."""
+    name, n, mant, expo = row[0], int(row[1]), float(row[2]), int(row[3])
+    c = workloads.uniform_cloud(n, n, 3)
+    f = orc.build(c.points, ("full", 0, 1), list_triangles=False)
+    size = f.n + f.K + f.T
+    assert round(size / 10 ** expo, 1) == mant
+
+
+@pytest.mark.parametrize("seed,thr", [(11, ("fraction", 30, 100)), (12, ("fraction", 8, 100)), (13, ("count", 500, 1))])
+def test_triangle_count_by_adjacency_cube(orc, seed, thr):
+    """T = trace(A^3)/6 and, per vertex, (A^3)_vv / 2 triangles contain v."""
+    c = workloads.uniform_cloud(seed, 120, 3, thr=thr)
+    f = orc.build(c.points, c.thr)
+    A = (f.R >= 0).astype(np.int64)
+    A3 = A @ A @ A
+    assert f.T == np.trace(A3) // 6
+    per_vertex = np.zeros(f.n, np.int64)
+    for col in (1, 2, 3):
+        np.add.at(per_vertex, f.tris[:, col], 1)
+    assert np.array_equal(per_vertex, np.diag(A3) // 2)
+
+
+def test_triangles_per_value_partition(orc):
+    c = workloads.noisy_circle(n=300)
+    f = orc.build(c.points, c.thr)
+    cnt = orc.triangles_per_value(f)
+    assert cnt.sum() == f.T
+    assert np.array_equal(cnt, np.bincount(f.tris[:, 0], minlength=f.K))
+    for r in (0, f.K // 3, f.K - 1):
+        rows = orc.triangles_of_value(f, r)
+        assert np.array_equal(rows, f.tris[f.tris[:, 0] == r])
+
+
+# ------------------------------------------------------------ reduction ----
+
+def _pairs_in_total_order(f, p):
+    """(birth, death) pairs and essential births as total-order indices."""
+    order = bf.total_order(f.n, list(zip(f.ei.tolist(), f.ej.tolist())), [tuple(t) for t in f.tris.tolist()])
+    pos = {s: i for i, s in enumerate(order)}
+    vid = lambda v: pos[("v", (v,))]
+    eid = lambda r: pos[("e", (int(f.ei[r]), int(f.ej[r])))]
+    tid = lambda t: pos[("t", tuple(int(x) for x in f.tris[t, 1:]))]
+    pairs = {0: [], 1: []}
+    for r in np.nonzero(p.e_low >= 0)[0]:
+        pairs[0].append((vid(int(p.e_low[r])), eid(r)))
+    for t in np.nonzero(p.t_low >= 0)[0]:
+        pairs[1].append((eid(int(p.t_low[t])), tid(t)))
+    e0, e1, e2 = p.essential()
+    ess = {0: [vid(v) for v in e0], 1: [eid(r) for r in e1], 2: [tid(t) for t in e2]}
+    return len(order), pairs, ess
+
+
+@pytest.mark.parametrize("case", [
+    workloads.uniform_cloud(21, 6, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(22, 7, 2, thr=("fraction", 70, 100)),
+    workloads.lattice_cloud(23, 7, side=3, thr=("fraction", 60, 100)),
+    workloads.uniform_cloud(24, 6, 3, thr=("count", 9, 1)),
+], ids=lambda c: c.name)
+@pytest.mark.parametrize("method", ["homology", "cohomology"])
+def test_reduction_matches_bruteforce_persistent_betti(orc, case, method):
+    """Pairs reproduce every persistent Betti number rank(H_k(X_s) -> H_k(X_t))."""
+    f = orc.build(case.points, case.thr)
+    p = orc.reduce(f, method)
+    N, pairs, ess = _pairs_in_total_order(f, p)
+    _, beta = bf.persistent_betti(f.n, list(zip(f.ei.tolist(), f.ej.tolist())), [tuple(t) for t in f.tris.tolist()])
+    got = bf.betti_from_pairs(N, pairs, ess)
+    for k in (0, 1, 2):
+        assert got[k] == beta[k], f"dimension {k}"
+
+
+@pytest.mark.parametrize("seed,thr", [(31, ("fraction", 15, 100)), (32, ("full", 0, 1)), (33, ("fraction", 40, 100))])
+def test_homology_and_cohomology_give_same_pivots(orc, seed, thr):
+    """Section 2.2.2: the anti-transpose yields the same pivot pairs."""
+    c = workloads.uniform_cloud(seed, 40, 3, thr=thr)
+    f = orc.build(c.points, c.thr)
+    a = orc.reduce(f, "homology", clear=False)
+    b = orc.reduce(f, "homology", clear=True)
+    h = orc.reduce(f, "cohomology")
+    for x in (b, h):
+        assert np.array_equal(a.e_low, x.e_low)
+        assert np.array_equal(a.t_low, x.t_low)
+
+
+@pytest.mark.parametrize("seed", [41, 42, 43])
+def test_h0_deaths_are_kruskal_edges(orc, seed):
+    c = workloads.uniform_cloud(seed, 150, 3, thr=("fraction", 5, 100))
+    f = orc.build(c.points, c.thr)
+    p = orc.reduce(f, "cohomology")
+    deaths = np.nonzero(p.e_low >= 0)[0].tolist()
+    assert deaths == bf.kruskal_deaths(f.n, list(zip(f.ei.tolist(), f.ej.tolist())))
+    assert p.betti()[0] == f.n - len(deaths)
+
+
+@pytest.mark.parametrize("seed,thr", [(51, ("fraction", 12, 100)), (52, ("fraction", 35, 100)), (53, ("sqdist", 900, 0))])
+def test_euler_characteristic(orc, seed, thr):
+    """n - K + T = beta0 - beta1 + beta2 (essential classes of the final complex)."""
+    c = workloads.uniform_cloud(seed, 90, 2, thr=thr)
+    f = orc.build(c.points, c.thr)
+    b0, b1, b2 = orc.reduce(f, "cohomology").betti()
+    assert f.n - f.K + f.T == b0 - b1 + b2
+
+
+def test_full_threshold_betti(orc):
+    """The 2-skeleton of a full simplex on n vertices: beta = (1, 0, C(n-1,3))."""
+    f = orc.build(*_cloud_args(workloads.plain64()))
+    assert orc.reduce(f, "cohomology").betti() == (1, 0, math.comb(63, 3))
+
+
+def test_noisy_circle_has_one_dominant_h1_bar(orc):
+    """A noisy circle at the 20th percentile: one essential H1 class, every
+    finite H1 bar shorter than a tenth of the kept ranks."""
+    c = workloads.noisy_circle(n=400)
+    f = orc.build(c.points, c.thr)
+    p = orc.reduce(f, "cohomology")
+    assert p.betti()[1] == 1
+    finite = [d - b for dim, b, d in orc.barcode(f, p) if dim == 1 and d != np.iinfo(np.int64).max]
+    assert max(finite, default=0) < f.K // 10
