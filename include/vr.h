@@ -1,0 +1,161 @@
+/*
+ * vr.h -- C ABI of the MI355X (gfx950) Vietoris-Rips filtration front end.
+ *
+ * One call builds the filtered Vietoris-Rips complex of a point cloud up to
+ * dimension 2 on the GPU: exact squared distances of all pairs, the integer
+ * rank of every edge, the threshold, every solid triangle valued at its
+ * largest edge rank, and all simplices in filtration order.
+ *
+ * The problem statement follows arXiv:1809.04424:
+ *   - Section 3 (the eirene call): a point cloud whose rows are points (or a
+ *     distance matrix; not supported here) plus an upper distance limit in,
+ *     an integer rank matrix ("symmat") and integer filtration values out;
+ *   - Section 2.1: an edge joins two points closer than the threshold, a
+ *     solid triangle exists once its three edges exist;
+ *   - Section 4.5: edge ranks are the sortperm of the distances;
+ *   - Section 4.4: the library is reached through plain extern "C" host
+ *     functions taking pointers and lengths.
+ *
+ * Conventions
+ *   - Every index is 0-based (the paper's Julia is 1-based).
+ *   - Squared distance q_ij = sum_c (x_ic - x_jc)^2, exact in integers; it
+ *     orders edges exactly as the distance does.
+ *   - Edge order: ascending (q, i, j) with i < j.  The rank r of an edge is
+ *     its 0-based position in that order; ranks are unique, so every output
+ *     is unique and bit-exact comparison is well defined.
+ *   - Kept edges are the ranks r < K.  Vertices have filtration value -1 (they
+ *     precede every edge); edge r has value r; a triangle has the value of its
+ *     largest edge.  The whole filtration is ordered by (value, dimension,
+ *     vertex tuple), so faces precede cofaces.
+ *   - Device pointers are HIP device memory of the current device.
+ *
+ * Thread safety: calls on different streams (and different results) may run
+ * concurrently from different host threads.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define VR_API __attribute__((visibility("default")))
+#else
+#define VR_API
+#endif
+
+/* Status codes.  Every entry point that can fail returns one of these. */
+typedef enum {
+    VR_OK = 0,
+    VR_EINVAL = -1, /* bad argument: null pointer, d < 1, unknown dtype/kind, bad threshold */
+    VR_ENOMEM = -2, /* a device allocation failed (nothing is leaked) */
+    VR_E2BIG = -3,  /* n > VR_MAX_POINTS or K > VR_MAX_EDGES: outside the key packing */
+    VR_EHIP = -4,   /* a HIP runtime call failed */
+    VR_ERANGE = -5  /* some squared distance does not fit in 32 bits unsigned */
+} vr_status;
+
+/* Coordinate types (signed integers). */
+enum { VR_I8 = 1, VR_I16 = 2, VR_I32 = 3 };
+
+/* Threshold kinds (the paper's upper limit, Section 3; infinite by default,
+ * Section 5).  E = n(n-1)/2 is the number of vertex pairs.
+ *   VR_THR_FULL     : K = E (every pair is an edge)
+ *   VR_THR_COUNT    : K = thr_num, 0 <= thr_num <= E
+ *   VR_THR_FRACTION : K = floor(thr_num * E / thr_den), 0 <= thr_num <= thr_den, thr_den > 0
+ *                     (the p-th percentile of edge ranks is thr_num/thr_den = p/100)
+ *   VR_THR_SQDIST   : keep q < thr_num (strict: "closer than"), K = #{q < thr_num} */
+enum { VR_THR_FULL = 0, VR_THR_COUNT = 1, VR_THR_FRACTION = 2, VR_THR_SQDIST = 3 };
+
+/* Request flags. */
+enum {
+    VR_COUNT_ONLY = 1u, /* compute (n, K, T) and the edges; do not write triangles */
+    VR_TIMING = 2u      /* record per-stage HIP events (see vr_query_stage_ms) */
+};
+
+/* Limits of the packed triangle key: 13 bits per vertex, 24 bits of value. */
+#define VR_MAX_POINTS 8192
+#define VR_MAX_EDGES (1 << 24)
+
+/* Optional device allocator, e.g. a framework's caching allocator.
+ * alloc returns device memory usable on `stream` (NULL on failure); free
+ * releases it in stream order.  With no allocator the library uses
+ * hipMallocAsync / hipFreeAsync on the stream (default memory pool). */
+typedef struct vr_allocator {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
+    void *ctx;
+} vr_allocator;
+
+/* One build request.  `points` is borrowed for the duration of vr_build only. */
+typedef struct vr_request {
+    const void *points; /* device pointer, row-major n x d, dtype coordinates (rows are points) */
+    int64_t n, d;       /* 0 <= n <= VR_MAX_POINTS, d >= 1 */
+    int32_t dtype;      /* VR_I8, VR_I16 or VR_I32 */
+    int32_t thr_kind;   /* VR_THR_* */
+    int64_t thr_num, thr_den;
+    int32_t maxdim;     /* 0: vertices only, 1: up to edges, 2: up to triangles */
+    uint32_t flags;     /* VR_COUNT_ONLY | VR_TIMING */
+    const vr_allocator *alloc; /* NULL: hipMallocAsync on the stream */
+} vr_request;
+
+/* Result handle, owned by the library until vr_free.  Fields are read-only. */
+typedef struct vr_result {
+    int64_t n_vertices;  /* n */
+    int64_t n_edges;     /* K */
+    int64_t n_triangles; /* T */
+    /* device, 2*K: edge r joins edge_ij[2r] < edge_ij[2r+1]; rank order */
+    const uint32_t *edge_ij;
+    /* device, K: squared length of edge r (non-decreasing in r) */
+    const int64_t *edge_q;
+    /* device, T: triangle keys v<<39 | i<<26 | j<<13 | k, i<j<k, v = largest
+     * edge rank; ascending, which is filtration order (NULL with VR_COUNT_ONLY) */
+    const uint64_t *tri_key;
+} vr_result;
+
+/*
+ * Build the filtration of one point cloud.
+ * Enqueues all work on `stream` (a hipStream_t; NULL = the null stream) and
+ * synchronises that stream once, to read the triangle count.  On VR_OK,
+ * *out receives a new handle whose device arrays are complete once `stream`
+ * reaches the end of this call's work (stream order).  On error *out is not
+ * written and nothing is leaked.
+ */
+VR_API int vr_build(const vr_request *req, void *stream, vr_result **out);
+
+/* counts[0..2] = (n, K, T).  Host only: no device call, no synchronisation. */
+VR_API int vr_query_counts(const vr_result *res, int64_t counts[3]);
+
+/*
+ * Per-stage GPU times (milliseconds) of a build made with VR_TIMING, in the
+ * order of vr_stage_name(0..).  Waits for the build's last event.
+ * Returns the number of stages written (<= cap), or a negative vr_status.
+ */
+VR_API int vr_query_stage_ms(const vr_result *res, float *ms, int cap);
+
+/* Name of stage s (static string), or NULL past the last stage. */
+VR_API const char *vr_stage_name(int s);
+
+/* Releases the handle's device memory in stream order on `stream`, then the
+ * handle.  NULL-safe. */
+VR_API void vr_free(vr_result *res, void *stream);
+
+/* Device bytes a build of this shape needs at most, besides its outputs
+ * (edges 16 B each, triangles 8 B each).  For admission by HBM footprint.
+ * Returns -1 for shapes vr_build would reject. */
+VR_API int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind);
+
+/* Static description of a status code. */
+VR_API const char *vr_status_string(int status);
+
+/* Library version, e.g. 100 for 0.1.0. */
+VR_API int vr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

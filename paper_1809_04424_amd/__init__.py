@@ -1,0 +1,270 @@
+"""Python binding of the gfx950 Vietoris-Rips filtration library (libvrhip.so).
+
+Argument marshalling only: every step of the build runs in the library's HIP
+kernels.  PyTorch supplies device memory (through the library's allocator
+hook, so outputs are ordinary torch tensors) and the stream.  There is no CPU
+fallback: importing works without the library, but every call raises until
+``build.py`` has produced ``libvrhip.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvrhip.so")
+
+VR_OK, VR_EINVAL, VR_ENOMEM, VR_E2BIG, VR_EHIP, VR_ERANGE = 0, -1, -2, -3, -4, -5
+VR_I8, VR_I16, VR_I32 = 1, 2, 3
+VR_THR = {"full": 0, "count": 1, "fraction": 2, "sqdist": 3}
+VR_COUNT_ONLY, VR_TIMING = 1, 2
+VR_MAX_POINTS = 8192
+VR_MAX_EDGES = 1 << 24
+
+# C symbols declared in include/vr.h
+SYMBOLS = ("vr_build", "vr_query_counts", "vr_query_stage_ms", "vr_stage_name", "vr_free",
+           "vr_workspace_bytes", "vr_status_string", "vr_version")
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class VrAllocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class VrRequest(ctypes.Structure):
+    _fields_ = [
+        ("points", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int64),
+        ("dtype", ctypes.c_int32),
+        ("thr_kind", ctypes.c_int32),
+        ("thr_num", ctypes.c_int64),
+        ("thr_den", ctypes.c_int64),
+        ("maxdim", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("alloc", ctypes.POINTER(VrAllocator)),
+    ]
+
+
+class VrResult(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_int64),
+        ("n_edges", ctypes.c_int64),
+        ("n_triangles", ctypes.c_int64),
+        ("edge_ij", ctypes.c_void_p),
+        ("edge_q", ctypes.c_void_p),
+        ("tri_key", ctypes.c_void_p),
+    ]
+
+
+class VrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded libvrhip.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1809_04424_amd/build.py (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.vr_build.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_void_p, ctypes.POINTER(ctypes.POINTER(VrResult))]
+        L.vr_build.restype = ctypes.c_int
+        L.vr_query_counts.argtypes = [ctypes.POINTER(VrResult), ctypes.POINTER(ctypes.c_int64)]
+        L.vr_query_counts.restype = ctypes.c_int
+        L.vr_query_stage_ms.argtypes = [ctypes.POINTER(VrResult), ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+        L.vr_query_stage_ms.restype = ctypes.c_int
+        L.vr_stage_name.argtypes = [ctypes.c_int]
+        L.vr_stage_name.restype = ctypes.c_char_p
+        L.vr_free.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p]
+        L.vr_free.restype = None
+        L.vr_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+        L.vr_workspace_bytes.restype = ctypes.c_int64
+        L.vr_status_string.argtypes = [ctypes.c_int]
+        L.vr_status_string.restype = ctypes.c_char_p
+        L.vr_version.argtypes = []
+        L.vr_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().vr_status_string(code).decode()
+
+
+def stage_names():
+    L = lib()
+    out, s = [], 0
+    while True:
+        p = L.vr_stage_name(s)
+        if not p:
+            return out
+        out.append(p.decode())
+        s += 1
+
+
+def workspace_bytes(n: int, d: int, dtype: int = VR_I8, thr_kind: str = "fraction") -> int:
+    return int(lib().vr_workspace_bytes(n, d, dtype, VR_THR[thr_kind]))
+
+
+class _TorchAllocator:
+    """Allocator hook: the library's device memory comes from torch's caching
+    allocator on the build's stream, so outputs are torch tensors."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+        self._a = _ALLOC_FN(self._alloc)
+        self._f = _FREE_FN(self._free)
+        self.struct = VrAllocator(self._a, self._f, None)
+
+    def _alloc(self, nbytes, stream, ctx):
+        import torch
+
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory: the library reports VR_ENOMEM
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, ptr, nbytes, stream, ctx):
+        self.live.pop(ptr, None)
+
+
+_allocators = {}
+
+
+def _allocator_for(device):
+    a = _allocators.get(device)
+    if a is None:
+        a = _allocators[device] = _TorchAllocator(device)
+    return a
+
+
+def _dtype_code(t):
+    import torch
+
+    m = {torch.int8: VR_I8, torch.int16: VR_I16, torch.int32: VR_I32}
+    if t.dtype not in m:
+        raise TypeError("points must be int8, int16 or int32")
+    return m[t.dtype]
+
+
+class Result:
+    """Handle of one build.  Device arrays are torch tensor views of the
+    library's output block; they stay valid while any of them is referenced."""
+
+    def __init__(self, ptr, alloc: _TorchAllocator, stream):
+        self._ptr = ptr
+        self._alloc = alloc
+        self._stream = stream
+        r = ptr.contents
+        self.n, self.K, self.T = int(r.n_vertices), int(r.n_edges), int(r.n_triangles)
+        self._block = alloc.live.get(r.edge_q) if r.edge_q else None
+        self._off_ij = (r.edge_ij - r.edge_q) if r.edge_q else 0
+        self._off_tri = (r.tri_key - r.edge_q) if r.tri_key else 0
+        self._tri = r.tri_key
+
+    @property
+    def counts(self):
+        return (self.n, self.K, self.T)
+
+    def _view(self, off_bytes, count, dtype, itemsize):
+        import torch
+
+        if self._block is None or count == 0:
+            return torch.empty(0, dtype=dtype, device=self._alloc.device)
+        return self._block[off_bytes: off_bytes + count * itemsize].view(dtype)
+
+    def edge_q(self):
+        """int64 (K,) squared lengths of the kept edges in rank order."""
+        import torch
+
+        return self._view(0, self.K, torch.int64, 8)
+
+    def edge_ij(self):
+        """int32 (K, 2) endpoints i < j of the kept edges in rank order."""
+        import torch
+
+        return self._view(self._off_ij, 2 * self.K, torch.int32, 4).view(-1, 2)
+
+    def tri_key(self):
+        """int64 (T,) packed triangle keys v<<39 | i<<26 | j<<13 | k, ascending."""
+        import torch
+
+        if not self._tri:
+            return torch.empty(0, dtype=torch.int64, device=self._alloc.device)
+        return self._view(self._off_tri, self.T, torch.int64, 8)
+
+    def stage_ms(self):
+        """{stage: ms} of a build made with timing=True."""
+        buf = (ctypes.c_float * 32)()
+        k = lib().vr_query_stage_ms(self._ptr, buf, 32)
+        if k < 0:
+            raise VrError(k, status_string(k))
+        return dict(zip(stage_names(), list(buf)[:k]))
+
+    def free(self):
+        if self._ptr is not None:
+            lib().vr_free(self._ptr, self._stream)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing: bool = False) -> Result:
+    """Build the Vietoris-Rips filtration (dim <= maxdim) of a device point cloud.
+
+    points: torch tensor on a HIP device, (n, d) int8/int16/int32, rows are points.
+    thr:    ("full", 0, 1) | ("count", K, 1) | ("fraction", num, den) | ("sqdist", tau, 0).
+    The work runs on torch's current stream of the points' device.
+    """
+    import torch
+
+    L = lib()
+    if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+        raise TypeError("points must be a torch tensor on a HIP device")
+    if points.dim() != 2:
+        raise ValueError("points must be 2-D (n, d)")
+    pts = points.contiguous()
+    kind, num, den = thr
+    alloc = _allocator_for(pts.device)
+    stream = torch.cuda.current_stream(pts.device)
+    req = VrRequest(
+        points=pts.data_ptr() if pts.numel() else None,
+        n=pts.shape[0],
+        d=pts.shape[1],
+        dtype=_dtype_code(pts),
+        thr_kind=VR_THR[kind],
+        thr_num=int(num),
+        thr_den=int(den),
+        maxdim=int(maxdim),
+        flags=(VR_COUNT_ONLY if count_only else 0) | (VR_TIMING if timing else 0),
+        alloc=ctypes.pointer(alloc.struct),
+    )
+    out = ctypes.POINTER(VrResult)()
+    with torch.cuda.device(pts.device):
+        rc = L.vr_build(ctypes.byref(req), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return Result(out, alloc, ctypes.c_void_p(stream.cuda_stream))
+

@@ -1,0 +1,394 @@
+// vr_api.hip -- the C ABI (include/vr.h): request validation, workspace
+// planning, the two-phase launch sequence and result ownership.
+//
+// Phase 1 (one stream, no host round trip): distances -> threshold select ->
+// radix passes -> kept edges -> stars -> triangle counts -> offsets.
+// One 32-byte device-to-host read of (candidates, K, T, flags) and one stream
+// synchronisation size the outputs.  Phase 2: ordered triangle write and the
+// public edge arrays.  The workspace is released in stream order.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <new>
+#include <string.h>
+
+#include "vr.h"
+#include "vr_device.h"
+
+namespace {
+
+enum Stage { ST_DIST, ST_SELECT, ST_SORT, ST_EDGES, ST_STAR, ST_COUNT, ST_SCAN, ST_SYNC, ST_WRITE, ST_EMIT, ST_N };
+const char *kStageNames[ST_N] = {"dist", "select", "radix_sort", "kept_edges", "star_sort",
+                                 "tri_count", "tri_scan", "count_readback", "tri_write", "emit_edges"};
+
+struct Alloc {
+    const vr_allocator *a;
+    hipStream_t s;
+    void *get(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        if (a && a->alloc) return a->alloc(bytes, (void *)s, a->ctx);
+        void *p = nullptr;
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void *p, size_t bytes) {
+        if (!p) return;
+        if (a && a->free) a->free(p, bytes, (void *)s, a->ctx);
+        else (void)hipFreeAsync(p, s);
+    }
+};
+
+struct Result : vr_result {
+    void *block;
+    size_t block_bytes;
+    vr_allocator alloc;
+    bool has_alloc;
+    bool timing;
+    hipEvent_t ev[ST_N + 1];
+    bool ev_used[ST_N + 1];
+};
+
+// Keep freed pool memory cached in the device's default pool, so repeated
+// builds do not return to the driver for every allocation.
+std::once_flag g_pool_once[64];
+void tune_pool(int dev) {
+    if (dev < 0 || dev >= 64) return;
+    std::call_once(g_pool_once[dev], [dev]() {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = ~0ull;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        (void)hipGetLastError();
+    });
+}
+
+// Pinned status buffer per host thread, for the single count read-back.
+struct Pinned {
+    uint32_t *p = nullptr;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+thread_local Pinned g_pinned;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    size_t off_ctl, off_deg, off_stsel, zero_bytes;
+    size_t off_q, off_key0, off_key1, off_val0, off_val1, off_st0, off_st1;
+    size_t off_seij, off_seq, off_inc, off_nbr, off_pos, off_cnt, off_off, off_stscan;
+    size_t total;
+};
+
+Plan plan(long long n, long long E, long long Kmax, bool tri) {
+    Plan P{};
+    const long long ntE = (E + VR_TILE - 1) / VR_TILE;
+    const long long ntK = (Kmax + VR_TILE - 1) / VR_TILE;
+    size_t o = 0;
+    // zeroed region: control block, degrees, select and scan statuses
+    P.off_ctl = o; o += sizeof(VrCtl);
+    o = (o + 15) & ~(size_t)15;
+    P.off_stscan = o; o += 8 * (size_t)(ntK > 0 ? ntK : 1);
+    P.off_deg = o; o += sizeof(uint32_t) * (size_t)n;
+    P.off_stsel = o; o += sizeof(uint32_t) * (size_t)(ntE > 0 ? ntE : 1);
+    P.zero_bytes = (o + 3) & ~(size_t)3;
+    o = align_up(o);
+    P.off_q = o; o = align_up(o + 4 * (size_t)E);
+    P.off_key0 = o; o = align_up(o + 4 * (size_t)E);
+    P.off_key1 = o; o = align_up(o + 4 * (size_t)E);
+    P.off_val0 = o; o = align_up(o + 4 * (size_t)E);
+    P.off_val1 = o; o = align_up(o + 4 * (size_t)E);
+    P.off_st0 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntE > 0 ? ntE : 1));
+    P.off_st1 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntE > 0 ? ntE : 1));
+    P.off_seij = o; o = align_up(o + 4 * (size_t)Kmax);
+    P.off_seq = o; o = align_up(o + 4 * (size_t)Kmax);
+    if (tri) {
+        P.off_inc = o; o = align_up(o + 4 * (size_t)n * (size_t)n);
+        P.off_nbr = o; o = align_up(o + 2 * (size_t)n * (size_t)n);
+        P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
+        P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
+        P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
+    }
+    P.total = o;
+    return P;
+}
+
+int key_bits(int dtype, long long d) {
+    if (dtype == VR_I8) {
+        unsigned long long m = 65025ull * (unsigned long long)d;  // 255^2 per coordinate
+        int b = 0;
+        while (b < 32 && (m >> b)) b++;
+        return b;
+    }
+    return 32;
+}
+
+int check_request(const vr_request *req, long long *E_out, long long *K_out) {
+    if (!req) return VR_EINVAL;
+    if (req->n < 0 || req->d < 1) return VR_EINVAL;
+    if (req->dtype != VR_I8 && req->dtype != VR_I16 && req->dtype != VR_I32) return VR_EINVAL;
+    if (req->maxdim < 0 || req->maxdim > 2) return VR_EINVAL;
+    if (req->n > 0 && !req->points) return VR_EINVAL;
+    if (req->n > VR_MAX_POINTS) return VR_E2BIG;
+    const long long n = req->n;
+    const long long E = n * (n - 1) / 2;
+    long long K = -1;
+    switch (req->thr_kind) {
+    case VR_THR_FULL: K = E; break;
+    case VR_THR_COUNT:
+        if (req->thr_num < 0 || req->thr_num > E) return VR_EINVAL;
+        K = req->thr_num;
+        break;
+    case VR_THR_FRACTION:
+        if (req->thr_den <= 0 || req->thr_num < 0 || req->thr_num > req->thr_den) return VR_EINVAL;
+        K = (long long)(((__int128)req->thr_num * E) / req->thr_den);
+        break;
+    case VR_THR_SQDIST:
+        if (req->thr_num < 0) return VR_EINVAL;
+        K = -1;
+        break;
+    default: return VR_EINVAL;
+    }
+    if (K > VR_MAX_EDGES) return VR_E2BIG;
+    *E_out = E;
+    *K_out = K;
+    return VR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vr_version(void) { return 100; }
+
+const char *vr_status_string(int status) {
+    switch (status) {
+    case VR_OK: return "ok";
+    case VR_EINVAL: return "invalid argument";
+    case VR_ENOMEM: return "device allocation failed";
+    case VR_E2BIG: return "too many points or edges for the packed keys";
+    case VR_EHIP: return "HIP runtime error";
+    case VR_ERANGE: return "a squared distance exceeds 32 bits";
+    default: return "unknown status";
+    }
+}
+
+const char *vr_stage_name(int s) { return (s >= 0 && s < ST_N) ? kStageNames[s] : nullptr; }
+
+int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind) {
+    vr_request r{};
+    r.n = n; r.d = d; r.dtype = dtype; r.thr_kind = thr_kind; r.thr_num = 0; r.thr_den = 1; r.maxdim = 2;
+    r.points = (const void *)16;
+    long long E, K;
+    if (check_request(&r, &E, &K) != VR_OK) return -1;
+    return (int64_t)plan(n, E, E, true).total;
+}
+
+int vr_query_counts(const vr_result *res, int64_t counts[3]) {
+    if (!res || !counts) return VR_EINVAL;
+    counts[0] = res->n_vertices;
+    counts[1] = res->n_edges;
+    counts[2] = res->n_triangles;
+    return VR_OK;
+}
+
+int vr_query_stage_ms(const vr_result *res_, float *ms, int cap) {
+    if (!res_ || (!ms && cap > 0)) return VR_EINVAL;
+    const Result *res = static_cast<const Result *>(res_);
+    if (!res->timing) return 0;
+    int last = -1;
+    for (int i = ST_N; i >= 0; i--)
+        if (res->ev_used[i]) { last = i; break; }
+    if (last < 0) return 0;
+    if (hipEventSynchronize(res->ev[last]) != hipSuccess) return VR_EHIP;
+    int w = 0;
+    for (int s = 0; s < ST_N && w < cap; s++, w++) {
+        ms[w] = 0.f;
+        if (res->ev_used[s] && res->ev_used[s + 1]) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, res->ev[s], res->ev[s + 1]) == hipSuccess) ms[w] = t;
+        }
+    }
+    return w;
+}
+
+void vr_free(vr_result *res_, void *stream) {
+    if (!res_) return;
+    Result *res = static_cast<Result *>(res_);
+    Alloc A{res->has_alloc ? &res->alloc : nullptr, (hipStream_t)stream};
+    A.put(res->block, res->block_bytes);
+    if (res->timing)
+        for (int i = 0; i <= ST_N; i++) (void)hipEventDestroy(res->ev[i]);
+    delete res;
+}
+
+int vr_build(const vr_request *req, void *stream_, vr_result **out) {
+    if (!out) return VR_EINVAL;
+    long long E = 0, Khost = -1;
+    int st = check_request(req, &E, &Khost);
+    if (st != VR_OK) return st;
+    hipStream_t s = (hipStream_t)stream_;
+    const long long n = req->n;
+    const bool want_edges = req->maxdim >= 1;
+    const bool want_tri = req->maxdim >= 2 && n >= 3;
+    const bool count_only = (req->flags & VR_COUNT_ONLY) != 0;
+    const bool timing = (req->flags & VR_TIMING) != 0;
+
+    Result *res = new (std::nothrow) Result();
+    if (!res) return VR_ENOMEM;
+    res->n_vertices = n;
+    res->has_alloc = req->alloc != nullptr;
+    if (res->has_alloc) res->alloc = *req->alloc;
+    res->timing = timing;
+    Alloc A{req->alloc, s};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { delete res; return VR_EHIP; }
+    tune_pool(dev);
+
+    auto fail = [&](int code, void *ws, size_t wsb) {
+        if (ws) A.put(ws, wsb);
+        if (res->timing)
+            for (int i = 0; i <= ST_N; i++)
+                if (res->ev[i]) (void)hipEventDestroy(res->ev[i]);
+        delete res;
+        (void)hipGetLastError();
+        return code;
+    };
+    if (timing) {
+        for (int i = 0; i <= ST_N; i++)
+            if (hipEventCreate(&res->ev[i]) != hipSuccess) return fail(VR_EHIP, nullptr, 0);
+    }
+    auto mark = [&](int i) {
+        if (timing) {
+            (void)hipEventRecord(res->ev[i], s);
+            res->ev_used[i] = true;
+        }
+    };
+
+    // Nothing to compute on the device: no pairs, or no edges requested/kept.
+    if (!want_edges || E == 0 || Khost == 0) {
+        res->n_edges = 0;
+        res->n_triangles = 0;
+        *out = res;
+        return VR_OK;
+    }
+
+    const long long Kmax = (Khost >= 0) ? Khost : E;
+    const Plan P = plan(n, E, Kmax, want_tri);
+    char *ws = (char *)A.get(P.total);
+    if (!ws) return fail(VR_ENOMEM, nullptr, 0);
+
+    VrDev D{};
+    D.n = (int)n;
+    D.d = (int)req->d;
+    D.dtype = req->dtype;
+    D.E = E;
+    D.thr_kind = req->thr_kind;
+    D.thr_num = req->thr_num;
+    D.K_host = Khost;
+    D.passes = (key_bits(req->dtype, req->d) + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
+    if (D.passes < 1) D.passes = 1;
+    D.need_hist = (req->thr_kind == VR_THR_COUNT || req->thr_kind == VR_THR_FRACTION) ? 1 : 0;
+    D.ctl = (VrCtl *)(ws + P.off_ctl);
+    D.deg = (uint32_t *)(ws + P.off_deg);
+    D.st_sel = (uint32_t *)(ws + P.off_stsel);
+    D.q = (uint32_t *)(ws + P.off_q);
+    D.key[0] = (uint32_t *)(ws + P.off_key0);
+    D.key[1] = (uint32_t *)(ws + P.off_key1);
+    D.val[0] = (uint32_t *)(ws + P.off_val0);
+    D.val[1] = (uint32_t *)(ws + P.off_val1);
+    D.st_sort[0] = (uint32_t *)(ws + P.off_st0);
+    D.st_sort[1] = (uint32_t *)(ws + P.off_st1);
+    D.se_ij = (uint32_t *)(ws + P.off_seij);
+    D.se_q = (uint32_t *)(ws + P.off_seq);
+    if (want_tri) {
+        D.inc = (uint32_t *)(ws + P.off_inc);
+        D.nbr = (uint16_t *)(ws + P.off_nbr);
+        D.pos = (uint16_t *)(ws + P.off_pos);
+        D.cnt = (uint32_t *)(ws + P.off_cnt);
+        D.off = (unsigned long long *)(ws + P.off_off);
+        D.st_scan = (unsigned long long *)(ws + P.off_stscan);
+    }
+    D.ntile_E = (E + VR_TILE - 1) / VR_TILE;
+
+    // ---------------------------------------------------------- phase 1 ----
+    mark(ST_DIST);
+    launch_init(D, P.zero_bytes / 4, s);
+    launch_dist(D, req->points, s);
+    mark(ST_SELECT);
+    launch_select(D, s);
+    mark(ST_SORT);
+    for (int p = 0; p < D.passes; p++) launch_sort_pass(D, p, s);
+    mark(ST_EDGES);
+    if (want_tri) {
+        launch_edges(D, s);
+    } else {
+        // edges only: no vertex binning
+        VrDev D2 = D;
+        D2.inc = nullptr;
+        launch_edges(D2, s);
+    }
+    mark(ST_STAR);
+    if (want_tri) launch_star(D, s);
+    mark(ST_COUNT);
+    if (want_tri) launch_tri_count(D, s);
+    mark(ST_SCAN);
+    // the scan reads K from the device (unknown on the host for SQDIST)
+    if (want_tri) launch_scan(D, Kmax, s);
+    mark(ST_SYNC);
+    if (hipGetLastError() != hipSuccess) return fail(VR_EHIP, ws, P.total);
+    if (!g_pinned.p) {
+        if (hipHostMalloc((void **)&g_pinned.p, 64, hipHostMallocDefault) != hipSuccess) {
+            g_pinned.p = nullptr;
+            (void)hipStreamSynchronize(s);
+            return fail(VR_ENOMEM, ws, P.total);
+        }
+    }
+    uint32_t *hp = g_pinned.p;
+    if (hipMemcpyAsync(hp, &D.ctl->flags, 24, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        return fail(VR_EHIP, ws, P.total);
+    }
+    const uint32_t flags = hp[0];
+    const long long K = (long long)hp[2];
+    unsigned long long T = want_tri ? ((unsigned long long)hp[4] | ((unsigned long long)hp[5] << 32)) : 0ull;
+    if (flags & 1u) return fail(VR_ERANGE, ws, P.total);
+    if (K > VR_MAX_EDGES) return fail(VR_E2BIG, ws, P.total);
+
+    // ---------------------------------------------------------- phase 2 ----
+    const bool write_tri = want_tri && !count_only && T > 0;
+    const size_t eq_bytes = align_up(8 * (size_t)K), eij_bytes = align_up(8 * (size_t)K);
+    const size_t tri_bytes = write_tri ? 8 * (size_t)T : 0;
+    const size_t ob = eq_bytes + eij_bytes + tri_bytes;
+    char *blk = (char *)A.get(ob);
+    if (!blk) return fail(VR_ENOMEM, ws, P.total);
+    res->block = blk;
+    res->block_bytes = ob;
+    res->edge_q = (const int64_t *)blk;
+    res->edge_ij = (const uint32_t *)(blk + eq_bytes);
+    res->tri_key = write_tri ? (const uint64_t *)(blk + eq_bytes + eij_bytes) : nullptr;
+    res->n_edges = K;
+    res->n_triangles = (int64_t)T;
+
+    mark(ST_WRITE);
+    if (write_tri) launch_tri_write(D, (unsigned long long *)res->tri_key, s);
+    mark(ST_EMIT);
+    launch_emit_edges(D, K, (uint32_t *)res->edge_ij, (long long *)res->edge_q, s);
+    mark(ST_N);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        A.put(blk, ob);
+        res->block = nullptr;
+        return fail(VR_EHIP, ws, P.total);
+    }
+    A.put(ws, P.total);
+    *out = res;
+    return VR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// vr_device.h -- device-side building blocks shared by the gfx950 kernels:
+// wave64 ballots and scans, work-group scans, decoupled look-back status
+// words, and the workspace layout the kernels agree on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VR_WAVE 64
+#define VR_BLOCK 256                 // threads per work-group in every kernel
+#define VR_WAVES (VR_BLOCK / VR_WAVE)
+#define VR_ITEMS 8                   // items per thread in tiled passes
+#define VR_TILE (VR_BLOCK * VR_ITEMS) // 2048 items per tile
+#define VR_RADIX_BITS 8
+#define VR_RADIX (1 << VR_RADIX_BITS)
+#define VR_MAX_PASSES 4
+#define VR_NBUCKET 1728              // log-linear buckets of a 32-bit key
+#define VR_NOT_KEPT 0xFFFFFFFFu
+
+// Look-back status words: 2-bit state in the top bits, value below.
+#define VR_ST_NONE 0u
+#define VR_ST_AGG 1u
+#define VR_ST_INC 2u
+
+// Control block in device memory, zeroed at the start of every build.
+struct VrCtl {
+    uint32_t ticket[8];             // tile tickets: 0 select, 1..4 sort passes, 5 scan
+    uint32_t flags;                 // bit 0: a squared distance overflowed 32 bits
+    uint32_t n_cand;                // candidates kept by the select pass
+    uint32_t n_kept;                // K
+    uint32_t pad0;
+    unsigned long long n_tri;       // T
+    uint32_t hist8[VR_MAX_PASSES][VR_RADIX];  // digit histograms of the candidates
+    uint32_t bucket[VR_NBUCKET];    // log-linear histogram of all squared distances
+};
+
+// ---------------------------------------------------------------- lanes ----
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    uint32_t l = lane_id();
+    return (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+}
+
+__device__ __forceinline__ unsigned long long ballot64(int p) { return __ballot(p); }
+
+// Inclusive scan across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+#pragma unroll
+    for (int o = 1; o < VR_WAVE; o <<= 1) {
+        T y = __shfl_up(x, o, VR_WAVE);
+        if ((int)lane_id() >= o) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int o = VR_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, VR_WAVE);
+    return x;
+}
+
+// Exclusive scan across a 256-thread work-group; returns the exclusive value
+// and writes the group total.  `sh` holds VR_WAVES entries of LDS.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T *sh, T *total) {
+    T inc = wave_incl_scan(x);
+    const int w = threadIdx.x / VR_WAVE;
+    if (lane_id() == VR_WAVE - 1) sh[w] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < VR_WAVES; i++) {
+        T s = sh[i];
+        if (i < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+// ---------------------------------------------------- look-back statuses ----
+__device__ __forceinline__ uint32_t st_load32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store32(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long st_load64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t st_pack32(uint32_t state, uint32_t v) { return (state << 30) | v; }
+__device__ __forceinline__ unsigned long long st_pack64(uint32_t state, unsigned long long v) {
+    return ((unsigned long long)state << 62) | v;
+}
+
+// Decoupled look-back (Merrill and Garland, "Single-pass Parallel Prefix Scan
+// with Decoupled Look-back", 2016): walk back over the predecessors' status
+// words, summing aggregates until an inclusive prefix is found.  Every
+// predecessor tile was claimed by a running work-group through the ticket
+// counter, so each wait ends.
+__device__ __forceinline__ uint32_t lookback32(const uint32_t *st, int tile, int stride) {
+    uint32_t acc = 0;
+    for (int t = tile - 1; t >= 0; t--) {
+        uint32_t s;
+        while (((s = st_load32(st + (size_t)t * stride)) >> 30) == VR_ST_NONE) __builtin_amdgcn_s_sleep(1);
+        acc += s & 0x3FFFFFFFu;
+        if ((s >> 30) == VR_ST_INC) break;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ unsigned long long lookback64(const unsigned long long *st, int tile) {
+    unsigned long long acc = 0;
+    for (int t = tile - 1; t >= 0; t--) {
+        unsigned long long s;
+        while (((s = st_load64(st + t)) >> 62) == VR_ST_NONE) __builtin_amdgcn_s_sleep(1);
+        acc += s & 0x3FFFFFFFFFFFFFFFull;
+        if ((s >> 62) == VR_ST_INC) break;
+    }
+    return acc;
+}
+
+// Claim the next tile of a persistent loop; broadcast through LDS.
+__device__ __forceinline__ int claim_tile(uint32_t *ticket, int *sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) *sh = (int)atomicAdd(ticket, 1u);
+    __syncthreads();
+    return *sh;
+}
+
+// ------------------------------------------------------ key conventions ----
+// Log-linear bucket of a 32-bit key: exact below 128, then 64 buckets per
+// power of two.  Monotone non-decreasing in q; 1728 buckets.
+__device__ __forceinline__ uint32_t bucket_of(uint32_t q) {
+    if (q < 128u) return q;
+    uint32_t m = 31u - (uint32_t)__clz(q);
+    return 128u + ((m - 7u) << 6) + ((q >> (m - 6u)) & 63u);
+}
+
+// Packed triangle key: value (24 bits) | i | j | k (13 bits each), i<j<k.
+__device__ __forceinline__ unsigned long long tri_key(uint32_t v, uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t lo = min(a, min(b, c)), hi = max(a, max(b, c));
+    uint32_t mid = a + b + c - lo - hi;
+    return ((unsigned long long)v << 39) | ((unsigned long long)lo << 26) |
+           ((unsigned long long)mid << 13) | (unsigned long long)hi;
+}
+
+// First pair index of row i in the lexicographic list of pairs (i<j).
+__host__ __device__ __forceinline__ long long row_start(long long i, long long n) {
+    return i * (2 * n - i - 1) / 2;
+}
+
+// Pair index -> (i, j): solve row_start(i) <= e < row_start(i+1) with a
+// floating-point guess corrected by exact integer comparisons.
+__device__ __forceinline__ void pair_of(long long e, long long n, int *pi, int *pj) {
+    double b = 2.0 * (double)n - 1.0;
+    double disc = b * b - 8.0 * (double)e;
+    long long i = (long long)((b - sqrt(disc > 0 ? disc : 0.0)) * 0.5);
+    if (i < 0) i = 0;
+    if (i > n - 2) i = n - 2;
+    while (i > 0 && row_start(i, n) > e) i--;
+    while (i < n - 2 && row_start(i + 1, n) <= e) i++;
+    *pi = (int)i;
+    *pj = (int)(e - row_start(i, n) + i + 1);
+}
+
+// ------------------------------------------------------- launch wrappers ----
+struct VrDev {
+    // shape
+    int n, d, dtype;
+    long long E;
+    int thr_kind;
+    long long thr_num;
+    long long K_host;       // K when known before the build (else -1)
+    int passes;             // radix passes launched (covering the key width)
+    int need_hist;          // histogram select needed (COUNT / FRACTION)
+    // workspace
+    VrCtl *ctl;
+    uint32_t *q;            // E
+    uint32_t *key[2];       // E each, ping-pong
+    uint32_t *val[2];       // E each (i<<16 | j)
+    uint32_t *st_sel;       // ceil(E/TILE) select statuses
+    uint32_t *st_sort[2];   // ceil(E/TILE)*RADIX sort statuses (by active-pass parity)
+    uint32_t *se_ij;        // K: sorted kept edges (i<<16|j)
+    uint32_t *se_q;         // K
+    uint32_t *deg;          // n
+    uint32_t *inc;          // n*n: per-vertex incident edge ranks (rank order after star sort)
+    uint16_t *nbr;          // n*n: per-vertex neighbours in rank order
+    uint16_t *pos;          // 2K: position of edge r in the star of its smaller/larger vertex
+    uint32_t *cnt;          // K: triangles per value
+    unsigned long long *off;     // K: exclusive offsets
+    unsigned long long *st_scan; // ceil(K/TILE)
+    long long ntile_E;
+};
+
+void launch_init(const VrDev &D, size_t zero_words, hipStream_t s);
+void launch_dist(const VrDev &D, const void *points, hipStream_t s);
+void launch_select(const VrDev &D, hipStream_t s);
+void launch_sort_pass(const VrDev &D, int pass, hipStream_t s);
+void launch_edges(const VrDev &D, hipStream_t s);
+void launch_star(const VrDev &D, hipStream_t s);
+void launch_tri_count(const VrDev &D, hipStream_t s);
+void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
+void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s);
+void launch_emit_edges(const VrDev &D, long long K, uint32_t *edge_ij, long long *edge_q, hipStream_t s);

@@ -1,0 +1,42 @@
+"""Helpers for tests that call the HIP library through its Python binding."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def decode_keys(keys) -> np.ndarray:
+    """Packed triangle keys (v<<39 | i<<26 | j<<13 | k) -> (T, 4) rows (v, i, j, k)."""
+    k = np.asarray(keys).astype(np.int64).view(np.uint64)
+    m13 = np.uint64(0x1FFF)
+    return np.stack([k >> np.uint64(39), (k >> np.uint64(26)) & m13, (k >> np.uint64(13)) & m13, k & m13],
+                    axis=1).astype(np.int64)
+
+
+def gpu_build(cloud, maxdim=2, count_only=False, timing=False, device="cuda:0"):
+    """Run one build on the GPU; returns (result, host dict of numpy arrays)."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    pts = torch.from_numpy(np.ascontiguousarray(cloud.points)).to(device)
+    res = vr.build(pts, cloud.thr, maxdim=maxdim, count_only=count_only, timing=timing)
+    torch.cuda.synchronize()
+    out = {
+        "counts": res.counts,
+        "edge_ij": res.edge_ij().cpu().numpy().astype(np.int64),
+        "edge_q": res.edge_q().cpu().numpy(),
+        "tri": res.tri_key().cpu().numpy(),
+    }
+    return res, out
+
+
+def assert_matches_oracle(out, f, check_tri=True):
+    """Bit-exact comparison of a GPU build with an oracle Filtration."""
+    assert tuple(out["counts"]) == (f.n, f.K, f.T)
+    assert np.array_equal(out["edge_ij"][:, 0], f.ei)
+    assert np.array_equal(out["edge_ij"][:, 1], f.ej)
+    assert np.array_equal(out["edge_q"], f.eq)
+    if check_tri:
+        got = decode_keys(out["tri"])
+        assert got.shape == f.tris.shape
+        assert np.array_equal(got, f.tris)

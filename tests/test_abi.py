@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every symbol include/vr.h declares, and
+rejects invalid requests before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1809_04424_amd as vr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vr_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_symbols():
+    assert _declared() == sorted(vr.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = vr.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_only_c_abi_is_exported():
+    import subprocess
+
+    out = subprocess.run(["nm", "-D", "--defined-only", vr.LIB_PATH], capture_output=True, text=True).stdout
+    syms = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert syms == sorted(_declared())
+
+
+def test_status_strings_and_version():
+    assert vr.status_string(vr.VR_OK) == "ok"
+    assert "32 bits" in vr.status_string(vr.VR_ERANGE)
+    assert vr.lib().vr_version() >= 100
+    assert vr.stage_names()[0] == "dist" and "tri_write" in vr.stage_names()
+
+
+def _req(**kw):
+    base = dict(points=16, n=10, d=3, dtype=vr.VR_I8, thr_kind=0, thr_num=0, thr_den=1, maxdim=2, flags=0, alloc=None)
+    base.update(kw)
+    return vr.VrRequest(**base)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(d=0), vr.VR_EINVAL),
+    (dict(n=-1), vr.VR_EINVAL),
+    (dict(dtype=7), vr.VR_EINVAL),
+    (dict(points=None), vr.VR_EINVAL),
+    (dict(maxdim=3), vr.VR_EINVAL),
+    (dict(thr_kind=9), vr.VR_EINVAL),
+    (dict(thr_kind=1, thr_num=46), vr.VR_EINVAL),      # more than C(10,2) edges
+    (dict(thr_kind=2, thr_num=3, thr_den=0), vr.VR_EINVAL),
+    (dict(thr_kind=2, thr_num=5, thr_den=4), vr.VR_EINVAL),
+    (dict(thr_kind=3, thr_num=-1), vr.VR_EINVAL),
+    (dict(n=8193), vr.VR_E2BIG),
+    (dict(n=8000), vr.VR_E2BIG),                        # C(8000,2) > 2^24 kept edges
+])
+def test_invalid_requests_rejected_before_device_work(kw, code):
+    out = ctypes.POINTER(vr.VrResult)()
+    rc = vr.lib().vr_build(ctypes.byref(_req(**kw)), None, ctypes.byref(out))
+    assert rc == code
+    assert not out
+
+
+def test_workspace_bytes():
+    a = vr.workspace_bytes(1000, 3)
+    b = vr.workspace_bytes(4000, 64)
+    assert 0 < a < b
+    assert vr.workspace_bytes(9000, 3) == -1
+    assert vr.lib().vr_query_counts(None, None) == vr.VR_EINVAL
+    vr.lib().vr_free(None, None)  # NULL-safe

@@ -1,0 +1,153 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact.
+
+Every comparison is on identical seeded inputs; every output is integer, so
+the tolerance is exact equality.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import assert_matches_oracle, decode_keys, gpu_build
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1809_04424_amd as vr
+
+    vr.lib()  # fails loudly if the library is missing
+    yield
+
+
+SMALL = [
+    workloads.uniform_cloud(1, 9, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(2, 11, 3, thr=("fraction", 40, 100)),
+    workloads.lattice_cloud(3, 40, side=3, thr=("fraction", 50, 100)),
+    workloads.lattice_cloud(4, 30, side=2, thr=("count", 17, 1)),
+    workloads.uniform_cloud(5, 50, 4, thr=("sqdist", 20000, 0)),
+    workloads.uniform_cloud(6, 3, 1, thr=("full", 0, 1)),
+    workloads.uniform_cloud(7, 2, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(8, 1, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(18, 0, 2, thr=("full", 0, 1)),
+    workloads.lattice_cloud(9, 80, side=1, thr=("fraction", 60, 100)),  # all points equal
+    workloads.uniform_cloud(10, 300, 16, thr=("fraction", 15, 100)),
+    workloads.uniform_cloud(11, 257, 3, thr=("count", 1, 1)),
+    workloads.uniform_cloud(12, 129, 3, thr=("count", 2, 1)),
+    workloads.uniform_cloud(13, 130, 3, thr=("count", 3, 1)),
+    workloads.uniform_cloud(14, 131, 3, thr=("count", 0, 1)),
+    workloads.uniform_cloud(15, 200, 64, thr=("fraction", 7, 100)),
+    workloads.uniform_cloud(16, 150, 5, dtype=np.int16, lo=-30000, hi=30000, thr=("fraction", 30, 100)),
+    workloads.uniform_cloud(17, 150, 2, dtype=np.int32, lo=0, hi=20000, thr=("fraction", 25, 100)),
+    workloads.uniform_cloud(19, 100, 3, thr=("sqdist", 10 ** 12, 0)),  # tau above every q: all kept
+    workloads.uniform_cloud(20, 100, 3, thr=("sqdist", 0, 0)),         # nothing kept
+    workloads.uniform_cloud(21, 333, 130, thr=("fraction", 12, 100)),  # several coordinate chunks
+    workloads.lattice_cloud(22, 500, side=4, d=3, thr=("fraction", 20, 100)),  # heavy ties across tiles
+]
+
+
+@pytest.mark.parametrize("cloud", SMALL, ids=lambda c: f"{c.name}_{c.thr[0]}{c.thr[1]}")
+def test_small_clouds_bit_exact(orc, cloud):
+    _say(f"[gpu] {cloud.name} n={cloud.n} d={cloud.d} thr={cloud.thr}")
+    f = orc.build(cloud.points, cloud.thr)
+    _, out = gpu_build(cloud)
+    assert_matches_oracle(out, f)
+
+
+@pytest.mark.parametrize("maxdim", [0, 1])
+def test_lower_maxdim(orc, maxdim):
+    c = workloads.uniform_cloud(30, 120, 3, thr=("fraction", 30, 100))
+    f = orc.build(c.points, c.thr, maxdim=maxdim)
+    _, out = gpu_build(c, maxdim=maxdim)
+    assert out["counts"] == (f.n, f.K, 0)
+    assert np.array_equal(out["edge_q"], f.eq)
+
+
+def test_count_only(orc):
+    c = workloads.noisy_circle(n=500)
+    f = orc.build(c.points, c.thr, list_triangles=False)
+    res, out = gpu_build(c, count_only=True)
+    assert out["counts"] == f.counts
+    assert len(out["tri"]) == 0
+
+
+def test_plain64_full_threshold(orc):
+    c = workloads.plain64()
+    f = orc.build(c.points, c.thr)
+    _, out = gpu_build(c)
+    assert out["counts"] == (64, 2016, 41664)
+    assert_matches_oracle(out, f)
+
+
+def test_circle1000_bit_exact(orc):
+    c = workloads.noisy_circle()
+    _say("[gpu] circle1000 oracle")
+    f = orc.build(c.points, c.thr)
+    _say("[gpu] circle1000 build")
+    _, out = gpu_build(c)
+    assert out["counts"][1] == 99900
+    assert_matches_oracle(out, f)
+
+
+def test_repeat_builds_identical():
+    c = workloads.noisy_circle(n=700)
+    a = gpu_build(c)[1]
+    b = gpu_build(c)[1]
+    assert np.array_equal(a["tri"], b["tri"])
+    assert np.array_equal(a["edge_ij"], b["edge_ij"])
+
+
+def test_mixture4000_sampled(orc):
+    """Full-size 4000 x R^64 mixture at the 10th percentile: every edge, every
+    per-value triangle count, and the triangles of sampled values, exactly."""
+    import torch
+
+    c = workloads.mixture()
+    _say("[gpu] mixture4000 oracle edges + per-value counts")
+    f = orc.build(c.points, c.thr, list_triangles=False)
+    cnt = orc.triangles_per_value(f)
+    _say("[gpu] mixture4000 build")
+    res, out = gpu_build(c)
+    assert out["counts"] == (4000, 799800, int(cnt.sum()))
+    assert np.array_equal(out["edge_ij"][:, 0], f.ei)
+    assert np.array_equal(out["edge_ij"][:, 1], f.ej)
+    assert np.array_equal(out["edge_q"], f.eq)
+    keys = res.tri_key()
+    v = (keys >> 39)
+    got_cnt = torch.bincount(v, minlength=f.K).cpu().numpy()
+    assert np.array_equal(got_cnt, cnt)
+    assert bool((keys[1:] > keys[:-1]).all().item())  # strictly ascending
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    rng = np.random.default_rng(0)
+    for r in list(rng.integers(0, f.K, 40)) + [0, f.K - 1, int(np.argmax(cnt))]:
+        rows = orc.triangles_of_value(f, int(r))
+        seg = decode_keys(out["tri"][off[r]: off[r + 1]])
+        assert np.array_equal(seg, rows), f"value {r}"
+
+
+def test_int32_overflow_is_reported():
+    import paper_1809_04424_amd as vr
+
+    c = workloads.uniform_cloud(40, 20, 3, dtype=np.int32, lo=-2 ** 30, hi=2 ** 30)
+    with pytest.raises(vr.VrError) as e:
+        gpu_build(c)
+    assert e.value.code == vr.VR_ERANGE
+
+
+def test_full_threshold_binomials():
+    for n in (3, 65, 190):
+        c = workloads.uniform_cloud(n, n, 2, dtype=np.int32, lo=0, hi=1023)
+        _, out = gpu_build(c)
+        assert out["counts"] == (n, math.comb(n, 2), math.comb(n, 3))
