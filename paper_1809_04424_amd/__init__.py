@@ -79,7 +79,7 @@ def lib():
         if _lib is not None:
             return _lib
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: run paper_1809_04424_amd/build.py (hipcc, gfx950)")
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1809_04424_amd/make_lib.py (hipcc, gfx950)")
         L = ctypes.CDLL(LIB_PATH)
         L.vr_build.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_void_p, ctypes.POINTER(ctypes.POINTER(VrResult))]
         L.vr_build.restype = ctypes.c_int
