@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 Vietoris-Rips filtration front end (dim <= 2).
+
+One step = one whole build (distances, ranks, threshold, triangles, ordered
+output) of the headline workload: 1000 points on a noisy circle in R^3
+(radius 100, sigma 5, int8), thresholded at the 20th-percentile edge rank.
+Inputs are resident in HBM before the timed region; outputs stay on the
+device.  The metric is filtered simplices per second, n + K + T per build.
+
+Prints ONE JSON line.  Only N = 1 GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+
+# HBM bytes per launch of the triangle writer from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a plain copy of known size), keyed by the SHA-256 of
+# the kernel source they were taken on; ignored once the source changes.
+TRAFFIC = {}
+
+
+def _src_sha(name: str) -> str:
+    p = os.path.join(ROOT, "paper_1809_04424_amd", "csrc", name)
+    with open(p, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def _workload(name):
+    import workloads
+
+    return {"circle1000": workloads.noisy_circle, "mixture4000": workloads.mixture,
+            "plain64": workloads.plain64}[name]()
+
+
+def _time_builds(vr, torch, pts, thr, steps, warmup):
+    """Time `steps` whole builds; HIP events bracket only the triangle write
+    (on the build's stream), so its average launch duration is measured live."""
+    for _ in range(warmup):
+        vr.build(pts, thr).free()
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res.append(vr.build(pts, thr, timing="write"))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tw = [r.stage_ms()["tri_write"] for r in res]
+    counts = res[0].counts
+    for r in res:
+        r.free()
+    torch.cuda.synchronize()
+    return (t1 - t0), counts, sum(tw) / len(tw)
+
+
+def _stage_breakdown(vr, torch, pts, thr, reps=10):
+    """Untimed builds with events between all stages (events add small gaps)."""
+    acc = {}
+    for _ in range(reps):
+        r = vr.build(pts, thr, timing=True)
+        for k, v in r.stage_ms().items():
+            acc.setdefault(k, []).append(v)
+        r.free()
+    torch.cuda.synchronize()
+    return {k: round(sum(v) / len(v), 5) for k, v in acc.items()}
+
+
+def _cpu_baseline(cloud, budget_s=12.0):
+    import oracle
+
+    oracle.lib()
+    reps, t0 = 0, time.perf_counter()
+    simp = 0
+    while True:
+        f = oracle.build(cloud.points, cloud.thr)
+        simp += f.n + f.K + f.T
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= 50:
+            break
+    return {"value": simp / el, "unit": "simplices/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} complete builds of {cloud.name} by the single-threaded C oracle "
+                      f"(distances, sortperm, rank matrix, triangle triple loop, qsort); {el:.1f} s"}
+
+
+def _copy_calibration(torch, mib=256):
+    """A plain device copy of known size, so FETCH_SIZE / WRITE_SIZE of other
+    kernels can be scaled to bytes (launched only with --copy-calib)."""
+    n = mib * 1024 * 1024
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[copy-calib] copied {n} bytes", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="circle1000")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
+    ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
+    ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU split is a design note, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    vr.lib()
+    cloud = _workload(args.workload)
+    pts = torch.from_numpy(cloud.points).to("cuda:0")
+    torch.cuda.synchronize()
+    if args.copy_calib:
+        _copy_calibration(torch)
+
+    el, counts, tri_ms = _time_builds(vr, torch, pts, cloud.thr, args.steps, args.warmup)
+    n, K, T = counts
+    simplices = n + K + T
+    value = simplices * args.steps / el
+    ms_step = 1e3 * el / args.steps
+    st = _stage_breakdown(vr, torch, pts, cloud.thr)
+    if args.stages:
+        print(json.dumps({"stages_ms": st}), file=sys.stderr, flush=True)
+
+    alg = 8 * T + 8 * K + n * n / 8.0  # output keys + kept ranks + adjacency bitset, once
+    achieved = alg / (tri_ms * 1e-3) / 1e9 if tri_ms > 0 else 0.0
+    tr = TRAFFIC.get((args.workload, "k_tri_write"))
+    traffic = tr["bytes"] if tr and tr["src_sha"] == _src_sha("k_triangles.hip") else None
+    roofline = {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}
+
+    extra = {}
+    if not args.no_extra and args.workload == "circle1000":
+        c3 = _workload("mixture4000")
+        p3 = torch.from_numpy(c3.points).to("cuda:0")
+        e3, cnt3, t3 = _time_builds(vr, torch, p3, c3.thr, 10, 2)
+        s3 = sum(cnt3)
+        a3 = 8 * cnt3[2] + 8 * cnt3[1] + cnt3[0] ** 2 / 8.0
+        extra["mixture4000_r64_p10"] = {
+            "value": s3 * 10 / e3, "unit": "simplices/s", "ms_per_step": 1e3 * e3 / 10,
+            "counts": list(cnt3), "tri_write_ms": round(t3, 5),
+            "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
+            "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3)}
+        del p3
+
+    line = {
+        "metric": "filtered simplices/sec (VR dim<=2, bit-exact)",
+        "value": value,
+        "unit": "simplices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": cloud.name, "n": n, "d": cloud.d, "coords": str(cloud.points.dtype),
+                   "threshold": f"{cloud.thr[0]} {cloud.thr[1]}/{cloud.thr[2]}", "kept_edges": K,
+                   "triangles": T, "simplices_per_build": simplices},
+        "roofline": roofline,
+        "stages_ms": st,
+    }
+    if extra:
+        line["extra"] = extra
+    if not args.no_cpu:
+        line["cpu_baseline"] = _cpu_baseline(cloud)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

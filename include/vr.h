@@ -72,8 +72,9 @@ enum { VR_THR_FULL = 0, VR_THR_COUNT = 1, VR_THR_FRACTION = 2, VR_THR_SQDIST = 3
 
 /* Request flags. */
 enum {
-    VR_COUNT_ONLY = 1u, /* compute (n, K, T) and the edges; do not write triangles */
-    VR_TIMING = 2u      /* record per-stage HIP events (see vr_query_stage_ms) */
+    VR_COUNT_ONLY = 1u,  /* compute (n, K, T) and the edges; do not write triangles */
+    VR_TIMING = 2u,      /* record HIP events between all stages (see vr_query_stage_ms) */
+    VR_TIMING_WRITE = 4u /* record HIP events around the triangle write only */
 };
 
 /* Limits of the packed triangle key: 13 bits per vertex, 24 bits of value. */
@@ -98,7 +99,7 @@ typedef struct vr_request {
     int32_t thr_kind;   /* VR_THR_* */
     int64_t thr_num, thr_den;
     int32_t maxdim;     /* 0: vertices only, 1: up to edges, 2: up to triangles */
-    uint32_t flags;     /* VR_COUNT_ONLY | VR_TIMING */
+    uint32_t flags;     /* VR_COUNT_ONLY | VR_TIMING | VR_TIMING_WRITE */
     const vr_allocator *alloc; /* NULL: hipMallocAsync on the stream */
 } vr_request;
 
@@ -131,7 +132,8 @@ VR_API int vr_query_counts(const vr_result *res, int64_t counts[3]);
 
 /*
  * Per-stage GPU times (milliseconds) of a build made with VR_TIMING, in the
- * order of vr_stage_name(0..).  Waits for the build's last event.
+ * order of vr_stage_name(0..); with VR_TIMING_WRITE only the triangle write
+ * stage is timed (the others read 0).  Waits for the build's last event.
  * Returns the number of stages written (<= cap), or a negative vr_status.
  */
 VR_API int vr_query_stage_ms(const vr_result *res, float *ms, int cap);

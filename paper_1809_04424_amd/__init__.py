@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvrhip.so")
 VR_OK, VR_EINVAL, VR_ENOMEM, VR_E2BIG, VR_EHIP, VR_ERANGE = 0, -1, -2, -3, -4, -5
 VR_I8, VR_I16, VR_I32 = 1, 2, 3
 VR_THR = {"full": 0, "count": 1, "fraction": 2, "sqdist": 3}
-VR_COUNT_ONLY, VR_TIMING = 1, 2
+VR_COUNT_ONLY, VR_TIMING, VR_TIMING_WRITE = 1, 2, 4
 VR_MAX_POINTS = 8192
 VR_MAX_EDGES = 1 << 24
 
@@ -165,51 +165,61 @@ def _dtype_code(t):
     return m[t.dtype]
 
 
+class _DeviceArray:
+    """Zero-copy view of library-owned device memory for torch.as_tensor;
+    holds the owning Result so the memory outlives every tensor made from it."""
+
+    def __init__(self, owner, ptr, shape, typestr):
+        self._owner = owner
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
 class Result:
-    """Handle of one build.  Device arrays are torch tensor views of the
+    """Handle of one build.  Device arrays are torch tensors over the
     library's output block; they stay valid while any of them is referenced."""
 
-    def __init__(self, ptr, alloc: _TorchAllocator, stream):
+    def __init__(self, ptr, alloc, stream, device):
         self._ptr = ptr
         self._alloc = alloc
         self._stream = stream
+        self._device = device
         r = ptr.contents
         self.n, self.K, self.T = int(r.n_vertices), int(r.n_edges), int(r.n_triangles)
-        self._block = alloc.live.get(r.edge_q) if r.edge_q else None
-        self._off_ij = (r.edge_ij - r.edge_q) if r.edge_q else 0
-        self._off_tri = (r.tri_key - r.edge_q) if r.tri_key else 0
-        self._tri = r.tri_key
+        self._p_q, self._p_ij, self._p_tri = r.edge_q, r.edge_ij, r.tri_key
+        self._block = alloc.live.get(r.edge_q) if (alloc is not None and r.edge_q) else None
 
     @property
     def counts(self):
         return (self.n, self.K, self.T)
 
-    def _view(self, off_bytes, count, dtype, itemsize):
+    def _tensor(self, ptr, count, dtype, typestr, itemsize, shape):
         import torch
 
-        if self._block is None or count == 0:
-            return torch.empty(0, dtype=dtype, device=self._alloc.device)
-        return self._block[off_bytes: off_bytes + count * itemsize].view(dtype)
+        if not ptr or count == 0:
+            return torch.empty(shape if count else (0,) + tuple(shape[1:]), dtype=dtype, device=self._device)
+        if self._block is not None:  # torch-allocated block
+            off = ptr - self._p_q
+            return self._block[off: off + count * itemsize].view(dtype).view(shape)
+        return torch.as_tensor(_DeviceArray(self, ptr, shape, typestr), device=self._device)
 
     def edge_q(self):
         """int64 (K,) squared lengths of the kept edges in rank order."""
         import torch
 
-        return self._view(0, self.K, torch.int64, 8)
+        return self._tensor(self._p_q, self.K, torch.int64, "<i8", 8, (self.K,))
 
     def edge_ij(self):
         """int32 (K, 2) endpoints i < j of the kept edges in rank order."""
         import torch
 
-        return self._view(self._off_ij, 2 * self.K, torch.int32, 4).view(-1, 2)
+        return self._tensor(self._p_ij, 2 * self.K, torch.int32, "<i4", 4, (self.K, 2))
 
     def tri_key(self):
         """int64 (T,) packed triangle keys v<<39 | i<<26 | j<<13 | k, ascending."""
         import torch
 
-        if not self._tri:
-            return torch.empty(0, dtype=torch.int64, device=self._alloc.device)
-        return self._view(self._off_tri, self.T, torch.int64, 8)
+        return self._tensor(self._p_tri, self.T, torch.int64, "<i8", 8, (self.T,))
 
     def stage_ms(self):
         """{stage: ms} of a build made with timing=True."""
@@ -231,11 +241,16 @@ class Result:
             pass
 
 
-def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing: bool = False) -> Result:
+def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing=False,
+          allocator: str = "library") -> Result:
     """Build the Vietoris-Rips filtration (dim <= maxdim) of a device point cloud.
 
-    points: torch tensor on a HIP device, (n, d) int8/int16/int32, rows are points.
-    thr:    ("full", 0, 1) | ("count", K, 1) | ("fraction", num, den) | ("sqdist", tau, 0).
+    points:    torch tensor on a HIP device, (n, d) int8/int16/int32, rows are points.
+    thr:       ("full", 0, 1) | ("count", K, 1) | ("fraction", num, den) | ("sqdist", tau, 0).
+    allocator: "library" (the library's stream-ordered pool) or "torch" (torch's
+               caching allocator through the library's allocator hook).
+    timing:    True: HIP events between all stages; "write": around the
+               triangle write only (see Result.stage_ms).
     The work runs on torch's current stream of the points' device.
     """
     import torch
@@ -247,7 +262,7 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
         raise ValueError("points must be 2-D (n, d)")
     pts = points.contiguous()
     kind, num, den = thr
-    alloc = _allocator_for(pts.device)
+    alloc = _allocator_for(pts.device) if allocator == "torch" else None
     stream = torch.cuda.current_stream(pts.device)
     req = VrRequest(
         points=pts.data_ptr() if pts.numel() else None,
@@ -258,13 +273,13 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
         thr_num=int(num),
         thr_den=int(den),
         maxdim=int(maxdim),
-        flags=(VR_COUNT_ONLY if count_only else 0) | (VR_TIMING if timing else 0),
-        alloc=ctypes.pointer(alloc.struct),
+        flags=(VR_COUNT_ONLY if count_only else 0) | (VR_TIMING_WRITE if timing == "write" else
+                                                      VR_TIMING if timing else 0),
+        alloc=ctypes.pointer(alloc.struct) if alloc is not None else None,
     )
     out = ctypes.POINTER(VrResult)()
     with torch.cuda.device(pts.device):
         rc = L.vr_build(ctypes.byref(req), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
-    return Result(out, alloc, ctypes.c_void_p(stream.cuda_stream))
-
+    return Result(out, alloc, ctypes.c_void_p(stream.cuda_stream), pts.device)

@@ -224,15 +224,15 @@ void launch_select(const VrDev &D, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
 }
 
-// Active radix passes: a pass whose digit is the same for every candidate is
-// the identity and is skipped.  Returns the number of active passes before
+// Active radix passes: a pass whose digit is the same for every key is the
+// identity and is skipped.  Returns the number of active passes before
 // `upto` and sets *active for pass `upto` (when upto < passes).
-__device__ __forceinline__ int active_before(const VrCtl *ctl, int passes, int upto, bool *active) {
+__device__ __forceinline__ int active_before(const uint32_t *hist, int passes, int upto, bool *active) {
     __shared__ int sh_nz[VR_MAX_PASSES];
     if (threadIdx.x < VR_MAX_PASSES) sh_nz[threadIdx.x] = 0;
     __syncthreads();
     for (int x = threadIdx.x; x < passes * VR_RADIX; x += VR_BLOCK)
-        if ((&ctl->hist8[0][0])[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+        if (hist[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
     __syncthreads();
     int a = 0;
     for (int p = 0; p < upto && p < passes; p++) a += (sh_nz[p] > 1) ? 1 : 0;
@@ -241,8 +241,36 @@ __device__ __forceinline__ int active_before(const VrCtl *ctl, int passes, int u
     return a;
 }
 
+SortJob edge_sort_job(const VrDev &D) {
+    SortJob J;
+    J.key[0] = D.key[0]; J.key[1] = D.key[1];
+    J.val[0] = D.val[0]; J.val[1] = D.val[1];
+    J.hist = &D.ctl->hist8[0][0];
+    J.ticket = &D.ctl->ticket[1];
+    J.st[0] = D.st_sort[0]; J.st[1] = D.st_sort[1];
+    J.count = &D.ctl->n_cand;
+    J.passes = D.passes;
+    return J;
+}
+
+SortJob star_sort_job(const VrDev &D) {
+    SortJob J;
+    J.key[0] = D.ikey[0]; J.key[1] = D.ikey[1];
+    J.val[0] = D.ival[0]; J.val[1] = D.ival[1];
+    J.hist = &D.ctl->hinc[0][0];
+    J.ticket = &D.ctl->ticket[6];
+    J.st[0] = D.ist[0]; J.st[1] = D.ist[1];
+    J.count = &D.ctl->n_inc;
+    J.passes = 2;
+    return J;
+}
+
 // ---------------------------------------------------------- k_sort_pass ----
-__global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(VrDev D, int pass) {
+// Tiles of 2048 keys; each wave ranks its 512 keys among equal digits in
+// order (8 ballots per 64 keys), the work-group combines the waves, one
+// look-back per digit gives the tile's global offsets, and the tile is
+// scattered through LDS so equal digits leave as contiguous runs.
+__global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass) {
     __shared__ uint32_t s_whist[VR_WAVES][VR_RADIX];
     __shared__ uint32_t s_tstart[VR_RADIX];
     __shared__ uint32_t s_gpre[VR_RADIX];
@@ -250,32 +278,29 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(VrDev D, int pass) {
     __shared__ uint32_t s_val[VR_TILE];
     __shared__ uint32_t sh_w[VR_WAVES];
     __shared__ int sh_tile;
-    VrCtl *ctl = D.ctl;
     bool active = false;
-    const int a = active_before(ctl, D.passes, pass, &active);
+    const int a = active_before(J.hist, J.passes, pass, &active);
     if (!active) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const uint32_t Kc = ctl->n_cand;
+    const uint32_t Kc = *J.count;
     const int ntiles = (int)((Kc + VR_TILE - 1) / VR_TILE);
-    const uint32_t *__restrict__ ksrc = D.key[a & 1];
-    const uint32_t *__restrict__ vsrc = D.val[a & 1];
-    uint32_t *__restrict__ kdst = D.key[(a + 1) & 1];
-    uint32_t *__restrict__ vdst = D.val[(a + 1) & 1];
-    uint32_t *st = D.st_sort[a & 1];
-    uint32_t *st_next = D.st_sort[(a + 1) & 1];
+    const uint32_t *__restrict__ ksrc = J.key[a & 1];
+    const uint32_t *__restrict__ vsrc = J.val[a & 1];
+    uint32_t *__restrict__ kdst = J.key[(a + 1) & 1];
+    uint32_t *__restrict__ vdst = J.val[(a + 1) & 1];
+    uint32_t *st = J.st[a & 1];
+    uint32_t *st_next = J.st[(a + 1) & 1];
     const int shift = VR_RADIX_BITS * pass;
 
     // global start of digit t
     uint32_t tot;
-    const uint32_t gstart = block_excl_scan<uint32_t>(ctl->hist8[pass][t], sh_w, &tot);
+    const uint32_t gstart = block_excl_scan<uint32_t>(J.hist[pass * VR_RADIX + t], sh_w, &tot);
 
     for (;;) {
-        const int tile = claim_tile(&ctl->ticket[1 + pass], &sh_tile);
+        const int tile = claim_tile(&J.ticket[pass], &sh_tile);
         if (tile >= ntiles) break;
-#pragma unroll
         for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = 0u;
         __syncthreads();
-        // rank every key among the keys of its digit inside the wave's chunk
         uint32_t kk[VR_ITEMS], vv[VR_ITEMS], rk[VR_ITEMS];
         const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
 #pragma unroll
@@ -301,7 +326,6 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(VrDev D, int pass) {
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
-        // thread t owns digit t: per-wave offsets, tile count, tile-local start
         uint32_t wpre[VR_WAVES];
         uint32_t tc = 0;
 #pragma unroll
@@ -309,7 +333,6 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(VrDev D, int pass) {
         uint32_t ttot;
         const uint32_t tstart = block_excl_scan<uint32_t>(tc, sh_w, &ttot);
         s_tstart[t] = tstart;
-        // look-back over earlier tiles for digit t
         uint32_t prev = 0;
         if (tile == 0) {
             st_store32(st + t, st_pack32(VR_ST_INC, tc));
@@ -320,7 +343,6 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(VrDev D, int pass) {
         }
         s_gpre[t] = gstart + prev;
         st_next[(size_t)tile * VR_RADIX + t] = 0u;
-        // wave offsets per digit, stored over the histogram
         __syncthreads();
 #pragma unroll
         for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = wpre[x];
@@ -351,32 +373,56 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(VrDev D, int pass) {
     }
 }
 
-void launch_sort_pass(const VrDev &D, int pass, hipStream_t s) {
-    long long g = D.ntile_E;
+void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s) {
+    long long g = max_tiles;
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D, pass);
+    hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass);
 }
 
 // -------------------------------------------------------------- k_edges ----
-// Kept edges in rank order, and each edge filed under both of its vertices.
-__global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D, int bin) {
+// Kept edges in rank order.  With triangles wanted, also the list of vertex
+// incidences (vertex, 2r+s) in rank order plus the digit histograms of the
+// vertices, input of the stable star sort, and clear its first statuses.
+__global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
+    __shared__ uint32_t h[2][VR_RADIX];
     VrCtl *ctl = D.ctl;
-    const int a = active_before(ctl, D.passes, VR_MAX_PASSES, nullptr);
+    const int a = active_before(&ctl->hist8[0][0], D.passes, VR_MAX_PASSES, nullptr);
     const uint32_t *__restrict__ kf = D.key[a & 1];
     const uint32_t *__restrict__ vf = D.val[a & 1];
     const long long K = (D.thr_kind == 3) ? (long long)ctl->n_cand : D.K_host;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_kept = (uint32_t)K;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->n_kept = (uint32_t)K;
+        ctl->n_inc = (uint32_t)(2 * K);
+    }
+    if (D.tri) {
+        for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK) (&h[0][0])[x] = 0u;
+        __syncthreads();
+        const long long words = (2 * K + VR_TILE - 1) / VR_TILE * VR_RADIX;
+        for (long long x = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; x < words; x += (long long)gridDim.x * VR_BLOCK)
+            D.ist[0][x] = 0u;
+    }
     for (long long r = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; r < K; r += (long long)gridDim.x * VR_BLOCK) {
         const uint32_t k = kf[r], v = vf[r];
         D.se_q[r] = k;
         D.se_ij[r] = v;
-        if (bin) {
+        if (D.tri) {
             const uint32_t i = v >> 16, j = v & 0xFFFFu;
-            const uint32_t si = atomicAdd(&D.deg[i], 1u);
-            D.inc[(size_t)i * D.n + si] = (uint32_t)r;
-            const uint32_t sj = atomicAdd(&D.deg[j], 1u);
-            D.inc[(size_t)j * D.n + sj] = (uint32_t)r;
+            D.ikey[0][2 * r] = i;
+            D.ikey[0][2 * r + 1] = j;
+            D.ival[0][2 * r] = (uint32_t)(2 * r);
+            D.ival[0][2 * r + 1] = (uint32_t)(2 * r + 1);
+            atomicAdd(&h[0][i & 255u], 1u);
+            atomicAdd(&h[1][i >> 8], 1u);
+            atomicAdd(&h[0][j & 255u], 1u);
+            atomicAdd(&h[1][j >> 8], 1u);
+        }
+    }
+    if (D.tri) {
+        __syncthreads();
+        for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK) {
+            const uint32_t c = (&h[0][0])[x];
+            if (c) atomicAdd(&(&ctl->hinc[0][0])[x], c);
         }
     }
 }
@@ -384,7 +430,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D, int bin) {
 void launch_edges(const VrDev &D, hipStream_t s) {
     long long K = (D.thr_kind == 3) ? D.E : D.K_host;
     long long g = (K + VR_BLOCK - 1) / VR_BLOCK;
-    if (g > 2048) g = 2048;
+    if (g > 1024) g = 1024;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_edges, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D, D.inc != nullptr ? 1 : 0);
+    hipLaunchKernelGGL(k_edges, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
 }

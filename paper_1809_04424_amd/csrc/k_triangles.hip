@@ -1,115 +1,196 @@
-// k_triangles.hip -- per-vertex stars, triangle counting, offsets and the
+// k_triangles.hip -- vertex stars, triangle counting, offsets and the
 // ordered triangle write.
 //
 // Ownership: a triangle enters the filtration with its largest edge (Section
 // 2.1), so the triangles of value r are exactly {a, b, k} with edge r = {a,b}
-// and both {a,k} and {b,k} ranked below r.  For a fixed edge the sorted vertex
-// triples are increasing in k, and edges are visited in rank order through the
-// offsets, so the output comes out in (value, i, j, k) order with no sort.
+// and both {a,k} and {b,k} ranked below r.  Those k are the neighbours of b
+// that come before edge r in b's rank-ordered star (a prefix of that star)
+// and whose edge to a also ranks below r.  For a fixed edge the sorted vertex
+// triples increase with k, and the offsets follow rank order, so the output
+// is written in (value, i, j, k) order with no sort.
 //
-//   k_star        per-vertex segmented sort of incident edge ranks (a stable
+//   k_star        CSR stars from the stably sorted incidences (a stable
 //                 per-column ordering, like the paper's
 //                 integersinsameorderbycolumn, Section 4.3)
-//   k_tri_count   one work-group per vertex a, its rank row staged in LDS;
+//   k_star_pos    position of every edge in both of its stars
+//   k_tri_count   one work-group per vertex a with a's ranks staged in LDS;
 //                 each edge is handled at the endpoint whose partner has the
-//                 shorter earlier-neighbour prefix
+//                 shorter prefix; a wave takes a batch of edges and walks all
+//                 their candidates as one flat stream (full lanes, independent
+//                 loads)
 //   k_scan        exclusive scan of the counts (decoupled look-back)
-//   k_tri_write   the same enumeration; hits go to a per-wave LDS bitset and
-//                 are compacted in k order with wave prefix sums (the paper's
-//                 ballot/popc compaction of init_supp, Section 4.4, on wave64)
+//   k_publish     counts to the host-pinned mailbox
+//   k_tri_write   the same walk; hits set bits of a per-edge LDS bitset, which
+//                 is then compacted in k order with popcounts and wave prefix
+//                 sums (the ballot/popc compaction of the paper's init_supp,
+//                 Section 4.4, on 64-wide waves)
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
-#define VR_MAXN 8192
-#define VR_MAXW (VR_MAXN / 64)
+#define VR_YBUDGET 512  // u64 bitset words per wave in the write kernel
+
+__device__ __forceinline__ int star_parity(const VrCtl *ctl) {
+    // number of active passes of the two-pass star sort, from its histograms
+    __shared__ int sh_nz[2];
+    if (threadIdx.x < 2) sh_nz[threadIdx.x] = 0;
+    __syncthreads();
+    for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK)
+        if ((&ctl->hinc[0][0])[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+    __syncthreads();
+    const int a = (sh_nz[0] > 1 ? 1 : 0) + (sh_nz[1] > 1 ? 1 : 0);
+    __syncthreads();
+    return a & 1;
+}
 
 // --------------------------------------------------------------- k_star ----
 __global__ __launch_bounds__(VR_BLOCK) void k_star(VrDev D) {
-    __shared__ uint32_t s[VR_MAXN];
-    const int v = blockIdx.x, n = D.n, t = threadIdx.x;
-    const uint32_t dg = D.deg[v];
-    uint32_t N = 1;
-    while (N < dg) N <<= 1;
-    uint32_t *__restrict__ row = D.inc + (size_t)v * n;
-    for (uint32_t x = t; x < N; x += VR_BLOCK) s[x] = (x < dg) ? row[x] : 0xFFFFFFFFu;
-    __syncthreads();
-    // bitonic sort of N keys (ranks are distinct)
-    for (uint32_t k = 2; k <= N; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t x = t; x < N; x += VR_BLOCK) {
-                const uint32_t l = x ^ j;
-                if (l > x) {
-                    const uint32_t a = s[x], b = s[l];
-                    const bool up = (x & k) == 0;
-                    if ((a > b) == up) { s[x] = b; s[l] = a; }
-                }
-            }
-            __syncthreads();
-        }
+    const VrCtl *ctl = D.ctl;
+    const int par = star_parity(ctl);
+    const uint32_t *__restrict__ kf = D.ikey[par];
+    const uint32_t *__restrict__ vf = D.ival[par];
+    const long long m = (long long)ctl->n_inc;
+    const int n = D.n;
+    if (m == 0) {
+        if (blockIdx.x == 0)
+            for (int u = threadIdx.x; u <= n; u += VR_BLOCK) D.start[u] = 0u;
+        return;
     }
-    uint16_t *__restrict__ nrow = D.nbr + (size_t)v * n;
-    for (uint32_t x = t; x < dg; x += VR_BLOCK) {
-        const uint32_t r = s[x];
+    for (long long p = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; p < m; p += (long long)gridDim.x * VR_BLOCK) {
+        const uint32_t v = kf[p], x = vf[p];
+        const uint32_t r = x >> 1;
         const uint32_t ij = D.se_ij[r];
-        const uint32_t i = ij >> 16, j = ij & 0xFFFFu;
-        const bool small = (i == (uint32_t)v);
-        row[x] = r;
-        nrow[x] = (uint16_t)(small ? j : i);
-        D.pos[2 * (size_t)r + (small ? 0 : 1)] = (uint16_t)x;
+        D.star_r[p] = r;
+        D.star_nbr[p] = (uint16_t)((x & 1u) ? (ij >> 16) : (ij & 0xFFFFu));
+        const int prev = (p == 0) ? -1 : (int)kf[p - 1];
+        for (int u = prev + 1; u <= (int)v; u++) D.start[u] = (uint32_t)p;
+        if (p == m - 1)
+            for (int u = (int)v + 1; u <= n; u++) D.start[u] = (uint32_t)m;
     }
+}
+
+__global__ __launch_bounds__(VR_BLOCK) void k_star_pos(VrDev D) {
+    const VrCtl *ctl = D.ctl;
+    const int par = star_parity(ctl);
+    const uint32_t *__restrict__ kf = D.ikey[par];
+    const uint32_t *__restrict__ vf = D.ival[par];
+    const long long m = (long long)ctl->n_inc;
+    for (long long p = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; p < m; p += (long long)gridDim.x * VR_BLOCK)
+        D.pos[vf[p]] = (uint16_t)(p - D.start[kf[p]]);
 }
 
 void launch_star(const VrDev &D, hipStream_t s) {
-    hipLaunchKernelGGL(k_star, dim3(D.n), dim3(VR_BLOCK), 0, s, D);
+    long long g = (2 * ((D.thr_kind == 3) ? D.E : D.K_host) + VR_BLOCK - 1) / VR_BLOCK;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_star, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_star_pos, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
 }
 
 // ------------------------------------------------- shared enumeration core ----
-// Stage the rank row of vertex a: Ra[k] = rank of edge {a,k}, or VR_NOT_KEPT.
-__device__ __forceinline__ uint32_t stage_row(const VrDev &D, int a, uint32_t *Ra) {
-    const int n = D.n;
-    for (int k = threadIdx.x; k < n; k += VR_BLOCK) Ra[k] = VR_NOT_KEPT;
+// Stage the ranks of vertex a: Ra[k] = rank of edge {a,k}, or VR_NOT_KEPT.
+__device__ __forceinline__ void stage_row(const VrDev &D, int a, uint32_t *Ra, uint32_t s0, uint32_t s1) {
+    for (int k = threadIdx.x; k < D.n; k += VR_BLOCK) Ra[k] = VR_NOT_KEPT;
     __syncthreads();
-    const uint32_t dg = D.deg[a];
-    const uint32_t *__restrict__ row = D.inc + (size_t)a * n;
-    const uint16_t *__restrict__ nrow = D.nbr + (size_t)a * n;
-    for (uint32_t x = threadIdx.x; x < dg; x += VR_BLOCK) Ra[nrow[x]] = row[x];
+    for (uint32_t p = s0 + threadIdx.x; p < s1; p += VR_BLOCK) Ra[D.star_nbr[p]] = D.star_r[p];
     __syncthreads();
-    return dg;
 }
 
-// Edge at position x of a's star: rank r, partner b, and the length of b's
-// prefix of neighbours joined by lower-ranked edges.  Returns whether a owns
-// the edge's enumeration (the partner's prefix is the shorter one).
-__device__ __forceinline__ bool edge_at(const VrDev &D, int a, uint32_t x, uint32_t *r, uint32_t *b, uint32_t *pb) {
-    const size_t o = (size_t)a * D.n + x;
-    const uint32_t rr = D.inc[o];
-    const uint32_t bb = D.nbr[o];
-    const uint32_t p = D.pos[2 * (size_t)rr + (bb > (uint32_t)a ? 1 : 0)];
-    *r = rr;
-    *b = bb;
-    *pb = p;
-    return p < x || (p == x && (uint32_t)a < bb);
+// Per-wave batch descriptors in LDS.
+struct Batch {
+    uint32_t r[VR_WAVE];
+    uint32_t sb[VR_WAVE];   // start of the partner's star
+    uint32_t b[VR_WAVE];
+    uint32_t beg[VR_WAVE];  // flat offset of the edge's candidates
+    uint32_t end[VR_WAVE];
+    uint32_t cnt[VR_WAVE];
+    unsigned long long off[VR_WAVE];
+};
+
+// Load the metadata of star entries [p0, p0+nb) of vertex a, keep the edges a
+// owns, compact them into the batch (in star order) and lay their candidate
+// prefixes end to end.  Returns (owned count, total candidates).
+template <bool WRITE>
+__device__ __forceinline__ void load_batch(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, int nb,
+                                           Batch &B, int *m_out, uint32_t *S_out) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t p = p0 + (uint32_t)lane;
+    bool owned = false;
+    uint32_t r = 0, b = 0, pb = 0;
+    if (lane < nb && p < s1) {
+        r = D.star_r[p];
+        b = D.star_nbr[p];
+        pb = D.pos[2 * (size_t)r + (b > (uint32_t)a ? 1 : 0)];
+        const uint32_t x = p - s0;
+        owned = pb < x || (pb == x && (uint32_t)a < b);
+    }
+    const unsigned long long mask = ballot64(owned);
+    const uint32_t idx = (uint32_t)__popcll(mask & lanemask_lt());
+    const uint32_t len = owned ? pb : 0u;
+    const uint32_t incl = wave_incl_scan(len);
+    if (owned) {
+        B.r[idx] = r;
+        B.b[idx] = b;
+        B.sb[idx] = D.start[b];
+        B.beg[idx] = incl - len;
+        B.end[idx] = incl;
+        B.cnt[idx] = 0u;
+        if (WRITE) B.off[idx] = D.off[r];
+    }
+    *m_out = __popcll(mask);
+    *S_out = __shfl(incl, VR_WAVE - 1, VR_WAVE);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Walk the flat candidate stream of a batch: candidate f of edge e is the
+// neighbour star_nbr[sb_e + f - beg_e] of the partner; it is a hit when its
+// edge to a ranks below r_e.  Count hits per edge, and with WRITE set the
+// hit's bit in the edge's bitset.
+template <bool WRITE>
+__device__ __forceinline__ void walk_batch(const VrDev &D, const uint32_t *Ra, Batch &B, int m, uint32_t S,
+                                           unsigned long long *Y, int W) {
+    const int lane = threadIdx.x & 63;
+    int seg = 0;
+    for (uint32_t f0 = 0; f0 < S; f0 += VR_WAVE) {
+        const uint32_t f = f0 + (uint32_t)lane;
+        if (f < S) {
+            while (seg < m - 1 && B.end[seg] <= f) seg++;
+            const uint32_t k = D.star_nbr[B.sb[seg] + (f - B.beg[seg])];
+            if (Ra[k] < B.r[seg]) {
+                if (WRITE) atomicOr(&Y[seg * W + (k >> 6)], 1ull << (k & 63));
+                else atomicAdd(&B.cnt[seg], 1u);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // ----------------------------------------------------------- k_tri_count ----
 __global__ __launch_bounds__(VR_BLOCK) void k_tri_count(VrDev D) {
-    __shared__ uint32_t Ra[VR_MAXN];
+    extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
-    const uint32_t dg = stage_row(D, a, Ra);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (uint32_t x = w; x < dg; x += VR_WAVES) {
-        uint32_t r, b, pb;
-        if (!edge_at(D, a, x, &r, &b, &pb)) continue;
-        const uint16_t *__restrict__ pre = D.nbr + (size_t)b * n;
-        uint32_t c = 0;
-        for (uint32_t y = lane; y < pb; y += VR_WAVE) c += (Ra[pre[y]] < r) ? 1u : 0u;
-        c = wave_sum(c);
-        if (lane == 0) D.cnt[r] = c;
+    uint32_t *Ra = lds;
+    Batch *Bs = (Batch *)(lds + ((n + 3) & ~3));
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Batch &B = Bs[w];
+    const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
+    stage_row(D, a, Ra, s0, s1);
+    for (uint32_t p0 = s0 + (uint32_t)w * VR_WAVE; p0 < s1; p0 += VR_WAVES * VR_WAVE) {
+        int m;
+        uint32_t S;
+        load_batch<false>(D, a, s0, s1, p0, VR_WAVE, B, &m, &S);
+        if (m == 0) continue;
+        walk_batch<false>(D, Ra, B, m, S, nullptr, 0);
+        if (lane < m) D.cnt[B.r[lane]] = B.cnt[lane];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
+size_t batch_lds(int n) { return 4 * (size_t)((n + 3) & ~3) + VR_WAVES * sizeof(Batch); }
+
 void launch_tri_count(const VrDev &D, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_count, dim3(D.n), dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_tri_count, dim3(D.n), dim3(VR_BLOCK), batch_lds(D.n), s, D);
 }
 
 // ---------------------------------------------------------------- k_scan ----
@@ -163,42 +244,69 @@ void launch_scan(const VrDev &D, long long Kmax, hipStream_t s) {
     hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
 }
 
+// ------------------------------------------------------------- k_publish ----
+__global__ void k_publish(VrDev D) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const VrCtl *ctl = D.ctl;
+    VrMailbox *mb = D.mailbox;
+    __hip_atomic_store(&mb->flags, ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->n_cand, ctl->n_cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->n_kept, ctl->n_kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->n_tri, D.tri ? ctl->n_tri : 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->seq, D.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const VrDev &D, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, D);
+}
+
 // ----------------------------------------------------------- k_tri_write ----
+__device__ __forceinline__ int write_batch_cap(int W) {
+    int c = VR_YBUDGET / W;
+    return c < 1 ? 1 : (c > VR_WAVE ? VR_WAVE : c);
+}
+
 __global__ __launch_bounds__(VR_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
-    __shared__ uint32_t Ra[VR_MAXN];
-    __shared__ unsigned long long Y[VR_WAVES][VR_MAXW];
+    extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int W = (n + 63) >> 6;
-    for (int x = lane; x < W; x += VR_WAVE) Y[w][x] = 0ull;
-    const uint32_t dg = stage_row(D, a, Ra);
-    for (uint32_t x = w; x < dg; x += VR_WAVES) {
-        uint32_t r, b, pb;
-        if (!edge_at(D, a, x, &r, &b, &pb)) continue;
-        const uint16_t *__restrict__ pre = D.nbr + (size_t)b * n;
-        for (uint32_t y = lane; y < pb; y += VR_WAVE) {
-            const uint32_t k = pre[y];
-            if (Ra[k] < r) atomicOr(&Y[w][k >> 6], 1ull << (k & 63));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        unsigned long long o = D.off[r];
-        for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
-            const int wi = x0 + lane;
-            unsigned long long word = 0ull;
-            if (wi < W) {
-                word = Y[w][wi];
-                Y[w][wi] = 0ull;
+    const int cap = write_batch_cap(W);
+    uint32_t *Ra = lds;
+    Batch *Bs = (Batch *)(lds + ((n + 3) & ~3));
+    unsigned long long *Yall = (unsigned long long *)(Bs + VR_WAVES);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Batch &B = Bs[w];
+    unsigned long long *Y = Yall + (size_t)w * cap * W;
+    for (int x = lane; x < cap * W; x += VR_WAVE) Y[x] = 0ull;
+    const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
+    stage_row(D, a, Ra, s0, s1);
+    for (uint32_t p0 = s0 + (uint32_t)w * cap; p0 < s1; p0 += (uint32_t)(VR_WAVES * cap)) {
+        int m;
+        uint32_t S;
+        load_batch<true>(D, a, s0, s1, p0, cap, B, &m, &S);
+        if (m == 0) continue;
+        walk_batch<true>(D, Ra, B, m, S, Y, W);
+        for (int e = 0; e < m; e++) {
+            const uint32_t r = B.r[e], bb = B.b[e];
+            unsigned long long o = B.off[e];
+            unsigned long long *Ye = Y + (size_t)e * W;
+            for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
+                const int wi = x0 + lane;
+                unsigned long long word = 0ull;
+                if (wi < W) {
+                    word = Ye[wi];
+                    Ye[wi] = 0ull;
+                }
+                const uint32_t pc = (uint32_t)__popcll(word);
+                const uint32_t inc = wave_incl_scan(pc);
+                unsigned long long p = o + (inc - pc);
+                while (word) {
+                    const int bit = __ffsll((long long)word) - 1;
+                    out[p++] = tri_key(r, (uint32_t)a, bb, (uint32_t)(wi * 64 + bit));
+                    word &= word - 1ull;
+                }
+                o += __shfl(inc, VR_WAVE - 1, VR_WAVE);
             }
-            const uint32_t pc = (uint32_t)__popcll(word);
-            const uint32_t inc = wave_incl_scan(pc);
-            unsigned long long p = o + (inc - pc);
-            while (word) {
-                const int bit = __ffsll((long long)word) - 1;
-                out[p++] = tri_key(r, (uint32_t)a, b, (uint32_t)(wi * 64 + bit));
-                word &= word - 1ull;
-            }
-            o += __shfl(inc, VR_WAVE - 1, VR_WAVE);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -206,7 +314,11 @@ __global__ __launch_bounds__(VR_BLOCK) void k_tri_write(VrDev D, unsigned long l
 }
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(VR_BLOCK), 0, s, D, tri_out);
+    const int W = (D.n + 63) >> 6;
+    int cap = 512 / W;
+    cap = cap < 1 ? 1 : (cap > 64 ? 64 : cap);
+    const size_t lds = batch_lds(D.n) + (size_t)VR_WAVES * cap * W * 8;
+    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(VR_BLOCK), lds, s, D, tri_out);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

@@ -2,15 +2,18 @@
 // planning, the two-phase launch sequence and result ownership.
 //
 // Phase 1 (one stream, no host round trip): distances -> threshold select ->
-// radix passes -> kept edges -> stars -> triangle counts -> offsets.
-// One 32-byte device-to-host read of (candidates, K, T, flags) and one stream
-// synchronisation size the outputs.  Phase 2: ordered triangle write and the
+// edge radix passes -> kept edges -> star radix passes -> stars -> triangle
+// counts -> offsets -> publish.  The last kernel stores (flags, K, T) into a
+// host-pinned mailbox; the host polls it (no stream synchronisation), sizes
+// the outputs, and enqueues phase 2: the ordered triangle write and the
 // public edge arrays.  The workspace is released in stream order.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <string.h>
+#include <immintrin.h>
 
 #include "vr.h"
 #include "vr_device.h"
@@ -66,21 +69,25 @@ void tune_pool(int dev) {
     });
 }
 
-// Pinned status buffer per host thread, for the single count read-back.
-struct Pinned {
-    uint32_t *p = nullptr;
-    ~Pinned() {
-        if (p) (void)hipHostFree(p);
+// Host-pinned, device-visible mailbox per host thread for the count read-back.
+struct Mailbox {
+    VrMailbox *h = nullptr;
+    VrMailbox *d = nullptr;
+    uint32_t seq = 0;
+    ~Mailbox() {
+        if (h) (void)hipHostFree(h);
     }
 };
-thread_local Pinned g_pinned;
+thread_local Mailbox g_mb;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
-    size_t off_ctl, off_deg, off_stsel, zero_bytes;
+    size_t off_ctl, off_stscan, off_stsel, zero_bytes;
     size_t off_q, off_key0, off_key1, off_val0, off_val1, off_st0, off_st1;
-    size_t off_seij, off_seq, off_inc, off_nbr, off_pos, off_cnt, off_off, off_stscan;
+    size_t off_seij, off_seq;
+    size_t off_ikey0, off_ikey1, off_ival0, off_ival1, off_ist0, off_ist1;
+    size_t off_star_r, off_star_nbr, off_start, off_pos, off_cnt, off_off;
     size_t total;
 };
 
@@ -88,12 +95,12 @@ Plan plan(long long n, long long E, long long Kmax, bool tri) {
     Plan P{};
     const long long ntE = (E + VR_TILE - 1) / VR_TILE;
     const long long ntK = (Kmax + VR_TILE - 1) / VR_TILE;
+    const long long ntI = (2 * Kmax + VR_TILE - 1) / VR_TILE;
     size_t o = 0;
-    // zeroed region: control block, degrees, select and scan statuses
+    // zeroed region: control block, select and scan statuses
     P.off_ctl = o; o += sizeof(VrCtl);
     o = (o + 15) & ~(size_t)15;
     P.off_stscan = o; o += 8 * (size_t)(ntK > 0 ? ntK : 1);
-    P.off_deg = o; o += sizeof(uint32_t) * (size_t)n;
     P.off_stsel = o; o += sizeof(uint32_t) * (size_t)(ntE > 0 ? ntE : 1);
     P.zero_bytes = (o + 3) & ~(size_t)3;
     o = align_up(o);
@@ -107,8 +114,15 @@ Plan plan(long long n, long long E, long long Kmax, bool tri) {
     P.off_seij = o; o = align_up(o + 4 * (size_t)Kmax);
     P.off_seq = o; o = align_up(o + 4 * (size_t)Kmax);
     if (tri) {
-        P.off_inc = o; o = align_up(o + 4 * (size_t)n * (size_t)n);
-        P.off_nbr = o; o = align_up(o + 2 * (size_t)n * (size_t)n);
+        P.off_ikey0 = o; o = align_up(o + 8 * (size_t)Kmax);
+        P.off_ikey1 = o; o = align_up(o + 8 * (size_t)Kmax);
+        P.off_ival0 = o; o = align_up(o + 8 * (size_t)Kmax);
+        P.off_ival1 = o; o = align_up(o + 8 * (size_t)Kmax);
+        P.off_ist0 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntI > 0 ? ntI : 1));
+        P.off_ist1 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntI > 0 ? ntI : 1));
+        P.off_star_r = o; o = align_up(o + 8 * (size_t)Kmax);
+        P.off_star_nbr = o; o = align_up(o + 4 * (size_t)Kmax);
+        P.off_start = o; o = align_up(o + 4 * (size_t)(n + 1));
         P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
@@ -236,7 +250,8 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     const bool want_edges = req->maxdim >= 1;
     const bool want_tri = req->maxdim >= 2 && n >= 3;
     const bool count_only = (req->flags & VR_COUNT_ONLY) != 0;
-    const bool timing = (req->flags & VR_TIMING) != 0;
+    const bool timing_all = (req->flags & VR_TIMING) != 0;
+    const bool timing = timing_all || (req->flags & VR_TIMING_WRITE) != 0;
 
     Result *res = new (std::nothrow) Result();
     if (!res) return VR_ENOMEM;
@@ -263,7 +278,7 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
             if (hipEventCreate(&res->ev[i]) != hipSuccess) return fail(VR_EHIP, nullptr, 0);
     }
     auto mark = [&](int i) {
-        if (timing) {
+        if (timing_all || (timing && (i == ST_WRITE || i == ST_EMIT))) {
             (void)hipEventRecord(res->ev[i], s);
             res->ev_used[i] = true;
         }
@@ -279,6 +294,19 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
 
     const long long Kmax = (Khost >= 0) ? Khost : E;
     const Plan P = plan(n, E, Kmax, want_tri);
+    if (!g_mb.h) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, sizeof(VrMailbox), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+            return fail(VR_ENOMEM, nullptr, 0);
+        void *d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipHostFree(h);
+            return fail(VR_EHIP, nullptr, 0);
+        }
+        memset(h, 0, sizeof(VrMailbox));
+        g_mb.h = (VrMailbox *)h;
+        g_mb.d = (VrMailbox *)d;
+    }
     char *ws = (char *)A.get(P.total);
     if (!ws) return fail(VR_ENOMEM, nullptr, 0);
 
@@ -293,8 +321,12 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     D.passes = (key_bits(req->dtype, req->d) + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
     if (D.passes < 1) D.passes = 1;
     D.need_hist = (req->thr_kind == VR_THR_COUNT || req->thr_kind == VR_THR_FRACTION) ? 1 : 0;
+    D.tri = want_tri ? 1 : 0;
+    D.mailbox = g_mb.d;
+    D.seq = ++g_mb.seq;
+    if (D.seq == 0) D.seq = ++g_mb.seq;
     D.ctl = (VrCtl *)(ws + P.off_ctl);
-    D.deg = (uint32_t *)(ws + P.off_deg);
+    D.st_scan = (unsigned long long *)(ws + P.off_stscan);
     D.st_sel = (uint32_t *)(ws + P.off_stsel);
     D.q = (uint32_t *)(ws + P.off_q);
     D.key[0] = (uint32_t *)(ws + P.off_key0);
@@ -306,14 +338,21 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     D.se_ij = (uint32_t *)(ws + P.off_seij);
     D.se_q = (uint32_t *)(ws + P.off_seq);
     if (want_tri) {
-        D.inc = (uint32_t *)(ws + P.off_inc);
-        D.nbr = (uint16_t *)(ws + P.off_nbr);
+        D.ikey[0] = (uint32_t *)(ws + P.off_ikey0);
+        D.ikey[1] = (uint32_t *)(ws + P.off_ikey1);
+        D.ival[0] = (uint32_t *)(ws + P.off_ival0);
+        D.ival[1] = (uint32_t *)(ws + P.off_ival1);
+        D.ist[0] = (uint32_t *)(ws + P.off_ist0);
+        D.ist[1] = (uint32_t *)(ws + P.off_ist1);
+        D.star_r = (uint32_t *)(ws + P.off_star_r);
+        D.star_nbr = (uint16_t *)(ws + P.off_star_nbr);
+        D.start = (uint32_t *)(ws + P.off_start);
         D.pos = (uint16_t *)(ws + P.off_pos);
         D.cnt = (uint32_t *)(ws + P.off_cnt);
         D.off = (unsigned long long *)(ws + P.off_off);
-        D.st_scan = (unsigned long long *)(ws + P.off_stscan);
     }
     D.ntile_E = (E + VR_TILE - 1) / VR_TILE;
+    D.ntile_I = (2 * Kmax + VR_TILE - 1) / VR_TILE;
 
     // ---------------------------------------------------------- phase 1 ----
     mark(ST_DIST);
@@ -322,41 +361,54 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     mark(ST_SELECT);
     launch_select(D, s);
     mark(ST_SORT);
-    for (int p = 0; p < D.passes; p++) launch_sort_pass(D, p, s);
-    mark(ST_EDGES);
-    if (want_tri) {
-        launch_edges(D, s);
-    } else {
-        // edges only: no vertex binning
-        VrDev D2 = D;
-        D2.inc = nullptr;
-        launch_edges(D2, s);
+    {
+        const SortJob J = edge_sort_job(D);
+        for (int p = 0; p < D.passes; p++) launch_sort_pass(J, D.ntile_E, p, s);
     }
+    mark(ST_EDGES);
+    launch_edges(D, s);
     mark(ST_STAR);
-    if (want_tri) launch_star(D, s);
+    if (want_tri) {
+        const SortJob J = star_sort_job(D);
+        launch_sort_pass(J, D.ntile_I, 0, s);
+        launch_sort_pass(J, D.ntile_I, 1, s);
+        launch_star(D, s);
+    }
     mark(ST_COUNT);
     if (want_tri) launch_tri_count(D, s);
     mark(ST_SCAN);
     // the scan reads K from the device (unknown on the host for SQDIST)
     if (want_tri) launch_scan(D, Kmax, s);
+    launch_publish(D, s);
     mark(ST_SYNC);
-    if (hipGetLastError() != hipSuccess) return fail(VR_EHIP, ws, P.total);
-    if (!g_pinned.p) {
-        if (hipHostMalloc((void **)&g_pinned.p, 64, hipHostMallocDefault) != hipSuccess) {
-            g_pinned.p = nullptr;
-            (void)hipStreamSynchronize(s);
-            return fail(VR_ENOMEM, ws, P.total);
-        }
-    }
-    uint32_t *hp = g_pinned.p;
-    if (hipMemcpyAsync(hp, &D.ctl->flags, 24, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);
         return fail(VR_EHIP, ws, P.total);
     }
-    const uint32_t flags = hp[0];
-    const long long K = (long long)hp[2];
-    unsigned long long T = want_tri ? ((unsigned long long)hp[4] | ((unsigned long long)hp[5] << 32)) : 0ull;
+    // Poll the mailbox; check the stream now and then so that a failed launch
+    // cannot leave the host waiting.
+    {
+        volatile VrMailbox *mb = g_mb.h;
+        unsigned long long spins = 0;
+        while (__atomic_load_n(&g_mb.h->seq, __ATOMIC_ACQUIRE) != D.seq) {
+            if ((++spins & 4095ull) == 0) {
+                hipError_t q = hipStreamQuery(s);
+                if (q == hipSuccess) {
+                    if (__atomic_load_n(&g_mb.h->seq, __ATOMIC_ACQUIRE) == D.seq) break;
+                    return fail(VR_EHIP, ws, P.total);
+                }
+                if (q != hipErrorNotReady) {
+                    (void)hipGetLastError();
+                    return fail(VR_EHIP, ws, P.total);
+                }
+            }
+            _mm_pause();
+        }
+        (void)mb;
+    }
+    const uint32_t flags = g_mb.h->flags;
+    const long long K = (long long)g_mb.h->n_kept;
+    unsigned long long T = want_tri ? g_mb.h->n_tri : 0ull;
     if (flags & 1u) return fail(VR_ERANGE, ws, P.total);
     if (K > VR_MAX_EDGES) return fail(VR_E2BIG, ws, P.total);
 

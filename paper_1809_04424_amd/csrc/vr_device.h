@@ -24,14 +24,26 @@
 
 // Control block in device memory, zeroed at the start of every build.
 struct VrCtl {
-    uint32_t ticket[8];             // tile tickets: 0 select, 1..4 sort passes, 5 scan
+    uint32_t ticket[16];            // tile tickets: 0 select, 1..4 edge sort, 5 scan, 6..7 star sort
     uint32_t flags;                 // bit 0: a squared distance overflowed 32 bits
     uint32_t n_cand;                // candidates kept by the select pass
     uint32_t n_kept;                // K
-    uint32_t pad0;
+    uint32_t n_inc;                 // 2K vertex incidences
     unsigned long long n_tri;       // T
-    uint32_t hist8[VR_MAX_PASSES][VR_RADIX];  // digit histograms of the candidates
+    uint32_t hist8[VR_MAX_PASSES][VR_RADIX];  // digit histograms of the edge candidates
+    uint32_t hinc[2][VR_RADIX];     // digit histograms of the incidence vertices
     uint32_t bucket[VR_NBUCKET];    // log-linear histogram of all squared distances
+};
+
+// Host-pinned mailbox: the end of phase 1 publishes the counts here; the
+// host polls `seq` instead of synchronising the stream.
+struct VrMailbox {
+    uint32_t seq;
+    uint32_t flags;
+    uint32_t n_cand;
+    uint32_t n_kept;
+    unsigned long long n_tri;
+    unsigned long long pad[5];
 };
 
 // ---------------------------------------------------------------- lanes ----
@@ -173,6 +185,17 @@ __device__ __forceinline__ void pair_of(long long e, long long n, int *pi, int *
 }
 
 // ------------------------------------------------------- launch wrappers ----
+// One stable LSD radix sort (keys with values) over a device-side count.
+struct SortJob {
+    uint32_t *key[2];
+    uint32_t *val[2];
+    const uint32_t *hist;     // [passes][VR_RADIX] digit histograms of all keys
+    uint32_t *ticket;         // one tile ticket per pass
+    uint32_t *st[2];          // look-back statuses, by parity of the active pass
+    const uint32_t *count;    // number of items
+    int passes;
+};
+
 struct VrDev {
     // shape
     int n, d, dtype;
@@ -180,34 +203,44 @@ struct VrDev {
     int thr_kind;
     long long thr_num;
     long long K_host;       // K when known before the build (else -1)
-    int passes;             // radix passes launched (covering the key width)
+    int passes;             // radix passes launched for the edge keys
     int need_hist;          // histogram select needed (COUNT / FRACTION)
+    int tri;                // triangles wanted
     // workspace
     VrCtl *ctl;
-    uint32_t *q;            // E
-    uint32_t *key[2];       // E each, ping-pong
+    VrMailbox *mailbox;     // host-pinned
+    uint32_t seq;
+    uint32_t *q;            // E squared distances
+    uint32_t *key[2];       // E each, ping-pong (edge sort)
     uint32_t *val[2];       // E each (i<<16 | j)
     uint32_t *st_sel;       // ceil(E/TILE) select statuses
-    uint32_t *st_sort[2];   // ceil(E/TILE)*RADIX sort statuses (by active-pass parity)
-    uint32_t *se_ij;        // K: sorted kept edges (i<<16|j)
+    uint32_t *st_sort[2];   // ceil(E/TILE)*RADIX edge-sort statuses
+    uint32_t *se_ij;        // K sorted kept edges (i<<16|j)
     uint32_t *se_q;         // K
-    uint32_t *deg;          // n
-    uint32_t *inc;          // n*n: per-vertex incident edge ranks (rank order after star sort)
-    uint16_t *nbr;          // n*n: per-vertex neighbours in rank order
-    uint16_t *pos;          // 2K: position of edge r in the star of its smaller/larger vertex
-    uint32_t *cnt;          // K: triangles per value
-    unsigned long long *off;     // K: exclusive offsets
+    uint32_t *ikey[2];      // 2K incidence vertices, ping-pong (star sort)
+    uint32_t *ival[2];      // 2K incidence ids 2r+s
+    uint32_t *ist[2];       // ceil(2K/TILE)*RADIX star-sort statuses
+    uint32_t *star_r;       // 2K: CSR stars, ranks ascending within a vertex
+    uint16_t *star_nbr;     // 2K: the other endpoint
+    uint32_t *start;        // n+1 CSR row starts
+    uint16_t *pos;          // 2K: position of edge r in the star of endpoint s (id 2r+s)
+    uint32_t *cnt;          // K triangles per value
+    unsigned long long *off;     // K exclusive offsets
     unsigned long long *st_scan; // ceil(K/TILE)
-    long long ntile_E;
+    long long ntile_E, ntile_I;
 };
+
+SortJob edge_sort_job(const VrDev &D);
+SortJob star_sort_job(const VrDev &D);
 
 void launch_init(const VrDev &D, size_t zero_words, hipStream_t s);
 void launch_dist(const VrDev &D, const void *points, hipStream_t s);
 void launch_select(const VrDev &D, hipStream_t s);
-void launch_sort_pass(const VrDev &D, int pass, hipStream_t s);
+void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s);
 void launch_edges(const VrDev &D, hipStream_t s);
 void launch_star(const VrDev &D, hipStream_t s);
 void launch_tri_count(const VrDev &D, hipStream_t s);
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
+void launch_publish(const VrDev &D, hipStream_t s);
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s);
 void launch_emit_edges(const VrDev &D, long long K, uint32_t *edge_ij, long long *edge_q, hipStream_t s);

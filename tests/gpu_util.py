@@ -12,14 +12,14 @@ def decode_keys(keys) -> np.ndarray:
                     axis=1).astype(np.int64)
 
 
-def gpu_build(cloud, maxdim=2, count_only=False, timing=False, device="cuda:0"):
+def gpu_build(cloud, maxdim=2, count_only=False, timing=False, device="cuda:0", allocator="library"):
     """Run one build on the GPU; returns (result, host dict of numpy arrays)."""
     import torch
 
     import paper_1809_04424_amd as vr
 
     pts = torch.from_numpy(np.ascontiguousarray(cloud.points)).to(device)
-    res = vr.build(pts, cloud.thr, maxdim=maxdim, count_only=count_only, timing=timing)
+    res = vr.build(pts, cloud.thr, maxdim=maxdim, count_only=count_only, timing=timing, allocator=allocator)
     torch.cuda.synchronize()
     out = {
         "counts": res.counts,

@@ -49,7 +49,7 @@ SMALL = [
     workloads.uniform_cloud(13, 130, 3, thr=("count", 3, 1)),
     workloads.uniform_cloud(14, 131, 3, thr=("count", 0, 1)),
     workloads.uniform_cloud(15, 200, 64, thr=("fraction", 7, 100)),
-    workloads.uniform_cloud(16, 150, 5, dtype=np.int16, lo=-30000, hi=30000, thr=("fraction", 30, 100)),
+    workloads.uniform_cloud(16, 150, 5, dtype=np.int16, lo=-10000, hi=10000, thr=("fraction", 30, 100)),  # q < 2^31
     workloads.uniform_cloud(17, 150, 2, dtype=np.int32, lo=0, hi=20000, thr=("fraction", 25, 100)),
     workloads.uniform_cloud(19, 100, 3, thr=("sqdist", 10 ** 12, 0)),  # tau above every q: all kept
     workloads.uniform_cloud(20, 100, 3, thr=("sqdist", 0, 0)),         # nothing kept
@@ -137,10 +137,14 @@ def test_mixture4000_sampled(orc):
         assert np.array_equal(seg, rows), f"value {r}"
 
 
-def test_int32_overflow_is_reported():
+@pytest.mark.parametrize("dtype,lo,hi,d", [(np.int32, -2 ** 30, 2 ** 30, 3), (np.int16, -30000, 30000, 5),
+                                            (np.int32, 0, 50000, 4)])
+def test_overflow_is_reported(orc, dtype, lo, hi, d):
+    """A squared distance of 2^32 or more is rejected with VR_ERANGE."""
     import paper_1809_04424_amd as vr
 
-    c = workloads.uniform_cloud(40, 20, 3, dtype=np.int32, lo=-2 ** 30, hi=2 ** 30)
+    c = workloads.uniform_cloud(40, 20, d, dtype=dtype, lo=lo, hi=hi)
+    assert orc.sqdist(c.points).max() >= 2 ** 32
     with pytest.raises(vr.VrError) as e:
         gpu_build(c)
     assert e.value.code == vr.VR_ERANGE
@@ -151,3 +155,65 @@ def test_full_threshold_binomials():
         c = workloads.uniform_cloud(n, n, 2, dtype=np.int32, lo=0, hi=1023)
         _, out = gpu_build(c)
         assert out["counts"] == (n, math.comb(n, 2), math.comb(n, 3))
+
+
+@pytest.mark.parametrize("pts,ok", [
+    ([[0], [65535]], True),            # q = 65535^2 = 2^32 - 2^17 + 1
+    ([[0, 0], [65535, 361]], True),    # q = 2^32 - 2^17 + 1 + 130321 < 2^32
+    ([[0], [65536]], False),           # q = 2^32
+    ([[0, 0], [65535, 363]], False),   # q = 2^32 + 698
+])
+def test_key_width_boundary(orc, pts, ok):
+    import paper_1809_04424_amd as vr
+
+    c = workloads.Cloud(np.array(pts, np.int32), ("full", 0, 1))
+    q = int(orc.sqdist(c.points)[0])
+    assert (q < 2 ** 32) == ok
+    if ok:
+        _, out = gpu_build(c)
+        assert out["edge_q"].tolist() == [q]
+    else:
+        with pytest.raises(vr.VrError) as e:
+            gpu_build(c)
+        assert e.value.code == vr.VR_ERANGE
+
+
+def test_torch_allocator_path(orc):
+    """Outputs through torch's caching allocator equal the library-pool path."""
+    c = workloads.noisy_circle(n=600)
+    f = orc.build(c.points, c.thr)
+    _, out = gpu_build(c, allocator="torch")
+    assert_matches_oracle(out, f)
+
+
+def test_outputs_outlive_handle(orc):
+    """Tensors keep the library's output memory alive after the handle goes."""
+    import gc
+
+    import torch
+
+    c = workloads.noisy_circle(n=400)
+    f = orc.build(c.points, c.thr)
+    res, _ = gpu_build(c)
+    keys = res.tri_key()
+    ij = res.edge_ij()
+    del res
+    gc.collect()
+    for _ in range(3):  # reuse of freed pool memory must not touch live outputs
+        gpu_build(workloads.noisy_circle(seed=9, n=400))
+    torch.cuda.synchronize()
+    assert np.array_equal(decode_keys(keys.cpu().numpy()), f.tris)
+    assert np.array_equal(ij.cpu().numpy()[:, 0], f.ei)
+
+
+def test_stage_timing_reports_every_stage():
+    import paper_1809_04424_amd as vr
+
+    c = workloads.noisy_circle(n=300)
+    res, _ = gpu_build(c, timing=True)
+    st = res.stage_ms()
+    assert list(st) == vr.stage_names()
+    assert st["tri_write"] > 0 and st["dist"] > 0
+    res2, _ = gpu_build(c, timing="write")
+    st2 = res2.stage_ms()
+    assert st2["tri_write"] > 0 and st2["dist"] == 0
