@@ -196,8 +196,8 @@ class Result:
     def _tensor(self, ptr, count, dtype, typestr, itemsize, shape):
         import torch
 
-        if not ptr or count == 0:
-            return torch.empty(shape if count else (0,) + tuple(shape[1:]), dtype=dtype, device=self._device)
+        if not ptr or count == 0:  # nothing written (count-only build) or empty
+            return torch.empty((0,) + tuple(shape[1:]), dtype=dtype, device=self._device)
         if self._block is not None:  # torch-allocated block
             off = ptr - self._p_q
             return self._block[off: off + count * itemsize].view(dtype).view(shape)

@@ -183,17 +183,19 @@ __global__ __launch_bounds__(VR_BLOCK) void k_select(VrDev D) {
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan<uint32_t>(c, sh_w, &tot);
-        if (t == 0) {
+        if (t < VR_WAVE) {
             uint32_t prefix = 0;
             if (tile == 0) {
-                st_store32(D.st_sel, st_pack32(VR_ST_INC, tot));
+                if (t == 0) st_store32(D.st_sel, st_pack32(VR_ST_INC, tot));
             } else {
-                st_store32(D.st_sel + tile, st_pack32(VR_ST_AGG, tot));
-                prefix = lookback32(D.st_sel, tile, 1);
-                st_store32(D.st_sel + tile, st_pack32(VR_ST_INC, prefix + tot));
+                if (t == 0) st_store32(D.st_sel + tile, st_pack32(VR_ST_AGG, tot));
+                prefix = lookback32_wave(D.st_sel, tile);
+                if (t == 0) st_store32(D.st_sel + tile, st_pack32(VR_ST_INC, prefix + tot));
             }
-            sh_prefix = prefix;
-            if (tile == ntiles - 1) ctl->n_cand = prefix + tot;
+            if (t == 0) {
+                sh_prefix = prefix;
+                if (tile == ntiles - 1) ctl->n_cand = prefix + tot;
+            }
         }
         // clear this tile's statuses for the first active radix pass
         D.st_sort[0][(size_t)tile * VR_RADIX + t] = 0u;

@@ -1,0 +1,99 @@
+// k_gram.hip -- squared distances of int8 points through the Gram identity
+// q_ij = |x_i|^2 + |x_j|^2 - 2 <x_i, x_j>, with the inner products on the
+// matrix cores (v_mfma_i32_16x16x64_i8: 16x16 output tile, 64-deep int8
+// products, exact int32 accumulation).  Exact: |<x,y>| <= 16384 d and
+// q <= 65025 d, both in int32 / uint32 for the dimensions routed here.
+//
+// A work-group owns a 64 x 64 tile of pairs (row block bi <= column block
+// bj).  Both blocks of points are staged in LDS, zero-padded to a multiple
+// of 64 coordinates (zeros change neither norms nor products).  Wave w
+// computes rows 16w..16w+15 against the four 16-column blocks.  Each lane
+// feeds the same 16-byte slice of coordinates to the A and B operands, so
+// the products pair coordinates consistently for any lane-to-k assignment of
+// the instruction.
+#include "vr_device.h"
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+#define GRAM_TB 64
+#define GRAM_KC 64  // coordinates per MFMA step
+
+__global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(const int8_t *__restrict__ pts, int n, int d, int dpad,
+                                                      int need_hist, uint32_t *__restrict__ q,
+                                                      VrCtl *__restrict__ ctl) {
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bi > bj) return;
+    extern __shared__ int4 lds4[];
+    int8_t *xi = (int8_t *)lds4;                  // GRAM_TB * dpad
+    int8_t *xj = xi + GRAM_TB * dpad;             // GRAM_TB * dpad
+    int32_t *ni = (int32_t *)(xj + GRAM_TB * dpad);
+    int32_t *nj = ni + GRAM_TB;
+    uint32_t *hist = (uint32_t *)(nj + GRAM_TB);  // VR_NBUCKET
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+
+    // stage both blocks (zero rows past n and coordinates past d)
+    for (int x = t; x < GRAM_TB * dpad; x += VR_BLOCK) {
+        const int r = x / dpad, c = x % dpad;
+        const int gi = bi * GRAM_TB + r, gj = bj * GRAM_TB + r;
+        xi[x] = (gi < n && c < d) ? pts[(size_t)gi * d + c] : (int8_t)0;
+        xj[x] = (gj < n && c < d) ? pts[(size_t)gj * d + c] : (int8_t)0;
+    }
+    if (need_hist)
+        for (int b = t; b < VR_NBUCKET; b += VR_BLOCK) hist[b] = 0u;
+    __syncthreads();
+    if (t < 2 * GRAM_TB) {
+        const int8_t *row = (t < GRAM_TB) ? xi + t * dpad : xj + (t - GRAM_TB) * dpad;
+        int32_t s = 0;
+        for (int c = 0; c < dpad; c++) s += (int32_t)row[c] * (int32_t)row[c];
+        if (t < GRAM_TB) ni[t] = s;
+        else nj[t - GRAM_TB] = s;
+    }
+    __syncthreads();
+
+    v4i acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++) acc[cb] = (v4i){0, 0, 0, 0};
+    const int r16 = lane & 15, g = lane >> 4;
+    for (int k0 = 0; k0 < dpad; k0 += GRAM_KC) {
+        const v4i a = *(const v4i *)(xi + (w * 16 + r16) * dpad + k0 + g * 16);
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) {
+            const v4i b = *(const v4i *)(xj + (cb * 16 + r16) * dpad + k0 + g * 16);
+            acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[cb], 0, 0, 0);
+        }
+    }
+
+    uint32_t *hist_or_null = need_hist ? hist : nullptr;
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++) {
+        const int jl = cb * 16 + r16;
+        const int j = bj * GRAM_TB + jl;
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) {
+            const int il = w * 16 + g * 4 + ii;
+            const int i = bi * GRAM_TB + il;
+            if (i < j && j < n) {
+                const uint32_t qq = (uint32_t)(ni[il] + nj[jl] - 2 * acc[cb][ii]);
+                q[row_start(i, n) + (j - i - 1)] = qq;
+                if (hist_or_null) atomicAdd(&hist_or_null[bucket_of(qq)], 1u);
+            }
+        }
+    }
+    if (need_hist) {
+        __syncthreads();
+        for (int b = t; b < VR_NBUCKET; b += VR_BLOCK)
+            if (hist[b]) atomicAdd(&ctl->bucket[b], hist[b]);
+    }
+}
+
+size_t gram_lds(int dpad) { return 2 * (size_t)GRAM_TB * dpad + 2 * GRAM_TB * 4 + VR_NBUCKET * 4; }
+
+// Route int8 clouds with enough coordinates to the matrix cores.
+bool gram_applies(const VrDev &D) { return D.dtype == 1 && D.d >= 16 && D.d <= 256; }
+
+void launch_gram(const VrDev &D, const void *points, hipStream_t s) {
+    const int nb = (D.n + GRAM_TB - 1) / GRAM_TB;
+    const int dpad = (D.d + GRAM_KC - 1) / GRAM_KC * GRAM_KC;
+    hipLaunchKernelGGL(k_gram_i8, dim3(nb, nb), dim3(VR_BLOCK), gram_lds(dpad), s, (const int8_t *)points, D.n,
+                       D.d, dpad, D.need_hist, D.q, D.ctl);
+}

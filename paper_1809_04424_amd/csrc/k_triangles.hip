@@ -145,20 +145,47 @@ __device__ __forceinline__ void load_batch(const VrDev &D, int a, uint32_t s0, u
 // Walk the flat candidate stream of a batch: candidate f of edge e is the
 // neighbour star_nbr[sb_e + f - beg_e] of the partner; it is a hit when its
 // edge to a ranks below r_e.  Count hits per edge, and with WRITE set the
-// hit's bit in the edge's bitset.
+// hit's bit in the edge's bitset.  VR_UNROLL chunks of 64 candidates are in
+// flight at once: all loads of a round are issued before any is consumed.
+#define VR_UNROLL 8
 template <bool WRITE>
 __device__ __forceinline__ void walk_batch(const VrDev &D, const uint32_t *Ra, Batch &B, int m, uint32_t S,
                                            unsigned long long *Y, int W) {
     const int lane = threadIdx.x & 63;
     int seg = 0;
-    for (uint32_t f0 = 0; f0 < S; f0 += VR_WAVE) {
-        const uint32_t f = f0 + (uint32_t)lane;
-        if (f < S) {
-            while (seg < m - 1 && B.end[seg] <= f) seg++;
-            const uint32_t k = D.star_nbr[B.sb[seg] + (f - B.beg[seg])];
-            if (Ra[k] < B.r[seg]) {
-                if (WRITE) atomicOr(&Y[seg * W + (k >> 6)], 1ull << (k & 63));
-                else atomicAdd(&B.cnt[seg], 1u);
+    for (uint32_t f0 = 0; f0 < S; f0 += VR_WAVE * VR_UNROLL) {
+        uint32_t kk[VR_UNROLL];
+        int sg[VR_UNROLL];
+#pragma unroll
+        for (int u = 0; u < VR_UNROLL; u++) {
+            const uint32_t f = f0 + (uint32_t)(u * VR_WAVE + lane);
+            sg[u] = -1;
+            kk[u] = 0;
+            if (f < S) {
+                while (seg < m - 1 && B.end[seg] <= f) seg++;
+                sg[u] = seg;
+                kk[u] = D.star_nbr[B.sb[seg] + (f - B.beg[seg])];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < VR_UNROLL; u++) {
+            const int g = sg[u];
+            const bool hit = g >= 0 && Ra[kk[u]] < B.r[g];
+            if (WRITE) {
+                if (hit) atomicOr(&Y[g * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
+            } else {
+                // segments are contiguous lane ranges: one add per segment
+                const unsigned long long hits = ballot64(hit);
+                const int gp = __shfl_up(g, 1, VR_WAVE);
+                const bool first = g >= 0 && (lane == 0 || gp != g);
+                const unsigned long long starts = ballot64(first);
+                if (first) {
+                    const unsigned long long above = starts & ~((2ull << lane) - 1ull);
+                    const unsigned long long upto = above ? (above & (~above + 1ull)) - 1ull : ~0ull;
+                    const unsigned long long mine = upto & ~((1ull << lane) - 1ull);
+                    const uint32_t c = (uint32_t)__popcll(hits & mine);
+                    if (c) atomicAdd(&B.cnt[g], c);
+                }
             }
         }
     }
@@ -215,17 +242,19 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
         }
         unsigned long long tot;
         const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
-        if (t == 0) {
+        if (t < VR_WAVE) {
             unsigned long long prefix = 0;
             if (tile == 0) {
-                st_store64(D.st_scan, st_pack64(VR_ST_INC, tot));
+                if (t == 0) st_store64(D.st_scan, st_pack64(VR_ST_INC, tot));
             } else {
-                st_store64(D.st_scan + tile, st_pack64(VR_ST_AGG, tot));
-                prefix = lookback64(D.st_scan, tile);
-                st_store64(D.st_scan + tile, st_pack64(VR_ST_INC, prefix + tot));
+                if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_AGG, tot));
+                prefix = lookback64_wave(D.st_scan, tile);
+                if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_INC, prefix + tot));
             }
-            sh_prefix = prefix;
-            if (tile == ntiles - 1) ctl->n_tri = prefix + tot;
+            if (t == 0) {
+                sh_prefix = prefix;
+                if (tile == ntiles - 1) ctl->n_tri = prefix + tot;
+            }
         }
         __syncthreads();
         unsigned long long o = sh_prefix + ex;

@@ -357,7 +357,8 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     // ---------------------------------------------------------- phase 1 ----
     mark(ST_DIST);
     launch_init(D, P.zero_bytes / 4, s);
-    launch_dist(D, req->points, s);
+    if (gram_applies(D)) launch_gram(D, req->points, s);
+    else launch_dist(D, req->points, s);
     mark(ST_SELECT);
     launch_select(D, s);
     mark(ST_SORT);

@@ -114,28 +114,75 @@ __device__ __forceinline__ unsigned long long st_pack64(uint32_t state, unsigned
 }
 
 // Decoupled look-back (Merrill and Garland, "Single-pass Parallel Prefix Scan
-// with Decoupled Look-back", 2016): walk back over the predecessors' status
-// words, summing aggregates until an inclusive prefix is found.  Every
-// predecessor tile was claimed by a running work-group through the ticket
-// counter, so each wait ends.
+// with Decoupled Look-back", 2016): sum the predecessors' aggregates back to
+// the nearest inclusive prefix.  Every predecessor tile was claimed earlier by
+// a running work-group through the ticket counter, so every wait ends.
+//
+// Per-digit form (one thread per digit): eight predecessors are polled with
+// independent loads per round.
 __device__ __forceinline__ uint32_t lookback32(const uint32_t *st, int tile, int stride) {
     uint32_t acc = 0;
-    for (int t = tile - 1; t >= 0; t--) {
-        uint32_t s;
-        while (((s = st_load32(st + (size_t)t * stride)) >> 30) == VR_ST_NONE) __builtin_amdgcn_s_sleep(1);
-        acc += s & 0x3FFFFFFFu;
-        if ((s >> 30) == VR_ST_INC) break;
+    for (int t = tile - 1; t >= 0; t -= 8) {
+        uint32_t s[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) s[j] = (t - j >= 0) ? st_load32(st + (size_t)(t - j) * stride) : (VR_ST_INC << 30);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            while ((s[j] >> 30) == VR_ST_NONE) {
+                __builtin_amdgcn_s_sleep(1);
+                s[j] = st_load32(st + (size_t)(t - j) * stride);
+            }
+            acc += s[j] & 0x3FFFFFFFu;
+            if ((s[j] >> 30) == VR_ST_INC) return acc;
+        }
     }
     return acc;
 }
 
-__device__ __forceinline__ unsigned long long lookback64(const unsigned long long *st, int tile) {
+// Wave form (all 64 lanes of one wave, same `tile`): 64 predecessors per
+// round; returns the exclusive prefix in every lane.
+__device__ __forceinline__ uint32_t lookback32_wave(const uint32_t *st, int tile) {
+    const int lane = (int)lane_id();
+    uint32_t acc = 0;
+    for (int base = tile - 1; base >= 0; base -= VR_WAVE) {
+        const int t = base - lane;
+        for (;;) {
+            const uint32_t s = (t >= 0) ? st_load32(st + t) : (VR_ST_INC << 30);
+            const unsigned long long inc = ballot64((s >> 30) == VR_ST_INC);
+            const unsigned long long none = ballot64((s >> 30) == VR_ST_NONE);
+            const int first = inc ? (__ffsll((long long)inc) - 1) : VR_WAVE;
+            const unsigned long long need = (first >= VR_WAVE - 1) ? ~0ull : ((2ull << first) - 1ull);
+            if (none & need) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            acc += wave_sum<uint32_t>(lane <= first ? (s & 0x3FFFFFFFu) : 0u);
+            if (first < VR_WAVE) return acc;
+            break;
+        }
+    }
+    return acc;
+}
+
+__device__ __forceinline__ unsigned long long lookback64_wave(const unsigned long long *st, int tile) {
+    const int lane = (int)lane_id();
     unsigned long long acc = 0;
-    for (int t = tile - 1; t >= 0; t--) {
-        unsigned long long s;
-        while (((s = st_load64(st + t)) >> 62) == VR_ST_NONE) __builtin_amdgcn_s_sleep(1);
-        acc += s & 0x3FFFFFFFFFFFFFFFull;
-        if ((s >> 62) == VR_ST_INC) break;
+    for (int base = tile - 1; base >= 0; base -= VR_WAVE) {
+        const int t = base - lane;
+        for (;;) {
+            const unsigned long long s = (t >= 0) ? st_load64(st + t) : ((unsigned long long)VR_ST_INC << 62);
+            const unsigned long long inc = ballot64((s >> 62) == VR_ST_INC);
+            const unsigned long long none = ballot64((s >> 62) == VR_ST_NONE);
+            const int first = inc ? (__ffsll((long long)inc) - 1) : VR_WAVE;
+            const unsigned long long need = (first >= VR_WAVE - 1) ? ~0ull : ((2ull << first) - 1ull);
+            if (none & need) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            acc += wave_sum<unsigned long long>(lane <= first ? (s & 0x3FFFFFFFFFFFFFFFull) : 0ull);
+            if (first < VR_WAVE) return acc;
+            break;
+        }
     }
     return acc;
 }
@@ -235,6 +282,8 @@ SortJob star_sort_job(const VrDev &D);
 
 void launch_init(const VrDev &D, size_t zero_words, hipStream_t s);
 void launch_dist(const VrDev &D, const void *points, hipStream_t s);
+bool gram_applies(const VrDev &D);
+void launch_gram(const VrDev &D, const void *points, hipStream_t s);
 void launch_select(const VrDev &D, hipStream_t s);
 void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s);
 void launch_edges(const VrDev &D, hipStream_t s);

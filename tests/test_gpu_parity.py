@@ -55,6 +55,10 @@ SMALL = [
     workloads.uniform_cloud(20, 100, 3, thr=("sqdist", 0, 0)),         # nothing kept
     workloads.uniform_cloud(21, 333, 130, thr=("fraction", 12, 100)),  # several coordinate chunks
     workloads.lattice_cloud(22, 500, side=4, d=3, thr=("fraction", 20, 100)),  # heavy ties across tiles
+    workloads.uniform_cloud(23, 150, 37, thr=("fraction", 20, 100)),   # matrix-core path, padded depth
+    workloads.uniform_cloud(24, 100, 256, thr=("fraction", 30, 100)),  # deepest matrix-core input
+    workloads.uniform_cloud(25, 90, 257, thr=("fraction", 30, 100)),   # vector path past it
+    workloads.uniform_cloud(26, 150, 64, lo=-128, hi=-100, thr=("count", 4000, 1)),  # -128 extremes
 ]
 
 
