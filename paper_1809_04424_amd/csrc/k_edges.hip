@@ -74,20 +74,18 @@ __global__ __launch_bounds__(VR_BLOCK) void k_dist(const T *__restrict__ pts, in
             }
         }
     }
-    if (j < n) {
-        const long long rs = 0;
-        (void)rs;
 #pragma unroll
-        for (int m = 0; m < 16; m++) {
-            const int i = bi * DIST_TB + w + 4 * m;
-            if (i < j) {
-                unsigned long long v = acc[m];
-                if (v > 0xFFFFFFFFull) { over = 1u; v = 0xFFFFFFFFull; }
-                const uint32_t qq = (uint32_t)v;
-                q[row_start(i, n) + (j - i - 1)] = qq;
-                if (need_hist) atomicAdd(&hist[bucket_of(qq)], 1u);
-            }
+    for (int m = 0; m < 16; m++) {
+        const int i = bi * DIST_TB + w + 4 * m;
+        const bool ok = i < j && j < n;
+        uint32_t qq = 0;
+        if (ok) {
+            unsigned long long v = acc[m];
+            if (v > 0xFFFFFFFFull) { over = 1u; v = 0xFFFFFFFFull; }
+            qq = (uint32_t)v;
+            q[row_start(i, n) + (j - i - 1)] = qq;
         }
+        if (need_hist) match_add<11>(hist, bucket_of(qq), ok);
     }
     if (over) atomicOr(&ctl->flags, 1u);
     if (need_hist) {
@@ -206,11 +204,13 @@ __global__ __launch_bounds__(VR_BLOCK) void k_select(VrDev D) {
             if (keep[m]) {
                 D.key[0][p] = qv[m];
                 D.val[0][p] = ((uint32_t)pi << 16) | (uint32_t)pj;
-                for (int ps = 0; ps < D.passes; ps++) atomicAdd(&h8[ps][(qv[m] >> (8 * ps)) & 255u], 1u);
                 p++;
             }
             if (++pj == D.n) { pi++; pj = pi + 1; }
         }
+        for (int ps = 0; ps < D.passes; ps++)
+#pragma unroll
+            for (int m = 0; m < VR_ITEMS; m++) match_add<8>(h8[ps], (qv[m] >> (8 * ps)) & 255u, keep[m]);
     }
     __syncthreads();
     for (int x = t; x < D.passes * VR_RADIX; x += VR_BLOCK) {
@@ -404,20 +404,28 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
         for (long long x = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; x < words; x += (long long)gridDim.x * VR_BLOCK)
             D.ist[0][x] = 0u;
     }
-    for (long long r = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; r < K; r += (long long)gridDim.x * VR_BLOCK) {
-        const uint32_t k = kf[r], v = vf[r];
-        D.se_q[r] = k;
-        D.se_ij[r] = v;
+    const long long Kr = (K + VR_BLOCK - 1) / VR_BLOCK * VR_BLOCK;  // whole waves take part in match_add
+    for (long long r = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; r < Kr; r += (long long)gridDim.x * VR_BLOCK) {
+        const bool ok = r < K;
+        uint32_t i = 0, j = 0;
+        if (ok) {
+            const uint32_t k = kf[r], v = vf[r];
+            D.se_q[r] = k;
+            D.se_ij[r] = v;
+            i = v >> 16;
+            j = v & 0xFFFFu;
+            if (D.tri) {
+                D.ikey[0][2 * r] = i;
+                D.ikey[0][2 * r + 1] = j;
+                D.ival[0][2 * r] = (uint32_t)(2 * r);
+                D.ival[0][2 * r + 1] = (uint32_t)(2 * r + 1);
+            }
+        }
         if (D.tri) {
-            const uint32_t i = v >> 16, j = v & 0xFFFFu;
-            D.ikey[0][2 * r] = i;
-            D.ikey[0][2 * r + 1] = j;
-            D.ival[0][2 * r] = (uint32_t)(2 * r);
-            D.ival[0][2 * r + 1] = (uint32_t)(2 * r + 1);
-            atomicAdd(&h[0][i & 255u], 1u);
-            atomicAdd(&h[1][i >> 8], 1u);
-            atomicAdd(&h[0][j & 255u], 1u);
-            atomicAdd(&h[1][j >> 8], 1u);
+            match_add<8>(h[0], i & 255u, ok);
+            match_add<5>(h[1], i >> 8, ok);
+            match_add<8>(h[0], j & 255u, ok);
+            match_add<5>(h[1], j >> 8, ok);
         }
     }
     if (D.tri) {

@@ -63,7 +63,6 @@ __global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(const int8_t *__restrict__
         }
     }
 
-    uint32_t *hist_or_null = need_hist ? hist : nullptr;
 #pragma unroll
     for (int cb = 0; cb < 4; cb++) {
         const int jl = cb * 16 + r16;
@@ -72,11 +71,13 @@ __global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(const int8_t *__restrict__
         for (int ii = 0; ii < 4; ii++) {
             const int il = w * 16 + g * 4 + ii;
             const int i = bi * GRAM_TB + il;
-            if (i < j && j < n) {
-                const uint32_t qq = (uint32_t)(ni[il] + nj[jl] - 2 * acc[cb][ii]);
+            const bool ok = i < j && j < n;
+            uint32_t qq = 0;
+            if (ok) {
+                qq = (uint32_t)(ni[il] + nj[jl] - 2 * acc[cb][ii]);
                 q[row_start(i, n) + (j - i - 1)] = qq;
-                if (hist_or_null) atomicAdd(&hist_or_null[bucket_of(qq)], 1u);
             }
+            if (need_hist) match_add<11>(hist, bucket_of(qq), ok);
         }
     }
     if (need_hist) {

@@ -27,7 +27,6 @@
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
-#define VR_YBUDGET 512  // u64 bitset words per wave in the write kernel
 
 __device__ __forceinline__ int star_parity(const VrCtl *ctl) {
     // number of active passes of the two-pass star sort, from its histograms
@@ -87,73 +86,97 @@ void launch_star(const VrDev &D, hipStream_t s) {
 }
 
 // ------------------------------------------------- shared enumeration core ----
-// Stage the ranks of vertex a: Ra[k] = rank of edge {a,k}, or VR_NOT_KEPT.
-__device__ __forceinline__ void stage_row(const VrDev &D, int a, uint32_t *Ra, uint32_t s0, uint32_t s1) {
-    for (int k = threadIdx.x; k < D.n; k += VR_BLOCK) Ra[k] = VR_NOT_KEPT;
-    __syncthreads();
-    for (uint32_t p = s0 + threadIdx.x; p < s1; p += VR_BLOCK) Ra[D.star_nbr[p]] = D.star_r[p];
-    __syncthreads();
-}
+// One work-group per vertex a.  Its star is taken in chunks of ENUM_BLOCK
+// entries; the edges a owns in a chunk are compacted (star order = rank
+// order) and their candidate prefixes laid end to end.  The flat candidate
+// range is split evenly over the waves (each wave a contiguous part, lanes
+// interleaved), so a vertex's late, long-prefix edges do not serialise on one
+// wave.  Eight chunks of 64 candidates are in flight per wave per round.
+#define ENUM_BLOCK 512
+#define ENUM_WAVES (ENUM_BLOCK / VR_WAVE)
+#define VR_UNROLL 8
+#define VR_YBUDGET 2048  // u64 bitset words per work-group in the write kernel
 
-// Per-wave batch descriptors in LDS.
-struct Batch {
-    uint32_t r[VR_WAVE];
-    uint32_t sb[VR_WAVE];   // start of the partner's star
-    uint32_t b[VR_WAVE];
-    uint32_t beg[VR_WAVE];  // flat offset of the edge's candidates
-    uint32_t end[VR_WAVE];
-    uint32_t cnt[VR_WAVE];
-    unsigned long long off[VR_WAVE];
+struct EnumLds {
+    uint32_t r[ENUM_BLOCK];
+    uint32_t b[ENUM_BLOCK];
+    uint32_t sb[ENUM_BLOCK];
+    uint32_t beg[ENUM_BLOCK + 1];
+    uint32_t cnt[ENUM_BLOCK];
+    unsigned long long off[ENUM_BLOCK];
+    uint32_t scan[ENUM_WAVES];
+    uint32_t scan2[ENUM_WAVES];
 };
 
-// Load the metadata of star entries [p0, p0+nb) of vertex a, keep the edges a
-// owns, compact them into the batch (in star order) and lay their candidate
-// prefixes end to end.  Returns (owned count, total candidates).
+__device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uint32_t *total) {
+    const uint32_t inc = wave_incl_scan(x);
+    const int w = threadIdx.x / VR_WAVE;
+    if (lane_id() == VR_WAVE - 1) sh[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < ENUM_WAVES; i++) {
+        const uint32_t v = sh[i];
+        if (i < w) off += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+// Compact the owned edges of star entries [p0, p0+ENUM_BLOCK) into L.
+// Returns the number of owned edges; L.beg[0..m] is their flat layout.
 template <bool WRITE>
-__device__ __forceinline__ void load_batch(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, int nb,
-                                           Batch &B, int *m_out, uint32_t *S_out) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t p = p0 + (uint32_t)lane;
+__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L) {
+    const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0;
-    if (lane < nb && p < s1) {
+    if (p < s1) {
         r = D.star_r[p];
         b = D.star_nbr[p];
         pb = D.pos[2 * (size_t)r + (b > (uint32_t)a ? 1 : 0)];
         const uint32_t x = p - s0;
         owned = pb < x || (pb == x && (uint32_t)a < b);
     }
-    const unsigned long long mask = ballot64(owned);
-    const uint32_t idx = (uint32_t)__popcll(mask & lanemask_lt());
-    const uint32_t len = owned ? pb : 0u;
-    const uint32_t incl = wave_incl_scan(len);
+    uint32_t m, S;
+    const uint32_t idx = enum_excl_scan(owned ? 1u : 0u, L.scan, &m);
+    const uint32_t fb = enum_excl_scan(owned ? pb : 0u, L.scan2, &S);
     if (owned) {
-        B.r[idx] = r;
-        B.b[idx] = b;
-        B.sb[idx] = D.start[b];
-        B.beg[idx] = incl - len;
-        B.end[idx] = incl;
-        B.cnt[idx] = 0u;
-        if (WRITE) B.off[idx] = D.off[r];
+        L.r[idx] = r;
+        L.b[idx] = b;
+        L.sb[idx] = D.start[b];
+        L.beg[idx] = fb;
+        L.cnt[idx] = 0u;
+        if (WRITE) L.off[idx] = D.off[r];
     }
-    *m_out = __popcll(mask);
-    *S_out = __shfl(incl, VR_WAVE - 1, VR_WAVE);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    if (threadIdx.x == 0) L.beg[m] = S;
+    __syncthreads();
+    return (int)m;
 }
 
-// Walk the flat candidate stream of a batch: candidate f of edge e is the
-// neighbour star_nbr[sb_e + f - beg_e] of the partner; it is a hit when its
-// edge to a ranks below r_e.  Count hits per edge, and with WRITE set the
-// hit's bit in the edge's bitset.  VR_UNROLL chunks of 64 candidates are in
-// flight at once: all loads of a round are issued before any is consumed.
-#define VR_UNROLL 8
+// Walk candidates [f_lo, f_hi) of edges e_lo.. (flat layout L.beg): the
+// candidate f of edge e is star_nbr[sb_e + f - beg_e]; a hit when its rank to
+// a is below r_e.  Without WRITE, hits are counted per edge (one LDS add per
+// edge run within 64 lanes); with WRITE, set in bitset Y row (e - e_lo).
 template <bool WRITE>
-__device__ __forceinline__ void walk_batch(const VrDev &D, const uint32_t *Ra, Batch &B, int m, uint32_t S,
-                                           unsigned long long *Y, int W) {
-    const int lane = threadIdx.x & 63;
-    int seg = 0;
-    for (uint32_t f0 = 0; f0 < S; f0 += VR_WAVE * VR_UNROLL) {
+__device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, EnumLds &L, int e_lo, int e_hi,
+                                     uint32_t f_lo, uint32_t f_hi, unsigned long long *Y, int W) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t span = f_hi - f_lo;
+    const uint32_t per = (span + ENUM_WAVES - 1) / ENUM_WAVES;
+    const uint32_t my_lo = f_lo + min(span, per * (uint32_t)w);
+    const uint32_t my_hi = f_lo + min(span, per * (uint32_t)(w + 1));
+    if (my_lo >= my_hi) return;
+    // first edge whose range reaches my_lo
+    int lo = e_lo, hi = e_hi - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.beg[mid] <= my_lo) lo = mid;
+        else hi = mid - 1;
+    }
+    int seg = lo;
+    for (uint32_t f0 = my_lo; f0 < my_hi; f0 += VR_WAVE * VR_UNROLL) {
         uint32_t kk[VR_UNROLL];
         int sg[VR_UNROLL];
 #pragma unroll
@@ -161,20 +184,19 @@ __device__ __forceinline__ void walk_batch(const VrDev &D, const uint32_t *Ra, B
             const uint32_t f = f0 + (uint32_t)(u * VR_WAVE + lane);
             sg[u] = -1;
             kk[u] = 0;
-            if (f < S) {
-                while (seg < m - 1 && B.end[seg] <= f) seg++;
+            if (f < my_hi) {
+                while (seg < e_hi - 1 && L.beg[seg + 1] <= f) seg++;
                 sg[u] = seg;
-                kk[u] = D.star_nbr[B.sb[seg] + (f - B.beg[seg])];
+                kk[u] = D.star_nbr[L.sb[seg] + (f - L.beg[seg])];
             }
         }
 #pragma unroll
         for (int u = 0; u < VR_UNROLL; u++) {
             const int g = sg[u];
-            const bool hit = g >= 0 && Ra[kk[u]] < B.r[g];
+            const bool hit = g >= 0 && Ra[kk[u]] < L.r[g];
             if (WRITE) {
-                if (hit) atomicOr(&Y[g * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
+                if (hit) atomicOr(&Y[(g - e_lo) * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
             } else {
-                // segments are contiguous lane ranges: one add per segment
                 const unsigned long long hits = ballot64(hit);
                 const int gp = __shfl_up(g, 1, VR_WAVE);
                 const bool first = g >= 0 && (lane == 0 || gp != g);
@@ -184,40 +206,42 @@ __device__ __forceinline__ void walk_batch(const VrDev &D, const uint32_t *Ra, B
                     const unsigned long long upto = above ? (above & (~above + 1ull)) - 1ull : ~0ull;
                     const unsigned long long mine = upto & ~((1ull << lane) - 1ull);
                     const uint32_t c = (uint32_t)__popcll(hits & mine);
-                    if (c) atomicAdd(&B.cnt[g], c);
+                    if (c) atomicAdd(&L.cnt[g], c);
                 }
             }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
 }
 
+__device__ __forceinline__ void stage_row(const VrDev &D, uint32_t *Ra, uint32_t s0, uint32_t s1) {
+    for (int k = threadIdx.x; k < D.n; k += ENUM_BLOCK) Ra[k] = VR_NOT_KEPT;
+    __syncthreads();
+    for (uint32_t p = s0 + threadIdx.x; p < s1; p += ENUM_BLOCK) Ra[D.star_nbr[p]] = D.star_r[p];
+    __syncthreads();
+}
+
+size_t enum_lds(int n) { return 4 * (size_t)((n + 3) & ~3) + sizeof(EnumLds); }
+
 // ----------------------------------------------------------- k_tri_count ----
-__global__ __launch_bounds__(VR_BLOCK) void k_tri_count(VrDev D) {
+__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
     extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
     uint32_t *Ra = lds;
-    Batch *Bs = (Batch *)(lds + ((n + 3) & ~3));
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Batch &B = Bs[w];
+    EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
-    stage_row(D, a, Ra, s0, s1);
-    for (uint32_t p0 = s0 + (uint32_t)w * VR_WAVE; p0 < s1; p0 += VR_WAVES * VR_WAVE) {
-        int m;
-        uint32_t S;
-        load_batch<false>(D, a, s0, s1, p0, VR_WAVE, B, &m, &S);
+    stage_row(D, Ra, s0, s1);
+    for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
+        const int m = load_chunk<false>(D, a, s0, s1, p0, L);
         if (m == 0) continue;
-        walk_batch<false>(D, Ra, B, m, S, nullptr, 0);
-        if (lane < m) D.cnt[B.r[lane]] = B.cnt[lane];
-        __builtin_amdgcn_wave_barrier();
+        walk<false>(D, Ra, L, 0, m, 0, L.beg[m], nullptr, 0);
+        __syncthreads();
+        if ((int)threadIdx.x < m) D.cnt[L.r[threadIdx.x]] = L.cnt[threadIdx.x];
+        __syncthreads();
     }
 }
 
-size_t batch_lds(int n) { return 4 * (size_t)((n + 3) & ~3) + VR_WAVES * sizeof(Batch); }
-
 void launch_tri_count(const VrDev &D, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_count, dim3(D.n), dim3(VR_BLOCK), batch_lds(D.n), s, D);
+    hipLaunchKernelGGL(k_tri_count, dim3(D.n), dim3(ENUM_BLOCK), enum_lds(D.n), s, D);
 }
 
 // ---------------------------------------------------------------- k_scan ----
@@ -291,63 +315,62 @@ void launch_publish(const VrDev &D, hipStream_t s) {
 
 // ----------------------------------------------------------- k_tri_write ----
 __device__ __forceinline__ int write_batch_cap(int W) {
-    int c = VR_YBUDGET / W;
-    return c < 1 ? 1 : (c > VR_WAVE ? VR_WAVE : c);
+    const int c = VR_YBUDGET / W;
+    return c < 1 ? 1 : (c > ENUM_BLOCK ? ENUM_BLOCK : c);
 }
 
-__global__ __launch_bounds__(VR_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
+__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
     extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
     const int W = (n + 63) >> 6;
     const int cap = write_batch_cap(W);
     uint32_t *Ra = lds;
-    Batch *Bs = (Batch *)(lds + ((n + 3) & ~3));
-    unsigned long long *Yall = (unsigned long long *)(Bs + VR_WAVES);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Batch &B = Bs[w];
-    unsigned long long *Y = Yall + (size_t)w * cap * W;
-    for (int x = lane; x < cap * W; x += VR_WAVE) Y[x] = 0ull;
+    EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
+    unsigned long long *Y = (unsigned long long *)(&L + 1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int x = threadIdx.x; x < cap * W; x += ENUM_BLOCK) Y[x] = 0ull;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
-    stage_row(D, a, Ra, s0, s1);
-    for (uint32_t p0 = s0 + (uint32_t)w * cap; p0 < s1; p0 += (uint32_t)(VR_WAVES * cap)) {
-        int m;
-        uint32_t S;
-        load_batch<true>(D, a, s0, s1, p0, cap, B, &m, &S);
-        if (m == 0) continue;
-        walk_batch<true>(D, Ra, B, m, S, Y, W);
-        for (int e = 0; e < m; e++) {
-            const uint32_t r = B.r[e], bb = B.b[e];
-            unsigned long long o = B.off[e];
-            unsigned long long *Ye = Y + (size_t)e * W;
-            for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
-                const int wi = x0 + lane;
-                unsigned long long word = 0ull;
-                if (wi < W) {
-                    word = Ye[wi];
-                    Ye[wi] = 0ull;
+    stage_row(D, Ra, s0, s1);
+    for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
+        const int m = load_chunk<true>(D, a, s0, s1, p0, L);
+        for (int e0 = 0; e0 < m; e0 += cap) {
+            const int e1 = min(m, e0 + cap);
+            walk<true>(D, Ra, L, e0, e1, L.beg[e0], L.beg[e1], Y, W);
+            __syncthreads();
+            // emit: wave w takes edges e0+w, e0+w+ENUM_WAVES, ...
+            for (int e = e0 + w; e < e1; e += ENUM_WAVES) {
+                const uint32_t r = L.r[e], bb = L.b[e];
+                unsigned long long o = L.off[e];
+                unsigned long long *Ye = Y + (size_t)(e - e0) * W;
+                for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
+                    const int wi = x0 + lane;
+                    unsigned long long word = 0ull;
+                    if (wi < W) {
+                        word = Ye[wi];
+                        Ye[wi] = 0ull;
+                    }
+                    const uint32_t pc = (uint32_t)__popcll(word);
+                    const uint32_t inc = wave_incl_scan(pc);
+                    unsigned long long q = o + (inc - pc);
+                    while (word) {
+                        const int bit = __ffsll((long long)word) - 1;
+                        out[q++] = tri_key(r, (uint32_t)a, bb, (uint32_t)(wi * 64 + bit));
+                        word &= word - 1ull;
+                    }
+                    o += __shfl(inc, VR_WAVE - 1, VR_WAVE);
                 }
-                const uint32_t pc = (uint32_t)__popcll(word);
-                const uint32_t inc = wave_incl_scan(pc);
-                unsigned long long p = o + (inc - pc);
-                while (word) {
-                    const int bit = __ffsll((long long)word) - 1;
-                    out[p++] = tri_key(r, (uint32_t)a, bb, (uint32_t)(wi * 64 + bit));
-                    word &= word - 1ull;
-                }
-                o += __shfl(inc, VR_WAVE - 1, VR_WAVE);
             }
+            __syncthreads();
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s) {
     const int W = (D.n + 63) >> 6;
-    int cap = 512 / W;
-    cap = cap < 1 ? 1 : (cap > 64 ? 64 : cap);
-    const size_t lds = batch_lds(D.n) + (size_t)VR_WAVES * cap * W * 8;
-    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(VR_BLOCK), lds, s, D, tri_out);
+    int cap = VR_YBUDGET / W;
+    cap = cap < 1 ? 1 : (cap > ENUM_BLOCK ? ENUM_BLOCK : cap);
+    const size_t lds = enum_lds(D.n) + (size_t)cap * W * 8;
+    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(ENUM_BLOCK), lds, s, D, tri_out);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

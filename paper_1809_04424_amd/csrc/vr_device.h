@@ -94,6 +94,20 @@ __device__ __forceinline__ T block_excl_scan(T x, T *sh, T *total) {
     return off + inc - x;
 }
 
+// Add 1 to hist[bin] for every lane with `valid`, one LDS add per distinct
+// bin: lanes holding the same bin find each other with one ballot per bin
+// bit, and the lowest of them adds the group's size.
+template <int BITS>
+__device__ __forceinline__ void match_add(uint32_t *hist, uint32_t bin, bool valid) {
+    unsigned long long peers = ballot64(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; b++) {
+        const unsigned long long m = ballot64((bin >> b) & 1u);
+        peers &= ((bin >> b) & 1u) ? m : ~m;
+    }
+    if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&hist[bin], (uint32_t)__popcll(peers));
+}
+
 // ---------------------------------------------------- look-back statuses ----
 __device__ __forceinline__ uint32_t st_load32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
