@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    ap.add_argument("--breakdown-reps", type=int, default=10, help="untimed builds for the stage breakdown (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -137,7 +138,7 @@ def main():
     simplices = n + K + T
     value = simplices * args.steps / el
     ms_step = 1e3 * el / args.steps
-    st = _stage_breakdown(vr, torch, pts, cloud.thr)
+    st = _stage_breakdown(vr, torch, pts, cloud.thr, args.breakdown_reps) if args.breakdown_reps > 0 else {}
     if args.stages:
         print(json.dumps({"stages_ms": st}), file=sys.stderr, flush=True)
 
@@ -160,7 +161,7 @@ def main():
             "value": s3 * 10 / e3, "unit": "simplices/s", "ms_per_step": 1e3 * e3 / 10,
             "counts": list(cnt3), "tri_write_ms": round(t3, 5),
             "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
-            "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3)}
+            "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3) if args.breakdown_reps > 0 else {}}
         del p3
 
     line = {
