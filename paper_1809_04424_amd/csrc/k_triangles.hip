@@ -88,20 +88,22 @@ void launch_star(const VrDev &D, hipStream_t s) {
 // ------------------------------------------------- shared enumeration core ----
 // One work-group per vertex a.  Its star is taken in chunks of ENUM_BLOCK
 // entries; the edges a owns in a chunk are compacted (star order = rank
-// order) and their candidate prefixes laid end to end.  The flat candidate
-// range is split evenly over the waves (each wave a contiguous part, lanes
-// interleaved), so a vertex's late, long-prefix edges do not serialise on one
-// wave.  Eight chunks of 64 candidates are in flight per wave per round.
+// order).  Edge e's candidates (the first pb_e entries of its partner's star)
+// are cut into ceil(pb_e / 64) wave-sized pieces, and the pieces of all edges
+// are split evenly over the waves.  A piece belongs to one edge, so its
+// addressing is scalar; eight pieces are in flight per wave per round.
 #define ENUM_BLOCK 512
 #define ENUM_WAVES (ENUM_BLOCK / VR_WAVE)
 #define VR_UNROLL 8
-#define VR_YBUDGET 2048  // u64 bitset words per work-group in the write kernel
+#define VR_YBUDGET 1024  // u64 bitset words per work-group in the write kernel
+#define VR_STAGE 256     // staged hits per wave in the write kernel
 
 struct EnumLds {
     uint32_t r[ENUM_BLOCK];
     uint32_t b[ENUM_BLOCK];
-    uint32_t sb[ENUM_BLOCK];
-    uint32_t beg[ENUM_BLOCK + 1];
+    uint32_t sb[ENUM_BLOCK];  // start of the partner's star
+    uint32_t pb[ENUM_BLOCK];  // candidates of the edge
+    uint32_t cb[ENUM_BLOCK + 1];  // first piece of the edge
     uint32_t cnt[ENUM_BLOCK];
     unsigned long long off[ENUM_BLOCK];
     uint32_t scan[ENUM_WAVES];
@@ -109,7 +111,7 @@ struct EnumLds {
 };
 
 __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uint32_t *total) {
-    const uint32_t inc = wave_incl_scan(x);
+    const uint32_t inc = wave_incl_scan_dpp(x);
     const int w = threadIdx.x / VR_WAVE;
     if (lane_id() == VR_WAVE - 1) sh[w] = inc;
     __syncthreads();
@@ -126,7 +128,6 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 }
 
 // Compact the owned edges of star entries [p0, p0+ENUM_BLOCK) into L.
-// Returns the number of owned edges; L.beg[0..m] is their flat layout.
 template <bool WRITE>
 __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L) {
     const uint32_t p = p0 + threadIdx.x;
@@ -139,75 +140,80 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, ui
         const uint32_t x = p - s0;
         owned = pb < x || (pb == x && (uint32_t)a < b);
     }
-    uint32_t m, S;
+    uint32_t m, C;
     const uint32_t idx = enum_excl_scan(owned ? 1u : 0u, L.scan, &m);
-    const uint32_t fb = enum_excl_scan(owned ? pb : 0u, L.scan2, &S);
+    const uint32_t pieces = owned ? (pb + VR_WAVE - 1) / VR_WAVE : 0u;
+    const uint32_t cbeg = enum_excl_scan(pieces, L.scan2, &C);
     if (owned) {
         L.r[idx] = r;
         L.b[idx] = b;
         L.sb[idx] = D.start[b];
-        L.beg[idx] = fb;
+        L.pb[idx] = pb;
+        L.cb[idx] = cbeg;
         L.cnt[idx] = 0u;
         if (WRITE) L.off[idx] = D.off[r];
     }
-    if (threadIdx.x == 0) L.beg[m] = S;
+    if (threadIdx.x == 0) L.cb[m] = C;
     __syncthreads();
     return (int)m;
 }
 
-// Walk candidates [f_lo, f_hi) of edges e_lo.. (flat layout L.beg): the
-// candidate f of edge e is star_nbr[sb_e + f - beg_e]; a hit when its rank to
-// a is below r_e.  Without WRITE, hits are counted per edge (one LDS add per
-// edge run within 64 lanes); with WRITE, set in bitset Y row (e - e_lo).
+__device__ __forceinline__ int sreg(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t sreg(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+// Walk the pieces of edges [e_lo, e_hi): piece c of edge e covers candidates
+// 64(c - cb_e) + lane of the partner's star; a candidate k is a hit when its
+// rank to a is below r_e.  Without WRITE the hits of a piece are counted with
+// one ballot; with WRITE each hit sets bit k of bitset row (e - e_lo).
 template <bool WRITE>
 __device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, EnumLds &L, int e_lo, int e_hi,
-                                     uint32_t f_lo, uint32_t f_hi, unsigned long long *Y, int W) {
+                                     unsigned long long *Y, int W) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t span = f_hi - f_lo;
+    const uint32_t c_lo0 = L.cb[e_lo], c_hi0 = L.cb[e_hi];
+    const uint32_t span = c_hi0 - c_lo0;
     const uint32_t per = (span + ENUM_WAVES - 1) / ENUM_WAVES;
-    const uint32_t my_lo = f_lo + min(span, per * (uint32_t)w);
-    const uint32_t my_hi = f_lo + min(span, per * (uint32_t)(w + 1));
+    const uint32_t my_lo = sreg(c_lo0 + min(span, per * (uint32_t)w));
+    const uint32_t my_hi = sreg(c_lo0 + min(span, per * (uint32_t)(w + 1)));
     if (my_lo >= my_hi) return;
-    // first edge whose range reaches my_lo
     int lo = e_lo, hi = e_hi - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (L.beg[mid] <= my_lo) lo = mid;
+        if (L.cb[mid] <= my_lo) lo = mid;
         else hi = mid - 1;
     }
-    int seg = lo;
-    for (uint32_t f0 = my_lo; f0 < my_hi; f0 += VR_WAVE * VR_UNROLL) {
-        uint32_t kk[VR_UNROLL];
-        int sg[VR_UNROLL];
+    int e = sreg(lo);
+    uint32_t e_end = sreg(L.cb[e + 1]);
+    for (uint32_t c0 = my_lo; c0 < my_hi; c0 += VR_UNROLL) {
+        uint32_t kk[VR_UNROLL], rr[VR_UNROLL];
+        int eu[VR_UNROLL];
+        bool ok[VR_UNROLL];
 #pragma unroll
         for (int u = 0; u < VR_UNROLL; u++) {
-            const uint32_t f = f0 + (uint32_t)(u * VR_WAVE + lane);
-            sg[u] = -1;
+            const uint32_t c = c0 + u;
+            eu[u] = -1;
+            ok[u] = false;
             kk[u] = 0;
-            if (f < my_hi) {
-                while (seg < e_hi - 1 && L.beg[seg + 1] <= f) seg++;
-                sg[u] = seg;
-                kk[u] = D.star_nbr[L.sb[seg] + (f - L.beg[seg])];
+            rr[u] = 0;
+            if (c < my_hi) {
+                while (c >= e_end) {
+                    e++;
+                    e_end = sreg(L.cb[e + 1]);
+                }
+                const uint32_t y = (c - sreg(L.cb[e])) * VR_WAVE + (uint32_t)lane;
+                eu[u] = e;
+                rr[u] = sreg(L.r[e]);
+                ok[u] = y < sreg(L.pb[e]);
+                if (ok[u]) kk[u] = D.star_nbr[sreg(L.sb[e]) + y];
             }
         }
 #pragma unroll
         for (int u = 0; u < VR_UNROLL; u++) {
-            const int g = sg[u];
-            const bool hit = g >= 0 && Ra[kk[u]] < L.r[g];
+            const bool hit = ok[u] && Ra[kk[u]] < rr[u];
             if (WRITE) {
-                if (hit) atomicOr(&Y[(g - e_lo) * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
+                if (hit) atomicOr(&Y[(eu[u] - e_lo) * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
             } else {
-                const unsigned long long hits = ballot64(hit);
-                const int gp = __shfl_up(g, 1, VR_WAVE);
-                const bool first = g >= 0 && (lane == 0 || gp != g);
-                const unsigned long long starts = ballot64(first);
-                if (first) {
-                    const unsigned long long above = starts & ~((2ull << lane) - 1ull);
-                    const unsigned long long upto = above ? (above & (~above + 1ull)) - 1ull : ~0ull;
-                    const unsigned long long mine = upto & ~((1ull << lane) - 1ull);
-                    const uint32_t c = (uint32_t)__popcll(hits & mine);
-                    if (c) atomicAdd(&L.cnt[g], c);
-                }
+                const uint32_t c = (uint32_t)__popcll(ballot64(hit));
+                if (lane == 0 && c) atomicAdd(&L.cnt[eu[u]], c);
             }
         }
     }
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
         const int m = load_chunk<false>(D, a, s0, s1, p0, L);
         if (m == 0) continue;
-        walk<false>(D, Ra, L, 0, m, 0, L.beg[m], nullptr, 0);
+        walk<false>(D, Ra, L, 0, m, nullptr, 0);
         __syncthreads();
         if ((int)threadIdx.x < m) D.cnt[L.r[threadIdx.x]] = L.cnt[threadIdx.x];
         __syncthreads();
@@ -319,6 +325,59 @@ __device__ __forceinline__ int write_batch_cap(int W) {
     return c < 1 ? 1 : (c > ENUM_BLOCK ? ENUM_BLOCK : c);
 }
 
+// Emit edge e's triangles from its bitset row Ye in k order.  The sorted
+// vertex triple is (k, lo, hi), (lo, k, hi) or (lo, hi, k) as k falls below,
+// between or above the edge's endpoints, so each key is a per-edge base plus
+// k shifted into place.  Hits are staged in LDS in k order and written with
+// all 64 lanes, each store covering 512 contiguous bytes.
+__device__ __forceinline__ void emit_edge(unsigned long long *Ye, int W, uint32_t r, uint32_t a, uint32_t b,
+                                          unsigned long long o, uint16_t *stage,
+                                          unsigned long long *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t lo = min(a, b), hi = max(a, b);
+    const unsigned long long R = (unsigned long long)r << 39;
+    const unsigned long long k_below = R | ((unsigned long long)lo << 13) | hi;           // | k << 26
+    const unsigned long long k_mid = R | ((unsigned long long)lo << 26) | hi;            // | k << 13
+    const unsigned long long k_above = R | ((unsigned long long)lo << 26) | ((unsigned long long)hi << 13);  // | k
+    for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
+        const int wi = x0 + lane;
+        unsigned long long word = 0ull;
+        if (wi < W) {
+            word = Ye[wi];
+            Ye[wi] = 0ull;
+        }
+        const uint32_t pc = (uint32_t)__popcll(word);
+        const uint32_t inc = wave_incl_scan_dpp(pc);
+        const uint32_t tot = wave_last(inc);
+        if (tot == 0) continue;
+        if (tot <= VR_STAGE) {
+            uint32_t q = inc - pc;
+            while (word) {
+                const int bit = __ffsll((long long)word) - 1;
+                stage[q++] = (uint16_t)(wi * 64 + bit);
+                word &= word - 1ull;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t t = (uint32_t)lane; t < tot; t += VR_WAVE) {
+                const unsigned long long k = stage[t];
+                const unsigned long long key = (k < lo) ? (k_below | (k << 26)) : (k < hi) ? (k_mid | (k << 13)) : (k_above | k);
+                out[o + t] = key;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            unsigned long long q = o + (inc - pc);
+            while (word) {
+                const unsigned long long k = (unsigned long long)(wi * 64 + __ffsll((long long)word) - 1);
+                out[q++] = (k < lo) ? (k_below | (k << 26)) : (k < hi) ? (k_mid | (k << 13)) : (k_above | k);
+                word &= word - 1ull;
+            }
+        }
+        o += tot;
+    }
+}
+
 __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
     extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
@@ -327,7 +386,8 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
     uint32_t *Ra = lds;
     EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
     unsigned long long *Y = (unsigned long long *)(&L + 1);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6;
+    uint16_t *stage = (uint16_t *)(Y + (size_t)cap * W) + (size_t)w * VR_STAGE;
     for (int x = threadIdx.x; x < cap * W; x += ENUM_BLOCK) Y[x] = 0ull;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
     stage_row(D, Ra, s0, s1);
@@ -335,31 +395,10 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
         const int m = load_chunk<true>(D, a, s0, s1, p0, L);
         for (int e0 = 0; e0 < m; e0 += cap) {
             const int e1 = min(m, e0 + cap);
-            walk<true>(D, Ra, L, e0, e1, L.beg[e0], L.beg[e1], Y, W);
+            walk<true>(D, Ra, L, e0, e1, Y, W);
             __syncthreads();
-            // emit: wave w takes edges e0+w, e0+w+ENUM_WAVES, ...
-            for (int e = e0 + w; e < e1; e += ENUM_WAVES) {
-                const uint32_t r = L.r[e], bb = L.b[e];
-                unsigned long long o = L.off[e];
-                unsigned long long *Ye = Y + (size_t)(e - e0) * W;
-                for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
-                    const int wi = x0 + lane;
-                    unsigned long long word = 0ull;
-                    if (wi < W) {
-                        word = Ye[wi];
-                        Ye[wi] = 0ull;
-                    }
-                    const uint32_t pc = (uint32_t)__popcll(word);
-                    const uint32_t inc = wave_incl_scan(pc);
-                    unsigned long long q = o + (inc - pc);
-                    while (word) {
-                        const int bit = __ffsll((long long)word) - 1;
-                        out[q++] = tri_key(r, (uint32_t)a, bb, (uint32_t)(wi * 64 + bit));
-                        word &= word - 1ull;
-                    }
-                    o += __shfl(inc, VR_WAVE - 1, VR_WAVE);
-                }
-            }
+            for (int e = e0 + w; e < e1; e += ENUM_WAVES)
+                emit_edge(Y + (size_t)(e - e0) * W, W, L.r[e], (uint32_t)a, L.b[e], L.off[e], stage, out);
             __syncthreads();
         }
     }
@@ -369,7 +408,7 @@ void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s
     const int W = (D.n + 63) >> 6;
     int cap = VR_YBUDGET / W;
     cap = cap < 1 ? 1 : (cap > ENUM_BLOCK ? ENUM_BLOCK : cap);
-    const size_t lds = enum_lds(D.n) + (size_t)cap * W * 8;
+    const size_t lds = enum_lds(D.n) + (size_t)cap * W * 8 + (size_t)ENUM_WAVES * VR_STAGE * 2;
     hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(ENUM_BLOCK), lds, s, D, tri_out);
 }
 

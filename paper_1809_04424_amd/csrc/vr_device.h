@@ -67,6 +67,22 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
     return x;
 }
 
+// Inclusive scan of a 32-bit value across the 64 lanes with DPP moves (row
+// shifts within 16-lane rows, then row broadcasts 15 and 31): VALU only.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, true);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, true);  // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_last(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, VR_WAVE - 1);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll

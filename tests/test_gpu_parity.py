@@ -221,3 +221,14 @@ def test_stage_timing_reports_every_stage():
     res2, _ = gpu_build(c, timing="write")
     st2 = res2.stage_ms()
     assert st2["tri_write"] > 0 and st2["dist"] == 0
+
+
+def test_largest_point_count(orc):
+    """n = 8192 (the key-packing limit) with a sparse threshold: the per-vertex
+    LDS staging at its largest."""
+    c = workloads.uniform_cloud(77, 8192, 2, dtype=np.int32, lo=0, hi=6000, thr=("count", 200000, 1))
+    _say("[gpu] n=8192 oracle")
+    f = orc.build(c.points, c.thr)
+    _say("[gpu] n=8192 build")
+    _, out = gpu_build(c)
+    assert_matches_oracle(out, f)
