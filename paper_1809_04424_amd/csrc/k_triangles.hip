@@ -27,6 +27,8 @@
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
+#define VR_MAXN 8192
+
 
 __device__ __forceinline__ int star_parity(const VrCtl *ctl) {
     // number of active passes of the two-pass star sort, from its histograms
@@ -86,26 +88,27 @@ void launch_star(const VrDev &D, hipStream_t s) {
 }
 
 // ------------------------------------------------- shared enumeration core ----
-// One work-group per vertex a.  Its star is taken in chunks of ENUM_BLOCK
-// entries; the edges a owns in a chunk are compacted (star order = rank
-// order).  Edge e's candidates (the first pb_e entries of its partner's star)
-// are cut into ceil(pb_e / 64) wave-sized pieces, and the pieces of all edges
-// are split evenly over the waves.  A piece belongs to one edge, so its
-// addressing is scalar; eight pieces are in flight per wave per round.
+// One work-group per vertex a, its ranks staged in LDS.  The star is taken in
+// chunks of ENUM_BLOCK entries; the edges a owns in a chunk are compacted
+// (star order = rank order).  Edge e's candidates (the first pb_e entries of
+// its partner's star) are cut into ceil(pb_e / 64) wave-sized pieces.  Each
+// wave takes a contiguous run of whole edges holding about 1/8 of the pieces
+// and works through it on its own, with no work-group barrier: the metadata
+// of up to 64 edges sits in lane registers (read back with readlane), so the
+// loads of VR_UNROLL pieces issue back to back.
 #define ENUM_BLOCK 512
 #define ENUM_WAVES (ENUM_BLOCK / VR_WAVE)
-#define VR_UNROLL 8
-#define VR_YBUDGET 1024  // u64 bitset words per work-group in the write kernel
-#define VR_STAGE 256     // staged hits per wave in the write kernel
+#define VR_UNROLL 16
+#define VR_YWAVE 256   // u64 bitset words per wave in the write kernel
+#define VR_STAGE 192   // staged hits per wave in the write kernel
 
 struct EnumLds {
     uint32_t r[ENUM_BLOCK];
     uint32_t b[ENUM_BLOCK];
-    uint32_t sb[ENUM_BLOCK];  // start of the partner's star
-    uint32_t pb[ENUM_BLOCK];  // candidates of the edge
+    uint32_t sb[ENUM_BLOCK];      // start of the partner's star
+    uint32_t pb[ENUM_BLOCK];      // candidates of the edge
     uint32_t cb[ENUM_BLOCK + 1];  // first piece of the edge
-    uint32_t cnt[ENUM_BLOCK];
-    unsigned long long off[ENUM_BLOCK];
+    uint32_t ew[ENUM_WAVES + 1];  // first edge of each wave
     uint32_t scan[ENUM_WAVES];
     uint32_t scan2[ENUM_WAVES];
 };
@@ -127,8 +130,8 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
     return off + inc - x;
 }
 
-// Compact the owned edges of star entries [p0, p0+ENUM_BLOCK) into L.
-template <bool WRITE>
+// Compact the owned edges of star entries [p0, p0+ENUM_BLOCK) into L and
+// split them over the waves by piece count.
 __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L) {
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
@@ -150,40 +153,44 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, ui
         L.sb[idx] = D.start[b];
         L.pb[idx] = pb;
         L.cb[idx] = cbeg;
-        L.cnt[idx] = 0u;
-        if (WRITE) L.off[idx] = D.off[r];
     }
     if (threadIdx.x == 0) L.cb[m] = C;
+    __syncthreads();
+    if ((int)threadIdx.x <= ENUM_WAVES) {
+        // first edge whose first piece reaches the wave's share
+        const uint32_t target = (uint32_t)(((unsigned long long)C * threadIdx.x) / ENUM_WAVES);
+        int lo = 0, hi = (int)m;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (L.cb[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
+        L.ew[threadIdx.x] = (threadIdx.x == ENUM_WAVES) ? m : (uint32_t)lo;
+    }
     __syncthreads();
     return (int)m;
 }
 
-__device__ __forceinline__ int sreg(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint32_t sreg(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint32_t rl(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
 
-// Walk the pieces of edges [e_lo, e_hi): piece c of edge e covers candidates
-// 64(c - cb_e) + lane of the partner's star; a candidate k is a hit when its
-// rank to a is below r_e.  Without WRITE the hits of a piece are counted with
-// one ballot; with WRITE each hit sets bit k of bitset row (e - e_lo).
+// Walk the pieces of edges [e_lo, e_hi) of the window of ne edges starting at
+// edge eb (lane l of the metadata registers describes edge eb + l; cb_end is
+// the first piece after the window).  Piece c of edge e covers candidates
+// 64(c - cb_e) + lane of the partner's star; candidate k is a hit when its
+// rank to a is below r_e.  Counts go to the lane of the edge; with WRITE each
+// hit sets bit k of bitset row (e - e_lo).
 template <bool WRITE>
-__device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, EnumLds &L, int e_lo, int e_hi,
-                                     unsigned long long *Y, int W) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t c_lo0 = L.cb[e_lo], c_hi0 = L.cb[e_hi];
-    const uint32_t span = c_hi0 - c_lo0;
-    const uint32_t per = (span + ENUM_WAVES - 1) / ENUM_WAVES;
-    const uint32_t my_lo = sreg(c_lo0 + min(span, per * (uint32_t)w));
-    const uint32_t my_hi = sreg(c_lo0 + min(span, per * (uint32_t)(w + 1)));
-    if (my_lo >= my_hi) return;
-    int lo = e_lo, hi = e_hi - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.cb[mid] <= my_lo) lo = mid;
-        else hi = mid - 1;
-    }
-    int e = sreg(lo);
-    uint32_t e_end = sreg(L.cb[e + 1]);
-    for (uint32_t c0 = my_lo; c0 < my_hi; c0 += VR_UNROLL) {
+__device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, int eb, int ne, int e_lo, int e_hi,
+                                     uint32_t vr, uint32_t vsb, uint32_t vpb, uint32_t vcb, uint32_t cb_end,
+                                     uint32_t *mycnt, unsigned long long *Y, int W) {
+    const int lane = threadIdx.x & 63;
+    auto cb_of = [&](int e) { return (e - eb < ne) ? rl(vcb, e - eb) : cb_end; };
+    const uint32_t c_lo = cb_of(e_lo), c_hi = cb_of(e_hi);
+    int e = e_lo;
+    uint32_t e_end = cb_of(e + 1);
+    for (uint32_t c0 = c_lo; c0 < c_hi; c0 += VR_UNROLL) {
         uint32_t kk[VR_UNROLL], rr[VR_UNROLL];
         int eu[VR_UNROLL];
         bool ok[VR_UNROLL];
@@ -194,16 +201,17 @@ __device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, EnumLds
             ok[u] = false;
             kk[u] = 0;
             rr[u] = 0;
-            if (c < my_hi) {
+            if (c < c_hi) {
                 while (c >= e_end) {
                     e++;
-                    e_end = sreg(L.cb[e + 1]);
+                    e_end = cb_of(e + 1);
                 }
-                const uint32_t y = (c - sreg(L.cb[e])) * VR_WAVE + (uint32_t)lane;
+                const int el = e - eb;
+                const uint32_t y = (c - rl(vcb, el)) * VR_WAVE + (uint32_t)lane;
                 eu[u] = e;
-                rr[u] = sreg(L.r[e]);
-                ok[u] = y < sreg(L.pb[e]);
-                if (ok[u]) kk[u] = D.star_nbr[sreg(L.sb[e]) + y];
+                rr[u] = rl(vr, el);
+                ok[u] = y < rl(vpb, el);
+                if (ok[u]) kk[u] = D.star_nbr[rl(vsb, el) + y];
             }
         }
 #pragma unroll
@@ -211,9 +219,9 @@ __device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, EnumLds
             const bool hit = ok[u] && Ra[kk[u]] < rr[u];
             if (WRITE) {
                 if (hit) atomicOr(&Y[(eu[u] - e_lo) * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
-            } else {
+            } else if (eu[u] >= 0) {
                 const uint32_t c = (uint32_t)__popcll(ballot64(hit));
-                if (lane == 0 && c) atomicAdd(&L.cnt[eu[u]], c);
+                if (lane == eu[u] - eb) *mycnt += c;
             }
         }
     }
@@ -234,15 +242,28 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
     const int a = blockIdx.x, n = D.n;
     uint32_t *Ra = lds;
     EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
     stage_row(D, Ra, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        const int m = load_chunk<false>(D, a, s0, s1, p0, L);
-        if (m == 0) continue;
-        walk<false>(D, Ra, L, 0, m, nullptr, 0);
+        const int m = load_chunk(D, a, s0, s1, p0, L);
+        const int w_lo = (int)L.ew[w], w_hi = (int)L.ew[w + 1];
+        for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
+            const int ne = min(VR_WAVE, w_hi - eb);
+            uint32_t vr = 0, vsb = 0, vpb = 0, vcb = 0;
+            if (lane < ne) {
+                vr = L.r[eb + lane];
+                vsb = L.sb[eb + lane];
+                vpb = L.pb[eb + lane];
+                vcb = L.cb[eb + lane];
+            }
+            const uint32_t cb_end = L.cb[eb + ne];
+            uint32_t mycnt = 0;
+            walk<false>(D, Ra, eb, ne, eb, eb + ne, vr, vsb, vpb, vcb, cb_end, &mycnt, nullptr, 0);
+            if (lane < ne) D.cnt[vr] = mycnt;
+        }
         __syncthreads();
-        if ((int)threadIdx.x < m) D.cnt[L.r[threadIdx.x]] = L.cnt[threadIdx.x];
-        __syncthreads();
+        (void)m;
     }
 }
 
@@ -320,16 +341,11 @@ void launch_publish(const VrDev &D, hipStream_t s) {
 }
 
 // ----------------------------------------------------------- k_tri_write ----
-__device__ __forceinline__ int write_batch_cap(int W) {
-    const int c = VR_YBUDGET / W;
-    return c < 1 ? 1 : (c > ENUM_BLOCK ? ENUM_BLOCK : c);
-}
-
-// Emit edge e's triangles from its bitset row Ye in k order.  The sorted
-// vertex triple is (k, lo, hi), (lo, k, hi) or (lo, hi, k) as k falls below,
-// between or above the edge's endpoints, so each key is a per-edge base plus
-// k shifted into place.  Hits are staged in LDS in k order and written with
-// all 64 lanes, each store covering 512 contiguous bytes.
+// Emit edge r = {a, b}'s triangles from its bitset row Ye in k order.  The
+// sorted vertex triple is (k, lo, hi), (lo, k, hi) or (lo, hi, k) as k falls
+// below, between or above the edge's endpoints, so each key is a per-edge base
+// plus k shifted into place.  Hits are staged in LDS in k order and written
+// with all 64 lanes, each store covering 512 contiguous bytes.
 __device__ __forceinline__ void emit_edge(unsigned long long *Ye, int W, uint32_t r, uint32_t a, uint32_t b,
                                           unsigned long long o, uint16_t *stage,
                                           unsigned long long *__restrict__ out) {
@@ -361,8 +377,7 @@ __device__ __forceinline__ void emit_edge(unsigned long long *Ye, int W, uint32_
             __builtin_amdgcn_wave_barrier();
             for (uint32_t t = (uint32_t)lane; t < tot; t += VR_WAVE) {
                 const unsigned long long k = stage[t];
-                const unsigned long long key = (k < lo) ? (k_below | (k << 26)) : (k < hi) ? (k_mid | (k << 13)) : (k_above | k);
-                out[o + t] = key;
+                out[o + t] = (k < lo) ? (k_below | (k << 26)) : (k < hi) ? (k_mid | (k << 13)) : (k_above | k);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -378,6 +393,11 @@ __device__ __forceinline__ void emit_edge(unsigned long long *Ye, int W, uint32_
     }
 }
 
+__device__ __forceinline__ int write_batch_cap(int W) {
+    const int c = VR_YWAVE / W;
+    return c < 1 ? 1 : (c > VR_WAVE ? VR_WAVE : c);
+}
+
 __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
     extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
@@ -385,30 +405,52 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
     const int cap = write_batch_cap(W);
     uint32_t *Ra = lds;
     EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
-    unsigned long long *Y = (unsigned long long *)(&L + 1);
-    const int w = threadIdx.x >> 6;
-    uint16_t *stage = (uint16_t *)(Y + (size_t)cap * W) + (size_t)w * VR_STAGE;
-    for (int x = threadIdx.x; x < cap * W; x += ENUM_BLOCK) Y[x] = 0ull;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned long long *Y = (unsigned long long *)(&L + 1) + (size_t)w * cap * W;
+    uint16_t *stage = (uint16_t *)((unsigned long long *)(&L + 1) + (size_t)ENUM_WAVES * cap * W) + (size_t)w * VR_STAGE;
+    for (int x = lane; x < cap * W; x += VR_WAVE) Y[x] = 0ull;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
     stage_row(D, Ra, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        const int m = load_chunk<true>(D, a, s0, s1, p0, L);
-        for (int e0 = 0; e0 < m; e0 += cap) {
-            const int e1 = min(m, e0 + cap);
-            walk<true>(D, Ra, L, e0, e1, Y, W);
-            __syncthreads();
-            for (int e = e0 + w; e < e1; e += ENUM_WAVES)
-                emit_edge(Y + (size_t)(e - e0) * W, W, L.r[e], (uint32_t)a, L.b[e], L.off[e], stage, out);
-            __syncthreads();
+        load_chunk(D, a, s0, s1, p0, L);
+        const int w_lo = (int)L.ew[w], w_hi = (int)L.ew[w + 1];
+        for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
+            const int ne = min(VR_WAVE, w_hi - eb);
+            uint32_t vr = 0, vsb = 0, vpb = 0, vcb = 0, vb = 0;
+            unsigned long long voff = 0;
+            if (lane < ne) {
+                vr = L.r[eb + lane];
+                vsb = L.sb[eb + lane];
+                vpb = L.pb[eb + lane];
+                vcb = L.cb[eb + lane];
+                vb = L.b[eb + lane];
+                voff = D.off[vr];
+            }
+            const uint32_t cb_end = L.cb[eb + ne];
+            for (int e0 = eb; e0 < eb + ne; e0 += cap) {
+                const int e1 = min(eb + ne, e0 + cap);
+                walk<true>(D, Ra, eb, ne, e0, e1, vr, vsb, vpb, vcb, cb_end, nullptr, Y, W);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (int e = e0; e < e1; e++) {
+                    const int el = e - eb;
+                    const unsigned long long o = ((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
+                                                 rl((uint32_t)voff, el);
+                    emit_edge(Y + (size_t)(e - e0) * W, W, rl(vr, el), (uint32_t)a, rl(vb, el), o, stage, out);
+                }
+            }
         }
+        __syncthreads();
     }
 }
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s) {
     const int W = (D.n + 63) >> 6;
-    int cap = VR_YBUDGET / W;
-    cap = cap < 1 ? 1 : (cap > ENUM_BLOCK ? ENUM_BLOCK : cap);
-    const size_t lds = enum_lds(D.n) + (size_t)cap * W * 8 + (size_t)ENUM_WAVES * VR_STAGE * 2;
+    int cap = VR_YWAVE / W;
+    cap = cap < 1 ? 1 : (cap > VR_WAVE ? VR_WAVE : cap);
+    const size_t lds = enum_lds(D.n) + (size_t)ENUM_WAVES * cap * W * 8 + (size_t)ENUM_WAVES * VR_STAGE * 2;
+    static_assert(4 * VR_MAXN + sizeof(EnumLds) + ENUM_WAVES * VR_YWAVE * 8 + ENUM_WAVES * VR_STAGE * 2 <= 65536,
+                  "write kernel LDS above 64 KiB at the largest n");
     hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(ENUM_BLOCK), lds, s, D, tri_out);
 }
 
