@@ -98,7 +98,7 @@ void launch_star(const VrDev &D, hipStream_t s) {
 // loads of VR_UNROLL pieces issue back to back.
 #define ENUM_BLOCK 512
 #define ENUM_WAVES (ENUM_BLOCK / VR_WAVE)
-#define VR_UNROLL 16
+#define VR_UNROLL 8
 #define VR_YWAVE 256   // u64 bitset words per wave in the write kernel
 #define VR_STAGE 192   // staged hits per wave in the write kernel
 
@@ -247,7 +247,8 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
     stage_row(D, Ra, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
         const int m = load_chunk(D, a, s0, s1, p0, L);
-        const int w_lo = (int)L.ew[w], w_hi = (int)L.ew[w + 1];
+        const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
+        const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
             const int ne = min(VR_WAVE, w_hi - eb);
             uint32_t vr = 0, vsb = 0, vpb = 0, vcb = 0;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
                 vpb = L.pb[eb + lane];
                 vcb = L.cb[eb + lane];
             }
-            const uint32_t cb_end = L.cb[eb + ne];
+            const uint32_t cb_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.cb[eb + ne]);
             uint32_t mycnt = 0;
             walk<false>(D, Ra, eb, ne, eb, eb + ne, vr, vsb, vpb, vcb, cb_end, &mycnt, nullptr, 0);
             if (lane < ne) D.cnt[vr] = mycnt;
@@ -413,7 +414,8 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
     stage_row(D, Ra, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
         load_chunk(D, a, s0, s1, p0, L);
-        const int w_lo = (int)L.ew[w], w_hi = (int)L.ew[w + 1];
+        const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
+        const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
             const int ne = min(VR_WAVE, w_hi - eb);
             uint32_t vr = 0, vsb = 0, vpb = 0, vcb = 0, vb = 0;
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                 vb = L.b[eb + lane];
                 voff = D.off[vr];
             }
-            const uint32_t cb_end = L.cb[eb + ne];
+            const uint32_t cb_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.cb[eb + ne]);
             for (int e0 = eb; e0 < eb + ne; e0 += cap) {
                 const int e1 = min(eb + ne, e0 + cap);
                 walk<true>(D, Ra, eb, ne, e0, e1, vr, vsb, vpb, vcb, cb_end, nullptr, Y, W);
