@@ -3,32 +3,31 @@
 //
 // Ownership: a triangle enters the filtration with its largest edge (Section
 // 2.1), so the triangles of value r are exactly {a, b, k} with edge r = {a,b}
-// and both {a,k} and {b,k} ranked below r.  Those k are the neighbours of b
-// that come before edge r in b's rank-ordered star (a prefix of that star)
-// and whose edge to a also ranks below r.  For a fixed edge the sorted vertex
+// and both {a,k} and {b,k} ranked below r.  In rank-ordered stars, "ranked
+// below r" is "before edge r": k lies in the first pb entries of b's star
+// (pb = position of edge r in b's star) and in the first xa entries of a's
+// star (xa = its position in a's star).  For a fixed edge the sorted vertex
 // triples increase with k, and the offsets follow rank order, so the output
 // is written in (value, i, j, k) order with no sort.
 //
-//   k_star        CSR stars from the stably sorted incidences (a stable
-//                 per-column ordering, like the paper's
+//   k_star        CSR stars in rank order from the stably sorted incidences
+//                 (a stable per-column ordering, like the paper's
 //                 integersinsameorderbycolumn, Section 4.3)
-//   k_star_pos    position of every edge in both of its stars
-//   k_tri_count   one work-group per vertex a with a's ranks staged in LDS;
-//                 each edge is handled at the endpoint whose partner has the
-//                 shorter prefix; a wave takes a batch of edges and walks all
-//                 their candidates as one flat stream (full lanes, independent
-//                 loads)
+//   k_kstar       per vertex: the position of every edge in its stars, and
+//                 the star again in neighbour order, each entry packing
+//                 (neighbour | position in the rank-ordered star << 16)
+//   k_tri_count   per vertex a: for each edge a owns, count the neighbours in
+//                 the partner's rank prefix that precede the edge in a's star
 //   k_scan        exclusive scan of the counts (decoupled look-back)
 //   k_publish     counts to the host-pinned mailbox
-//   k_tri_write   the same walk; hits set bits of a per-edge LDS bitset, which
-//                 is then compacted in k order with popcounts and wave prefix
-//                 sums (the ballot/popc compaction of the paper's init_supp,
-//                 Section 4.4, on 64-wide waves)
+//   k_tri_write   per vertex a: for each edge a owns, walk the partner's
+//                 neighbour-ordered star; hits are compacted with ballot and
+//                 mbcnt (the ballot/popc compaction of the paper's init_supp,
+//                 Section 4.4, on 64-wide waves) and stored contiguously
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
 #define VR_MAXN 8192
-
 
 __device__ __forceinline__ int star_parity(const VrCtl *ctl) {
     // number of active passes of the two-pass star sort, from its histograms
@@ -69,14 +68,33 @@ __global__ __launch_bounds__(VR_BLOCK) void k_star(VrDev D) {
     }
 }
 
-__global__ __launch_bounds__(VR_BLOCK) void k_star_pos(VrDev D) {
-    const VrCtl *ctl = D.ctl;
-    const int par = star_parity(ctl);
-    const uint32_t *__restrict__ kf = D.ikey[par];
-    const uint32_t *__restrict__ vf = D.ival[par];
-    const long long m = (long long)ctl->n_inc;
-    for (long long p = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; p < m; p += (long long)gridDim.x * VR_BLOCK)
-        D.pos[vf[p]] = (uint16_t)(p - D.start[kf[p]]);
+// -------------------------------------------------------------- k_kstar ----
+// One work-group per vertex v (n <= 8192, so its <= 128 bitset words fit one
+// pass of 256 threads).
+__global__ __launch_bounds__(VR_BLOCK) void k_kstar(VrDev D) {
+    __shared__ uint16_t P[VR_MAXN];
+    __shared__ unsigned long long bits[VR_MAXN / 64];
+    __shared__ uint32_t sh_w[VR_WAVES];
+    const int v = blockIdx.x, n = D.n, t = threadIdx.x;
+    const int W = (n + 63) >> 6;
+    const uint32_t s0 = D.start[v], s1 = D.start[v + 1];
+    if (t < W) bits[t] = 0ull;
+    __syncthreads();
+    for (uint32_t p = s0 + t; p < s1; p += VR_BLOCK) {
+        const uint32_t k = D.star_nbr[p], r = D.star_r[p], x = p - s0;
+        P[k] = (uint16_t)x;
+        atomicOr(&bits[k >> 6], 1ull << (k & 63));
+        D.pos[2 * (size_t)r + (k > (uint32_t)v ? 0 : 1)] = (uint16_t)x;
+    }
+    __syncthreads();
+    unsigned long long word = (t < W) ? bits[t] : 0ull;
+    uint32_t tot;
+    uint32_t q = block_excl_scan<uint32_t>((uint32_t)__popcll(word), sh_w, &tot);
+    while (word) {
+        const uint32_t k = (uint32_t)(t * 64 + __ffsll((long long)word) - 1);
+        D.star_k[s0 + q++] = k | ((uint32_t)P[k] << 16);
+        word &= word - 1ull;
+    }
 }
 
 void launch_star(const VrDev &D, hipStream_t s) {
@@ -84,29 +102,28 @@ void launch_star(const VrDev &D, hipStream_t s) {
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_star, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
-    hipLaunchKernelGGL(k_star_pos, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_kstar, dim3(D.n), dim3(VR_BLOCK), 0, s, D);
 }
 
 // ------------------------------------------------- shared enumeration core ----
-// One work-group per vertex a, its ranks staged in LDS.  The star is taken in
-// chunks of ENUM_BLOCK entries; the edges a owns in a chunk are compacted
-// (star order = rank order).  Edge e's candidates (the first pb_e entries of
-// its partner's star) are cut into ceil(pb_e / 64) wave-sized pieces.  Each
-// wave takes a contiguous run of whole edges holding about 1/8 of the pieces
-// and works through it on its own, with no work-group barrier: the metadata
-// of up to 64 edges sits in lane registers (read back with readlane), so the
-// loads of VR_UNROLL pieces issue back to back.
+// One work-group per vertex a with Pa[k] = position of edge {a,k} in a's
+// star (0xFFFF when k is no neighbour) staged in LDS.  The star is taken in
+// chunks of ENUM_BLOCK entries; the edges a owns in a chunk are compacted and
+// cut into wave-sized pieces of candidates; each wave takes a contiguous run
+// of whole edges holding about 1/8 of the pieces.  The metadata of up to 64
+// edges sits in lane registers; the loads of the next edge are issued before
+// the current edge is consumed.
 #define ENUM_BLOCK 512
 #define ENUM_WAVES (ENUM_BLOCK / VR_WAVE)
-#define VR_UNROLL 8
-#define VR_YWAVE 256   // u64 bitset words per wave in the write kernel
-#define VR_STAGE 192   // staged hits per wave in the write kernel
+#define VR_PIECES 8  // pieces of an edge loaded in one go (64 candidates each)
 
 struct EnumLds {
     uint32_t r[ENUM_BLOCK];
     uint32_t b[ENUM_BLOCK];
     uint32_t sb[ENUM_BLOCK];      // start of the partner's star
-    uint32_t pb[ENUM_BLOCK];      // candidates of the edge
+    uint32_t len[ENUM_BLOCK];     // candidates of the edge
+    uint32_t pb[ENUM_BLOCK];      // position of the edge in the partner's star
+    uint32_t xa[ENUM_BLOCK];      // position of the edge in a's star
     uint32_t cb[ENUM_BLOCK + 1];  // first piece of the edge
     uint32_t ew[ENUM_WAVES + 1];  // first edge of each wave
     uint32_t scan[ENUM_WAVES];
@@ -130,34 +147,47 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
     return off + inc - x;
 }
 
-// Compact the owned edges of star entries [p0, p0+ENUM_BLOCK) into L and
-// split them over the waves by piece count.
+// Compact the edges a owns among star entries [p0, p0+ENUM_BLOCK) and split
+// them over the waves by piece count.  WRITE: an edge is written at the
+// endpoint whose partner has the shorter star (candidates = the partner's
+// whole neighbour-ordered star).  Otherwise it is counted at the endpoint
+// whose partner has the shorter rank prefix (candidates = that prefix).
+template <bool WRITE>
 __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L) {
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
-    uint32_t r = 0, b = 0, pb = 0;
+    uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
+    const uint32_t x = p - s0;
     if (p < s1) {
         r = D.star_r[p];
         b = D.star_nbr[p];
         pb = D.pos[2 * (size_t)r + (b > (uint32_t)a ? 1 : 0)];
-        const uint32_t x = p - s0;
-        owned = pb < x || (pb == x && (uint32_t)a < b);
+        sb = D.start[b];
+        if (WRITE) {
+            const uint32_t db = D.start[b + 1] - sb, da = s1 - s0;
+            owned = db < da || (db == da && (uint32_t)a < b);
+            len = db;
+        } else {
+            owned = pb < x || (pb == x && (uint32_t)a < b);
+            len = pb;
+        }
     }
     uint32_t m, C;
     const uint32_t idx = enum_excl_scan(owned ? 1u : 0u, L.scan, &m);
-    const uint32_t pieces = owned ? (pb + VR_WAVE - 1) / VR_WAVE : 0u;
+    const uint32_t pieces = owned ? (len + VR_WAVE - 1) / VR_WAVE : 0u;
     const uint32_t cbeg = enum_excl_scan(pieces, L.scan2, &C);
     if (owned) {
         L.r[idx] = r;
         L.b[idx] = b;
-        L.sb[idx] = D.start[b];
+        L.sb[idx] = sb;
+        L.len[idx] = len;
         L.pb[idx] = pb;
+        L.xa[idx] = x;
         L.cb[idx] = cbeg;
     }
     if (threadIdx.x == 0) L.cb[m] = C;
     __syncthreads();
     if ((int)threadIdx.x <= ENUM_WAVES) {
-        // first edge whose first piece reaches the wave's share
         const uint32_t target = (uint32_t)(((unsigned long long)C * threadIdx.x) / ENUM_WAVES);
         int lo = 0, hi = (int)m;
         while (lo < hi) {
@@ -175,96 +205,73 @@ __device__ __forceinline__ uint32_t rl(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// Walk the pieces of edges [e_lo, e_hi) of the window of ne edges starting at
-// edge eb (lane l of the metadata registers describes edge eb + l; cb_end is
-// the first piece after the window).  Piece c of edge e covers candidates
-// 64(c - cb_e) + lane of the partner's star; candidate k is a hit when its
-// rank to a is below r_e.  Counts go to the lane of the edge; with WRITE each
-// hit sets bit k of bitset row (e - e_lo).
-template <bool WRITE>
-__device__ __forceinline__ void walk(const VrDev &D, const uint32_t *Ra, int eb, int ne, int e_lo, int e_hi,
-                                     uint32_t vr, uint32_t vsb, uint32_t vpb, uint32_t vcb, uint32_t cb_end,
-                                     uint32_t *mycnt, unsigned long long *Y, int W) {
+__device__ __forceinline__ void stage_pos(const VrDev &D, uint16_t *Pa, uint32_t s0, uint32_t s1) {
+    for (int k = threadIdx.x; k < D.n; k += ENUM_BLOCK) Pa[k] = 0xFFFF;
+    __syncthreads();
+    for (uint32_t p = s0 + threadIdx.x; p < s1; p += ENUM_BLOCK) Pa[D.star_nbr[p]] = (uint16_t)(p - s0);
+    __syncthreads();
+}
+
+size_t enum_lds(int n) { return 2 * (size_t)((n + 7) & ~7) + sizeof(EnumLds); }
+
+// Load up to VR_PIECES pieces of `len` candidates starting at src.
+template <typename T>
+__device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T fill, T (&kk)[VR_PIECES]) {
     const int lane = threadIdx.x & 63;
-    auto cb_of = [&](int e) { return (e - eb < ne) ? rl(vcb, e - eb) : cb_end; };
-    const uint32_t c_lo = cb_of(e_lo), c_hi = cb_of(e_hi);
-    int e = e_lo;
-    uint32_t e_end = cb_of(e + 1);
-    for (uint32_t c0 = c_lo; c0 < c_hi; c0 += VR_UNROLL) {
-        uint32_t kk[VR_UNROLL], rr[VR_UNROLL];
-        int eu[VR_UNROLL];
-        bool ok[VR_UNROLL];
 #pragma unroll
-        for (int u = 0; u < VR_UNROLL; u++) {
-            const uint32_t c = c0 + u;
-            eu[u] = -1;
-            ok[u] = false;
-            kk[u] = 0;
-            rr[u] = 0;
-            if (c < c_hi) {
-                while (c >= e_end) {
-                    e++;
-                    e_end = cb_of(e + 1);
-                }
-                const int el = e - eb;
-                const uint32_t y = (c - rl(vcb, el)) * VR_WAVE + (uint32_t)lane;
-                eu[u] = e;
-                rr[u] = rl(vr, el);
-                ok[u] = y < rl(vpb, el);
-                if (ok[u]) kk[u] = D.star_nbr[rl(vsb, el) + y];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < VR_UNROLL; u++) {
-            const bool hit = ok[u] && Ra[kk[u]] < rr[u];
-            if (WRITE) {
-                if (hit) atomicOr(&Y[(eu[u] - e_lo) * W + (kk[u] >> 6)], 1ull << (kk[u] & 63));
-            } else if (eu[u] >= 0) {
-                const uint32_t c = (uint32_t)__popcll(ballot64(hit));
-                if (lane == eu[u] - eb) *mycnt += c;
-            }
-        }
+    for (int j = 0; j < VR_PIECES; j++) {
+        const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
+        kk[j] = (y < len) ? src[y] : fill;
     }
 }
-
-__device__ __forceinline__ void stage_row(const VrDev &D, uint32_t *Ra, uint32_t s0, uint32_t s1) {
-    for (int k = threadIdx.x; k < D.n; k += ENUM_BLOCK) Ra[k] = VR_NOT_KEPT;
-    __syncthreads();
-    for (uint32_t p = s0 + threadIdx.x; p < s1; p += ENUM_BLOCK) Ra[D.star_nbr[p]] = D.star_r[p];
-    __syncthreads();
-}
-
-size_t enum_lds(int n) { return 4 * (size_t)((n + 3) & ~3) + sizeof(EnumLds); }
 
 // ----------------------------------------------------------- k_tri_count ----
 __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
     extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
-    uint32_t *Ra = lds;
-    EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
+    uint16_t *Pa = (uint16_t *)lds;
+    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
-    stage_row(D, Ra, s0, s1);
+    stage_pos(D, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        const int m = load_chunk(D, a, s0, s1, p0, L);
+        load_chunk<false>(D, a, s0, s1, p0, L);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
             const int ne = min(VR_WAVE, w_hi - eb);
-            uint32_t vr = 0, vsb = 0, vpb = 0, vcb = 0;
+            uint32_t vr = 0, vsb = 0, vlen = 0, vxa = 0;
             if (lane < ne) {
                 vr = L.r[eb + lane];
                 vsb = L.sb[eb + lane];
-                vpb = L.pb[eb + lane];
-                vcb = L.cb[eb + lane];
+                vlen = L.len[eb + lane];
+                vxa = L.xa[eb + lane];
             }
-            const uint32_t cb_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.cb[eb + ne]);
             uint32_t mycnt = 0;
-            walk<false>(D, Ra, eb, ne, eb, eb + ne, vr, vsb, vpb, vcb, cb_end, &mycnt, nullptr, 0);
+            uint16_t kA[VR_PIECES], kB[VR_PIECES];
+            issue<uint16_t>(D.star_nbr + rl(vsb, 0), rl(vlen, 0), (uint16_t)0xFFFF, kA);
+            for (int el = 0; el < ne; el++) {
+                if (el + 1 < ne) issue<uint16_t>(D.star_nbr + rl(vsb, el + 1), rl(vlen, el + 1), (uint16_t)0xFFFF, kB);
+                const uint32_t xa = rl(vxa, el), len = rl(vlen, el);
+                uint32_t c = 0;
+#pragma unroll
+                for (int j = 0; j < VR_PIECES; j++) {
+                    const uint32_t k = kA[j];
+                    const bool hit = k != 0xFFFFu && Pa[k] < xa;
+                    c += (uint32_t)__popcll(ballot64(hit));
+                }
+                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                    const uint32_t y = y0 + (uint32_t)lane;
+                    const uint32_t k = (y < len) ? D.star_nbr[rl(vsb, el) + y] : 0xFFFFu;
+                    c += (uint32_t)__popcll(ballot64(k != 0xFFFFu && Pa[k] < xa));
+                }
+                if (lane == el) mycnt = c;
+#pragma unroll
+                for (int j = 0; j < VR_PIECES; j++) kA[j] = kB[j];
+            }
             if (lane < ne) D.cnt[vr] = mycnt;
         }
         __syncthreads();
-        (void)m;
     }
 }
 
@@ -342,104 +349,68 @@ void launch_publish(const VrDev &D, hipStream_t s) {
 }
 
 // ----------------------------------------------------------- k_tri_write ----
-// Emit edge r = {a, b}'s triangles from its bitset row Ye in k order.  The
-// sorted vertex triple is (k, lo, hi), (lo, k, hi) or (lo, hi, k) as k falls
-// below, between or above the edge's endpoints, so each key is a per-edge base
-// plus k shifted into place.  Hits are staged in LDS in k order and written
-// with all 64 lanes, each store covering 512 contiguous bytes.
-__device__ __forceinline__ void emit_edge(unsigned long long *Ye, int W, uint32_t r, uint32_t a, uint32_t b,
-                                          unsigned long long o, uint16_t *stage,
-                                          unsigned long long *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t lo = min(a, b), hi = max(a, b);
-    const unsigned long long R = (unsigned long long)r << 39;
-    const unsigned long long k_below = R | ((unsigned long long)lo << 13) | hi;           // | k << 26
-    const unsigned long long k_mid = R | ((unsigned long long)lo << 26) | hi;            // | k << 13
-    const unsigned long long k_above = R | ((unsigned long long)lo << 26) | ((unsigned long long)hi << 13);  // | k
-    for (int x0 = 0; x0 < W; x0 += VR_WAVE) {
-        const int wi = x0 + lane;
-        unsigned long long word = 0ull;
-        if (wi < W) {
-            word = Ye[wi];
-            Ye[wi] = 0ull;
-        }
-        const uint32_t pc = (uint32_t)__popcll(word);
-        const uint32_t inc = wave_incl_scan_dpp(pc);
-        const uint32_t tot = wave_last(inc);
-        if (tot == 0) continue;
-        if (tot <= VR_STAGE) {
-            uint32_t q = inc - pc;
-            while (word) {
-                const int bit = __ffsll((long long)word) - 1;
-                stage[q++] = (uint16_t)(wi * 64 + bit);
-                word &= word - 1ull;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            for (uint32_t t = (uint32_t)lane; t < tot; t += VR_WAVE) {
-                const unsigned long long k = stage[t];
-                out[o + t] = (k < lo) ? (k_below | (k << 26)) : (k < hi) ? (k_mid | (k << 13)) : (k_above | k);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        } else {
-            unsigned long long q = o + (inc - pc);
-            while (word) {
-                const unsigned long long k = (unsigned long long)(wi * 64 + __ffsll((long long)word) - 1);
-                out[q++] = (k < lo) ? (k_below | (k << 26)) : (k < hi) ? (k_mid | (k << 13)) : (k_above | k);
-                word &= word - 1ull;
-            }
-        }
-        o += tot;
-    }
-}
-
-__device__ __forceinline__ int write_batch_cap(int W) {
-    const int c = VR_YWAVE / W;
-    return c < 1 ? 1 : (c > VR_WAVE ? VR_WAVE : c);
-}
-
+// Edge r = {a, b}: walk b's neighbour-ordered star; entry (k, position pk in
+// b's rank-ordered star) is a triangle of value r when pk < pb and Pa[k] < xa.
+// The sorted vertex triple is (k, lo, hi), (lo, k, hi) or (lo, hi, k) as k
+// falls below, between or above the endpoints, so a key is a per-edge base
+// plus k shifted into place.  Hits of a piece are compacted with ballot and
+// mbcnt and stored contiguously, in k order.
 __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
     extern __shared__ uint32_t lds[];
     const int a = blockIdx.x, n = D.n;
-    const int W = (n + 63) >> 6;
-    const int cap = write_batch_cap(W);
-    uint32_t *Ra = lds;
-    EnumLds &L = *(EnumLds *)(lds + ((n + 3) & ~3));
+    uint16_t *Pa = (uint16_t *)lds;
+    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    unsigned long long *Y = (unsigned long long *)(&L + 1) + (size_t)w * cap * W;
-    uint16_t *stage = (uint16_t *)((unsigned long long *)(&L + 1) + (size_t)ENUM_WAVES * cap * W) + (size_t)w * VR_STAGE;
-    for (int x = lane; x < cap * W; x += VR_WAVE) Y[x] = 0ull;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
-    stage_row(D, Ra, s0, s1);
+    stage_pos(D, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk(D, a, s0, s1, p0, L);
+        load_chunk<true>(D, a, s0, s1, p0, L);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
             const int ne = min(VR_WAVE, w_hi - eb);
-            uint32_t vr = 0, vsb = 0, vpb = 0, vcb = 0, vb = 0;
+            uint32_t vr = 0, vsb = 0, vlen = 0, vxa = 0, vpb = 0, vb = 0;
             unsigned long long voff = 0;
             if (lane < ne) {
                 vr = L.r[eb + lane];
                 vsb = L.sb[eb + lane];
+                vlen = L.len[eb + lane];
+                vxa = L.xa[eb + lane];
                 vpb = L.pb[eb + lane];
-                vcb = L.cb[eb + lane];
                 vb = L.b[eb + lane];
                 voff = D.off[vr];
             }
-            const uint32_t cb_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.cb[eb + ne]);
-            for (int e0 = eb; e0 < eb + ne; e0 += cap) {
-                const int e1 = min(eb + ne, e0 + cap);
-                walk<true>(D, Ra, eb, ne, e0, e1, vr, vsb, vpb, vcb, cb_end, nullptr, Y, W);
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                for (int e = e0; e < e1; e++) {
-                    const int el = e - eb;
-                    const unsigned long long o = ((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
-                                                 rl((uint32_t)voff, el);
-                    emit_edge(Y + (size_t)(e - e0) * W, W, rl(vr, el), (uint32_t)a, rl(vb, el), o, stage, out);
+            uint32_t kA[VR_PIECES], kB[VR_PIECES];
+            issue<uint32_t>(D.star_k + rl(vsb, 0), rl(vlen, 0), 0xFFFFFFFFu, kA);
+            for (int el = 0; el < ne; el++) {
+                if (el + 1 < ne) issue<uint32_t>(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), 0xFFFFFFFFu, kB);
+                const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
+                const uint32_t r = rl(vr, el);
+                unsigned long long o = ((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) | rl((uint32_t)voff, el);
+                const uint32_t lo = min((uint32_t)a, b), hi = max((uint32_t)a, b);
+                const unsigned long long R = (unsigned long long)r << 39;
+                const unsigned long long k_below = R | ((unsigned long long)lo << 13) | hi;
+                const unsigned long long k_mid = R | ((unsigned long long)lo << 26) | hi;
+                const unsigned long long k_above = R | ((unsigned long long)lo << 26) | ((unsigned long long)hi << 13);
+                auto piece = [&](uint32_t v) {
+                    const uint32_t k = v & 0xFFFFu, pk = v >> 16;
+                    const bool hit = pk < pb && Pa[k] < xa;
+                    const unsigned long long m = ballot64(hit);
+                    if (hit) {
+                        const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        const unsigned long long kk = k;
+                        out[o + at] = (kk < lo) ? (k_below | (kk << 26)) : (kk < hi) ? (k_mid | (kk << 13)) : (k_above | kk);
+                    }
+                    o += (unsigned long long)__popcll(m);
+                };
+#pragma unroll
+                for (int j = 0; j < VR_PIECES; j++) piece(kA[j]);
+                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                    const uint32_t y = y0 + (uint32_t)lane;
+                    piece((y < len) ? D.star_k[rl(vsb, el) + y] : 0xFFFFFFFFu);
                 }
+#pragma unroll
+                for (int j = 0; j < VR_PIECES; j++) kA[j] = kB[j];
             }
         }
         __syncthreads();
@@ -447,13 +418,7 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
 }
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s) {
-    const int W = (D.n + 63) >> 6;
-    int cap = VR_YWAVE / W;
-    cap = cap < 1 ? 1 : (cap > VR_WAVE ? VR_WAVE : cap);
-    const size_t lds = enum_lds(D.n) + (size_t)ENUM_WAVES * cap * W * 8 + (size_t)ENUM_WAVES * VR_STAGE * 2;
-    static_assert(4 * VR_MAXN + sizeof(EnumLds) + ENUM_WAVES * VR_YWAVE * 8 + ENUM_WAVES * VR_STAGE * 2 <= 65536,
-                  "write kernel LDS above 64 KiB at the largest n");
-    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(ENUM_BLOCK), lds, s, D, tri_out);
+    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, tri_out);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

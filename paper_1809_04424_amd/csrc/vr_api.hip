@@ -87,7 +87,7 @@ struct Plan {
     size_t off_q, off_key0, off_key1, off_val0, off_val1, off_st0, off_st1;
     size_t off_seij, off_seq;
     size_t off_ikey0, off_ikey1, off_ival0, off_ival1, off_ist0, off_ist1;
-    size_t off_star_r, off_star_nbr, off_start, off_pos, off_cnt, off_off;
+    size_t off_star_r, off_star_nbr, off_star_k, off_start, off_pos, off_cnt, off_off;
     size_t total;
 };
 
@@ -122,6 +122,7 @@ Plan plan(long long n, long long E, long long Kmax, bool tri) {
         P.off_ist1 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntI > 0 ? ntI : 1));
         P.off_star_r = o; o = align_up(o + 8 * (size_t)Kmax);
         P.off_star_nbr = o; o = align_up(o + 4 * (size_t)Kmax);
+        P.off_star_k = o; o = align_up(o + 8 * (size_t)Kmax);
         P.off_start = o; o = align_up(o + 4 * (size_t)(n + 1));
         P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
@@ -346,6 +347,7 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
         D.ist[1] = (uint32_t *)(ws + P.off_ist1);
         D.star_r = (uint32_t *)(ws + P.off_star_r);
         D.star_nbr = (uint16_t *)(ws + P.off_star_nbr);
+        D.star_k = (uint32_t *)(ws + P.off_star_k);
         D.start = (uint32_t *)(ws + P.off_start);
         D.pos = (uint16_t *)(ws + P.off_pos);
         D.cnt = (uint32_t *)(ws + P.off_cnt);

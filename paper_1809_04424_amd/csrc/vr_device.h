@@ -299,6 +299,7 @@ struct VrDev {
     uint32_t *ist[2];       // ceil(2K/TILE)*RADIX star-sort statuses
     uint32_t *star_r;       // 2K: CSR stars, ranks ascending within a vertex
     uint16_t *star_nbr;     // 2K: the other endpoint
+    uint32_t *star_k;       // 2K: stars in neighbour order, neighbour | rank-order position << 16
     uint32_t *start;        // n+1 CSR row starts
     uint16_t *pos;          // 2K: position of edge r in the star of endpoint s (id 2r+s)
     uint32_t *cnt;          // K triangles per value
