@@ -148,12 +148,14 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 }
 
 // Compact the edges a owns among star entries [p0, p0+ENUM_BLOCK) and split
-// them over the waves by piece count.  WRITE: an edge is written at the
+// them by piece count: `parts` work-groups share a vertex (part = this one's
+// index), each taking a contiguous slice, cut again into one run per wave.  WRITE: an edge is written at the
 // endpoint whose partner has the shorter star (candidates = the partner's
 // whole neighbour-ordered star).  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
 template <bool WRITE>
-__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L) {
+__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L,
+                                          int part, int parts) {
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
@@ -188,14 +190,16 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, ui
     if (threadIdx.x == 0) L.cb[m] = C;
     __syncthreads();
     if ((int)threadIdx.x <= ENUM_WAVES) {
-        const uint32_t target = (uint32_t)(((unsigned long long)C * threadIdx.x) / ENUM_WAVES);
+        // this work-group's slice of the pieces, then one run per wave
+        const unsigned long long gw = (unsigned long long)part * ENUM_WAVES + threadIdx.x;
+        const uint32_t target = (uint32_t)(((unsigned long long)C * gw) / ((unsigned long long)parts * ENUM_WAVES));
         int lo = 0, hi = (int)m;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (L.cb[mid] < target) lo = mid + 1;
             else hi = mid;
         }
-        L.ew[threadIdx.x] = (threadIdx.x == ENUM_WAVES) ? m : (uint32_t)lo;
+        L.ew[threadIdx.x] = (gw == (unsigned long long)parts * ENUM_WAVES) ? m : (uint32_t)lo;
     }
     __syncthreads();
     return (int)m;
@@ -226,16 +230,16 @@ __device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T
 }
 
 // ----------------------------------------------------------- k_tri_count ----
-__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
+__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
     extern __shared__ uint32_t lds[];
-    const int a = blockIdx.x, n = D.n;
+    const int a = blockIdx.x / parts, part = blockIdx.x % parts, n = D.n;
     uint16_t *Pa = (uint16_t *)lds;
     EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
     stage_pos(D, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk<false>(D, a, s0, s1, p0, L);
+        load_chunk<false>(D, a, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -275,8 +279,16 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D) {
     }
 }
 
+// Work-groups per vertex: enough groups to spread heavy vertices over many
+// compute units when the cloud is small.
+int enum_parts(int n) {
+    int p = 4096 / (n > 0 ? n : 1);
+    return p < 1 ? 1 : (p > 8 ? 8 : p);
+}
+
 void launch_tri_count(const VrDev &D, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_count, dim3(D.n), dim3(ENUM_BLOCK), enum_lds(D.n), s, D);
+    const int parts = enum_parts(D.n);
+    hipLaunchKernelGGL(k_tri_count, dim3(D.n * parts), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, parts);
 }
 
 // ---------------------------------------------------------------- k_scan ----
@@ -355,16 +367,16 @@ void launch_publish(const VrDev &D, hipStream_t s) {
 // falls below, between or above the endpoints, so a key is a per-edge base
 // plus k shifted into place.  Hits of a piece are compacted with ballot and
 // mbcnt and stored contiguously, in k order.
-__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out) {
+__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts) {
     extern __shared__ uint32_t lds[];
-    const int a = blockIdx.x, n = D.n;
+    const int a = blockIdx.x / parts, part = blockIdx.x % parts, n = D.n;
     uint16_t *Pa = (uint16_t *)lds;
     EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
     stage_pos(D, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk<true>(D, a, s0, s1, p0, L);
+        load_chunk<true>(D, a, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -418,7 +430,8 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
 }
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_write, dim3(D.n), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, tri_out);
+    const int parts = enum_parts(D.n);
+    hipLaunchKernelGGL(k_tri_write, dim3(D.n * parts), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, tri_out, parts);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----
