@@ -218,14 +218,17 @@ __device__ __forceinline__ void stage_pos(const VrDev &D, uint16_t *Pa, uint32_t
 
 size_t enum_lds(int n) { return 2 * (size_t)((n + 7) & ~7) + sizeof(EnumLds); }
 
-// Load up to VR_PIECES pieces of `len` candidates starting at src.
+// Load up to VR_PIECES pieces of `len` (>= 1) candidates starting at src.
+// Indices are clamped, so every lane loads (no predication); the consumer
+// masks lanes past len.
 template <typename T>
-__device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T fill, T (&kk)[VR_PIECES]) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T (&kk)[VR_PIECES]) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t last = len - 1u;
 #pragma unroll
     for (int j = 0; j < VR_PIECES; j++) {
-        const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
-        kk[j] = (y < len) ? src[y] : fill;
+        const uint32_t y = (uint32_t)(j * VR_WAVE) + lane;
+        kk[j] = src[y < last ? y : last];
     }
 }
 
@@ -253,21 +256,24 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
             }
             uint32_t mycnt = 0;
             uint16_t kA[VR_PIECES], kB[VR_PIECES];
-            issue<uint16_t>(D.star_nbr + rl(vsb, 0), rl(vlen, 0), (uint16_t)0xFFFF, kA);
+            // an edge with an empty prefix loads nothing (its count is 0)
+            if (rl(vlen, 0)) issue<uint16_t>(D.star_nbr + rl(vsb, 0), rl(vlen, 0), kA);
             for (int el = 0; el < ne; el++) {
-                if (el + 1 < ne) issue<uint16_t>(D.star_nbr + rl(vsb, el + 1), rl(vlen, el + 1), (uint16_t)0xFFFF, kB);
+                if (el + 1 < ne && rl(vlen, el + 1)) issue<uint16_t>(D.star_nbr + rl(vsb, el + 1), rl(vlen, el + 1), kB);
                 const uint32_t xa = rl(vxa, el), len = rl(vlen, el);
                 uint32_t c = 0;
+                if (len) {
 #pragma unroll
-                for (int j = 0; j < VR_PIECES; j++) {
-                    const uint32_t k = kA[j];
-                    const bool hit = k != 0xFFFFu && Pa[k] < xa;
-                    c += (uint32_t)__popcll(ballot64(hit));
-                }
-                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
-                    const uint32_t y = y0 + (uint32_t)lane;
-                    const uint32_t k = (y < len) ? D.star_nbr[rl(vsb, el) + y] : 0xFFFFu;
-                    c += (uint32_t)__popcll(ballot64(k != 0xFFFFu && Pa[k] < xa));
+                    for (int j = 0; j < VR_PIECES; j++) {
+                        const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
+                        const bool hit = (y < len) & ((uint32_t)Pa[kA[j]] < xa);
+                        c += (uint32_t)__popcll(ballot64(hit));
+                    }
+                    for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                        const uint32_t y = y0 + (uint32_t)lane;
+                        const uint32_t k = D.star_nbr[rl(vsb, el) + (y < len ? y : len - 1u)];
+                        c += (uint32_t)__popcll(ballot64((y < len) & ((uint32_t)Pa[k] < xa)));
+                    }
                 }
                 if (lane == el) mycnt = c;
 #pragma unroll
@@ -393,33 +399,41 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                 voff = D.off[vr];
             }
             uint32_t kA[VR_PIECES], kB[VR_PIECES];
-            issue<uint32_t>(D.star_k + rl(vsb, 0), rl(vlen, 0), 0xFFFFFFFFu, kA);
+            issue<uint32_t>(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
             for (int el = 0; el < ne; el++) {
-                if (el + 1 < ne) issue<uint32_t>(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), 0xFFFFFFFFu, kB);
+                if (el + 1 < ne) issue<uint32_t>(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), kB);
                 const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
                 const uint32_t r = rl(vr, el);
-                unsigned long long o = ((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) | rl((uint32_t)voff, el);
+                unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
+                                                 rl((uint32_t)voff, el));
+                // key = (r << 39) | (sorted triple), split into 32-bit halves
                 const uint32_t lo = min((uint32_t)a, b), hi = max((uint32_t)a, b);
-                const unsigned long long R = (unsigned long long)r << 39;
-                const unsigned long long k_below = R | ((unsigned long long)lo << 13) | hi;
-                const unsigned long long k_mid = R | ((unsigned long long)lo << 26) | hi;
-                const unsigned long long k_above = R | ((unsigned long long)lo << 26) | ((unsigned long long)hi << 13);
-                auto piece = [&](uint32_t v) {
+                const uint32_t rh = r << 7;                      // bits 39.. of the key, in the high word
+                const uint32_t below_lo = (lo << 13) | hi;       // (k, lo, hi): k<<26 added per lane
+                const uint32_t mid_lo = (lo << 26) | hi;         // (lo, k, hi): k<<13
+                const uint32_t mid_hi = rh | (lo >> 6);
+                const uint32_t above_lo = (lo << 26) | (hi << 13);  // (lo, hi, k): k
+                // one 64-entry piece of the partner's neighbour-ordered star
+                auto piece = [&](uint32_t v, uint32_t y) {
                     const uint32_t k = v & 0xFFFFu, pk = v >> 16;
-                    const bool hit = pk < pb && Pa[k] < xa;
+                    const bool hit = (y < len) & (pk < pb) & ((uint32_t)Pa[k] < xa);
                     const unsigned long long m = ballot64(hit);
-                    if (hit) {
-                        const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        const unsigned long long kk = k;
-                        out[o + at] = (kk < lo) ? (k_below | (kk << 26)) : (kk < hi) ? (k_mid | (kk << 13)) : (k_above | kk);
-                    }
-                    o += (unsigned long long)__popcll(m);
+                    // all three candidates first, then selects (no divergent branches)
+                    const uint32_t c_below = below_lo | (k << 26), c_mid = mid_lo | (k << 13), c_above = above_lo | k;
+                    const uint32_t h_below = rh | (k >> 6);
+                    const bool blw = k < lo, abv = k >= hi;
+                    const uint32_t c_up = abv ? c_above : c_mid;
+                    const uint32_t klo = blw ? c_below : c_up;
+                    const uint32_t khi = blw ? h_below : mid_hi;
+                    const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (hit) dst[at] = ((unsigned long long)khi << 32) | klo;
+                    dst += __popcll(m);
                 };
 #pragma unroll
-                for (int j = 0; j < VR_PIECES; j++) piece(kA[j]);
+                for (int j = 0; j < VR_PIECES; j++) piece(kA[j], (uint32_t)(j * VR_WAVE + lane));
                 for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                     const uint32_t y = y0 + (uint32_t)lane;
-                    piece((y < len) ? D.star_k[rl(vsb, el) + y] : 0xFFFFFFFFu);
+                    piece(D.star_k[rl(vsb, el) + (y < len ? y : len - 1u)], y);
                 }
 #pragma unroll
                 for (int j = 0; j < VR_PIECES; j++) kA[j] = kB[j];
