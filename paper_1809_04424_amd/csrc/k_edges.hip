@@ -396,6 +396,8 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->n_kept = (uint32_t)K;
         ctl->n_inc = (uint32_t)(2 * K);
+        // without triangles this is the last phase-1 kernel: publish now
+        if (!D.tri) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, (uint32_t)K, 0ull);
     }
     if (D.tri) {
         for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK) (&h[0][0])[x] = 0u;

@@ -18,8 +18,8 @@
 //                 (neighbour | position in the rank-ordered star << 16)
 //   k_tri_count   per vertex a: for each edge a owns, count the neighbours in
 //                 the partner's rank prefix that precede the edge in a's star
-//   k_scan        exclusive scan of the counts (decoupled look-back)
-//   k_publish     counts to the host-pinned mailbox
+//   k_scan        exclusive scan of the counts (decoupled look-back); the
+//                 last tile stores (flags, K, T) into the host-pinned mailbox
 //   k_tri_write   per vertex a: for each edge a owns, walk the partner's
 //                 neighbour-ordered star; hits are compacted with ballot and
 //                 mbcnt (the ballot/popc compaction of the paper's init_supp,
@@ -306,6 +306,8 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
     const int t = threadIdx.x;
     const long long K = (long long)ctl->n_kept;
     const int ntiles = (int)((K + VR_TILE - 1) / VR_TILE);
+    if (ntiles == 0 && blockIdx.x == 0 && t == 0)
+        publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, 0ull);
     for (;;) {
         const int tile = claim_tile(&ctl->ticket[5], &sh_tile);
         if (tile >= ntiles) break;
@@ -330,7 +332,10 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
             }
             if (t == 0) {
                 sh_prefix = prefix;
-                if (tile == ntiles - 1) ctl->n_tri = prefix + tot;
+                if (tile == ntiles - 1) {
+                    ctl->n_tri = prefix + tot;
+                    publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
+                }
             }
         }
         __syncthreads();
@@ -350,22 +355,6 @@ void launch_scan(const VrDev &D, long long Kmax, hipStream_t s) {
     hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
 }
 
-// ------------------------------------------------------------- k_publish ----
-__global__ void k_publish(VrDev D) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const VrCtl *ctl = D.ctl;
-    VrMailbox *mb = D.mailbox;
-    __hip_atomic_store(&mb->flags, ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mb->n_cand, ctl->n_cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mb->n_kept, ctl->n_kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mb->n_tri, D.tri ? ctl->n_tri : 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mb->seq, D.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-void launch_publish(const VrDev &D, hipStream_t s) {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, D);
-}
-
 // ----------------------------------------------------------- k_tri_write ----
 // Edge r = {a, b}: walk b's neighbour-ordered star; entry (k, position pk in
 // b's rank-ordered star) is a triangle of value r when pk < pb and Pa[k] < xa.
@@ -373,8 +362,28 @@ void launch_publish(const VrDev &D, hipStream_t s) {
 // falls below, between or above the endpoints, so a key is a per-edge base
 // plus k shifted into place.  Hits of a piece are compacted with ballot and
 // mbcnt and stored contiguously, in k order.
-__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts) {
+__device__ __forceinline__ void emit_edges_range(const VrDev &D, long long K, uint32_t *__restrict__ ij,
+                                                 long long *__restrict__ q, long long first, long long stride) {
+    for (long long r = first; r < K; r += stride) {
+        const uint32_t v = D.se_ij[r];
+        ij[2 * r] = v >> 16;
+        ij[2 * r + 1] = v & 0xFFFFu;
+        q[r] = (long long)D.se_q[r];
+    }
+}
+
+// Blocks [0, n*parts) write triangles; the blocks after them write the
+// public edge arrays.
+__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts,
+                                                          long long K, uint32_t *__restrict__ edge_ij,
+                                                          long long *__restrict__ edge_q) {
     extern __shared__ uint32_t lds[];
+    const int nb = D.n * parts;
+    if ((int)blockIdx.x >= nb) {
+        emit_edges_range(D, K, edge_ij, edge_q, (long long)(blockIdx.x - nb) * ENUM_BLOCK + threadIdx.x,
+                         (long long)(gridDim.x - nb) * ENUM_BLOCK);
+        return;
+    }
     const int a = blockIdx.x / parts, part = blockIdx.x % parts, n = D.n;
     uint16_t *Pa = (uint16_t *)lds;
     EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
@@ -443,9 +452,14 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
     }
 }
 
-void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s) {
+void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
+                      hipStream_t s) {
     const int parts = enum_parts(D.n);
-    hipLaunchKernelGGL(k_tri_write, dim3(D.n * parts), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, tri_out, parts);
+    long long eb = (K + ENUM_BLOCK - 1) / ENUM_BLOCK;
+    if (eb > 256) eb = 256;
+    if (eb < 1) eb = 1;
+    hipLaunchKernelGGL(k_tri_write, dim3((unsigned)(D.n * parts + eb)), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, tri_out,
+                       parts, K, edge_ij, edge_q);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

@@ -381,8 +381,7 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     if (want_tri) launch_tri_count(D, s);
     mark(ST_SCAN);
     // the scan reads K from the device (unknown on the host for SQDIST)
-    if (want_tri) launch_scan(D, Kmax, s);
-    launch_publish(D, s);
+    if (want_tri) launch_scan(D, Kmax, s);  // its last tile publishes the counts
     mark(ST_SYNC);
     if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);
@@ -431,9 +430,15 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     res->n_triangles = (int64_t)T;
 
     mark(ST_WRITE);
-    if (write_tri) launch_tri_write(D, (unsigned long long *)res->tri_key, s);
-    mark(ST_EMIT);
-    launch_emit_edges(D, K, (uint32_t *)res->edge_ij, (long long *)res->edge_q, s);
+    if (write_tri) {
+        // the triangle writer also writes the public edge arrays
+        launch_tri_write(D, (unsigned long long *)res->tri_key, K, (uint32_t *)res->edge_ij,
+                         (long long *)res->edge_q, s);
+        mark(ST_EMIT);
+    } else {
+        mark(ST_EMIT);
+        launch_emit_edges(D, K, (uint32_t *)res->edge_ij, (long long *)res->edge_q, s);
+    }
     mark(ST_N);
     if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);

@@ -261,6 +261,17 @@ __device__ __forceinline__ void pair_of(long long e, long long n, int *pi, int *
     *pj = (int)(e - row_start(i, n) + i + 1);
 }
 
+// Store the phase-1 results into the host-pinned mailbox (system scope; the
+// sequence number last, so the host sees complete counts once it matches).
+__device__ __forceinline__ void publish_counts(VrMailbox *mb, uint32_t seq, uint32_t flags, uint32_t n_cand,
+                                               uint32_t n_kept, unsigned long long n_tri) {
+    __hip_atomic_store(&mb->flags, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->n_cand, n_cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->n_kept, n_kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->n_tri, n_tri, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ------------------------------------------------------- launch wrappers ----
 // One stable LSD radix sort (keys with values) over a device-side count.
 struct SortJob {
@@ -321,6 +332,6 @@ void launch_edges(const VrDev &D, hipStream_t s);
 void launch_star(const VrDev &D, hipStream_t s);
 void launch_tri_count(const VrDev &D, hipStream_t s);
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
-void launch_publish(const VrDev &D, hipStream_t s);
-void launch_tri_write(const VrDev &D, unsigned long long *tri_out, hipStream_t s);
+void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
+                      hipStream_t s);
 void launch_emit_edges(const VrDev &D, long long K, uint32_t *edge_ij, long long *edge_q, hipStream_t s);
