@@ -92,6 +92,36 @@ def _cpu_baseline(cloud, budget_s=12.0):
                       f"(distances, sortperm, rank matrix, triangle triple loop, qsort); {el:.1f} s"}
 
 
+def _batched(vr, torch, reps=3):
+    """512 R^3 clouds (n log-uniform in [50, 2000], 5th-25th percentile) as
+    one batched build, against the same clouds built one call at a time."""
+    import workloads
+
+    clouds = workloads.batched()
+    pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
+    thrs = [c.thr for c in clouds]
+    torch.cuda.synchronize()
+    vr.build_batch(pts, thrs).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b = vr.build_batch(pts, thrs)
+        simp = sum(sum(it.counts) for it in b)
+        b.free()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    print(f"[bench] batched512: {tb * 1e3:.2f} ms per batch", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for p, t in zip(pts, thrs):
+        vr.build(p, t).free()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    print(f"[bench] batched512: {ts * 1e3:.2f} ms one cloud at a time", file=sys.stderr, flush=True)
+    return {"value": simp / tb, "unit": "simplices/s", "ms_per_batch": 1e3 * tb, "simplices": simp,
+            "clouds": len(clouds), "points": sum(c.n for c in clouds),
+            "per_cloud_builds": {"value": simp / ts, "ms": 1e3 * ts}, "speedup_vs_per_cloud": ts / tb}
+
+
 def _copy_calibration(torch, mib=256):
     """A plain device copy of known size, so FETCH_SIZE / WRITE_SIZE of other
     kernels can be scaled to bytes (launched only with --copy-calib)."""
@@ -112,6 +142,7 @@ def main():
     ap.add_argument("--workload", default="circle1000")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-cloud batched side measurement")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--breakdown-reps", type=int, default=10, help="untimed builds for the stage breakdown (0: skip)")
@@ -163,6 +194,9 @@ def main():
             "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
             "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3) if args.breakdown_reps > 0 else {}}
         del p3
+
+    if not args.no_batch and args.workload == "circle1000":
+        extra["batched512_r3"] = _batched(vr, torch)
 
     line = {
         "metric": "filtered simplices/sec (VR dim<=2, bit-exact)",

@@ -120,7 +120,8 @@ typedef struct vr_result {
 /*
  * Build the filtration of one point cloud.
  * Enqueues all work on `stream` (a hipStream_t; NULL = the null stream) and
- * synchronises that stream once, to read the triangle count.  On VR_OK,
+ * waits once for the first phase (distances up to triangle counts) to reach
+ * the host through host-pinned memory, to size the outputs.  On VR_OK,
  * *out receives a new handle whose device arrays are complete once `stream`
  * reaches the end of this call's work (stream order).  On error *out is not
  * written and nothing is leaked.
@@ -150,10 +151,44 @@ VR_API void vr_free(vr_result *res, void *stream);
  * Returns -1 for shapes vr_build would reject. */
 VR_API int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind);
 
+/*
+ * Batched builds: many independent clouds in one launch sequence instead of
+ * one sequence per cloud.  Like the column partition of Section 4.6, the
+ * parts are computed independently and their output offsets are fixed up
+ * afterwards; here a part is a cloud.
+ *
+ * A batch is `count` requests that share dtype, d, thr_kind, maxdim and flags
+ * (VR_EINVAL otherwise) and take their allocator from reqs[0]; n, points and
+ * the threshold values are per request.  Every kernel runs once over all
+ * clouds: vertices, pairs and distance tiles are numbered across the batch,
+ * and the edge sort key carries the cloud index above the squared distance,
+ * so each cloud's result is bit-identical to its own vr_build.  The key must
+ * fit 32 bits: bits(255^2 d) + bits(count-1) <= 32 for VR_I8, so VR_I16 and
+ * VR_I32 batches hold one cloud each (VR_E2BIG otherwise; split the batch).
+ * Other limits of the whole batch: fewer than 2^24 vertices, fewer than 2^32
+ * pairs and 2^31 kept edges (VR_E2BIG).  Each request keeps the per-cloud
+ * limits of vr_build.  Same stream semantics and error behaviour as vr_build.
+ */
+typedef struct vr_batch vr_batch;
+
+VR_API int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, vr_batch **out);
+
+/* View of request `index`: counts and device pointers into the batch's
+ * output block (valid until vr_batch_free).  Host only.  VR_EINVAL for an
+ * index outside [0, count). */
+VR_API int vr_batch_result(const vr_batch *batch, int64_t index, vr_result *view);
+
+/* As vr_query_stage_ms, for the whole batch. */
+VR_API int vr_batch_stage_ms(const vr_batch *batch, float *ms, int cap);
+
+/* Releases the batch's device memory in stream order on `stream`, then the
+ * handle; every view dies with it.  NULL-safe. */
+VR_API void vr_batch_free(vr_batch *batch, void *stream);
+
 /* Static description of a status code. */
 VR_API const char *vr_status_string(int status);
 
-/* Library version, e.g. 100 for 0.1.0. */
+/* Library version, e.g. 110 for 0.1.1. */
 VR_API int vr_version(void);
 
 #ifdef __cplusplus

@@ -4,7 +4,7 @@ Argument marshalling only: every step of the build runs in the library's HIP
 kernels.  PyTorch supplies device memory (through the library's allocator
 hook, so outputs are ordinary torch tensors) and the stream.  There is no CPU
 fallback: importing works without the library, but every call raises until
-``build.py`` has produced ``libvrhip.so``.
+``make_lib.py`` has produced ``libvrhip.so``.
 """
 from __future__ import annotations
 
@@ -24,7 +24,8 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_status_string", "vr_version")
+           "vr_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free",
+           "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -93,6 +94,15 @@ def lib():
         L.vr_free.restype = None
         L.vr_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
         L.vr_workspace_bytes.restype = ctypes.c_int64
+        L.vr_build_batch.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+        L.vr_build_batch.restype = ctypes.c_int
+        L.vr_batch_result.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(VrResult)]
+        L.vr_batch_result.restype = ctypes.c_int
+        L.vr_batch_stage_ms.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+        L.vr_batch_stage_ms.restype = ctypes.c_int
+        L.vr_batch_free.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_batch_free.restype = None
         L.vr_status_string.argtypes = [ctypes.c_int]
         L.vr_status_string.restype = ctypes.c_char_p
         L.vr_version.argtypes = []
@@ -175,19 +185,14 @@ class _DeviceArray:
                                          "version": 2, "strides": None}
 
 
-class Result:
-    """Handle of one build.  Device arrays are torch tensors over the
-    library's output block; they stay valid while any of them is referenced."""
+class _Arrays:
+    """Counts and device arrays of one cloud's filtration (a vr_result view)."""
 
-    def __init__(self, ptr, alloc, stream, device):
-        self._ptr = ptr
-        self._alloc = alloc
-        self._stream = stream
+    def _init_arrays(self, r, device, block=None, block_ptr=0):
         self._device = device
-        r = ptr.contents
         self.n, self.K, self.T = int(r.n_vertices), int(r.n_edges), int(r.n_triangles)
         self._p_q, self._p_ij, self._p_tri = r.edge_q, r.edge_ij, r.tri_key
-        self._block = alloc.live.get(r.edge_q) if (alloc is not None and r.edge_q) else None
+        self._block, self._block_ptr = block, block_ptr
 
     @property
     def counts(self):
@@ -199,7 +204,7 @@ class Result:
         if not ptr or count == 0:  # nothing written (count-only build) or empty
             return torch.empty((0,) + tuple(shape[1:]), dtype=dtype, device=self._device)
         if self._block is not None:  # torch-allocated block
-            off = ptr - self._p_q
+            off = ptr - self._block_ptr
             return self._block[off: off + count * itemsize].view(dtype).view(shape)
         return torch.as_tensor(_DeviceArray(self, ptr, shape, typestr), device=self._device)
 
@@ -221,13 +226,30 @@ class Result:
 
         return self._tensor(self._p_tri, self.T, torch.int64, "<i8", 8, (self.T,))
 
+
+def _stage_dict(fn, handle):
+    buf = (ctypes.c_float * 32)()
+    k = fn(handle, buf, 32)
+    if k < 0:
+        raise VrError(k, status_string(k))
+    return dict(zip(stage_names(), list(buf)[:k]))
+
+
+class Result(_Arrays):
+    """Handle of one build.  Device arrays are torch tensors over the
+    library's output block; they stay valid while any of them is referenced."""
+
+    def __init__(self, ptr, alloc, stream, device):
+        self._ptr = ptr
+        self._alloc = alloc
+        self._stream = stream
+        r = ptr.contents
+        blk = alloc.live.get(r.edge_q) if (alloc is not None and r.edge_q) else None
+        self._init_arrays(r, device, blk, r.edge_q or 0)
+
     def stage_ms(self):
         """{stage: ms} of a build made with timing=True."""
-        buf = (ctypes.c_float * 32)()
-        k = lib().vr_query_stage_ms(self._ptr, buf, 32)
-        if k < 0:
-            raise VrError(k, status_string(k))
-        return dict(zip(stage_names(), list(buf)[:k]))
+        return _stage_dict(lib().vr_query_stage_ms, self._ptr)
 
     def free(self):
         if self._ptr is not None:
@@ -239,6 +261,102 @@ class Result:
             self.free()
         except Exception:
             pass
+
+
+class BatchItem(_Arrays):
+    """One cloud of a batch: a view into the batch's output block."""
+
+    def __init__(self, batch, r, device, block, block_ptr):
+        self._batch = batch  # library-owned memory lives as long as the batch
+        self._init_arrays(r, device, block, block_ptr)
+
+
+class Batch:
+    """Handle of one batched build; batch[i] is the result of request i."""
+
+    def __init__(self, ptr, alloc, stream, device, count):
+        self._ptr = ptr
+        self._alloc = alloc
+        self._stream = stream
+        L = lib()
+        views = []
+        for i in range(count):
+            r = VrResult()
+            rc = L.vr_batch_result(ptr, i, ctypes.byref(r))
+            if rc != VR_OK:
+                raise VrError(rc, status_string(rc))
+            views.append(r)
+        blk, base = None, 0
+        if alloc is not None:  # the view whose edges start the block
+            for r in views:
+                if r.edge_q and r.edge_q in alloc.live:
+                    blk, base = alloc.live[r.edge_q], r.edge_q
+                    break
+        self.items = [BatchItem(self, r, device, blk, base) for r in views]
+
+    def __len__(self):
+        return len(self.items)
+
+    def __getitem__(self, i):
+        return self.items[i]
+
+    def __iter__(self):
+        return iter(self.items)
+
+    def stage_ms(self):
+        """{stage: ms} of a batch built with timing=True."""
+        return _stage_dict(lib().vr_batch_stage_ms, self._ptr)
+
+    def free(self):
+        if self._ptr is not None:
+            lib().vr_batch_free(self._ptr, self._stream)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _flags(count_only, timing):
+    return (VR_COUNT_ONLY if count_only else 0) | (VR_TIMING_WRITE if timing == "write" else
+                                                   VR_TIMING if timing else 0)
+
+
+def _request(pts, thr, maxdim, flags, alloc):
+    kind, num, den = thr
+    return VrRequest(
+        points=pts.data_ptr() if pts.numel() else None,
+        n=pts.shape[0],
+        d=pts.shape[1],
+        dtype=_dtype_code(pts),
+        thr_kind=VR_THR[kind],
+        thr_num=int(num),
+        thr_den=int(den),
+        maxdim=int(maxdim),
+        flags=flags,
+        alloc=ctypes.pointer(alloc.struct) if alloc is not None else None,
+    )
+
+
+def _check_points(points):
+    import torch
+
+    if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+        raise TypeError("points must be a torch tensor on a HIP device")
+    if points.dim() != 2:
+        raise ValueError("points must be 2-D (n, d)")
+    return points.contiguous()
+
+
+def batch_limit(dtype: int, d: int) -> int:
+    """Most clouds one batch of this coordinate type and dimension may hold:
+    the sort key keeps the cloud index above a squared distance in 32 bits."""
+    if dtype != VR_I8:
+        return 1
+    qbits = (65025 * int(d)).bit_length()
+    return 1 << max(0, 32 - qbits)
 
 
 def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing=False,
@@ -256,30 +374,46 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
     import torch
 
     L = lib()
-    if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
-        raise TypeError("points must be a torch tensor on a HIP device")
-    if points.dim() != 2:
-        raise ValueError("points must be 2-D (n, d)")
-    pts = points.contiguous()
-    kind, num, den = thr
+    pts = _check_points(points)
     alloc = _allocator_for(pts.device) if allocator == "torch" else None
     stream = torch.cuda.current_stream(pts.device)
-    req = VrRequest(
-        points=pts.data_ptr() if pts.numel() else None,
-        n=pts.shape[0],
-        d=pts.shape[1],
-        dtype=_dtype_code(pts),
-        thr_kind=VR_THR[kind],
-        thr_num=int(num),
-        thr_den=int(den),
-        maxdim=int(maxdim),
-        flags=(VR_COUNT_ONLY if count_only else 0) | (VR_TIMING_WRITE if timing == "write" else
-                                                      VR_TIMING if timing else 0),
-        alloc=ctypes.pointer(alloc.struct) if alloc is not None else None,
-    )
+    req = _request(pts, thr, maxdim, _flags(count_only, timing), alloc)
     out = ctypes.POINTER(VrResult)()
     with torch.cuda.device(pts.device):
         rc = L.vr_build(ctypes.byref(req), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return Result(out, alloc, ctypes.c_void_p(stream.cuda_stream), pts.device)
+
+
+def build_batch(points, thr, maxdim: int = 2, count_only: bool = False, timing=False,
+                allocator: str = "library") -> Batch:
+    """Build the filtrations of many clouds with one launch sequence.
+
+    points: list of device tensors (n_c, d), one dtype and d for all.
+    thr:    one threshold tuple for all clouds, or a list of them (one kind).
+    Each batch[c] is bit-identical to build(points[c], thr[c]).  At most
+    batch_limit(dtype, d) clouds per batch.
+    """
+    import torch
+
+    L = lib()
+    pts = [_check_points(p) for p in points]
+    if not pts:
+        raise ValueError("empty batch")
+    thrs = list(thr) if isinstance(thr, list) else [thr] * len(pts)
+    if len(thrs) != len(pts):
+        raise ValueError("one threshold per cloud")
+    dev = pts[0].device
+    if any(p.device != dev for p in pts):
+        raise ValueError("all clouds must be on one device")
+    alloc = _allocator_for(dev) if allocator == "torch" else None
+    stream = torch.cuda.current_stream(dev)
+    flags = _flags(count_only, timing)
+    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, flags, alloc) for p, t in zip(pts, thrs)])
+    out = ctypes.c_void_p()
+    with torch.cuda.device(dev):
+        rc = L.vr_build_batch(reqs, len(pts), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return Batch(out, alloc, ctypes.c_void_p(stream.cuda_stream), dev, len(pts))

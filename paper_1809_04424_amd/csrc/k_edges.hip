@@ -1,33 +1,59 @@
 // k_edges.hip -- squared distances, threshold selection and the edge-rank
 // radix sort (the paper's sortperm step, Section 4.5, rebuilt as a stable
-// LSD radix sort over the kept edges only).
+// LSD radix sort over the kept edges only), for one cloud or a batch.
 //
-//   k_init       zero the control block, degrees and select statuses
-//   k_dist       exact integer squared distance of every pair i<j (VALU),
-//                plus a log-linear histogram used to find the threshold
-//   k_select     compact the candidate edges in pair order (decoupled
-//                look-back) and histogram their radix digits
+//   k_init       zero the control block, histograms and statuses
+//   k_dist       exact integer squared distance of every pair i<j of every
+//                cloud (VALU), plus a per-cloud log-linear histogram used to
+//                find percentile thresholds
+//   k_pivot      per cloud, the histogram bucket holding the K-th distance
+//   k_select     compact the candidate edges in (cloud, pair) order
+//                (decoupled look-back) and histogram their radix digits
 //   k_sort_pass  one stable 8-bit LSD pass (Onesweep: Adinets and Merrill,
-//                2022), skipped when every key shares the digit
-//   k_edges      write the K kept edges in rank order and bin them by vertex
+//                2022), skipped when every key shares the digit; keys are
+//                (cloud << qbits) | q, so clouds stay apart
+//   k_edges      the kept edges of every cloud in rank order, and their two
+//                vertex incidences for the star sort
 #include "vr_device.h"
 
 // --------------------------------------------------------------- k_init ----
-__global__ __launch_bounds__(VR_BLOCK) void k_init(uint32_t *__restrict__ w, size_t words) {
+__global__ __launch_bounds__(VR_BLOCK) void k_init(uint32_t *__restrict__ w, size_t words, VrCloud one,
+                                                    VrCloud *__restrict__ dst) {
+    if (dst && blockIdx.x == 0 && threadIdx.x == 0) *dst = one;
     for (size_t x = (size_t)blockIdx.x * VR_BLOCK + threadIdx.x; x < words; x += (size_t)gridDim.x * VR_BLOCK)
         w[x] = 0u;
 }
 
-void launch_init(const VrDev &D, size_t zero_words, hipStream_t s) {
+// dst != null: also store the single cloud's descriptor (no host copy).
+void launch_init(const VrDev &D, size_t zero_words, const VrCloud *one, VrCloud *dst, hipStream_t s) {
     size_t blocks = (zero_words + VR_BLOCK - 1) / VR_BLOCK;
     if (blocks > 1024) blocks = 1024;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(VR_BLOCK), 0, s, (uint32_t *)D.ctl, zero_words);
+    VrCloud c{};
+    if (one) c = *one;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(VR_BLOCK), 0, s, (uint32_t *)D.ctl, zero_words, c,
+                       one ? dst : nullptr);
+}
+
+// Distance tile t of a cloud with nb 64-point blocks: tiles are the blocks
+// (bi, bj), bi <= bj, in row order.
+__device__ __forceinline__ long long tile_row_start(long long bi, long long nb) { return bi * nb - bi * (bi - 1) / 2; }
+
+__device__ __forceinline__ void tile_of(long long t, long long nb, int *bi, int *bj) {
+    double b = 2.0 * (double)nb + 1.0;
+    double disc = b * b - 8.0 * (double)t;
+    long long i = (long long)((b - sqrt(disc > 0 ? disc : 0.0)) * 0.5);
+    if (i < 0) i = 0;
+    if (i > nb - 1) i = nb - 1;
+    while (i > 0 && tile_row_start(i, nb) > t) i--;
+    while (i < nb - 1 && tile_row_start(i + 1, nb) <= t) i++;
+    *bi = (int)i;
+    *bj = (int)(t - tile_row_start(i, nb) + i);
 }
 
 // --------------------------------------------------------------- k_dist ----
-// One work-group computes the 64 x 64 pairs (i in block bi, j in block bj),
-// bi <= bj.  Lane l of every wave owns column j = 64*bj + l; wave w owns rows
+// One work-group computes the 64 x 64 pairs (i in block bi, j in block bj) of
+// one cloud.  Lane l of every wave owns column j = 64*bj + l; wave w owns rows
 // i = 64*bi + w + 4m (m < 16).  Coordinates are staged through LDS 64 at a
 // time; the column operand is padded to avoid bank conflicts.  Writes of a
 // row are contiguous in pair order, so every wave stores 256 contiguous bytes.
@@ -35,13 +61,19 @@ void launch_init(const VrDev &D, size_t zero_words, hipStream_t s) {
 #define DIST_CC 64
 
 template <typename T>
-__global__ __launch_bounds__(VR_BLOCK) void k_dist(const T *__restrict__ pts, int n, int d, int need_hist,
-                                                   uint32_t *__restrict__ q, VrCtl *__restrict__ ctl) {
-    const int bi = blockIdx.y, bj = blockIdx.x;
-    if (bi > bj) return;
+__global__ __launch_bounds__(VR_BLOCK) void k_dist(VrDev D) {
+    const long long tg = blockIdx.x;
+    const int c = cloud_of(tg, D.C, [&](int k) { return D.cl[k].tbase; });
+    const VrCloud cl = D.cl[c];
+    const int n = cl.n, d = D.d;
+    int bi, bj;
+    tile_of(tg - cl.tbase, (n + DIST_TB - 1) / DIST_TB, &bi, &bj);
+    const T *__restrict__ pts = (const T *)cl.points;
+    uint32_t *__restrict__ q = D.q + cl.pbase;
     __shared__ int32_t xi[DIST_TB][DIST_CC];
     __shared__ int32_t xj[DIST_TB][DIST_CC + 1];
     __shared__ uint32_t hist[VR_NBUCKET];
+    const int need_hist = D.need_hist;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = bj * DIST_TB + lane;
     unsigned long long acc[16];
@@ -54,17 +86,17 @@ __global__ __launch_bounds__(VR_BLOCK) void k_dist(const T *__restrict__ pts, in
         const int cc = min(DIST_CC, d - c0);
         __syncthreads();
         for (int x = threadIdx.x; x < DIST_TB * DIST_CC; x += VR_BLOCK) {
-            int r = x / DIST_CC, c = x % DIST_CC;
+            int r = x / DIST_CC, cx = x % DIST_CC;
             int gi = bi * DIST_TB + r, gj = bj * DIST_TB + r;
-            xi[r][c] = (gi < n && c < cc) ? (int32_t)pts[(size_t)gi * d + c0 + c] : 0;
-            xj[r][c] = (gj < n && c < cc) ? (int32_t)pts[(size_t)gj * d + c0 + c] : 0;
+            xi[r][cx] = (gi < n && cx < cc) ? (int32_t)pts[(size_t)gi * d + c0 + cx] : 0;
+            xj[r][cx] = (gj < n && cx < cc) ? (int32_t)pts[(size_t)gj * d + c0 + cx] : 0;
         }
         __syncthreads();
-        for (int c = 0; c < cc; c++) {
-            const long long y = xj[lane][c];
+        for (int cx = 0; cx < cc; cx++) {
+            const long long y = xj[lane][cx];
 #pragma unroll
             for (int m = 0; m < 16; m++) {
-                long long df = (long long)xi[w + 4 * m][c] - y;
+                long long df = (long long)xi[w + 4 * m][cx] - y;
                 if (sizeof(T) == 4) {
                     // |df| >= 2^16 makes df^2 >= 2^32 on its own
                     over |= (df >= 65536 || df <= -65536) ? 1u : 0u;
@@ -77,80 +109,84 @@ __global__ __launch_bounds__(VR_BLOCK) void k_dist(const T *__restrict__ pts, in
 #pragma unroll
     for (int m = 0; m < 16; m++) {
         const int i = bi * DIST_TB + w + 4 * m;
-        const bool ok = i < j && j < n;
-        uint32_t qq = 0;
-        if (ok) {
+        if (i < j && j < n) {
             unsigned long long v = acc[m];
             if (v > 0xFFFFFFFFull) { over = 1u; v = 0xFFFFFFFFull; }
-            qq = (uint32_t)v;
+            const uint32_t qq = (uint32_t)v;
             q[row_start(i, n) + (j - i - 1)] = qq;
+            if (need_hist) atomicAdd(&hist[bucket_of(qq)], 1u);
         }
-        if (need_hist) match_add<11>(hist, bucket_of(qq), ok);
     }
-    if (over) atomicOr(&ctl->flags, 1u);
+    if (over) atomicOr(&D.ctl->flags, 1u);
     if (need_hist) {
         __syncthreads();
+        uint32_t *gh = D.hist + (size_t)c * VR_NBUCKET;
         for (int b = threadIdx.x; b < VR_NBUCKET; b += VR_BLOCK)
-            if (hist[b]) atomicAdd(&ctl->bucket[b], hist[b]);
+            if (hist[b]) atomicAdd(&gh[b], hist[b]);
     }
 }
 
 void launch_dist(const VrDev &D, const void *points, hipStream_t s) {
-    const int nb = (D.n + DIST_TB - 1) / DIST_TB;
-    dim3 grid(nb, nb);
-    if (D.dtype == 1)
-        hipLaunchKernelGGL(k_dist<int8_t>, grid, dim3(VR_BLOCK), 0, s, (const int8_t *)points, D.n, D.d,
-                           D.need_hist, D.q, D.ctl);
-    else if (D.dtype == 2)
-        hipLaunchKernelGGL(k_dist<int16_t>, grid, dim3(VR_BLOCK), 0, s, (const int16_t *)points, D.n, D.d,
-                           D.need_hist, D.q, D.ctl);
-    else
-        hipLaunchKernelGGL(k_dist<int32_t>, grid, dim3(VR_BLOCK), 0, s, (const int32_t *)points, D.n, D.d,
-                           D.need_hist, D.q, D.ctl);
+    (void)points;
+    const dim3 grid((unsigned)D.tiles);
+    if (D.dtype == 1) hipLaunchKernelGGL(k_dist<int8_t>, grid, dim3(VR_BLOCK), 0, s, D);
+    else if (D.dtype == 2) hipLaunchKernelGGL(k_dist<int16_t>, grid, dim3(VR_BLOCK), 0, s, D);
+    else hipLaunchKernelGGL(k_dist<int32_t>, grid, dim3(VR_BLOCK), 0, s, D);
+}
+
+// -------------------------------------------------------------- k_pivot ----
+// Work-group c: the smallest bucket of cloud c whose cumulative count reaches
+// K_c; the candidates are then every pair at or below it (a superset of the
+// K_c smallest, as buckets are monotone in q).
+__global__ __launch_bounds__(VR_BLOCK) void k_pivot(VrDev D) {
+    __shared__ unsigned long long sh_w[VR_WAVES];
+    __shared__ uint32_t sh_pivot;
+    const int c = blockIdx.x, t = threadIdx.x;
+    const uint32_t *h = D.hist + (size_t)c * VR_NBUCKET;
+    const unsigned long long K = (unsigned long long)D.cl[c].K;
+    const int per = (VR_NBUCKET + VR_BLOCK - 1) / VR_BLOCK;  // 7
+    unsigned long long loc = 0;
+    for (int b = t * per; b < min(VR_NBUCKET, (t + 1) * per); b++) loc += h[b];
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
+    if (t == 0) sh_pivot = 0u;
+    __syncthreads();
+    if (K > 0 && ex < K && K <= ex + loc) {
+        unsigned long long cum = ex;
+        for (int b = t * per; b < min(VR_NBUCKET, (t + 1) * per); b++) {
+            cum += h[b];
+            if (cum >= K) { sh_pivot = (uint32_t)b; break; }
+        }
+    }
+    __syncthreads();
+    if (t == 0) D.cs[c].pivot = sh_pivot;
+}
+
+void launch_pivot(const VrDev &D, hipStream_t s) {
+    hipLaunchKernelGGL(k_pivot, dim3((unsigned)D.C), dim3(VR_BLOCK), 0, s, D);
 }
 
 // ------------------------------------------------------------- k_select ----
-// Select modes: which edges become sort candidates.
-#define SEL_ALL 0     // every pair (infinite threshold)
-#define SEL_BUCKET 1  // bucket(q) <= pivot bucket: a superset of the K smallest
-#define SEL_LESS 2    // q < tau (distance threshold)
-#define SEL_NONE 3    // K = 0
+// A pair is a candidate when (full threshold) always, (count / fraction) its
+// bucket is at or below the cloud's pivot and the cloud keeps any edge, or
+// (distance) q < tau.  Candidates keep (cloud, pair) order; the first pair of
+// each cloud records where the cloud's candidates begin.
+__device__ __forceinline__ bool is_candidate(const VrDev &D, int c, uint32_t q) {
+    if (D.thr_kind == 0) return true;
+    if (D.thr_kind == 3) {
+        const long long tau = D.cl[c].thr_num;
+        return tau > 0xFFFFFFFFll || (long long)q < tau;
+    }
+    return D.cl[c].K > 0 && bucket_of(q) <= D.cs[c].pivot;
+}
 
 __global__ __launch_bounds__(VR_BLOCK) void k_select(VrDev D) {
     __shared__ uint32_t sh_w[VR_WAVES];
-    __shared__ unsigned long long sh_w64[VR_WAVES];
     __shared__ int sh_tile;
-    __shared__ uint32_t sh_pivot, sh_prefix;
+    __shared__ uint32_t sh_prefix;
     __shared__ uint32_t h8[VR_MAX_PASSES][VR_RADIX];
     VrCtl *ctl = D.ctl;
     const int t = threadIdx.x;
-
-    int mode;
-    if (D.thr_kind == 0) mode = SEL_ALL;
-    else if (D.thr_kind == 3) mode = SEL_LESS;
-    else mode = (D.K_host == 0) ? SEL_NONE : SEL_BUCKET;
-
-    if (mode == SEL_BUCKET) {
-        // pivot bucket: the smallest b whose cumulative count reaches K
-        const int per = (VR_NBUCKET + VR_BLOCK - 1) / VR_BLOCK;  // 7
-        unsigned long long loc = 0;
-        for (int b = t * per; b < min(VR_NBUCKET, (t + 1) * per); b++) loc += ctl->bucket[b];
-        unsigned long long tot;
-        unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w64, &tot);
-        const unsigned long long K = (unsigned long long)D.K_host;
-        if (ex < K && K <= ex + loc) {
-            unsigned long long c = ex;
-            for (int b = t * per; b < min(VR_NBUCKET, (t + 1) * per); b++) {
-                c += ctl->bucket[b];
-                if (c >= K) { sh_pivot = (uint32_t)b; break; }
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t pivot = (mode == SEL_BUCKET) ? sh_pivot : 0u;
-    const uint32_t tau = (mode == SEL_LESS) ? (uint32_t)min((long long)D.thr_num, 0xFFFFFFFFll) : 0u;
-    const bool tau_all = (mode == SEL_LESS) && D.thr_num > 0xFFFFFFFFll;
-
     for (int x = t; x < VR_MAX_PASSES * VR_RADIX; x += VR_BLOCK) (&h8[0][0])[x] = 0u;
 
     const long long E = D.E;
@@ -159,28 +195,49 @@ __global__ __launch_bounds__(VR_BLOCK) void k_select(VrDev D) {
         const int tile = claim_tile(&ctl->ticket[0], &sh_tile);
         if (tile >= ntiles) break;
         const long long e0 = (long long)tile * VR_TILE + (long long)t * VR_ITEMS;
-        uint32_t qv[VR_ITEMS];
-        bool keep[VR_ITEMS];
-        uint32_t c = 0;
-        int pi = 0, pj = 0;
-        if (e0 < E) pair_of(e0, D.n, &pi, &pj);
+        uint32_t qv[VR_ITEMS], kv[VR_ITEMS], vv[VR_ITEMS];
+        bool keep[VR_ITEMS], first[VR_ITEMS];
+        int cc[VR_ITEMS];
+        uint32_t cnt = 0;
+        int c = 0, pi = 0, pj = 0, n = 0;
+        long long le = 0, Ec = 0;
+        if (e0 < E) {
+            c = cloud_of(e0, D.C, [&](int k) { return D.cl[k].pbase; });
+            n = D.cl[c].n;
+            le = e0 - D.cl[c].pbase;
+            Ec = (long long)n * (n - 1) / 2;
+            pair_of(le, n, &pi, &pj);
+        }
 #pragma unroll
         for (int m = 0; m < VR_ITEMS; m++) {
             const long long e = e0 + m;
-            bool k = false;
-            uint32_t v = 0;
+            bool k = false, f = false;
+            uint32_t q = 0;
             if (e < E) {
-                v = D.q[e];
-                if (mode == SEL_ALL) k = true;
-                else if (mode == SEL_BUCKET) k = bucket_of(v) <= pivot;
-                else if (mode == SEL_LESS) k = tau_all || v < tau;
+                if (le == Ec) {  // next cloud (every cloud of a batch has a pair)
+                    c++;
+                    n = D.cl[c].n;
+                    le = 0;
+                    Ec = (long long)n * (n - 1) / 2;
+                    pi = 0;
+                    pj = 1;
+                }
+                q = D.q[e];
+                k = is_candidate(D, c, q);
+                f = (le == 0);
             }
-            qv[m] = v;
+            qv[m] = q;
+            kv[m] = (D.qbits >= 32) ? q : (((uint32_t)c << D.qbits) | q);  // one cloud when q takes 32 bits
+            vv[m] = ((uint32_t)pi << 16) | (uint32_t)pj;
             keep[m] = k;
-            c += k ? 1u : 0u;
+            first[m] = f;
+            cc[m] = c;
+            cnt += k ? 1u : 0u;
+            le++;
+            if (++pj == n) { pi++; pj = pi + 1; }
         }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan<uint32_t>(c, sh_w, &tot);
+        const uint32_t ex = block_excl_scan<uint32_t>(cnt, sh_w, &tot);
         if (t < VR_WAVE) {
             uint32_t prefix = 0;
             if (tile == 0) {
@@ -201,16 +258,17 @@ __global__ __launch_bounds__(VR_BLOCK) void k_select(VrDev D) {
         uint32_t p = sh_prefix + ex;
 #pragma unroll
         for (int m = 0; m < VR_ITEMS; m++) {
+            if (first[m]) D.cs[cc[m]].cand_base = p;
             if (keep[m]) {
-                D.key[0][p] = qv[m];
-                D.val[0][p] = ((uint32_t)pi << 16) | (uint32_t)pj;
+                D.key[0][p] = kv[m];
+                D.val[0][p] = vv[m];
                 p++;
             }
-            if (++pj == D.n) { pi++; pj = pi + 1; }
         }
         for (int ps = 0; ps < D.passes; ps++)
 #pragma unroll
-            for (int m = 0; m < VR_ITEMS; m++) match_add<8>(h8[ps], (qv[m] >> (8 * ps)) & 255u, keep[m]);
+            for (int m = 0; m < VR_ITEMS; m++) match_add<8>(h8[ps], (kv[m] >> (8 * ps)) & 255u, keep[m]);
+        (void)qv;
     }
     __syncthreads();
     for (int x = t; x < D.passes * VR_RADIX; x += VR_BLOCK) {
@@ -263,7 +321,7 @@ SortJob star_sort_job(const VrDev &D) {
     J.ticket = &D.ctl->ticket[6];
     J.st[0] = D.ist[0]; J.st[1] = D.ist[1];
     J.count = &D.ctl->n_inc;
-    J.passes = 2;
+    J.passes = D.spasses;
     return J;
 }
 
@@ -383,56 +441,64 @@ void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream
 }
 
 // -------------------------------------------------------------- k_edges ----
-// Kept edges in rank order.  With triangles wanted, also the list of vertex
-// incidences (vertex, 2r+s) in rank order plus the digit histograms of the
-// vertices, input of the stable star sort, and clear its first statuses.
+// Kept edge g of cloud c is the (g - kbase_c)-th candidate of the cloud in
+// sorted order.  With triangles wanted, also the vertex incidences
+// (global vertex, 2g+s) in rank order plus their digit histograms, input of
+// the stable star sort, and clear its first statuses.
 __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
-    __shared__ uint32_t h[2][VR_RADIX];
+    __shared__ uint32_t h[3][VR_RADIX];
     VrCtl *ctl = D.ctl;
     const int a = active_before(&ctl->hist8[0][0], D.passes, VR_MAX_PASSES, nullptr);
     const uint32_t *__restrict__ kf = D.key[a & 1];
     const uint32_t *__restrict__ vf = D.val[a & 1];
     const long long K = (D.thr_kind == 3) ? (long long)ctl->n_cand : D.K_host;
+    const uint32_t qmask = (D.qbits >= 32) ? 0xFFFFFFFFu : ((1u << D.qbits) - 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->n_kept = (uint32_t)K;
         ctl->n_inc = (uint32_t)(2 * K);
-        // without triangles this is the last phase-1 kernel: publish now
-        if (!D.tri) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, (uint32_t)K, 0ull);
+        // without triangles this is the last phase-1 kernel of a single build
+        if (!D.tri && D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, (uint32_t)K, 0ull);
     }
     if (D.tri) {
-        for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK) (&h[0][0])[x] = 0u;
+        for (int x = threadIdx.x; x < 3 * VR_RADIX; x += VR_BLOCK) (&h[0][0])[x] = 0u;
         __syncthreads();
         const long long words = (2 * K + VR_TILE - 1) / VR_TILE * VR_RADIX;
         for (long long x = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; x < words; x += (long long)gridDim.x * VR_BLOCK)
             D.ist[0][x] = 0u;
     }
     const long long Kr = (K + VR_BLOCK - 1) / VR_BLOCK * VR_BLOCK;  // whole waves take part in match_add
-    for (long long r = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; r < Kr; r += (long long)gridDim.x * VR_BLOCK) {
-        const bool ok = r < K;
-        uint32_t i = 0, j = 0;
+    for (long long g = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; g < Kr; g += (long long)gridDim.x * VR_BLOCK) {
+        const bool ok = g < K;
+        uint32_t vi = 0, vj = 0;
         if (ok) {
-            const uint32_t k = kf[r], v = vf[r];
-            D.se_q[r] = k;
-            D.se_ij[r] = v;
-            i = v >> 16;
-            j = v & 0xFFFFu;
+            const int c = cloud_of(g, D.C, [&](int k) { return kept_base(D, k); });
+            const long long sp = (long long)D.cs[c].cand_base + (g - kept_base(D, c));
+            const uint32_t k = kf[sp], v = vf[sp];
+            D.se_q[g] = k & qmask;
+            D.se_ij[g] = v;
+            const uint32_t vb = (uint32_t)D.cl[c].vbase;
+            vi = vb + (v >> 16);
+            vj = vb + (v & 0xFFFFu);
             if (D.tri) {
-                D.ikey[0][2 * r] = i;
-                D.ikey[0][2 * r + 1] = j;
-                D.ival[0][2 * r] = (uint32_t)(2 * r);
-                D.ival[0][2 * r + 1] = (uint32_t)(2 * r + 1);
+                D.ikey[0][2 * g] = vi;
+                D.ikey[0][2 * g + 1] = vj;
+                D.ival[0][2 * g] = (uint32_t)(2 * g);
+                D.ival[0][2 * g + 1] = (uint32_t)(2 * g + 1);
             }
         }
         if (D.tri) {
-            match_add<8>(h[0], i & 255u, ok);
-            match_add<5>(h[1], i >> 8, ok);
-            match_add<8>(h[0], j & 255u, ok);
-            match_add<5>(h[1], j >> 8, ok);
+#pragma unroll
+            for (int ps = 0; ps < 3; ps++) {
+                if (ps < D.spasses) {
+                    match_add<8>(h[ps], (vi >> (8 * ps)) & 255u, ok);
+                    match_add<8>(h[ps], (vj >> (8 * ps)) & 255u, ok);
+                }
+            }
         }
     }
     if (D.tri) {
         __syncthreads();
-        for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK) {
+        for (int x = threadIdx.x; x < 3 * VR_RADIX; x += VR_BLOCK) {
             const uint32_t c = (&h[0][0])[x];
             if (c) atomicAdd(&(&ctl->hinc[0][0])[x], c);
         }

@@ -5,7 +5,7 @@
 // q <= 65025 d, both in int32 / uint32 for the dimensions routed here.
 //
 // A work-group owns a 64 x 64 tile of pairs (row block bi <= column block
-// bj).  Both blocks of points are staged in LDS, zero-padded to a multiple
+// bj) of one cloud of the batch.  Both blocks of points are staged in LDS, zero-padded to a multiple
 // of 64 coordinates (zeros change neither norms nor products).  Wave w
 // computes rows 16w..16w+15 against the four 16-column blocks.  Each lane
 // feeds the same 16-byte slice of coordinates to the A and B operands, so
@@ -18,11 +18,27 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 #define GRAM_TB 64
 #define GRAM_KC 64  // coordinates per MFMA step
 
-__global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(const int8_t *__restrict__ pts, int n, int d, int dpad,
-                                                      int need_hist, uint32_t *__restrict__ q,
-                                                      VrCtl *__restrict__ ctl) {
-    const int bi = blockIdx.y, bj = blockIdx.x;
-    if (bi > bj) return;
+__device__ __forceinline__ long long gram_tile_row_start(long long bi, long long nb) {
+    return bi * nb - bi * (bi - 1) / 2;
+}
+
+__global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(VrDev D, int dpad) {
+    const long long tg = blockIdx.x;
+    const int c = cloud_of(tg, D.C, [&](int k) { return D.cl[k].tbase; });
+    const VrCloud cl = D.cl[c];
+    const int n = cl.n, d = D.d, need_hist = D.need_hist;
+    const long long nb = (n + GRAM_TB - 1) / GRAM_TB, tl = tg - cl.tbase;
+    // tile (bi, bj), bi <= bj, in row order
+    long long ib = (long long)(((2.0 * nb + 1.0) - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * (double)tl)) * 0.5);
+    if (ib < 0) ib = 0;
+    if (ib > nb - 1) ib = nb - 1;
+    while (ib > 0 && gram_tile_row_start(ib, nb) > tl) ib--;
+    while (ib < nb - 1 && gram_tile_row_start(ib + 1, nb) <= tl) ib++;
+    const int bi = (int)ib, bj = (int)(tl - gram_tile_row_start(ib, nb) + ib);
+    const int8_t *__restrict__ pts = (const int8_t *)cl.points;
+    uint32_t *__restrict__ q = D.q + cl.pbase;
+    VrCtl *__restrict__ ctl = D.ctl;
+    (void)ctl;
     extern __shared__ int4 lds4[];
     int8_t *xi = (int8_t *)lds4;                  // GRAM_TB * dpad
     int8_t *xj = xi + GRAM_TB * dpad;             // GRAM_TB * dpad
@@ -82,8 +98,9 @@ __global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(const int8_t *__restrict__
     }
     if (need_hist) {
         __syncthreads();
+        uint32_t *gh = D.hist + (size_t)c * VR_NBUCKET;
         for (int b = t; b < VR_NBUCKET; b += VR_BLOCK)
-            if (hist[b]) atomicAdd(&ctl->bucket[b], hist[b]);
+            if (hist[b]) atomicAdd(&gh[b], hist[b]);
     }
 }
 
@@ -93,8 +110,7 @@ size_t gram_lds(int dpad) { return 2 * (size_t)GRAM_TB * dpad + 2 * GRAM_TB * 4 
 bool gram_applies(const VrDev &D) { return D.dtype == 1 && D.d >= 16 && D.d <= 256; }
 
 void launch_gram(const VrDev &D, const void *points, hipStream_t s) {
-    const int nb = (D.n + GRAM_TB - 1) / GRAM_TB;
+    (void)points;
     const int dpad = (D.d + GRAM_KC - 1) / GRAM_KC * GRAM_KC;
-    hipLaunchKernelGGL(k_gram_i8, dim3(nb, nb), dim3(VR_BLOCK), gram_lds(dpad), s, (const int8_t *)points, D.n,
-                       D.d, dpad, D.need_hist, D.q, D.ctl);
+    hipLaunchKernelGGL(k_gram_i8, dim3((unsigned)D.tiles), dim3(VR_BLOCK), gram_lds(dpad), s, D, dpad);
 }

@@ -29,30 +29,35 @@
 
 #define VR_MAXN 8192
 
-__device__ __forceinline__ int star_parity(const VrCtl *ctl) {
-    // number of active passes of the two-pass star sort, from its histograms
-    __shared__ int sh_nz[2];
-    if (threadIdx.x < 2) sh_nz[threadIdx.x] = 0;
+__device__ __forceinline__ int star_parity(const VrDev &D) {
+    // parity of the active passes of the star sort, from its histograms
+    __shared__ int sh_nz[3];
+    if (threadIdx.x < 3) sh_nz[threadIdx.x] = 0;
     __syncthreads();
-    for (int x = threadIdx.x; x < 2 * VR_RADIX; x += VR_BLOCK)
-        if ((&ctl->hinc[0][0])[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+    for (int x = threadIdx.x; x < D.spasses * VR_RADIX; x += VR_BLOCK)
+        if ((&D.ctl->hinc[0][0])[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
     __syncthreads();
-    const int a = (sh_nz[0] > 1 ? 1 : 0) + (sh_nz[1] > 1 ? 1 : 0);
+    const int a = (sh_nz[0] > 1 ? 1 : 0) + (sh_nz[1] > 1 ? 1 : 0) + (sh_nz[2] > 1 ? 1 : 0);
     __syncthreads();
     return a & 1;
+}
+
+// Cloud of global vertex v, and v's local index.
+__device__ __forceinline__ int vertex_cloud(const VrDev &D, long long v) {
+    return cloud_of(v, D.C, [&](int k) { return D.cl[k].vbase; });
 }
 
 // --------------------------------------------------------------- k_star ----
 __global__ __launch_bounds__(VR_BLOCK) void k_star(VrDev D) {
     const VrCtl *ctl = D.ctl;
-    const int par = star_parity(ctl);
+    const int par = star_parity(D);
     const uint32_t *__restrict__ kf = D.ikey[par];
     const uint32_t *__restrict__ vf = D.ival[par];
     const long long m = (long long)ctl->n_inc;
-    const int n = D.n;
+    const long long n = D.V;  // row starts over all vertices of the batch
     if (m == 0) {
         if (blockIdx.x == 0)
-            for (int u = threadIdx.x; u <= n; u += VR_BLOCK) D.start[u] = 0u;
+            for (long long u = threadIdx.x; u <= n; u += VR_BLOCK) D.start[u] = 0u;
         return;
     }
     for (long long p = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; p < m; p += (long long)gridDim.x * VR_BLOCK) {
@@ -61,10 +66,10 @@ __global__ __launch_bounds__(VR_BLOCK) void k_star(VrDev D) {
         const uint32_t ij = D.se_ij[r];
         D.star_r[p] = r;
         D.star_nbr[p] = (uint16_t)((x & 1u) ? (ij >> 16) : (ij & 0xFFFFu));
-        const int prev = (p == 0) ? -1 : (int)kf[p - 1];
-        for (int u = prev + 1; u <= (int)v; u++) D.start[u] = (uint32_t)p;
+        const long long prev = (p == 0) ? -1 : (long long)kf[p - 1];
+        for (long long u = prev + 1; u <= (long long)v; u++) D.start[u] = (uint32_t)p;
         if (p == m - 1)
-            for (int u = (int)v + 1; u <= n; u++) D.start[u] = (uint32_t)m;
+            for (long long u = (long long)v + 1; u <= n; u++) D.start[u] = (uint32_t)m;
     }
 }
 
@@ -75,9 +80,11 @@ __global__ __launch_bounds__(VR_BLOCK) void k_kstar(VrDev D) {
     __shared__ uint16_t P[VR_MAXN];
     __shared__ unsigned long long bits[VR_MAXN / 64];
     __shared__ uint32_t sh_w[VR_WAVES];
-    const int v = blockIdx.x, n = D.n, t = threadIdx.x;
+    const long long vg = blockIdx.x;
+    const int c = vertex_cloud(D, vg);
+    const int v = (int)(vg - D.cl[c].vbase), n = D.cl[c].n, t = threadIdx.x;
     const int W = (n + 63) >> 6;
-    const uint32_t s0 = D.start[v], s1 = D.start[v + 1];
+    const uint32_t s0 = D.start[vg], s1 = D.start[vg + 1];
     if (t < W) bits[t] = 0ull;
     __syncthreads();
     for (uint32_t p = s0 + t; p < s1; p += VR_BLOCK) {
@@ -102,7 +109,7 @@ void launch_star(const VrDev &D, hipStream_t s) {
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_star, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
-    hipLaunchKernelGGL(k_kstar, dim3(D.n), dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_kstar, dim3((unsigned)D.V), dim3(VR_BLOCK), 0, s, D);
 }
 
 // ------------------------------------------------- shared enumeration core ----
@@ -154,8 +161,8 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 // whole neighbour-ordered star).  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
 template <bool WRITE>
-__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, uint32_t s1, uint32_t p0, EnumLds &L,
-                                          int part, int parts) {
+__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, uint32_t s0, uint32_t s1, uint32_t p0,
+                                          EnumLds &L, int part, int parts) {
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
@@ -164,9 +171,9 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t s0, ui
         r = D.star_r[p];
         b = D.star_nbr[p];
         pb = D.pos[2 * (size_t)r + (b > (uint32_t)a ? 1 : 0)];
-        sb = D.start[b];
+        sb = D.start[vb + b];
         if (WRITE) {
-            const uint32_t db = D.start[b + 1] - sb, da = s1 - s0;
+            const uint32_t db = D.start[vb + b + 1] - sb, da = s1 - s0;
             owned = db < da || (db == da && (uint32_t)a < b);
             len = db;
         } else {
@@ -209,14 +216,14 @@ __device__ __forceinline__ uint32_t rl(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-__device__ __forceinline__ void stage_pos(const VrDev &D, uint16_t *Pa, uint32_t s0, uint32_t s1) {
-    for (int k = threadIdx.x; k < D.n; k += ENUM_BLOCK) Pa[k] = 0xFFFF;
+__device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, uint32_t s0, uint32_t s1) {
+    for (int k = threadIdx.x; k < n; k += ENUM_BLOCK) Pa[k] = 0xFFFF;
     __syncthreads();
     for (uint32_t p = s0 + threadIdx.x; p < s1; p += ENUM_BLOCK) Pa[D.star_nbr[p]] = (uint16_t)(p - s0);
     __syncthreads();
 }
 
-size_t enum_lds(int n) { return 2 * (size_t)((n + 7) & ~7) + sizeof(EnumLds); }
+size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLds); }
 
 // Load up to VR_PIECES pieces of `len` (>= 1) candidates starting at src.
 // Indices are clamped, so every lane loads (no predication); the consumer
@@ -235,14 +242,18 @@ __device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T
 // ----------------------------------------------------------- k_tri_count ----
 __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
     extern __shared__ uint32_t lds[];
-    const int a = blockIdx.x / parts, part = blockIdx.x % parts, n = D.n;
+    const long long ag = blockIdx.x / parts;
+    const int part = blockIdx.x % parts;
+    const int c = vertex_cloud(D, ag);
+    const uint32_t vb = (uint32_t)D.cl[c].vbase;
+    const int a = (int)(ag - vb), n = D.cl[c].n;
     uint16_t *Pa = (uint16_t *)lds;
-    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
+    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
-    stage_pos(D, Pa, s0, s1);
+    const uint32_t s0 = D.start[ag], s1 = D.start[ag + 1];
+    stage_pos(D, n, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk<false>(D, a, s0, s1, p0, L, part, parts);
+        load_chunk<false>(D, a, vb, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -287,14 +298,14 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
 
 // Work-groups per vertex: enough groups to spread heavy vertices over many
 // compute units when the cloud is small.
-int enum_parts(int n) {
-    int p = 4096 / (n > 0 ? n : 1);
-    return p < 1 ? 1 : (p > 8 ? 8 : p);
+int enum_parts(long long V) {
+    long long p = 4096 / (V > 0 ? V : 1);
+    return p < 1 ? 1 : (p > 8 ? 8 : (int)p);
 }
 
 void launch_tri_count(const VrDev &D, hipStream_t s) {
-    const int parts = enum_parts(D.n);
-    hipLaunchKernelGGL(k_tri_count, dim3(D.n * parts), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, parts);
+    const int parts = enum_parts(D.V);
+    hipLaunchKernelGGL(k_tri_count, dim3((unsigned)(D.V * parts)), dim3(ENUM_BLOCK), enum_lds(D.maxn), s, D, parts);
 }
 
 // ---------------------------------------------------------------- k_scan ----
@@ -306,7 +317,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
     const int t = threadIdx.x;
     const long long K = (long long)ctl->n_kept;
     const int ntiles = (int)((K + VR_TILE - 1) / VR_TILE);
-    if (ntiles == 0 && blockIdx.x == 0 && t == 0)
+    if (D.C == 1 && ntiles == 0 && blockIdx.x == 0 && t == 0)
         publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, 0ull);
     for (;;) {
         const int tile = claim_tile(&ctl->ticket[5], &sh_tile);
@@ -334,7 +345,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
                 sh_prefix = prefix;
                 if (tile == ntiles - 1) {
                     ctl->n_tri = prefix + tot;
-                    publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
+                    if (D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
                 }
             }
         }
@@ -353,6 +364,43 @@ void launch_scan(const VrDev &D, long long Kmax, hipStream_t s) {
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
+}
+
+// ------------------------------------------------------ k_cloud_publish ----
+// Batches: per cloud (kbase, K, first triangle, T) into host-pinned memory,
+// then the counts into the mailbox from the last work-group to finish.
+__global__ __launch_bounds__(VR_BLOCK) void k_cloud_publish(VrDev D) {
+    __shared__ bool sh_last;
+    const VrCtl *ctl = D.ctl;
+    const int c = blockIdx.x * VR_BLOCK + threadIdx.x;
+    if (c < D.C) {
+        const long long kb = kept_base(D, c), K = kept_count(D, c);
+        unsigned long long tb = 0, T = 0;
+        if (D.tri && K > 0) {
+            tb = D.off[kb];
+            T = D.off[kb + K - 1] + D.cnt[kb + K - 1] - tb;
+        } else if (D.tri) {
+            tb = (kb < (long long)ctl->n_kept) ? D.off[kb] : ctl->n_tri;
+        }
+        unsigned long long *h = D.host_cloud + 4 * (size_t)c;
+        __hip_atomic_store(&h[0], (unsigned long long)kb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&h[1], (unsigned long long)K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&h[2], tb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&h[3], T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        sh_last = atomicAdd(&((VrCtl *)ctl)->done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (sh_last && threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, D.tri ? ctl->n_tri : 0ull);
+    }
+}
+
+void launch_cloud_publish(const VrDev &D, hipStream_t s) {
+    hipLaunchKernelGGL(k_cloud_publish, dim3((unsigned)((D.C + VR_BLOCK - 1) / VR_BLOCK)), dim3(VR_BLOCK), 0, s, D);
 }
 
 // ----------------------------------------------------------- k_tri_write ----
@@ -378,20 +426,25 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                                                           long long K, uint32_t *__restrict__ edge_ij,
                                                           long long *__restrict__ edge_q) {
     extern __shared__ uint32_t lds[];
-    const int nb = D.n * parts;
-    if ((int)blockIdx.x >= nb) {
+    const long long nb = D.V * parts;
+    if ((long long)blockIdx.x >= nb) {
         emit_edges_range(D, K, edge_ij, edge_q, (long long)(blockIdx.x - nb) * ENUM_BLOCK + threadIdx.x,
                          (long long)(gridDim.x - nb) * ENUM_BLOCK);
         return;
     }
-    const int a = blockIdx.x / parts, part = blockIdx.x % parts, n = D.n;
+    const long long ag = blockIdx.x / parts;
+    const int part = blockIdx.x % parts;
+    const int c = vertex_cloud(D, ag);
+    const uint32_t vb = (uint32_t)D.cl[c].vbase;
+    const uint32_t kb = (uint32_t)kept_base(D, c);  // the cloud's ranks start here
+    const int a = (int)(ag - vb), n = D.cl[c].n;
     uint16_t *Pa = (uint16_t *)lds;
-    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((n + 7) & ~7));
+    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t s0 = D.start[a], s1 = D.start[a + 1];
-    stage_pos(D, Pa, s0, s1);
+    const uint32_t s0 = D.start[ag], s1 = D.start[ag + 1];
+    stage_pos(D, n, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk<true>(D, a, s0, s1, p0, L, part, parts);
+        load_chunk<true>(D, a, vb, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -412,7 +465,7 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
             for (int el = 0; el < ne; el++) {
                 if (el + 1 < ne) issue<uint32_t>(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), kB);
                 const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
-                const uint32_t r = rl(vr, el);
+                const uint32_t r = rl(vr, el) - kb;  // local rank within the cloud
                 unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
                                                  rl((uint32_t)voff, el));
                 // key = (r << 39) | (sorted triple), split into 32-bit halves
@@ -454,12 +507,12 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
                       hipStream_t s) {
-    const int parts = enum_parts(D.n);
+    const int parts = enum_parts(D.V);
     long long eb = (K + ENUM_BLOCK - 1) / ENUM_BLOCK;
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;
-    hipLaunchKernelGGL(k_tri_write, dim3((unsigned)(D.n * parts + eb)), dim3(ENUM_BLOCK), enum_lds(D.n), s, D, tri_out,
-                       parts, K, edge_ij, edge_q);
+    hipLaunchKernelGGL(k_tri_write, dim3((unsigned)(D.V * parts + eb)), dim3(ENUM_BLOCK), enum_lds(D.maxn), s, D,
+                       tri_out, parts, K, edge_ij, edge_q);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

@@ -1,18 +1,21 @@
 // vr_api.hip -- the C ABI (include/vr.h): request validation, workspace
-// planning, the two-phase launch sequence and result ownership.
+// planning, the two-phase launch sequence and result ownership, for one
+// cloud (vr_build) or a batch of clouds (vr_build_batch).  A single build is
+// a batch of one: every kernel takes the cloud table.
 //
 // Phase 1 (one stream, no host round trip): distances -> threshold select ->
 // edge radix passes -> kept edges -> star radix passes -> stars -> triangle
 // counts -> offsets -> publish.  The last kernel stores (flags, K, T) into a
-// host-pinned mailbox; the host polls it (no stream synchronisation), sizes
-// the outputs, and enqueues phase 2: the ordered triangle write and the
-// public edge arrays.  The workspace is released in stream order.
+// host-pinned mailbox (and, for batches, per-cloud counts into host-pinned
+// memory); the host polls it (no stream synchronisation), sizes the
+// outputs, and enqueues phase 2: the ordered triangle write and the public
+// edge arrays.  The workspace is released in stream order.
 #include <hip/hip_runtime.h>
 
-#include <chrono>
 #include <mutex>
 #include <new>
 #include <string.h>
+#include <vector>
 #include <immintrin.h>
 
 #include "vr.h"
@@ -44,15 +47,57 @@ struct Alloc {
     }
 };
 
-struct Result : vr_result {
-    void *block;
-    size_t block_bytes;
-    vr_allocator alloc;
-    bool has_alloc;
-    bool timing;
-    hipEvent_t ev[ST_N + 1];
-    bool ev_used[ST_N + 1];
+// The output block and stage events of one build, shared by its views.
+struct Owner {
+    void *block = nullptr;
+    size_t block_bytes = 0;
+    vr_allocator alloc{};
+    bool has_alloc = false;
+    bool timing = false;
+    hipEvent_t ev[ST_N + 1] = {};
+    bool ev_used[ST_N + 1] = {};
+
+    void release(hipStream_t s) {
+        Alloc A{has_alloc ? &alloc : nullptr, s};
+        A.put(block, block_bytes);
+        block = nullptr;
+        for (int i = 0; i <= ST_N; i++) {
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+            ev[i] = nullptr;
+        }
+        timing = false;
+    }
+    int stage_ms(float *ms, int cap) const {
+        if (!timing) return 0;
+        int last = -1;
+        for (int i = ST_N; i >= 0; i--)
+            if (ev_used[i]) { last = i; break; }
+        if (last < 0) return 0;
+        if (hipEventSynchronize(ev[last]) != hipSuccess) return VR_EHIP;
+        int w = 0;
+        for (int s = 0; s < ST_N && w < cap; s++, w++) {
+            ms[w] = 0.f;
+            if (ev_used[s] && ev_used[s + 1]) {
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, ev[s], ev[s + 1]) == hipSuccess) ms[w] = t;
+            }
+        }
+        return w;
+    }
 };
+
+struct Result : vr_result {
+    Owner own;
+};
+
+}  // namespace
+
+struct vr_batch {
+    Owner own;
+    std::vector<vr_result> views;
+};
+
+namespace {
 
 // Keep freed pool memory cached in the device's default pool, so repeated
 // builds do not return to the driver for every allocation.
@@ -69,21 +114,71 @@ void tune_pool(int dev) {
     });
 }
 
-// Host-pinned, device-visible mailbox per host thread for the count read-back.
-struct Mailbox {
-    VrMailbox *h = nullptr;
-    VrMailbox *d = nullptr;
+// Host-pinned memory per host thread: the count mailbox and the per-cloud
+// counts of a batch (device-visible, coherent), and the staging copy of a
+// batch's cloud table.  A build waits for its phase 1 before returning, so
+// the next build of the thread may reuse all three.
+struct HostMem {
+    VrMailbox *mb_h = nullptr, *mb_d = nullptr;
     uint32_t seq = 0;
-    ~Mailbox() {
-        if (h) (void)hipHostFree(h);
+    unsigned long long *pc_h = nullptr, *pc_d = nullptr;
+    size_t pc_cap = 0;
+    VrCloud *tab = nullptr;
+    size_t tab_cap = 0;
+
+    ~HostMem() {
+        if (mb_h) (void)hipHostFree(mb_h);
+        if (pc_h) (void)hipHostFree(pc_h);
+        if (tab) (void)hipHostFree(tab);
+    }
+    static bool mapped(size_t bytes, void **h, void **d) {
+        if (hipHostMalloc(h, bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return false;
+        if (hipHostGetDevicePointer(d, *h, 0) != hipSuccess) {
+            (void)hipHostFree(*h);
+            *h = nullptr;
+            return false;
+        }
+        memset(*h, 0, bytes);
+        return true;
+    }
+    bool mailbox() {
+        if (mb_h) return true;
+        void *h = nullptr, *d = nullptr;
+        if (!mapped(sizeof(VrMailbox), &h, &d)) return false;
+        mb_h = (VrMailbox *)h;
+        mb_d = (VrMailbox *)d;
+        return true;
+    }
+    bool clouds(size_t C) {
+        if (pc_cap < C) {
+            if (pc_h) (void)hipHostFree(pc_h);
+            pc_h = pc_d = nullptr;
+            pc_cap = 0;
+            void *h = nullptr, *d = nullptr;
+            if (!mapped(4 * sizeof(unsigned long long) * C, &h, &d)) return false;
+            pc_h = (unsigned long long *)h;
+            pc_d = (unsigned long long *)d;
+            pc_cap = C;
+        }
+        if (tab_cap < C) {
+            if (tab) (void)hipHostFree(tab);
+            tab = nullptr;
+            tab_cap = 0;
+            void *h = nullptr;
+            if (hipHostMalloc(&h, sizeof(VrCloud) * C, hipHostMallocDefault) != hipSuccess) return false;
+            tab = (VrCloud *)h;
+            tab_cap = C;
+        }
+        return true;
     }
 };
-thread_local Mailbox g_mb;
+thread_local HostMem g_host;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
-    size_t off_ctl, off_stscan, off_stsel, zero_bytes;
+    size_t off_ctl, off_stscan, off_stsel, off_hist, zero_bytes;
+    size_t off_cl, off_cs;
     size_t off_q, off_key0, off_key1, off_val0, off_val1, off_st0, off_st1;
     size_t off_seij, off_seq;
     size_t off_ikey0, off_ikey1, off_ival0, off_ival1, off_ist0, off_ist1;
@@ -91,19 +186,23 @@ struct Plan {
     size_t total;
 };
 
-Plan plan(long long n, long long E, long long Kmax, bool tri) {
+// C clouds with V vertices and E pairs in all; Kmax bounds the kept edges.
+Plan plan(long long C, long long V, long long E, long long Kmax, bool hist, bool tri) {
     Plan P{};
     const long long ntE = (E + VR_TILE - 1) / VR_TILE;
     const long long ntK = (Kmax + VR_TILE - 1) / VR_TILE;
     const long long ntI = (2 * Kmax + VR_TILE - 1) / VR_TILE;
     size_t o = 0;
-    // zeroed region: control block, select and scan statuses
+    // zeroed region: control block, scan and select statuses, histograms
     P.off_ctl = o; o += sizeof(VrCtl);
     o = (o + 15) & ~(size_t)15;
     P.off_stscan = o; o += 8 * (size_t)(ntK > 0 ? ntK : 1);
     P.off_stsel = o; o += sizeof(uint32_t) * (size_t)(ntE > 0 ? ntE : 1);
+    P.off_hist = o; if (hist) o += 4 * (size_t)VR_NBUCKET * (size_t)C;
     P.zero_bytes = (o + 3) & ~(size_t)3;
     o = align_up(o);
+    P.off_cl = o; o = align_up(o + sizeof(VrCloud) * (size_t)C);
+    P.off_cs = o; o = align_up(o + sizeof(VrCloudState) * (size_t)C);
     P.off_q = o; o = align_up(o + 4 * (size_t)E);
     P.off_key0 = o; o = align_up(o + 4 * (size_t)E);
     P.off_key1 = o; o = align_up(o + 4 * (size_t)E);
@@ -123,7 +222,7 @@ Plan plan(long long n, long long E, long long Kmax, bool tri) {
         P.off_star_r = o; o = align_up(o + 8 * (size_t)Kmax);
         P.off_star_nbr = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_star_k = o; o = align_up(o + 8 * (size_t)Kmax);
-        P.off_start = o; o = align_up(o + 4 * (size_t)(n + 1));
+        P.off_start = o; o = align_up(o + 4 * (size_t)(V + 1));
         P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
@@ -132,12 +231,18 @@ Plan plan(long long n, long long E, long long Kmax, bool tri) {
     return P;
 }
 
+int bits_of(unsigned long long m) {
+    int b = 0;
+    while (b < 64 && (m >> b)) b++;
+    return b;
+}
+
+// Bits of the largest squared distance the coordinate type allows (int8:
+// 255^2 per coordinate; wider types use the whole 32-bit key).
 int key_bits(int dtype, long long d) {
     if (dtype == VR_I8) {
-        unsigned long long m = 65025ull * (unsigned long long)d;  // 255^2 per coordinate
-        int b = 0;
-        while (b < 32 && (m >> b)) b++;
-        return b;
+        const int b = bits_of(65025ull * (unsigned long long)d);
+        return b > 32 ? 32 : b;
     }
     return 32;
 }
@@ -174,161 +279,138 @@ int check_request(const vr_request *req, long long *E_out, long long *K_out) {
     return VR_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int vr_version(void) { return 100; }
-
-const char *vr_status_string(int status) {
-    switch (status) {
-    case VR_OK: return "ok";
-    case VR_EINVAL: return "invalid argument";
-    case VR_ENOMEM: return "device allocation failed";
-    case VR_E2BIG: return "too many points or edges for the packed keys";
-    case VR_EHIP: return "HIP runtime error";
-    case VR_ERANGE: return "a squared distance exceeds 32 bits";
-    default: return "unknown status";
+// Build `count` clouds on stream s.  On VR_OK `own` holds the output block
+// and views[i] describes request i (device pointers into the block).  On an
+// error `own` holds nothing.
+int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &own, std::vector<vr_result> &views) {
+    const vr_request &r0 = reqs[0];
+    std::vector<long long> Es((size_t)count), Ks((size_t)count);
+    for (long long i = 0; i < count; i++) {
+        const int st = check_request(&reqs[i], &Es[i], &Ks[i]);
+        if (st != VR_OK) return st;
+        const vr_request &r = reqs[i];
+        // a batch shares coordinate type, dimension, threshold kind, maxdim and flags
+        if (r.dtype != r0.dtype || r.d != r0.d || r.maxdim != r0.maxdim || r.flags != r0.flags ||
+            r.thr_kind != r0.thr_kind)
+            return VR_EINVAL;
     }
-}
+    const bool count_only = (r0.flags & VR_COUNT_ONLY) != 0;
+    const bool timing_all = (r0.flags & VR_TIMING) != 0;
+    const bool timing = timing_all || (r0.flags & VR_TIMING_WRITE) != 0;
+    const bool sq = r0.thr_kind == VR_THR_SQDIST;
 
-const char *vr_stage_name(int s) { return (s >= 0 && s < ST_N) ? kStageNames[s] : nullptr; }
+    views.assign((size_t)count, vr_result{});
+    for (long long i = 0; i < count; i++) views[i].n_vertices = reqs[i].n;
 
-int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind) {
-    vr_request r{};
-    r.n = n; r.d = d; r.dtype = dtype; r.thr_kind = thr_kind; r.thr_num = 0; r.thr_den = 1; r.maxdim = 2;
-    r.points = (const void *)16;
-    long long E, K;
-    if (check_request(&r, &E, &K) != VR_OK) return -1;
-    return (int64_t)plan(n, E, E, true).total;
-}
-
-int vr_query_counts(const vr_result *res, int64_t counts[3]) {
-    if (!res || !counts) return VR_EINVAL;
-    counts[0] = res->n_vertices;
-    counts[1] = res->n_edges;
-    counts[2] = res->n_triangles;
-    return VR_OK;
-}
-
-int vr_query_stage_ms(const vr_result *res_, float *ms, int cap) {
-    if (!res_ || (!ms && cap > 0)) return VR_EINVAL;
-    const Result *res = static_cast<const Result *>(res_);
-    if (!res->timing) return 0;
-    int last = -1;
-    for (int i = ST_N; i >= 0; i--)
-        if (res->ev_used[i]) { last = i; break; }
-    if (last < 0) return 0;
-    if (hipEventSynchronize(res->ev[last]) != hipSuccess) return VR_EHIP;
-    int w = 0;
-    for (int s = 0; s < ST_N && w < cap; s++, w++) {
-        ms[w] = 0.f;
-        if (res->ev_used[s] && res->ev_used[s + 1]) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, res->ev[s], res->ev[s + 1]) == hipSuccess) ms[w] = t;
-        }
+    // Device clouds: the requests with a pair and a possibly kept edge.  The
+    // others have no edges and are answered on the host.
+    std::vector<long long> which;
+    if (r0.maxdim >= 1)
+        for (long long i = 0; i < count; i++)
+            if (Es[i] > 0 && Ks[i] != 0) which.push_back(i);
+    const long long C = (long long)which.size();
+    if (C == 0) return VR_OK;
+    const int d = (int)r0.d;
+    long long V = 0, E = 0, tiles = 0, Ksum = 0;
+    int maxn = 0;
+    for (long long c = 0; c < C; c++) {
+        const long long n = reqs[which[c]].n, nb = (n + 63) / 64;
+        V += n;
+        E += Es[which[c]];
+        tiles += nb * (nb + 1) / 2;
+        Ksum += sq ? 0 : Ks[which[c]];
+        if (n > maxn) maxn = (int)n;
     }
-    return w;
-}
+    const bool want_tri = r0.maxdim >= 2 && maxn >= 3;
+    const int qbits = key_bits(r0.dtype, d);
+    const int cbits = bits_of((unsigned long long)(C - 1));
+    // sort keys (cloud, q) in 32 bits; vertices in 24 bits (three star
+    // passes); incidence ids 2g+s in 32 bits
+    const long long Khost = sq ? -1 : Ksum;
+    const long long Kmax = (Khost >= 0) ? Khost : E;
+    if (qbits + cbits > 32 || E > 0xFFFFFFFFll || V >= (1ll << 24) || Kmax > 0x7FFFFFFFll) return VR_E2BIG;
 
-void vr_free(vr_result *res_, void *stream) {
-    if (!res_) return;
-    Result *res = static_cast<Result *>(res_);
-    Alloc A{res->has_alloc ? &res->alloc : nullptr, (hipStream_t)stream};
-    A.put(res->block, res->block_bytes);
-    if (res->timing)
-        for (int i = 0; i <= ST_N; i++) (void)hipEventDestroy(res->ev[i]);
-    delete res;
-}
-
-int vr_build(const vr_request *req, void *stream_, vr_result **out) {
-    if (!out) return VR_EINVAL;
-    long long E = 0, Khost = -1;
-    int st = check_request(req, &E, &Khost);
-    if (st != VR_OK) return st;
-    hipStream_t s = (hipStream_t)stream_;
-    const long long n = req->n;
-    const bool want_edges = req->maxdim >= 1;
-    const bool want_tri = req->maxdim >= 2 && n >= 3;
-    const bool count_only = (req->flags & VR_COUNT_ONLY) != 0;
-    const bool timing_all = (req->flags & VR_TIMING) != 0;
-    const bool timing = timing_all || (req->flags & VR_TIMING_WRITE) != 0;
-
-    Result *res = new (std::nothrow) Result();
-    if (!res) return VR_ENOMEM;
-    res->n_vertices = n;
-    res->has_alloc = req->alloc != nullptr;
-    if (res->has_alloc) res->alloc = *req->alloc;
-    res->timing = timing;
-    Alloc A{req->alloc, s};
+    own.has_alloc = r0.alloc != nullptr;
+    if (own.has_alloc) own.alloc = *r0.alloc;
+    Alloc A{r0.alloc, s};
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) { delete res; return VR_EHIP; }
+    if (hipGetDevice(&dev) != hipSuccess) return VR_EHIP;
     tune_pool(dev);
-
     auto fail = [&](int code, void *ws, size_t wsb) {
         if (ws) A.put(ws, wsb);
-        if (res->timing)
-            for (int i = 0; i <= ST_N; i++)
-                if (res->ev[i]) (void)hipEventDestroy(res->ev[i]);
-        delete res;
+        own.release(s);
         (void)hipGetLastError();
         return code;
     };
     if (timing) {
+        own.timing = true;
         for (int i = 0; i <= ST_N; i++)
-            if (hipEventCreate(&res->ev[i]) != hipSuccess) return fail(VR_EHIP, nullptr, 0);
+            if (hipEventCreate(&own.ev[i]) != hipSuccess) return fail(VR_EHIP, nullptr, 0);
     }
     auto mark = [&](int i) {
         if (timing_all || (timing && (i == ST_WRITE || i == ST_EMIT))) {
-            (void)hipEventRecord(res->ev[i], s);
-            res->ev_used[i] = true;
+            (void)hipEventRecord(own.ev[i], s);
+            own.ev_used[i] = true;
         }
     };
-
-    // Nothing to compute on the device: no pairs, or no edges requested/kept.
-    if (!want_edges || E == 0 || Khost == 0) {
-        res->n_edges = 0;
-        res->n_triangles = 0;
-        *out = res;
-        return VR_OK;
-    }
-
-    const long long Kmax = (Khost >= 0) ? Khost : E;
-    const Plan P = plan(n, E, Kmax, want_tri);
-    if (!g_mb.h) {
-        void *h = nullptr;
-        if (hipHostMalloc(&h, sizeof(VrMailbox), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
-            return fail(VR_ENOMEM, nullptr, 0);
-        void *d = nullptr;
-        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
-            (void)hipHostFree(h);
-            return fail(VR_EHIP, nullptr, 0);
+    if (!g_host.mailbox()) return fail(VR_ENOMEM, nullptr, 0);
+    if (C > 1 && !g_host.clouds((size_t)C)) return fail(VR_ENOMEM, nullptr, 0);
+    VrCloud one{};
+    {
+        long long vb = 0, pb = 0, tb = 0, kb = 0;
+        for (long long c = 0; c < C; c++) {
+            const vr_request &r = reqs[which[c]];
+            VrCloud cl{};
+            cl.points = r.points;
+            cl.n = (int)r.n;
+            cl.d = d;
+            cl.vbase = vb;
+            cl.pbase = pb;
+            cl.tbase = tb;
+            cl.kbase = kb;
+            cl.K = sq ? 0 : Ks[which[c]];
+            cl.thr_num = r.thr_num;
+            const long long nb = (r.n + 63) / 64;
+            vb += r.n;
+            pb += Es[which[c]];
+            tb += nb * (nb + 1) / 2;
+            kb += cl.K;
+            if (C == 1) one = cl;
+            else g_host.tab[c] = cl;
         }
-        memset(h, 0, sizeof(VrMailbox));
-        g_mb.h = (VrMailbox *)h;
-        g_mb.d = (VrMailbox *)d;
     }
+    const bool need_hist = r0.thr_kind == VR_THR_COUNT || r0.thr_kind == VR_THR_FRACTION;
+    const Plan P = plan(C, V, E, Kmax, need_hist, want_tri);
     char *ws = (char *)A.get(P.total);
     if (!ws) return fail(VR_ENOMEM, nullptr, 0);
 
     VrDev D{};
-    D.n = (int)n;
-    D.d = (int)req->d;
-    D.dtype = req->dtype;
+    D.C = (int)C;
+    D.dtype = r0.dtype;
+    D.d = d;
+    D.maxn = maxn;
+    D.V = V;
     D.E = E;
-    D.thr_kind = req->thr_kind;
-    D.thr_num = req->thr_num;
+    D.tiles = tiles;
+    D.thr_kind = r0.thr_kind;
     D.K_host = Khost;
-    D.passes = (key_bits(req->dtype, req->d) + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
+    D.qbits = qbits;
+    D.passes = (qbits + cbits + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
     if (D.passes < 1) D.passes = 1;
-    D.need_hist = (req->thr_kind == VR_THR_COUNT || req->thr_kind == VR_THR_FRACTION) ? 1 : 0;
+    D.spasses = (bits_of((unsigned long long)(V - 1)) + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
+    if (D.spasses < 1) D.spasses = 1;
+    D.need_hist = need_hist ? 1 : 0;
     D.tri = want_tri ? 1 : 0;
-    D.mailbox = g_mb.d;
-    D.seq = ++g_mb.seq;
-    if (D.seq == 0) D.seq = ++g_mb.seq;
+    D.mailbox = g_host.mb_d;
+    D.seq = ++g_host.seq;
+    if (D.seq == 0) D.seq = ++g_host.seq;
+    D.host_cloud = (C > 1) ? g_host.pc_d : nullptr;
     D.ctl = (VrCtl *)(ws + P.off_ctl);
     D.st_scan = (unsigned long long *)(ws + P.off_stscan);
     D.st_sel = (uint32_t *)(ws + P.off_stsel);
+    D.hist = (uint32_t *)(ws + P.off_hist);
+    D.cl = (const VrCloud *)(ws + P.off_cl);
+    D.cs = (VrCloudState *)(ws + P.off_cs);
     D.q = (uint32_t *)(ws + P.off_q);
     D.key[0] = (uint32_t *)(ws + P.off_key0);
     D.key[1] = (uint32_t *)(ws + P.off_key1);
@@ -358,10 +440,18 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
 
     // ---------------------------------------------------------- phase 1 ----
     mark(ST_DIST);
-    launch_init(D, P.zero_bytes / 4, s);
-    if (gram_applies(D)) launch_gram(D, req->points, s);
-    else launch_dist(D, req->points, s);
+    if (C > 1) {
+        if (hipMemcpyAsync((void *)D.cl, g_host.tab, sizeof(VrCloud) * (size_t)C, hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return fail(VR_EHIP, ws, P.total);
+        launch_init(D, P.zero_bytes / 4, nullptr, nullptr, s);
+    } else {
+        launch_init(D, P.zero_bytes / 4, &one, (VrCloud *)D.cl, s);
+    }
+    if (gram_applies(D)) launch_gram(D, nullptr, s);
+    else launch_dist(D, nullptr, s);
     mark(ST_SELECT);
+    if (need_hist) launch_pivot(D, s);
     launch_select(D, s);
     mark(ST_SORT);
     {
@@ -373,46 +463,53 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     mark(ST_STAR);
     if (want_tri) {
         const SortJob J = star_sort_job(D);
-        launch_sort_pass(J, D.ntile_I, 0, s);
-        launch_sort_pass(J, D.ntile_I, 1, s);
+        for (int p = 0; p < D.spasses; p++) launch_sort_pass(J, D.ntile_I, p, s);
         launch_star(D, s);
     }
     mark(ST_COUNT);
     if (want_tri) launch_tri_count(D, s);
     mark(ST_SCAN);
-    // the scan reads K from the device (unknown on the host for SQDIST)
-    if (want_tri) launch_scan(D, Kmax, s);  // its last tile publishes the counts
+    // the scan reads K from the device (unknown on the host for a distance
+    // threshold); for one cloud its last tile publishes the counts
+    if (want_tri) launch_scan(D, Kmax, s);
+    if (C > 1) launch_cloud_publish(D, s);
     mark(ST_SYNC);
     if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);
         return fail(VR_EHIP, ws, P.total);
     }
-    // Poll the mailbox; check the stream now and then so that a failed launch
-    // cannot leave the host waiting.
+    // Poll the mailbox; query the stream now and then so that a failed
+    // launch cannot leave the host waiting.
     {
-        volatile VrMailbox *mb = g_mb.h;
         unsigned long long spins = 0;
-        while (__atomic_load_n(&g_mb.h->seq, __ATOMIC_ACQUIRE) != D.seq) {
+        while (__atomic_load_n(&g_host.mb_h->seq, __ATOMIC_ACQUIRE) != D.seq) {
             if ((++spins & 4095ull) == 0) {
-                hipError_t q = hipStreamQuery(s);
+                const hipError_t q = hipStreamQuery(s);
                 if (q == hipSuccess) {
-                    if (__atomic_load_n(&g_mb.h->seq, __ATOMIC_ACQUIRE) == D.seq) break;
+                    if (__atomic_load_n(&g_host.mb_h->seq, __ATOMIC_ACQUIRE) == D.seq) break;
                     return fail(VR_EHIP, ws, P.total);
                 }
-                if (q != hipErrorNotReady) {
-                    (void)hipGetLastError();
-                    return fail(VR_EHIP, ws, P.total);
-                }
+                if (q != hipErrorNotReady) return fail(VR_EHIP, ws, P.total);
             }
             _mm_pause();
         }
-        (void)mb;
     }
-    const uint32_t flags = g_mb.h->flags;
-    const long long K = (long long)g_mb.h->n_kept;
-    unsigned long long T = want_tri ? g_mb.h->n_tri : 0ull;
+    const uint32_t flags = __atomic_load_n(&g_host.mb_h->flags, __ATOMIC_ACQUIRE);
+    const long long K = (long long)__atomic_load_n(&g_host.mb_h->n_kept, __ATOMIC_ACQUIRE);
+    const unsigned long long T = want_tri ? __atomic_load_n(&g_host.mb_h->n_tri, __ATOMIC_ACQUIRE) : 0ull;
     if (flags & 1u) return fail(VR_ERANGE, ws, P.total);
-    if (K > VR_MAX_EDGES) return fail(VR_E2BIG, ws, P.total);
+    // per device cloud: first kept edge, kept edges, first triangle, triangles
+    std::vector<unsigned long long> pc((size_t)(4 * C));
+    if (C > 1) {
+        for (long long x = 0; x < 4 * C; x++) pc[x] = __atomic_load_n(&g_host.pc_h[x], __ATOMIC_ACQUIRE);
+    } else {
+        pc[0] = 0;
+        pc[1] = (unsigned long long)K;
+        pc[2] = 0;
+        pc[3] = T;
+    }
+    for (long long c = 0; c < C; c++)
+        if (pc[4 * c + 1] > (unsigned long long)VR_MAX_EDGES) return fail(VR_E2BIG, ws, P.total);
 
     // ---------------------------------------------------------- phase 2 ----
     const bool write_tri = want_tri && !count_only && T > 0;
@@ -421,34 +518,131 @@ int vr_build(const vr_request *req, void *stream_, vr_result **out) {
     const size_t ob = eq_bytes + eij_bytes + tri_bytes;
     char *blk = (char *)A.get(ob);
     if (!blk) return fail(VR_ENOMEM, ws, P.total);
-    res->block = blk;
-    res->block_bytes = ob;
-    res->edge_q = (const int64_t *)blk;
-    res->edge_ij = (const uint32_t *)(blk + eq_bytes);
-    res->tri_key = write_tri ? (const uint64_t *)(blk + eq_bytes + eij_bytes) : nullptr;
-    res->n_edges = K;
-    res->n_triangles = (int64_t)T;
+    own.block = blk;
+    own.block_bytes = ob;
+    const int64_t *edge_q = (const int64_t *)blk;
+    const uint32_t *edge_ij = (const uint32_t *)(blk + eq_bytes);
+    const uint64_t *tri_key = write_tri ? (const uint64_t *)(blk + eq_bytes + eij_bytes) : nullptr;
+    for (long long c = 0; c < C; c++) {
+        vr_result &v = views[(size_t)which[c]];
+        const unsigned long long kb = pc[4 * c], Kc = pc[4 * c + 1], tb = pc[4 * c + 2], Tc = pc[4 * c + 3];
+        v.n_edges = (int64_t)Kc;
+        v.n_triangles = (int64_t)Tc;
+        v.edge_q = edge_q + kb;
+        v.edge_ij = edge_ij + 2 * kb;
+        v.tri_key = (tri_key && Tc > 0) ? tri_key + tb : nullptr;
+    }
 
     mark(ST_WRITE);
     if (write_tri) {
         // the triangle writer also writes the public edge arrays
-        launch_tri_write(D, (unsigned long long *)res->tri_key, K, (uint32_t *)res->edge_ij,
-                         (long long *)res->edge_q, s);
+        launch_tri_write(D, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
         mark(ST_EMIT);
     } else {
         mark(ST_EMIT);
-        launch_emit_edges(D, K, (uint32_t *)res->edge_ij, (long long *)res->edge_q, s);
+        launch_emit_edges(D, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
     }
     mark(ST_N);
     if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);
-        A.put(blk, ob);
-        res->block = nullptr;
         return fail(VR_EHIP, ws, P.total);
     }
     A.put(ws, P.total);
+    return VR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vr_version(void) { return 110; }
+
+const char *vr_status_string(int status) {
+    switch (status) {
+    case VR_OK: return "ok";
+    case VR_EINVAL: return "invalid argument";
+    case VR_ENOMEM: return "device allocation failed";
+    case VR_E2BIG: return "too many points or edges for the packed keys";
+    case VR_EHIP: return "HIP runtime error";
+    case VR_ERANGE: return "a squared distance exceeds 32 bits";
+    default: return "unknown status";
+    }
+}
+
+const char *vr_stage_name(int s) { return (s >= 0 && s < ST_N) ? kStageNames[s] : nullptr; }
+
+int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind) {
+    vr_request r{};
+    r.n = n; r.d = d; r.dtype = dtype; r.thr_kind = thr_kind; r.thr_num = 0; r.thr_den = 1; r.maxdim = 2;
+    r.points = (const void *)16;
+    long long E, K;
+    if (check_request(&r, &E, &K) != VR_OK) return -1;
+    return (int64_t)plan(1, n, E, E, true, true).total;
+}
+
+int vr_query_counts(const vr_result *res, int64_t counts[3]) {
+    if (!res || !counts) return VR_EINVAL;
+    counts[0] = res->n_vertices;
+    counts[1] = res->n_edges;
+    counts[2] = res->n_triangles;
+    return VR_OK;
+}
+
+int vr_query_stage_ms(const vr_result *res, float *ms, int cap) {
+    if (!res || (!ms && cap > 0)) return VR_EINVAL;
+    return static_cast<const Result *>(res)->own.stage_ms(ms, cap);
+}
+
+void vr_free(vr_result *res_, void *stream) {
+    if (!res_) return;
+    Result *res = static_cast<Result *>(res_);
+    res->own.release((hipStream_t)stream);
+    delete res;
+}
+
+int vr_build(const vr_request *req, void *stream, vr_result **out) {
+    if (!out || !req) return VR_EINVAL;
+    Result *res = new (std::nothrow) Result();
+    if (!res) return VR_ENOMEM;
+    std::vector<vr_result> views;
+    const int st = build_impl(req, 1, (hipStream_t)stream, res->own, views);
+    if (st != VR_OK) {
+        delete res;
+        return st;
+    }
+    static_cast<vr_result &>(*res) = views[0];
     *out = res;
     return VR_OK;
+}
+
+int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, vr_batch **out) {
+    if (!out || !reqs || count < 1) return VR_EINVAL;
+    vr_batch *b = new (std::nothrow) vr_batch();
+    if (!b) return VR_ENOMEM;
+    const int st = build_impl(reqs, count, (hipStream_t)stream, b->own, b->views);
+    if (st != VR_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return VR_OK;
+}
+
+int vr_batch_result(const vr_batch *b, int64_t index, vr_result *view) {
+    if (!b || !view || index < 0 || index >= (int64_t)b->views.size()) return VR_EINVAL;
+    *view = b->views[(size_t)index];
+    return VR_OK;
+}
+
+int vr_batch_stage_ms(const vr_batch *b, float *ms, int cap) {
+    if (!b || (!ms && cap > 0)) return VR_EINVAL;
+    return b->own.stage_ms(ms, cap);
+}
+
+void vr_batch_free(vr_batch *b, void *stream) {
+    if (!b) return;
+    b->own.release((hipStream_t)stream);
+    delete b;
 }
 
 }  // extern "C"

@@ -24,14 +24,15 @@
 
 // Control block in device memory, zeroed at the start of every build.
 struct VrCtl {
-    uint32_t ticket[16];            // tile tickets: 0 select, 1..4 edge sort, 5 scan, 6..7 star sort
+    uint32_t ticket[16];            // tile tickets: 0 select, 1..4 edge sort, 5 scan, 6..8 star sort
+    uint32_t done;                  // finished work-groups of the per-cloud publisher
     uint32_t flags;                 // bit 0: a squared distance overflowed 32 bits
     uint32_t n_cand;                // candidates kept by the select pass
     uint32_t n_kept;                // K
     uint32_t n_inc;                 // 2K vertex incidences
     unsigned long long n_tri;       // T
     uint32_t hist8[VR_MAX_PASSES][VR_RADIX];  // digit histograms of the edge candidates
-    uint32_t hinc[2][VR_RADIX];     // digit histograms of the incidence vertices
+    uint32_t hinc[3][VR_RADIX];     // digit histograms of the incidence vertices
     uint32_t bucket[VR_NBUCKET];    // log-linear histogram of all squared distances
 };
 
@@ -284,45 +285,98 @@ struct SortJob {
     int passes;
 };
 
+// One cloud of a batch (written by the host).  Vertices, pairs and distance
+// tiles of all clouds are numbered globally; every output of a cloud uses its
+// own local vertex indices and local edge ranks.
+struct VrCloud {
+    const void *points;   // device, n x d row-major
+    int n, d;
+    long long vbase;      // first global vertex
+    long long pbase;      // first global pair
+    long long tbase;      // first distance tile
+    long long kbase;      // first global kept edge (unless distance threshold)
+    long long K;          // kept edges (unless distance threshold)
+    long long thr_num;    // distance threshold (strict)
+};
+
+// Per-cloud results written on the device.
+struct VrCloudState {
+    uint32_t pivot;       // pivot bucket of the percentile/count threshold
+    uint32_t cand_base;   // first candidate of the cloud in the candidate list
+};
+
 struct VrDev {
-    // shape
-    int n, d, dtype;
-    long long E;
+    // shape (dtype and d shared by every cloud of a batch)
+    int C;                  // clouds
+    int dtype, d;
+    int maxn;               // largest cloud
+    long long V, E;         // vertices, pairs over all clouds
+    long long tiles;        // 64x64 distance tiles over all clouds
     int thr_kind;
-    long long thr_num;
-    long long K_host;       // K when known before the build (else -1)
+    long long K_host;       // kept edges over all clouds when known on the host (else -1)
+    int qbits;              // bits of a squared distance in the sort key; cloud id above
     int passes;             // radix passes launched for the edge keys
+    int spasses;            // radix passes launched for the star sort
     int need_hist;          // histogram select needed (COUNT / FRACTION)
     int tri;                // triangles wanted
     // workspace
     VrCtl *ctl;
     VrMailbox *mailbox;     // host-pinned
     uint32_t seq;
+    const VrCloud *cl;      // C clouds
+    VrCloudState *cs;       // C per-cloud results
+    uint32_t *hist;         // C x VR_NBUCKET log-linear histograms
+    unsigned long long *host_cloud;  // host-pinned: per cloud (kbase, K, tri_base, T)
     uint32_t *q;            // E squared distances
     uint32_t *key[2];       // E each, ping-pong (edge sort)
-    uint32_t *val[2];       // E each (i<<16 | j)
+    uint32_t *val[2];       // E each (i<<16 | j, local)
     uint32_t *st_sel;       // ceil(E/TILE) select statuses
     uint32_t *st_sort[2];   // ceil(E/TILE)*RADIX edge-sort statuses
-    uint32_t *se_ij;        // K sorted kept edges (i<<16|j)
+    uint32_t *se_ij;        // K sorted kept edges (i<<16|j, local)
     uint32_t *se_q;         // K
-    uint32_t *ikey[2];      // 2K incidence vertices, ping-pong (star sort)
-    uint32_t *ival[2];      // 2K incidence ids 2r+s
+    uint32_t *ikey[2];      // 2K incidence vertices (global), ping-pong (star sort)
+    uint32_t *ival[2];      // 2K incidence ids 2g+s
     uint32_t *ist[2];       // ceil(2K/TILE)*RADIX star-sort statuses
-    uint32_t *star_r;       // 2K: CSR stars, ranks ascending within a vertex
-    uint16_t *star_nbr;     // 2K: the other endpoint
+    uint32_t *star_r;       // 2K: CSR stars, global kept-edge index, rank order
+    uint16_t *star_nbr;     // 2K: the other endpoint (local)
     uint32_t *star_k;       // 2K: stars in neighbour order, neighbour | rank-order position << 16
-    uint32_t *start;        // n+1 CSR row starts
-    uint16_t *pos;          // 2K: position of edge r in the star of endpoint s (id 2r+s)
-    uint32_t *cnt;          // K triangles per value
+    uint32_t *start;        // V+1 CSR row starts
+    uint16_t *pos;          // 2K: position of edge g in the star of endpoint s (id 2g+s)
+    uint32_t *cnt;          // K triangles per kept edge
     unsigned long long *off;     // K exclusive offsets
     unsigned long long *st_scan; // ceil(K/TILE)
     long long ntile_E, ntile_I;
 };
 
+// Cloud of a global index, by the cloud's first index (upper bound - 1).
+template <typename F>
+__device__ __forceinline__ int cloud_of(long long x, int C, F first) {
+    int lo = 0, hi = C - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Kept edges of cloud c and its first global kept edge.  With a distance
+// threshold every candidate is kept, so both come from the candidate bases.
+__device__ __forceinline__ long long kept_base(const VrDev &D, int c) {
+    return (D.thr_kind == 3) ? (long long)D.cs[c].cand_base : D.cl[c].kbase;
+}
+__device__ __forceinline__ long long kept_count(const VrDev &D, int c) {
+    if (D.thr_kind != 3) return D.cl[c].K;
+    const long long nb = (c + 1 < D.C) ? (long long)D.cs[c + 1].cand_base : (long long)D.ctl->n_cand;
+    return nb - (long long)D.cs[c].cand_base;
+}
+
 SortJob edge_sort_job(const VrDev &D);
 SortJob star_sort_job(const VrDev &D);
 
-void launch_init(const VrDev &D, size_t zero_words, hipStream_t s);
+void launch_init(const VrDev &D, size_t zero_words, const VrCloud *one, VrCloud *dst, hipStream_t s);
+void launch_pivot(const VrDev &D, hipStream_t s);
+void launch_cloud_publish(const VrDev &D, hipStream_t s);
 void launch_dist(const VrDev &D, const void *points, hipStream_t s);
 bool gram_applies(const VrDev &D);
 void launch_gram(const VrDev &D, const void *points, hipStream_t s);

@@ -40,3 +40,25 @@ def assert_matches_oracle(out, f, check_tri=True):
         got = decode_keys(out["tri"])
         assert got.shape == f.tris.shape
         assert np.array_equal(got, f.tris)
+
+
+def item_host(item):
+    """Host copies of one result's arrays (a Result or a batch item)."""
+    return {
+        "counts": item.counts,
+        "edge_ij": item.edge_ij().cpu().numpy().astype(np.int64),
+        "edge_q": item.edge_q().cpu().numpy(),
+        "tri": item.tri_key().cpu().numpy(),
+    }
+
+
+def gpu_build_batch(clouds, maxdim=2, count_only=False, device="cuda:0", allocator="library"):
+    """One batched build of `clouds` (one threshold kind); returns (batch, [host dicts])."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    pts = [torch.from_numpy(np.ascontiguousarray(c.points)).to(device) for c in clouds]
+    b = vr.build_batch(pts, [c.thr for c in clouds], maxdim=maxdim, count_only=count_only, allocator=allocator)
+    torch.cuda.synchronize()
+    return b, [item_host(it) for it in b]

@@ -76,3 +76,47 @@ def test_workspace_bytes():
     assert vr.workspace_bytes(9000, 3) == -1
     assert vr.lib().vr_query_counts(None, None) == vr.VR_EINVAL
     vr.lib().vr_free(None, None)  # NULL-safe
+
+
+def _batch_rc(reqs):
+    arr = (vr.VrRequest * max(1, len(reqs)))(*reqs)
+    out = ctypes.c_void_p()
+    rc = vr.lib().vr_build_batch(arr, len(reqs), None, ctypes.byref(out))
+    return rc, out
+
+
+@pytest.mark.parametrize("reqs,code", [
+    ([], vr.VR_EINVAL),                                                     # empty batch
+    ([_req(), _req(dtype=vr.VR_I16)], vr.VR_EINVAL),                        # mixed coordinate types
+    ([_req(), _req(d=4)], vr.VR_EINVAL),                                    # mixed dimensions
+    ([_req(), _req(thr_kind=2, thr_num=1, thr_den=5)], vr.VR_EINVAL),        # mixed threshold kinds
+    ([_req(), _req(maxdim=1)], vr.VR_EINVAL),                               # mixed maxdim
+    ([_req(), _req(flags=vr.VR_COUNT_ONLY)], vr.VR_EINVAL),                 # mixed flags
+    ([_req(), _req(n=-1)], vr.VR_EINVAL),                                   # one bad request
+    ([_req(), _req(n=8193)], vr.VR_E2BIG),
+    ([_req(dtype=vr.VR_I16), _req(dtype=vr.VR_I16)], vr.VR_E2BIG),          # 32-bit distances: one cloud per batch
+    ([_req(d=40000)] * 2, vr.VR_E2BIG),                                     # 255^2 d needs 32 bits, 2 clouds 1 more
+])
+def test_invalid_batches_rejected_before_device_work(reqs, code):
+    rc, out = _batch_rc(reqs)
+    assert rc == code
+    assert not out.value
+
+
+def test_batch_key_budget():
+    # int8, d = 3: squared distances need 18 bits, so 2^14 clouds fit the 32-bit key
+    assert vr.batch_limit(vr.VR_I8, 3) == 1 << 14
+    assert vr.batch_limit(vr.VR_I8, 64) == 1 << 10
+    assert vr.batch_limit(vr.VR_I16, 3) == 1
+    rc, _ = _batch_rc([_req(d=3)] * ((1 << 14) + 1))
+    assert rc == vr.VR_E2BIG
+
+
+def test_batch_handles_null_safe():
+    L = vr.lib()
+    r = vr.VrResult()
+    assert L.vr_batch_result(None, 0, ctypes.byref(r)) == vr.VR_EINVAL
+    assert L.vr_batch_stage_ms(None, None, 0) == vr.VR_EINVAL
+    L.vr_batch_free(None, None)
+    out = ctypes.c_void_p()
+    assert L.vr_build_batch(None, 1, None, ctypes.byref(out)) == vr.VR_EINVAL
