@@ -122,6 +122,86 @@ def _batched(vr, torch, reps=3):
             "per_cloud_builds": {"value": simp / ts, "ms": 1e3 * ts}, "speedup_vs_per_cloud": ts / tb}
 
 
+def _pcts(lat):
+    lat = sorted(lat)
+    pick = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]  # noqa: E731
+    return {"p50_ms": round(1e3 * pick(0.50), 4), "p99_ms": round(1e3 * pick(0.99), 4),
+            "mean_ms": round(1e3 * sum(lat) / len(lat), 4)}
+
+
+def _serving(vr, torch, qps=None, requests=2000, warm=100, slots=4, max_batch=32):
+    """Poisson stream of clouds (n log-uniform in [100, 5000], d in {2, 3, 16,
+    64}, 5th-20th percentile): the plain build (FIFO, one at a time) and the
+    continuous-batching request loop at the same fixed QPS.  Latency is
+    completion (outputs on the device) minus scheduled arrival; the first
+    `warm` requests are excluded from the statistics."""
+    import workloads
+    from paper_1809_04424_amd.serve import Server
+
+    stream = workloads.serving_stream(requests=requests, qps=1.0)  # arrival times scale as 1/qps
+    clouds = [c for _, c in stream]
+    unit_t = [t for t, _ in stream]
+    pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
+    torch.cuda.synchronize()
+    for p, c in zip(pts[:warm], clouds[:warm]):
+        vr.build(p, c.thr).free()
+    torch.cuda.synchronize()
+    # capacity of the plain build: back to back, FIFO
+    t0 = time.perf_counter()
+    simp = []
+    for p, c in zip(pts, clouds):
+        r = vr.build(p, c.thr)
+        simp.append(sum(r.counts))
+        r.free()
+    torch.cuda.synchronize()
+    mu = requests / (time.perf_counter() - t0)
+    if qps is None:
+        qps = max(1.0, round(0.7 * mu))
+    arr = [t / qps for t in unit_t]
+    print(f"[bench] serving: plain capacity {mu:.1f} req/s, fixed QPS {qps}", file=sys.stderr, flush=True)
+
+    def _sleep_until(t):
+        dt = t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+
+    # plain: one build at a time, in arrival order
+    start = time.perf_counter() + 0.02
+    done = []
+    s = torch.cuda.current_stream()
+    for a, p, c in zip(arr, pts, clouds):
+        _sleep_until(start + a)
+        r = vr.build(p, c.thr)
+        s.synchronize()
+        done.append(time.perf_counter())
+        r.free()
+    lat_plain = [d - (start + a) for d, a in zip(done, arr)]
+    span_plain = done[-1] - (start + arr[warm])
+    print("[bench] serving: plain FIFO done", file=sys.stderr, flush=True)
+
+    # served: continuous batching
+    with Server(slots=slots, max_batch=max_batch, keep_results=False) as srv:
+        start = time.perf_counter() + 0.02
+        reqs = []
+        for a, p, c in zip(arr, pts, clouds):
+            _sleep_until(start + a)
+            reqs.append(srv.submit(p, c.thr, arrival=start + a))
+        for r in reqs:
+            r.wait(timeout=300)
+    lat_srv = [r.latency for r in reqs]
+    span_srv = max(r.t_done for r in reqs[warm:]) - reqs[warm].arrival
+    assert all(sum(r.counts) == n for r, n in zip(reqs, simp)), "served counts differ from plain builds"
+    print("[bench] serving: request loop done", file=sys.stderr, flush=True)
+    total = sum(simp[warm:])
+    sizes = [r.batch_size for r in reqs]
+    return {"qps": qps, "plain_capacity_rps": round(mu, 2), "requests": requests, "warmup_requests": warm,
+            "simplices": total,
+            "plain_fifo": dict(_pcts(lat_plain[warm:]), simplices_per_s=total / span_plain),
+            "served": dict(_pcts(lat_srv[warm:]), simplices_per_s=total / span_srv, slots=slots,
+                           max_batch=max_batch, batches=srv.batches,
+                           mean_batch=round(sum(sizes) / len(sizes), 3), peak_bytes=srv.peak_bytes)}
+
+
 def _copy_calibration(torch, mib=256):
     """A plain device copy of known size, so FETCH_SIZE / WRITE_SIZE of other
     kernels can be scaled to bytes (launched only with --copy-calib)."""
@@ -143,6 +223,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cloud batched side measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (Poisson stream) side measurement")
+    ap.add_argument("--qps", type=float, default=None, help="serving QPS (default: 0.7 x the plain capacity)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--breakdown-reps", type=int, default=10, help="untimed builds for the stage breakdown (0: skip)")
@@ -197,6 +279,8 @@ def main():
 
     if not args.no_batch and args.workload == "circle1000":
         extra["batched512_r3"] = _batched(vr, torch)
+    if not args.no_serve and args.workload == "circle1000":
+        extra["serving_poisson"] = _serving(vr, torch, qps=args.qps)
 
     line = {
         "metric": "filtered simplices/sec (VR dim<=2, bit-exact)",

@@ -83,8 +83,8 @@ enum {
 
 /* Optional device allocator, e.g. a framework's caching allocator.
  * alloc returns device memory usable on `stream` (NULL on failure); free
- * releases it in stream order.  With no allocator the library uses
- * hipMallocAsync / hipFreeAsync on the stream (default memory pool). */
+ * releases it in stream order.  With no allocator the library uses its own
+ * stream-ordered cache (see vr_trim). */
 typedef struct vr_allocator {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
@@ -100,7 +100,7 @@ typedef struct vr_request {
     int64_t thr_num, thr_den;
     int32_t maxdim;     /* 0: vertices only, 1: up to edges, 2: up to triangles */
     uint32_t flags;     /* VR_COUNT_ONLY | VR_TIMING | VR_TIMING_WRITE */
-    const vr_allocator *alloc; /* NULL: hipMallocAsync on the stream */
+    const vr_allocator *alloc; /* NULL: the library's stream-ordered cache */
 } vr_request;
 
 /* Result handle, owned by the library until vr_free.  Fields are read-only. */
@@ -178,12 +178,28 @@ VR_API int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, v
  * index outside [0, count). */
 VR_API int vr_batch_result(const vr_batch *batch, int64_t index, vr_result *view);
 
+/* Exact device workspace bytes vr_build_batch would allocate for these
+ * requests (count = 1: vr_build), besides the outputs (edges 16 B each,
+ * triangles 8 B each, each array 256-byte aligned).  Host only.  0 when no
+ * request needs the device; a negative vr_status for requests the build
+ * would reject. */
+VR_API int64_t vr_batch_workspace_bytes(const vr_request *reqs, int64_t count);
+
 /* As vr_query_stage_ms, for the whole batch. */
 VR_API int vr_batch_stage_ms(const vr_batch *batch, float *ms, int cap);
 
 /* Releases the batch's device memory in stream order on `stream`, then the
  * handle; every view dies with it.  NULL-safe. */
 VR_API void vr_batch_free(vr_batch *batch, void *stream);
+
+/* Device memory.  Without a caller allocator, workspaces and output blocks
+ * come from a stream-ordered cache inside the library: blocks are taken from
+ * the driver once and reused by later builds of any stream (a reuse on
+ * another stream first waits, on the device, for the block's last use), so
+ * a stream of requests of changing sizes does not return to the driver.
+ * vr_trim releases the cached blocks of the current device that no result
+ * holds (it synchronises the device) and returns the bytes released. */
+VR_API int64_t vr_trim(void);
 
 /* Static description of a status code. */
 VR_API const char *vr_status_string(int status);

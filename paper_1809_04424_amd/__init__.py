@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_trim",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -94,6 +94,8 @@ def lib():
         L.vr_free.restype = None
         L.vr_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
         L.vr_workspace_bytes.restype = ctypes.c_int64
+        L.vr_batch_workspace_bytes.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64]
+        L.vr_batch_workspace_bytes.restype = ctypes.c_int64
         L.vr_build_batch.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.POINTER(ctypes.c_void_p)]
         L.vr_build_batch.restype = ctypes.c_int
@@ -103,12 +105,19 @@ def lib():
         L.vr_batch_stage_ms.restype = ctypes.c_int
         L.vr_batch_free.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.vr_batch_free.restype = None
+        L.vr_trim.argtypes = []
+        L.vr_trim.restype = ctypes.c_int64
         L.vr_status_string.argtypes = [ctypes.c_int]
         L.vr_status_string.restype = ctypes.c_char_p
         L.vr_version.argtypes = []
         L.vr_version.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def trim() -> int:
+    """Release the library's cached device blocks not in use (current device)."""
+    return int(lib().vr_trim())
 
 
 def status_string(code: int) -> str:
@@ -128,6 +137,20 @@ def stage_names():
 
 def workspace_bytes(n: int, d: int, dtype: int = VR_I8, thr_kind: str = "fraction") -> int:
     return int(lib().vr_workspace_bytes(n, d, dtype, VR_THR[thr_kind]))
+
+
+def batch_workspace_bytes(shapes, maxdim: int = 2) -> int:
+    """Exact workspace of build_batch over clouds given as (n, d, dtype, thr)
+    tuples (no device memory needed); raises VrError for rejected shapes."""
+    reqs = (VrRequest * len(shapes))()
+    for r, (n, d, dtype, thr) in zip(reqs, shapes):
+        kind, num, den = thr
+        r.points, r.n, r.d, r.dtype = (16 if n else None), n, d, dtype
+        r.thr_kind, r.thr_num, r.thr_den, r.maxdim, r.flags = VR_THR[kind], int(num), int(den), maxdim, 0
+    v = int(lib().vr_batch_workspace_bytes(reqs, len(shapes)))
+    if v < 0:
+        raise VrError(v, status_string(v))
+    return v
 
 
 class _TorchAllocator:
@@ -365,7 +388,7 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
 
     points:    torch tensor on a HIP device, (n, d) int8/int16/int32, rows are points.
     thr:       ("full", 0, 1) | ("count", K, 1) | ("fraction", num, den) | ("sqdist", tau, 0).
-    allocator: "library" (the library's stream-ordered pool) or "torch" (torch's
+    allocator: "library" (the library's stream-ordered cache) or "torch" (torch's
                caching allocator through the library's allocator hook).
     timing:    True: HIP events between all stages; "write": around the
                triangle write only (see Result.stage_ms).

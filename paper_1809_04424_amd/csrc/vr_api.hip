@@ -19,6 +19,7 @@
 #include <immintrin.h>
 
 #include "vr.h"
+#include "vr_cache.h"
 #include "vr_device.h"
 
 namespace {
@@ -27,23 +28,20 @@ enum Stage { ST_DIST, ST_SELECT, ST_SORT, ST_EDGES, ST_STAR, ST_COUNT, ST_SCAN, 
 const char *kStageNames[ST_N] = {"dist", "select", "radix_sort", "kept_edges", "star_sort",
                                  "tri_count", "tri_scan", "count_readback", "tri_write", "emit_edges"};
 
+// Device memory of one build: the caller's allocator, else the library's
+// stream-ordered cache.
 struct Alloc {
     const vr_allocator *a;
     hipStream_t s;
     void *get(size_t bytes) {
         if (bytes == 0) bytes = 256;
         if (a && a->alloc) return a->alloc(bytes, (void *)s, a->ctx);
-        void *p = nullptr;
-        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-        return p;
+        return cache_get(bytes, s);
     }
     void put(void *p, size_t bytes) {
         if (!p) return;
         if (a && a->free) a->free(p, bytes, (void *)s, a->ctx);
-        else (void)hipFreeAsync(p, s);
+        else cache_put(p, s);
     }
 };
 
@@ -98,21 +96,6 @@ struct vr_batch {
 };
 
 namespace {
-
-// Keep freed pool memory cached in the device's default pool, so repeated
-// builds do not return to the driver for every allocation.
-std::once_flag g_pool_once[64];
-void tune_pool(int dev) {
-    if (dev < 0 || dev >= 64) return;
-    std::call_once(g_pool_once[dev], [dev]() {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t thr = ~0ull;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-        }
-        (void)hipGetLastError();
-    });
-}
 
 // Host-pinned memory per host thread: the count mailbox and the per-cloud
 // counts of a batch (device-visible, coherent), and the staging copy of a
@@ -279,14 +262,21 @@ int check_request(const vr_request *req, long long *E_out, long long *K_out) {
     return VR_OK;
 }
 
-// Build `count` clouds on stream s.  On VR_OK `own` holds the output block
-// and views[i] describes request i (device pointers into the block).  On an
-// error `own` holds nothing.
-int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &own, std::vector<vr_result> &views) {
+// Host-side shape of a batch: which requests need the device, totals over
+// them, key widths.  Touches no device state.
+struct Shape {
+    std::vector<long long> Es, Ks, which;
+    long long C = 0, V = 0, E = 0, tiles = 0, Khost = -1, Kmax = 0;
+    int d = 0, maxn = 0, qbits = 0, cbits = 0;
+    bool sq = false, want_tri = false, need_hist = false;
+};
+
+int shape_of(const vr_request *reqs, long long count, Shape &S) {
     const vr_request &r0 = reqs[0];
-    std::vector<long long> Es((size_t)count), Ks((size_t)count);
+    S.Es.assign((size_t)count, 0);
+    S.Ks.assign((size_t)count, 0);
     for (long long i = 0; i < count; i++) {
-        const int st = check_request(&reqs[i], &Es[i], &Ks[i]);
+        const int st = check_request(&reqs[i], &S.Es[i], &S.Ks[i]);
         if (st != VR_OK) return st;
         const vr_request &r = reqs[i];
         // a batch shares coordinate type, dimension, threshold kind, maxdim and flags
@@ -294,48 +284,66 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             r.thr_kind != r0.thr_kind)
             return VR_EINVAL;
     }
+    S.sq = r0.thr_kind == VR_THR_SQDIST;
+    S.need_hist = r0.thr_kind == VR_THR_COUNT || r0.thr_kind == VR_THR_FRACTION;
+    S.d = (int)r0.d;
+    // Device clouds: the requests with a pair and a possibly kept edge.  The
+    // others have no edges and are answered on the host.
+    S.which.clear();
+    if (r0.maxdim >= 1)
+        for (long long i = 0; i < count; i++)
+            if (S.Es[i] > 0 && S.Ks[i] != 0) S.which.push_back(i);
+    S.C = (long long)S.which.size();
+    if (S.C == 0) return VR_OK;
+    long long Ksum = 0;
+    for (long long c = 0; c < S.C; c++) {
+        const long long n = reqs[S.which[c]].n, nb = (n + 63) / 64;
+        S.V += n;
+        S.E += S.Es[S.which[c]];
+        S.tiles += nb * (nb + 1) / 2;
+        Ksum += S.sq ? 0 : S.Ks[S.which[c]];
+        if (n > S.maxn) S.maxn = (int)n;
+    }
+    S.want_tri = r0.maxdim >= 2 && S.maxn >= 3;
+    S.qbits = key_bits(r0.dtype, S.d);
+    S.cbits = bits_of((unsigned long long)(S.C - 1));
+    S.Khost = S.sq ? -1 : Ksum;
+    S.Kmax = (S.Khost >= 0) ? S.Khost : S.E;
+    // sort keys (cloud, q) in 32 bits; vertices in 24 bits (three star
+    // passes); incidence ids 2g+s in 32 bits
+    if (S.qbits + S.cbits > 32 || S.E > 0xFFFFFFFFll || S.V >= (1ll << 24) || S.Kmax > 0x7FFFFFFFll)
+        return VR_E2BIG;
+    return VR_OK;
+}
+
+Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.Kmax, S.need_hist, S.want_tri); }
+
+// Build `count` clouds on stream s.  On VR_OK `own` holds the output block
+// and views[i] describes request i (device pointers into the block).  On an
+// error `own` holds nothing.
+int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &own, std::vector<vr_result> &views) {
+    const vr_request &r0 = reqs[0];
+    Shape S;
+    const int st0 = shape_of(reqs, count, S);
+    if (st0 != VR_OK) return st0;
     const bool count_only = (r0.flags & VR_COUNT_ONLY) != 0;
     const bool timing_all = (r0.flags & VR_TIMING) != 0;
     const bool timing = timing_all || (r0.flags & VR_TIMING_WRITE) != 0;
-    const bool sq = r0.thr_kind == VR_THR_SQDIST;
-
+    const bool sq = S.sq;
     views.assign((size_t)count, vr_result{});
     for (long long i = 0; i < count; i++) views[i].n_vertices = reqs[i].n;
-
-    // Device clouds: the requests with a pair and a possibly kept edge.  The
-    // others have no edges and are answered on the host.
-    std::vector<long long> which;
-    if (r0.maxdim >= 1)
-        for (long long i = 0; i < count; i++)
-            if (Es[i] > 0 && Ks[i] != 0) which.push_back(i);
-    const long long C = (long long)which.size();
+    const long long C = S.C;
     if (C == 0) return VR_OK;
-    const int d = (int)r0.d;
-    long long V = 0, E = 0, tiles = 0, Ksum = 0;
-    int maxn = 0;
-    for (long long c = 0; c < C; c++) {
-        const long long n = reqs[which[c]].n, nb = (n + 63) / 64;
-        V += n;
-        E += Es[which[c]];
-        tiles += nb * (nb + 1) / 2;
-        Ksum += sq ? 0 : Ks[which[c]];
-        if (n > maxn) maxn = (int)n;
-    }
-    const bool want_tri = r0.maxdim >= 2 && maxn >= 3;
-    const int qbits = key_bits(r0.dtype, d);
-    const int cbits = bits_of((unsigned long long)(C - 1));
-    // sort keys (cloud, q) in 32 bits; vertices in 24 bits (three star
-    // passes); incidence ids 2g+s in 32 bits
-    const long long Khost = sq ? -1 : Ksum;
-    const long long Kmax = (Khost >= 0) ? Khost : E;
-    if (qbits + cbits > 32 || E > 0xFFFFFFFFll || V >= (1ll << 24) || Kmax > 0x7FFFFFFFll) return VR_E2BIG;
+    const std::vector<long long> &which = S.which, &Es = S.Es, &Ks = S.Ks;
+    const int d = S.d, maxn = S.maxn, qbits = S.qbits, cbits = S.cbits;
+    const long long V = S.V, E = S.E, tiles = S.tiles, Khost = S.Khost, Kmax = S.Kmax;
+    const bool want_tri = S.want_tri, need_hist = S.need_hist;
 
     own.has_alloc = r0.alloc != nullptr;
     if (own.has_alloc) own.alloc = *r0.alloc;
     Alloc A{r0.alloc, s};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return VR_EHIP;
-    tune_pool(dev);
     auto fail = [&](int code, void *ws, size_t wsb) {
         if (ws) A.put(ws, wsb);
         own.release(s);
@@ -379,8 +387,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             else g_host.tab[c] = cl;
         }
     }
-    const bool need_hist = r0.thr_kind == VR_THR_COUNT || r0.thr_kind == VR_THR_FRACTION;
-    const Plan P = plan(C, V, E, Kmax, need_hist, want_tri);
+    const Plan P = plan_of(S);
     char *ws = (char *)A.get(P.total);
     if (!ws) return fail(VR_ENOMEM, nullptr, 0);
 
@@ -615,6 +622,14 @@ int vr_build(const vr_request *req, void *stream, vr_result **out) {
     return VR_OK;
 }
 
+int64_t vr_batch_workspace_bytes(const vr_request *reqs, int64_t count) {
+    if (!reqs || count < 1) return VR_EINVAL;
+    Shape S;
+    const int st = shape_of(reqs, count, S);
+    if (st != VR_OK) return st;
+    return S.C == 0 ? 0 : (int64_t)plan_of(S).total;
+}
+
 int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, vr_batch **out) {
     if (!out || !reqs || count < 1) return VR_EINVAL;
     vr_batch *b = new (std::nothrow) vr_batch();
@@ -638,6 +653,8 @@ int vr_batch_stage_ms(const vr_batch *b, float *ms, int cap) {
     if (!b || (!ms && cap > 0)) return VR_EINVAL;
     return b->own.stage_ms(ms, cap);
 }
+
+int64_t vr_trim(void) { return (int64_t)cache_trim(); }
 
 void vr_batch_free(vr_batch *b, void *stream) {
     if (!b) return;

@@ -120,3 +120,16 @@ def test_batch_handles_null_safe():
     L.vr_batch_free(None, None)
     out = ctypes.c_void_p()
     assert L.vr_build_batch(None, 1, None, ctypes.byref(out)) == vr.VR_EINVAL
+
+
+def test_batch_workspace_bytes():
+    one = vr.batch_workspace_bytes([(10, 3, vr.VR_I8, ("fraction", 1, 1))])
+    assert one == vr.workspace_bytes(10, 3)  # K = E: the shape's maximum
+    a = vr.batch_workspace_bytes([(500, 3, vr.VR_I8, ("fraction", 20, 100))])
+    b = vr.batch_workspace_bytes([(700, 3, vr.VR_I8, ("fraction", 10, 100))])
+    ab = vr.batch_workspace_bytes([(500, 3, vr.VR_I8, ("fraction", 20, 100)), (700, 3, vr.VR_I8, ("fraction", 10, 100))])
+    assert max(a, b) < ab <= a + b
+    assert vr.batch_workspace_bytes([(1, 3, vr.VR_I8, ("full", 0, 1)), (0, 3, vr.VR_I8, ("full", 0, 1))]) == 0
+    assert vr.batch_workspace_bytes([(40, 3, vr.VR_I8, ("count", 0, 1))]) == 0  # nothing kept
+    with pytest.raises(vr.VrError):
+        vr.batch_workspace_bytes([(10, 3, vr.VR_I8, ("full", 0, 1)), (10, 4, vr.VR_I8, ("full", 0, 1))])
