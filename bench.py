@@ -214,6 +214,50 @@ def _copy_calibration(torch, mib=256):
     print(f"[copy-calib] copied {n} bytes", file=sys.stderr, flush=True)
 
 
+def _main_batched(vr, torch, args):
+    """The 512-cloud workload as the timed step: one batched build."""
+    import workloads
+
+    clouds = workloads.batched()
+    pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
+    thrs = [c.thr for c in clouds]
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        vr.build_batch(pts, thrs).free()
+    torch.cuda.synchronize()
+    tw = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b = vr.build_batch(pts, thrs, timing="write")
+        tw.append(b.stage_ms()["tri_write"])
+        counts = [it.counts for it in b]
+        b.free()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n, K, T = (sum(c[i] for c in counts) for i in range(3))
+    simp = n + K + T
+    tri_ms = sum(tw) / len(tw)
+    alg = _alg_bytes(n, K, T, sum(c[0] ** 2 for c in counts))
+    achieved = alg / (tri_ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "filtered simplices/sec (VR dim<=2, bit-exact)", "value": simp * args.steps / el,
+        "unit": "simplices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batched512_r3", "clouds": len(clouds), "points": n, "kept_edges": K,
+                   "triangles": T, "simplices_per_step": simp},
+        "roofline": {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}}), flush=True)
+
+
+def _alg_bytes(n, K, T, n2):
+    """Algorithmic bytes of the triangle writer: triangle keys out (8 T), kept
+    ranks in (8 K), the adjacency once (n^2/8 over the clouds), and the fused
+    public edge arrays (8 K in, 16 K out)."""
+    return 8 * T + 8 * K + n2 / 8.0 + 24 * K
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +284,9 @@ def main():
     import paper_1809_04424_amd as vr
 
     vr.lib()
+    if args.workload == "batched512":
+        _main_batched(vr, torch, args)
+        return
     cloud = _workload(args.workload)
     pts = torch.from_numpy(cloud.points).to("cuda:0")
     torch.cuda.synchronize()
@@ -255,7 +302,7 @@ def main():
     if args.stages:
         print(json.dumps({"stages_ms": st}), file=sys.stderr, flush=True)
 
-    alg = 8 * T + 8 * K + n * n / 8.0  # output keys + kept ranks + adjacency bitset, once
+    alg = _alg_bytes(n, K, T, n * n)
     achieved = alg / (tri_ms * 1e-3) / 1e9 if tri_ms > 0 else 0.0
     tr = TRAFFIC.get((args.workload, "k_tri_write"))
     traffic = tr["bytes"] if tr and tr["src_sha"] == _src_sha("k_triangles.hip") else None
@@ -269,7 +316,7 @@ def main():
         p3 = torch.from_numpy(c3.points).to("cuda:0")
         e3, cnt3, t3 = _time_builds(vr, torch, p3, c3.thr, 10, 2)
         s3 = sum(cnt3)
-        a3 = 8 * cnt3[2] + 8 * cnt3[1] + cnt3[0] ** 2 / 8.0
+        a3 = _alg_bytes(cnt3[0], cnt3[1], cnt3[2], cnt3[0] ** 2)
         extra["mixture4000_r64_p10"] = {
             "value": s3 * 10 / e3, "unit": "simplices/s", "ms_per_step": 1e3 * e3 / 10,
             "counts": list(cnt3), "tri_write_ms": round(t3, 5),

@@ -225,17 +225,20 @@ __device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, u
 
 size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLds); }
 
-// Load up to VR_PIECES pieces of `len` (>= 1) candidates starting at src.
-// Indices are clamped, so every lane loads (no predication); the consumer
-// masks lanes past len.
+// Load the first min(VR_PIECES, ceil(len/64)) pieces of `len` (>= 1, wave-
+// uniform) candidates starting at src; pieces past len are skipped with a
+// scalar branch.  Indices inside the last piece are clamped, so every lane
+// of a loaded piece loads (no predication); the consumer masks lanes past len.
 template <typename T>
 __device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T (&kk)[VR_PIECES]) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t last = len - 1u;
 #pragma unroll
     for (int j = 0; j < VR_PIECES; j++) {
-        const uint32_t y = (uint32_t)(j * VR_WAVE) + lane;
-        kk[j] = src[y < last ? y : last];
+        if ((uint32_t)(j * VR_WAVE) < len) {
+            const uint32_t y = (uint32_t)(j * VR_WAVE) + lane;
+            kk[j] = src[y < last ? y : last];
+        }
     }
 }
 
@@ -276,9 +279,11 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
                 if (len) {
 #pragma unroll
                     for (int j = 0; j < VR_PIECES; j++) {
-                        const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
-                        const bool hit = (y < len) & ((uint32_t)Pa[kA[j]] < xa);
-                        c += (uint32_t)__popcll(ballot64(hit));
+                        if ((uint32_t)(j * VR_WAVE) < len) {  // whole pieces past len are skipped
+                            const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
+                            const bool hit = (y < len) & ((uint32_t)Pa[kA[j]] < xa);
+                            c += (uint32_t)__popcll(ballot64(hit));
+                        }
                     }
                     for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                         const uint32_t y = y0 + (uint32_t)lane;
@@ -414,9 +419,9 @@ __device__ __forceinline__ void emit_edges_range(const VrDev &D, long long K, ui
                                                  long long *__restrict__ q, long long first, long long stride) {
     for (long long r = first; r < K; r += stride) {
         const uint32_t v = D.se_ij[r];
-        ij[2 * r] = v >> 16;
-        ij[2 * r + 1] = v & 0xFFFFu;
-        q[r] = (long long)D.se_q[r];
+        __builtin_nontemporal_store(v >> 16, ij + 2 * r);
+        __builtin_nontemporal_store(v & 0xFFFFu, ij + 2 * r + 1);
+        __builtin_nontemporal_store((long long)D.se_q[r], q + r);
     }
 }
 
@@ -488,11 +493,13 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                     const uint32_t klo = blw ? c_below : c_up;
                     const uint32_t khi = blw ? h_below : mid_hi;
                     const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    if (hit) dst[at] = ((unsigned long long)khi << 32) | klo;
+                    // streaming store: keeps the stars, not the output, in L2
+                    if (hit) __builtin_nontemporal_store(((unsigned long long)khi << 32) | klo, dst + at);
                     dst += __popcll(m);
                 };
 #pragma unroll
-                for (int j = 0; j < VR_PIECES; j++) piece(kA[j], (uint32_t)(j * VR_WAVE + lane));
+                for (int j = 0; j < VR_PIECES; j++)
+                    if ((uint32_t)(j * VR_WAVE) < len) piece(kA[j], (uint32_t)(j * VR_WAVE + lane));
                 for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                     const uint32_t y = y0 + (uint32_t)lane;
                     piece(D.star_k[rl(vsb, el) + (y < len ? y : len - 1u)], y);
