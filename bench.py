@@ -24,15 +24,34 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 
 # HBM bytes per launch of the triangle writer from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by a plain copy of known size), keyed by the SHA-256 of
-# the kernel source they were taken on; ignored once the source changes.
-TRAFFIC = {}
+# WRITE_SIZE, each scaled by what the counter reads for a 256 MiB device copy
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000), keyed by workload; `src` is the
+# SHA-256 prefix of the writer's sources the counters were taken on, and the
+# figure is dropped (null) once those sources change.
+TRAFFIC = {
+    "circle1000": {"bytes": 77813951, "src": "21a507b121b787b1"},
+    "mixture4000": {"bytes": 1796087703, "src": "21a507b121b787b1"},
+    "batched512": {"bytes": 20244676483, "src": "21a507b121b787b1"},
+}
+WRITER_SOURCES = ("k_triangles.hip", "vr_device.h")
+
+# Fixed arrival rate of the serving stream: 0.7 x the plain one-at-a-time
+# build's capacity on this stream, measured once on MI355X (2488-2520
+# builds/s back to back), then kept for every later run.
+SERVE_QPS = 1750.0
 
 
-def _src_sha(name: str) -> str:
-    p = os.path.join(ROOT, "paper_1809_04424_amd", "csrc", name)
-    with open(p, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def _writer_sha() -> str:
+    h = hashlib.sha256()
+    for name in WRITER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1809_04424_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(workload):
+    tr = TRAFFIC.get(workload)
+    return tr["bytes"] if tr and tr["src"] == _writer_sha() else None
 
 
 def _workload(name):
@@ -155,7 +174,7 @@ def _serving(vr, torch, qps=None, requests=2000, warm=100, slots=4, max_batch=32
         r.free()
     torch.cuda.synchronize()
     mu = requests / (time.perf_counter() - t0)
-    if qps is None:
+    if not qps:
         qps = max(1.0, round(0.7 * mu))
     arr = [t / qps for t in unit_t]
     print(f"[bench] serving: plain capacity {mu:.1f} req/s, fixed QPS {qps}", file=sys.stderr, flush=True)
@@ -247,7 +266,7 @@ def _main_batched(vr, torch, args):
         "config": {"workload": "batched512_r3", "clouds": len(clouds), "points": n, "kept_edges": K,
                    "triangles": T, "simplices_per_step": simp},
         "roofline": {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic("batched512"),
                      "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}}), flush=True)
 
 
@@ -268,7 +287,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cloud batched side measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (Poisson stream) side measurement")
-    ap.add_argument("--qps", type=float, default=None, help="serving QPS (default: 0.7 x the plain capacity)")
+    ap.add_argument("--qps", type=float, default=SERVE_QPS,
+                    help="serving QPS; 0 measures 0.7 x the plain build's capacity instead")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--breakdown-reps", type=int, default=10, help="untimed builds for the stage breakdown (0: skip)")
@@ -284,14 +304,14 @@ def main():
     import paper_1809_04424_amd as vr
 
     vr.lib()
+    if args.copy_calib:
+        _copy_calibration(torch)
     if args.workload == "batched512":
         _main_batched(vr, torch, args)
         return
     cloud = _workload(args.workload)
     pts = torch.from_numpy(cloud.points).to("cuda:0")
     torch.cuda.synchronize()
-    if args.copy_calib:
-        _copy_calibration(torch)
 
     el, counts, tri_ms = _time_builds(vr, torch, pts, cloud.thr, args.steps, args.warmup)
     n, K, T = counts
@@ -304,8 +324,7 @@ def main():
 
     alg = _alg_bytes(n, K, T, n * n)
     achieved = alg / (tri_ms * 1e-3) / 1e9 if tri_ms > 0 else 0.0
-    tr = TRAFFIC.get((args.workload, "k_tri_write"))
-    traffic = tr["bytes"] if tr and tr["src_sha"] == _src_sha("k_triangles.hip") else None
+    traffic = _traffic(args.workload)
     roofline = {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}
@@ -319,7 +338,7 @@ def main():
         a3 = _alg_bytes(cnt3[0], cnt3[1], cnt3[2], cnt3[0] ** 2)
         extra["mixture4000_r64_p10"] = {
             "value": s3 * 10 / e3, "unit": "simplices/s", "ms_per_step": 1e3 * e3 / 10,
-            "counts": list(cnt3), "tri_write_ms": round(t3, 5),
+            "counts": list(cnt3), "tri_write_ms": round(t3, 5), "tri_write_traffic": _traffic("mixture4000"),
             "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
             "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3) if args.breakdown_reps > 0 else {}}
         del p3
