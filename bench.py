@@ -63,20 +63,32 @@ def _workload(name):
 
 def _time_builds(vr, torch, pts, thr, steps, warmup):
     """Time `steps` whole builds; HIP events bracket only the triangle write
-    (on the build's stream), so its average launch duration is measured live."""
-    for _ in range(warmup):
-        vr.build(pts, thr).free()
+    (on the build's stream), so its average launch duration is measured live.
+    Each result is freed once the next build has been issued, as a caller
+    consuming results would; its events have completed by then."""
+    prev = None
+    for _ in range(max(warmup, 2)):  # two results alive at once, as in the timed loop
+        r = vr.build(pts, thr, timing="write")
+        if prev is not None:
+            prev.free()
+        prev = r
     torch.cuda.synchronize()
-    res = []
+    if prev is not None:
+        prev.free()
+    tw = []
+    prev = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        res.append(vr.build(pts, thr, timing="write"))
+        r = vr.build(pts, thr, timing="write")
+        if prev is not None:
+            tw.append(prev.stage_ms()["tri_write"])
+            prev.free()
+        prev = r
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tw = [r.stage_ms()["tri_write"] for r in res]
-    counts = res[0].counts
-    for r in res:
-        r.free()
+    tw.append(prev.stage_ms()["tri_write"])
+    counts = prev.counts
+    prev.free()
     torch.cuda.synchronize()
     return (t1 - t0), counts, sum(tw) / len(tw)
 
@@ -241,18 +253,28 @@ def _main_batched(vr, torch, args):
     pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
     thrs = [c.thr for c in clouds]
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        vr.build_batch(pts, thrs).free()
+    prev = None
+    for _ in range(max(args.warmup, 2)):  # two results alive at once, as in the timed loop
+        b = vr.build_batch(pts, thrs, timing="write")
+        if prev is not None:
+            prev.free()
+        prev = b
     torch.cuda.synchronize()
+    prev.free()
     tw = []
+    prev = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         b = vr.build_batch(pts, thrs, timing="write")
-        tw.append(b.stage_ms()["tri_write"])
-        counts = [it.counts for it in b]
-        b.free()
+        if prev is not None:
+            tw.append(prev.stage_ms()["tri_write"])
+            prev.free()
+        prev = b
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    tw.append(prev.stage_ms()["tri_write"])
+    counts = [it.counts for it in prev]
+    prev.free()
     n, K, T = (sum(c[i] for c in counts) for i in range(3))
     simp = n + K + T
     tri_ms = sum(tw) / len(tw)

@@ -165,7 +165,7 @@ VR_API int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t t
  * so each cloud's result is bit-identical to its own vr_build.  The key must
  * fit 32 bits: bits(255^2 d) + bits(count-1) <= 32 for VR_I8, so VR_I16 and
  * VR_I32 batches hold one cloud each (VR_E2BIG otherwise; split the batch).
- * Other limits of the whole batch: fewer than 2^24 vertices, fewer than 2^32
+ * Other limits of the whole batch: fewer than 2^24 vertices, fewer than 2^30
  * pairs and 2^31 kept edges (VR_E2BIG).  Each request keeps the per-cloud
  * limits of vr_build.  Same stream semantics and error behaviour as vr_build.
  */

@@ -7,8 +7,9 @@
 //                cloud (VALU), plus a per-cloud log-linear histogram used to
 //                find percentile thresholds
 //   k_pivot      per cloud, the histogram bucket holding the K-th distance
-//   k_select     compact the candidate edges in (cloud, pair) order
-//                (decoupled look-back) and histogram their radix digits
+//   k_sel_count, k_sel_scan, k_sel_write
+//                compact the candidate edges in (cloud, pair) order (count
+//                per tile, scan, write) and histogram their radix digits
 //   k_sort_pass  one stable 8-bit LSD pass (Onesweep: Adinets and Merrill,
 //                2022), skipped when every key shares the digit; keys are
 //                (cloud << qbits) | q, so clouds stay apart
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_dist(VrDev D) {
     if (over) atomicOr(&D.ctl->flags, 1u);
     if (need_hist) {
         __syncthreads();
-        uint32_t *gh = D.hist + (size_t)c * VR_NBUCKET;
+        uint32_t *gh = D.hist + ((size_t)c * D.hcopies + blockIdx.x % D.hcopies) * VR_NBUCKET;
         for (int b = threadIdx.x; b < VR_NBUCKET; b += VR_BLOCK)
             if (hist[b]) atomicAdd(&gh[b], hist[b]);
     }
@@ -136,163 +137,218 @@ void launch_dist(const VrDev &D, const void *points, hipStream_t s) {
 
 // -------------------------------------------------------------- k_pivot ----
 // Work-group c: the smallest bucket of cloud c whose cumulative count reaches
-// K_c; the candidates are then every pair at or below it (a superset of the
-// K_c smallest, as buckets are monotone in q).
-__global__ __launch_bounds__(VR_BLOCK) void k_pivot(VrDev D) {
-    __shared__ unsigned long long sh_w[VR_WAVES];
+// K_c; the candidates are then every pair below the end of that bucket (a
+// superset of the K_c smallest, as buckets are monotone in q).
+#define PIVOT_BLOCK 1024
+__global__ __launch_bounds__(PIVOT_BLOCK) void k_pivot(VrDev D) {
+    __shared__ uint32_t hb[VR_NBUCKET];
+    __shared__ unsigned long long sh_w[PIVOT_BLOCK / VR_WAVE];
     __shared__ uint32_t sh_pivot;
     const int c = blockIdx.x, t = threadIdx.x;
-    const uint32_t *h = D.hist + (size_t)c * VR_NBUCKET;
+    const uint32_t *h = D.hist + (size_t)c * D.hcopies * VR_NBUCKET;
     const unsigned long long K = (unsigned long long)D.cl[c].K;
-    const int per = (VR_NBUCKET + VR_BLOCK - 1) / VR_BLOCK;  // 7
-    unsigned long long loc = 0;
-    for (int b = t * per; b < min(VR_NBUCKET, (t + 1) * per); b++) loc += h[b];
-    unsigned long long tot;
-    const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
+    for (int b = t; b < VR_NBUCKET; b += PIVOT_BLOCK) hb[b] = hist_sum(h, VR_NBUCKET, D.hcopies, b);
     if (t == 0) sh_pivot = 0u;
     __syncthreads();
-    if (K > 0 && ex < K && K <= ex + loc) {
-        unsigned long long cum = ex;
-        for (int b = t * per; b < min(VR_NBUCKET, (t + 1) * per); b++) {
-            cum += h[b];
-            if (cum >= K) { sh_pivot = (uint32_t)b; break; }
-        }
+    // two buckets per thread, in order
+    const int b0 = 2 * t;
+    const uint32_t h0 = (b0 < VR_NBUCKET) ? hb[b0] : 0u, h1 = (b0 + 1 < VR_NBUCKET) ? hb[b0 + 1] : 0u;
+    const unsigned long long loc = (unsigned long long)h0 + h1;
+    unsigned long long inc = loc;
+#pragma unroll
+    for (int o = 1; o < VR_WAVE; o <<= 1) {
+        const unsigned long long y = __shfl_up(inc, o, VR_WAVE);
+        if ((t & 63) >= o) inc += y;
     }
+    const int w = t / VR_WAVE;
+    if ((t & 63) == 63) sh_w[w] = inc;
     __syncthreads();
-    if (t == 0) D.cs[c].pivot = sh_pivot;
+    unsigned long long ex = inc - loc;
+    for (int x = 0; x < w; x++) ex += sh_w[x];
+    if (K > 0 && ex < K && K <= ex + loc) sh_pivot = (ex + h0 >= K) ? (uint32_t)b0 : (uint32_t)(b0 + 1);
+    __syncthreads();
+    // candidates: every q below the end of the pivot bucket (none when K = 0)
+    if (t == 0) D.cs[c].qend = (K > 0) ? bucket_start(sh_pivot + 1u) : 0ull;
 }
 
 void launch_pivot(const VrDev &D, hipStream_t s) {
-    hipLaunchKernelGGL(k_pivot, dim3((unsigned)D.C), dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_pivot, dim3((unsigned)D.C), dim3(PIVOT_BLOCK), 0, s, D);
 }
 
-// ------------------------------------------------------------- k_select ----
-// A pair is a candidate when (full threshold) always, (count / fraction) its
-// bucket is at or below the cloud's pivot and the cloud keeps any edge, or
-// (distance) q < tau.  Candidates keep (cloud, pair) order; the first pair of
-// each cloud records where the cloud's candidates begin.
-__device__ __forceinline__ bool is_candidate(const VrDev &D, int c, uint32_t q) {
-    if (D.thr_kind == 0) return true;
+// -------------------------------------------------------------- select ----
+// A pair of cloud c is a candidate when q < qend(c): every pair (full
+// threshold), q < tau (distance threshold), or q below the end of the
+// cloud's pivot bucket (count / fraction threshold; a superset of the K_c
+// smallest, as buckets are monotone in q).  Candidates keep (cloud, pair)
+// order; the first pair of each cloud records where its candidates begin.
+__device__ __forceinline__ unsigned long long cloud_qend(const VrDev &D, int c) {
+    if (D.thr_kind == 0) return 1ull << 32;
     if (D.thr_kind == 3) {
         const long long tau = D.cl[c].thr_num;
-        return tau > 0xFFFFFFFFll || (long long)q < tau;
+        return tau > (1ll << 32) ? (1ull << 32) : (unsigned long long)tau;
     }
-    return D.cl[c].K > 0 && bucket_of(q) <= D.cs[c].pivot;
+    return D.cs[c].qend;
 }
 
-__global__ __launch_bounds__(VR_BLOCK) void k_select(VrDev D) {
+// The 8 pairs of thread t in 2048-pair tile `tile`: candidate flags, sort
+// keys (cloud << qbits | q), values (i << 16 | j), and the pairs that start
+// a cloud.  Returns the thread's candidate count.
+struct SelItems {
+    uint32_t kv[VR_ITEMS], vv[VR_ITEMS];
+    bool keep[VR_ITEMS], first[VR_ITEMS];
+    int cc[VR_ITEMS];
+};
+
+__device__ __forceinline__ uint32_t select_items(const VrDev &D, int tile, SelItems &I) {
+    const long long E = D.E;
+    const long long e0 = (long long)tile * VR_TILE + (long long)threadIdx.x * VR_ITEMS;
+    uint32_t q[VR_ITEMS];
+    if (e0 + VR_ITEMS <= E) {  // 8 aligned words: two 16-byte loads
+        const uint4 a = *(const uint4 *)(D.q + e0), b = *(const uint4 *)(D.q + e0 + 4);
+        q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w;
+        q[4] = b.x; q[5] = b.y; q[6] = b.z; q[7] = b.w;
+    } else {
+#pragma unroll
+        for (int m = 0; m < VR_ITEMS; m++) q[m] = (e0 + m < E) ? D.q[e0 + m] : 0u;
+    }
+    int c = 0, pi = 0, pj = 0, n = 2;
+    long long cstart = -1, cend = 0;
+    unsigned long long qend = 0;
+    if (e0 < E) {
+        c = cloud_of(e0, D.C, [&](int k) { return D.cl[k].pbase; });
+        n = D.cl[c].n;
+        cstart = D.cl[c].pbase;
+        cend = cstart + (long long)n * (n - 1) / 2;
+        qend = cloud_qend(D, c);
+        pair_of(e0 - cstart, n, &pi, &pj);
+    }
+    const uint32_t qb = (uint32_t)D.qbits;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int m = 0; m < VR_ITEMS; m++) {
+        const long long e = e0 + m;
+        const bool valid = e < E;
+        bool f = valid && e == cstart;
+        if (valid && e == cend) {  // next cloud (rare: every cloud of a batch has a pair)
+            c++;
+            n = D.cl[c].n;
+            cend += (long long)n * (n - 1) / 2;
+            qend = cloud_qend(D, c);
+            pi = 0;
+            pj = 1;
+            f = true;
+        }
+        const bool k = valid && (unsigned long long)q[m] < qend;
+        I.kv[m] = (qb >= 32) ? q[m] : (((uint32_t)c << qb) | q[m]);  // one cloud when q takes 32 bits
+        I.vv[m] = ((uint32_t)pi << 16) | (uint32_t)pj;
+        I.keep[m] = k;
+        I.first[m] = f;
+        I.cc[m] = c;
+        cnt += k ? 1u : 0u;
+        if (++pj == n) { pi++; pj = pi + 1; }
+    }
+    return cnt;
+}
+
+// Three launches, none of which waits on another work-group: the candidates
+// of every tile are counted, the counts are scanned by one work-group into
+// tile offsets, and every tile writes its candidates (reading q again).
+// Cross-XCD status polling and a shared tile ticket cost more than the
+// second read of q.
+__global__ __launch_bounds__(VR_BLOCK) void k_sel_count(VrDev D) {
     __shared__ uint32_t sh_w[VR_WAVES];
-    __shared__ int sh_tile;
-    __shared__ uint32_t sh_prefix;
+    SelItems I;
+    const uint32_t c = select_items(D, (int)blockIdx.x, I);
+    uint32_t tot;
+    (void)block_excl_scan<uint32_t>(c, sh_w, &tot);
+    if (threadIdx.x == 0) D.st_sel[blockIdx.x] = tot;
+}
+
+// One work-group: exclusive scan of the tile counts in place; the total is
+// the candidate count.
+#define SCAN_BLOCK 1024
+__global__ __launch_bounds__(SCAN_BLOCK) void k_sel_scan(VrDev D) {
+    __shared__ uint32_t sh_w[SCAN_BLOCK / VR_WAVE];
+    __shared__ uint32_t sh_carry;
+    const int ntiles = (int)D.ntile_E, t = threadIdx.x;
+    if (t == 0) sh_carry = 0u;
+    __syncthreads();
+    for (int base = 0; base < ntiles; base += SCAN_BLOCK) {
+        const int i = base + t;
+        const uint32_t v = (i < ntiles) ? D.st_sel[i] : 0u;
+        const uint32_t inc = wave_incl_scan_dpp(v);
+        const int w = t / VR_WAVE;
+        if ((t & 63) == 63) sh_w[w] = inc;
+        __syncthreads();
+        uint32_t off = sh_carry, tot = 0;
+        for (int x = 0; x < SCAN_BLOCK / VR_WAVE; x++) {
+            const uint32_t y = sh_w[x];
+            if (x < w) off += y;
+            tot += y;
+        }
+        if (i < ntiles) D.st_sel[i] = off + inc - v;
+        __syncthreads();
+        if (t == 0) sh_carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) D.ctl->n_cand = sh_carry;
+}
+
+__global__ __launch_bounds__(VR_BLOCK) void k_sel_write(VrDev D) {
+    __shared__ uint32_t sh_w[VR_WAVES];
     __shared__ uint32_t h8[VR_MAX_PASSES][VR_RADIX];
     VrCtl *ctl = D.ctl;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, tile = (int)blockIdx.x;
     for (int x = t; x < VR_MAX_PASSES * VR_RADIX; x += VR_BLOCK) (&h8[0][0])[x] = 0u;
-
-    const long long E = D.E;
-    const int ntiles = (int)D.ntile_E;
-    for (;;) {
-        const int tile = claim_tile(&ctl->ticket[0], &sh_tile);
-        if (tile >= ntiles) break;
-        const long long e0 = (long long)tile * VR_TILE + (long long)t * VR_ITEMS;
-        uint32_t qv[VR_ITEMS], kv[VR_ITEMS], vv[VR_ITEMS];
-        bool keep[VR_ITEMS], first[VR_ITEMS];
-        int cc[VR_ITEMS];
-        uint32_t cnt = 0;
-        int c = 0, pi = 0, pj = 0, n = 0;
-        long long le = 0, Ec = 0;
-        if (e0 < E) {
-            c = cloud_of(e0, D.C, [&](int k) { return D.cl[k].pbase; });
-            n = D.cl[c].n;
-            le = e0 - D.cl[c].pbase;
-            Ec = (long long)n * (n - 1) / 2;
-            pair_of(le, n, &pi, &pj);
-        }
+    // clear this tile's statuses for the first active radix pass
+    D.st_sort[0][(size_t)tile * VR_RADIX + t] = 0u;
+    SelItems I;
+    const uint32_t c = select_items(D, tile, I);
+    uint32_t tt;
+    const uint32_t ex = block_excl_scan<uint32_t>(c, sh_w, &tt);  // also orders the h8 clear
+    uint32_t p = D.st_sel[tile] + ex;
 #pragma unroll
-        for (int m = 0; m < VR_ITEMS; m++) {
-            const long long e = e0 + m;
-            bool k = false, f = false;
-            uint32_t q = 0;
-            if (e < E) {
-                if (le == Ec) {  // next cloud (every cloud of a batch has a pair)
-                    c++;
-                    n = D.cl[c].n;
-                    le = 0;
-                    Ec = (long long)n * (n - 1) / 2;
-                    pi = 0;
-                    pj = 1;
-                }
-                q = D.q[e];
-                k = is_candidate(D, c, q);
-                f = (le == 0);
-            }
-            qv[m] = q;
-            kv[m] = (D.qbits >= 32) ? q : (((uint32_t)c << D.qbits) | q);  // one cloud when q takes 32 bits
-            vv[m] = ((uint32_t)pi << 16) | (uint32_t)pj;
-            keep[m] = k;
-            first[m] = f;
-            cc[m] = c;
-            cnt += k ? 1u : 0u;
-            le++;
-            if (++pj == n) { pi++; pj = pi + 1; }
+    for (int m = 0; m < VR_ITEMS; m++) {
+        if (I.first[m]) D.cs[I.cc[m]].cand_base = p;
+        if (I.keep[m]) {
+            D.key[0][p] = I.kv[m];
+            D.val[0][p] = I.vv[m];
+            p++;
         }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<uint32_t>(cnt, sh_w, &tot);
-        if (t < VR_WAVE) {
-            uint32_t prefix = 0;
-            if (tile == 0) {
-                if (t == 0) st_store32(D.st_sel, st_pack32(VR_ST_INC, tot));
-            } else {
-                if (t == 0) st_store32(D.st_sel + tile, st_pack32(VR_ST_AGG, tot));
-                prefix = lookback32_wave(D.st_sel, tile);
-                if (t == 0) st_store32(D.st_sel + tile, st_pack32(VR_ST_INC, prefix + tot));
-            }
-            if (t == 0) {
-                sh_prefix = prefix;
-                if (tile == ntiles - 1) ctl->n_cand = prefix + tot;
-            }
-        }
-        // clear this tile's statuses for the first active radix pass
-        D.st_sort[0][(size_t)tile * VR_RADIX + t] = 0u;
-        __syncthreads();
-        uint32_t p = sh_prefix + ex;
-#pragma unroll
-        for (int m = 0; m < VR_ITEMS; m++) {
-            if (first[m]) D.cs[cc[m]].cand_base = p;
-            if (keep[m]) {
-                D.key[0][p] = kv[m];
-                D.val[0][p] = vv[m];
-                p++;
-            }
-        }
-        for (int ps = 0; ps < D.passes; ps++)
-#pragma unroll
-            for (int m = 0; m < VR_ITEMS; m++) match_add<8>(h8[ps], (kv[m] >> (8 * ps)) & 255u, keep[m]);
-        (void)qv;
     }
+    if (tt == 0) return;  // nothing to histogram (uniform over the work-group)
+    // digit histograms: low digits are spread, the top one (cloud and high
+    // bits of q) takes few values
+    for (int ps = 0; ps < D.passes - 1; ps++)
+#pragma unroll
+        for (int m = 0; m < VR_ITEMS; m++) spread_add(h8[ps], (I.kv[m] >> (8 * ps)) & 255u, I.keep[m]);
+#pragma unroll
+    for (int m = 0; m < VR_ITEMS; m++)
+        narrow_add<8>(h8[D.passes - 1], (I.kv[m] >> (8 * (D.passes - 1))) & 255u, I.keep[m]);
     __syncthreads();
+    uint32_t *gh = hist_copy(&ctl->hist8[0][0][0], VR_HIST8_STRIDE);
     for (int x = t; x < D.passes * VR_RADIX; x += VR_BLOCK) {
-        uint32_t v = (&h8[0][0])[x];
-        if (v) atomicAdd(&(&ctl->hist8[0][0])[x], v);
+        const uint32_t v = (&h8[0][0])[x];
+        if (v) atomicAdd(&gh[x], v);
     }
 }
 
 void launch_select(const VrDev &D, hipStream_t s) {
-    long long g = D.ntile_E;
-    if (g > 2048) g = 2048;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_select, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
+    const dim3 grid((unsigned)(D.ntile_E > 0 ? D.ntile_E : 1));
+    hipLaunchKernelGGL(k_sel_count, grid, dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(SCAN_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_sel_write, grid, dim3(VR_BLOCK), 0, s, D);
 }
 
 // Active radix passes: a pass whose digit is the same for every key is the
 // identity and is skipped.  Returns the number of active passes before
 // `upto` and sets *active for pass `upto` (when upto < passes).
-__device__ __forceinline__ int active_before(const uint32_t *hist, int passes, int upto, bool *active) {
+__device__ __forceinline__ int active_before(const uint32_t *hist, int stride, int passes, int upto, bool *active) {
     __shared__ int sh_nz[VR_MAX_PASSES];
     if (threadIdx.x < VR_MAX_PASSES) sh_nz[threadIdx.x] = 0;
     __syncthreads();
     for (int x = threadIdx.x; x < passes * VR_RADIX; x += VR_BLOCK)
-        if (hist[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+        if (hist_sum(hist, stride, VR_HCOPY, x)) atomicAdd(&sh_nz[x / VR_RADIX], 1);
     __syncthreads();
     int a = 0;
     for (int p = 0; p < upto && p < passes; p++) a += (sh_nz[p] > 1) ? 1 : 0;
@@ -305,7 +361,8 @@ SortJob edge_sort_job(const VrDev &D) {
     SortJob J;
     J.key[0] = D.key[0]; J.key[1] = D.key[1];
     J.val[0] = D.val[0]; J.val[1] = D.val[1];
-    J.hist = &D.ctl->hist8[0][0];
+    J.hist = &D.ctl->hist8[0][0][0];
+    J.hist_stride = VR_HIST8_STRIDE;
     J.ticket = &D.ctl->ticket[1];
     J.st[0] = D.st_sort[0]; J.st[1] = D.st_sort[1];
     J.count = &D.ctl->n_cand;
@@ -317,7 +374,8 @@ SortJob star_sort_job(const VrDev &D) {
     SortJob J;
     J.key[0] = D.ikey[0]; J.key[1] = D.ikey[1];
     J.val[0] = D.ival[0]; J.val[1] = D.ival[1];
-    J.hist = &D.ctl->hinc[0][0];
+    J.hist = &D.ctl->hinc[0][0][0];
+    J.hist_stride = VR_HINC_STRIDE;
     J.ticket = &D.ctl->ticket[6];
     J.st[0] = D.ist[0]; J.st[1] = D.ist[1];
     J.count = &D.ctl->n_inc;
@@ -330,7 +388,7 @@ SortJob star_sort_job(const VrDev &D) {
 // order (8 ballots per 64 keys), the work-group combines the waves, one
 // look-back per digit gives the tile's global offsets, and the tile is
 // scattered through LDS so equal digits leave as contiguous runs.
-__global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass) {
+__global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int S) {
     __shared__ uint32_t s_whist[VR_WAVES][VR_RADIX];
     __shared__ uint32_t s_tstart[VR_RADIX];
     __shared__ uint32_t s_gpre[VR_RADIX];
@@ -339,7 +397,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass) {
     __shared__ uint32_t sh_w[VR_WAVES];
     __shared__ int sh_tile;
     bool active = false;
-    const int a = active_before(J.hist, J.passes, pass, &active);
+    const int a = active_before(J.hist, J.hist_stride, J.passes, pass, &active);
     if (!active) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const uint32_t Kc = *J.count;
@@ -354,90 +412,96 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass) {
 
     // global start of digit t
     uint32_t tot;
-    const uint32_t gstart = block_excl_scan<uint32_t>(J.hist[pass * VR_RADIX + t], sh_w, &tot);
+    const uint32_t gstart =
+        block_excl_scan<uint32_t>(hist_sum(J.hist, J.hist_stride, VR_HCOPY, pass * VR_RADIX + t), sh_w, &tot);
 
     for (;;) {
-        const int tile = claim_tile(&J.ticket[pass], &sh_tile);
-        if (tile >= ntiles) break;
-        for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = 0u;
-        __syncthreads();
-        uint32_t kk[VR_ITEMS], vv[VR_ITEMS], rk[VR_ITEMS];
-        const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
+        const int t0 = claim_tiles(&J.ticket[pass], S, &sh_tile);
+        if (t0 >= ntiles) break;
+        for (int tile = t0; tile < min(t0 + S, ntiles); tile++) {
+            if (tile > t0) __syncthreads();  // LDS of the previous tile is reused
+            for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = 0u;
+            __syncthreads();
+            uint32_t kk[VR_ITEMS], vv[VR_ITEMS], rk[VR_ITEMS];
+            const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
 #pragma unroll
-        for (int it = 0; it < VR_ITEMS; it++) {
-            const long long idx = base + (long long)it * VR_WAVE + lane;
-            const bool valid = idx < (long long)Kc;
-            const uint32_t k = valid ? ksrc[idx] : 0u;
-            kk[it] = k;
-            vv[it] = valid ? vsrc[idx] : 0u;
-            const uint32_t dg = (k >> shift) & 255u;
-            unsigned long long peers = ballot64(valid);
-#pragma unroll
-            for (int b = 0; b < VR_RADIX_BITS; b++) {
-                const unsigned long long m = ballot64((dg >> b) & 1u);
-                peers &= ((dg >> b) & 1u) ? m : ~m;
-            }
-            uint32_t before = 0;
-            if (valid) before = s_whist[w][dg];
-            const uint32_t r = before + (uint32_t)__popcll(peers & lanemask_lt());
-            rk[it] = r;
-            if (valid && (peers & lanemask_lt()) == 0ull) s_whist[w][dg] = before + (uint32_t)__popcll(peers);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-        __syncthreads();
-        uint32_t wpre[VR_WAVES];
-        uint32_t tc = 0;
-#pragma unroll
-        for (int x = 0; x < VR_WAVES; x++) { wpre[x] = tc; tc += s_whist[x][t]; }
-        uint32_t ttot;
-        const uint32_t tstart = block_excl_scan<uint32_t>(tc, sh_w, &ttot);
-        s_tstart[t] = tstart;
-        uint32_t prev = 0;
-        if (tile == 0) {
-            st_store32(st + t, st_pack32(VR_ST_INC, tc));
-        } else {
-            st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_AGG, tc));
-            prev = lookback32(st + t, tile, VR_RADIX);
-            st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_INC, prev + tc));
-        }
-        s_gpre[t] = gstart + prev;
-        st_next[(size_t)tile * VR_RADIX + t] = 0u;
-        __syncthreads();
-#pragma unroll
-        for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = wpre[x];
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < VR_ITEMS; it++) {
-            const long long idx = base + (long long)it * VR_WAVE + lane;
-            if (idx < (long long)Kc) {
-                const uint32_t dg = (kk[it] >> shift) & 255u;
-                const uint32_t lp = s_tstart[dg] + s_whist[w][dg] + rk[it];
-                s_key[lp] = kk[it];
-                s_val[lp] = vv[it];
-            }
-        }
-        __syncthreads();
-        const uint32_t valid_n = (uint32_t)min((long long)VR_TILE, (long long)Kc - (long long)tile * VR_TILE);
-#pragma unroll
-        for (int m = 0; m < VR_ITEMS; m++) {
-            const uint32_t lp = (uint32_t)t + (uint32_t)m * VR_BLOCK;
-            if (lp < valid_n) {
-                const uint32_t k = s_key[lp];
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const long long idx = base + (long long)it * VR_WAVE + lane;
+                const bool valid = idx < (long long)Kc;
+                const uint32_t k = valid ? ksrc[idx] : 0u;
+                kk[it] = k;
+                vv[it] = valid ? vsrc[idx] : 0u;
                 const uint32_t dg = (k >> shift) & 255u;
-                const uint32_t gp = s_gpre[dg] + (lp - s_tstart[dg]);
-                kdst[gp] = k;
-                vdst[gp] = s_val[lp];
+                unsigned long long peers = ballot64(valid);
+#pragma unroll
+                for (int b = 0; b < VR_RADIX_BITS; b++) {
+                    const unsigned long long m = ballot64((dg >> b) & 1u);
+                    peers &= ((dg >> b) & 1u) ? m : ~m;
+                }
+                uint32_t before = 0;
+                if (valid) before = s_whist[w][dg];
+                const uint32_t r = before + (uint32_t)__popcll(peers & lanemask_lt());
+                rk[it] = r;
+                if (valid && (peers & lanemask_lt()) == 0ull) s_whist[w][dg] = before + (uint32_t)__popcll(peers);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            uint32_t wpre[VR_WAVES];
+            uint32_t tc = 0;
+#pragma unroll
+            for (int x = 0; x < VR_WAVES; x++) { wpre[x] = tc; tc += s_whist[x][t]; }
+            uint32_t ttot;
+            const uint32_t tstart = block_excl_scan<uint32_t>(tc, sh_w, &ttot);
+            s_tstart[t] = tstart;
+            uint32_t prev = 0;
+            if (tile == 0) {
+                st_store32(st + t, st_pack32(VR_ST_INC, tc));
+            } else {
+                st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_AGG, tc));
+                prev = lookback32(st + t, tile, VR_RADIX);
+                st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_INC, prev + tc));
+            }
+            s_gpre[t] = gstart + prev;
+            st_next[(size_t)tile * VR_RADIX + t] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = wpre[x];
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const long long idx = base + (long long)it * VR_WAVE + lane;
+                if (idx < (long long)Kc) {
+                    const uint32_t dg = (kk[it] >> shift) & 255u;
+                    const uint32_t lp = s_tstart[dg] + s_whist[w][dg] + rk[it];
+                    s_key[lp] = kk[it];
+                    s_val[lp] = vv[it];
+                }
+            }
+            __syncthreads();
+            const uint32_t valid_n = (uint32_t)min((long long)VR_TILE, (long long)Kc - (long long)tile * VR_TILE);
+#pragma unroll
+            for (int m = 0; m < VR_ITEMS; m++) {
+                const uint32_t lp = (uint32_t)t + (uint32_t)m * VR_BLOCK;
+                if (lp < valid_n) {
+                    const uint32_t k = s_key[lp];
+                    const uint32_t dg = (k >> shift) & 255u;
+                    const uint32_t gp = s_gpre[dg] + (lp - s_tstart[dg]);
+                    kdst[gp] = k;
+                    vdst[gp] = s_val[lp];
+                }
             }
         }
     }
 }
 
 void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s) {
+    // one tile per claim: a tile's aggregate is published as soon as it is
+    // ranked, which tiles claimed in batches would delay
     long long g = max_tiles;
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass);
+    hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass, 1);
 }
 
 // -------------------------------------------------------------- k_edges ----
@@ -448,7 +512,7 @@ void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream
 __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
     __shared__ uint32_t h[3][VR_RADIX];
     VrCtl *ctl = D.ctl;
-    const int a = active_before(&ctl->hist8[0][0], D.passes, VR_MAX_PASSES, nullptr);
+    const int a = active_before(&ctl->hist8[0][0][0], VR_HIST8_STRIDE, D.passes, VR_MAX_PASSES, nullptr);
     const uint32_t *__restrict__ kf = D.key[a & 1];
     const uint32_t *__restrict__ vf = D.val[a & 1];
     const long long K = (D.thr_kind == 3) ? (long long)ctl->n_cand : D.K_host;
@@ -466,7 +530,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
         for (long long x = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; x < words; x += (long long)gridDim.x * VR_BLOCK)
             D.ist[0][x] = 0u;
     }
-    const long long Kr = (K + VR_BLOCK - 1) / VR_BLOCK * VR_BLOCK;  // whole waves take part in match_add
+    const long long Kr = (K + VR_BLOCK - 1) / VR_BLOCK * VR_BLOCK;  // whole waves take part in narrow_add
     for (long long g = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; g < Kr; g += (long long)gridDim.x * VR_BLOCK) {
         const bool ok = g < K;
         uint32_t vi = 0, vj = 0;
@@ -487,20 +551,25 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
             }
         }
         if (D.tri) {
+            // vertex digits: the low ones are spread, the top one takes few values
 #pragma unroll
-            for (int ps = 0; ps < 3; ps++) {
-                if (ps < D.spasses) {
-                    match_add<8>(h[ps], (vi >> (8 * ps)) & 255u, ok);
-                    match_add<8>(h[ps], (vj >> (8 * ps)) & 255u, ok);
+            for (int ps = 0; ps < 2; ps++) {
+                if (ps < D.spasses - 1) {
+                    spread_add(h[ps], (vi >> (8 * ps)) & 255u, ok);
+                    spread_add(h[ps], (vj >> (8 * ps)) & 255u, ok);
                 }
             }
+            const int top = D.spasses - 1;
+            narrow_add<8>(h[top], (vi >> (8 * top)) & 255u, ok);
+            narrow_add<8>(h[top], (vj >> (8 * top)) & 255u, ok);
         }
     }
     if (D.tri) {
         __syncthreads();
+        uint32_t *gh = hist_copy(&ctl->hinc[0][0][0], VR_HINC_STRIDE);
         for (int x = threadIdx.x; x < 3 * VR_RADIX; x += VR_BLOCK) {
             const uint32_t c = (&h[0][0])[x];
-            if (c) atomicAdd(&(&ctl->hinc[0][0])[x], c);
+            if (c) atomicAdd(&gh[x], c);
         }
     }
 }

@@ -93,12 +93,12 @@ __global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(VrDev D, int dpad) {
                 qq = (uint32_t)(ni[il] + nj[jl] - 2 * acc[cb][ii]);
                 q[row_start(i, n) + (j - i - 1)] = qq;
             }
-            if (need_hist) match_add<11>(hist, bucket_of(qq), ok);
+            if (need_hist) spread_add(hist, bucket_of(qq), ok);
         }
     }
     if (need_hist) {
         __syncthreads();
-        uint32_t *gh = D.hist + (size_t)c * VR_NBUCKET;
+        uint32_t *gh = D.hist + ((size_t)c * D.hcopies + blockIdx.x % D.hcopies) * VR_NBUCKET;
         for (int b = t; b < VR_NBUCKET; b += VR_BLOCK)
             if (hist[b]) atomicAdd(&gh[b], hist[b]);
     }

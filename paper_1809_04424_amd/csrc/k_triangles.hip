@@ -35,7 +35,7 @@ __device__ __forceinline__ int star_parity(const VrDev &D) {
     if (threadIdx.x < 3) sh_nz[threadIdx.x] = 0;
     __syncthreads();
     for (int x = threadIdx.x; x < D.spasses * VR_RADIX; x += VR_BLOCK)
-        if ((&D.ctl->hinc[0][0])[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+        if (hist_sum(&D.ctl->hinc[0][0][0], VR_HINC_STRIDE, VR_HCOPY, x)) atomicAdd(&sh_nz[x / VR_RADIX], 1);
     __syncthreads();
     const int a = (sh_nz[0] > 1 ? 1 : 0) + (sh_nz[1] > 1 ? 1 : 0) + (sh_nz[2] > 1 ? 1 : 0);
     __syncthreads();
@@ -73,6 +73,11 @@ __global__ __launch_bounds__(VR_BLOCK) void k_star(VrDev D) {
     }
 }
 
+// Neighbour-ordered stars are padded: vertex v's entries start at
+// start[v] + 64 v and are followed by 64 sentinel entries.
+#define STAR_SENTINEL 0xFFFF0000u  // neighbour 0, position 0xFFFF
+__device__ __forceinline__ uint32_t star_k_base(uint32_t s0, long long v) { return s0 + 64u * (uint32_t)v; }
+
 // -------------------------------------------------------------- k_kstar ----
 // One work-group per vertex v (n <= 8192, so its <= 128 bitset words fit one
 // pass of 256 threads).
@@ -97,11 +102,15 @@ __global__ __launch_bounds__(VR_BLOCK) void k_kstar(VrDev D) {
     unsigned long long word = (t < W) ? bits[t] : 0ull;
     uint32_t tot;
     uint32_t q = block_excl_scan<uint32_t>((uint32_t)__popcll(word), sh_w, &tot);
+    uint32_t *sk = D.star_k + star_k_base(s0, vg);
     while (word) {
         const uint32_t k = (uint32_t)(t * 64 + __ffsll((long long)word) - 1);
-        D.star_k[s0 + q++] = k | ((uint32_t)P[k] << 16);
+        sk[q++] = k | ((uint32_t)P[k] << 16);
         word &= word - 1ull;
     }
+    // 64 sentinels after the star: position 0xFFFF fails every prefix test,
+    // so a piece may run past the star's end without a bounds test
+    if (t < VR_WAVE) sk[(s1 - s0) + t] = STAR_SENTINEL;
 }
 
 void launch_star(const VrDev &D, hipStream_t s) {
@@ -176,6 +185,7 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
             const uint32_t db = D.start[vb + b + 1] - sb, da = s1 - s0;
             owned = db < da || (db == da && (uint32_t)a < b);
             len = db;
+            sb = star_k_base(sb, vb + b);
         } else {
             owned = pb < x || (pb == x && (uint32_t)a < b);
             len = pb;
@@ -242,6 +252,16 @@ __device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T
     }
 }
 
+// As issue(), for a padded neighbour-ordered star: a piece's lanes past len
+// read sentinels, so indices need no clamp.
+__device__ __forceinline__ void issue_padded(const uint32_t *__restrict__ src, uint32_t len,
+                                             uint32_t (&kk)[VR_PIECES]) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < VR_PIECES; j++)
+        if ((uint32_t)(j * VR_WAVE) < len) kk[j] = src[(uint32_t)(j * VR_WAVE) + lane];
+}
+
 // ----------------------------------------------------------- k_tri_count ----
 __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
     extern __shared__ uint32_t lds[];
@@ -282,13 +302,13 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
                         if ((uint32_t)(j * VR_WAVE) < len) {  // whole pieces past len are skipped
                             const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
                             const bool hit = (y < len) & ((uint32_t)Pa[kA[j]] < xa);
-                            c += (uint32_t)__popcll(ballot64(hit));
+                            c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
                         }
                     }
                     for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                         const uint32_t y = y0 + (uint32_t)lane;
                         const uint32_t k = D.star_nbr[rl(vsb, el) + (y < len ? y : len - 1u)];
-                        c += (uint32_t)__popcll(ballot64((y < len) & ((uint32_t)Pa[k] < xa)));
+                        c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((y < len) & ((uint32_t)Pa[k] < xa)));
                     }
                 }
                 if (lane == el) mycnt = c;
@@ -314,7 +334,7 @@ void launch_tri_count(const VrDev &D, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- k_scan ----
-__global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
+__global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D, int S) {
     __shared__ unsigned long long sh_w[VR_WAVES];
     __shared__ unsigned long long sh_prefix;
     __shared__ int sh_tile;
@@ -325,41 +345,44 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D) {
     if (D.C == 1 && ntiles == 0 && blockIdx.x == 0 && t == 0)
         publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, 0ull);
     for (;;) {
-        const int tile = claim_tile(&ctl->ticket[5], &sh_tile);
-        if (tile >= ntiles) break;
-        const long long i0 = (long long)tile * VR_TILE + (long long)t * VR_ITEMS;
-        uint32_t c[VR_ITEMS];
-        unsigned long long loc = 0;
+        const int t0 = claim_tiles(&ctl->ticket[5], S, &sh_tile);
+        if (t0 >= ntiles) break;
+        for (int tile = t0; tile < min(t0 + S, ntiles); tile++) {
+            if (tile > t0) __syncthreads();  // sh_prefix and sh_w are reused
+            const long long i0 = (long long)tile * VR_TILE + (long long)t * VR_ITEMS;
+            uint32_t c[VR_ITEMS];
+            unsigned long long loc = 0;
 #pragma unroll
-        for (int m = 0; m < VR_ITEMS; m++) {
-            c[m] = (i0 + m < K) ? D.cnt[i0 + m] : 0u;
-            loc += c[m];
-        }
-        unsigned long long tot;
-        const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
-        if (t < VR_WAVE) {
-            unsigned long long prefix = 0;
-            if (tile == 0) {
-                if (t == 0) st_store64(D.st_scan, st_pack64(VR_ST_INC, tot));
-            } else {
-                if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_AGG, tot));
-                prefix = lookback64_wave(D.st_scan, tile);
-                if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_INC, prefix + tot));
+            for (int m = 0; m < VR_ITEMS; m++) {
+                c[m] = (i0 + m < K) ? D.cnt[i0 + m] : 0u;
+                loc += c[m];
             }
-            if (t == 0) {
-                sh_prefix = prefix;
-                if (tile == ntiles - 1) {
-                    ctl->n_tri = prefix + tot;
-                    if (D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
+            unsigned long long tot;
+            const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
+            if (t < VR_WAVE) {
+                unsigned long long prefix = 0;
+                if (tile == 0) {
+                    if (t == 0) st_store64(D.st_scan, st_pack64(VR_ST_INC, tot));
+                } else {
+                    if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_AGG, tot));
+                    prefix = lookback64_wave(D.st_scan, tile);
+                    if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_INC, prefix + tot));
+                }
+                if (t == 0) {
+                    sh_prefix = prefix;
+                    if (tile == ntiles - 1) {
+                        ctl->n_tri = prefix + tot;
+                        if (D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
+                    }
                 }
             }
-        }
-        __syncthreads();
-        unsigned long long o = sh_prefix + ex;
+            __syncthreads();
+            unsigned long long o = sh_prefix + ex;
 #pragma unroll
-        for (int m = 0; m < VR_ITEMS; m++) {
-            if (i0 + m < K) D.off[i0 + m] = o;
-            o += c[m];
+            for (int m = 0; m < VR_ITEMS; m++) {
+                if (i0 + m < K) D.off[i0 + m] = o;
+                o += c[m];
+            }
         }
     }
 }
@@ -368,7 +391,7 @@ void launch_scan(const VrDev &D, long long Kmax, hipStream_t s) {
     long long g = (Kmax + VR_TILE - 1) / VR_TILE;
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D, 1);  // one tile per claim
 }
 
 // ------------------------------------------------------ k_cloud_publish ----
@@ -466,32 +489,26 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                 voff = D.off[vr];
             }
             uint32_t kA[VR_PIECES], kB[VR_PIECES];
-            issue<uint32_t>(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
+            issue_padded(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
             for (int el = 0; el < ne; el++) {
-                if (el + 1 < ne) issue<uint32_t>(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), kB);
+                if (el + 1 < ne) issue_padded(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), kB);
                 const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
                 const uint32_t r = rl(vr, el) - kb;  // local rank within the cloud
                 unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
                                                  rl((uint32_t)voff, el));
-                // key = (r << 39) | (sorted triple), split into 32-bit halves
+                // key = (r << 39) | (x0 << 26) | (x1 << 13) | x2 with x0 < x1 < x2 the
+                // sorted triple {lo, hi, k}; k differs from both endpoints
                 const uint32_t lo = min((uint32_t)a, b), hi = max((uint32_t)a, b);
-                const uint32_t rh = r << 7;                      // bits 39.. of the key, in the high word
-                const uint32_t below_lo = (lo << 13) | hi;       // (k, lo, hi): k<<26 added per lane
-                const uint32_t mid_lo = (lo << 26) | hi;         // (lo, k, hi): k<<13
-                const uint32_t mid_hi = rh | (lo >> 6);
-                const uint32_t above_lo = (lo << 26) | (hi << 13);  // (lo, hi, k): k
+                const uint32_t rh = r << 7;  // bits 39.. of the key, in the high word
                 // one 64-entry piece of the partner's neighbour-ordered star
-                auto piece = [&](uint32_t v, uint32_t y) {
+                // (lanes past the star read sentinels, which never hit)
+                auto piece = [&](uint32_t v) {
                     const uint32_t k = v & 0xFFFFu, pk = v >> 16;
-                    const bool hit = (y < len) & (pk < pb) & ((uint32_t)Pa[k] < xa);
-                    const unsigned long long m = ballot64(hit);
-                    // all three candidates first, then selects (no divergent branches)
-                    const uint32_t c_below = below_lo | (k << 26), c_mid = mid_lo | (k << 13), c_above = above_lo | k;
-                    const uint32_t h_below = rh | (k >> 6);
-                    const bool blw = k < lo, abv = k >= hi;
-                    const uint32_t c_up = abv ? c_above : c_mid;
-                    const uint32_t klo = blw ? c_below : c_up;
-                    const uint32_t khi = blw ? h_below : mid_hi;
+                    const bool hit = (pk < pb) & ((uint32_t)Pa[k] < xa);
+                    const unsigned long long m = __builtin_amdgcn_ballot_w64(hit);
+                    const uint32_t x0 = min(lo, k), x2 = max(hi, k), x1 = max(lo, min(hi, k));
+                    const uint32_t klo = (x0 << 26) | (x1 << 13) | x2;
+                    const uint32_t khi = rh | (x0 >> 6);
                     const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                     // streaming store: keeps the stars, not the output, in L2
                     if (hit) __builtin_nontemporal_store(((unsigned long long)khi << 32) | klo, dst + at);
@@ -499,11 +516,9 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                 };
 #pragma unroll
                 for (int j = 0; j < VR_PIECES; j++)
-                    if ((uint32_t)(j * VR_WAVE) < len) piece(kA[j], (uint32_t)(j * VR_WAVE + lane));
-                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
-                    const uint32_t y = y0 + (uint32_t)lane;
-                    piece(D.star_k[rl(vsb, el) + (y < len ? y : len - 1u)], y);
-                }
+                    if ((uint32_t)(j * VR_WAVE) < len) piece(kA[j]);
+                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE)
+                    piece(D.star_k[rl(vsb, el) + y0 + (uint32_t)lane]);
 #pragma unroll
                 for (int j = 0; j < VR_PIECES; j++) kA[j] = kB[j];
             }

@@ -45,6 +45,39 @@ struct Alloc {
     }
 };
 
+// Stage events are reused across builds: creating and destroying a set of
+// them costs more than all the kernels of a small build.
+struct EventPool {
+    std::mutex mu;
+    std::vector<std::pair<int, hipEvent_t>> free_;  // (device, event)
+
+    hipEvent_t get(int dev) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            for (size_t i = free_.size(); i-- > 0;)
+                if (free_[i].first == dev) {
+                    hipEvent_t e = free_[i].second;
+                    free_.erase(free_.begin() + (long)i);
+                    return e;
+                }
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+    void put(int dev, hipEvent_t e) {
+        std::lock_guard<std::mutex> g(mu);
+        free_.emplace_back(dev, e);
+    }
+};
+EventPool &event_pool() {
+    static EventPool *p = new EventPool();  // never destroyed, like the device cache
+    return *p;
+}
+
 // The output block and stage events of one build, shared by its views.
 struct Owner {
     void *block = nullptr;
@@ -52,6 +85,7 @@ struct Owner {
     vr_allocator alloc{};
     bool has_alloc = false;
     bool timing = false;
+    int dev = 0;
     hipEvent_t ev[ST_N + 1] = {};
     bool ev_used[ST_N + 1] = {};
 
@@ -60,8 +94,9 @@ struct Owner {
         A.put(block, block_bytes);
         block = nullptr;
         for (int i = 0; i <= ST_N; i++) {
-            if (ev[i]) (void)hipEventDestroy(ev[i]);
+            if (ev[i]) event_pool().put(dev, ev[i]);
             ev[i] = nullptr;
+            ev_used[i] = false;
         }
         timing = false;
     }
@@ -169,6 +204,13 @@ struct Plan {
     size_t total;
 };
 
+// Copies of each cloud's distance histogram: a single cloud's tiles all add
+// to one histogram, a batch spreads over its clouds already.
+int hist_copies(long long C) {
+    const long long h = VR_HCOPY / (C > 0 ? C : 1);
+    return h < 1 ? 1 : (int)h;
+}
+
 // C clouds with V vertices and E pairs in all; Kmax bounds the kept edges.
 Plan plan(long long C, long long V, long long E, long long Kmax, bool hist, bool tri) {
     Plan P{};
@@ -181,7 +223,7 @@ Plan plan(long long C, long long V, long long E, long long Kmax, bool hist, bool
     o = (o + 15) & ~(size_t)15;
     P.off_stscan = o; o += 8 * (size_t)(ntK > 0 ? ntK : 1);
     P.off_stsel = o; o += sizeof(uint32_t) * (size_t)(ntE > 0 ? ntE : 1);
-    P.off_hist = o; if (hist) o += 4 * (size_t)VR_NBUCKET * (size_t)C;
+    P.off_hist = o; if (hist) o += 4 * (size_t)VR_NBUCKET * (size_t)C * (size_t)hist_copies(C);
     P.zero_bytes = (o + 3) & ~(size_t)3;
     o = align_up(o);
     P.off_cl = o; o = align_up(o + sizeof(VrCloud) * (size_t)C);
@@ -204,7 +246,7 @@ Plan plan(long long C, long long V, long long E, long long Kmax, bool hist, bool
         P.off_ist1 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntI > 0 ? ntI : 1));
         P.off_star_r = o; o = align_up(o + 8 * (size_t)Kmax);
         P.off_star_nbr = o; o = align_up(o + 4 * (size_t)Kmax);
-        P.off_star_k = o; o = align_up(o + 8 * (size_t)Kmax);
+        P.off_star_k = o; o = align_up(o + 4 * (2 * (size_t)Kmax + 64 * (size_t)V));  // padded stars
         P.off_start = o; o = align_up(o + 4 * (size_t)(V + 1));
         P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
@@ -309,9 +351,10 @@ int shape_of(const vr_request *reqs, long long count, Shape &S) {
     S.cbits = bits_of((unsigned long long)(S.C - 1));
     S.Khost = S.sq ? -1 : Ksum;
     S.Kmax = (S.Khost >= 0) ? S.Khost : S.E;
-    // sort keys (cloud, q) in 32 bits; vertices in 24 bits (three star
-    // passes); incidence ids 2g+s in 32 bits
-    if (S.qbits + S.cbits > 32 || S.E > 0xFFFFFFFFll || S.V >= (1ll << 24) || S.Kmax > 0x7FFFFFFFll)
+    // sort keys (cloud, q) in 32 bits; candidate counts in the 30-bit
+    // look-back statuses; vertices in 24 bits (three star passes);
+    // incidence ids 2g+s in 32 bits
+    if (S.qbits + S.cbits > 32 || S.E >= (1ll << 30) || S.V >= (1ll << 24) || S.Kmax > 0x7FFFFFFFll)
         return VR_E2BIG;
     return VR_OK;
 }
@@ -350,15 +393,12 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         (void)hipGetLastError();
         return code;
     };
-    if (timing) {
-        own.timing = true;
-        for (int i = 0; i <= ST_N; i++)
-            if (hipEventCreate(&own.ev[i]) != hipSuccess) return fail(VR_EHIP, nullptr, 0);
-    }
+    own.timing = timing;
+    own.dev = dev;
     auto mark = [&](int i) {
         if (timing_all || (timing && (i == ST_WRITE || i == ST_EMIT))) {
-            (void)hipEventRecord(own.ev[i], s);
-            own.ev_used[i] = true;
+            if (!own.ev[i]) own.ev[i] = event_pool().get(dev);
+            if (own.ev[i] && hipEventRecord(own.ev[i], s) == hipSuccess) own.ev_used[i] = true;
         }
     };
     if (!g_host.mailbox()) return fail(VR_ENOMEM, nullptr, 0);
@@ -416,6 +456,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.st_scan = (unsigned long long *)(ws + P.off_stscan);
     D.st_sel = (uint32_t *)(ws + P.off_stsel);
     D.hist = (uint32_t *)(ws + P.off_hist);
+    D.hcopies = hist_copies(C);
     D.cl = (const VrCloud *)(ws + P.off_cl);
     D.cs = (VrCloudState *)(ws + P.off_cs);
     D.q = (uint32_t *)(ws + P.off_q);

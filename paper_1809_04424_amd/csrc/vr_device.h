@@ -22,19 +22,27 @@
 #define VR_ST_AGG 1u
 #define VR_ST_INC 2u
 
+// Global histograms that every work-group adds to are kept in VR_HCOPY
+// copies, a work-group adding to copy blockIdx % VR_HCOPY, and summed by
+// their readers: device-scope atomics on one address serialise across the
+// XCDs, and a histogram flushed by thousands of work-groups would wait on
+// them.
+#define VR_HCOPY 32
+
 // Control block in device memory, zeroed at the start of every build.
 struct VrCtl {
-    uint32_t ticket[16];            // tile tickets: 0 select, 1..4 edge sort, 5 scan, 6..8 star sort
+    uint32_t ticket[16];            // tile tickets: 1..4 edge sort, 5 scan, 6..8 star sort
     uint32_t done;                  // finished work-groups of the per-cloud publisher
     uint32_t flags;                 // bit 0: a squared distance overflowed 32 bits
     uint32_t n_cand;                // candidates kept by the select pass
     uint32_t n_kept;                // K
     uint32_t n_inc;                 // 2K vertex incidences
     unsigned long long n_tri;       // T
-    uint32_t hist8[VR_MAX_PASSES][VR_RADIX];  // digit histograms of the edge candidates
-    uint32_t hinc[3][VR_RADIX];     // digit histograms of the incidence vertices
-    uint32_t bucket[VR_NBUCKET];    // log-linear histogram of all squared distances
+    uint32_t hist8[VR_HCOPY][VR_MAX_PASSES][VR_RADIX];  // digit histograms of the edge candidates
+    uint32_t hinc[VR_HCOPY][3][VR_RADIX];               // digit histograms of the incidence vertices
 };
+#define VR_HIST8_STRIDE (VR_MAX_PASSES * VR_RADIX)
+#define VR_HINC_STRIDE (3 * VR_RADIX)
 
 // Host-pinned mailbox: the end of phase 1 publishes the counts here; the
 // host polls `seq` instead of synchronising the stream.
@@ -125,6 +133,28 @@ __device__ __forceinline__ void match_add(uint32_t *hist, uint32_t bin, bool val
     if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&hist[bin], (uint32_t)__popcll(peers));
 }
 
+// Add 1 to hist[bin] for every lane with `valid` when bins are spread, so
+// that few lanes of a wave share one: a plain LDS atomic per lane.
+__device__ __forceinline__ void spread_add(uint32_t *hist, uint32_t bin, bool valid) {
+    if (valid) atomicAdd(&hist[bin], 1u);
+}
+
+// The same for bins that a few values cover, often one per wave (the top
+// digit of a key): one add when every valid lane holds the same bin, else
+// match_add.  Called by the whole wave.
+template <int BITS>
+__device__ __forceinline__ void narrow_add(uint32_t *hist, uint32_t bin, bool valid) {
+    const unsigned long long act = ballot64(valid);
+    if (act == 0ull) return;
+    const int first = __ffsll((long long)act) - 1;
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bin, first);
+    if (ballot64(valid && bin == b0) == act) {
+        if ((int)lane_id() == first) atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+        return;
+    }
+    match_add<BITS>(hist, bin, valid);
+}
+
 // ---------------------------------------------------- look-back statuses ----
 __device__ __forceinline__ uint32_t st_load32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -149,18 +179,30 @@ __device__ __forceinline__ unsigned long long st_pack64(uint32_t state, unsigned
 // the nearest inclusive prefix.  Every predecessor tile was claimed earlier by
 // a running work-group through the ticket counter, so every wait ends.
 //
-// Per-digit form (one thread per digit): eight predecessors are polled with
-// independent loads per round.
+// Status words live in memory shared by all XCDs, so each poll is a round
+// trip of a microsecond or more: the rounds are made wide, with many
+// independent loads in flight, so that a tile far from the nearest inclusive
+// prefix needs few of them.
+//
+// A poll that finds a predecessor unpublished sleeps before polling again,
+// longer each time (nap x 128 cycles, up to about 1 us): thousands of waves
+// polling the same few lines back to back would slow every poll down.
+__device__ __forceinline__ void backoff(int nap) {
+    for (int i = 0; i < nap; i++) __builtin_amdgcn_s_sleep(2);
+}
+
+// Per-digit form (one thread per digit): R predecessors per round.
+template <int R = 16>
 __device__ __forceinline__ uint32_t lookback32(const uint32_t *st, int tile, int stride) {
     uint32_t acc = 0;
-    for (int t = tile - 1; t >= 0; t -= 8) {
-        uint32_t s[8];
+    for (int t = tile - 1; t >= 0; t -= R) {
+        uint32_t s[R];
 #pragma unroll
-        for (int j = 0; j < 8; j++) s[j] = (t - j >= 0) ? st_load32(st + (size_t)(t - j) * stride) : (VR_ST_INC << 30);
+        for (int j = 0; j < R; j++) s[j] = (t - j >= 0) ? st_load32(st + (size_t)(t - j) * stride) : (VR_ST_INC << 30);
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            while ((s[j] >> 30) == VR_ST_NONE) {
-                __builtin_amdgcn_s_sleep(1);
+        for (int j = 0; j < R; j++) {
+            for (int nap = 1; (s[j] >> 30) == VR_ST_NONE; nap = nap < 16 ? 2 * nap : 16) {
+                backoff(nap);
                 s[j] = st_load32(st + (size_t)(t - j) * stride);
             }
             acc += s[j] & 0x3FFFFFFFu;
@@ -170,61 +212,102 @@ __device__ __forceinline__ uint32_t lookback32(const uint32_t *st, int tile, int
     return acc;
 }
 
-// Wave form (all 64 lanes of one wave, same `tile`): 64 predecessors per
-// round; returns the exclusive prefix in every lane.
-__device__ __forceinline__ uint32_t lookback32_wave(const uint32_t *st, int tile) {
+// Wave form (all 64 lanes of one wave, same `tile`): 64 R predecessors per
+// round, predecessor tile - 1 - (lane + 64 j) in slot j of a lane; returns
+// the exclusive prefix in every lane.  T is the status word (u32 with 30
+// value bits, or u64 with 62).
+template <typename T, int R = 4>
+__device__ __forceinline__ T lookback_wave(const T *st, int tile) {
+    constexpr int SH = 8 * (int)sizeof(T) - 2;
+    constexpr T VMASK = ((T)1 << SH) - 1;
     const int lane = (int)lane_id();
-    uint32_t acc = 0;
-    for (int base = tile - 1; base >= 0; base -= VR_WAVE) {
-        const int t = base - lane;
-        for (;;) {
-            const uint32_t s = (t >= 0) ? st_load32(st + t) : (VR_ST_INC << 30);
-            const unsigned long long inc = ballot64((s >> 30) == VR_ST_INC);
-            const unsigned long long none = ballot64((s >> 30) == VR_ST_NONE);
-            const int first = inc ? (__ffsll((long long)inc) - 1) : VR_WAVE;
-            const unsigned long long need = (first >= VR_WAVE - 1) ? ~0ull : ((2ull << first) - 1ull);
-            if (none & need) {
-                __builtin_amdgcn_s_sleep(1);
+    T acc = 0;
+    for (int base = tile - 1; base >= 0; base -= VR_WAVE * R) {
+        T s[R];
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            const int i = base - lane - VR_WAVE * j;
+            s[j] = (i >= 0) ? (sizeof(T) == 4 ? (T)st_load32((const uint32_t *)st + i)
+                                              : (T)st_load64((const unsigned long long *)st + i))
+                            : ((T)VR_ST_INC << SH);
+        }
+        for (int nap = 1;; nap = nap < 16 ? 2 * nap : 16) {
+            // nearest inclusive prefix: the smallest distance d = lane + 64 j
+            int dmin = VR_WAVE * R;
+#pragma unroll
+            for (int j = R - 1; j >= 0; j--) {
+                const unsigned long long inc = ballot64((s[j] >> SH) == VR_ST_INC);
+                if (inc) dmin = VR_WAVE * j + __ffsll((long long)inc) - 1;
+            }
+            bool wait = false;
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                const bool need = VR_WAVE * j + lane <= dmin;
+                wait |= ballot64(need && (s[j] >> SH) == VR_ST_NONE) != 0ull;
+            }
+            if (wait) {
+                backoff(nap);
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const int i = base - lane - VR_WAVE * j;
+                    if (i >= 0 && (s[j] >> SH) == VR_ST_NONE)
+                        s[j] = sizeof(T) == 4 ? (T)st_load32((const uint32_t *)st + i)
+                                              : (T)st_load64((const unsigned long long *)st + i);
+                }
                 continue;
             }
-            acc += wave_sum<uint32_t>(lane <= first ? (s & 0x3FFFFFFFu) : 0u);
-            if (first < VR_WAVE) return acc;
+            T v = 0;
+#pragma unroll
+            for (int j = 0; j < R; j++)
+                if (VR_WAVE * j + lane <= dmin) v += s[j] & VMASK;
+            acc += wave_sum<T>(v);
+            if (dmin < VR_WAVE * R) return acc;
             break;
         }
     }
     return acc;
+}
+
+__device__ __forceinline__ uint32_t lookback32_wave(const uint32_t *st, int tile) {
+    return lookback_wave<uint32_t>(st, tile);
 }
 
 __device__ __forceinline__ unsigned long long lookback64_wave(const unsigned long long *st, int tile) {
-    const int lane = (int)lane_id();
-    unsigned long long acc = 0;
-    for (int base = tile - 1; base >= 0; base -= VR_WAVE) {
-        const int t = base - lane;
-        for (;;) {
-            const unsigned long long s = (t >= 0) ? st_load64(st + t) : ((unsigned long long)VR_ST_INC << 62);
-            const unsigned long long inc = ballot64((s >> 62) == VR_ST_INC);
-            const unsigned long long none = ballot64((s >> 62) == VR_ST_NONE);
-            const int first = inc ? (__ffsll((long long)inc) - 1) : VR_WAVE;
-            const unsigned long long need = (first >= VR_WAVE - 1) ? ~0ull : ((2ull << first) - 1ull);
-            if (none & need) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            acc += wave_sum<unsigned long long>(lane <= first ? (s & 0x3FFFFFFFFFFFFFFFull) : 0ull);
-            if (first < VR_WAVE) return acc;
-            break;
-        }
-    }
-    return acc;
+    return lookback_wave<unsigned long long>(st, tile);
 }
 
-// Claim the next tile of a persistent loop; broadcast through LDS.
-__device__ __forceinline__ int claim_tile(uint32_t *ticket, int *sh) {
+// Claim the next S consecutive tiles of a persistent loop with one atomic;
+// broadcast through LDS.  A tile looking back at the last tile of the
+// previous claim waits until that claim's work-group reaches it, so kernels
+// that publish a tile's aggregate only when they process it claim one tile
+// at a time.
+__device__ __forceinline__ int claim_tiles(uint32_t *ticket, int S, int *sh) {
     __syncthreads();
-    if (threadIdx.x == 0) *sh = (int)atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) *sh = (int)atomicAdd(ticket, (uint32_t)S);
     __syncthreads();
     return *sh;
 }
+
+// Copy of a global histogram that this work-group adds to, and the sum of
+// bin `idx` over all copies (copies `stride` words apart).
+__device__ __forceinline__ uint32_t *hist_copy(uint32_t *h0, int stride) {
+    return h0 + (size_t)(blockIdx.x % VR_HCOPY) * stride;
+}
+__device__ __forceinline__ uint32_t hist_sum(const uint32_t *h0, int stride, int copies, int idx) {
+    uint32_t v = 0;
+    if (copies == VR_HCOPY) {  // all loads in flight at once
+        uint32_t x[VR_HCOPY];
+#pragma unroll
+        for (int c = 0; c < VR_HCOPY; c++) x[c] = h0[(size_t)c * stride + idx];
+#pragma unroll
+        for (int c = 0; c < VR_HCOPY; c++) v += x[c];
+        return v;
+    }
+    for (int c = 0; c < copies; c++) v += h0[(size_t)c * stride + idx];
+    return v;
+}
+
+
 
 // ------------------------------------------------------ key conventions ----
 // Log-linear bucket of a 32-bit key: exact below 128, then 64 buckets per
@@ -233,6 +316,14 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t q) {
     if (q < 128u) return q;
     uint32_t m = 31u - (uint32_t)__clz(q);
     return 128u + ((m - 7u) << 6) + ((q >> (m - 6u)) & 63u);
+}
+
+// Smallest key of bucket b (2^32 for b = VR_NBUCKET): the inverse of
+// bucket_of on bucket starts.
+__host__ __device__ __forceinline__ unsigned long long bucket_start(uint32_t b) {
+    if (b < 128u) return b;
+    const uint32_t r = b - 128u, m = 7u + r / 64u, f = r % 64u;
+    return (1ull << m) | ((unsigned long long)f << (m - 6u));
 }
 
 // Packed triangle key: value (24 bits) | i | j | k (13 bits each), i<j<k.
@@ -278,7 +369,8 @@ __device__ __forceinline__ void publish_counts(VrMailbox *mb, uint32_t seq, uint
 struct SortJob {
     uint32_t *key[2];
     uint32_t *val[2];
-    const uint32_t *hist;     // [passes][VR_RADIX] digit histograms of all keys
+    const uint32_t *hist;     // [VR_HCOPY][hist_stride]: per copy, [passes][VR_RADIX] digit histograms
+    int hist_stride;
     uint32_t *ticket;         // one tile ticket per pass
     uint32_t *st[2];          // look-back statuses, by parity of the active pass
     const uint32_t *count;    // number of items
@@ -301,8 +393,9 @@ struct VrCloud {
 
 // Per-cloud results written on the device.
 struct VrCloudState {
-    uint32_t pivot;       // pivot bucket of the percentile/count threshold
-    uint32_t cand_base;   // first candidate of the cloud in the candidate list
+    unsigned long long qend;  // candidates of a count/fraction threshold: q < qend (end of the pivot bucket)
+    uint32_t cand_base;       // first candidate of the cloud in the candidate list
+    uint32_t pad;
 };
 
 struct VrDev {
@@ -325,12 +418,13 @@ struct VrDev {
     uint32_t seq;
     const VrCloud *cl;      // C clouds
     VrCloudState *cs;       // C per-cloud results
-    uint32_t *hist;         // C x VR_NBUCKET log-linear histograms
+    uint32_t *hist;         // C x hcopies x VR_NBUCKET log-linear histograms
+    int hcopies;            // copies of each cloud's histogram
     unsigned long long *host_cloud;  // host-pinned: per cloud (kbase, K, tri_base, T)
     uint32_t *q;            // E squared distances
     uint32_t *key[2];       // E each, ping-pong (edge sort)
     uint32_t *val[2];       // E each (i<<16 | j, local)
-    uint32_t *st_sel;       // ceil(E/TILE) select statuses
+    uint32_t *st_sel;       // ceil(E/TILE) candidates per pair tile, then their offsets
     uint32_t *st_sort[2];   // ceil(E/TILE)*RADIX edge-sort statuses
     uint32_t *se_ij;        // K sorted kept edges (i<<16|j, local)
     uint32_t *se_q;         // K
@@ -339,7 +433,7 @@ struct VrDev {
     uint32_t *ist[2];       // ceil(2K/TILE)*RADIX star-sort statuses
     uint32_t *star_r;       // 2K: CSR stars, global kept-edge index, rank order
     uint16_t *star_nbr;     // 2K: the other endpoint (local)
-    uint32_t *star_k;       // 2K: stars in neighbour order, neighbour | rank-order position << 16
+    uint32_t *star_k;       // 2K + 64V: stars in neighbour order (neighbour | rank-order position << 16), each followed by 64 sentinels
     uint32_t *start;        // V+1 CSR row starts
     uint16_t *pos;          // 2K: position of edge g in the star of endpoint s (id 2g+s)
     uint32_t *cnt;          // K triangles per kept edge
