@@ -424,13 +424,20 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
             __syncthreads();
             uint32_t kk[VR_ITEMS], vv[VR_ITEMS], rk[VR_ITEMS];
             const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
+            // all loads first: the ranking below orders LDS traffic, and no
+            // wait of it should hold a global load back
 #pragma unroll
             for (int it = 0; it < VR_ITEMS; it++) {
                 const long long idx = base + (long long)it * VR_WAVE + lane;
                 const bool valid = idx < (long long)Kc;
-                const uint32_t k = valid ? ksrc[idx] : 0u;
-                kk[it] = k;
+                kk[it] = valid ? ksrc[idx] : 0u;
                 vv[it] = valid ? vsrc[idx] : 0u;
+            }
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const long long idx = base + (long long)it * VR_WAVE + lane;
+                const bool valid = idx < (long long)Kc;
+                const uint32_t k = kk[it];
                 const uint32_t dg = (k >> shift) & 255u;
                 unsigned long long peers = ballot64(valid);
 #pragma unroll
@@ -443,7 +450,8 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
                 const uint32_t r = before + (uint32_t)__popcll(peers & lanemask_lt());
                 rk[it] = r;
                 if (valid && (peers & lanemask_lt()) == 0ull) s_whist[w][dg] = before + (uint32_t)__popcll(peers);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                // the wave's LDS operations run in order; keep the compiler
+                // from moving the next item's read above this write
                 __builtin_amdgcn_wave_barrier();
             }
             __syncthreads();

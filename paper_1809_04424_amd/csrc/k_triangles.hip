@@ -235,31 +235,33 @@ __device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, u
 
 size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLds); }
 
-// Load the first min(VR_PIECES, ceil(len/64)) pieces of `len` (>= 1, wave-
-// uniform) candidates starting at src; pieces past len are skipped with a
-// scalar branch.  Indices inside the last piece are clamped, so every lane
-// of a loaded piece loads (no predication); the consumer masks lanes past len.
-template <typename T>
-__device__ __forceinline__ void issue(const T *__restrict__ src, uint32_t len, T (&kk)[VR_PIECES]) {
+// Prefetch of one edge's candidates, VR_PIECES pieces of 64.  Every load is
+// issued unconditionally, with addresses clamped into valid memory, so that
+// the compiler can count outstanding loads exactly: a conditional load makes
+// it wait for every load in flight, the next edge's prefetch included.
+// Pieces past the candidates are never consumed.
+//
+// Rank-prefix candidates (u16 neighbours; len may be 0): pieces past len
+// re-read the last candidate, or the array's first entry when len is 0.
+__device__ __forceinline__ void issue_prefix(const uint16_t *__restrict__ base, uint32_t sb, uint32_t len,
+                                             uint32_t (&kk)[VR_PIECES]) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t last = len - 1u;
+    const uint16_t *src = base + (len ? sb : 0u);
+    const uint32_t last = len ? len - 1u : 0u;
 #pragma unroll
     for (int j = 0; j < VR_PIECES; j++) {
-        if ((uint32_t)(j * VR_WAVE) < len) {
-            const uint32_t y = (uint32_t)(j * VR_WAVE) + lane;
-            kk[j] = src[y < last ? y : last];
-        }
+        const uint32_t y = (uint32_t)(j * VR_WAVE) + lane;
+        kk[j] = src[y < last ? y : last];
     }
 }
 
-// As issue(), for a padded neighbour-ordered star: a piece's lanes past len
-// read sentinels, so indices need no clamp.
+// Padded neighbour-ordered star (len >= 1): pieces past len read the 64
+// sentinels that follow the star.
 __device__ __forceinline__ void issue_padded(const uint32_t *__restrict__ src, uint32_t len,
                                              uint32_t (&kk)[VR_PIECES]) {
     const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < VR_PIECES; j++)
-        if ((uint32_t)(j * VR_WAVE) < len) kk[j] = src[(uint32_t)(j * VR_WAVE) + lane];
+    for (int j = 0; j < VR_PIECES; j++) kk[j] = src[min((uint32_t)(j * VR_WAVE), len) + lane];
 }
 
 // ----------------------------------------------------------- k_tri_count ----
@@ -289,31 +291,35 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
                 vxa = L.xa[eb + lane];
             }
             uint32_t mycnt = 0;
-            uint16_t kA[VR_PIECES], kB[VR_PIECES];
-            // an edge with an empty prefix loads nothing (its count is 0)
-            if (rl(vlen, 0)) issue<uint16_t>(D.star_nbr + rl(vsb, 0), rl(vlen, 0), kA);
-            for (int el = 0; el < ne; el++) {
-                if (el + 1 < ne && rl(vlen, el + 1)) issue<uint16_t>(D.star_nbr + rl(vsb, el + 1), rl(vlen, el + 1), kB);
+            // count of edge el from its prefetched pieces
+            auto count_edge = [&](int el, const uint32_t (&kk)[VR_PIECES]) {
                 const uint32_t xa = rl(vxa, el), len = rl(vlen, el);
                 uint32_t c = 0;
-                if (len) {
 #pragma unroll
-                    for (int j = 0; j < VR_PIECES; j++) {
-                        if ((uint32_t)(j * VR_WAVE) < len) {  // whole pieces past len are skipped
-                            const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
-                            const bool hit = (y < len) & ((uint32_t)Pa[kA[j]] < xa);
-                            c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
-                        }
-                    }
-                    for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
-                        const uint32_t y = y0 + (uint32_t)lane;
-                        const uint32_t k = D.star_nbr[rl(vsb, el) + (y < len ? y : len - 1u)];
-                        c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((y < len) & ((uint32_t)Pa[k] < xa)));
+                for (int j = 0; j < VR_PIECES; j++) {
+                    if ((uint32_t)(j * VR_WAVE) < len) {  // whole pieces past len are skipped
+                        const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
+                        const bool hit = (y < len) & ((uint32_t)Pa[kk[j]] < xa);
+                        c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
                     }
                 }
+                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                    const uint32_t y = y0 + (uint32_t)lane;
+                    const uint32_t k = D.star_nbr[rl(vsb, el) + (y < len ? y : len - 1u)];
+                    c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((y < len) & ((uint32_t)Pa[k] < xa)));
+                }
                 if (lane == el) mycnt = c;
-#pragma unroll
-                for (int j = 0; j < VR_PIECES; j++) kA[j] = kB[j];
+            };
+            // ping-pong prefetch one edge ahead; past the last edge the loads
+            // repeat the last edge's (never consumed)
+            uint32_t kA[VR_PIECES], kB[VR_PIECES];
+            issue_prefix(D.star_nbr, rl(vsb, 0), rl(vlen, 0), kA);
+            for (int el = 0; el < ne; el += 2) {
+                const int e1 = min(el + 1, ne - 1), e2 = min(el + 2, ne - 1);
+                issue_prefix(D.star_nbr, rl(vsb, e1), rl(vlen, e1), kB);
+                count_edge(el, kA);
+                issue_prefix(D.star_nbr, rl(vsb, e2), rl(vlen, e2), kA);
+                if (el + 1 < ne) count_edge(el + 1, kB);
             }
             if (lane < ne) D.cnt[vr] = mycnt;
         }
@@ -488,39 +494,60 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
                 vb = L.b[eb + lane];
                 voff = D.off[vr];
             }
-            uint32_t kA[VR_PIECES], kB[VR_PIECES];
-            issue_padded(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
-            for (int el = 0; el < ne; el++) {
-                if (el + 1 < ne) issue_padded(D.star_k + rl(vsb, el + 1), rl(vlen, el + 1), kB);
+            // write the triangles of edge el from its prefetched pieces
+            auto write_edge = [&](int el, const uint32_t (&kk)[VR_PIECES]) {
                 const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
                 const uint32_t r = rl(vr, el) - kb;  // local rank within the cloud
                 unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
                                                  rl((uint32_t)voff, el));
+                uint32_t run = 0;  // keys of this edge written so far
                 // key = (r << 39) | (x0 << 26) | (x1 << 13) | x2 with x0 < x1 < x2 the
                 // sorted triple {lo, hi, k}; k differs from both endpoints
                 const uint32_t lo = min((uint32_t)a, b), hi = max((uint32_t)a, b);
                 const uint32_t rh = r << 7;  // bits 39.. of the key, in the high word
-                // one 64-entry piece of the partner's neighbour-ordered star
-                // (lanes past the star read sentinels, which never hit)
-                auto piece = [&](uint32_t v) {
+                // one 64-entry piece of the partner's neighbour-ordered star, with
+                // the position of each entry's neighbour in a's star (lanes past
+                // the star read sentinels, which never hit)
+                auto piece = [&](uint32_t v, uint32_t pa) {
                     const uint32_t k = v & 0xFFFFu, pk = v >> 16;
-                    const bool hit = (pk < pb) & ((uint32_t)Pa[k] < xa);
+                    const bool hit = (pk < pb) & (pa < xa);
                     const unsigned long long m = __builtin_amdgcn_ballot_w64(hit);
                     const uint32_t x0 = min(lo, k), x2 = max(hi, k), x1 = max(lo, min(hi, k));
                     const uint32_t klo = (x0 << 26) | (x1 << 13) | x2;
                     const uint32_t khi = rh | (x0 >> 6);
-                    const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, run));
                     // streaming store: keeps the stars, not the output, in L2
                     if (hit) __builtin_nontemporal_store(((unsigned long long)khi << 32) | klo, dst + at);
-                    dst += __popcll(m);
+                    run += (uint32_t)__popcll(m);
                 };
+                // pieces in groups of four: a group past len is skipped whole
+                // (pieces past len inside a group read sentinels), and the four
+                // position lookups of a group are issued together
 #pragma unroll
-                for (int j = 0; j < VR_PIECES; j++)
-                    if ((uint32_t)(j * VR_WAVE) < len) piece(kA[j]);
-                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE)
-                    piece(D.star_k[rl(vsb, el) + y0 + (uint32_t)lane]);
+                for (int g = 0; g < VR_PIECES; g += 4) {
+                    if ((uint32_t)(g * VR_WAVE) < len) {
+                        uint32_t pa[4];
 #pragma unroll
-                for (int j = 0; j < VR_PIECES; j++) kA[j] = kB[j];
+                        for (int j = 0; j < 4; j++) pa[j] = Pa[kk[g + j] & 0xFFFFu];
+#pragma unroll
+                        for (int j = 0; j < 4; j++) piece(kk[g + j], pa[j]);
+                    }
+                }
+                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                    const uint32_t v = D.star_k[rl(vsb, el) + y0 + (uint32_t)lane];
+                    piece(v, Pa[v & 0xFFFFu]);
+                }
+            };
+            // ping-pong prefetch one edge ahead; past the last edge the loads
+            // repeat the last edge's (never consumed)
+            uint32_t kA[VR_PIECES], kB[VR_PIECES];
+            issue_padded(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
+            for (int el = 0; el < ne; el += 2) {
+                const int e1 = min(el + 1, ne - 1), e2 = min(el + 2, ne - 1);
+                issue_padded(D.star_k + rl(vsb, e1), rl(vlen, e1), kB);
+                write_edge(el, kA);
+                issue_padded(D.star_k + rl(vsb, e2), rl(vlen, e2), kA);
+                if (el + 1 < ne) write_edge(el + 1, kB);
             }
         }
         __syncthreads();
