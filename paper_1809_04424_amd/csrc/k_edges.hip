@@ -340,15 +340,26 @@ void launch_select(const VrDev &D, hipStream_t s) {
     hipLaunchKernelGGL(k_sel_write, grid, dim3(VR_BLOCK), 0, s, D);
 }
 
+// Sum the VR_HCOPY copies of a histogram set into copy 0, which is all its
+// readers then read (one work-group).
+#define FOLD_BLOCK 1024
+__global__ __launch_bounds__(FOLD_BLOCK) void k_hist_fold(uint32_t *h0, int stride, int bins) {
+    for (int x = threadIdx.x; x < bins; x += FOLD_BLOCK) h0[x] = hist_sum(h0, stride, VR_HCOPY, x);
+}
+
+void launch_hist_fold(uint32_t *h0, int stride, int bins, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist_fold, dim3(1), dim3(FOLD_BLOCK), 0, s, h0, stride, bins);
+}
+
 // Active radix passes: a pass whose digit is the same for every key is the
 // identity and is skipped.  Returns the number of active passes before
 // `upto` and sets *active for pass `upto` (when upto < passes).
-__device__ __forceinline__ int active_before(const uint32_t *hist, int stride, int passes, int upto, bool *active) {
+__device__ __forceinline__ int active_before(const uint32_t *hist, int passes, int upto, bool *active) {
     __shared__ int sh_nz[VR_MAX_PASSES];
     if (threadIdx.x < VR_MAX_PASSES) sh_nz[threadIdx.x] = 0;
     __syncthreads();
     for (int x = threadIdx.x; x < passes * VR_RADIX; x += VR_BLOCK)
-        if (hist_sum(hist, stride, VR_HCOPY, x)) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+        if (hist[x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);
     __syncthreads();
     int a = 0;
     for (int p = 0; p < upto && p < passes; p++) a += (sh_nz[p] > 1) ? 1 : 0;
@@ -361,8 +372,7 @@ SortJob edge_sort_job(const VrDev &D) {
     SortJob J;
     J.key[0] = D.key[0]; J.key[1] = D.key[1];
     J.val[0] = D.val[0]; J.val[1] = D.val[1];
-    J.hist = &D.ctl->hist8[0][0][0];
-    J.hist_stride = VR_HIST8_STRIDE;
+    J.hist = &D.ctl->hist8[0][0][0];  // copy 0, folded
     J.ticket = &D.ctl->ticket[1];
     J.st[0] = D.st_sort[0]; J.st[1] = D.st_sort[1];
     J.count = &D.ctl->n_cand;
@@ -374,8 +384,7 @@ SortJob star_sort_job(const VrDev &D) {
     SortJob J;
     J.key[0] = D.ikey[0]; J.key[1] = D.ikey[1];
     J.val[0] = D.ival[0]; J.val[1] = D.ival[1];
-    J.hist = &D.ctl->hinc[0][0][0];
-    J.hist_stride = VR_HINC_STRIDE;
+    J.hist = &D.ctl->hinc[0][0][0];  // copy 0, folded
     J.ticket = &D.ctl->ticket[6];
     J.st[0] = D.ist[0]; J.st[1] = D.ist[1];
     J.count = &D.ctl->n_inc;
@@ -397,11 +406,12 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
     __shared__ uint32_t sh_w[VR_WAVES];
     __shared__ int sh_tile;
     bool active = false;
-    const int a = active_before(J.hist, J.hist_stride, J.passes, pass, &active);
-    if (!active) return;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const uint32_t Kc = *J.count;
     const int ntiles = (int)((Kc + VR_TILE - 1) / VR_TILE);
+    if ((int)blockIdx.x >= ntiles) return;  // surplus work-groups never touch the ticket
+    const int a = active_before(J.hist, J.passes, pass, &active);
+    if (!active) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const uint32_t *__restrict__ ksrc = J.key[a & 1];
     const uint32_t *__restrict__ vsrc = J.val[a & 1];
     uint32_t *__restrict__ kdst = J.key[(a + 1) & 1];
@@ -412,8 +422,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
 
     // global start of digit t
     uint32_t tot;
-    const uint32_t gstart =
-        block_excl_scan<uint32_t>(hist_sum(J.hist, J.hist_stride, VR_HCOPY, pass * VR_RADIX + t), sh_w, &tot);
+    const uint32_t gstart = block_excl_scan<uint32_t>(J.hist[pass * VR_RADIX + t], sh_w, &tot);
 
     for (;;) {
         const int t0 = claim_tiles(&J.ticket[pass], S, &sh_tile);
@@ -500,6 +509,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
                 }
             }
         }
+        if ((int)gridDim.x >= ntiles) break;  // every tile went out in the first round of claims
     }
 }
 
@@ -520,7 +530,7 @@ void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream
 __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
     __shared__ uint32_t h[3][VR_RADIX];
     VrCtl *ctl = D.ctl;
-    const int a = active_before(&ctl->hist8[0][0][0], VR_HIST8_STRIDE, D.passes, VR_MAX_PASSES, nullptr);
+    const int a = active_before(&ctl->hist8[0][0][0], D.passes, VR_MAX_PASSES, nullptr);
     const uint32_t *__restrict__ kf = D.key[a & 1];
     const uint32_t *__restrict__ vf = D.val[a & 1];
     const long long K = (D.thr_kind == 3) ? (long long)ctl->n_cand : D.K_host;

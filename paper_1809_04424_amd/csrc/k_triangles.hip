@@ -35,7 +35,7 @@ __device__ __forceinline__ int star_parity(const VrDev &D) {
     if (threadIdx.x < 3) sh_nz[threadIdx.x] = 0;
     __syncthreads();
     for (int x = threadIdx.x; x < D.spasses * VR_RADIX; x += VR_BLOCK)
-        if (hist_sum(&D.ctl->hinc[0][0][0], VR_HINC_STRIDE, VR_HCOPY, x)) atomicAdd(&sh_nz[x / VR_RADIX], 1);
+        if (D.ctl->hinc[0][0][x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);  // copy 0, folded
     __syncthreads();
     const int a = (sh_nz[0] > 1 ? 1 : 0) + (sh_nz[1] > 1 ? 1 : 0) + (sh_nz[2] > 1 ? 1 : 0);
     __syncthreads();

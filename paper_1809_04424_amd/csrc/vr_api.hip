@@ -501,6 +501,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     mark(ST_SELECT);
     if (need_hist) launch_pivot(D, s);
     launch_select(D, s);
+    launch_hist_fold(&D.ctl->hist8[0][0][0], VR_HIST8_STRIDE, D.passes * VR_RADIX, s);
     mark(ST_SORT);
     {
         const SortJob J = edge_sort_job(D);
@@ -510,6 +511,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     launch_edges(D, s);
     mark(ST_STAR);
     if (want_tri) {
+        launch_hist_fold(&D.ctl->hinc[0][0][0], VR_HINC_STRIDE, D.spasses * VR_RADIX, s);
         const SortJob J = star_sort_job(D);
         for (int p = 0; p < D.spasses; p++) launch_sort_pass(J, D.ntile_I, p, s);
         launch_star(D, s);

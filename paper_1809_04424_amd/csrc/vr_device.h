@@ -369,8 +369,7 @@ __device__ __forceinline__ void publish_counts(VrMailbox *mb, uint32_t seq, uint
 struct SortJob {
     uint32_t *key[2];
     uint32_t *val[2];
-    const uint32_t *hist;     // [VR_HCOPY][hist_stride]: per copy, [passes][VR_RADIX] digit histograms
-    int hist_stride;
+    const uint32_t *hist;     // [passes][VR_RADIX] digit histograms (copy 0 after folding)
     uint32_t *ticket;         // one tile ticket per pass
     uint32_t *st[2];          // look-back statuses, by parity of the active pass
     const uint32_t *count;    // number of items
@@ -476,6 +475,7 @@ bool gram_applies(const VrDev &D);
 void launch_gram(const VrDev &D, const void *points, hipStream_t s);
 void launch_select(const VrDev &D, hipStream_t s);
 void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s);
+void launch_hist_fold(uint32_t *h0, int stride, int bins, hipStream_t s);
 void launch_edges(const VrDev &D, hipStream_t s);
 void launch_star(const VrDev &D, hipStream_t s);
 void launch_tri_count(const VrDev &D, hipStream_t s);
