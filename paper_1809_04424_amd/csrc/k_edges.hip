@@ -36,6 +36,28 @@ void launch_init(const VrDev &D, size_t zero_words, const VrCloud *one, VrCloud 
                        one ? dst : nullptr);
 }
 
+// ------------------------------------------------------- k_cloud_maps ----
+// Work-group c writes cloud c into the batch's maps: its vertices, its
+// distance tiles, the select tiles and kept blocks whose first element it
+// holds (kept blocks only when the kept counts are known on the host).
+__global__ __launch_bounds__(VR_BLOCK) void k_cloud_maps(VrDev D) {
+    const int c = blockIdx.x, t = threadIdx.x;
+    const VrCloud cl = D.cl[c];
+    const long long n = cl.n, E = n * (n - 1) / 2, nb = (n + 63) / 64;
+    for (long long v = t; v < n; v += VR_BLOCK) D.vcloud[cl.vbase + v] = (uint32_t)c;
+    for (long long x = t; x < nb * (nb + 1) / 2; x += VR_BLOCK) D.tcloud[cl.tbase + x] = (uint32_t)c;
+    const long long s0 = (cl.pbase + VR_TILE - 1) / VR_TILE, s1 = (cl.pbase + E + VR_TILE - 1) / VR_TILE;
+    for (long long x = s0 + t; x < s1; x += VR_BLOCK) D.scloud[x] = (uint32_t)c;
+    if (D.thr_kind != 3) {
+        const long long k0 = (cl.kbase + VR_BLOCK - 1) / VR_BLOCK, k1 = (cl.kbase + cl.K + VR_BLOCK - 1) / VR_BLOCK;
+        for (long long x = k0 + t; x < k1; x += VR_BLOCK) D.kcloud[x] = (uint32_t)c;
+    }
+}
+
+void launch_cloud_maps(const VrDev &D, hipStream_t s) {
+    if (D.C > 1) hipLaunchKernelGGL(k_cloud_maps, dim3((unsigned)D.C), dim3(VR_BLOCK), 0, s, D);
+}
+
 // Distance tile t of a cloud with nb 64-point blocks: tiles are the blocks
 // (bi, bj), bi <= bj, in row order.
 __device__ __forceinline__ long long tile_row_start(long long bi, long long nb) { return bi * nb - bi * (bi - 1) / 2; }
@@ -64,7 +86,7 @@ __device__ __forceinline__ void tile_of(long long t, long long nb, int *bi, int 
 template <typename T>
 __global__ __launch_bounds__(VR_BLOCK) void k_dist(VrDev D) {
     const long long tg = blockIdx.x;
-    const int c = cloud_of(tg, D.C, [&](int k) { return D.cl[k].tbase; });
+    const int c = (D.C == 1) ? 0 : (int)D.tcloud[tg];
     const VrCloud cl = D.cl[c];
     const int n = cl.n, d = D.d;
     int bi, bj;
@@ -215,7 +237,7 @@ __device__ __forceinline__ uint32_t select_items(const VrDev &D, int tile, SelIt
     long long cstart = -1, cend = 0;
     unsigned long long qend = 0;
     if (e0 < E) {
-        c = cloud_of(e0, D.C, [&](int k) { return D.cl[k].pbase; });
+        c = cloud_from_map(D, D.scloud, e0, VR_TILE, [&](int k) { return D.cl[k].pbase; });
         n = D.cl[c].n;
         cstart = D.cl[c].pbase;
         cend = cstart + (long long)n * (n - 1) / 2;
@@ -513,12 +535,161 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
     }
 }
 
+// ---------------------------------------------------- k_sort_pass_multi ----
+// The same stable pass for large key counts, where one ticket per tile would
+// serialise on the ticket: a work-group claims S consecutive tiles, first
+// counts the digits of all S (publishing every tile's aggregate at once, so
+// that later claims never wait for this one's scatter), then looks back once
+// for its first tile, publishes the inclusive prefixes of all S, and finally
+// re-reads, ranks and scatters each tile as the single-tile pass does.
+#define SORT_MULTI_MAX 16
+__global__ __launch_bounds__(VR_BLOCK) void k_sort_pass_multi(SortJob J, int pass) {
+    __shared__ uint32_t s_whist[VR_WAVES][VR_RADIX];
+    __shared__ uint32_t s_tstart[VR_RADIX];
+    __shared__ uint32_t s_gpre[VR_RADIX];
+    __shared__ uint32_t s_key[VR_TILE];
+    __shared__ uint32_t s_val[VR_TILE];
+    __shared__ uint32_t s_cnt[SORT_MULTI_MAX][VR_RADIX];  // digit counts of the claimed tiles
+    __shared__ uint32_t sh_w[VR_WAVES];
+    __shared__ int sh_tile;
+    bool active = false;
+    const uint32_t Kc = *J.count;
+    const int ntiles = (int)((Kc + VR_TILE - 1) / VR_TILE);
+    // tiles per claim from the device-side count: about a thousand claims
+    const int S = max(1, min(SORT_MULTI_MAX, ntiles / 1024));
+    const int nclaims = (ntiles + S - 1) / S;
+    if ((int)blockIdx.x >= nclaims) return;  // surplus work-groups never touch the ticket
+    const int a = active_before(J.hist, J.passes, pass, &active);
+    if (!active) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t *__restrict__ ksrc = J.key[a & 1];
+    const uint32_t *__restrict__ vsrc = J.val[a & 1];
+    uint32_t *__restrict__ kdst = J.key[(a + 1) & 1];
+    uint32_t *__restrict__ vdst = J.val[(a + 1) & 1];
+    uint32_t *st = J.st[a & 1];
+    uint32_t *st_next = J.st[(a + 1) & 1];
+    const int shift = VR_RADIX_BITS * pass;
+    uint32_t tot;
+    const uint32_t gstart = block_excl_scan<uint32_t>(J.hist[pass * VR_RADIX + t], sh_w, &tot);
+
+    for (;;) {
+        const int t0 = claim_tiles(&J.ticket[pass], S, &sh_tile);
+        if (t0 >= ntiles) break;
+        const int nt = min(S, ntiles - t0);
+        // counts of every claimed tile, then all their aggregates
+        for (int j = 0; j < SORT_MULTI_MAX; j++) s_cnt[j][t] = 0u;
+        __syncthreads();
+        const bool top = pass == J.passes - 1;  // the top digit takes few values
+        for (int j = 0; j < nt; j++) {
+            const long long base = (long long)(t0 + j) * VR_TILE + (long long)t * VR_ITEMS;
+            uint32_t kk[VR_ITEMS];
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) kk[it] = (base + it < (long long)Kc) ? ksrc[base + it] : 0u;
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const bool valid = base + it < (long long)Kc;
+                const uint32_t dg = (kk[it] >> shift) & 255u;
+                if (top) narrow_add<8>(s_cnt[j], dg, valid);
+                else spread_add(s_cnt[j], dg, valid);
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < nt; j++) {
+            const int tile = t0 + j;
+            if (tile == 0) st_store32(st + t, st_pack32(VR_ST_INC, s_cnt[0][t]));
+            else st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_AGG, s_cnt[j][t]));
+        }
+        // one look-back for the first tile; the others follow from the
+        // counts.  s_cnt[j][t] becomes tile j's prefix of digit t.
+        uint32_t run = (t0 == 0) ? 0u : lookback32(st + t, t0, VR_RADIX);
+        for (int j = 0; j < nt; j++) {
+            const int tile = t0 + j;
+            const uint32_t c = s_cnt[j][t];
+            if (tile > 0) st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_INC, run + c));
+            st_next[(size_t)tile * VR_RADIX + t] = 0u;
+            s_cnt[j][t] = run;
+            run += c;
+        }
+        for (int j = 0; j < nt; j++) {
+            const int tile = t0 + j;
+            __syncthreads();  // LDS of the previous tile is reused
+            for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = 0u;
+            __syncthreads();
+            uint32_t kk[VR_ITEMS], vv[VR_ITEMS], rk[VR_ITEMS];
+            const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const long long idx = base + (long long)it * VR_WAVE + lane;
+                const bool valid = idx < (long long)Kc;
+                kk[it] = valid ? ksrc[idx] : 0u;
+                vv[it] = valid ? vsrc[idx] : 0u;
+            }
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const long long idx = base + (long long)it * VR_WAVE + lane;
+                const bool valid = idx < (long long)Kc;
+                const uint32_t dg = (kk[it] >> shift) & 255u;
+                unsigned long long peers = ballot64(valid);
+#pragma unroll
+                for (int b = 0; b < VR_RADIX_BITS; b++) {
+                    const unsigned long long m = ballot64((dg >> b) & 1u);
+                    peers &= ((dg >> b) & 1u) ? m : ~m;
+                }
+                uint32_t before = 0;
+                if (valid) before = s_whist[w][dg];
+                rk[it] = before + (uint32_t)__popcll(peers & lanemask_lt());
+                if (valid && (peers & lanemask_lt()) == 0ull) s_whist[w][dg] = before + (uint32_t)__popcll(peers);
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            uint32_t wpre[VR_WAVES];
+            uint32_t tc = 0;
+#pragma unroll
+            for (int x = 0; x < VR_WAVES; x++) { wpre[x] = tc; tc += s_whist[x][t]; }
+            uint32_t ttot;
+            s_tstart[t] = block_excl_scan<uint32_t>(tc, sh_w, &ttot);
+            s_gpre[t] = gstart + s_cnt[j][t];
+            __syncthreads();
+#pragma unroll
+            for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = wpre[x];
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < VR_ITEMS; it++) {
+                const long long idx = base + (long long)it * VR_WAVE + lane;
+                if (idx < (long long)Kc) {
+                    const uint32_t dg = (kk[it] >> shift) & 255u;
+                    const uint32_t lp = s_tstart[dg] + s_whist[w][dg] + rk[it];
+                    s_key[lp] = kk[it];
+                    s_val[lp] = vv[it];
+                }
+            }
+            __syncthreads();
+            const uint32_t valid_n = (uint32_t)min((long long)VR_TILE, (long long)Kc - (long long)tile * VR_TILE);
+#pragma unroll
+            for (int m = 0; m < VR_ITEMS; m++) {
+                const uint32_t lp = (uint32_t)t + (uint32_t)m * VR_BLOCK;
+                if (lp < valid_n) {
+                    const uint32_t k = s_key[lp];
+                    const uint32_t dg = (k >> shift) & 255u;
+                    kdst[s_gpre[dg] + (lp - s_tstart[dg])] = k;
+                    vdst[s_gpre[dg] + (lp - s_tstart[dg])] = s_val[lp];
+                }
+            }
+        }
+        __syncthreads();  // s_cnt is reused by the next claim
+    }
+}
+
 void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s) {
-    // one tile per claim: a tile's aggregate is published as soon as it is
-    // ranked, which tiles claimed in batches would delay
     long long g = max_tiles;
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
+    if (max_tiles > 2048) {  // possibly many tiles: several per claim
+        hipLaunchKernelGGL(k_sort_pass_multi, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass);
+        return;
+    }
+    // one tile per claim: a tile's aggregate is published as soon as it is
+    // ranked
     hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass, 1);
 }
 
@@ -553,7 +724,9 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
         const bool ok = g < K;
         uint32_t vi = 0, vj = 0;
         if (ok) {
-            const int c = cloud_of(g, D.C, [&](int k) { return kept_base(D, k); });
+            const int c = (D.thr_kind == 3)  // kept bases known only on the device: search
+                              ? cloud_of(g, D.C, [&](int k) { return kept_base(D, k); })
+                              : cloud_from_map(D, D.kcloud, g, VR_BLOCK, [&](int k) { return D.cl[k].kbase; });
             const long long sp = (long long)D.cs[c].cand_base + (g - kept_base(D, c));
             const uint32_t k = kf[sp], v = vf[sp];
             D.se_q[g] = k & qmask;

@@ -24,7 +24,7 @@ __device__ __forceinline__ long long gram_tile_row_start(long long bi, long long
 
 __global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(VrDev D, int dpad) {
     const long long tg = blockIdx.x;
-    const int c = cloud_of(tg, D.C, [&](int k) { return D.cl[k].tbase; });
+    const int c = (D.C == 1) ? 0 : (int)D.tcloud[tg];
     const VrCloud cl = D.cl[c];
     const int n = cl.n, d = D.d, need_hist = D.need_hist;
     const long long nb = (n + GRAM_TB - 1) / GRAM_TB, tl = tg - cl.tbase;

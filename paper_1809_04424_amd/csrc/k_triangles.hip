@@ -44,7 +44,7 @@ __device__ __forceinline__ int star_parity(const VrDev &D) {
 
 // Cloud of global vertex v, and v's local index.
 __device__ __forceinline__ int vertex_cloud(const VrDev &D, long long v) {
-    return cloud_of(v, D.C, [&](int k) { return D.cl[k].vbase; });
+    return (D.C == 1) ? 0 : (int)D.vcloud[v];
 }
 
 // --------------------------------------------------------------- k_star ----

@@ -201,6 +201,7 @@ struct Plan {
     size_t off_seij, off_seq;
     size_t off_ikey0, off_ikey1, off_ival0, off_ival1, off_ist0, off_ist1;
     size_t off_star_r, off_star_nbr, off_star_k, off_start, off_pos, off_cnt, off_off;
+    size_t off_vcloud, off_tcloud, off_scloud, off_kcloud;
     size_t total;
 };
 
@@ -211,8 +212,9 @@ int hist_copies(long long C) {
     return h < 1 ? 1 : (int)h;
 }
 
-// C clouds with V vertices and E pairs in all; Kmax bounds the kept edges.
-Plan plan(long long C, long long V, long long E, long long Kmax, bool hist, bool tri) {
+// C clouds with V vertices, E pairs and `tiles` distance tiles in all; Kmax
+// bounds the kept edges.
+Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax, bool hist, bool tri) {
     Plan P{};
     const long long ntE = (E + VR_TILE - 1) / VR_TILE;
     const long long ntK = (Kmax + VR_TILE - 1) / VR_TILE;
@@ -251,6 +253,12 @@ Plan plan(long long C, long long V, long long E, long long Kmax, bool hist, bool
         P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
+    }
+    if (C > 1) {  // cloud maps
+        P.off_vcloud = o; o = align_up(o + 4 * (size_t)V);
+        P.off_tcloud = o; o = align_up(o + 4 * (size_t)tiles);
+        P.off_scloud = o; o = align_up(o + 4 * (size_t)(ntE > 0 ? ntE : 1));
+        P.off_kcloud = o; o = align_up(o + 4 * (size_t)((Kmax + VR_BLOCK - 1) / VR_BLOCK + 1));
     }
     P.total = o;
     return P;
@@ -359,7 +367,7 @@ int shape_of(const vr_request *reqs, long long count, Shape &S) {
     return VR_OK;
 }
 
-Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.Kmax, S.need_hist, S.want_tri); }
+Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.tiles, S.Kmax, S.need_hist, S.want_tri); }
 
 // Build `count` clouds on stream s.  On VR_OK `own` holds the output block
 // and views[i] describes request i (device pointers into the block).  On an
@@ -483,6 +491,12 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         D.cnt = (uint32_t *)(ws + P.off_cnt);
         D.off = (unsigned long long *)(ws + P.off_off);
     }
+    if (C > 1) {
+        D.vcloud = (uint32_t *)(ws + P.off_vcloud);
+        D.tcloud = (uint32_t *)(ws + P.off_tcloud);
+        D.scloud = (uint32_t *)(ws + P.off_scloud);
+        D.kcloud = (uint32_t *)(ws + P.off_kcloud);
+    }
     D.ntile_E = (E + VR_TILE - 1) / VR_TILE;
     D.ntile_I = (2 * Kmax + VR_TILE - 1) / VR_TILE;
 
@@ -493,6 +507,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             hipSuccess)
             return fail(VR_EHIP, ws, P.total);
         launch_init(D, P.zero_bytes / 4, nullptr, nullptr, s);
+        launch_cloud_maps(D, s);
     } else {
         launch_init(D, P.zero_bytes / 4, &one, (VrCloud *)D.cl, s);
     }
@@ -627,7 +642,8 @@ int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind
     r.points = (const void *)16;
     long long E, K;
     if (check_request(&r, &E, &K) != VR_OK) return -1;
-    return (int64_t)plan(1, n, E, E, true, true).total;
+    const long long nb = (n + 63) / 64;
+    return (int64_t)plan(1, n, E, nb * (nb + 1) / 2, E, true, true).total;
 }
 
 int vr_query_counts(const vr_result *res, int64_t counts[3]) {

@@ -420,6 +420,10 @@ struct VrDev {
     uint32_t *hist;         // C x hcopies x VR_NBUCKET log-linear histograms
     int hcopies;            // copies of each cloud's histogram
     unsigned long long *host_cloud;  // host-pinned: per cloud (kbase, K, tri_base, T)
+    // cloud maps of a batch (null for one cloud): vertex, distance tile,
+    // 2048-pair select tile and 256-edge kept block -> the cloud holding it
+    // (a tile or block: the cloud of its first element)
+    uint32_t *vcloud, *tcloud, *scloud, *kcloud;
     uint32_t *q;            // E squared distances
     uint32_t *key[2];       // E each, ping-pong (edge sort)
     uint32_t *val[2];       // E each (i<<16 | j, local)
@@ -453,6 +457,17 @@ __device__ __forceinline__ int cloud_of(long long x, int C, F first) {
     return lo;
 }
 
+// Cloud of element x from a map over blocks of B elements (the cloud of
+// each block's first element), walking forward over the rare cloud starts
+// inside the block.  first(c) is the first element of cloud c.
+template <typename F>
+__device__ __forceinline__ int cloud_from_map(const VrDev &D, const uint32_t *map, long long x, int B, F first) {
+    if (D.C == 1) return 0;
+    int c = (int)map[x / B];
+    while (c + 1 < D.C && first(c + 1) <= x) c++;
+    return c;
+}
+
 // Kept edges of cloud c and its first global kept edge.  With a distance
 // threshold every candidate is kept, so both come from the candidate bases.
 __device__ __forceinline__ long long kept_base(const VrDev &D, int c) {
@@ -469,6 +484,7 @@ SortJob star_sort_job(const VrDev &D);
 
 void launch_init(const VrDev &D, size_t zero_words, const VrCloud *one, VrCloud *dst, hipStream_t s);
 void launch_pivot(const VrDev &D, hipStream_t s);
+void launch_cloud_maps(const VrDev &D, hipStream_t s);
 void launch_cloud_publish(const VrDev &D, hipStream_t s);
 void launch_dist(const VrDev &D, const void *points, hipStream_t s);
 bool gram_applies(const VrDev &D);
