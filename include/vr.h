@@ -192,6 +192,19 @@ VR_API int vr_batch_stage_ms(const vr_batch *batch, float *ms, int cap);
  * handle; every view dies with it.  NULL-safe. */
 VR_API void vr_batch_free(vr_batch *batch, void *stream);
 
+/*
+ * Autotuning of the triangle kernels' schedule (work-groups per vertex),
+ * for the size class of these requests (bits of their total vertex count and
+ * of their mean degree).  Runs one build of the requests (as vr_build_batch),
+ * then times the count and write kernels at 1, 2, 4, 8 and 16 work-groups
+ * per vertex, keeps the fastest of each in a process-wide table that later
+ * builds of the class use, and frees the build.  Schedules change no output.
+ * Synchronises `stream`.  parts[0], parts[1] receive the chosen values (0
+ * when the requests have no triangles).  Same error behaviour as
+ * vr_build_batch.
+ */
+VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t parts[2]);
+
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from
  * the driver once and reused by later builds of any stream (a reuse on

@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_trim",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_trim",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -105,6 +105,9 @@ def lib():
         L.vr_batch_stage_ms.restype = ctypes.c_int
         L.vr_batch_free.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.vr_batch_free.restype = None
+        L.vr_autotune.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_int32)]
+        L.vr_autotune.restype = ctypes.c_int
         L.vr_trim.argtypes = []
         L.vr_trim.restype = ctypes.c_int64
         L.vr_status_string.argtypes = [ctypes.c_int]
@@ -371,6 +374,27 @@ def _check_points(points):
     if points.dim() != 2:
         raise ValueError("points must be 2-D (n, d)")
     return points.contiguous()
+
+
+def autotune(points, thr, maxdim: int = 2):
+    """Tune the triangle kernels' schedule for the size class of these clouds
+    (one tensor or a list, as build_batch); returns (parts_count,
+    parts_write), the work-groups per vertex that later builds of the class
+    use.  Outputs do not depend on the schedule."""
+    import torch
+
+    L = lib()
+    pts = [_check_points(p) for p in (points if isinstance(points, (list, tuple)) else [points])]
+    thrs = list(thr) if isinstance(thr, list) else [thr] * len(pts)
+    dev = pts[0].device
+    stream = torch.cuda.current_stream(dev)
+    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None) for p, t in zip(pts, thrs)])
+    parts = (ctypes.c_int32 * 2)()
+    with torch.cuda.device(dev):
+        rc = L.vr_autotune(reqs, len(pts), ctypes.c_void_p(stream.cuda_stream), parts)
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return int(parts[0]), int(parts[1])
 
 
 def batch_limit(dtype: int, d: int) -> int:

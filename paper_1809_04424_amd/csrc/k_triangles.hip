@@ -327,15 +327,16 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
     }
 }
 
-// Work-groups per vertex: enough groups to spread heavy vertices over many
-// compute units when the cloud is small.
+// Work-groups per vertex, the default when no tuned value is known: enough
+// groups to spread heavy vertices over many compute units when the cloud is
+// small.
 int enum_parts(long long V) {
     long long p = 4096 / (V > 0 ? V : 1);
     return p < 1 ? 1 : (p > 8 ? 8 : (int)p);
 }
 
 void launch_tri_count(const VrDev &D, hipStream_t s) {
-    const int parts = enum_parts(D.V);
+    const int parts = D.parts_count;
     hipLaunchKernelGGL(k_tri_count, dim3((unsigned)(D.V * parts)), dim3(ENUM_BLOCK), enum_lds(D.maxn), s, D, parts);
 }
 
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
                       hipStream_t s) {
-    const int parts = enum_parts(D.V);
+    const int parts = D.parts_write;
     long long eb = (K + ENUM_BLOCK - 1) / ENUM_BLOCK;
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;

@@ -12,6 +12,7 @@
 // edge arrays.  The workspace is released in stream order.
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <new>
 #include <string.h>
@@ -194,6 +195,23 @@ thread_local HostMem g_host;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int bits_of(unsigned long long m);
+
+// Enumeration schedule picked by vr_autotune, per size class (bits of the
+// vertex count, bits of the mean degree): work-groups per vertex for the
+// count and the write.  Builds of a class never tuned use enum_parts.
+struct Tuning {
+    std::mutex mu;
+    std::map<std::pair<int, int>, std::pair<int, int>> parts;
+};
+Tuning &tuning() {
+    static Tuning *t = new Tuning();
+    return *t;
+}
+std::pair<int, int> size_class(long long V, long long K) {
+    return {bits_of((unsigned long long)V), bits_of((unsigned long long)(2 * K / (V > 0 ? V : 1)))};
+}
+
 struct Plan {
     size_t off_ctl, off_stscan, off_stsel, off_hist, zero_bytes;
     size_t off_cl, off_cs;
@@ -372,7 +390,8 @@ Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.tiles, S.Kmax, S.nee
 // Build `count` clouds on stream s.  On VR_OK `own` holds the output block
 // and views[i] describes request i (device pointers into the block).  On an
 // error `own` holds nothing.
-int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &own, std::vector<vr_result> &views) {
+int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &own, std::vector<vr_result> &views,
+               int32_t *tune_out = nullptr) {
     const vr_request &r0 = reqs[0];
     Shape S;
     const int st0 = shape_of(reqs, count, S);
@@ -456,6 +475,16 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     if (D.spasses < 1) D.spasses = 1;
     D.need_hist = need_hist ? 1 : 0;
     D.tri = want_tri ? 1 : 0;
+    D.parts_count = D.parts_write = enum_parts(V);
+    {
+        Tuning &tu = tuning();
+        std::lock_guard<std::mutex> g(tu.mu);
+        auto it = tu.parts.find(size_class(V, Kmax));
+        if (it != tu.parts.end()) {
+            D.parts_count = it->second.first;
+            D.parts_write = it->second.second;
+        }
+    }
     D.mailbox = g_host.mb_d;
     D.seq = ++g_host.seq;
     if (D.seq == 0) D.seq = ++g_host.seq;
@@ -612,6 +641,42 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         (void)hipStreamSynchronize(s);
         return fail(VR_EHIP, ws, P.total);
     }
+    if (tune_out && want_tri) {
+        // Time the count and the write at each schedule (both are idempotent:
+        // every run writes the same counts and keys) and keep the fastest.
+        const int cand[] = {1, 2, 4, 8, 16};
+        float best_c = 1e30f, best_w = 1e30f;
+        int pc = D.parts_count, pw = D.parts_write;
+        hipEvent_t e[3];
+        for (int i = 0; i < 3; i++)
+            if (hipEventCreate(&e[i]) != hipSuccess) return fail(VR_EHIP, ws, P.total);
+        for (int rep = 0; rep < 2; rep++)
+            for (int p : cand) {
+                if (V * p > (1ll << 30)) continue;
+                VrDev Dp = D;
+                Dp.parts_count = Dp.parts_write = p;
+                (void)hipEventRecord(e[0], s);
+                launch_tri_count(Dp, s);
+                (void)hipEventRecord(e[1], s);
+                if (write_tri) launch_tri_write(Dp, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
+                (void)hipEventRecord(e[2], s);
+                if (hipEventSynchronize(e[2]) != hipSuccess) break;
+                float tc = 0.f, tw = 0.f;
+                (void)hipEventElapsedTime(&tc, e[0], e[1]);
+                (void)hipEventElapsedTime(&tw, e[1], e[2]);
+                if (tc < best_c) { best_c = tc; pc = p; }
+                if (write_tri && tw < best_w) { best_w = tw; pw = p; }
+            }
+        for (int i = 0; i < 3; i++) (void)hipEventDestroy(e[i]);
+        if (hipGetLastError() != hipSuccess) return fail(VR_EHIP, ws, P.total);
+        {
+            Tuning &tu = tuning();
+            std::lock_guard<std::mutex> g(tu.mu);
+            tu.parts[size_class(V, Kmax)] = {pc, pw};
+        }
+        tune_out[0] = pc;
+        tune_out[1] = pw;
+    }
     A.put(ws, P.total);
     return VR_OK;
 }
@@ -687,6 +752,21 @@ int64_t vr_batch_workspace_bytes(const vr_request *reqs, int64_t count) {
     const int st = shape_of(reqs, count, S);
     if (st != VR_OK) return st;
     return S.C == 0 ? 0 : (int64_t)plan_of(S).total;
+}
+
+int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t parts[2]) {
+    if (!reqs || count < 1 || !parts) return VR_EINVAL;
+    vr_batch *b = new (std::nothrow) vr_batch();
+    if (!b) return VR_ENOMEM;
+    int32_t chosen[2] = {0, 0};
+    const int st = build_impl(reqs, count, (hipStream_t)stream, b->own, b->views, chosen);
+    if (st == VR_OK) {
+        b->own.release((hipStream_t)stream);
+        parts[0] = chosen[0];
+        parts[1] = chosen[1];
+    }
+    delete b;
+    return st;
 }
 
 int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, vr_batch **out) {

@@ -411,6 +411,7 @@ struct VrDev {
     int spasses;            // radix passes launched for the star sort
     int need_hist;          // histogram select needed (COUNT / FRACTION)
     int tri;                // triangles wanted
+    int parts_count, parts_write;  // work-groups per vertex in the enumeration kernels
     // workspace
     VrCtl *ctl;
     VrMailbox *mailbox;     // host-pinned
@@ -494,6 +495,7 @@ void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream
 void launch_hist_fold(uint32_t *h0, int stride, int bins, hipStream_t s);
 void launch_edges(const VrDev &D, hipStream_t s);
 void launch_star(const VrDev &D, hipStream_t s);
+int enum_parts(long long V);
 void launch_tri_count(const VrDev &D, hipStream_t s);
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,

@@ -133,3 +133,13 @@ def test_batch_workspace_bytes():
     assert vr.batch_workspace_bytes([(40, 3, vr.VR_I8, ("count", 0, 1))]) == 0  # nothing kept
     with pytest.raises(vr.VrError):
         vr.batch_workspace_bytes([(10, 3, vr.VR_I8, ("full", 0, 1)), (10, 4, vr.VR_I8, ("full", 0, 1))])
+
+
+def test_autotune_rejects_bad_arguments():
+    L = vr.lib()
+    parts = (ctypes.c_int32 * 2)()
+    assert L.vr_autotune(None, 1, None, parts) == vr.VR_EINVAL
+    arr = (vr.VrRequest * 1)(_req())
+    assert L.vr_autotune(arr, 1, None, None) == vr.VR_EINVAL
+    arr = (vr.VrRequest * 1)(_req(d=0))
+    assert L.vr_autotune(arr, 1, None, parts) == vr.VR_EINVAL

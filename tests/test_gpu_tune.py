@@ -1,0 +1,49 @@
+"""The enumeration schedule picked by the autotuner changes no output."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import assert_matches_oracle, gpu_build, gpu_build_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_then_build_matches_oracle(orc):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.noisy_circle(n=600)
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    pc, pw = vr.autotune(pts, c.thr)
+    assert pc in (1, 2, 4, 8, 16) and pw in (1, 2, 4, 8, 16)
+    r, out = gpu_build(c)
+    assert_matches_oracle(out, orc.build(c.points, c.thr))
+    r.free()
+
+
+def test_autotune_batch_then_build_batch(orc):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    clouds = [workloads.uniform_cloud(70 + i, n, 3, lo=-40, hi=40) for i, n in enumerate([90, 150, 300, 40])]
+    for c in clouds:
+        c.thr = ("fraction", 25, 100)
+    pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
+    pc, pw = vr.autotune(pts, [c.thr for c in clouds])
+    assert pc >= 1 and pw >= 1
+    b, outs = gpu_build_batch(clouds)
+    for c, out in zip(clouds, outs):
+        assert_matches_oracle(out, orc.build(c.points, c.thr))
+    b.free()
+
+
+def test_autotune_without_triangles():
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.uniform_cloud(5, 50, 3)
+    c.thr = ("fraction", 10, 100)
+    assert vr.autotune(torch.from_numpy(c.points).to("cuda:0"), c.thr, maxdim=1) == (0, 0)
