@@ -123,7 +123,7 @@ def _cpu_baseline(cloud, budget_s=12.0):
                       f"(distances, sortperm, rank matrix, triangle triple loop, qsort); {el:.1f} s"}
 
 
-def _batched(vr, torch, reps=3):
+def _batched(vr, torch, reps=3, tune=True):
     """512 R^3 clouds (n log-uniform in [50, 2000], 5th-25th percentile) as
     one batched build, against the same clouds built one call at a time."""
     import workloads
@@ -132,6 +132,8 @@ def _batched(vr, torch, reps=3):
     pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
     thrs = [c.thr for c in clouds]
     torch.cuda.synchronize()
+    if tune:
+        vr.autotune(pts, thrs)  # one-time, untimed
     vr.build_batch(pts, thrs).free()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -253,6 +255,8 @@ def _main_batched(vr, torch, args):
     pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
     thrs = [c.thr for c in clouds]
     torch.cuda.synchronize()
+    if not args.no_tune:
+        vr.autotune(pts, thrs)  # one-time, untimed
     prev = None
     for _ in range(max(args.warmup, 2)):  # two results alive at once, as in the timed loop
         b = vr.build_batch(pts, thrs, timing="write")
@@ -312,6 +316,7 @@ def main():
     ap.add_argument("--qps", type=float, default=SERVE_QPS,
                     help="serving QPS; 0 measures 0.7 x the plain build's capacity instead")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
+    ap.add_argument("--no-tune", action="store_true", help="skip the one-time schedule autotuning")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--breakdown-reps", type=int, default=10, help="untimed builds for the stage breakdown (0: skip)")
     args = ap.parse_args()
@@ -335,6 +340,7 @@ def main():
     pts = torch.from_numpy(cloud.points).to("cuda:0")
     torch.cuda.synchronize()
 
+    tuned = vr.autotune(pts, cloud.thr) if not args.no_tune else None  # one-time, untimed
     el, counts, tri_ms = _time_builds(vr, torch, pts, cloud.thr, args.steps, args.warmup)
     n, K, T = counts
     simplices = n + K + T
@@ -355,6 +361,8 @@ def main():
     if not args.no_extra and args.workload == "circle1000":
         c3 = _workload("mixture4000")
         p3 = torch.from_numpy(c3.points).to("cuda:0")
+        if not args.no_tune:
+            vr.autotune(p3, c3.thr)
         e3, cnt3, t3 = _time_builds(vr, torch, p3, c3.thr, 10, 2)
         s3 = sum(cnt3)
         a3 = _alg_bytes(cnt3[0], cnt3[1], cnt3[2], cnt3[0] ** 2)
@@ -366,7 +374,7 @@ def main():
         del p3
 
     if not args.no_batch and args.workload == "circle1000":
-        extra["batched512_r3"] = _batched(vr, torch)
+        extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)
     if not args.no_serve and args.workload == "circle1000":
         extra["serving_poisson"] = _serving(vr, torch, qps=args.qps)
 
@@ -385,7 +393,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": cloud.name, "n": n, "d": cloud.d, "coords": str(cloud.points.dtype),
                    "threshold": f"{cloud.thr[0]} {cloud.thr[1]}/{cloud.thr[2]}", "kept_edges": K,
-                   "triangles": T, "simplices_per_build": simplices},
+                   "triangles": T, "simplices_per_build": simplices,
+                   "schedule": list(tuned) if tuned else "default"},
         "roofline": roofline,
         "stages_ms": st,
     }

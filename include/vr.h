@@ -129,6 +129,13 @@ typedef struct vr_result {
 VR_API int vr_build(const vr_request *req, void *stream, vr_result **out);
 
 /* counts[0..2] = (n, K, T).  Host only: no device call, no synchronisation. */
+
+/* Triangles of a result (or of a batch view) unpacked into T rows of four
+ * int32 (i, j, k, v), i < j < k, v = the value (largest edge rank), in the
+ * filtration order of tri_key.  `rows` is caller-owned device memory of
+ * 16*T bytes; enqueued on `stream` after the build's work.  VR_EINVAL for a
+ * null argument or a count-only result with triangles. */
+VR_API int vr_unpack_triangles(const vr_result *res, int32_t *rows, void *stream);
 VR_API int vr_query_counts(const vr_result *res, int64_t counts[3]);
 
 /*
@@ -193,17 +200,18 @@ VR_API int vr_batch_stage_ms(const vr_batch *batch, float *ms, int cap);
 VR_API void vr_batch_free(vr_batch *batch, void *stream);
 
 /*
- * Autotuning of the triangle kernels' schedule (work-groups per vertex),
- * for the size class of these requests (bits of their total vertex count and
- * of their mean degree).  Runs one build of the requests (as vr_build_batch),
- * then times the count and write kernels at 1, 2, 4, 8 and 16 work-groups
- * per vertex, keeps the fastest of each in a process-wide table that later
- * builds of the class use, and frees the build.  Schedules change no output.
- * Synchronises `stream`.  parts[0], parts[1] receive the chosen values (0
- * when the requests have no triangles).  Same error behaviour as
- * vr_build_batch.
+ * Autotuning of the triangle kernels' schedule (work-group size 256 or 512,
+ * and work-groups per vertex 1, 2, 4, 8 or 16) for the size class of these
+ * requests (bits of their total vertex count and of their mean degree).
+ * Runs one build of the requests (as vr_build_batch), then times the count
+ * and the write kernel at every schedule, keeps the fastest of each in a
+ * process-wide table that later builds of the class use, and frees the
+ * build.  Schedules change no output.  Synchronises `stream`.  sched[0..3]
+ * receive (count work-group size, count work-groups per vertex, write
+ * work-group size, write work-groups per vertex); all 0 when the requests
+ * have no triangles.  Same error behaviour as vr_build_batch.
  */
-VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t parts[2]);
+VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[4]);
 
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from

@@ -23,7 +23,7 @@ VR_MAX_POINTS = 8192
 VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
-SYMBOLS = ("vr_build", "vr_query_counts", "vr_query_stage_ms", "vr_stage_name", "vr_free",
+SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
            "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_trim",
            "vr_status_string", "vr_version")
 
@@ -105,6 +105,8 @@ def lib():
         L.vr_batch_stage_ms.restype = ctypes.c_int
         L.vr_batch_free.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.vr_batch_free.restype = None
+        L.vr_unpack_triangles.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_unpack_triangles.restype = ctypes.c_int
         L.vr_autotune.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_int32)]
         L.vr_autotune.restype = ctypes.c_int
@@ -252,6 +254,21 @@ class _Arrays:
 
         return self._tensor(self._p_tri, self.T, torch.int64, "<i8", 8, (self.T,))
 
+    def triangles(self):
+        """int32 (T, 4) rows (i, j, k, v) in filtration order, unpacked on the device."""
+        import torch
+
+        rows = torch.empty((self.T, 4), dtype=torch.int32, device=self._device)
+        if self.T == 0:
+            return rows
+        r = VrResult(self.n, self.K, self.T, self._p_ij, self._p_q, self._p_tri)
+        stream = torch.cuda.current_stream(self._device)
+        rc = lib().vr_unpack_triangles(ctypes.byref(r), ctypes.c_void_p(rows.data_ptr()),
+                                       ctypes.c_void_p(stream.cuda_stream))
+        if rc != VR_OK:
+            raise VrError(rc, status_string(rc))
+        return rows
+
 
 def _stage_dict(fn, handle):
     buf = (ctypes.c_float * 32)()
@@ -378,9 +395,9 @@ def _check_points(points):
 
 def autotune(points, thr, maxdim: int = 2):
     """Tune the triangle kernels' schedule for the size class of these clouds
-    (one tensor or a list, as build_batch); returns (parts_count,
-    parts_write), the work-groups per vertex that later builds of the class
-    use.  Outputs do not depend on the schedule."""
+    (one tensor or a list, as build_batch); returns (count block size, count
+    work-groups per vertex, write block size, write work-groups per vertex),
+    which later builds of the class use.  Outputs do not depend on it."""
     import torch
 
     L = lib()
@@ -389,12 +406,12 @@ def autotune(points, thr, maxdim: int = 2):
     dev = pts[0].device
     stream = torch.cuda.current_stream(dev)
     reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None) for p, t in zip(pts, thrs)])
-    parts = (ctypes.c_int32 * 2)()
+    sched = (ctypes.c_int32 * 4)()
     with torch.cuda.device(dev):
-        rc = L.vr_autotune(reqs, len(pts), ctypes.c_void_p(stream.cuda_stream), parts)
+        rc = L.vr_autotune(reqs, len(pts), ctypes.c_void_p(stream.cuda_stream), sched)
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
-    return int(parts[0]), int(parts[1])
+    return tuple(int(x) for x in sched)
 
 
 def batch_limit(dtype: int, d: int) -> int:

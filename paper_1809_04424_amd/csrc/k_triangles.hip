@@ -124,29 +124,32 @@ void launch_star(const VrDev &D, hipStream_t s) {
 // ------------------------------------------------- shared enumeration core ----
 // One work-group per vertex a with Pa[k] = position of edge {a,k} in a's
 // star (0xFFFF when k is no neighbour) staged in LDS.  The star is taken in
-// chunks of ENUM_BLOCK entries; the edges a owns in a chunk are compacted and
+// chunks of EB entries (EB = the work-group size, 256 or 512, a schedule
+// choice like the work-groups per vertex); the edges a owns in a chunk are compacted and
 // cut into wave-sized pieces of candidates; each wave takes a contiguous run
 // of whole edges holding about 1/8 of the pieces.  The metadata of up to 64
 // edges sits in lane registers; the loads of the next edge are issued before
 // the current edge is consumed.
-#define ENUM_BLOCK 512
-#define ENUM_WAVES (ENUM_BLOCK / VR_WAVE)
 #define VR_PIECES 8  // pieces of an edge loaded in one go (64 candidates each)
 
+template <int EB>
 struct EnumLds {
-    uint32_t r[ENUM_BLOCK];
-    uint32_t b[ENUM_BLOCK];
-    uint32_t sb[ENUM_BLOCK];      // start of the partner's star
-    uint32_t len[ENUM_BLOCK];     // candidates of the edge
-    uint32_t pb[ENUM_BLOCK];      // position of the edge in the partner's star
-    uint32_t xa[ENUM_BLOCK];      // position of the edge in a's star
-    uint32_t cb[ENUM_BLOCK + 1];  // first piece of the edge
-    uint32_t ew[ENUM_WAVES + 1];  // first edge of each wave
-    uint32_t scan[ENUM_WAVES];
-    uint32_t scan2[ENUM_WAVES];
+    static constexpr int W = EB / VR_WAVE;
+    uint32_t r[EB];
+    uint32_t b[EB];
+    uint32_t sb[EB];      // start of the partner's star
+    uint32_t len[EB];     // candidates of the edge
+    uint32_t pb[EB];      // position of the edge in the partner's star
+    uint32_t xa[EB];      // position of the edge in a's star
+    uint32_t cb[EB + 1];  // first piece of the edge
+    uint32_t ew[W + 1];   // first edge of each wave
+    uint32_t scan[W];
+    uint32_t scan2[W];
 };
 
+template <int EB>
 __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uint32_t *total) {
+    constexpr int ENUM_WAVES = EB / VR_WAVE;
     const uint32_t inc = wave_incl_scan_dpp(x);
     const int w = threadIdx.x / VR_WAVE;
     if (lane_id() == VR_WAVE - 1) sh[w] = inc;
@@ -163,15 +166,16 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
     return off + inc - x;
 }
 
-// Compact the edges a owns among star entries [p0, p0+ENUM_BLOCK) and split
+// Compact the edges a owns among star entries [p0, p0+EB) and split
 // them by piece count: `parts` work-groups share a vertex (part = this one's
 // index), each taking a contiguous slice, cut again into one run per wave.  WRITE: an edge is written at the
 // endpoint whose partner has the shorter star (candidates = the partner's
 // whole neighbour-ordered star).  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
-template <bool WRITE>
+template <bool WRITE, int EB>
 __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, uint32_t s0, uint32_t s1, uint32_t p0,
-                                          EnumLds &L, int part, int parts) {
+                                          EnumLds<EB> &L, int part, int parts) {
+    constexpr int ENUM_WAVES = EB / VR_WAVE;
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
@@ -192,9 +196,9 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
         }
     }
     uint32_t m, C;
-    const uint32_t idx = enum_excl_scan(owned ? 1u : 0u, L.scan, &m);
+    const uint32_t idx = enum_excl_scan<EB>(owned ? 1u : 0u, L.scan, &m);
     const uint32_t pieces = owned ? (len + VR_WAVE - 1) / VR_WAVE : 0u;
-    const uint32_t cbeg = enum_excl_scan(pieces, L.scan2, &C);
+    const uint32_t cbeg = enum_excl_scan<EB>(pieces, L.scan2, &C);
     if (owned) {
         L.r[idx] = r;
         L.b[idx] = b;
@@ -226,14 +230,16 @@ __device__ __forceinline__ uint32_t rl(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
+template <int EB>
 __device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, uint32_t s0, uint32_t s1) {
-    for (int k = threadIdx.x; k < n; k += ENUM_BLOCK) Pa[k] = 0xFFFF;
+    for (int k = threadIdx.x; k < n; k += EB) Pa[k] = 0xFFFF;
     __syncthreads();
-    for (uint32_t p = s0 + threadIdx.x; p < s1; p += ENUM_BLOCK) Pa[D.star_nbr[p]] = (uint16_t)(p - s0);
+    for (uint32_t p = s0 + threadIdx.x; p < s1; p += EB) Pa[D.star_nbr[p]] = (uint16_t)(p - s0);
     __syncthreads();
 }
 
-size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLds); }
+template <int EB>
+size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLds<EB>); }
 
 // Prefetch of one edge's candidates, VR_PIECES pieces of 64.  Every load is
 // issued unconditionally, with addresses clamped into valid memory, so that
@@ -265,7 +271,8 @@ __device__ __forceinline__ void issue_padded(const uint32_t *__restrict__ src, u
 }
 
 // ----------------------------------------------------------- k_tri_count ----
-__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
+template <int EB>
+__global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
     extern __shared__ uint32_t lds[];
     const long long ag = blockIdx.x / parts;
     const int part = blockIdx.x % parts;
@@ -273,12 +280,12 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_count(VrDev D, int parts) {
     const uint32_t vb = (uint32_t)D.cl[c].vbase;
     const int a = (int)(ag - vb), n = D.cl[c].n;
     uint16_t *Pa = (uint16_t *)lds;
-    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
+    EnumLds<EB> &L = *(EnumLds<EB> *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t s0 = D.start[ag], s1 = D.start[ag + 1];
-    stage_pos(D, n, Pa, s0, s1);
-    for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk<false>(D, a, vb, s0, s1, p0, L, part, parts);
+    stage_pos<EB>(D, n, Pa, s0, s1);
+    for (uint32_t p0 = s0; p0 < s1; p0 += EB) {
+        load_chunk<false, EB>(D, a, vb, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -335,9 +342,15 @@ int enum_parts(long long V) {
     return p < 1 ? 1 : (p > 8 ? 8 : (int)p);
 }
 
+// Work-group size, the default: 256 threads for small clouds (more
+// work-groups in flight), 512 for large ones (fewer chunk barriers).
+int enum_block(long long V) { return V <= 2048 ? 256 : 512; }
+
 void launch_tri_count(const VrDev &D, hipStream_t s) {
     const int parts = D.parts_count;
-    hipLaunchKernelGGL(k_tri_count, dim3((unsigned)(D.V * parts)), dim3(ENUM_BLOCK), enum_lds(D.maxn), s, D, parts);
+    const dim3 grid((unsigned)(D.V * parts));
+    if (D.eb_count == 256) hipLaunchKernelGGL(k_tri_count<256>, grid, dim3(256), enum_lds<256>(D.maxn), s, D, parts);
+    else hipLaunchKernelGGL(k_tri_count<512>, grid, dim3(512), enum_lds<512>(D.maxn), s, D, parts);
 }
 
 // ---------------------------------------------------------------- k_scan ----
@@ -457,14 +470,15 @@ __device__ __forceinline__ void emit_edges_range(const VrDev &D, long long K, ui
 
 // Blocks [0, n*parts) write triangles; the blocks after them write the
 // public edge arrays.
-__global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts,
+template <int EB>
+__global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts,
                                                           long long K, uint32_t *__restrict__ edge_ij,
                                                           long long *__restrict__ edge_q) {
     extern __shared__ uint32_t lds[];
     const long long nb = D.V * parts;
     if ((long long)blockIdx.x >= nb) {
-        emit_edges_range(D, K, edge_ij, edge_q, (long long)(blockIdx.x - nb) * ENUM_BLOCK + threadIdx.x,
-                         (long long)(gridDim.x - nb) * ENUM_BLOCK);
+        emit_edges_range(D, K, edge_ij, edge_q, (long long)(blockIdx.x - nb) * EB + threadIdx.x,
+                         (long long)(gridDim.x - nb) * EB);
         return;
     }
     const long long ag = blockIdx.x / parts;
@@ -474,12 +488,12 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
     const uint32_t kb = (uint32_t)kept_base(D, c);  // the cloud's ranks start here
     const int a = (int)(ag - vb), n = D.cl[c].n;
     uint16_t *Pa = (uint16_t *)lds;
-    EnumLds &L = *(EnumLds *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
+    EnumLds<EB> &L = *(EnumLds<EB> *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t s0 = D.start[ag], s1 = D.start[ag + 1];
-    stage_pos(D, n, Pa, s0, s1);
-    for (uint32_t p0 = s0; p0 < s1; p0 += ENUM_BLOCK) {
-        load_chunk<true>(D, a, vb, s0, s1, p0, L, part, parts);
+    stage_pos<EB>(D, n, Pa, s0, s1);
+    for (uint32_t p0 = s0; p0 < s1; p0 += EB) {
+        load_chunk<true, EB>(D, a, vb, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -557,12 +571,15 @@ __global__ __launch_bounds__(ENUM_BLOCK) void k_tri_write(VrDev D, unsigned long
 
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
                       hipStream_t s) {
-    const int parts = D.parts_write;
-    long long eb = (K + ENUM_BLOCK - 1) / ENUM_BLOCK;
+    const int parts = D.parts_write, EB = D.eb_write;
+    long long eb = (K + EB - 1) / EB;  // extra work-groups that write the edge arrays
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;
-    hipLaunchKernelGGL(k_tri_write, dim3((unsigned)(D.V * parts + eb)), dim3(ENUM_BLOCK), enum_lds(D.maxn), s, D,
-                       tri_out, parts, K, edge_ij, edge_q);
+    const dim3 grid((unsigned)(D.V * parts + eb));
+    if (EB == 256)
+        hipLaunchKernelGGL(k_tri_write<256>, grid, dim3(256), enum_lds<256>(D.maxn), s, D, tri_out, parts, K, edge_ij, edge_q);
+    else
+        hipLaunchKernelGGL(k_tri_write<512>, grid, dim3(512), enum_lds<512>(D.maxn), s, D, tri_out, parts, K, edge_ij, edge_q);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----
@@ -581,4 +598,23 @@ void launch_emit_edges(const VrDev &D, long long K, uint32_t *edge_ij, long long
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_emit_edges, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D, K, edge_ij, edge_q);
+}
+
+// ----------------------------------------------------------- k_unpack ----
+// Packed triangle keys -> rows (i, j, k, v) of int32, for callers that want
+// the filtration's triangles unpacked.
+__global__ __launch_bounds__(VR_BLOCK) void k_unpack(const unsigned long long *__restrict__ keys, long long T,
+                                                     int4 *__restrict__ rows) {
+    for (long long x = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; x < T; x += (long long)gridDim.x * VR_BLOCK) {
+        const unsigned long long k = keys[x];
+        rows[x] = make_int4((int)((k >> 26) & 0x1FFFu), (int)((k >> 13) & 0x1FFFu), (int)(k & 0x1FFFu),
+                            (int)(k >> 39));
+    }
+}
+
+void launch_unpack(const unsigned long long *keys, long long T, int *rows, hipStream_t s) {
+    long long g = (T + VR_BLOCK - 1) / VR_BLOCK;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_unpack, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, keys, T, (int4 *)rows);
 }

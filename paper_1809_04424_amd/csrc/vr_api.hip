@@ -198,11 +198,15 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 int bits_of(unsigned long long m);
 
 // Enumeration schedule picked by vr_autotune, per size class (bits of the
-// vertex count, bits of the mean degree): work-groups per vertex for the
-// count and the write.  Builds of a class never tuned use enum_parts.
+// vertex count, bits of the mean degree): work-group size and work-groups
+// per vertex, for the count and for the write.  Builds of a class never
+// tuned use enum_block and enum_parts.
+struct Sched {
+    int eb_count, parts_count, eb_write, parts_write;
+};
 struct Tuning {
     std::mutex mu;
-    std::map<std::pair<int, int>, std::pair<int, int>> parts;
+    std::map<std::pair<int, int>, Sched> sched;
 };
 Tuning &tuning() {
     static Tuning *t = new Tuning();
@@ -476,13 +480,16 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.need_hist = need_hist ? 1 : 0;
     D.tri = want_tri ? 1 : 0;
     D.parts_count = D.parts_write = enum_parts(V);
+    D.eb_count = D.eb_write = enum_block(V);
     {
         Tuning &tu = tuning();
         std::lock_guard<std::mutex> g(tu.mu);
-        auto it = tu.parts.find(size_class(V, Kmax));
-        if (it != tu.parts.end()) {
-            D.parts_count = it->second.first;
-            D.parts_write = it->second.second;
+        auto it = tu.sched.find(size_class(V, Kmax));
+        if (it != tu.sched.end()) {
+            D.eb_count = it->second.eb_count;
+            D.parts_count = it->second.parts_count;
+            D.eb_write = it->second.eb_write;
+            D.parts_write = it->second.parts_write;
         }
     }
     D.mailbox = g_host.mb_d;
@@ -644,38 +651,43 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     if (tune_out && want_tri) {
         // Time the count and the write at each schedule (both are idempotent:
         // every run writes the same counts and keys) and keep the fastest.
-        const int cand[] = {1, 2, 4, 8, 16};
+        const int cand_eb[] = {256, 512}, cand_p[] = {1, 2, 4, 8, 16};
         float best_c = 1e30f, best_w = 1e30f;
-        int pc = D.parts_count, pw = D.parts_write;
+        Sched best{D.eb_count, D.parts_count, D.eb_write, D.parts_write};
         hipEvent_t e[3];
         for (int i = 0; i < 3; i++)
             if (hipEventCreate(&e[i]) != hipSuccess) return fail(VR_EHIP, ws, P.total);
         for (int rep = 0; rep < 2; rep++)
-            for (int p : cand) {
-                if (V * p > (1ll << 30)) continue;
-                VrDev Dp = D;
-                Dp.parts_count = Dp.parts_write = p;
-                (void)hipEventRecord(e[0], s);
-                launch_tri_count(Dp, s);
-                (void)hipEventRecord(e[1], s);
-                if (write_tri) launch_tri_write(Dp, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
-                (void)hipEventRecord(e[2], s);
-                if (hipEventSynchronize(e[2]) != hipSuccess) break;
-                float tc = 0.f, tw = 0.f;
-                (void)hipEventElapsedTime(&tc, e[0], e[1]);
-                (void)hipEventElapsedTime(&tw, e[1], e[2]);
-                if (tc < best_c) { best_c = tc; pc = p; }
-                if (write_tri && tw < best_w) { best_w = tw; pw = p; }
-            }
+            for (int eb : cand_eb)
+                for (int p : cand_p) {
+                    if (V * p > (1ll << 30)) continue;
+                    VrDev Dp = D;
+                    Dp.eb_count = Dp.eb_write = eb;
+                    Dp.parts_count = Dp.parts_write = p;
+                    (void)hipEventRecord(e[0], s);
+                    launch_tri_count(Dp, s);
+                    (void)hipEventRecord(e[1], s);
+                    if (write_tri)
+                        launch_tri_write(Dp, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
+                    (void)hipEventRecord(e[2], s);
+                    if (hipEventSynchronize(e[2]) != hipSuccess) break;
+                    float tc = 0.f, tw = 0.f;
+                    (void)hipEventElapsedTime(&tc, e[0], e[1]);
+                    (void)hipEventElapsedTime(&tw, e[1], e[2]);
+                    if (tc < best_c) { best_c = tc; best.eb_count = eb; best.parts_count = p; }
+                    if (write_tri && tw < best_w) { best_w = tw; best.eb_write = eb; best.parts_write = p; }
+                }
         for (int i = 0; i < 3; i++) (void)hipEventDestroy(e[i]);
         if (hipGetLastError() != hipSuccess) return fail(VR_EHIP, ws, P.total);
         {
             Tuning &tu = tuning();
             std::lock_guard<std::mutex> g(tu.mu);
-            tu.parts[size_class(V, Kmax)] = {pc, pw};
+            tu.sched[size_class(V, Kmax)] = best;
         }
-        tune_out[0] = pc;
-        tune_out[1] = pw;
+        tune_out[0] = best.eb_count;
+        tune_out[1] = best.parts_count;
+        tune_out[2] = best.eb_write;
+        tune_out[3] = best.parts_write;
     }
     A.put(ws, P.total);
     return VR_OK;
@@ -754,16 +766,15 @@ int64_t vr_batch_workspace_bytes(const vr_request *reqs, int64_t count) {
     return S.C == 0 ? 0 : (int64_t)plan_of(S).total;
 }
 
-int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t parts[2]) {
-    if (!reqs || count < 1 || !parts) return VR_EINVAL;
+int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[4]) {
+    if (!reqs || count < 1 || !sched) return VR_EINVAL;
     vr_batch *b = new (std::nothrow) vr_batch();
     if (!b) return VR_ENOMEM;
-    int32_t chosen[2] = {0, 0};
+    int32_t chosen[4] = {0, 0, 0, 0};
     const int st = build_impl(reqs, count, (hipStream_t)stream, b->own, b->views, chosen);
     if (st == VR_OK) {
         b->own.release((hipStream_t)stream);
-        parts[0] = chosen[0];
-        parts[1] = chosen[1];
+        for (int i = 0; i < 4; i++) sched[i] = chosen[i];
     }
     delete b;
     return st;
@@ -791,6 +802,14 @@ int vr_batch_result(const vr_batch *b, int64_t index, vr_result *view) {
 int vr_batch_stage_ms(const vr_batch *b, float *ms, int cap) {
     if (!b || (!ms && cap > 0)) return VR_EINVAL;
     return b->own.stage_ms(ms, cap);
+}
+
+int vr_unpack_triangles(const vr_result *res, int32_t *rows, void *stream) {
+    if (!res || (!rows && res->n_triangles > 0)) return VR_EINVAL;
+    if (res->n_triangles == 0) return VR_OK;
+    if (!res->tri_key) return VR_EINVAL;  // a count-only build has no keys
+    launch_unpack((const unsigned long long *)res->tri_key, res->n_triangles, rows, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
 }
 
 int64_t vr_trim(void) { return (int64_t)cache_trim(); }

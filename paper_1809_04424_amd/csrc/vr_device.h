@@ -412,6 +412,7 @@ struct VrDev {
     int need_hist;          // histogram select needed (COUNT / FRACTION)
     int tri;                // triangles wanted
     int parts_count, parts_write;  // work-groups per vertex in the enumeration kernels
+    int eb_count, eb_write;        // their work-group sizes (256 or 512)
     // workspace
     VrCtl *ctl;
     VrMailbox *mailbox;     // host-pinned
@@ -496,8 +497,10 @@ void launch_hist_fold(uint32_t *h0, int stride, int bins, hipStream_t s);
 void launch_edges(const VrDev &D, hipStream_t s);
 void launch_star(const VrDev &D, hipStream_t s);
 int enum_parts(long long V);
+int enum_block(long long V);
 void launch_tri_count(const VrDev &D, hipStream_t s);
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
                       hipStream_t s);
 void launch_emit_edges(const VrDev &D, long long K, uint32_t *edge_ij, long long *edge_q, hipStream_t s);
+void launch_unpack(const unsigned long long *keys, long long T, int *rows, hipStream_t s);

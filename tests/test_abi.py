@@ -137,9 +137,18 @@ def test_batch_workspace_bytes():
 
 def test_autotune_rejects_bad_arguments():
     L = vr.lib()
-    parts = (ctypes.c_int32 * 2)()
+    parts = (ctypes.c_int32 * 4)()
     assert L.vr_autotune(None, 1, None, parts) == vr.VR_EINVAL
     arr = (vr.VrRequest * 1)(_req())
     assert L.vr_autotune(arr, 1, None, None) == vr.VR_EINVAL
     arr = (vr.VrRequest * 1)(_req(d=0))
     assert L.vr_autotune(arr, 1, None, parts) == vr.VR_EINVAL
+
+
+def test_unpack_rejects_bad_arguments():
+    L = vr.lib()
+    assert L.vr_unpack_triangles(None, None, None) == vr.VR_EINVAL
+    r = vr.VrResult(10, 5, 3, None, None, None)  # count-only result: no keys
+    assert L.vr_unpack_triangles(ctypes.byref(r), 16, None) == vr.VR_EINVAL
+    empty = vr.VrResult(10, 5, 0, None, None, None)
+    assert L.vr_unpack_triangles(ctypes.byref(empty), None, None) == vr.VR_OK

@@ -232,3 +232,17 @@ def test_largest_point_count(orc):
     _say("[gpu] n=8192 build")
     _, out = gpu_build(c)
     assert_matches_oracle(out, f)
+
+
+def test_unpacked_triangles(orc):
+    import workloads as wl
+
+    c = wl.uniform_cloud(77, 150, 3, lo=-40, hi=40)
+    c.thr = ("fraction", 30, 100)
+    r, out = gpu_build(c)
+    rows = r.triangles().cpu().numpy()
+    f = orc.build(c.points, c.thr)
+    # oracle rows are (v, i, j, k); the unpacked rows are (i, j, k, v)
+    assert rows.shape == (f.T, 4)
+    assert np.array_equal(rows[:, :3], f.tris[:, 1:]) and np.array_equal(rows[:, 3], f.tris[:, 0])
+    r.free()

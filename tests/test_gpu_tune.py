@@ -15,7 +15,8 @@ def test_autotune_then_build_matches_oracle(orc):
 
     c = workloads.noisy_circle(n=600)
     pts = torch.from_numpy(c.points).to("cuda:0")
-    pc, pw = vr.autotune(pts, c.thr)
+    ebc, pc, ebw, pw = vr.autotune(pts, c.thr)
+    assert ebc in (256, 512) and ebw in (256, 512)
     assert pc in (1, 2, 4, 8, 16) and pw in (1, 2, 4, 8, 16)
     r, out = gpu_build(c)
     assert_matches_oracle(out, orc.build(c.points, c.thr))
@@ -31,8 +32,8 @@ def test_autotune_batch_then_build_batch(orc):
     for c in clouds:
         c.thr = ("fraction", 25, 100)
     pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
-    pc, pw = vr.autotune(pts, [c.thr for c in clouds])
-    assert pc >= 1 and pw >= 1
+    sched = vr.autotune(pts, [c.thr for c in clouds])
+    assert min(sched) >= 1
     b, outs = gpu_build_batch(clouds)
     for c, out in zip(clouds, outs):
         assert_matches_oracle(out, orc.build(c.points, c.thr))
@@ -46,4 +47,4 @@ def test_autotune_without_triangles():
 
     c = workloads.uniform_cloud(5, 50, 3)
     c.thr = ("fraction", 10, 100)
-    assert vr.autotune(torch.from_numpy(c.points).to("cuda:0"), c.thr, maxdim=1) == (0, 0)
+    assert vr.autotune(torch.from_numpy(c.points).to("cuda:0"), c.thr, maxdim=1) == (0, 0, 0, 0)
