@@ -13,8 +13,8 @@
 //   k_sort_pass  one stable 8-bit LSD pass (Onesweep: Adinets and Merrill,
 //                2022), skipped when every key shares the digit; keys are
 //                (cloud << qbits) | q, so clouds stay apart
-//   k_edges      the kept edges of every cloud in rank order, and their two
-//                vertex incidences for the star sort
+//   k_edges      the kept edges of every cloud in rank order, and their
+//                ranks scattered into each cloud's rank matrix
 #include "vr_device.h"
 
 // --------------------------------------------------------------- k_init ----
@@ -402,18 +402,6 @@ SortJob edge_sort_job(const VrDev &D) {
     return J;
 }
 
-SortJob star_sort_job(const VrDev &D) {
-    SortJob J;
-    J.key[0] = D.ikey[0]; J.key[1] = D.ikey[1];
-    J.val[0] = D.ival[0]; J.val[1] = D.ival[1];
-    J.hist = &D.ctl->hinc[0][0][0];  // copy 0, folded
-    J.ticket = &D.ctl->ticket[6];
-    J.st[0] = D.ist[0]; J.st[1] = D.ist[1];
-    J.count = &D.ctl->n_inc;
-    J.passes = D.spasses;
-    return J;
-}
-
 // ---------------------------------------------------------- k_sort_pass ----
 // Tiles of 2048 keys; each wave ranks its 512 keys among equal digits in
 // order (8 ballots per 64 keys), the work-group combines the waves, one
@@ -695,11 +683,10 @@ void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream
 
 // -------------------------------------------------------------- k_edges ----
 // Kept edge g of cloud c is the (g - kbase_c)-th candidate of the cloud in
-// sorted order.  With triangles wanted, also the vertex incidences
-// (global vertex, 2g+s) in rank order plus their digit histograms, input of
-// the stable star sort, and clear its first statuses.
+// sorted order.  With triangles wanted, its rank within the cloud, tagged
+// with the build's tag in the top byte, also goes to entries [i][j] and
+// [j][i] of the cloud's rank matrix, which k_rows turns into stars.
 __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
-    __shared__ uint32_t h[3][VR_RADIX];
     VrCtl *ctl = D.ctl;
     const int a = active_before(&ctl->hist8[0][0][0], D.passes, VR_MAX_PASSES, nullptr);
     const uint32_t *__restrict__ kf = D.key[a & 1];
@@ -708,59 +695,24 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
     const uint32_t qmask = (D.qbits >= 32) ? 0xFFFFFFFFu : ((1u << D.qbits) - 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->n_kept = (uint32_t)K;
-        ctl->n_inc = (uint32_t)(2 * K);
         // without triangles this is the last phase-1 kernel of a single build
         if (!D.tri && D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, (uint32_t)K, 0ull);
     }
-    if (D.tri) {
-        for (int x = threadIdx.x; x < 3 * VR_RADIX; x += VR_BLOCK) (&h[0][0])[x] = 0u;
-        __syncthreads();
-        const long long words = (2 * K + VR_TILE - 1) / VR_TILE * VR_RADIX;
-        for (long long x = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; x < words; x += (long long)gridDim.x * VR_BLOCK)
-            D.ist[0][x] = 0u;
-    }
-    const long long Kr = (K + VR_BLOCK - 1) / VR_BLOCK * VR_BLOCK;  // whole waves take part in narrow_add
-    for (long long g = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; g < Kr; g += (long long)gridDim.x * VR_BLOCK) {
-        const bool ok = g < K;
-        uint32_t vi = 0, vj = 0;
-        if (ok) {
-            const int c = (D.thr_kind == 3)  // kept bases known only on the device: search
-                              ? cloud_of(g, D.C, [&](int k) { return kept_base(D, k); })
-                              : cloud_from_map(D, D.kcloud, g, VR_BLOCK, [&](int k) { return D.cl[k].kbase; });
-            const long long sp = (long long)D.cs[c].cand_base + (g - kept_base(D, c));
-            const uint32_t k = kf[sp], v = vf[sp];
-            D.se_q[g] = k & qmask;
-            D.se_ij[g] = v;
-            const uint32_t vb = (uint32_t)D.cl[c].vbase;
-            vi = vb + (v >> 16);
-            vj = vb + (v & 0xFFFFu);
-            if (D.tri) {
-                D.ikey[0][2 * g] = vi;
-                D.ikey[0][2 * g + 1] = vj;
-                D.ival[0][2 * g] = (uint32_t)(2 * g);
-                D.ival[0][2 * g + 1] = (uint32_t)(2 * g + 1);
-            }
-        }
+    for (long long g = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; g < K; g += (long long)gridDim.x * VR_BLOCK) {
+        const int c = (D.thr_kind == 3)  // kept bases known only on the device: search
+                          ? cloud_of(g, D.C, [&](int k) { return kept_base(D, k); })
+                          : cloud_from_map(D, D.kcloud, g, VR_BLOCK, [&](int k) { return D.cl[k].kbase; });
+        const long long lr = g - kept_base(D, c);  // rank within the cloud
+        const long long sp = (long long)D.cs[c].cand_base + lr;
+        const uint32_t k = kf[sp], v = vf[sp];
+        D.se_q[g] = k & qmask;
+        D.se_ij[g] = v;
         if (D.tri) {
-            // vertex digits: the low ones are spread, the top one takes few values
-#pragma unroll
-            for (int ps = 0; ps < 2; ps++) {
-                if (ps < D.spasses - 1) {
-                    spread_add(h[ps], (vi >> (8 * ps)) & 255u, ok);
-                    spread_add(h[ps], (vj >> (8 * ps)) & 255u, ok);
-                }
-            }
-            const int top = D.spasses - 1;
-            narrow_add<8>(h[top], (vi >> (8 * top)) & 255u, ok);
-            narrow_add<8>(h[top], (vj >> (8 * top)) & 255u, ok);
-        }
-    }
-    if (D.tri) {
-        __syncthreads();
-        uint32_t *gh = hist_copy(&ctl->hinc[0][0][0], VR_HINC_STRIDE);
-        for (int x = threadIdx.x; x < 3 * VR_RADIX; x += VR_BLOCK) {
-            const uint32_t c = (&h[0][0])[x];
-            if (c) atomicAdd(&gh[x], c);
+            // rank matrix: (tag, rank) at [i][j] and [j][i] of the cloud's star slots
+            const uint32_t mb = (uint32_t)D.cl[c].mbase, n = (uint32_t)D.cl[c].n;
+            const uint32_t i = v >> 16, j = v & 0xFFFFu, e = (D.tag << 24) | (uint32_t)lr;
+            D.star_r[mb + i * n + j] = e;
+            D.star_r[mb + j * n + i] = e;
         }
     }
 }

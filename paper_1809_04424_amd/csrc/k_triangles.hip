@@ -10,12 +10,11 @@
 // triples increase with k, and the offsets follow rank order, so the output
 // is written in (value, i, j, k) order with no sort.
 //
-//   k_star        CSR stars in rank order from the stably sorted incidences
-//                 (a stable per-column ordering, like the paper's
-//                 integersinsameorderbycolumn, Section 4.3)
-//   k_kstar       per vertex: the position of every edge in its stars, and
-//                 the star again in neighbour order, each entry packing
-//                 (neighbour | position in the rank-ordered star << 16)
+//   k_rows        per vertex: its row of the rank matrix, sorted by rank in
+//                 LDS (the paper's per-column ordering, Section 4.3), gives
+//                 the rank-ordered star, the position of each of its edges
+//                 there, and the star again in neighbour order, each entry
+//                 packing (neighbour | position in the rank-ordered star << 16)
 //   k_tri_count   per vertex a: for each edge a owns, count the neighbours in
 //                 the partner's rank prefix that precede the edge in a's star
 //   k_scan        exclusive scan of the counts (decoupled look-back); the
@@ -27,98 +26,219 @@
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
-#define VR_MAXN 8192
-
-__device__ __forceinline__ int star_parity(const VrDev &D) {
-    // parity of the active passes of the star sort, from its histograms
-    __shared__ int sh_nz[3];
-    if (threadIdx.x < 3) sh_nz[threadIdx.x] = 0;
-    __syncthreads();
-    for (int x = threadIdx.x; x < D.spasses * VR_RADIX; x += VR_BLOCK)
-        if (D.ctl->hinc[0][0][x]) atomicAdd(&sh_nz[x / VR_RADIX], 1);  // copy 0, folded
-    __syncthreads();
-    const int a = (sh_nz[0] > 1 ? 1 : 0) + (sh_nz[1] > 1 ? 1 : 0) + (sh_nz[2] > 1 ? 1 : 0);
-    __syncthreads();
-    return a & 1;
-}
-
 // Cloud of global vertex v, and v's local index.
 __device__ __forceinline__ int vertex_cloud(const VrDev &D, long long v) {
     return (D.C == 1) ? 0 : (int)D.vcloud[v];
 }
 
-// --------------------------------------------------------------- k_star ----
-__global__ __launch_bounds__(VR_BLOCK) void k_star(VrDev D) {
-    const VrCtl *ctl = D.ctl;
-    const int par = star_parity(D);
-    const uint32_t *__restrict__ kf = D.ikey[par];
-    const uint32_t *__restrict__ vf = D.ival[par];
-    const long long m = (long long)ctl->n_inc;
-    const long long n = D.V;  // row starts over all vertices of the batch
-    if (m == 0) {
-        if (blockIdx.x == 0)
-            for (long long u = threadIdx.x; u <= n; u += VR_BLOCK) D.start[u] = 0u;
-        return;
+// --------------------------------------------------------------- k_rows ----
+// Star slots: vertex v of a cloud with n points owns n entries of star_r
+// and star_nbr at star_slot(mbase, n, v), and of star_k 64 entries further
+// per preceding vertex, which leaves room for its 64 sentinels.
+#define STAR_SENTINEL 0xFFFF0000u  // neighbour 0, position 0xFFFF
+__device__ __forceinline__ uint32_t star_slot(uint32_t mbase, int n, int v) { return mbase + (uint32_t)v * (uint32_t)n; }
+__device__ __forceinline__ uint32_t star_k_base(uint32_t s0, long long v) { return s0 + 64u * (uint32_t)v; }
+
+// One work-group per vertex v reads row v of the rank matrix that k_edges
+// scattered into v's star_r slot (entry k = this build's tag << 24 | rank
+// of edge {v,k} within the cloud).  Entries of pairs that are not kept are
+// left from earlier use of the memory: an entry counts only when it carries
+// the tag and names a kept edge of this cloud whose endpoints are {v, k} in
+// the sorted edge list, so the matrix is never cleared (the paper avoids
+// re-initialising its per-column work array the same way, Section 4.3); the
+// tag only spares most stale entries the look-up (the stars written over
+// the rows carry tag 0, and tags repeat only every 255 builds).  The kept entries, in neighbour order, are sorted
+// by rank in LDS (bitonic), which orders v's edges the way the paper's
+// per-column ordering of the distance matrix does (Section 4.3).  Outputs:
+// v's star in rank order (rank within the cloud, written over the row, and
+// the neighbour), each edge's position in it (pos), the star in neighbour
+// order with those positions (star_k, then 64 sentinels) and its size.
+//
+// Wave w reads the row's entries [64 S w, 64 S (w+1)) in S steps of 64, so
+// the neighbour order is the order of (wave, step, lane); S * 256 >= n.
+#define VR_ROWS_COUNT_MAX 512  // largest star ranked by counting (two keys per thread)
+
+// Counting rank of a star of 1 <= deg <= NK * 256 entries: keys[x] = rank of the
+// x-th neighbour (padded to a multiple of 4 with ~0), nbr[x] = that
+// neighbour.  Writes the star in rank order over the row, its neighbours,
+// the edges' positions, and the neighbour-ordered star.
+template <int NK>
+__device__ __forceinline__ void rows_count_rank(const VrDev &D, const uint32_t *keys, const uint16_t *nbr, uint32_t deg,
+                                                uint32_t *__restrict__ row, uint32_t s0, uint32_t *__restrict__ sk,
+                                                int v, long long kb) {
+    uint32_t own[NK], y[NK];
+#pragma unroll
+    for (int i = 0; i < NK; i++) {
+        const uint32_t x = threadIdx.x + VR_BLOCK * i;
+        own[i] = keys[min(x, deg - 1)];
+        y[i] = 0;
     }
-    for (long long p = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; p < m; p += (long long)gridDim.x * VR_BLOCK) {
-        const uint32_t v = kf[p], x = vf[p];
-        const uint32_t r = x >> 1;
-        const uint32_t ij = D.se_ij[r];
-        D.star_r[p] = r;
-        D.star_nbr[p] = (uint16_t)((x & 1u) ? (ij >> 16) : (ij & 0xFFFFu));
-        const long long prev = (p == 0) ? -1 : (long long)kf[p - 1];
-        for (long long u = prev + 1; u <= (long long)v; u++) D.start[u] = (uint32_t)p;
-        if (p == m - 1)
-            for (long long u = (long long)v + 1; u <= n; u++) D.start[u] = (uint32_t)m;
+    const uint4 *k4 = (const uint4 *)keys;
+    for (uint32_t q = 0; q < (deg + 3) / 4; q++) {
+        const uint4 e = k4[q];
+#pragma unroll
+        for (int i = 0; i < NK; i++)
+            y[i] += (uint32_t)(e.x < own[i]) + (uint32_t)(e.y < own[i]) + (uint32_t)(e.z < own[i]) + (uint32_t)(e.w < own[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NK; i++) {
+        const uint32_t x = threadIdx.x + VR_BLOCK * i;
+        if (x < deg) {
+            const uint32_t k = nbr[x], lr = own[i];
+            row[y[i]] = lr;
+            D.star_nbr[s0 + y[i]] = (uint16_t)k;
+            D.pos[2 * (kb + lr) + (k > (uint32_t)v ? 0 : 1)] = (uint16_t)y[i];
+            sk[x] = k | (y[i] << 16);
+        }
     }
 }
 
-// Neighbour-ordered stars are padded: vertex v's entries start at
-// start[v] + 64 v and are followed by 64 sentinel entries.
-#define STAR_SENTINEL 0xFFFF0000u  // neighbour 0, position 0xFFFF
-__device__ __forceinline__ uint32_t star_k_base(uint32_t s0, long long v) { return s0 + 64u * (uint32_t)v; }
-
-// -------------------------------------------------------------- k_kstar ----
-// One work-group per vertex v (n <= 8192, so its <= 128 bitset words fit one
-// pass of 256 threads).
-__global__ __launch_bounds__(VR_BLOCK) void k_kstar(VrDev D) {
-    __shared__ uint16_t P[VR_MAXN];
-    __shared__ unsigned long long bits[VR_MAXN / 64];
+template <int S>
+__global__ __launch_bounds__(VR_BLOCK) void k_rows(VrDev D) {
+    extern __shared__ uint32_t lds[];  // P sort keys, then the position of each neighbour (u16)
     __shared__ uint32_t sh_w[VR_WAVES];
     const long long vg = blockIdx.x;
     const int c = vertex_cloud(D, vg);
-    const int v = (int)(vg - D.cl[c].vbase), n = D.cl[c].n, t = threadIdx.x;
-    const int W = (n + 63) >> 6;
-    const uint32_t s0 = D.start[vg], s1 = D.start[vg + 1];
-    if (t < W) bits[t] = 0ull;
+    const int v = (int)(vg - D.cl[c].vbase), n = D.cl[c].n;
+    const long long kb = kept_base(D, c), Kc = kept_count(D, c);
+    const uint32_t s0 = star_slot((uint32_t)D.cl[c].mbase, n, v);
+    uint32_t *__restrict__ row = D.star_r + s0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int per = (n + VR_BLOCK - 1) / VR_BLOCK;  // steps this launch needs (<= S)
+    // Loads are issued unconditionally at clamped addresses: a guarded load
+    // makes the compiler wait for it before the next one is issued.
+    uint32_t rr[S];
+#pragma unroll
+    for (int s = 0; s < S; s++) rr[s] = row[min((w * per + s) * VR_WAVE + lane, n - 1)];
+    // keep an entry when it names a kept edge {v, k} of this cloud; rr = rank within the cloud
+    unsigned long long mk[S];  // kept entries of each step (wave-uniform)
+    uint32_t cw = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const int k = (w * per + s) * VR_WAVE + lane;
+        const uint32_t lr = rr[s] & 0xFFFFFFu;
+        const bool in = s < per && k < n && k != v && (rr[s] >> 24) == D.tag && (long long)lr < Kc;
+        const uint32_t ij = D.se_ij[kb + (in ? lr : 0u)];  // kept base itself when not in (se_ij has room)
+        const uint32_t want = (k < v) ? (((uint32_t)k << 16) | (uint32_t)v) : (((uint32_t)v << 16) | (uint32_t)k);
+        const bool kept = in && ij == want;
+        rr[s] = lr;
+        mk[s] = __builtin_amdgcn_ballot_w64(kept);
+        cw += (uint32_t)__popcll(mk[s]);
+    }
+    if (lane == 0) sh_w[w] = cw;
     __syncthreads();
-    for (uint32_t p = s0 + t; p < s1; p += VR_BLOCK) {
-        const uint32_t k = D.star_nbr[p], r = D.star_r[p], x = p - s0;
-        P[k] = (uint16_t)x;
-        atomicOr(&bits[k >> 6], 1ull << (k & 63));
-        D.pos[2 * (size_t)r + (k > (uint32_t)v ? 0 : 1)] = (uint16_t)x;
+    uint32_t run = 0, deg = 0;
+#pragma unroll
+    for (int i = 0; i < VR_WAVES; i++) {
+        const uint32_t t = sh_w[i];
+        if (i < w) run += t;
+        deg += t;
+    }
+    // sort keys: local ranks in neighbour order (entry x = x-th kept
+    // neighbour), padded; small stars are ranked by counting, larger ones
+    // sorted (bitonic)
+    uint32_t P = VR_WAVE;
+    while (P < deg) P <<= 1;
+    const bool by_count = deg <= VR_ROWS_COUNT_MAX;
+    // counting: the neighbour of entry x; bitonic: the position of neighbour k
+    uint16_t *pk = (uint16_t *)(lds + P);
+    for (uint32_t y = deg + threadIdx.x; y < P; y += VR_BLOCK) lds[y] = 0xFFFFFFFFu;
+    {
+        uint32_t x = run;
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk[s] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[s], x));
+            if ((mk[s] >> lane) & 1ull) {
+                lds[at] = rr[s];
+                if (by_count) pk[at] = (uint16_t)((w * per + s) * VR_WAVE + lane);
+            }
+            x += (uint32_t)__popcll(mk[s]);
+        }
     }
     __syncthreads();
-    unsigned long long word = (t < W) ? bits[t] : 0ull;
-    uint32_t tot;
-    uint32_t q = block_excl_scan<uint32_t>((uint32_t)__popcll(word), sh_w, &tot);
     uint32_t *sk = D.star_k + star_k_base(s0, vg);
-    while (word) {
-        const uint32_t k = (uint32_t)(t * 64 + __ffsll((long long)word) - 1);
-        sk[q++] = k | ((uint32_t)P[k] << 16);
-        word &= word - 1ull;
+    if (by_count) {
+        // rank-order position of entry x = number of smaller keys (ranks
+        // are distinct); every lane reads the same keys, which LDS
+        // broadcasts
+        if (deg == 0) {
+        } else if (deg <= VR_BLOCK) {
+            rows_count_rank<1>(D, lds, pk, deg, row, s0, sk, v, kb);
+        } else {
+            rows_count_rank<2>(D, lds, pk, deg, row, s0, sk, v, kb);
+        }
+    } else {
+        // Bitonic sort.  Wave w's pairs in a stage with distance j <= 64 lie
+        // in its own 128-key blocks, so only stages with j >= 128 exchange
+        // keys between waves and need the work-group barrier; the others
+        // need the wave's LDS accesses in order, which a wave's LDS
+        // instructions are.
+        for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+                if (j >= 2 * VR_WAVE) __syncthreads();
+                for (uint32_t i = threadIdx.x; i < P / 2; i += VR_BLOCK) {
+                    const uint32_t lo = 2 * i - (i & (j - 1)), hi = lo + j;
+                    const uint32_t x0 = lds[lo], x1 = lds[hi];
+                    if ((x0 > x1) == ((lo & kk) == 0)) {
+                        lds[lo] = x1;
+                        lds[hi] = x0;
+                    }
+                }
+                if (j >= 2 * VR_WAVE) __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        // rank order: entry y is the y-th smallest rank; its neighbour comes
+        // from the edge list (lanes past the star repeat the last entry's
+        // loads and store nothing)
+        uint32_t ij[S];
+#pragma unroll
+        for (int i = 0; i < S; i++) ij[i] = D.se_ij[kb + lds[min(threadIdx.x + VR_BLOCK * i, deg - 1)]];
+#pragma unroll
+        for (int i = 0; i < S; i++) {
+            const uint32_t y = threadIdx.x + VR_BLOCK * i;
+            if (y < deg) {
+                const uint32_t lr = lds[y];
+                const uint32_t k = ((ij[i] >> 16) == (uint32_t)v) ? (ij[i] & 0xFFFFu) : (ij[i] >> 16);
+                row[y] = lr;
+                D.star_nbr[s0 + y] = (uint16_t)k;
+                D.pos[2 * (kb + lr) + (k > (uint32_t)v ? 0 : 1)] = (uint16_t)y;
+                pk[k] = (uint16_t)y;
+            }
+        }
+        __syncthreads();
+        uint32_t x = run;
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const uint32_t k = (uint32_t)((w * per + s) * VR_WAVE + lane);
+            const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk[s] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[s], x));
+            if ((mk[s] >> lane) & 1ull) sk[at] = k | ((uint32_t)pk[k] << 16);
+            x += (uint32_t)__popcll(mk[s]);
+        }
     }
     // 64 sentinels after the star: position 0xFFFF fails every prefix test,
     // so a piece may run past the star's end without a bounds test
-    if (t < VR_WAVE) sk[(s1 - s0) + t] = STAR_SENTINEL;
+    if (threadIdx.x < VR_WAVE) sk[deg + threadIdx.x] = STAR_SENTINEL;
+    if (threadIdx.x == 0) D.deg[vg] = deg;
 }
 
-void launch_star(const VrDev &D, hipStream_t s) {
-    long long g = (2 * ((D.thr_kind == 3) ? D.E : D.K_host) + VR_BLOCK - 1) / VR_BLOCK;
-    if (g > 1024) g = 1024;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_star, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
-    hipLaunchKernelGGL(k_kstar, dim3((unsigned)D.V), dim3(VR_BLOCK), 0, s, D);
+static uint32_t pow2_at_least(uint32_t x) {
+    uint32_t p = VR_WAVE;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+void launch_rows(const VrDev &D, hipStream_t s) {
+    const int steps = (D.maxn + VR_BLOCK - 1) / VR_BLOCK;
+    // sort keys (P <= pow2(maxn)) and the positions of the neighbours
+    const size_t lds = 4 * (size_t)pow2_at_least((uint32_t)D.maxn) + 2 * (size_t)((D.maxn + 1) & ~1);
+    const dim3 grid((unsigned)D.V);
+    if (steps <= 4) hipLaunchKernelGGL(k_rows<4>, grid, dim3(VR_BLOCK), lds, s, D);
+    else if (steps <= 8) hipLaunchKernelGGL(k_rows<8>, grid, dim3(VR_BLOCK), lds, s, D);
+    else if (steps <= 16) hipLaunchKernelGGL(k_rows<16>, grid, dim3(VR_BLOCK), lds, s, D);
+    else hipLaunchKernelGGL(k_rows<32>, grid, dim3(VR_BLOCK), lds, s, D);
 }
 
 // ------------------------------------------------- shared enumeration core ----
@@ -173,20 +293,21 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 // whole neighbour-ordered star).  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
 template <bool WRITE, int EB>
-__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, uint32_t s0, uint32_t s1, uint32_t p0,
-                                          EnumLds<EB> &L, int part, int parts) {
+__device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, uint32_t mb, int n, uint32_t kb,
+                                          uint32_t s0, uint32_t s1, uint32_t p0, EnumLds<EB> &L, int part,
+                                          int parts) {
     constexpr int ENUM_WAVES = EB / VR_WAVE;
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
     const uint32_t x = p - s0;
     if (p < s1) {
-        r = D.star_r[p];
+        r = kb + D.star_r[p];  // global kept-edge index
         b = D.star_nbr[p];
         pb = D.pos[2 * (size_t)r + (b > (uint32_t)a ? 1 : 0)];
-        sb = D.start[vb + b];
+        sb = star_slot(mb, n, (int)b);
         if (WRITE) {
-            const uint32_t db = D.start[vb + b + 1] - sb, da = s1 - s0;
+            const uint32_t db = D.deg[vb + b], da = s1 - s0;
             owned = db < da || (db == da && (uint32_t)a < b);
             len = db;
             sb = star_k_base(sb, vb + b);
@@ -282,10 +403,11 @@ __global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
     uint16_t *Pa = (uint16_t *)lds;
     EnumLds<EB> &L = *(EnumLds<EB> *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t s0 = D.start[ag], s1 = D.start[ag + 1];
+    const uint32_t mb = (uint32_t)D.cl[c].mbase, kb = (uint32_t)kept_base(D, c);
+    const uint32_t s0 = star_slot(mb, n, a), s1 = s0 + D.deg[ag];
     stage_pos<EB>(D, n, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += EB) {
-        load_chunk<false, EB>(D, a, vb, s0, s1, p0, L, part, parts);
+        load_chunk<false, EB>(D, a, vb, mb, n, kb, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -490,10 +612,11 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
     uint16_t *Pa = (uint16_t *)lds;
     EnumLds<EB> &L = *(EnumLds<EB> *)((char *)lds + 2 * ((D.maxn + 7) & ~7));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t s0 = D.start[ag], s1 = D.start[ag + 1];
+    const uint32_t mb = (uint32_t)D.cl[c].mbase;
+    const uint32_t s0 = star_slot(mb, n, a), s1 = s0 + D.deg[ag];
     stage_pos<EB>(D, n, Pa, s0, s1);
     for (uint32_t p0 = s0; p0 < s1; p0 += EB) {
-        load_chunk<true, EB>(D, a, vb, s0, s1, p0, L, part, parts);
+        load_chunk<true, EB>(D, a, vb, mb, n, kb, s0, s1, p0, L, part, parts);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {

@@ -4,12 +4,13 @@
 // a batch of one: every kernel takes the cloud table.
 //
 // Phase 1 (one stream, no host round trip): distances -> threshold select ->
-// edge radix passes -> kept edges -> star radix passes -> stars -> triangle
-// counts -> offsets -> publish.  The last kernel stores (flags, K, T) into a
-// host-pinned mailbox (and, for batches, per-cloud counts into host-pinned
-// memory); the host polls it (no stream synchronisation), sizes the
-// outputs, and enqueues phase 2: the ordered triangle write and the public
-// edge arrays.  The workspace is released in stream order.
+// edge radix passes -> kept edges (scattered into rank matrices) -> stars
+// (one row per vertex) -> triangle counts -> offsets -> publish.  The last
+// kernel stores (flags, K, T) into a host-pinned mailbox (and, for batches,
+// per-cloud counts into host-pinned memory); the host polls it (no stream
+// synchronisation), sizes the outputs, and enqueues phase 2: the ordered
+// triangle write and the public edge arrays.  The workspace is released in
+// stream order.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -26,7 +27,7 @@
 namespace {
 
 enum Stage { ST_DIST, ST_SELECT, ST_SORT, ST_EDGES, ST_STAR, ST_COUNT, ST_SCAN, ST_SYNC, ST_WRITE, ST_EMIT, ST_N };
-const char *kStageNames[ST_N] = {"dist", "select", "radix_sort", "kept_edges", "star_sort",
+const char *kStageNames[ST_N] = {"dist", "select", "radix_sort", "kept_edges", "stars",
                                  "tri_count", "tri_scan", "count_readback", "tri_write", "emit_edges"};
 
 // Device memory of one build: the caller's allocator, else the library's
@@ -221,8 +222,7 @@ struct Plan {
     size_t off_cl, off_cs;
     size_t off_q, off_key0, off_key1, off_val0, off_val1, off_st0, off_st1;
     size_t off_seij, off_seq;
-    size_t off_ikey0, off_ikey1, off_ival0, off_ival1, off_ist0, off_ist1;
-    size_t off_star_r, off_star_nbr, off_star_k, off_start, off_pos, off_cnt, off_off;
+    size_t off_star_r, off_star_nbr, off_star_k, off_deg, off_pos, off_cnt, off_off;
     size_t off_vcloud, off_tcloud, off_scloud, off_kcloud;
     size_t total;
 };
@@ -235,12 +235,11 @@ int hist_copies(long long C) {
 }
 
 // C clouds with V vertices, E pairs and `tiles` distance tiles in all; Kmax
-// bounds the kept edges.
-Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax, bool hist, bool tri) {
+// bounds the kept edges; N2 = sum of n^2 over the clouds (star slots).
+Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax, long long N2, bool hist, bool tri) {
     Plan P{};
     const long long ntE = (E + VR_TILE - 1) / VR_TILE;
     const long long ntK = (Kmax + VR_TILE - 1) / VR_TILE;
-    const long long ntI = (2 * Kmax + VR_TILE - 1) / VR_TILE;
     size_t o = 0;
     // zeroed region: control block, scan and select statuses, histograms
     P.off_ctl = o; o += sizeof(VrCtl);
@@ -259,19 +258,14 @@ Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax
     P.off_val1 = o; o = align_up(o + 4 * (size_t)E);
     P.off_st0 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntE > 0 ? ntE : 1));
     P.off_st1 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntE > 0 ? ntE : 1));
-    P.off_seij = o; o = align_up(o + 4 * (size_t)Kmax);
+    P.off_seij = o; o = align_up(o + 4 * (size_t)(Kmax + 1));  // one entry of room for clamped loads
     P.off_seq = o; o = align_up(o + 4 * (size_t)Kmax);
     if (tri) {
-        P.off_ikey0 = o; o = align_up(o + 8 * (size_t)Kmax);
-        P.off_ikey1 = o; o = align_up(o + 8 * (size_t)Kmax);
-        P.off_ival0 = o; o = align_up(o + 8 * (size_t)Kmax);
-        P.off_ival1 = o; o = align_up(o + 8 * (size_t)Kmax);
-        P.off_ist0 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntI > 0 ? ntI : 1));
-        P.off_ist1 = o; o = align_up(o + 4 * (size_t)VR_RADIX * (size_t)(ntI > 0 ? ntI : 1));
-        P.off_star_r = o; o = align_up(o + 8 * (size_t)Kmax);
-        P.off_star_nbr = o; o = align_up(o + 4 * (size_t)Kmax);
-        P.off_star_k = o; o = align_up(o + 4 * (2 * (size_t)Kmax + 64 * (size_t)V));  // padded stars
-        P.off_start = o; o = align_up(o + 4 * (size_t)(V + 1));
+        // star slots: n entries per vertex (the rank matrix, then the stars)
+        P.off_star_r = o; o = align_up(o + 4 * (size_t)N2);
+        P.off_star_nbr = o; o = align_up(o + 2 * (size_t)N2);
+        P.off_star_k = o; o = align_up(o + 4 * ((size_t)N2 + 64 * (size_t)V));  // padded stars
+        P.off_deg = o; o = align_up(o + 4 * (size_t)V);
         P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
@@ -338,7 +332,7 @@ int check_request(const vr_request *req, long long *E_out, long long *K_out) {
 // them, key widths.  Touches no device state.
 struct Shape {
     std::vector<long long> Es, Ks, which;
-    long long C = 0, V = 0, E = 0, tiles = 0, Khost = -1, Kmax = 0;
+    long long C = 0, V = 0, E = 0, tiles = 0, Khost = -1, Kmax = 0, N2 = 0;
     int d = 0, maxn = 0, qbits = 0, cbits = 0;
     bool sq = false, want_tri = false, need_hist = false;
 };
@@ -371,6 +365,7 @@ int shape_of(const vr_request *reqs, long long count, Shape &S) {
     for (long long c = 0; c < S.C; c++) {
         const long long n = reqs[S.which[c]].n, nb = (n + 63) / 64;
         S.V += n;
+        S.N2 += n * n;
         S.E += S.Es[S.which[c]];
         S.tiles += nb * (nb + 1) / 2;
         Ksum += S.sq ? 0 : S.Ks[S.which[c]];
@@ -382,14 +377,14 @@ int shape_of(const vr_request *reqs, long long count, Shape &S) {
     S.Khost = S.sq ? -1 : Ksum;
     S.Kmax = (S.Khost >= 0) ? S.Khost : S.E;
     // sort keys (cloud, q) in 32 bits; candidate counts in the 30-bit
-    // look-back statuses; vertices in 24 bits (three star passes);
-    // incidence ids 2g+s in 32 bits
+    // look-back statuses; vertices in 24 bits; kept-edge index + 1 in 32
+    // bits.  Star slot indices (sum n^2 + 64 V = 2E + 65 V) then fit 32 bits.
     if (S.qbits + S.cbits > 32 || S.E >= (1ll << 30) || S.V >= (1ll << 24) || S.Kmax > 0x7FFFFFFFll)
         return VR_E2BIG;
     return VR_OK;
 }
 
-Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.tiles, S.Kmax, S.need_hist, S.want_tri); }
+Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.tiles, S.Kmax, S.N2, S.need_hist, S.want_tri); }
 
 // Build `count` clouds on stream s.  On VR_OK `own` holds the output block
 // and views[i] describes request i (device pointers into the block).  On an
@@ -436,7 +431,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     if (C > 1 && !g_host.clouds((size_t)C)) return fail(VR_ENOMEM, nullptr, 0);
     VrCloud one{};
     {
-        long long vb = 0, pb = 0, tb = 0, kb = 0;
+        long long vb = 0, pb = 0, tb = 0, kb = 0, mb = 0;
         for (long long c = 0; c < C; c++) {
             const vr_request &r = reqs[which[c]];
             VrCloud cl{};
@@ -447,6 +442,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             cl.pbase = pb;
             cl.tbase = tb;
             cl.kbase = kb;
+            cl.mbase = mb;
             cl.K = sq ? 0 : Ks[which[c]];
             cl.thr_num = r.thr_num;
             const long long nb = (r.n + 63) / 64;
@@ -454,6 +450,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             pb += Es[which[c]];
             tb += nb * (nb + 1) / 2;
             kb += cl.K;
+            mb += r.n * r.n;
             if (C == 1) one = cl;
             else g_host.tab[c] = cl;
         }
@@ -475,8 +472,6 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.qbits = qbits;
     D.passes = (qbits + cbits + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
     if (D.passes < 1) D.passes = 1;
-    D.spasses = (bits_of((unsigned long long)(V - 1)) + VR_RADIX_BITS - 1) / VR_RADIX_BITS;
-    if (D.spasses < 1) D.spasses = 1;
     D.need_hist = need_hist ? 1 : 0;
     D.tri = want_tri ? 1 : 0;
     D.parts_count = D.parts_write = enum_parts(V);
@@ -495,6 +490,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.mailbox = g_host.mb_d;
     D.seq = ++g_host.seq;
     if (D.seq == 0) D.seq = ++g_host.seq;
+    D.tag = 1u + D.seq % 255u;
     D.host_cloud = (C > 1) ? g_host.pc_d : nullptr;
     D.ctl = (VrCtl *)(ws + P.off_ctl);
     D.st_scan = (unsigned long long *)(ws + P.off_stscan);
@@ -513,16 +509,10 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.se_ij = (uint32_t *)(ws + P.off_seij);
     D.se_q = (uint32_t *)(ws + P.off_seq);
     if (want_tri) {
-        D.ikey[0] = (uint32_t *)(ws + P.off_ikey0);
-        D.ikey[1] = (uint32_t *)(ws + P.off_ikey1);
-        D.ival[0] = (uint32_t *)(ws + P.off_ival0);
-        D.ival[1] = (uint32_t *)(ws + P.off_ival1);
-        D.ist[0] = (uint32_t *)(ws + P.off_ist0);
-        D.ist[1] = (uint32_t *)(ws + P.off_ist1);
         D.star_r = (uint32_t *)(ws + P.off_star_r);
         D.star_nbr = (uint16_t *)(ws + P.off_star_nbr);
         D.star_k = (uint32_t *)(ws + P.off_star_k);
-        D.start = (uint32_t *)(ws + P.off_start);
+        D.deg = (uint32_t *)(ws + P.off_deg);
         D.pos = (uint16_t *)(ws + P.off_pos);
         D.cnt = (uint32_t *)(ws + P.off_cnt);
         D.off = (unsigned long long *)(ws + P.off_off);
@@ -534,7 +524,6 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         D.kcloud = (uint32_t *)(ws + P.off_kcloud);
     }
     D.ntile_E = (E + VR_TILE - 1) / VR_TILE;
-    D.ntile_I = (2 * Kmax + VR_TILE - 1) / VR_TILE;
 
     // ---------------------------------------------------------- phase 1 ----
     mark(ST_DIST);
@@ -562,10 +551,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     launch_edges(D, s);
     mark(ST_STAR);
     if (want_tri) {
-        launch_hist_fold(&D.ctl->hinc[0][0][0], VR_HINC_STRIDE, D.spasses * VR_RADIX, s);
-        const SortJob J = star_sort_job(D);
-        for (int p = 0; p < D.spasses; p++) launch_sort_pass(J, D.ntile_I, p, s);
-        launch_star(D, s);
+        launch_rows(D, s);
     }
     mark(ST_COUNT);
     if (want_tri) launch_tri_count(D, s);
@@ -720,7 +706,7 @@ int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t thr_kind
     long long E, K;
     if (check_request(&r, &E, &K) != VR_OK) return -1;
     const long long nb = (n + 63) / 64;
-    return (int64_t)plan(1, n, E, nb * (nb + 1) / 2, E, true, true).total;
+    return (int64_t)plan(1, n, E, nb * (nb + 1) / 2, E, (long long)n * n, true, true).total;
 }
 
 int vr_query_counts(const vr_result *res, int64_t counts[3]) {

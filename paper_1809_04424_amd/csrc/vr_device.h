@@ -31,18 +31,15 @@
 
 // Control block in device memory, zeroed at the start of every build.
 struct VrCtl {
-    uint32_t ticket[16];            // tile tickets: 1..4 edge sort, 5 scan, 6..8 star sort
+    uint32_t ticket[16];            // tile tickets: 1..4 edge sort, 5 scan
     uint32_t done;                  // finished work-groups of the per-cloud publisher
     uint32_t flags;                 // bit 0: a squared distance overflowed 32 bits
     uint32_t n_cand;                // candidates kept by the select pass
     uint32_t n_kept;                // K
-    uint32_t n_inc;                 // 2K vertex incidences
     unsigned long long n_tri;       // T
     uint32_t hist8[VR_HCOPY][VR_MAX_PASSES][VR_RADIX];  // digit histograms of the edge candidates
-    uint32_t hinc[VR_HCOPY][3][VR_RADIX];               // digit histograms of the incidence vertices
 };
 #define VR_HIST8_STRIDE (VR_MAX_PASSES * VR_RADIX)
-#define VR_HINC_STRIDE (3 * VR_RADIX)
 
 // Host-pinned mailbox: the end of phase 1 publishes the counts here; the
 // host polls `seq` instead of synchronising the stream.
@@ -388,6 +385,7 @@ struct VrCloud {
     long long kbase;      // first global kept edge (unless distance threshold)
     long long K;          // kept edges (unless distance threshold)
     long long thr_num;    // distance threshold (strict)
+    long long mbase;      // first entry of the cloud's star slots (n x n per cloud)
 };
 
 // Per-cloud results written on the device.
@@ -408,7 +406,6 @@ struct VrDev {
     long long K_host;       // kept edges over all clouds when known on the host (else -1)
     int qbits;              // bits of a squared distance in the sort key; cloud id above
     int passes;             // radix passes launched for the edge keys
-    int spasses;            // radix passes launched for the star sort
     int need_hist;          // histogram select needed (COUNT / FRACTION)
     int tri;                // triangles wanted
     int parts_count, parts_write;  // work-groups per vertex in the enumeration kernels
@@ -417,6 +414,7 @@ struct VrDev {
     VrCtl *ctl;
     VrMailbox *mailbox;     // host-pinned
     uint32_t seq;
+    uint32_t tag;           // 1..255: top byte of this build's rank-matrix entries
     const VrCloud *cl;      // C clouds
     VrCloudState *cs;       // C per-cloud results
     uint32_t *hist;         // C x hcopies x VR_NBUCKET log-linear histograms
@@ -433,18 +431,21 @@ struct VrDev {
     uint32_t *st_sort[2];   // ceil(E/TILE)*RADIX edge-sort statuses
     uint32_t *se_ij;        // K sorted kept edges (i<<16|j, local)
     uint32_t *se_q;         // K
-    uint32_t *ikey[2];      // 2K incidence vertices (global), ping-pong (star sort)
-    uint32_t *ival[2];      // 2K incidence ids 2g+s
-    uint32_t *ist[2];       // ceil(2K/TILE)*RADIX star-sort statuses
-    uint32_t *star_r;       // 2K: CSR stars, global kept-edge index, rank order
-    uint16_t *star_nbr;     // 2K: the other endpoint (local)
-    uint32_t *star_k;       // 2K + 64V: stars in neighbour order (neighbour | rank-order position << 16), each followed by 64 sentinels
-    uint32_t *start;        // V+1 CSR row starts
+    // Star slots: vertex v of a cloud with n points owns entries
+    // [mbase + v n, mbase + v n + n) of star_r and star_nbr, and the same
+    // entries shifted by 64 (global vertex) of star_k, which leaves room
+    // for the 64 sentinels after each star.
+    uint32_t *star_r;       // sum n^2: first the rank matrix (tag << 24 | local rank at [v][k]),
+                            // then each row's star in rank order (local rank, tag 0)
+    uint16_t *star_nbr;     // sum n^2: the other endpoint (local), rank order
+    uint32_t *star_k;       // sum n^2 + 64V: stars in neighbour order (neighbour | rank-order position << 16),
+                            // each followed by 64 sentinels
+    uint32_t *deg;          // V: star sizes
     uint16_t *pos;          // 2K: position of edge g in the star of endpoint s (id 2g+s)
     uint32_t *cnt;          // K triangles per kept edge
     unsigned long long *off;     // K exclusive offsets
     unsigned long long *st_scan; // ceil(K/TILE)
-    long long ntile_E, ntile_I;
+    long long ntile_E;
 };
 
 // Cloud of a global index, by the cloud's first index (upper bound - 1).
@@ -482,7 +483,6 @@ __device__ __forceinline__ long long kept_count(const VrDev &D, int c) {
 }
 
 SortJob edge_sort_job(const VrDev &D);
-SortJob star_sort_job(const VrDev &D);
 
 void launch_init(const VrDev &D, size_t zero_words, const VrCloud *one, VrCloud *dst, hipStream_t s);
 void launch_pivot(const VrDev &D, hipStream_t s);
@@ -495,7 +495,7 @@ void launch_select(const VrDev &D, hipStream_t s);
 void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream_t s);
 void launch_hist_fold(uint32_t *h0, int stride, int bins, hipStream_t s);
 void launch_edges(const VrDev &D, hipStream_t s);
-void launch_star(const VrDev &D, hipStream_t s);
+void launch_rows(const VrDev &D, hipStream_t s);
 int enum_parts(long long V);
 int enum_block(long long V);
 void launch_tri_count(const VrDev &D, hipStream_t s);
