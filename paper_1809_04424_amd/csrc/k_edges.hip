@@ -698,7 +698,15 @@ __global__ __launch_bounds__(VR_BLOCK) void k_edges(VrDev D) {
         // without triangles this is the last phase-1 kernel of a single build
         if (!D.tri && D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, (uint32_t)K, 0ull);
     }
-    for (long long g = (long long)blockIdx.x * VR_BLOCK + threadIdx.x; g < K; g += (long long)gridDim.x * VR_BLOCK) {
+    // Work-groups go to the 8 XCDs in turn (b -> XCD b % 8).  Each XCD takes
+    // one contiguous eighth of the edges and its work-groups stride through
+    // it together, so the rank-matrix stores of one XCD fall into the
+    // matrices of few clouds at a time and gather in that XCD's L2.
+    const uint32_t G = gridDim.x, x8 = blockIdx.x % 8, i8 = blockIdx.x / 8;
+    const long long nb8 = (long long)(G / 8) + (x8 < G % 8 ? 1 : 0), span8 = (K + 7) / 8;
+    const long long gend = min(K, (long long)(x8 + 1) * span8);
+    for (long long g = (long long)x8 * span8 + (long long)i8 * VR_BLOCK + threadIdx.x; g < gend;
+         g += nb8 * VR_BLOCK) {
         const int c = (D.thr_kind == 3)  // kept bases known only on the device: search
                           ? cloud_of(g, D.C, [&](int k) { return kept_base(D, k); })
                           : cloud_from_map(D, D.kcloud, g, VR_BLOCK, [&](int k) { return D.cl[k].kbase; });
@@ -721,6 +729,6 @@ void launch_edges(const VrDev &D, hipStream_t s) {
     long long K = (D.thr_kind == 3) ? D.E : D.K_host;
     long long g = (K + VR_BLOCK - 1) / VR_BLOCK;
     if (g > 1024) g = 1024;
-    if (g < 1) g = 1;
+    if (g < 8) g = 8;  // every XCD's eighth of the edges needs a work-group
     hipLaunchKernelGGL(k_edges, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D);
 }
