@@ -201,17 +201,19 @@ VR_API void vr_batch_free(vr_batch *batch, void *stream);
 
 /*
  * Autotuning of the triangle kernels' schedule (work-group size 256 or 512,
- * and work-groups per vertex 1, 2, 4, 8 or 16) for the size class of these
- * requests (bits of their total vertex count and of their mean degree).
- * Runs one build of the requests (as vr_build_batch), then times the count
- * and the write kernel at every schedule, keeps the fastest of each in a
- * process-wide table that later builds of the class use, and frees the
- * build.  Schedules change no output.  Synchronises `stream`.  sched[0..3]
- * receive (count work-group size, count work-groups per vertex, write
- * work-group size, write work-groups per vertex); all 0 when the requests
- * have no triangles.  Same error behaviour as vr_build_batch.
+ * work-groups per vertex 1, 2, 4, 8 or 16, and candidate pieces of 64 loaded
+ * at a time: 2, 4 or 8 for the count, 4 or 8 for the write) for the size
+ * class of these requests (bits of their total vertex count and of their
+ * mean degree).  Runs one build of the requests (as vr_build_batch), then
+ * times the count and the write kernel at every schedule, keeps the fastest
+ * of each in a process-wide table that later builds of the class use, and
+ * frees the build.  Schedules change no output.  Synchronises `stream`.
+ * sched[0..5] receive (count work-group size, count work-groups per vertex,
+ * count pieces, write work-group size, write work-groups per vertex, write
+ * pieces); all 0 when the requests have no triangles.  Same error behaviour
+ * as vr_build_batch.
  */
-VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[4]);
+VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[6]);
 
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from
@@ -225,7 +227,7 @@ VR_API int64_t vr_trim(void);
 /* Static description of a status code. */
 VR_API const char *vr_status_string(int status);
 
-/* Library version, e.g. 110 for 0.1.1. */
+/* Library version, e.g. 120 for 0.1.2. */
 VR_API int vr_version(void);
 
 #ifdef __cplusplus

@@ -396,8 +396,9 @@ def _check_points(points):
 def autotune(points, thr, maxdim: int = 2):
     """Tune the triangle kernels' schedule for the size class of these clouds
     (one tensor or a list, as build_batch); returns (count block size, count
-    work-groups per vertex, write block size, write work-groups per vertex),
-    which later builds of the class use.  Outputs do not depend on it."""
+    work-groups per vertex, count pieces, write block size, write work-groups
+    per vertex, write pieces), which later builds of the class use.  Outputs
+    do not depend on it."""
     import torch
 
     L = lib()
@@ -406,7 +407,7 @@ def autotune(points, thr, maxdim: int = 2):
     dev = pts[0].device
     stream = torch.cuda.current_stream(dev)
     reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None) for p, t in zip(pts, thrs)])
-    sched = (ctypes.c_int32 * 4)()
+    sched = (ctypes.c_int32 * 6)()
     with torch.cuda.device(dev):
         rc = L.vr_autotune(reqs, len(pts), ctypes.c_void_p(stream.cuda_stream), sched)
     if rc != VR_OK:

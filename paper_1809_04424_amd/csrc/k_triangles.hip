@@ -250,7 +250,9 @@ void launch_rows(const VrDev &D, hipStream_t s) {
 // of whole edges holding about 1/8 of the pieces.  The metadata of up to 64
 // edges sits in lane registers; the loads of the next edge are issued before
 // the current edge is consumed.
-#define VR_PIECES 8  // pieces of an edge loaded in one go (64 candidates each)
+// An edge's candidates are loaded NP pieces of 64 at a time (NP a schedule
+// choice: 2, 4 or 8 for the count, 4 or 8 for the write); longer candidate
+// lists finish piece by piece.
 
 template <int EB>
 struct EnumLds {
@@ -362,7 +364,7 @@ __device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, u
 template <int EB>
 size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLds<EB>); }
 
-// Prefetch of one edge's candidates, VR_PIECES pieces of 64.  Every load is
+// Prefetch of one edge's candidates, NP pieces of 64.  Every load is
 // issued unconditionally, with addresses clamped into valid memory, so that
 // the compiler can count outstanding loads exactly: a conditional load makes
 // it wait for every load in flight, the next edge's prefetch included.
@@ -370,13 +372,14 @@ size_t enum_lds(int maxn) { return 2 * (size_t)((maxn + 7) & ~7) + sizeof(EnumLd
 //
 // Rank-prefix candidates (u16 neighbours; len may be 0): pieces past len
 // re-read the last candidate, or the array's first entry when len is 0.
+template <int NP>
 __device__ __forceinline__ void issue_prefix(const uint16_t *__restrict__ base, uint32_t sb, uint32_t len,
-                                             uint32_t (&kk)[VR_PIECES]) {
+                                             uint32_t (&kk)[NP]) {
     const uint32_t lane = threadIdx.x & 63;
     const uint16_t *src = base + (len ? sb : 0u);
     const uint32_t last = len ? len - 1u : 0u;
 #pragma unroll
-    for (int j = 0; j < VR_PIECES; j++) {
+    for (int j = 0; j < NP; j++) {
         const uint32_t y = (uint32_t)(j * VR_WAVE) + lane;
         kk[j] = src[y < last ? y : last];
     }
@@ -384,15 +387,16 @@ __device__ __forceinline__ void issue_prefix(const uint16_t *__restrict__ base, 
 
 // Padded neighbour-ordered star (len >= 1): pieces past len read the 64
 // sentinels that follow the star.
+template <int NP>
 __device__ __forceinline__ void issue_padded(const uint32_t *__restrict__ src, uint32_t len,
-                                             uint32_t (&kk)[VR_PIECES]) {
+                                             uint32_t (&kk)[NP]) {
     const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < VR_PIECES; j++) kk[j] = src[min((uint32_t)(j * VR_WAVE), len) + lane];
+    for (int j = 0; j < NP; j++) kk[j] = src[min((uint32_t)(j * VR_WAVE), len) + lane];
 }
 
 // ----------------------------------------------------------- k_tri_count ----
-template <int EB>
+template <int EB, int NP>
 __global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
     extern __shared__ uint32_t lds[];
     const long long ag = blockIdx.x / parts;
@@ -421,18 +425,18 @@ __global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
             }
             uint32_t mycnt = 0;
             // count of edge el from its prefetched pieces
-            auto count_edge = [&](int el, const uint32_t (&kk)[VR_PIECES]) {
+            auto count_edge = [&](int el, const uint32_t (&kk)[NP]) {
                 const uint32_t xa = rl(vxa, el), len = rl(vlen, el);
                 uint32_t c = 0;
 #pragma unroll
-                for (int j = 0; j < VR_PIECES; j++) {
+                for (int j = 0; j < NP; j++) {
                     if ((uint32_t)(j * VR_WAVE) < len) {  // whole pieces past len are skipped
                         const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
                         const bool hit = (y < len) & ((uint32_t)Pa[kk[j]] < xa);
                         c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
                     }
                 }
-                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                for (uint32_t y0 = NP * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                     const uint32_t y = y0 + (uint32_t)lane;
                     const uint32_t k = D.star_nbr[rl(vsb, el) + (y < len ? y : len - 1u)];
                     c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((y < len) & ((uint32_t)Pa[k] < xa)));
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
             };
             // ping-pong prefetch one edge ahead; past the last edge the loads
             // repeat the last edge's (never consumed)
-            uint32_t kA[VR_PIECES], kB[VR_PIECES];
+            uint32_t kA[NP], kB[NP];
             issue_prefix(D.star_nbr, rl(vsb, 0), rl(vlen, 0), kA);
             for (int el = 0; el < ne; el += 2) {
                 const int e1 = min(el + 1, ne - 1), e2 = min(el + 2, ne - 1);
@@ -468,11 +472,24 @@ int enum_parts(long long V) {
 // work-groups in flight), 512 for large ones (fewer chunk barriers).
 int enum_block(long long V) { return V <= 2048 ? 256 : 512; }
 
+// Pieces loaded at a time, the defaults: 4 for the count (its candidates are
+// rank prefixes, often short), 8 for the write (whole stars).
+int enum_pieces_count(long long) { return 4; }
+int enum_pieces_write(long long) { return 8; }
+
+template <int EB, int NP>
+static void count_at(const VrDev &D, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_tri_count<EB, NP>), grid, dim3(EB), enum_lds<EB>(D.maxn), s, D, D.parts_count);
+}
+
 void launch_tri_count(const VrDev &D, hipStream_t s) {
-    const int parts = D.parts_count;
-    const dim3 grid((unsigned)(D.V * parts));
-    if (D.eb_count == 256) hipLaunchKernelGGL(k_tri_count<256>, grid, dim3(256), enum_lds<256>(D.maxn), s, D, parts);
-    else hipLaunchKernelGGL(k_tri_count<512>, grid, dim3(512), enum_lds<512>(D.maxn), s, D, parts);
+    const dim3 grid((unsigned)(D.V * D.parts_count));
+    const bool big = D.eb_count != 256;
+    switch (D.pieces_count) {
+    case 2: big ? count_at<512, 2>(D, grid, s) : count_at<256, 2>(D, grid, s); break;
+    case 8: big ? count_at<512, 8>(D, grid, s) : count_at<256, 8>(D, grid, s); break;
+    default: big ? count_at<512, 4>(D, grid, s) : count_at<256, 4>(D, grid, s); break;
+    }
 }
 
 // ---------------------------------------------------------------- k_scan ----
@@ -592,7 +609,7 @@ __device__ __forceinline__ void emit_edges_range(const VrDev &D, long long K, ui
 
 // Blocks [0, n*parts) write triangles; the blocks after them write the
 // public edge arrays.
-template <int EB>
+template <int EB, int NP>
 __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts,
                                                           long long K, uint32_t *__restrict__ edge_ij,
                                                           long long *__restrict__ edge_q) {
@@ -633,7 +650,7 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
                 voff = D.off[vr];
             }
             // write the triangles of edge el from its prefetched pieces
-            auto write_edge = [&](int el, const uint32_t (&kk)[VR_PIECES]) {
+            auto write_edge = [&](int el, const uint32_t (&kk)[NP]) {
                 const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
                 const uint32_t r = rl(vr, el) - kb;  // local rank within the cloud
                 unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
@@ -662,7 +679,7 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
                 // (pieces past len inside a group read sentinels), and the four
                 // position lookups of a group are issued together
 #pragma unroll
-                for (int g = 0; g < VR_PIECES; g += 4) {
+                for (int g = 0; g < NP; g += 4) {
                     if ((uint32_t)(g * VR_WAVE) < len) {
                         uint32_t pa[4];
 #pragma unroll
@@ -671,14 +688,14 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
                         for (int j = 0; j < 4; j++) piece(kk[g + j], pa[j]);
                     }
                 }
-                for (uint32_t y0 = VR_PIECES * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+                for (uint32_t y0 = NP * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                     const uint32_t v = D.star_k[rl(vsb, el) + y0 + (uint32_t)lane];
                     piece(v, Pa[v & 0xFFFFu]);
                 }
             };
             // ping-pong prefetch one edge ahead; past the last edge the loads
             // repeat the last edge's (never consumed)
-            uint32_t kA[VR_PIECES], kB[VR_PIECES];
+            uint32_t kA[NP], kB[NP];
             issue_padded(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
             for (int el = 0; el < ne; el += 2) {
                 const int e1 = min(el + 1, ne - 1), e2 = min(el + 2, ne - 1);
@@ -699,10 +716,15 @@ void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, 
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;
     const dim3 grid((unsigned)(D.V * parts + eb));
-    if (EB == 256)
-        hipLaunchKernelGGL(k_tri_write<256>, grid, dim3(256), enum_lds<256>(D.maxn), s, D, tri_out, parts, K, edge_ij, edge_q);
+    const size_t lds = (EB == 256) ? enum_lds<256>(D.maxn) : enum_lds<512>(D.maxn);
+    if (EB == 256 && D.pieces_write == 4)
+        hipLaunchKernelGGL((k_tri_write<256, 4>), grid, dim3(256), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
+    else if (EB == 256)
+        hipLaunchKernelGGL((k_tri_write<256, 8>), grid, dim3(256), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
+    else if (D.pieces_write == 4)
+        hipLaunchKernelGGL((k_tri_write<512, 4>), grid, dim3(512), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
     else
-        hipLaunchKernelGGL(k_tri_write<512>, grid, dim3(512), enum_lds<512>(D.maxn), s, D, tri_out, parts, K, edge_ij, edge_q);
+        hipLaunchKernelGGL((k_tri_write<512, 8>), grid, dim3(512), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

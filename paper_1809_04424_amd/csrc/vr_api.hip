@@ -199,11 +199,12 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 int bits_of(unsigned long long m);
 
 // Enumeration schedule picked by vr_autotune, per size class (bits of the
-// vertex count, bits of the mean degree): work-group size and work-groups
-// per vertex, for the count and for the write.  Builds of a class never
-// tuned use enum_block and enum_parts.
+// vertex count, bits of the mean degree): work-group size, work-groups per
+// vertex and candidate pieces loaded at a time, for the count and for the
+// write.  Builds of a class never tuned use enum_block, enum_parts and
+// enum_pieces_*.
 struct Sched {
-    int eb_count, parts_count, eb_write, parts_write;
+    int eb_count, parts_count, pieces_count, eb_write, parts_write, pieces_write;
 };
 struct Tuning {
     std::mutex mu;
@@ -476,6 +477,8 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.tri = want_tri ? 1 : 0;
     D.parts_count = D.parts_write = enum_parts(V);
     D.eb_count = D.eb_write = enum_block(V);
+    D.pieces_count = enum_pieces_count(V);
+    D.pieces_write = enum_pieces_write(V);
     {
         Tuning &tu = tuning();
         std::lock_guard<std::mutex> g(tu.mu);
@@ -483,8 +486,10 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         if (it != tu.sched.end()) {
             D.eb_count = it->second.eb_count;
             D.parts_count = it->second.parts_count;
+            D.pieces_count = it->second.pieces_count;
             D.eb_write = it->second.eb_write;
             D.parts_write = it->second.parts_write;
+            D.pieces_write = it->second.pieces_write;
         }
     }
     D.mailbox = g_host.mb_d;
@@ -638,11 +643,20 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         // Time the count and the write at each schedule (both are idempotent:
         // every run writes the same counts and keys) and keep the fastest.
         const int cand_eb[] = {256, 512}, cand_p[] = {1, 2, 4, 8, 16};
+        const int cand_nc[] = {2, 4, 8}, cand_nw[] = {4, 8};
         float best_c = 1e30f, best_w = 1e30f;
-        Sched best{D.eb_count, D.parts_count, D.eb_write, D.parts_write};
-        hipEvent_t e[3];
-        for (int i = 0; i < 3; i++)
+        Sched best{D.eb_count, D.parts_count, D.pieces_count, D.eb_write, D.parts_write, D.pieces_write};
+        hipEvent_t e[2];
+        for (int i = 0; i < 2; i++)
             if (hipEventCreate(&e[i]) != hipSuccess) return fail(VR_EHIP, ws, P.total);
+        auto timed = [&](auto &&launch) {
+            (void)hipEventRecord(e[0], s);
+            launch();
+            (void)hipEventRecord(e[1], s);
+            float t = 1e30f;
+            if (hipEventSynchronize(e[1]) == hipSuccess) (void)hipEventElapsedTime(&t, e[0], e[1]);
+            return t;
+        };
         for (int rep = 0; rep < 2; rep++)
             for (int eb : cand_eb)
                 for (int p : cand_p) {
@@ -650,20 +664,22 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
                     VrDev Dp = D;
                     Dp.eb_count = Dp.eb_write = eb;
                     Dp.parts_count = Dp.parts_write = p;
-                    (void)hipEventRecord(e[0], s);
-                    launch_tri_count(Dp, s);
-                    (void)hipEventRecord(e[1], s);
+                    for (int nc : cand_nc) {
+                        Dp.pieces_count = nc;
+                        const float t = timed([&] { launch_tri_count(Dp, s); });
+                        if (t < best_c) { best_c = t; best.eb_count = eb; best.parts_count = p; best.pieces_count = nc; }
+                    }
                     if (write_tri)
-                        launch_tri_write(Dp, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
-                    (void)hipEventRecord(e[2], s);
-                    if (hipEventSynchronize(e[2]) != hipSuccess) break;
-                    float tc = 0.f, tw = 0.f;
-                    (void)hipEventElapsedTime(&tc, e[0], e[1]);
-                    (void)hipEventElapsedTime(&tw, e[1], e[2]);
-                    if (tc < best_c) { best_c = tc; best.eb_count = eb; best.parts_count = p; }
-                    if (write_tri && tw < best_w) { best_w = tw; best.eb_write = eb; best.parts_write = p; }
+                        for (int nw : cand_nw) {
+                            Dp.pieces_write = nw;
+                            const float t = timed([&] {
+                                launch_tri_write(Dp, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij,
+                                                 (long long *)edge_q, s);
+                            });
+                            if (t < best_w) { best_w = t; best.eb_write = eb; best.parts_write = p; best.pieces_write = nw; }
+                        }
                 }
-        for (int i = 0; i < 3; i++) (void)hipEventDestroy(e[i]);
+        for (int i = 0; i < 2; i++) (void)hipEventDestroy(e[i]);
         if (hipGetLastError() != hipSuccess) return fail(VR_EHIP, ws, P.total);
         {
             Tuning &tu = tuning();
@@ -672,8 +688,10 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         }
         tune_out[0] = best.eb_count;
         tune_out[1] = best.parts_count;
-        tune_out[2] = best.eb_write;
-        tune_out[3] = best.parts_write;
+        tune_out[2] = best.pieces_count;
+        tune_out[3] = best.eb_write;
+        tune_out[4] = best.parts_write;
+        tune_out[5] = best.pieces_write;
     }
     A.put(ws, P.total);
     return VR_OK;
@@ -683,7 +701,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
 
 extern "C" {
 
-int vr_version(void) { return 110; }
+int vr_version(void) { return 120; }
 
 const char *vr_status_string(int status) {
     switch (status) {
@@ -752,15 +770,15 @@ int64_t vr_batch_workspace_bytes(const vr_request *reqs, int64_t count) {
     return S.C == 0 ? 0 : (int64_t)plan_of(S).total;
 }
 
-int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[4]) {
+int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[6]) {
     if (!reqs || count < 1 || !sched) return VR_EINVAL;
     vr_batch *b = new (std::nothrow) vr_batch();
     if (!b) return VR_ENOMEM;
-    int32_t chosen[4] = {0, 0, 0, 0};
+    int32_t chosen[6] = {0, 0, 0, 0, 0, 0};
     const int st = build_impl(reqs, count, (hipStream_t)stream, b->own, b->views, chosen);
     if (st == VR_OK) {
         b->own.release((hipStream_t)stream);
-        for (int i = 0; i < 4; i++) sched[i] = chosen[i];
+        for (int i = 0; i < 6; i++) sched[i] = chosen[i];
     }
     delete b;
     return st;

@@ -410,6 +410,7 @@ struct VrDev {
     int tri;                // triangles wanted
     int parts_count, parts_write;  // work-groups per vertex in the enumeration kernels
     int eb_count, eb_write;        // their work-group sizes (256 or 512)
+    int pieces_count, pieces_write;  // candidate pieces of 64 loaded at a time (count 2/4/8, write 4/8)
     // workspace
     VrCtl *ctl;
     VrMailbox *mailbox;     // host-pinned
@@ -498,6 +499,8 @@ void launch_edges(const VrDev &D, hipStream_t s);
 void launch_rows(const VrDev &D, hipStream_t s);
 int enum_parts(long long V);
 int enum_block(long long V);
+int enum_pieces_count(long long V);
+int enum_pieces_write(long long V);
 void launch_tri_count(const VrDev &D, hipStream_t s);
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,

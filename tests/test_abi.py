@@ -137,7 +137,7 @@ def test_batch_workspace_bytes():
 
 def test_autotune_rejects_bad_arguments():
     L = vr.lib()
-    parts = (ctypes.c_int32 * 4)()
+    parts = (ctypes.c_int32 * 6)()
     assert L.vr_autotune(None, 1, None, parts) == vr.VR_EINVAL
     arr = (vr.VrRequest * 1)(_req())
     assert L.vr_autotune(arr, 1, None, None) == vr.VR_EINVAL

@@ -15,9 +15,10 @@ def test_autotune_then_build_matches_oracle(orc):
 
     c = workloads.noisy_circle(n=600)
     pts = torch.from_numpy(c.points).to("cuda:0")
-    ebc, pc, ebw, pw = vr.autotune(pts, c.thr)
+    ebc, pc, nc, ebw, pw, nw = vr.autotune(pts, c.thr)
     assert ebc in (256, 512) and ebw in (256, 512)
     assert pc in (1, 2, 4, 8, 16) and pw in (1, 2, 4, 8, 16)
+    assert nc in (2, 4, 8) and nw in (4, 8)
     r, out = gpu_build(c)
     assert_matches_oracle(out, orc.build(c.points, c.thr))
     r.free()
@@ -47,4 +48,4 @@ def test_autotune_without_triangles():
 
     c = workloads.uniform_cloud(5, 50, 3)
     c.thr = ("fraction", 10, 100)
-    assert vr.autotune(torch.from_numpy(c.points).to("cuda:0"), c.thr, maxdim=1) == (0, 0, 0, 0)
+    assert vr.autotune(torch.from_numpy(c.points).to("cuda:0"), c.thr, maxdim=1) == (0,) * 6
