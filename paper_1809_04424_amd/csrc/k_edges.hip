@@ -398,6 +398,7 @@ SortJob edge_sort_job(const VrDev &D) {
     J.ticket = &D.ctl->ticket[1];
     J.st[0] = D.st_sort[0]; J.st[1] = D.st_sort[1];
     J.count = &D.ctl->n_cand;
+    J.cap = D.E > 0 ? D.E : 1;
     J.passes = D.passes;
     return J;
 }
@@ -414,16 +415,57 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
     __shared__ uint32_t s_key[VR_TILE];
     __shared__ uint32_t s_val[VR_TILE];
     __shared__ uint32_t sh_w[VR_WAVES];
+    __shared__ uint32_t sh_nz[VR_MAX_PASSES][VR_WAVES];
     __shared__ int sh_tile;
-    bool active = false;
-    const uint32_t Kc = *J.count;
-    const int ntiles = (int)((Kc + VR_TILE - 1) / VR_TILE);
-    if ((int)blockIdx.x >= ntiles) return;  // surplus work-groups never touch the ticket
-    const int a = active_before(J.hist, J.passes, pass, &active);
-    if (!active) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const uint32_t *__restrict__ ksrc = J.key[a & 1];
+    // S == 0: tile = blockIdx.x, one per work-group, with every tile's
+    // work-group launched; else tiles are claimed S at a time from the pass's
+    // ticket.  Everything needed first is loaded at once: the item count,
+    // this thread's digit in every pass's histogram and, with direct tiles,
+    // the tile's keys from both buffers (which one holds the input depends on
+    // the passes skipped so far, known only from the histograms).  Loads
+    // are clamped to the buffers; items past the count are never used.
+    const bool direct = S == 0;
+    const uint32_t Kc = *J.count;
+    uint32_t hv[VR_MAX_PASSES];
+#pragma unroll
+    for (int p = 0; p < VR_MAX_PASSES; p++) hv[p] = J.hist[p * VR_RADIX + t];
+    uint32_t kA[VR_ITEMS], kB[VR_ITEMS];
+    {
+        const long long base = (long long)blockIdx.x * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
+#pragma unroll
+        for (int it = 0; it < VR_ITEMS; it++) {
+            const long long idx = min(base + (long long)it * VR_WAVE + lane, J.cap - 1);
+            kA[it] = direct ? J.key[0][idx] : 0u;
+            kB[it] = direct ? J.key[1][idx] : 0u;
+        }
+    }
+    // passes whose digit takes more than one value are active; the others
+    // are skipped and do not flip the buffers
+#pragma unroll
+    for (int p = 0; p < VR_MAX_PASSES; p++) {
+        const uint32_t nz = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hv[p] != 0u));
+        if (lane == 0) sh_nz[p][w] = nz;
+    }
+    __syncthreads();
+    int a = 0;
+    bool active = false;
+    uint32_t hp = 0;
+#pragma unroll
+    for (int p = 0; p < VR_MAX_PASSES; p++) {
+        uint32_t nz = 0;
+#pragma unroll
+        for (int x = 0; x < VR_WAVES; x++) nz += sh_nz[p][x];
+        if (p < pass && p < J.passes) a += (nz > 1) ? 1 : 0;
+        if (p == pass) {
+            active = nz > 1;
+            hp = hv[p];
+        }
+    }
+    const int ntiles = (int)((Kc + VR_TILE - 1) / VR_TILE);
+    if (!active || (int)blockIdx.x >= ntiles) return;  // surplus work-groups never touch the ticket
     const uint32_t *__restrict__ vsrc = J.val[a & 1];
+    const uint32_t *__restrict__ ksrc = J.key[a & 1];
     uint32_t *__restrict__ kdst = J.key[(a + 1) & 1];
     uint32_t *__restrict__ vdst = J.val[(a + 1) & 1];
     uint32_t *st = J.st[a & 1];
@@ -432,92 +474,101 @@ __global__ __launch_bounds__(VR_BLOCK) void k_sort_pass(SortJob J, int pass, int
 
     // global start of digit t
     uint32_t tot;
-    const uint32_t gstart = block_excl_scan<uint32_t>(J.hist[pass * VR_RADIX + t], sh_w, &tot);
+    const uint32_t gstart = block_excl_scan<uint32_t>(hp, sh_w, &tot);
 
+    auto do_tile = [&](int tile, const uint32_t (&kk)[VR_ITEMS]) {
+        for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = 0u;
+        __syncthreads();
+        uint32_t vv[VR_ITEMS], rk[VR_ITEMS];
+        const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
+        // values at clamped addresses, issued before the ranking (items
+        // past the count are never used)
+#pragma unroll
+        for (int it = 0; it < VR_ITEMS; it++) vv[it] = vsrc[min(base + (long long)it * VR_WAVE + lane, J.cap - 1)];
+#pragma unroll
+        for (int it = 0; it < VR_ITEMS; it++) {
+            const long long idx = base + (long long)it * VR_WAVE + lane;
+            const bool valid = idx < (long long)Kc;
+            const uint32_t k = kk[it];
+            const uint32_t dg = (k >> shift) & 255u;
+            unsigned long long peers = ballot64(valid);
+#pragma unroll
+            for (int b = 0; b < VR_RADIX_BITS; b++) {
+                const unsigned long long m = ballot64((dg >> b) & 1u);
+                peers &= ((dg >> b) & 1u) ? m : ~m;
+            }
+            uint32_t before = 0;
+            if (valid) before = s_whist[w][dg];
+            const uint32_t r = before + (uint32_t)__popcll(peers & lanemask_lt());
+            rk[it] = r;
+            if (valid && (peers & lanemask_lt()) == 0ull) s_whist[w][dg] = before + (uint32_t)__popcll(peers);
+            // the wave's LDS operations run in order; keep the compiler
+            // from moving the next item's read above this write
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        uint32_t wpre[VR_WAVES];
+        uint32_t tc = 0;
+#pragma unroll
+        for (int x = 0; x < VR_WAVES; x++) { wpre[x] = tc; tc += s_whist[x][t]; }
+        uint32_t ttot;
+        const uint32_t tstart = block_excl_scan<uint32_t>(tc, sh_w, &ttot);
+        s_tstart[t] = tstart;
+        uint32_t prev = 0;
+        if (tile == 0) {
+            st_store32(st + t, st_pack32(VR_ST_INC, tc));
+        } else {
+            st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_AGG, tc));
+            prev = lookback32(st + t, tile, VR_RADIX);
+            st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_INC, prev + tc));
+        }
+        s_gpre[t] = gstart + prev;
+        st_next[(size_t)tile * VR_RADIX + t] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = wpre[x];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < VR_ITEMS; it++) {
+            const long long idx = base + (long long)it * VR_WAVE + lane;
+            if (idx < (long long)Kc) {
+                const uint32_t dg = (kk[it] >> shift) & 255u;
+                const uint32_t lp = s_tstart[dg] + s_whist[w][dg] + rk[it];
+                s_key[lp] = kk[it];
+                s_val[lp] = vv[it];
+            }
+        }
+        __syncthreads();
+        const uint32_t valid_n = (uint32_t)min((long long)VR_TILE, (long long)Kc - (long long)tile * VR_TILE);
+#pragma unroll
+        for (int m = 0; m < VR_ITEMS; m++) {
+            const uint32_t lp = (uint32_t)t + (uint32_t)m * VR_BLOCK;
+            if (lp < valid_n) {
+                const uint32_t k = s_key[lp];
+                const uint32_t dg = (k >> shift) & 255u;
+                const uint32_t gp = s_gpre[dg] + (lp - s_tstart[dg]);
+                kdst[gp] = k;
+                vdst[gp] = s_val[lp];
+            }
+        }
+    };
+    if (direct) {
+        uint32_t kk[VR_ITEMS];
+#pragma unroll
+        for (int it = 0; it < VR_ITEMS; it++) kk[it] = (a & 1) ? kB[it] : kA[it];
+        do_tile((int)blockIdx.x, kk);
+        return;
+    }
     for (;;) {
         const int t0 = claim_tiles(&J.ticket[pass], S, &sh_tile);
         if (t0 >= ntiles) break;
         for (int tile = t0; tile < min(t0 + S, ntiles); tile++) {
             if (tile > t0) __syncthreads();  // LDS of the previous tile is reused
-            for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = 0u;
-            __syncthreads();
-            uint32_t kk[VR_ITEMS], vv[VR_ITEMS], rk[VR_ITEMS];
+            uint32_t kk[VR_ITEMS];
             const long long base = (long long)tile * VR_TILE + (long long)w * (VR_TILE / VR_WAVES);
-            // all loads first: the ranking below orders LDS traffic, and no
-            // wait of it should hold a global load back
 #pragma unroll
-            for (int it = 0; it < VR_ITEMS; it++) {
-                const long long idx = base + (long long)it * VR_WAVE + lane;
-                const bool valid = idx < (long long)Kc;
-                kk[it] = valid ? ksrc[idx] : 0u;
-                vv[it] = valid ? vsrc[idx] : 0u;
-            }
-#pragma unroll
-            for (int it = 0; it < VR_ITEMS; it++) {
-                const long long idx = base + (long long)it * VR_WAVE + lane;
-                const bool valid = idx < (long long)Kc;
-                const uint32_t k = kk[it];
-                const uint32_t dg = (k >> shift) & 255u;
-                unsigned long long peers = ballot64(valid);
-#pragma unroll
-                for (int b = 0; b < VR_RADIX_BITS; b++) {
-                    const unsigned long long m = ballot64((dg >> b) & 1u);
-                    peers &= ((dg >> b) & 1u) ? m : ~m;
-                }
-                uint32_t before = 0;
-                if (valid) before = s_whist[w][dg];
-                const uint32_t r = before + (uint32_t)__popcll(peers & lanemask_lt());
-                rk[it] = r;
-                if (valid && (peers & lanemask_lt()) == 0ull) s_whist[w][dg] = before + (uint32_t)__popcll(peers);
-                // the wave's LDS operations run in order; keep the compiler
-                // from moving the next item's read above this write
-                __builtin_amdgcn_wave_barrier();
-            }
-            __syncthreads();
-            uint32_t wpre[VR_WAVES];
-            uint32_t tc = 0;
-#pragma unroll
-            for (int x = 0; x < VR_WAVES; x++) { wpre[x] = tc; tc += s_whist[x][t]; }
-            uint32_t ttot;
-            const uint32_t tstart = block_excl_scan<uint32_t>(tc, sh_w, &ttot);
-            s_tstart[t] = tstart;
-            uint32_t prev = 0;
-            if (tile == 0) {
-                st_store32(st + t, st_pack32(VR_ST_INC, tc));
-            } else {
-                st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_AGG, tc));
-                prev = lookback32(st + t, tile, VR_RADIX);
-                st_store32(st + (size_t)tile * VR_RADIX + t, st_pack32(VR_ST_INC, prev + tc));
-            }
-            s_gpre[t] = gstart + prev;
-            st_next[(size_t)tile * VR_RADIX + t] = 0u;
-            __syncthreads();
-#pragma unroll
-            for (int x = 0; x < VR_WAVES; x++) s_whist[x][t] = wpre[x];
-            __syncthreads();
-#pragma unroll
-            for (int it = 0; it < VR_ITEMS; it++) {
-                const long long idx = base + (long long)it * VR_WAVE + lane;
-                if (idx < (long long)Kc) {
-                    const uint32_t dg = (kk[it] >> shift) & 255u;
-                    const uint32_t lp = s_tstart[dg] + s_whist[w][dg] + rk[it];
-                    s_key[lp] = kk[it];
-                    s_val[lp] = vv[it];
-                }
-            }
-            __syncthreads();
-            const uint32_t valid_n = (uint32_t)min((long long)VR_TILE, (long long)Kc - (long long)tile * VR_TILE);
-#pragma unroll
-            for (int m = 0; m < VR_ITEMS; m++) {
-                const uint32_t lp = (uint32_t)t + (uint32_t)m * VR_BLOCK;
-                if (lp < valid_n) {
-                    const uint32_t k = s_key[lp];
-                    const uint32_t dg = (k >> shift) & 255u;
-                    const uint32_t gp = s_gpre[dg] + (lp - s_tstart[dg]);
-                    kdst[gp] = k;
-                    vdst[gp] = s_val[lp];
-                }
-            }
+            for (int it = 0; it < VR_ITEMS; it++) kk[it] = ksrc[min(base + (long long)it * VR_WAVE + lane, J.cap - 1)];
+            do_tile(tile, kk);
         }
         if ((int)gridDim.x >= ntiles) break;  // every tile went out in the first round of claims
     }
@@ -676,9 +727,10 @@ void launch_sort_pass(const SortJob &J, long long max_tiles, int pass, hipStream
         hipLaunchKernelGGL(k_sort_pass_multi, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass);
         return;
     }
-    // one tile per claim: a tile's aggregate is published as soon as it is
-    // ranked
-    hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass, 1);
+    // one tile per work-group (every tile's work-group is launched and all
+    // fit on the device at once), else one tile per claim: a tile's
+    // aggregate is published as soon as it is ranked
+    hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, J, pass, max_tiles <= 1024 ? 0 : 1);
 }
 
 // -------------------------------------------------------------- k_edges ----

@@ -370,6 +370,7 @@ struct SortJob {
     uint32_t *ticket;         // one tile ticket per pass
     uint32_t *st[2];          // look-back statuses, by parity of the active pass
     const uint32_t *count;    // number of items
+    long long cap;            // capacity of key[] and val[] (items)
     int passes;
 };
 
