@@ -493,16 +493,67 @@ void launch_tri_count(const VrDev &D, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- k_scan ----
+// S == 0: tile = blockIdx.x (every tile's work-group is launched), with the
+// tile's counts loaded together with K (clamped to the buffer; counts past
+// K are never used); else tiles are claimed S at a time from a ticket.
 __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D, int S) {
     __shared__ unsigned long long sh_w[VR_WAVES];
     __shared__ unsigned long long sh_prefix;
     __shared__ int sh_tile;
     VrCtl *ctl = D.ctl;
     const int t = threadIdx.x;
+    const bool direct = S == 0;
+    const long long cap = (D.K_host >= 0) ? D.K_host : D.E;  // entries of cnt and off
+    uint32_t cd[VR_ITEMS];
+    {
+        const long long i0 = (long long)blockIdx.x * VR_TILE + (long long)t * VR_ITEMS;
+#pragma unroll
+        for (int m = 0; m < VR_ITEMS; m++) cd[m] = (direct && cap > 0) ? D.cnt[min(i0 + m, cap - 1)] : 0u;
+    }
     const long long K = (long long)ctl->n_kept;
     const int ntiles = (int)((K + VR_TILE - 1) / VR_TILE);
     if (D.C == 1 && ntiles == 0 && blockIdx.x == 0 && t == 0)
         publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, 0ull);
+    auto do_tile = [&](int tile, const uint32_t (&cin)[VR_ITEMS]) {
+        const long long i0 = (long long)tile * VR_TILE + (long long)t * VR_ITEMS;
+        uint32_t c[VR_ITEMS];
+        unsigned long long loc = 0;
+#pragma unroll
+        for (int m = 0; m < VR_ITEMS; m++) {
+            c[m] = (i0 + m < K) ? cin[m] : 0u;
+            loc += c[m];
+        }
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
+        if (t < VR_WAVE) {
+            unsigned long long prefix = 0;
+            if (tile == 0) {
+                if (t == 0) st_store64(D.st_scan, st_pack64(VR_ST_INC, tot));
+            } else {
+                if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_AGG, tot));
+                prefix = lookback64_wave(D.st_scan, tile);
+                if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_INC, prefix + tot));
+            }
+            if (t == 0) {
+                sh_prefix = prefix;
+                if (tile == ntiles - 1) {
+                    ctl->n_tri = prefix + tot;
+                    if (D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
+                }
+            }
+        }
+        __syncthreads();
+        unsigned long long o = sh_prefix + ex;
+#pragma unroll
+        for (int m = 0; m < VR_ITEMS; m++) {
+            if (i0 + m < K) D.off[i0 + m] = o;
+            o += c[m];
+        }
+    };
+    if (direct) {
+        if ((int)blockIdx.x < ntiles) do_tile((int)blockIdx.x, cd);
+        return;
+    }
     for (;;) {
         const int t0 = claim_tiles(&ctl->ticket[5], S, &sh_tile);
         if (t0 >= ntiles) break;
@@ -510,47 +561,21 @@ __global__ __launch_bounds__(VR_BLOCK) void k_scan(VrDev D, int S) {
             if (tile > t0) __syncthreads();  // sh_prefix and sh_w are reused
             const long long i0 = (long long)tile * VR_TILE + (long long)t * VR_ITEMS;
             uint32_t c[VR_ITEMS];
-            unsigned long long loc = 0;
 #pragma unroll
-            for (int m = 0; m < VR_ITEMS; m++) {
-                c[m] = (i0 + m < K) ? D.cnt[i0 + m] : 0u;
-                loc += c[m];
-            }
-            unsigned long long tot;
-            const unsigned long long ex = block_excl_scan<unsigned long long>(loc, sh_w, &tot);
-            if (t < VR_WAVE) {
-                unsigned long long prefix = 0;
-                if (tile == 0) {
-                    if (t == 0) st_store64(D.st_scan, st_pack64(VR_ST_INC, tot));
-                } else {
-                    if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_AGG, tot));
-                    prefix = lookback64_wave(D.st_scan, tile);
-                    if (t == 0) st_store64(D.st_scan + tile, st_pack64(VR_ST_INC, prefix + tot));
-                }
-                if (t == 0) {
-                    sh_prefix = prefix;
-                    if (tile == ntiles - 1) {
-                        ctl->n_tri = prefix + tot;
-                        if (D.C == 1) publish_counts(D.mailbox, D.seq, ctl->flags, ctl->n_cand, ctl->n_kept, prefix + tot);
-                    }
-                }
-            }
-            __syncthreads();
-            unsigned long long o = sh_prefix + ex;
-#pragma unroll
-            for (int m = 0; m < VR_ITEMS; m++) {
-                if (i0 + m < K) D.off[i0 + m] = o;
-                o += c[m];
-            }
+            for (int m = 0; m < VR_ITEMS; m++) c[m] = D.cnt[min(i0 + m, cap - 1)];
+            do_tile(tile, c);
         }
     }
 }
 
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s) {
     long long g = (Kmax + VR_TILE - 1) / VR_TILE;
+    // every tile gets its own work-group when they all fit at once, else
+    // 1024 work-groups claim one tile at a time
+    const int S = (g <= 1024) ? 0 : 1;
     if (g > 1024) g = 1024;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D, 1);  // one tile per claim
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)g), dim3(VR_BLOCK), 0, s, D, S);
 }
 
 // ------------------------------------------------------ k_cloud_publish ----
