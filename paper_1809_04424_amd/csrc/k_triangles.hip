@@ -636,9 +636,13 @@ __device__ __forceinline__ void emit_edges_range(const VrDev &D, long long K, ui
 // public edge arrays.
 template <int EB, int NP>
 __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *__restrict__ out, int parts,
-                                                          long long K, uint32_t *__restrict__ edge_ij,
+                                                          long long cap_k, unsigned long long cap_t,
+                                                          uint32_t *__restrict__ edge_ij,
                                                           long long *__restrict__ edge_q) {
     extern __shared__ uint32_t lds[];
+    // outputs sized before the counts were known: write nothing unless they fit
+    const long long K = (long long)D.ctl->n_kept;
+    if (K > cap_k || D.ctl->n_tri > cap_t) return;
     const long long nb = D.V * parts;
     if ((long long)blockIdx.x >= nb) {
         emit_edges_range(D, K, edge_ij, edge_q, (long long)(blockIdx.x - nb) * EB + threadIdx.x,
@@ -734,22 +738,25 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
     }
 }
 
-void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long K, uint32_t *edge_ij, long long *edge_q,
-                      hipStream_t s) {
+// The outputs hold cap_k edges and cap_t triangles; the kernel writes nothing
+// when the build's counts (read on the device) exceed them.
+void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long cap_k, unsigned long long cap_t,
+                      uint32_t *edge_ij, long long *edge_q, hipStream_t s) {
     const int parts = D.parts_write, EB = D.eb_write;
+    const long long K = cap_k;
     long long eb = (K + EB - 1) / EB;  // extra work-groups that write the edge arrays
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;
     const dim3 grid((unsigned)(D.V * parts + eb));
     const size_t lds = (EB == 256) ? enum_lds<256>(D.maxn) : enum_lds<512>(D.maxn);
     if (EB == 256 && D.pieces_write == 4)
-        hipLaunchKernelGGL((k_tri_write<256, 4>), grid, dim3(256), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
+        hipLaunchKernelGGL((k_tri_write<256, 4>), grid, dim3(256), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
     else if (EB == 256)
-        hipLaunchKernelGGL((k_tri_write<256, 8>), grid, dim3(256), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
+        hipLaunchKernelGGL((k_tri_write<256, 8>), grid, dim3(256), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
     else if (D.pieces_write == 4)
-        hipLaunchKernelGGL((k_tri_write<512, 4>), grid, dim3(512), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
+        hipLaunchKernelGGL((k_tri_write<512, 4>), grid, dim3(512), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
     else
-        hipLaunchKernelGGL((k_tri_write<512, 8>), grid, dim3(512), lds, s, D, tri_out, parts, K, edge_ij, edge_q);
+        hipLaunchKernelGGL((k_tri_write<512, 8>), grid, dim3(512), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

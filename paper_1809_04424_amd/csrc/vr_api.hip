@@ -13,6 +13,7 @@
 // stream order.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <map>
 #include <mutex>
 #include <new>
@@ -216,6 +217,22 @@ Tuning &tuning() {
 }
 std::pair<int, int> size_class(long long V, long long K) {
     return {bits_of((unsigned long long)V), bits_of((unsigned long long)(2 * K / (V > 0 ? V : 1)))};
+}
+
+// Edge and triangle counts of the last build of each shape (clouds, vertices,
+// pairs, kept-edge bound, threshold kind).  A build of a known shape enqueues
+// the triangle write right after its counting, into outputs of those sizes;
+// the writer checks the real counts on the device and writes nothing when
+// they do not fit, and the host then falls back to sizing the outputs from
+// the counts.  Repeated shapes (a benchmark loop, a stream of similar
+// requests) so keep the device busy while the host reads the counts.
+struct OutGuess {
+    std::mutex mu;
+    std::map<std::array<long long, 5>, std::pair<long long, unsigned long long>> last;
+};
+OutGuess &out_guess() {
+    static OutGuess *g = new OutGuess();
+    return *g;
 }
 
 struct Plan {
@@ -565,10 +582,42 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     // threshold); for one cloud its last tile publishes the counts
     if (want_tri) launch_scan(D, Kmax, s);
     if (C > 1) launch_cloud_publish(D, s);
+    // the triangle write into outputs of the last build's sizes, if any
+    // (stage timing of the whole build keeps the write after the read-back)
+    const bool guess_ok = want_tri && !count_only && !timing_all && !tune_out;
+    const std::array<long long, 5> gkey{C, V, E, Kmax, (long long)r0.thr_kind};
+    long long gK = -1;
+    unsigned long long gT = 0;
+    if (guess_ok) {
+        OutGuess &og = out_guess();
+        std::lock_guard<std::mutex> g(og.mu);
+        auto it = og.last.find(gkey);
+        if (it != og.last.end()) {
+            gK = it->second.first;
+            gT = it->second.second;
+        }
+    }
+    char *sblk = nullptr;
+    size_t s_eq = 0, sbytes = 0;
+    if (gK >= 0 && gT > 0) {
+        s_eq = align_up(8 * (size_t)gK);
+        sbytes = 2 * s_eq + 8 * (size_t)gT;
+        sblk = (char *)A.get(sbytes);
+        if (sblk) {
+            mark(ST_WRITE);
+            launch_tri_write(D, (unsigned long long *)(sblk + 2 * s_eq), gK, gT, (uint32_t *)(sblk + s_eq),
+                             (long long *)sblk, s);
+            mark(ST_EMIT);
+        }
+    }
+    auto fail2 = [&](int code) {
+        if (sblk) A.put(sblk, sbytes);
+        return fail(code, ws, P.total);
+    };
     mark(ST_SYNC);
     if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);
-        return fail(VR_EHIP, ws, P.total);
+        return fail2(VR_EHIP);
     }
     // Poll the mailbox; query the stream now and then so that a failed
     // launch cannot leave the host waiting.
@@ -579,9 +628,9 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
                 const hipError_t q = hipStreamQuery(s);
                 if (q == hipSuccess) {
                     if (__atomic_load_n(&g_host.mb_h->seq, __ATOMIC_ACQUIRE) == D.seq) break;
-                    return fail(VR_EHIP, ws, P.total);
+                    return fail2(VR_EHIP);
                 }
-                if (q != hipErrorNotReady) return fail(VR_EHIP, ws, P.total);
+                if (q != hipErrorNotReady) return fail2(VR_EHIP);
             }
             _mm_pause();
         }
@@ -589,7 +638,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     const uint32_t flags = __atomic_load_n(&g_host.mb_h->flags, __ATOMIC_ACQUIRE);
     const long long K = (long long)__atomic_load_n(&g_host.mb_h->n_kept, __ATOMIC_ACQUIRE);
     const unsigned long long T = want_tri ? __atomic_load_n(&g_host.mb_h->n_tri, __ATOMIC_ACQUIRE) : 0ull;
-    if (flags & 1u) return fail(VR_ERANGE, ws, P.total);
+    if (flags & 1u) return fail2(VR_ERANGE);
     // per device cloud: first kept edge, kept edges, first triangle, triangles
     std::vector<unsigned long long> pc((size_t)(4 * C));
     if (C > 1) {
@@ -601,14 +650,25 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         pc[3] = T;
     }
     for (long long c = 0; c < C; c++)
-        if (pc[4 * c + 1] > (unsigned long long)VR_MAX_EDGES) return fail(VR_E2BIG, ws, P.total);
+        if (pc[4 * c + 1] > (unsigned long long)VR_MAX_EDGES) return fail2(VR_E2BIG);
 
     // ---------------------------------------------------------- phase 2 ----
+    if (guess_ok) {
+        OutGuess &og = out_guess();
+        std::lock_guard<std::mutex> g(og.mu);
+        og.last[gkey] = {K, T};
+    }
+    // the write already enqueued went through when the counts fit its outputs
+    const bool done = sblk && K <= gK && T <= gT;
+    if (sblk && !done) {
+        A.put(sblk, sbytes);  // in stream order, after the writer that wrote nothing
+        sblk = nullptr;
+    }
     const bool write_tri = want_tri && !count_only && T > 0;
-    const size_t eq_bytes = align_up(8 * (size_t)K), eij_bytes = align_up(8 * (size_t)K);
+    const size_t eq_bytes = done ? s_eq : align_up(8 * (size_t)K), eij_bytes = eq_bytes;
     const size_t tri_bytes = write_tri ? 8 * (size_t)T : 0;
-    const size_t ob = eq_bytes + eij_bytes + tri_bytes;
-    char *blk = (char *)A.get(ob);
+    const size_t ob = done ? sbytes : eq_bytes + eij_bytes + tri_bytes;
+    char *blk = done ? sblk : (char *)A.get(ob);
     if (!blk) return fail(VR_ENOMEM, ws, P.total);
     own.block = blk;
     own.block_bytes = ob;
@@ -625,14 +685,16 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         v.tri_key = (tri_key && Tc > 0) ? tri_key + tb : nullptr;
     }
 
-    mark(ST_WRITE);
-    if (write_tri) {
-        // the triangle writer also writes the public edge arrays
-        launch_tri_write(D, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
-        mark(ST_EMIT);
-    } else {
-        mark(ST_EMIT);
-        launch_emit_edges(D, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
+    if (!done) {  // (else the write went out before the read-back, between its events)
+        mark(ST_WRITE);
+        if (write_tri) {
+            // the triangle writer also writes the public edge arrays
+            launch_tri_write(D, (unsigned long long *)tri_key, K, T, (uint32_t *)edge_ij, (long long *)edge_q, s);
+            mark(ST_EMIT);
+        } else {
+            mark(ST_EMIT);
+            launch_emit_edges(D, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
+        }
     }
     mark(ST_N);
     if (hipGetLastError() != hipSuccess) {
@@ -673,7 +735,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
                         for (int nw : cand_nw) {
                             Dp.pieces_write = nw;
                             const float t = timed([&] {
-                                launch_tri_write(Dp, (unsigned long long *)tri_key, K, (uint32_t *)edge_ij,
+                                launch_tri_write(Dp, (unsigned long long *)tri_key, K, T, (uint32_t *)edge_ij,
                                                  (long long *)edge_q, s);
                             });
                             if (t < best_w) { best_w = t; best.eb_write = eb; best.parts_write = p; best.pieces_write = nw; }

@@ -246,3 +246,36 @@ def test_unpacked_triangles(orc):
     assert rows.shape == (f.T, 4)
     assert np.array_equal(rows[:, :3], f.tris[:, 1:]) and np.array_equal(rows[:, 3], f.tris[:, 0])
     r.free()
+
+
+def test_output_guess_follows_counts(orc):
+    """A build of a shape seen before enqueues its triangle write into outputs
+    of the last build's sizes before the counts reach the host: a build with
+    more triangles than the last must fall back, one with fewer writes into
+    the larger outputs; every result stays exact."""
+    few = workloads.uniform_cloud(31, 400, 3, thr=("fraction", 20, 100))
+    many = workloads.noisy_circle(seed=32, n=400)
+    assert many.thr == few.thr
+    ref = {c.name: orc.build(c.points, c.thr) for c in (few, many)}
+    assert ref[many.name].T > ref[few.name].T
+    for c in (few, many, few, many, many):
+        _say(f"[gpu] output guess {c.name}")
+        r, out = gpu_build(c)
+        assert_matches_oracle(out, ref[c.name])
+        r.free()
+
+
+def test_output_guess_batches(orc):
+    """Batches of one shape with the clouds' triangle counts swapped between
+    them reuse the outputs' size but not their per-cloud layout."""
+    from tests.gpu_util import gpu_build_batch
+
+    few = workloads.uniform_cloud(33, 300, 3, thr=("fraction", 20, 100))
+    many = workloads.noisy_circle(seed=34, n=300)
+    ref = {c.name: orc.build(c.points, c.thr) for c in (few, many)}
+    for order in ([few, many], [many, few], [few, many]):
+        _say(f"[gpu] output guess batch {[c.name for c in order]}")
+        b, outs = gpu_build_batch(order)
+        for c, out in zip(order, outs):
+            assert_matches_oracle(out, ref[c.name])
+        b.free()
