@@ -121,10 +121,15 @@ typedef struct vr_result {
  * Build the filtration of one point cloud.
  * Enqueues all work on `stream` (a hipStream_t; NULL = the null stream) and
  * waits once for the first phase (distances up to triangle counts) to reach
- * the host through host-pinned memory, to size the outputs.  On VR_OK,
- * *out receives a new handle whose device arrays are complete once `stream`
- * reaches the end of this call's work (stream order).  On error *out is not
- * written and nothing is leaked.
+ * the host through host-pinned memory, to size the outputs.  When a build
+ * of the same shape (vertices, pairs, kept-edge bound, threshold kind) ran
+ * before in the process, the triangle write is enqueued before that wait,
+ * into outputs of the earlier build's sizes; it writes nothing if the counts
+ * do not fit them, and the outputs are then sized from the counts.  The
+ * handle's output block may so be larger than its arrays (up to the earlier
+ * build's).  On VR_OK, *out receives a new handle whose device arrays are
+ * complete once `stream` reaches the end of this call's work (stream
+ * order).  On error *out is not written and nothing is leaked.
  */
 VR_API int vr_build(const vr_request *req, void *stream, vr_result **out);
 
