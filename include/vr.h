@@ -205,7 +205,7 @@ VR_API int vr_batch_stage_ms(const vr_batch *batch, float *ms, int cap);
 VR_API void vr_batch_free(vr_batch *batch, void *stream);
 
 /*
- * Autotuning of the triangle kernels' schedule (work-group size 256 or 512,
+ * Autotuning of the triangle kernels' schedule (work-group size 128, 256 or 512,
  * work-groups per vertex 1, 2, 4, 8 or 16, and candidate pieces of 64 loaded
  * at a time: 2, 4 or 8 for the count, 4 or 8 for the write) for the size
  * class of these requests (bits of their total vertex count and of their

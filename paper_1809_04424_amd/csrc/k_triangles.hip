@@ -26,6 +26,8 @@
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
+#include <type_traits>
+
 // Cloud of global vertex v, and v's local index.
 __device__ __forceinline__ int vertex_cloud(const VrDev &D, long long v) {
     return (D.C == 1) ? 0 : (int)D.vcloud[v];
@@ -482,13 +484,21 @@ static void count_at(const VrDev &D, dim3 grid, hipStream_t s) {
     hipLaunchKernelGGL((k_tri_count<EB, NP>), grid, dim3(EB), enum_lds<EB>(D.maxn), s, D, D.parts_count);
 }
 
+template <int EB>
+static void count_eb(const VrDev &D, dim3 grid, hipStream_t s) {
+    switch (D.pieces_count) {
+    case 2: count_at<EB, 2>(D, grid, s); break;
+    case 8: count_at<EB, 8>(D, grid, s); break;
+    default: count_at<EB, 4>(D, grid, s); break;
+    }
+}
+
 void launch_tri_count(const VrDev &D, hipStream_t s) {
     const dim3 grid((unsigned)(D.V * D.parts_count));
-    const bool big = D.eb_count != 256;
-    switch (D.pieces_count) {
-    case 2: big ? count_at<512, 2>(D, grid, s) : count_at<256, 2>(D, grid, s); break;
-    case 8: big ? count_at<512, 8>(D, grid, s) : count_at<256, 8>(D, grid, s); break;
-    default: big ? count_at<512, 4>(D, grid, s) : count_at<256, 4>(D, grid, s); break;
+    switch (D.eb_count) {
+    case 128: count_eb<128>(D, grid, s); break;
+    case 256: count_eb<256>(D, grid, s); break;
+    default: count_eb<512>(D, grid, s); break;
     }
 }
 
@@ -748,15 +758,20 @@ void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long cap
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;
     const dim3 grid((unsigned)(D.V * parts + eb));
-    const size_t lds = (EB == 256) ? enum_lds<256>(D.maxn) : enum_lds<512>(D.maxn);
-    if (EB == 256 && D.pieces_write == 4)
-        hipLaunchKernelGGL((k_tri_write<256, 4>), grid, dim3(256), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
-    else if (EB == 256)
-        hipLaunchKernelGGL((k_tri_write<256, 8>), grid, dim3(256), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
-    else if (D.pieces_write == 4)
-        hipLaunchKernelGGL((k_tri_write<512, 4>), grid, dim3(512), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
-    else
-        hipLaunchKernelGGL((k_tri_write<512, 8>), grid, dim3(512), lds, s, D, tri_out, parts, cap_k, cap_t, edge_ij, edge_q);
+    auto go = [&](auto eb_c, auto np_c) {
+        constexpr int E = decltype(eb_c)::value, N = decltype(np_c)::value;
+        hipLaunchKernelGGL((k_tri_write<E, N>), grid, dim3(E), enum_lds<E>(D.maxn), s, D, tri_out, parts, cap_k, cap_t,
+                           edge_ij, edge_q);
+    };
+    using I128 = std::integral_constant<int, 128>;
+    using I256 = std::integral_constant<int, 256>;
+    using I512 = std::integral_constant<int, 512>;
+    using P4 = std::integral_constant<int, 4>;
+    using P8 = std::integral_constant<int, 8>;
+    const bool p4 = D.pieces_write == 4;
+    if (EB == 128) p4 ? go(I128{}, P4{}) : go(I128{}, P8{});
+    else if (EB == 256) p4 ? go(I256{}, P4{}) : go(I256{}, P8{});
+    else p4 ? go(I512{}, P4{}) : go(I512{}, P8{});
 }
 
 // ---------------------------------------------------------- k_emit_edges ----

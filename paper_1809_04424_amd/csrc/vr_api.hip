@@ -704,7 +704,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     if (tune_out && want_tri) {
         // Time the count and the write at each schedule (both are idempotent:
         // every run writes the same counts and keys) and keep the fastest.
-        const int cand_eb[] = {256, 512}, cand_p[] = {1, 2, 4, 8, 16};
+        const int cand_eb[] = {128, 256, 512}, cand_p[] = {1, 2, 4, 8, 16};
         const int cand_nc[] = {2, 4, 8}, cand_nw[] = {4, 8};
         float best_c = 1e30f, best_w = 1e30f;
         Sched best{D.eb_count, D.parts_count, D.pieces_count, D.eb_write, D.parts_write, D.pieces_write};
