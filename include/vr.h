@@ -74,7 +74,8 @@ enum { VR_THR_FULL = 0, VR_THR_COUNT = 1, VR_THR_FRACTION = 2, VR_THR_SQDIST = 3
 enum {
     VR_COUNT_ONLY = 1u,  /* compute (n, K, T) and the edges; do not write triangles */
     VR_TIMING = 2u,      /* record HIP events between all stages (see vr_query_stage_ms) */
-    VR_TIMING_WRITE = 4u /* record HIP events around the triangle write only */
+    VR_TIMING_WRITE = 4u, /* record HIP events around the triangle write only */
+    VR_GRAPH = 8u         /* capture the first phase into a hipGraph and replay it (see vr_build) */
 };
 
 /* Limits of the packed triangle key: 13 bits per vertex, 24 bits of value. */
@@ -127,9 +128,16 @@ typedef struct vr_result {
  * into outputs of the earlier build's sizes; it writes nothing if the counts
  * do not fit them, and the outputs are then sized from the counts.  The
  * handle's output block may so be larger than its arrays (up to the earlier
- * build's).  On VR_OK, *out receives a new handle whose device arrays are
- * complete once `stream` reaches the end of this call's work (stream
- * order).  On error *out is not written and nothing is leaked.
+ * build's).  With VR_GRAPH, the first build of a request (same points
+ * pointer, size, threshold, flags and schedule) on a host thread captures
+ * the first phase's launches into a hipGraph, and later builds of that
+ * request on the thread replay it with one launch; the points may change
+ * in place between builds.  Each captured graph keeps its own workspace
+ * (at most 4 per thread, least recently used dropped first; vr_trim drops
+ * the calling thread's).  Not combined with VR_TIMING.  On VR_OK, *out
+ * receives a new handle whose device arrays are complete once `stream`
+ * reaches the end of this call's work (stream order).  On error *out is
+ * not written and nothing is leaked.
  */
 VR_API int vr_build(const vr_request *req, void *stream, vr_result **out);
 
@@ -225,8 +233,9 @@ VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int3
  * the driver once and reused by later builds of any stream (a reuse on
  * another stream first waits, on the device, for the block's last use), so
  * a stream of requests of changing sizes does not return to the driver.
- * vr_trim releases the cached blocks of the current device that no result
- * holds (it synchronises the device) and returns the bytes released. */
+ * vr_trim drops the calling thread's captured graphs (VR_GRAPH), then
+ * releases the cached blocks of the current device that no result holds
+ * (it synchronises the device) and returns the bytes released. */
 VR_API int64_t vr_trim(void);
 
 /* Static description of a status code. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvrhip.so")
 VR_OK, VR_EINVAL, VR_ENOMEM, VR_E2BIG, VR_EHIP, VR_ERANGE = 0, -1, -2, -3, -4, -5
 VR_I8, VR_I16, VR_I32 = 1, 2, 3
 VR_THR = {"full": 0, "count": 1, "fraction": 2, "sqdist": 3}
-VR_COUNT_ONLY, VR_TIMING, VR_TIMING_WRITE = 1, 2, 4
+VR_COUNT_ONLY, VR_TIMING, VR_TIMING_WRITE, VR_GRAPH = 1, 2, 4, 8
 VR_MAX_POINTS = 8192
 VR_MAX_EDGES = 1 << 24
 
@@ -362,9 +362,10 @@ class Batch:
             pass
 
 
-def _flags(count_only, timing):
-    return (VR_COUNT_ONLY if count_only else 0) | (VR_TIMING_WRITE if timing == "write" else
-                                                   VR_TIMING if timing else 0)
+def _flags(count_only, timing, graph=False):
+    return ((VR_COUNT_ONLY if count_only else 0) | (VR_TIMING_WRITE if timing == "write" else
+                                                    VR_TIMING if timing else 0) |
+            (VR_GRAPH if graph else 0))
 
 
 def _request(pts, thr, maxdim, flags, alloc):
@@ -425,7 +426,7 @@ def batch_limit(dtype: int, d: int) -> int:
 
 
 def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing=False,
-          allocator: str = "library") -> Result:
+          allocator: str = "library", graph: bool = False) -> Result:
     """Build the Vietoris-Rips filtration (dim <= maxdim) of a device point cloud.
 
     points:    torch tensor on a HIP device, (n, d) int8/int16/int32, rows are points.
@@ -434,6 +435,9 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
                caching allocator through the library's allocator hook).
     timing:    True: HIP events between all stages; "write": around the
                triangle write only (see Result.stage_ms).
+    graph:     capture the first phase into a hipGraph on the first build of
+               this request (points pointer, size, threshold) on this thread
+               and replay it on later ones (not with timing=True).
     The work runs on torch's current stream of the points' device.
     """
     import torch
@@ -442,7 +446,7 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
     pts = _check_points(points)
     alloc = _allocator_for(pts.device) if allocator == "torch" else None
     stream = torch.cuda.current_stream(pts.device)
-    req = _request(pts, thr, maxdim, _flags(count_only, timing), alloc)
+    req = _request(pts, thr, maxdim, _flags(count_only, timing, graph), alloc)
     out = ctypes.POINTER(VrResult)()
     with torch.cuda.device(pts.device):
         rc = L.vr_build(ctypes.byref(req), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
@@ -452,13 +456,13 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
 
 
 def build_batch(points, thr, maxdim: int = 2, count_only: bool = False, timing=False,
-                allocator: str = "library") -> Batch:
+                allocator: str = "library", graph: bool = False) -> Batch:
     """Build the filtrations of many clouds with one launch sequence.
 
     points: list of device tensors (n_c, d), one dtype and d for all.
     thr:    one threshold tuple for all clouds, or a list of them (one kind).
     Each batch[c] is bit-identical to build(points[c], thr[c]).  At most
-    batch_limit(dtype, d) clouds per batch.
+    batch_limit(dtype, d) clouds per batch.  graph: as for build.
     """
     import torch
 
@@ -474,7 +478,7 @@ def build_batch(points, thr, maxdim: int = 2, count_only: bool = False, timing=F
         raise ValueError("all clouds must be on one device")
     alloc = _allocator_for(dev) if allocator == "torch" else None
     stream = torch.cuda.current_stream(dev)
-    flags = _flags(count_only, timing)
+    flags = _flags(count_only, timing, graph)
     reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, flags, alloc) for p, t in zip(pts, thrs)])
     out = ctypes.c_void_p()
     with torch.cuda.device(dev):

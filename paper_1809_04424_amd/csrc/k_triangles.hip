@@ -26,6 +26,8 @@
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 // Cloud of global vertex v, and v's local index.
@@ -749,9 +751,10 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
 }
 
 // The outputs hold cap_k edges and cap_t triangles; the kernel writes nothing
-// when the build's counts (read on the device) exceed them.
+// when the build's counts (read on the device) exceed them.  With events,
+// they take the dispatch's own start and end times (no separate markers).
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long cap_k, unsigned long long cap_t,
-                      uint32_t *edge_ij, long long *edge_q, hipStream_t s) {
+                      uint32_t *edge_ij, long long *edge_q, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int parts = D.parts_write, EB = D.eb_write;
     const long long K = cap_k;
     long long eb = (K + EB - 1) / EB;  // extra work-groups that write the edge arrays
@@ -760,8 +763,12 @@ void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long cap
     const dim3 grid((unsigned)(D.V * parts + eb));
     auto go = [&](auto eb_c, auto np_c) {
         constexpr int E = decltype(eb_c)::value, N = decltype(np_c)::value;
-        hipLaunchKernelGGL((k_tri_write<E, N>), grid, dim3(E), enum_lds<E>(D.maxn), s, D, tri_out, parts, cap_k, cap_t,
-                           edge_ij, edge_q);
+        if (ev0 && ev1)
+            hipExtLaunchKernelGGL((k_tri_write<E, N>), grid, dim3(E), enum_lds<E>(D.maxn), s, ev0, ev1, 0u, D, tri_out,
+                                  parts, cap_k, cap_t, edge_ij, edge_q);
+        else
+            hipLaunchKernelGGL((k_tri_write<E, N>), grid, dim3(E), enum_lds<E>(D.maxn), s, D, tri_out, parts, cap_k,
+                               cap_t, edge_ij, edge_q);
     };
     using I128 = std::integral_constant<int, 128>;
     using I256 = std::integral_constant<int, 256>;

@@ -14,9 +14,11 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <list>
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <string.h>
 #include <vector>
 #include <immintrin.h>
@@ -404,6 +406,94 @@ int shape_of(const vr_request *reqs, long long count, Shape &S) {
 
 Plan plan_of(const Shape &S) { return plan(S.C, S.V, S.E, S.tiles, S.Kmax, S.N2, S.need_hist, S.want_tri); }
 
+// Captured launch sequences (requests flagged VR_GRAPH).  The first build of
+// a request set captures its first phase (initialisation up to the offsets
+// scan) into a hipGraph; later builds of the same set on the same host
+// thread replay it with one launch.  The key holds everything the captured
+// launches bake in: device, shape, schedule, each cloud's points pointer,
+// size and threshold, and the pinned host tables they read.  An entry owns
+// its workspace (taken from the device cache and returned when the entry is
+// dropped); a replay first waits, on the device, for the previous build's
+// last use of it.  The mailbox sequence number is baked in too, so the host
+// clears the mailbox before each replay.  The triangle write stays outside
+// the graph: its outputs change with every build.
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    char *ws = nullptr;
+    uint32_t seq = 0;
+    hipEvent_t done = nullptr;  // recorded after each build's last use of ws
+    bool rec = false;           // done has been recorded
+    unsigned long long used = 0;
+};
+
+struct GraphTable {
+    static constexpr size_t kMax = 4;  // entries per host thread
+    std::list<GraphEntry> e;
+    unsigned long long tick = 0;
+    hipStream_t cap = nullptr;  // capture stream (default priority)
+    int cap_dev = -1;
+
+    GraphEntry *find(const std::string &k) {
+        for (auto &x : e)
+            if (x.key == k) {
+                x.used = ++tick;
+                return &x;
+            }
+        return nullptr;
+    }
+    static void release(GraphEntry &x) {
+        if (x.done) {
+            (void)hipEventSynchronize(x.done);
+            (void)hipEventDestroy(x.done);
+        }
+        if (x.exec) (void)hipGraphExecDestroy(x.exec);
+        if (x.ws) cache_put(x.ws, nullptr);
+        x = GraphEntry{};
+    }
+    GraphEntry *add(GraphEntry &&x) {
+        if (e.size() >= kMax) {
+            auto lru = e.begin();
+            for (auto it = e.begin(); it != e.end(); ++it)
+                if (it->used < lru->used) lru = it;
+            release(*lru);
+            e.erase(lru);
+        }
+        x.used = ++tick;
+        e.push_back(std::move(x));
+        return &e.back();
+    }
+    void drop(const GraphEntry *x) {
+        for (auto it = e.begin(); it != e.end(); ++it)
+            if (&*it == x) {
+                release(*it);
+                e.erase(it);
+                return;
+            }
+    }
+    void clear() {
+        for (auto &x : e) release(x);
+        e.clear();
+    }
+    hipStream_t capture_stream(int dev) {
+        if (cap && cap_dev != dev) {
+            (void)hipStreamDestroy(cap);
+            cap = nullptr;
+        }
+        if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            cap = nullptr;
+        }
+        cap_dev = dev;
+        return cap;
+    }
+    ~GraphTable() {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+thread_local GraphTable g_graphs;
+
 // Build `count` clouds on stream s.  On VR_OK `own` holds the output block
 // and views[i] describes request i (device pointers into the block).  On an
 // error `own` holds nothing.
@@ -445,6 +535,27 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             if (own.ev[i] && hipEventRecord(own.ev[i], s) == hipSuccess) own.ev_used[i] = true;
         }
     };
+    // The triangle write, timed by its dispatch's own start and end when only
+    // the write is timed (marker events would add their own gaps), else
+    // between stage markers.
+    const bool write_events = timing && !timing_all;
+    auto launch_write = [&](const VrDev &Dw, unsigned long long *tri, long long ck, unsigned long long ct,
+                            uint32_t *eij, long long *eq) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (write_events) {
+            for (int i : {(int)ST_WRITE, (int)ST_EMIT})
+                if (!own.ev[i]) own.ev[i] = event_pool().get(dev);
+            if (own.ev[ST_WRITE] && own.ev[ST_EMIT]) {
+                e0 = own.ev[ST_WRITE];
+                e1 = own.ev[ST_EMIT];
+                own.ev_used[ST_WRITE] = own.ev_used[ST_EMIT] = true;
+            }
+        } else {
+            mark(ST_WRITE);
+        }
+        launch_tri_write(Dw, tri, ck, ct, eij, eq, s, e0, e1);
+        if (!write_events) mark(ST_EMIT);
+    };
     if (!g_host.mailbox()) return fail(VR_ENOMEM, nullptr, 0);
     if (C > 1 && !g_host.clouds((size_t)C)) return fail(VR_ENOMEM, nullptr, 0);
     VrCloud one{};
@@ -474,8 +585,53 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         }
     }
     const Plan P = plan_of(S);
-    char *ws = (char *)A.get(P.total);
+    Sched sch{enum_block(V), enum_parts(V), enum_pieces_count(V), enum_block(V), enum_parts(V), enum_pieces_write(V)};
+    {
+        Tuning &tu = tuning();
+        std::lock_guard<std::mutex> g(tu.mu);
+        auto it = tu.sched.find(size_class(V, Kmax));
+        if (it != tu.sched.end()) sch = it->second;
+    }
+    // a captured first phase for this request set, if asked for
+    const bool use_graph = (r0.flags & VR_GRAPH) && !timing_all && !tune_out;
+    std::string gk;
+    GraphEntry *ge = nullptr;
+    if (use_graph) {
+        auto put = [&](const void *p, size_t b) { gk.append((const char *)p, b); };
+        const uint32_t fl = r0.flags & ~(uint32_t)(VR_TIMING_WRITE | VR_GRAPH);
+        const void *ptrs[3] = {g_host.mb_d, C > 1 ? (const void *)g_host.pc_d : nullptr,
+                               C > 1 ? (const void *)g_host.tab : nullptr};
+        put(&dev, sizeof dev);
+        put(&C, sizeof C);
+        put(&r0.dtype, sizeof r0.dtype);
+        put(&r0.d, sizeof r0.d);
+        put(&r0.maxdim, sizeof r0.maxdim);
+        put(&fl, sizeof fl);
+        put(&r0.thr_kind, sizeof r0.thr_kind);
+        put(&sch, sizeof sch);
+        put(ptrs, sizeof ptrs);
+        put(&P.total, sizeof P.total);
+        for (long long c = 0; c < C; c++) {
+            const vr_request &r = reqs[which[c]];
+            put(&r.points, sizeof r.points);
+            put(&r.n, sizeof r.n);
+            put(&r.thr_num, sizeof r.thr_num);
+            put(&r.thr_den, sizeof r.thr_den);
+        }
+        ge = g_graphs.find(gk);
+    }
+    const bool capture = use_graph && !ge;
+    // a graph's workspace belongs to its entry and comes from the device cache
+    char *ws = ge ? ge->ws : capture ? (char *)cache_get(P.total, s) : (char *)A.get(P.total);
     if (!ws) return fail(VR_ENOMEM, nullptr, 0);
+    bool ws_kept = ge != nullptr;  // true once an entry owns ws
+    auto failw = [&](int code) {
+        if (!use_graph) return fail(code, ws, P.total);
+        (void)hipStreamSynchronize(s);   // nothing of this build may still use ws
+        if (ws_kept) g_graphs.drop(ge);  // a failed replay drops its entry (and workspace)
+        else cache_put(ws, s);
+        return fail(code, nullptr, 0);
+    };
 
     VrDev D{};
     D.C = (int)C;
@@ -492,26 +648,19 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     if (D.passes < 1) D.passes = 1;
     D.need_hist = need_hist ? 1 : 0;
     D.tri = want_tri ? 1 : 0;
-    D.parts_count = D.parts_write = enum_parts(V);
-    D.eb_count = D.eb_write = enum_block(V);
-    D.pieces_count = enum_pieces_count(V);
-    D.pieces_write = enum_pieces_write(V);
-    {
-        Tuning &tu = tuning();
-        std::lock_guard<std::mutex> g(tu.mu);
-        auto it = tu.sched.find(size_class(V, Kmax));
-        if (it != tu.sched.end()) {
-            D.eb_count = it->second.eb_count;
-            D.parts_count = it->second.parts_count;
-            D.pieces_count = it->second.pieces_count;
-            D.eb_write = it->second.eb_write;
-            D.parts_write = it->second.parts_write;
-            D.pieces_write = it->second.pieces_write;
-        }
-    }
+    D.eb_count = sch.eb_count;
+    D.parts_count = sch.parts_count;
+    D.pieces_count = sch.pieces_count;
+    D.eb_write = sch.eb_write;
+    D.parts_write = sch.parts_write;
+    D.pieces_write = sch.pieces_write;
     D.mailbox = g_host.mb_d;
-    D.seq = ++g_host.seq;
-    if (D.seq == 0) D.seq = ++g_host.seq;
+    if (ge) {
+        D.seq = ge->seq;  // baked into the captured launches
+    } else {
+        D.seq = ++g_host.seq;
+        if (D.seq == 0) D.seq = ++g_host.seq;
+    }
     D.tag = 1u + D.seq % 255u;
     D.host_cloud = (C > 1) ? g_host.pc_d : nullptr;
     D.ctl = (VrCtl *)(ws + P.off_ctl);
@@ -548,40 +697,81 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     D.ntile_E = (E + VR_TILE - 1) / VR_TILE;
 
     // ---------------------------------------------------------- phase 1 ----
-    mark(ST_DIST);
-    if (C > 1) {
-        if (hipMemcpyAsync((void *)D.cl, g_host.tab, sizeof(VrCloud) * (size_t)C, hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-            return fail(VR_EHIP, ws, P.total);
-        launch_init(D, P.zero_bytes / 4, nullptr, nullptr, s);
-        launch_cloud_maps(D, s);
-    } else {
-        launch_init(D, P.zero_bytes / 4, &one, (VrCloud *)D.cl, s);
+    // Enqueues the first phase on st (the build's stream, or the capture
+    // stream of a graph); stage events only in builds timed stage by stage,
+    // which are never captured.
+    auto phase1 = [&](hipStream_t st) -> bool {
+        mark(ST_DIST);
+        if (C > 1) {
+            if (hipMemcpyAsync((void *)D.cl, g_host.tab, sizeof(VrCloud) * (size_t)C, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return false;
+            launch_init(D, P.zero_bytes / 4, nullptr, nullptr, st);
+            launch_cloud_maps(D, st);
+        } else {
+            launch_init(D, P.zero_bytes / 4, &one, (VrCloud *)D.cl, st);
+        }
+        if (gram_applies(D)) launch_gram(D, nullptr, st);
+        else launch_dist(D, nullptr, st);
+        mark(ST_SELECT);
+        if (need_hist) launch_pivot(D, st);
+        launch_select(D, st);
+        launch_hist_fold(&D.ctl->hist8[0][0][0], VR_HIST8_STRIDE, D.passes * VR_RADIX, st);
+        mark(ST_SORT);
+        {
+            const SortJob J = edge_sort_job(D);
+            for (int p = 0; p < D.passes; p++) launch_sort_pass(J, D.ntile_E, p, st);
+        }
+        mark(ST_EDGES);
+        launch_edges(D, st);
+        mark(ST_STAR);
+        if (want_tri) launch_rows(D, st);
+        mark(ST_COUNT);
+        if (want_tri) launch_tri_count(D, st);
+        mark(ST_SCAN);
+        // the scan reads K from the device (unknown on the host for a distance
+        // threshold); for one cloud its last tile publishes the counts
+        if (want_tri) launch_scan(D, Kmax, st);
+        if (C > 1) launch_cloud_publish(D, st);
+        return hipGetLastError() == hipSuccess;
+    };
+    if (capture) {
+        // capture on the thread's own stream (the null stream cannot be captured)
+        hipStream_t cs = g_graphs.capture_stream(dev);
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const bool ok = phase1(cs);
+            if (hipStreamEndCapture(cs, &g) == hipSuccess && ok && g)
+                if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+            if (g) (void)hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+        hipEvent_t done = nullptr;
+        if (ex && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+        }
+        if (!ex) return failw(VR_EHIP);
+        GraphEntry x;
+        x.key = gk;
+        x.exec = ex;
+        x.ws = ws;
+        x.seq = D.seq;
+        x.done = done;
+        ge = g_graphs.add(std::move(x));
+        ws_kept = true;
     }
-    if (gram_applies(D)) launch_gram(D, nullptr, s);
-    else launch_dist(D, nullptr, s);
-    mark(ST_SELECT);
-    if (need_hist) launch_pivot(D, s);
-    launch_select(D, s);
-    launch_hist_fold(&D.ctl->hist8[0][0][0], VR_HIST8_STRIDE, D.passes * VR_RADIX, s);
-    mark(ST_SORT);
-    {
-        const SortJob J = edge_sort_job(D);
-        for (int p = 0; p < D.passes; p++) launch_sort_pass(J, D.ntile_E, p, s);
+    if (ge) {
+        // wait (on the device) for the last build's use of the workspace,
+        // clear the mailbox (the replay publishes the same sequence number)
+        if (ge->rec && hipStreamWaitEvent(s, ge->done, 0) != hipSuccess) return failw(VR_EHIP);
+        __atomic_store_n(&g_host.mb_h->seq, 0u, __ATOMIC_RELEASE);
+        if (hipGraphLaunch(ge->exec, s) != hipSuccess) return failw(VR_EHIP);
+    } else if (!phase1(s)) {
+        (void)hipStreamSynchronize(s);
+        return failw(VR_EHIP);
     }
-    mark(ST_EDGES);
-    launch_edges(D, s);
-    mark(ST_STAR);
-    if (want_tri) {
-        launch_rows(D, s);
-    }
-    mark(ST_COUNT);
-    if (want_tri) launch_tri_count(D, s);
-    mark(ST_SCAN);
-    // the scan reads K from the device (unknown on the host for a distance
-    // threshold); for one cloud its last tile publishes the counts
-    if (want_tri) launch_scan(D, Kmax, s);
-    if (C > 1) launch_cloud_publish(D, s);
     // the triangle write into outputs of the last build's sizes, if any
     // (stage timing of the whole build keeps the write after the read-back)
     const bool guess_ok = want_tri && !count_only && !timing_all && !tune_out;
@@ -603,16 +793,13 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         s_eq = align_up(8 * (size_t)gK);
         sbytes = 2 * s_eq + 8 * (size_t)gT;
         sblk = (char *)A.get(sbytes);
-        if (sblk) {
-            mark(ST_WRITE);
-            launch_tri_write(D, (unsigned long long *)(sblk + 2 * s_eq), gK, gT, (uint32_t *)(sblk + s_eq),
-                             (long long *)sblk, s);
-            mark(ST_EMIT);
-        }
+        if (sblk)
+            launch_write(D, (unsigned long long *)(sblk + 2 * s_eq), gK, gT, (uint32_t *)(sblk + s_eq),
+                         (long long *)sblk);
     }
     auto fail2 = [&](int code) {
         if (sblk) A.put(sblk, sbytes);
-        return fail(code, ws, P.total);
+        return failw(code);
     };
     mark(ST_SYNC);
     if (hipGetLastError() != hipSuccess) {
@@ -669,7 +856,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     const size_t tri_bytes = write_tri ? 8 * (size_t)T : 0;
     const size_t ob = done ? sbytes : eq_bytes + eij_bytes + tri_bytes;
     char *blk = done ? sblk : (char *)A.get(ob);
-    if (!blk) return fail(VR_ENOMEM, ws, P.total);
+    if (!blk) return failw(VR_ENOMEM);
     own.block = blk;
     own.block_bytes = ob;
     const int64_t *edge_q = (const int64_t *)blk;
@@ -685,13 +872,12 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         v.tri_key = (tri_key && Tc > 0) ? tri_key + tb : nullptr;
     }
 
-    if (!done) {  // (else the write went out before the read-back, between its events)
-        mark(ST_WRITE);
+    if (!done) {  // (else the write went out before the read-back, with its events)
         if (write_tri) {
             // the triangle writer also writes the public edge arrays
-            launch_tri_write(D, (unsigned long long *)tri_key, K, T, (uint32_t *)edge_ij, (long long *)edge_q, s);
-            mark(ST_EMIT);
+            launch_write(D, (unsigned long long *)tri_key, K, T, (uint32_t *)edge_ij, (long long *)edge_q);
         } else {
+            mark(ST_WRITE);
             mark(ST_EMIT);
             launch_emit_edges(D, K, (uint32_t *)edge_ij, (long long *)edge_q, s);
         }
@@ -699,7 +885,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     mark(ST_N);
     if (hipGetLastError() != hipSuccess) {
         (void)hipStreamSynchronize(s);
-        return fail(VR_EHIP, ws, P.total);
+        return failw(VR_EHIP);
     }
     if (tune_out && want_tri) {
         // Time the count and the write at each schedule (both are idempotent:
@@ -710,7 +896,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         Sched best{D.eb_count, D.parts_count, D.pieces_count, D.eb_write, D.parts_write, D.pieces_write};
         hipEvent_t e[2];
         for (int i = 0; i < 2; i++)
-            if (hipEventCreate(&e[i]) != hipSuccess) return fail(VR_EHIP, ws, P.total);
+            if (hipEventCreate(&e[i]) != hipSuccess) return failw(VR_EHIP);
         auto timed = [&](auto &&launch) {
             (void)hipEventRecord(e[0], s);
             launch();
@@ -742,7 +928,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
                         }
                 }
         for (int i = 0; i < 2; i++) (void)hipEventDestroy(e[i]);
-        if (hipGetLastError() != hipSuccess) return fail(VR_EHIP, ws, P.total);
+        if (hipGetLastError() != hipSuccess) return failw(VR_EHIP);
         {
             Tuning &tu = tuning();
             std::lock_guard<std::mutex> g(tu.mu);
@@ -755,7 +941,13 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         tune_out[4] = best.parts_write;
         tune_out[5] = best.pieces_write;
     }
-    A.put(ws, P.total);
+    if (ge) {
+        // the next replay waits for this build's last use of the workspace
+        if (hipEventRecord(ge->done, s) == hipSuccess) ge->rec = true;
+        else return failw(VR_EHIP);
+    } else {
+        A.put(ws, P.total);
+    }
     return VR_OK;
 }
 
@@ -878,7 +1070,10 @@ int vr_unpack_triangles(const vr_result *res, int32_t *rows, void *stream) {
     return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
 }
 
-int64_t vr_trim(void) { return (int64_t)cache_trim(); }
+int64_t vr_trim(void) {
+    g_graphs.clear();  // this thread's captured graphs hold workspaces
+    return (int64_t)cache_trim();
+}
 
 void vr_batch_free(vr_batch *b, void *stream) {
     if (!b) return;

@@ -505,6 +505,7 @@ int enum_pieces_write(long long V);
 void launch_tri_count(const VrDev &D, hipStream_t s);
 void launch_scan(const VrDev &D, long long Kmax, hipStream_t s);
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long cap_k, unsigned long long cap_t,
-                      uint32_t *edge_ij, long long *edge_q, hipStream_t s);
+                      uint32_t *edge_ij, long long *edge_q, hipStream_t s, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 void launch_emit_edges(const VrDev &D, long long K, uint32_t *edge_ij, long long *edge_q, hipStream_t s);
 void launch_unpack(const unsigned long long *keys, long long T, int *rows, hipStream_t s);
