@@ -91,7 +91,7 @@ __device__ __forceinline__ void rows_count_rank(const VrDev &D, const uint32_t *
             const uint32_t k = nbr[x], lr = own[i];
             row[y[i]] = lr;
             D.star_nbr[s0 + y[i]] = (uint16_t)k;
-            D.pos[2 * (kb + lr) + (k > (uint32_t)v ? 0 : 1)] = (uint16_t)y[i];
+            D.pos[s0 + k] = (uint16_t)y[i];
             sk[x] = k | (y[i] << 16);
         }
     }
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_rows(VrDev D) {
                 const uint32_t k = ((ij[i] >> 16) == (uint32_t)v) ? (ij[i] & 0xFFFFu) : (ij[i] >> 16);
                 row[y] = lr;
                 D.star_nbr[s0 + y] = (uint16_t)k;
-                D.pos[2 * (kb + lr) + (k > (uint32_t)v ? 0 : 1)] = (uint16_t)y;
+                D.pos[s0 + k] = (uint16_t)y;
                 pk[k] = (uint16_t)y;
             }
         }
@@ -310,7 +310,7 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
     if (p < s1) {
         r = kb + D.star_r[p];  // global kept-edge index
         b = D.star_nbr[p];
-        pb = D.pos[2 * (size_t)r + (b > (uint32_t)a ? 1 : 0)];
+        pb = D.pos[star_slot(mb, n, (int)b) + (uint32_t)a];  // edge {b,a} in b's star
         sb = star_slot(mb, n, (int)b);
         if (WRITE) {
             const uint32_t db = D.deg[vb + b], da = s1 - s0;

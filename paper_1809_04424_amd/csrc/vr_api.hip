@@ -286,7 +286,7 @@ Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax
         P.off_star_nbr = o; o = align_up(o + 2 * (size_t)N2);
         P.off_star_k = o; o = align_up(o + 4 * ((size_t)N2 + 64 * (size_t)V));  // padded stars
         P.off_deg = o; o = align_up(o + 4 * (size_t)V);
-        P.off_pos = o; o = align_up(o + 4 * (size_t)Kmax);
+        P.off_pos = o; o = align_up(o + 2 * (size_t)N2);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
     }

@@ -443,7 +443,8 @@ struct VrDev {
     uint32_t *star_k;       // sum n^2 + 64V: stars in neighbour order (neighbour | rank-order position << 16),
                             // each followed by 64 sentinels
     uint32_t *deg;          // V: star sizes
-    uint16_t *pos;          // 2K: position of edge g in the star of endpoint s (id 2g+s)
+    uint16_t *pos;          // sum n^2, in the star slots: entry k of v's slot = position of edge {v,k}
+                            // in v's rank-ordered star (set for v's neighbours only)
     uint32_t *cnt;          // K triangles per kept edge
     unsigned long long *off;     // K exclusive offsets
     unsigned long long *st_scan; // ceil(K/TILE)
