@@ -843,6 +843,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
     if (guess_ok) {
         OutGuess &og = out_guess();
         std::lock_guard<std::mutex> g(og.mu);
+        if (og.last.size() >= 4096 && og.last.find(gkey) == og.last.end()) og.last.clear();  // bounded
         og.last[gkey] = {K, T};
     }
     // the write already enqueued went through when the counts fit its outputs
