@@ -298,18 +298,19 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 // endpoint whose partner has the shorter star (candidates = the partner's
 // whole neighbour-ordered star).  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
+// The first chunk's star entries come preloaded (r0, b0: see stage_pos).
 template <bool WRITE, int EB>
 __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, uint32_t mb, int n, uint32_t kb,
                                           uint32_t s0, uint32_t s1, uint32_t p0, EnumLds<EB> &L, int part,
-                                          int parts) {
+                                          int parts, uint32_t r0, uint32_t b0) {
     constexpr int ENUM_WAVES = EB / VR_WAVE;
     const uint32_t p = p0 + threadIdx.x;
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
     const uint32_t x = p - s0;
     if (p < s1) {
-        r = kb + D.star_r[p];  // global kept-edge index
-        b = D.star_nbr[p];
+        r = kb + (p0 == s0 ? r0 : D.star_r[p]);  // global kept-edge index
+        b = p0 == s0 ? b0 : D.star_nbr[p];
         pb = D.pos[star_slot(mb, n, (int)b) + (uint32_t)a];  // edge {b,a} in b's star
         sb = star_slot(mb, n, (int)b);
         if (WRITE) {
@@ -357,11 +358,23 @@ __device__ __forceinline__ uint32_t rl(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
+// Pa[k] = position of neighbour k in a's rank-ordered star (0xFFFF for
+// non-neighbours).  The star's first EB entries (rank and neighbour) are
+// loaded before the table is cleared and handed back for the first chunk,
+// so neither waits on the other.
 template <int EB>
-__device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, uint32_t s0, uint32_t s1) {
+__device__ __forceinline__ void stage_pos(const VrDev &D, int n, uint16_t *Pa, uint32_t s0, uint32_t s1,
+                                          uint32_t &r0, uint32_t &b0) {
+    r0 = b0 = 0;
+    if (s1 > s0) {  // clamped loads: every lane issues them
+        const uint32_t pc = min(s0 + (uint32_t)threadIdx.x, s1 - 1);
+        r0 = D.star_r[pc];
+        b0 = D.star_nbr[pc];
+    }
     for (int k = threadIdx.x; k < n; k += EB) Pa[k] = 0xFFFF;
     __syncthreads();
-    for (uint32_t p = s0 + threadIdx.x; p < s1; p += EB) Pa[D.star_nbr[p]] = (uint16_t)(p - s0);
+    if (s0 + threadIdx.x < s1) Pa[b0] = (uint16_t)threadIdx.x;
+    for (uint32_t p = s0 + threadIdx.x + EB; p < s1; p += EB) Pa[D.star_nbr[p]] = (uint16_t)(p - s0);
     __syncthreads();
 }
 
@@ -413,9 +426,10 @@ __global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t mb = (uint32_t)D.cl[c].mbase, kb = (uint32_t)kept_base(D, c);
     const uint32_t s0 = star_slot(mb, n, a), s1 = s0 + D.deg[ag];
-    stage_pos<EB>(D, n, Pa, s0, s1);
+    uint32_t r0, b0;
+    stage_pos<EB>(D, n, Pa, s0, s1, r0, b0);
     for (uint32_t p0 = s0; p0 < s1; p0 += EB) {
-        load_chunk<false, EB>(D, a, vb, mb, n, kb, s0, s1, p0, L, part, parts);
+        load_chunk<false, EB>(D, a, vb, mb, n, kb, s0, s1, p0, L, part, parts, r0, b0);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
@@ -672,9 +686,10 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t mb = (uint32_t)D.cl[c].mbase;
     const uint32_t s0 = star_slot(mb, n, a), s1 = s0 + D.deg[ag];
-    stage_pos<EB>(D, n, Pa, s0, s1);
+    uint32_t r0, b0;
+    stage_pos<EB>(D, n, Pa, s0, s1, r0, b0);
     for (uint32_t p0 = s0; p0 < s1; p0 += EB) {
-        load_chunk<true, EB>(D, a, vb, mb, n, kb, s0, s1, p0, L, part, parts);
+        load_chunk<true, EB>(D, a, vb, mb, n, kb, s0, s1, p0, L, part, parts, r0, b0);
         const int w_lo = __builtin_amdgcn_readfirstlane((int)L.ew[w]);
         const int w_hi = __builtin_amdgcn_readfirstlane((int)L.ew[w + 1]);
         for (int eb = w_lo; eb < w_hi; eb += VR_WAVE) {
