@@ -29,9 +29,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 # SHA-256 prefix of the writer's sources the counters were taken on, and the
 # figure is dropped (null) once those sources change.
 TRAFFIC = {
-    "circle1000": {"bytes": 85011270, "src": "a9dff9b4aa470d5e"},
-    "mixture4000": {"bytes": 2132063961, "src": "a9dff9b4aa470d5e"},
-    "batched512": {"bytes": 25505641029, "src": "a9dff9b4aa470d5e"},
+    "circle1000": {"bytes": 92240179, "src": "a504010f66a4d24d"},
+    "mixture4000": {"bytes": 2066404424, "src": "a504010f66a4d24d"},
+    "batched512": {"bytes": 36531157628, "src": "a504010f66a4d24d"},
 }
 WRITER_SOURCES = ("k_triangles.hip", "vr_device.h")
 
@@ -132,8 +132,7 @@ def _batched(vr, torch, reps=3, tune=True):
     pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
     thrs = [c.thr for c in clouds]
     torch.cuda.synchronize()
-    if tune:
-        vr.autotune(pts, thrs)  # one-time, untimed
+    tuned = vr.autotune(pts, thrs) if tune else None  # one-time, untimed
     vr.build_batch(pts, thrs).free()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -151,6 +150,7 @@ def _batched(vr, torch, reps=3, tune=True):
     ts = time.perf_counter() - t0
     print(f"[bench] batched512: {ts * 1e3:.2f} ms one cloud at a time", file=sys.stderr, flush=True)
     return {"value": simp / tb, "unit": "simplices/s", "ms_per_batch": 1e3 * tb, "simplices": simp,
+            "schedule": list(tuned) if tuned else "default",
             "clouds": len(clouds), "points": sum(c.n for c in clouds),
             "per_cloud_builds": {"value": simp / ts, "ms": 1e3 * ts}, "speedup_vs_per_cloud": ts / tb}
 
@@ -255,8 +255,7 @@ def _main_batched(vr, torch, args):
     pts = [torch.from_numpy(c.points).to("cuda:0") for c in clouds]
     thrs = [c.thr for c in clouds]
     torch.cuda.synchronize()
-    if not args.no_tune:
-        vr.autotune(pts, thrs)  # one-time, untimed
+    tuned = _schedule(vr, args, pts, thrs)  # one-time, untimed
     prev = None
     for _ in range(max(args.warmup, 2)):  # two results alive at once, as in the timed loop
         b = vr.build_batch(pts, thrs, timing="write")
@@ -290,10 +289,21 @@ def _main_batched(vr, torch, args):
         "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": "batched512_r3", "clouds": len(clouds), "points": n, "kept_edges": K,
-                   "triangles": T, "simplices_per_step": simp},
+                   "triangles": T, "simplices_per_step": simp,
+                   "schedule": list(tuned) if tuned else "default"},
         "roofline": {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic("batched512"),
                      "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}}), flush=True)
+
+
+def _schedule(vr, args, pts, thr):
+    """The main workload's schedule: pinned with --schedule, else tuned once
+    (untimed), else the library's default."""
+    if args.schedule:
+        sched = tuple(int(x) for x in args.schedule.split(","))
+        vr.set_schedule(pts, thr, sched)
+        return sched
+    return vr.autotune(pts, thr) if not args.no_tune else None
 
 
 def _alg_bytes(n, K, T, n2):
@@ -317,6 +327,9 @@ def main():
                     help="serving QPS; 0 measures 0.7 x the plain build's capacity instead")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 256 MiB plain copy")
     ap.add_argument("--no-tune", action="store_true", help="skip the one-time schedule autotuning")
+    ap.add_argument("--schedule", default=None,
+                    help="pin the main workload's schedule (six comma-separated values, as reported in config) "
+                         "instead of tuning it")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--breakdown-reps", type=int, default=10, help="untimed builds for the stage breakdown (0: skip)")
     args = ap.parse_args()
@@ -340,7 +353,7 @@ def main():
     pts = torch.from_numpy(cloud.points).to("cuda:0")
     torch.cuda.synchronize()
 
-    tuned = vr.autotune(pts, cloud.thr) if not args.no_tune else None  # one-time, untimed
+    tuned = _schedule(vr, args, pts, cloud.thr)  # one-time, untimed
     el, counts, tri_ms = _time_builds(vr, torch, pts, cloud.thr, args.steps, args.warmup)
     n, K, T = counts
     simplices = n + K + T
@@ -361,14 +374,14 @@ def main():
     if not args.no_extra and args.workload == "circle1000":
         c3 = _workload("mixture4000")
         p3 = torch.from_numpy(c3.points).to("cuda:0")
-        if not args.no_tune:
-            vr.autotune(p3, c3.thr)
+        t3s = vr.autotune(p3, c3.thr) if not args.no_tune else None
         e3, cnt3, t3 = _time_builds(vr, torch, p3, c3.thr, 10, 2)
         s3 = sum(cnt3)
         a3 = _alg_bytes(cnt3[0], cnt3[1], cnt3[2], cnt3[0] ** 2)
         extra["mixture4000_r64_p10"] = {
             "value": s3 * 10 / e3, "unit": "simplices/s", "ms_per_step": 1e3 * e3 / 10,
-            "counts": list(cnt3), "tri_write_ms": round(t3, 5), "tri_write_traffic": _traffic("mixture4000"),
+            "counts": list(cnt3), "schedule": list(t3s) if t3s else "default",
+            "tri_write_ms": round(t3, 5), "tri_write_traffic": _traffic("mixture4000"),
             "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
             "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3) if args.breakdown_reps > 0 else {}}
         del p3

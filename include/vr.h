@@ -228,6 +228,12 @@ VR_API void vr_batch_free(vr_batch *batch, void *stream);
  */
 VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sched[6]);
 
+/* Sets the schedule of these requests' size class, as vr_autotune would
+ * have chosen it: sched[0..5] as vr_autotune reports them, each one of that
+ * function's candidates (else VR_EINVAL).  For reusing a schedule tuned
+ * earlier (e.g. in another process) without tuning again.  Host only. */
+VR_API int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t sched[6]);
+
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from
  * the driver once and reused by later builds of any stream (a reuse on

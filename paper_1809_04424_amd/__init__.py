@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_trim",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -110,6 +110,8 @@ def lib():
         L.vr_autotune.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_int32)]
         L.vr_autotune.restype = ctypes.c_int
+        L.vr_set_schedule.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
+        L.vr_set_schedule.restype = ctypes.c_int
         L.vr_trim.argtypes = []
         L.vr_trim.restype = ctypes.c_int64
         L.vr_status_string.argtypes = [ctypes.c_int]
@@ -414,6 +416,19 @@ def autotune(points, thr, maxdim: int = 2):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return tuple(int(x) for x in sched)
+
+
+def set_schedule(points, thr, sched, maxdim: int = 2):
+    """Pin the triangle kernels' schedule (the 6-tuple autotune returns) for
+    the size class of these clouds, without tuning."""
+    L = lib()
+    pts = [_check_points(p) for p in (points if isinstance(points, (list, tuple)) else [points])]
+    thrs = list(thr) if isinstance(thr, list) else [thr] * len(pts)
+    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None) for p, t in zip(pts, thrs)])
+    arr = (ctypes.c_int32 * 6)(*[int(x) for x in sched])
+    rc = L.vr_set_schedule(reqs, len(pts), arr)
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
 
 
 def batch_limit(dtype: int, d: int) -> int:

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <initializer_list>
 #include <list>
 #include <map>
 #include <mutex>
@@ -906,7 +907,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             if (hipEventSynchronize(e[1]) == hipSuccess) (void)hipEventElapsedTime(&t, e[0], e[1]);
             return t;
         };
-        for (int rep = 0; rep < 2; rep++)
+        for (int rep = 0; rep < 3; rep++)
             for (int eb : cand_eb)
                 for (int p : cand_p) {
                     if (V * p > (1ll << 30)) continue;
@@ -1037,6 +1038,25 @@ int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int32_t sch
     }
     delete b;
     return st;
+}
+
+int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t sched[6]) {
+    if (!reqs || count < 1 || !sched) return VR_EINVAL;
+    auto in = [](int v, std::initializer_list<int> ok) {
+        for (int x : ok)
+            if (v == x) return true;
+        return false;
+    };
+    if (!in(sched[0], {128, 256, 512}) || !in(sched[1], {1, 2, 4, 8, 16}) || !in(sched[2], {2, 4, 8}) ||
+        !in(sched[3], {128, 256, 512}) || !in(sched[4], {1, 2, 4, 8, 16}) || !in(sched[5], {4, 8}))
+        return VR_EINVAL;
+    Shape S;
+    const int st = shape_of(reqs, count, S);
+    if (st != VR_OK) return st;
+    Tuning &tu = tuning();
+    std::lock_guard<std::mutex> g(tu.mu);
+    tu.sched[size_class(S.V, S.Kmax)] = Sched{sched[0], sched[1], sched[2], sched[3], sched[4], sched[5]};
+    return VR_OK;
 }
 
 int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, vr_batch **out) {

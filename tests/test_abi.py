@@ -152,3 +152,18 @@ def test_unpack_rejects_bad_arguments():
     assert L.vr_unpack_triangles(ctypes.byref(r), 16, None) == vr.VR_EINVAL
     empty = vr.VrResult(10, 5, 0, None, None, None)
     assert L.vr_unpack_triangles(ctypes.byref(empty), None, None) == vr.VR_OK
+
+
+def test_set_schedule_validates():
+    L = vr.lib()
+    arr = (vr.VrRequest * 1)(_req())
+    good = (ctypes.c_int32 * 6)(256, 1, 4, 256, 2, 8)
+    assert L.vr_set_schedule(arr, 1, good) == vr.VR_OK
+    for bad in [(64, 1, 4, 256, 2, 8), (256, 3, 4, 256, 2, 8), (256, 1, 5, 256, 2, 8), (256, 1, 4, 256, 2, 2),
+                (256, 1, 4, 1024, 2, 8), (256, 1, 4, 256, 32, 8)]:
+        assert L.vr_set_schedule(arr, 1, (ctypes.c_int32 * 6)(*bad)) == vr.VR_EINVAL
+    assert L.vr_set_schedule(None, 1, good) == vr.VR_EINVAL
+    assert L.vr_set_schedule(arr, 0, good) == vr.VR_EINVAL
+    assert L.vr_set_schedule(arr, 1, None) == vr.VR_EINVAL
+    arr = (vr.VrRequest * 1)(_req(d=0))
+    assert L.vr_set_schedule(arr, 1, good) == vr.VR_EINVAL

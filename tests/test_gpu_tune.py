@@ -49,3 +49,17 @@ def test_autotune_without_triangles():
     c = workloads.uniform_cloud(5, 50, 3)
     c.thr = ("fraction", 10, 100)
     assert vr.autotune(torch.from_numpy(c.points).to("cuda:0"), c.thr, maxdim=1) == (0,) * 6
+
+
+@pytest.mark.parametrize("sched", [(128, 16, 2, 128, 16, 4), (512, 1, 8, 512, 1, 8), (256, 4, 4, 128, 2, 4)])
+def test_pinned_schedule_builds_match_oracle(orc, sched):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.noisy_circle(seed=60, n=450)
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    vr.set_schedule(pts, c.thr, sched)
+    r, out = gpu_build(c)
+    assert_matches_oracle(out, orc.build(c.points, c.thr))
+    r.free()
