@@ -9,7 +9,10 @@ only marshals numpy arrays through ctypes.  What each step computes, with the
 passage of arXiv:1809.04424 it follows:
 
 * squared distances of all pairs i<j in lexicographic order (Section 2.1:
-  points closer than the threshold are joined by an edge);
+  points closer than the threshold are joined by an edge), or, for a
+  dissimilarity-matrix input (Section 3: the input may be a symmetric
+  distance matrix instead of points), the matrix's entries above the
+  diagonal in the same order;
 * edge ranks: the sortperm of those distances, ties by pair index
   (Section 4.5, the sortperm example);
 * kept edges: the first K ranks for the threshold specification
@@ -137,12 +140,33 @@ class Filtration:
         return (self.n, self.K, self.T)
 
 
+def matrix_pairs(M) -> np.ndarray:
+    """q[e] = M[i, j] for every pair i<j in lexicographic order (int64), for a
+    square matrix of non-negative integer dissimilarities (the entries below
+    the diagonal are not read)."""
+    m = np.asarray(M)
+    if m.ndim != 2 or m.shape[0] != m.shape[1] or m.dtype.kind not in "iu":
+        raise ValueError("a dissimilarity matrix must be a square integer array")
+    i, j = pair_lists(m.shape[0])
+    q = m[i, j].astype(np.int64)
+    if len(q) and q.min() < 0:
+        raise ValueError("dissimilarities must be non-negative")
+    return q
+
+
 def build(points, thr, maxdim: int = 2, list_triangles: bool = True) -> Filtration:
     """The whole front end on the CPU: distances, ranks, threshold, triangles."""
-    L = lib()
     p = _pts(points)
-    n = p.shape[0]
-    q = sqdist(p)
+    return _build_from_pairs(p.shape[0], sqdist(p), thr, maxdim, list_triangles)
+
+
+def build_matrix(M, thr, maxdim: int = 2, list_triangles: bool = True) -> Filtration:
+    """As build, from a dissimilarity matrix (its upper triangle) instead of points."""
+    return _build_from_pairs(np.asarray(M).shape[0], matrix_pairs(M), thr, maxdim, list_triangles)
+
+
+def _build_from_pairs(n, q, thr, maxdim, list_triangles) -> Filtration:
+    L = lib()
     E = len(q)
     order = sortperm(q)
     K = num_kept(thr, q)

@@ -275,3 +275,77 @@ def test_noisy_circle_has_one_dominant_h1_bar(orc):
     assert p.betti()[1] == 1
     finite = [d - b for dim, b, d in orc.barcode(f, p) if dim == 1 and d != np.iinfo(np.int64).max]
     assert max(finite, default=0) < f.K // 10
+
+
+# ---------------------------------------------------------------------------
+# Dissimilarity-matrix input (the paper's Section 3: the input may be a
+# symmetric distance matrix instead of points; its HIV example uses Hamming
+# distances).
+
+
+def _sq_matrix(points):
+    p = points.astype(np.int64)
+    return ((p[:, None, :] - p[None, :, :]) ** 2).sum(-1)
+
+
+@pytest.mark.parametrize("case", [
+    (workloads.uniform_cloud(91, 60, 3), ("fraction", 25, 100)),
+    (workloads.lattice_cloud(92, 70, side=3, d=2), ("fraction", 40, 100)),  # many ties
+    (workloads.uniform_cloud(93, 45, 5), ("sqdist", 20000, 0)),
+    (workloads.uniform_cloud(94, 30, 2), ("full", 0, 1)),
+])
+def test_matrix_input_equals_points_input(orc, case):
+    cloud, thr = case
+    f = orc.build(cloud.points, thr)
+    g = orc.build_matrix(_sq_matrix(cloud.points).astype(np.int32), thr)
+    assert f.counts == g.counts
+    for a, b in ((f.ei, g.ei), (f.ej, g.ej), (f.eq, g.eq), (f.tris, g.tris), (f.R, g.R)):
+        assert np.array_equal(a, b)
+
+
+def _hypercube_hamming(m):
+    x = np.arange(1 << m)
+    return np.array([[bin(a ^ b).count("1") for b in x] for a in x], np.int32)
+
+
+@pytest.mark.parametrize("m", [3, 4, 5])
+def test_hypercube_hamming_closed_forms(orc, m):
+    n = 1 << m
+    M = _hypercube_hamming(m)
+    # distance < 2: the hypercube graph, m 2^(m-1) edges and, being
+    # bipartite, no triangles
+    f = orc.build_matrix(M, ("sqdist", 2, 0))
+    assert f.counts == (n, m * (1 << (m - 1)), 0)
+    assert set(f.eq.tolist()) == {1}
+    # full threshold: every pair and triple
+    f = orc.build_matrix(M, ("full", 0, 1))
+    assert f.counts == (n, math.comb(n, 2), math.comb(n, 3))
+    # distance < 3: each vertex has C(m,1) + C(m,2) neighbours; a triple is a
+    # triangle when its three distances are at most 2 (brute force)
+    f = orc.build_matrix(M, ("sqdist", 3, 0))
+    assert f.K == n * (m + math.comb(m, 2)) // 2
+    T = sum(1 for a in range(n) for b in range(a + 1, n) for c in range(b + 1, n)
+            if M[a, b] <= 2 and M[a, c] <= 2 and M[b, c] <= 2)
+    assert f.T == T
+
+
+def test_matrix_ties_rank_by_pair_index(orc):
+    n, frac = 14, ("fraction", 30, 100)
+    M = np.ones((n, n), np.int32)
+    f = orc.build_matrix(M, frac)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    K = len(pairs) * 30 // 100  # the fraction threshold keeps floor(E num / den) edges
+    assert f.K == K
+    assert list(zip(f.ei.tolist(), f.ej.tolist())) == pairs[:K]
+    rank = {p: r for r, p in enumerate(pairs[:K])}
+    want = sorted((max(rank[(a, b)], rank[(a, c)], rank[(b, c)]), a, b, c)
+                  for a in range(n) for b in range(a + 1, n) for c in range(b + 1, n)
+                  if (a, b) in rank and (a, c) in rank and (b, c) in rank)
+    assert [tuple(t) for t in f.tris.tolist()] == want
+
+
+def test_matrix_input_rejects_negative_or_nonsquare(orc):
+    with pytest.raises(ValueError):
+        orc.build_matrix(-np.ones((5, 5), np.int32), ("full", 0, 1))
+    with pytest.raises(ValueError):
+        orc.build_matrix(np.ones((5, 4), np.int32), ("full", 0, 1))
