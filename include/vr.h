@@ -55,11 +55,16 @@ typedef enum {
     VR_ENOMEM = -2, /* a device allocation failed (nothing is leaked) */
     VR_E2BIG = -3,  /* n > VR_MAX_POINTS or K > VR_MAX_EDGES: outside the key packing */
     VR_EHIP = -4,   /* a HIP runtime call failed */
-    VR_ERANGE = -5  /* some squared distance does not fit in 32 bits unsigned */
+    VR_ERANGE = -5  /* some squared distance does not fit in 32 bits unsigned (or a VR_DIST entry is negative) */
 } vr_status;
 
-/* Coordinate types (signed integers). */
-enum { VR_I8 = 1, VR_I16 = 2, VR_I32 = 3 };
+/* Coordinate types (signed integers).  VR_DIST: `points` is instead an
+ * n x n row-major int32 matrix of non-negative dissimilarities (d = n, or 1
+ * when n = 0); entry [i][j], i < j, is the pair's squared distance q (the
+ * paper accepts a symmetric distance matrix in place of points, Section 3);
+ * entries on and below the diagonal are not read, and a negative entry
+ * fails the build with VR_ERANGE. */
+enum { VR_I8 = 1, VR_I16 = 2, VR_I32 = 3, VR_DIST = 4 };
 
 /* Threshold kinds (the paper's upper limit, Section 3; infinite by default,
  * Section 5).  E = n(n-1)/2 is the number of vertex pairs.
@@ -96,7 +101,7 @@ typedef struct vr_allocator {
 typedef struct vr_request {
     const void *points; /* device pointer, row-major n x d, dtype coordinates (rows are points) */
     int64_t n, d;       /* 0 <= n <= VR_MAX_POINTS, d >= 1 */
-    int32_t dtype;      /* VR_I8, VR_I16 or VR_I32 */
+    int32_t dtype;      /* VR_I8, VR_I16, VR_I32, or VR_DIST (a dissimilarity matrix) */
     int32_t thr_kind;   /* VR_THR_* */
     int64_t thr_num, thr_den;
     int32_t maxdim;     /* 0: vertices only, 1: up to edges, 2: up to triangles */

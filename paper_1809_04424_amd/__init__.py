@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvrhip.so")
 
 VR_OK, VR_EINVAL, VR_ENOMEM, VR_E2BIG, VR_EHIP, VR_ERANGE = 0, -1, -2, -3, -4, -5
-VR_I8, VR_I16, VR_I32 = 1, 2, 3
+VR_I8, VR_I16, VR_I32, VR_DIST = 1, 2, 3, 4
 VR_THR = {"full": 0, "count": 1, "fraction": 2, "sqdist": 3}
 VR_COUNT_ONLY, VR_TIMING, VR_TIMING_WRITE, VR_GRAPH = 1, 2, 4, 8
 VR_MAX_POINTS = 8192
@@ -370,13 +370,13 @@ def _flags(count_only, timing, graph=False):
             (VR_GRAPH if graph else 0))
 
 
-def _request(pts, thr, maxdim, flags, alloc):
+def _request(pts, thr, maxdim, flags, alloc, matrix=False):
     kind, num, den = thr
     return VrRequest(
         points=pts.data_ptr() if pts.numel() else None,
         n=pts.shape[0],
-        d=pts.shape[1],
-        dtype=_dtype_code(pts),
+        d=pts.shape[1] if pts.shape[0] or not matrix else 1,
+        dtype=VR_DIST if matrix else _dtype_code(pts),
         thr_kind=VR_THR[kind],
         thr_num=int(num),
         thr_den=int(den),
@@ -468,6 +468,32 @@ def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False,
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return Result(out, alloc, ctypes.c_void_p(stream.cuda_stream), pts.device)
+
+
+def build_matrix(dist, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing=False,
+                 allocator: str = "library") -> Result:
+    """As build, from a dissimilarity matrix instead of points.
+
+    dist: torch int32 tensor (n, n) on a HIP device, entries >= 0; entry
+          [i][j] with i < j is the squared distance of the pair (entries on
+          and below the diagonal are not read).  thr as for build ("sqdist"
+          compares the entries).
+    """
+    import torch
+
+    L = lib()
+    m = _check_points(dist)
+    if m.dtype != torch.int32 or m.shape[0] != m.shape[1]:
+        raise ValueError("a dissimilarity matrix must be a square int32 tensor")
+    alloc = _allocator_for(m.device) if allocator == "torch" else None
+    stream = torch.cuda.current_stream(m.device)
+    req = _request(m, thr, maxdim, _flags(count_only, timing), alloc, matrix=True)
+    out = ctypes.POINTER(VrResult)()
+    with torch.cuda.device(m.device):
+        rc = L.vr_build(ctypes.byref(req), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return Result(out, alloc, ctypes.c_void_p(stream.cuda_stream), m.device)
 
 
 def build_batch(points, thr, maxdim: int = 2, count_only: bool = False, timing=False,

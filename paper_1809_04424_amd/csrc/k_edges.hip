@@ -149,12 +149,64 @@ __global__ __launch_bounds__(VR_BLOCK) void k_dist(VrDev D) {
     }
 }
 
+// ---------------------------------------------------------- k_dist_mat ----
+// Dissimilarity-matrix input (the paper's Section 3 accepts a symmetric
+// distance matrix in place of points): q of pair i<j is entry [i][j] of the
+// cloud's n x n int32 matrix; the entries below the diagonal are not read.
+// Same tiles, pair order and histogram as k_dist; a negative entry raises
+// the overflow flag (VR_ERANGE).  Lane l of every wave reads column
+// j = 64 bj + l of rows i = 64 bi + w + 4m, so each wave reads 256
+// contiguous bytes of a row.
+__global__ __launch_bounds__(VR_BLOCK) void k_dist_mat(VrDev D) {
+    const long long tg = blockIdx.x;
+    const int c = (D.C == 1) ? 0 : (int)D.tcloud[tg];
+    const VrCloud cl = D.cl[c];
+    const int n = cl.n;
+    int bi, bj;
+    tile_of(tg - cl.tbase, (n + DIST_TB - 1) / DIST_TB, &bi, &bj);
+    const int32_t *__restrict__ M = (const int32_t *)cl.points;
+    uint32_t *__restrict__ q = D.q + cl.pbase;
+    __shared__ uint32_t hist[VR_NBUCKET];
+    const int need_hist = D.need_hist;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = bj * DIST_TB + lane;
+    if (need_hist) {
+        for (int b = threadIdx.x; b < VR_NBUCKET; b += VR_BLOCK) hist[b] = 0u;
+        __syncthreads();
+    }
+    uint32_t over = 0;
+    int32_t v[16];
+#pragma unroll
+    for (int m = 0; m < 16; m++) {  // clamped addresses: every load is issued at once
+        const int i = min(bi * DIST_TB + w + 4 * m, n - 1);
+        v[m] = M[(size_t)i * n + min(j, n - 1)];
+    }
+#pragma unroll
+    for (int m = 0; m < 16; m++) {
+        const int i = bi * DIST_TB + w + 4 * m;
+        if (i < j && j < n) {
+            if (v[m] < 0) over = 1u;
+            const uint32_t qq = v[m] < 0 ? 0u : (uint32_t)v[m];
+            q[row_start(i, n) + (j - i - 1)] = qq;
+            if (need_hist) atomicAdd(&hist[bucket_of(qq)], 1u);
+        }
+    }
+    if (over) atomicOr(&D.ctl->flags, 1u);
+    if (need_hist) {
+        __syncthreads();
+        uint32_t *gh = D.hist + ((size_t)c * D.hcopies + blockIdx.x % D.hcopies) * VR_NBUCKET;
+        for (int b = threadIdx.x; b < VR_NBUCKET; b += VR_BLOCK)
+            if (hist[b]) atomicAdd(&gh[b], hist[b]);
+    }
+}
+
 void launch_dist(const VrDev &D, const void *points, hipStream_t s) {
     (void)points;
     const dim3 grid((unsigned)D.tiles);
     if (D.dtype == 1) hipLaunchKernelGGL(k_dist<int8_t>, grid, dim3(VR_BLOCK), 0, s, D);
     else if (D.dtype == 2) hipLaunchKernelGGL(k_dist<int16_t>, grid, dim3(VR_BLOCK), 0, s, D);
-    else hipLaunchKernelGGL(k_dist<int32_t>, grid, dim3(VR_BLOCK), 0, s, D);
+    else if (D.dtype == 3) hipLaunchKernelGGL(k_dist<int32_t>, grid, dim3(VR_BLOCK), 0, s, D);
+    else hipLaunchKernelGGL(k_dist_mat, grid, dim3(VR_BLOCK), 0, s, D);  // VR_DIST
 }
 
 // -------------------------------------------------------------- k_pivot ----

@@ -320,7 +320,8 @@ int key_bits(int dtype, long long d) {
 int check_request(const vr_request *req, long long *E_out, long long *K_out) {
     if (!req) return VR_EINVAL;
     if (req->n < 0 || req->d < 1) return VR_EINVAL;
-    if (req->dtype != VR_I8 && req->dtype != VR_I16 && req->dtype != VR_I32) return VR_EINVAL;
+    if (req->dtype != VR_I8 && req->dtype != VR_I16 && req->dtype != VR_I32 && req->dtype != VR_DIST) return VR_EINVAL;
+    if (req->dtype == VR_DIST && req->d != (req->n > 0 ? req->n : 1)) return VR_EINVAL;  // an n x n matrix
     if (req->maxdim < 0 || req->maxdim > 2) return VR_EINVAL;
     if (req->n > 0 && !req->points) return VR_EINVAL;
     if (req->n > VR_MAX_POINTS) return VR_E2BIG;
@@ -966,7 +967,7 @@ const char *vr_status_string(int status) {
     case VR_ENOMEM: return "device allocation failed";
     case VR_E2BIG: return "too many points or edges for the packed keys";
     case VR_EHIP: return "HIP runtime error";
-    case VR_ERANGE: return "a squared distance exceeds 32 bits";
+    case VR_ERANGE: return "a squared distance exceeds 32 bits, or a dissimilarity is negative";
     default: return "unknown status";
     }
 }

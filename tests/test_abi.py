@@ -167,3 +167,13 @@ def test_set_schedule_validates():
     assert L.vr_set_schedule(arr, 1, None) == vr.VR_EINVAL
     arr = (vr.VrRequest * 1)(_req(d=0))
     assert L.vr_set_schedule(arr, 1, good) == vr.VR_EINVAL
+
+
+def test_dissimilarity_matrix_request_shape():
+    L = vr.lib()
+    assert L.vr_workspace_bytes(100, 100, vr.VR_DIST, vr.VR_THR["fraction"]) > 0
+    assert L.vr_workspace_bytes(100, 3, vr.VR_DIST, vr.VR_THR["fraction"]) == -1  # d must equal n
+    arr = (vr.VrRequest * 1)(_req(d=3))
+    arr[0].dtype = vr.VR_DIST
+    out = ctypes.POINTER(vr.VrResult)()
+    assert L.vr_build(arr, None, ctypes.byref(out)) == vr.VR_EINVAL

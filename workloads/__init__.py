@@ -168,6 +168,18 @@ def uniform_cloud(seed: int, n: int, d: int, lo: int = -127, hi: int = 127,
     return Cloud(np.ascontiguousarray(pts), thr, name=f"uniform{n}x{d}_s{seed}")
 
 
+def hamming_matrix(seed: int, n: int, bits: int = 96, flip: float = 0.1, clusters: int = 6):
+    """Pairwise Hamming distances (int32 n x n) of n binary sequences of
+    `bits` bits drawn around a few random centre sequences (each bit flipped
+    with probability `flip`): a stand-in for sequence data such as the
+    paper's HIV example, which uses Hamming distances."""
+    rng = np.random.default_rng(seed)
+    centres = rng.integers(0, 2, (clusters, bits), dtype=np.int8)
+    seqs = centres[rng.integers(0, clusters, n)] ^ (rng.random((n, bits)) < flip).astype(np.int8)
+    m = (seqs[:, None, :] != seqs[None, :, :]).sum(-1).astype(np.int32)
+    return np.ascontiguousarray(m)
+
+
 def lattice_cloud(seed: int, n: int, side: int = 4, d: int = 2, thr=("full", 0, 1)) -> Cloud:
     """Points drawn from the lattice {0..side-1}^d: many exact distance ties and duplicates."""
     rng = np.random.default_rng(seed)
