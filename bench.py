@@ -61,14 +61,15 @@ def _workload(name):
             "plain64": workloads.plain64}[name]()
 
 
-def _time_builds(vr, torch, pts, thr, steps, warmup):
+def _time_builds(vr, torch, pts, thr, steps, warmup, build=None):
     """Time `steps` whole builds; HIP events bracket only the triangle write
     (on the build's stream), so its average launch duration is measured live.
     Each result is freed once the next build has been issued, as a caller
     consuming results would; its events have completed by then."""
+    build = build or vr.build
     prev = None
     for _ in range(max(warmup, 2)):  # two results alive at once, as in the timed loop
-        r = vr.build(pts, thr, timing="write")
+        r = build(pts, thr, timing="write")
         if prev is not None:
             prev.free()
         prev = r
@@ -79,7 +80,7 @@ def _time_builds(vr, torch, pts, thr, steps, warmup):
     prev = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = vr.build(pts, thr, timing="write")
+        r = build(pts, thr, timing="write")
         if prev is not None:
             tw.append(prev.stage_ms()["tri_write"])
             prev.free()
@@ -306,6 +307,25 @@ def _schedule(vr, args, pts, thr):
     return vr.autotune(pts, thr) if not args.no_tune else None
 
 
+def _hamming(vr, torch, tune=True, steps=5, warmup=2):
+    """Dissimilarity-matrix input: pairwise Hamming distances of 1088 synthetic
+    binary sequences (the shape of the paper's sequence example), every pair
+    kept: C(1088, 3) = 214 million triangles per build."""
+    import workloads
+
+    M = torch.from_numpy(workloads.hamming_matrix(1088, 1088)).to("cuda:0")
+    thr = ("full", 0, 1)
+    sch = vr.autotune(M, thr, matrix=True) if tune else None
+    el, cnt, tw = _time_builds(vr, torch, M, thr, steps, warmup, build=vr.build_matrix)
+    a = _alg_bytes(cnt[0], cnt[1], cnt[2], cnt[0] ** 2)
+    del M
+    return {"value": sum(cnt) * steps / el, "unit": "simplices/s", "ms_per_step": 1e3 * el / steps,
+            "steps": steps, "counts": list(cnt), "schedule": list(sch) if sch else "default",
+            "input": "int32 1088 x 1088 Hamming matrix of 96-bit sequences, full threshold",
+            "tri_write_ms": round(tw, 5),
+            "tri_write_frac_hbm": round(a / (tw * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tw > 0 else None}
+
+
 def _alg_bytes(n, K, T, n2):
     """Algorithmic bytes of the triangle writer: triangle keys out (8 T), kept
     ranks in (8 K), the adjacency once (n^2/8 over the clouds), and the fused
@@ -385,6 +405,9 @@ def main():
             "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
             "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3) if args.breakdown_reps > 0 else {}}
         del p3
+
+    if not args.no_extra and args.workload == "circle1000":
+        extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
 
     if not args.no_batch and args.workload == "circle1000":
         extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)

@@ -396,12 +396,13 @@ def _check_points(points):
     return points.contiguous()
 
 
-def autotune(points, thr, maxdim: int = 2):
+def autotune(points, thr, maxdim: int = 2, matrix: bool = False):
     """Tune the triangle kernels' schedule for the size class of these clouds
-    (one tensor or a list, as build_batch); returns (count block size, count
-    work-groups per vertex, count pieces, write block size, write work-groups
-    per vertex, write pieces), which later builds of the class use.  Outputs
-    do not depend on it."""
+    (one tensor or a list, as build_batch; matrix=True: one dissimilarity
+    matrix, as build_matrix); returns (count block size, count work-groups
+    per vertex, count pieces, write block size, write work-groups per vertex,
+    write pieces), which later builds of the class use.  Outputs do not
+    depend on it."""
     import torch
 
     L = lib()
@@ -409,7 +410,7 @@ def autotune(points, thr, maxdim: int = 2):
     thrs = list(thr) if isinstance(thr, list) else [thr] * len(pts)
     dev = pts[0].device
     stream = torch.cuda.current_stream(dev)
-    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None) for p, t in zip(pts, thrs)])
+    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None, matrix) for p, t in zip(pts, thrs)])
     sched = (ctypes.c_int32 * 6)()
     with torch.cuda.device(dev):
         rc = L.vr_autotune(reqs, len(pts), ctypes.c_void_p(stream.cuda_stream), sched)
@@ -418,13 +419,13 @@ def autotune(points, thr, maxdim: int = 2):
     return tuple(int(x) for x in sched)
 
 
-def set_schedule(points, thr, sched, maxdim: int = 2):
+def set_schedule(points, thr, sched, maxdim: int = 2, matrix: bool = False):
     """Pin the triangle kernels' schedule (the 6-tuple autotune returns) for
     the size class of these clouds, without tuning."""
     L = lib()
     pts = [_check_points(p) for p in (points if isinstance(points, (list, tuple)) else [points])]
     thrs = list(thr) if isinstance(thr, list) else [thr] * len(pts)
-    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None) for p, t in zip(pts, thrs)])
+    reqs = (VrRequest * len(pts))(*[_request(p, t, maxdim, 0, None, matrix) for p, t in zip(pts, thrs)])
     arr = (ctypes.c_int32 * 6)(*[int(x) for x in sched])
     rc = L.vr_set_schedule(reqs, len(pts), arr)
     if rc != VR_OK:

@@ -100,3 +100,39 @@ def test_negative_entry_is_reported():
     with pytest.raises(vr.VrError) as e:
         vr.build_matrix(_mat(M), ("fraction", 20, 100))
     assert e.value.code == vr.VR_ERANGE
+
+
+def test_hamming1088_full_threshold_at_size(orc):
+    """The sequence-data shape at full size (1088 sequences, every pair kept,
+    C(1088, 3) triangles), in the launch configuration the benchmark times.
+    Edges are compared bit-exactly; the 214 million triangle keys through
+    properties that pin them: strictly increasing keys, i < j < k, and each
+    key's value equal to the largest rank among its three edges, so with the
+    closed-form count every triangle appears once, in (value, lex) order."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    n = 1088
+    M = workloads.hamming_matrix(1088, n)
+    f = orc.build_matrix(M, ("full", 0, 1), list_triangles=False)
+    assert f.T == n * (n - 1) * (n - 2) // 6
+    print("[gpu] hamming1088 full", flush=True)
+    r = vr.build_matrix(_mat(M), ("full", 0, 1))
+    torch.cuda.synchronize()
+    assert tuple(r.counts) == (n, f.K, f.T)
+    ij = r.edge_ij().cpu().numpy().astype(np.int64)
+    assert np.array_equal(ij[:, 0], f.ei) and np.array_equal(ij[:, 1], f.ej)
+    assert np.array_equal(r.edge_q().cpu().numpy(), f.eq)
+    keys = r.tri_key()
+    R = torch.from_numpy(f.R.astype(np.int64)).to("cuda:0").reshape(-1)
+    mask = (1 << 13) - 1
+    step = 1 << 24
+    for a in range(0, keys.numel(), step):
+        k = keys[a:a + step + 1]
+        assert bool((k[1:] > k[:-1]).all())
+        v, i, j, l = k >> 39, (k >> 26) & mask, (k >> 13) & mask, k & mask
+        assert bool(((i < j) & (j < l) & (l < n)).all())
+        want = torch.maximum(torch.maximum(R[i * n + j], R[i * n + l]), R[j * n + l])
+        assert bool((v == want).all())
+    r.free()
