@@ -19,6 +19,9 @@ passage of arXiv:1809.04424 it follows:
   (Section 2.1; Section 5 uses the infinite threshold by default);
 * triangles: every triple whose three edges are kept, valued at its largest
   edge rank, sorted by (value, i, j, k) (Section 2.1);
+* per-column ordering of a compressed-sparse-column array: the slot of every
+  entry when its column is sorted stably by value, by the original and by the
+  modified counting sort of Section 4.3;
 * persistence pairs: Algorithm 1 over F2 on the boundary matrix, and the same
   algorithm on the anti-transpose with clearing (Sections 2.2.1, 2.2.2).
 """
@@ -76,6 +79,10 @@ def lib():
     L.or_reduce_homology.restype = None
     L.or_reduce_cohomology.argtypes = [i64, i64, _I64P, _I64P, i64, _I64P, _I64P, _I64P]
     L.or_reduce_cohomology.restype = None
+    L.or_colorder_original.argtypes = [i64, _I64P, _I64P, i64, _I64P]
+    L.or_colorder_original.restype = ctypes.c_int
+    L.or_colorder_modified.argtypes = [i64, _I64P, _I64P, i64, _I64P]
+    L.or_colorder_modified.restype = ctypes.c_int
     _LIB = L
     return L
 
@@ -287,3 +294,44 @@ def barcode(f: Filtration, pairs: Pairs):
     bars += [(1, int(r), INF) for r in b_]
     bars += [(2, int(tv[t]), INF) for t in c]
     return sorted(bars)
+
+
+def _csc(colptr, v):
+    cp = np.ascontiguousarray(colptr, dtype=np.int64)
+    vv = np.ascontiguousarray(v, dtype=np.int64)
+    if cp.ndim != 1 or len(cp) < 1 or cp[0] != 0 or np.any(np.diff(cp) < 0) or cp[-1] != len(vv):
+        raise ValueError("colptr must start at 0, not decrease, and end at len(v)")
+    return cp, vv
+
+
+def _colorder(fn, colptr, v, maxvalue):
+    cp, vv = _csc(colptr, v)
+    if maxvalue is None:
+        maxvalue = int(vv.max()) if len(vv) else 0
+    z = np.zeros(max(len(vv), 1), np.int64)
+    rc = fn(len(cp) - 1, cp, vv if len(vv) else np.zeros(1, np.int64), int(maxvalue), z)
+    if rc != 0:
+        raise ValueError("values must lie in 0..maxvalue")
+    return z[: len(vv)]
+
+
+def column_order_original(colptr, v, maxvalue=None) -> np.ndarray:
+    """Section 4.3, original version: z[i] = slot of entry i in its column
+    sorted stably by value (0-based), values in 0..maxvalue."""
+    return _colorder(lib().or_colorder_original, colptr, v, maxvalue)
+
+
+def column_order_modified(colptr, v, maxvalue=None) -> np.ndarray:
+    """Section 4.3, modified version (prefix sums over each column's own value
+    range only, counts cleared per range); same result as the original."""
+    return _colorder(lib().or_colorder_modified, colptr, v, maxvalue)
+
+
+def column_order(colptr, v) -> np.ndarray:
+    """The per-column order for any integer values: the modified counting
+    sort after replacing each value by its position among the distinct
+    values (an order-preserving relabelling keeps every comparison, hence
+    the order, and bounds the count array by the number of entries)."""
+    cp, vv = _csc(colptr, v)
+    _, dense = np.unique(vv, return_inverse=True)
+    return column_order_modified(cp, dense.astype(np.int64).reshape(-1))

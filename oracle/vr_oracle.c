@@ -461,3 +461,81 @@ void or_reduce_cohomology(int64_t n, int64_t K, const int64_t *ei, const int64_t
         free(piv); free(skip); free(cr); free(cp); free(cnt); free(R);
     }
 }
+
+/*
+ * Section 4.3 (redundant calculations): the per-column ordering of integers
+ * of a compressed-sparse-column array.  Column j holds the entries
+ * colptr[j] .. colptr[j+1]-1 with integer values v in 0..maxvalue; z[i] is
+ * the slot entry i takes when its column is sorted by value, equal values
+ * keeping their order (a stable counting sort per column).  Indices here are
+ * 0-based where the paper's are 1-based.
+ *
+ * The original version clears one count per possible value for every column,
+ * counts the column's values, takes prefix sums over the whole value range
+ * into a second array starting at the column's first slot, and hands out the
+ * slots in entry order.
+ *
+ * The modified version keeps a single count array, cleared once: it counts
+ * the column's values, finds the column's smallest and largest value, turns
+ * the counts of that range into starting slots in place, hands out the
+ * slots, and clears only that range again.  The paper's version reads the
+ * first value of a column without checking that the column has entries; an
+ * empty column is skipped here.
+ *
+ * Both return 0, or -1 when a value lies outside 0..maxvalue (the modified
+ * version takes maxvalue only to size its count array).
+ */
+static int values_in_range(int64_t n, const int64_t *v, int64_t maxvalue) {
+    for (int64_t i = 0; i < n; i++)
+        if (v[i] < 0 || v[i] > maxvalue) return 0;
+    return 1;
+}
+
+int or_colorder_original(int64_t ncols, const int64_t *colptr, const int64_t *v, int64_t maxvalue,
+                         int64_t *z) {
+    if (!values_in_range(colptr[ncols], v, maxvalue)) return -1;
+    int64_t *x = (int64_t *)malloc(sizeof(int64_t) * (size_t)(maxvalue + 1));
+    int64_t *y = (int64_t *)malloc(sizeof(int64_t) * (size_t)(maxvalue + 2));
+    for (int64_t j = 0; j < ncols; j++) {
+        for (int64_t u = 0; u <= maxvalue; u++) x[u] = 0;
+        for (int64_t i = colptr[j]; i < colptr[j + 1]; i++) x[v[i]] += 1;
+        y[0] = colptr[j];
+        for (int64_t u = 0; u <= maxvalue; u++) y[u + 1] = y[u] + x[u];
+        for (int64_t i = colptr[j]; i < colptr[j + 1]; i++) {
+            z[i] = y[v[i]];
+            y[v[i]] += 1;
+        }
+    }
+    free(y);
+    free(x);
+    return 0;
+}
+
+int or_colorder_modified(int64_t ncols, const int64_t *colptr, const int64_t *v, int64_t maxvalue,
+                         int64_t *z) {
+    if (!values_in_range(colptr[ncols], v, maxvalue)) return -1;
+    int64_t *x = (int64_t *)calloc((size_t)(maxvalue + 1), sizeof(int64_t));
+    for (int64_t j = 0; j < ncols; j++) {
+        int64_t first = colptr[j], end = colptr[j + 1];
+        if (first == end) continue;
+        for (int64_t i = first; i < end; i++) x[v[i]] += 1;
+        int64_t lo = v[first], hi = v[first];
+        for (int64_t i = first + 1; i < end; i++) {
+            if (v[i] > hi) hi = v[i];
+            else if (v[i] < lo) lo = v[i];
+        }
+        int64_t next = first;
+        for (int64_t u = lo; u <= hi; u++) {
+            int64_t c = x[u];
+            x[u] = next;
+            next += c;
+        }
+        for (int64_t i = first; i < end; i++) {
+            z[i] = x[v[i]];
+            x[v[i]] += 1;
+        }
+        for (int64_t u = lo; u <= hi; u++) x[u] = 0;
+    }
+    free(x);
+    return 0;
+}

@@ -140,3 +140,14 @@ def kruskal_deaths(n, kept):
             parent[max(a, b)] = min(a, b)
             deaths.append(r)
     return deaths
+
+
+def column_order(colptr, v):
+    """z[i] = first slot of i's column + the entries of the column with a
+    smaller value + the earlier entries of the column with the same value."""
+    z = []
+    for j in range(len(colptr) - 1):
+        a, b = int(colptr[j]), int(colptr[j + 1])
+        for i in range(a, b):
+            z.append(a + sum(1 for t in range(a, b) if v[t] < v[i] or (v[t] == v[i] and t < i)))
+    return z

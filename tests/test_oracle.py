@@ -349,3 +349,74 @@ def test_matrix_input_rejects_negative_or_nonsquare(orc):
         orc.build_matrix(-np.ones((5, 5), np.int32), ("full", 0, 1))
     with pytest.raises(ValueError):
         orc.build_matrix(np.ones((5, 4), np.int32), ("full", 0, 1))
+
+
+# --- per-column ordering (Section 4.3) -------------------------------------
+
+def test_column_order_matches_paper_sortperm_example(orc):
+    """One column holding the Section 4.5 example: the slot of each entry is
+    the inverse of the printed sortperm (the two are inverse permutations)."""
+    rows = dict((r[0], [int(x) for x in r[1:]]) for r in _golden_rows("sortperm_example.txt"))
+    perm = [p - 1 for p in rows["sortperm"]]
+    inv = [0] * len(perm)
+    for slot, e in enumerate(perm):
+        inv[e] = slot
+    v = rows["v"]
+    for fn in (orc.column_order_original, orc.column_order_modified):
+        assert list(fn([0, len(v)], v)) == inv
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_column_order_versions_agree_and_match_bruteforce(orc, seed):
+    """Original vs modified (the paper's differential pair) and the
+    definition by counting, on ragged columns with empties and ties."""
+    colptr, v = workloads.csc_columns(seed, ncols=40, mean_len=6, maxvalue=[1, 3, 9, 50][seed % 4])
+    a = orc.column_order_original(colptr, v)
+    b = orc.column_order_modified(colptr, v)
+    assert np.array_equal(a, b)
+    assert list(a) == bf.column_order(colptr, [int(x) for x in v])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_column_order_equals_stable_library_sort(orc, seed):
+    """Per column, the inverse of numpy's stable argsort."""
+    colptr, v = workloads.csc_columns(100 + seed, ncols=300, mean_len=40, maxvalue=[0, 5, 1000, 2**20][seed],
+                                      long_cols=2, long_len=3000)
+    z = orc.column_order_modified(colptr, v)
+    ref = np.empty_like(z)
+    for j in range(len(colptr) - 1):
+        a, b = colptr[j], colptr[j + 1]
+        ref[a + np.argsort(v[a:b], kind="stable")] = np.arange(a, b)
+    assert np.array_equal(z, ref)
+    assert np.array_equal(orc.column_order_original(colptr, v), ref)
+
+
+def test_column_order_invariants(orc):
+    """Each column's slots are a permutation of its own range; placing the
+    values by z sorts every column; equal values keep their entry order."""
+    colptr, v = workloads.csc_columns(7, ncols=500, mean_len=30, maxvalue=12)
+    z = orc.column_order(colptr, v)
+    out = np.empty_like(v)
+    out[z] = v
+    src = np.empty_like(z)
+    src[z] = np.arange(len(z))
+    for j in range(len(colptr) - 1):
+        a, b = colptr[j], colptr[j + 1]
+        assert np.array_equal(np.sort(z[a:b]), np.arange(a, b))
+        assert np.all(np.diff(out[a:b]) >= 0)
+        same = np.diff(out[a:b]) == 0
+        assert np.all(np.diff(src[a:b])[same] > 0)
+
+
+def test_column_order_special_cases(orc):
+    """Empty array, empty columns only, one entry, constant columns (identity),
+    and columns already sorted (identity) or strictly descending (reversal)."""
+    assert len(orc.column_order([0, 0, 0], [])) == 0
+    assert list(orc.column_order([0, 1], [5])) == [0]
+    assert list(orc.column_order([0, 0, 4, 4], [3, 3, 3, 3])) == [0, 1, 2, 3]
+    assert list(orc.column_order([0, 3, 6], [1, 2, 3, 9, 8, 7])) == [0, 1, 2, 5, 4, 3]
+    assert list(orc.column_order([0, 4], [-5, 2**31 - 1, -2**31, 0])) == [1, 3, 0, 2]
+    with pytest.raises(ValueError):
+        orc.column_order_original([0, 2], [1, 5], maxvalue=4)
+    with pytest.raises(ValueError):
+        orc.column_order([0, 3], [1, 2])

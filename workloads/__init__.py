@@ -180,6 +180,32 @@ def hamming_matrix(seed: int, n: int, bits: int = 96, flip: float = 0.1, cluster
     return np.ascontiguousarray(m)
 
 
+def csc_columns(seed: int, ncols: int, mean_len: float, maxvalue: int, empty: float = 0.1,
+                long_cols: int = 0, long_len: int = 0, lo: int = 0):
+    """A compressed-sparse-column array (colptr int64, v int32): column
+    lengths geometric with the given mean, a fraction `empty` of the columns
+    empty, `long_cols` columns of `long_len` entries at random places, values
+    uniform in lo..lo+maxvalue (ties wherever the range is small)."""
+    rng = np.random.default_rng(seed)
+    lens = rng.geometric(1.0 / max(mean_len, 1.0), ncols).astype(np.int64) if ncols else np.zeros(0, np.int64)
+    lens[rng.random(ncols) < empty] = 0
+    if long_cols and ncols:
+        lens[rng.choice(ncols, min(long_cols, ncols), replace=False)] = long_len
+    colptr = np.zeros(ncols + 1, np.int64)
+    np.cumsum(lens, out=colptr[1:])
+    v = rng.integers(lo, lo + maxvalue + 1, int(colptr[-1]), dtype=np.int64).astype(np.int32)
+    return colptr, v
+
+
+def full_columns(seed: int, ncols: int, length: int, maxvalue: int):
+    """ncols columns of `length` entries each, values uniform in 0..maxvalue:
+    the shape of a complete graph's rank matrix stored by column."""
+    rng = np.random.default_rng(seed)
+    colptr = np.arange(ncols + 1, dtype=np.int64) * length
+    v = rng.integers(0, maxvalue + 1, ncols * length, dtype=np.int64).astype(np.int32)
+    return colptr, v
+
+
 def lattice_cloud(seed: int, n: int, side: int = 4, d: int = 2, thr=("full", 0, 1)) -> Cloud:
     """Points drawn from the lattice {0..side-1}^d: many exact distance ties and duplicates."""
     rng = np.random.default_rng(seed)
