@@ -326,6 +326,35 @@ def _hamming(vr, torch, tune=True, steps=5, warmup=2):
             "tri_write_frac_hbm": round(a / (tw * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tw > 0 else None}
 
 
+def _column_order(vr, torch, reps=20):
+    """Per-column stable order of 2000 columns x 1999 entries (the shape of a
+    complete 2000-point graph's rank matrix), values uniform in 0..1999000.
+    HIP events on the current stream bracket each call (all of its kernels)."""
+    import workloads
+
+    colptr, v = workloads.full_columns(2000, 2000, 1999, 1999000)
+    cp = torch.from_numpy(colptr).to("cuda:0")
+    vv = torch.from_numpy(v).to("cuda:0")
+    z = torch.empty(len(v), dtype=torch.int64, device="cuda:0")
+    for _ in range(3):
+        vr.column_order(cp, vv, out=z)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record()
+        vr.column_order(cp, vv, out=z)
+        e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
+    nnz, ncols = len(v), len(colptr) - 1
+    alg = 12 * nnz + 8 * (ncols + 1)  # values in, slots out, column pointers in
+    return {"entries_per_s": nnz / (ms * 1e-3), "ms_per_call": round(ms, 5), "wall_ms_per_call": round(1e3 * wall, 5),
+            "ncols": ncols, "nnz": nnz, "algorithmic_bytes": alg,
+            "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def _alg_bytes(n, K, T, n2):
     """Algorithmic bytes of the triangle writer: triangle keys out (8 T), kept
     ranks in (8 K), the adjacency once (n^2/8 over the clouds), and the fused
@@ -408,6 +437,7 @@ def main():
 
     if not args.no_extra and args.workload == "circle1000":
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
+        extra["column_order_2000x1999"] = _column_order(vr, torch)
 
     if not args.no_batch and args.workload == "circle1000":
         extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)

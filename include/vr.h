@@ -239,6 +239,24 @@ VR_API int vr_autotune(const vr_request *reqs, int64_t count, void *stream, int3
  * earlier (e.g. in another process) without tuning again.  Host only. */
 VR_API int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t sched[6]);
 
+/* Per-column stable order of a compressed-sparse-column array (Section 4.3,
+ * the ordering of the integers of every column; the paper's counting sort
+ * prefix-sums each column's value range).
+ * colptr: device, ncols + 1 int64 entries, colptr[0] = 0, non-decreasing,
+ *         colptr[ncols] = nnz; column c holds entries colptr[c] ..
+ *         colptr[c+1] - 1.
+ * v:      device, nnz int32 values (any sign).
+ * z:      device, nnz int64, caller-owned output: z[e] = colptr[c] + the
+ *         entries of e's column with a smaller value + the entries before e
+ *         in its column with the same value, i.e. the slot of entry e when
+ *         its column is sorted stably by value.
+ * Enqueued on `stream`; scratch of 4 bytes per entry comes from the
+ * library's cache.  VR_EINVAL for negative sizes, a null pointer, or
+ * entries without columns; nnz = 0 does nothing.  A colptr that breaks the
+ * rules above gives unspecified z but no access outside the arrays. */
+VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz, int64_t *z,
+                           void *stream);
+
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from
  * the driver once and reused by later builds of any stream (a reuse on

@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -112,6 +112,9 @@ def lib():
         L.vr_autotune.restype = ctypes.c_int
         L.vr_set_schedule.argtypes = [ctypes.POINTER(VrRequest), ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
         L.vr_set_schedule.restype = ctypes.c_int
+        L.vr_column_order.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_column_order.restype = ctypes.c_int
         L.vr_trim.argtypes = []
         L.vr_trim.restype = ctypes.c_int64
         L.vr_status_string.argtypes = [ctypes.c_int]
@@ -528,3 +531,32 @@ def build_batch(points, thr, maxdim: int = 2, count_only: bool = False, timing=F
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return Batch(out, alloc, ctypes.c_void_p(stream.cuda_stream), dev, len(pts))
+
+
+def column_order(colptr, v, out=None):
+    """Per-column stable order of a compressed-sparse-column array (Section
+    4.3): z[e] = the slot of entry e when its column is sorted by value,
+    equal values keeping their order.
+
+    colptr: int64 (ncols + 1,) device tensor (0, ..., nnz); v: int32 (nnz,)
+    device tensor; out: optional int64 (nnz,) device tensor.  Returns z.
+    """
+    import torch
+
+    L = lib()
+    for name, t, dt in (("colptr", colptr, torch.int64), ("v", v, torch.int32)):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dt or t.dim() != 1:
+            raise TypeError(f"{name} must be a 1-D {dt} tensor on a HIP device")
+    colptr, v = colptr.contiguous(), v.contiguous()
+    nnz = v.numel()
+    z = out if out is not None else torch.empty(nnz, dtype=torch.int64, device=v.device)
+    if z.dtype != torch.int64 or z.numel() != nnz or not z.is_contiguous():
+        raise ValueError("out must be a contiguous int64 tensor of nnz entries")
+    stream = torch.cuda.current_stream(v.device)
+    with torch.cuda.device(v.device):
+        rc = L.vr_column_order(ctypes.c_void_p(colptr.data_ptr()), colptr.numel() - 1,
+                               ctypes.c_void_p(v.data_ptr() if nnz else 0), nnz,
+                               ctypes.c_void_p(z.data_ptr() if nnz else 0), ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return z

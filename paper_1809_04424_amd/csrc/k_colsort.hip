@@ -1,0 +1,292 @@
+// k_colsort.hip -- per-column stable ordering of a compressed-sparse-column
+// array (Section 4.3: the slot every entry takes when its column is sorted by
+// value, equal values keeping their order).
+//
+// The entries are cut into windows of CO_WIN consecutive entries, whatever
+// the columns.  A window's entries fall into segments, one per column that
+// meets the window.
+//   k_co_first  per column: the windows whose first entry lies in it.
+//   k_co_local  per window: each entry's rank inside its segment (counting
+//               against the segment in LDS when every segment is short, an
+//               LDS bitonic sort otherwise), plus the column's first slot;
+//               the sorted values of segments whose column leaves the window
+//               are kept for the next kernel.
+//   k_co_merge  per window, only for the (at most two) columns that leave
+//               it: adds, for every other window the column meets, the
+//               entries there that come first (binary search in that
+//               window's sorted run: values <= x before, < x after).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vr.h"
+#include "vr_cache.h"
+
+#define CO_BLOCK 256
+#define CO_WIN 4096
+#define CO_PER (CO_WIN / CO_BLOCK)
+#define CO_COUNT_MAX 256  // longest segment ranked by counting
+#define CO_WAVE 64
+
+static __device__ __forceinline__ int64_t clampi(int64_t x, int64_t lo, int64_t hi) {
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// first[w] = the column holding entry w*CO_WIN (the non-empty column c with
+// colptr[c] <= w*CO_WIN < colptr[c+1]).
+__global__ void __launch_bounds__(CO_BLOCK) k_co_first(const int64_t *colptr, int64_t ncols, int64_t nnz,
+                                                      int64_t *first) {
+    for (int64_t c = blockIdx.x * (int64_t)CO_BLOCK + threadIdx.x; c < ncols;
+         c += (int64_t)gridDim.x * CO_BLOCK) {
+        const int64_t s = clampi(colptr[c], 0, nnz), e = clampi(colptr[c + 1], s, nnz);
+        if (e == s) continue;
+        for (int64_t w = (s + CO_WIN - 1) / CO_WIN; w <= (e - 1) / CO_WIN; w++) first[w] = c;
+    }
+}
+
+struct CoWindow {
+    int64_t a;    // first entry
+    int cnt;      // entries
+    int64_t c0;   // column of the first entry
+    int64_t cs0;  // first slot of that column
+    int64_t cl;   // column of entry a + CO_WIN (next window), or -1
+};
+
+static __device__ __forceinline__ CoWindow co_window(const int64_t *colptr, int64_t ncols, int64_t nnz,
+                                                     const int64_t *first, int64_t nwin, int64_t w) {
+    CoWindow W;
+    W.a = w * CO_WIN;
+    W.cnt = (int)min((int64_t)CO_WIN, nnz - W.a);
+    W.c0 = clampi(first[w], 0, ncols - 1);
+    W.cs0 = clampi(colptr[W.c0], 0, W.a);
+    W.cl = w + 1 < nwin ? clampi(first[w + 1], W.c0, ncols - 1) : -1;
+    return W;
+}
+
+__global__ void __launch_bounds__(CO_BLOCK) k_co_local(const int64_t *colptr, int64_t ncols, const int32_t *v,
+                                                      int64_t nnz, const int64_t *first, int64_t nwin, int64_t *z,
+                                                      uint32_t *vs) {
+    // keys: counting path, the values with the sign bit flipped (unsigned
+    // order); sorting path, the bitonic keys, then the slots
+    __shared__ unsigned long long keys[CO_WIN];
+    uint32_t *kv = (uint32_t *)keys;
+    __shared__ uint16_t segid[CO_WIN];  // first the segment-start flags
+    __shared__ uint16_t segstart[CO_WIN + 2];
+    __shared__ uint32_t wsum[CO_BLOCK / CO_WAVE];
+    __shared__ uint32_t maxlen;
+
+    const int t = threadIdx.x, lane = t % CO_WAVE, wv = t / CO_WAVE;
+    const CoWindow W = co_window(colptr, ncols, nnz, first, nwin, blockIdx.x);
+    const int cnt = W.cnt;
+    const int64_t a = W.a;
+
+    // values (clamped loads past the end, never stored) and cleared flags
+    int32_t x[CO_PER];
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) x[m] = v[a + min(t + m * CO_BLOCK, cnt - 1)];
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) {
+        kv[t + m * CO_BLOCK] = (uint32_t)x[m] ^ 0x80000000u;
+        segid[t + m * CO_BLOCK] = 0;
+    }
+    if (t == 0) maxlen = 0;
+    __syncthreads();
+    // segment starts: every column that begins strictly inside the window
+    const int64_t cend = W.cl >= 0 ? W.cl : ncols - 1;
+    for (int64_t c = W.c0 + 1 + t; c <= cend; c += CO_BLOCK) {
+        const int64_t p = colptr[c] - a;
+        if (p > 0 && p < cnt) segid[p] = 1;
+    }
+    __syncthreads();
+    // segment of every position: inclusive count of the starts up to it
+    // (thread t scans positions CO_PER*t .. CO_PER*t + CO_PER-1)
+    uint32_t f[CO_PER], own = 0;
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) {
+        f[m] = segid[CO_PER * t + m];
+        own += f[m];
+    }
+    uint32_t incl = own;
+#pragma unroll
+    for (int d = 1; d < CO_WAVE; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, CO_WAVE);
+        if (lane >= d) incl += y;
+    }
+    if (lane == CO_WAVE - 1) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t run = incl - own, total = 0;
+#pragma unroll
+    for (int i = 0; i < CO_BLOCK / CO_WAVE; i++) {
+        if (i < wv) run += wsum[i];
+        total += wsum[i];
+    }
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) {
+        const int p = CO_PER * t + m;
+        run += f[m];
+        segid[p] = (uint16_t)run;
+        if (f[m]) segstart[run] = (uint16_t)p;
+    }
+    const int nseg = (int)total + 1;
+    if (t == 0) {
+        segstart[0] = 0;
+        segstart[nseg] = (uint16_t)cnt;
+    }
+    __syncthreads();
+    for (int s = t; s < nseg; s += CO_BLOCK) atomicMax(&maxlen, (uint32_t)(segstart[s + 1] - segstart[s]));
+    __syncthreads();
+
+    // the first segment leaves the window on the left if its column began
+    // earlier, the last on the right if the next window's first column
+    // began in this one
+    const bool spans_l = W.cs0 < a;
+    const bool spans_r = W.cl >= 0 && colptr[W.cl] < a + cnt;
+    auto base_of = [&](int s) -> int64_t { return s == 0 ? W.cs0 : a + segstart[s]; };
+    auto spans = [&](int s) -> bool { return (s == 0 && spans_l) || (s == nseg - 1 && spans_r); };
+
+    if (maxlen <= CO_COUNT_MAX) {
+        // rank = entries of the segment with a smaller value or an equal
+        // value earlier; lanes of a wave mostly share a segment, so LDS
+        // broadcasts the compared values
+#pragma unroll 1
+        for (int m = 0; m < CO_PER; m++) {
+            const int p = t + m * CO_BLOCK;
+            if (p >= cnt) break;
+            const uint32_t xv = kv[p];
+            const int s = segid[p], st = segstart[s], en = segstart[s + 1];
+            uint32_t r = 0;
+            for (int q = st; q < en; q++) {
+                const uint32_t u = kv[q];
+                r += (uint32_t)(u < xv) | ((uint32_t)(u == xv) & (uint32_t)(q < p));
+            }
+            z[a + p] = base_of(s) + r;
+            if (spans(s)) vs[a + st + r] = xv;
+        }
+        return;
+    }
+
+    // bitonic sort of (segment, value, position), built from the values in
+    // registers since the keys overwrite them in LDS; pads sort last
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) {
+        const int p = t + m * CO_BLOCK;
+        const unsigned long long u = (uint32_t)x[m] ^ 0x80000000u;
+        keys[p] = p < cnt ? ((unsigned long long)segid[p] << 44) | (u << 12) | (unsigned)p : ~0ull;
+    }
+    __syncthreads();
+    // a wave's pairs at distance j <= 64 lie in its own 128-key blocks: only
+    // longer distances need the work-group barrier; within a wave LDS
+    // accesses stay in order
+    for (int kk = 2; kk <= CO_WIN; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 2 * CO_WAVE) __syncthreads();
+#pragma unroll 4
+            for (int i = t; i < CO_WIN / 2; i += CO_BLOCK) {
+                const int lo = 2 * i - (i & (j - 1)), hi = lo + j;
+                const unsigned long long k0 = keys[lo], k1 = keys[hi];
+                if ((k0 > k1) == ((lo & kk) == 0)) {
+                    keys[lo] = k1;
+                    keys[hi] = k0;
+                }
+            }
+            if (j >= 2 * CO_WAVE) __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    unsigned long long ky[CO_PER];
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) ky[m] = keys[t + m * CO_BLOCK];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) {
+        const int y = t + m * CO_BLOCK;  // sorted position
+        if (y < cnt) {
+            const int s = (int)(ky[m] >> 44), idx = (int)(ky[m] & 0xFFFu);
+            keys[idx] = (unsigned long long)(base_of(s) + (y - segstart[s]));
+            if (spans(s)) vs[a + y] = (uint32_t)(ky[m] >> 12);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CO_PER; m++) {
+        const int p = t + m * CO_BLOCK;
+        if (p < cnt) z[a + p] = (int64_t)keys[p];
+    }
+}
+
+// entries of column [cs, ce) in window w' come first when their value is
+// smaller, or equal and w' < w
+static __device__ int64_t co_before(const uint32_t *vs, int64_t cs, int64_t ce, int64_t w, uint32_t xv) {
+    int64_t add = 0;
+    const int64_t w0 = cs / CO_WIN, w1 = (ce - 1) / CO_WIN;
+    for (int64_t u = w0; u <= w1; u++) {
+        if (u == w) continue;
+        int64_t lo = max(cs, u * CO_WIN), hi = min(ce, (u + 1) * CO_WIN);
+        const int64_t r0 = lo;
+        if (u < w) {
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (vs[mid] <= xv) lo = mid + 1;
+                else hi = mid;
+            }
+        } else {
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (vs[mid] < xv) lo = mid + 1;
+                else hi = mid;
+            }
+        }
+        add += lo - r0;
+    }
+    return add;
+}
+
+__global__ void __launch_bounds__(CO_BLOCK) k_co_merge(const int64_t *colptr, int64_t ncols, const int32_t *v,
+                                                      int64_t nnz, const int64_t *first, int64_t nwin, int64_t *z,
+                                                      const uint32_t *vs) {
+    const int64_t w = blockIdx.x;
+    const CoWindow W = co_window(colptr, ncols, nnz, first, nwin, w);
+    const int64_t a = W.a, b = a + W.cnt;
+    // the window's first column, and the column running into the next window
+    const int64_t ce0 = clampi(colptr[W.c0 + 1], W.cs0, nnz);
+    const bool l = W.cs0 < a || ce0 > b;
+    const bool r = W.cl >= 0 && W.cl != W.c0 && colptr[W.cl] < b;
+    if (!l && !r) return;
+    for (int side = 0; side < 2; side++) {
+        if (side == 0 ? !l : !r) continue;
+        const int64_t c = side == 0 ? W.c0 : W.cl;
+        const int64_t cs = side == 0 ? W.cs0 : clampi(colptr[c], a, b);
+        const int64_t ce = side == 0 ? ce0 : clampi(colptr[c + 1], b, nnz);
+        const int64_t ps = max(cs, a), pe = min(ce, b);
+        for (int64_t p = ps + threadIdx.x; p < pe; p += CO_BLOCK) {
+            const uint32_t xv = (uint32_t)v[p] ^ 0x80000000u;
+            z[p] += co_before(vs, cs, ce, w, xv);
+        }
+    }
+}
+
+extern "C" VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz,
+                                      int64_t *z, void *stream) {
+    if (ncols < 0 || nnz < 0 || (ncols > 0 && !colptr)) return VR_EINVAL;
+    if (nnz == 0) return VR_OK;
+    if (ncols == 0 || !v || !z) return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    const int64_t nwin = (nnz + CO_WIN - 1) / CO_WIN;
+    if (nwin > 0x7FFFFFFF) return VR_E2BIG;
+    const size_t off_vs = ((size_t)nwin * 8 + 255) & ~(size_t)255;
+    char *ws = (char *)cache_get(off_vs + (size_t)nnz * 4, s);
+    if (!ws) return VR_ENOMEM;
+    int64_t *first = (int64_t *)ws;
+    uint32_t *vs = (uint32_t *)(ws + off_vs);
+    const int64_t gb = (ncols + CO_BLOCK - 1) / CO_BLOCK;
+    hipLaunchKernelGGL(k_co_first, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(CO_BLOCK), 0, s, colptr, ncols,
+                       nnz, first);
+    hipLaunchKernelGGL(k_co_local, dim3((unsigned)nwin), dim3(CO_BLOCK), 0, s, colptr, ncols, v, nnz,
+                       (const int64_t *)first, nwin, z, vs);
+    hipLaunchKernelGGL(k_co_merge, dim3((unsigned)nwin), dim3(CO_BLOCK), 0, s, colptr, ncols, v, nnz,
+                       (const int64_t *)first, nwin, z, (const uint32_t *)vs);
+    const hipError_t e = hipGetLastError();
+    cache_put(ws, s);
+    return e == hipSuccess ? VR_OK : VR_EHIP;
+}

@@ -177,3 +177,12 @@ def test_dissimilarity_matrix_request_shape():
     arr[0].dtype = vr.VR_DIST
     out = ctypes.POINTER(vr.VrResult)()
     assert L.vr_build(arr, None, ctypes.byref(out)) == vr.VR_EINVAL
+
+
+def test_column_order_argument_checks():
+    """Argument errors come back before any device work."""
+    L = vr.lib()
+    assert L.vr_column_order(None, -1, None, 0, None, None) == vr.VR_EINVAL
+    assert L.vr_column_order(None, 0, None, -1, None, None) == vr.VR_EINVAL
+    assert L.vr_column_order(None, 3, None, 0, None, None) == vr.VR_EINVAL  # colptr missing
+    assert L.vr_column_order(None, 0, None, 0, None, None) == vr.VR_OK      # nothing to do
