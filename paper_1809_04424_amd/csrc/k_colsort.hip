@@ -62,12 +62,64 @@ static __device__ __forceinline__ CoWindow co_window(const int64_t *colptr, int6
     return W;
 }
 
+// LDS index of key position p: one pad slot per 16 keys, so that the lanes
+// of layout C (16 keys apart) spread over the banks
+static __device__ __forceinline__ int co_phys(int p) { return p + (p >> 4); }
+
+// position of register g of thread t in layout LAY (0: C, 1: S, 2: L)
+template <int LAY>
+static __device__ __forceinline__ int co_pos(int t, int g) {
+    return LAY == 0 ? CO_PER * t + g : (LAY == 1 ? 256 * (t >> 4) + 16 * g + (t & 15) : 256 * g + t);
+}
+
+template <int LAY>
+static __device__ __forceinline__ void co_put(const unsigned long long (&r)[CO_PER], int t, unsigned long long *keys) {
+#pragma unroll
+    for (int g = 0; g < CO_PER; g++) keys[co_phys(co_pos<LAY>(t, g))] = r[g];
+}
+
+// move the keys from layout cur to layout TO through LDS
+template <int TO>
+static __device__ __forceinline__ void co_to(unsigned long long (&r)[CO_PER], int &cur, int t,
+                                             unsigned long long *keys) {
+    if (cur == TO) return;  // uniform over the work-group
+    __syncthreads();        // earlier reads of the buffer are done
+    if (cur == 0) co_put<0>(r, t, keys);
+    else if (cur == 1) co_put<1>(r, t, keys);
+    else co_put<2>(r, t, keys);
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < CO_PER; g++) r[g] = keys[co_phys(co_pos<TO>(t, g))];
+    cur = TO;
+}
+
+// the stages of one merge width kk on the position bits that layout LAY
+// holds in registers (bits 4*LAY .. 4*LAY+3, at most bhi), highest first
+template <int LAY>
+static __device__ __forceinline__ void co_stages(unsigned long long (&r)[CO_PER], int t, int kk, int bhi) {
+#pragma unroll
+    for (int gb = 3; gb >= 0; gb--) {
+        if (4 * LAY + gb > bhi) continue;
+        const int j = 1 << gb;
+#pragma unroll
+        for (int g = 0; g < CO_PER; g++) {
+            if (g & j) continue;
+            const int h = g | j;
+            const bool up = (co_pos<LAY>(t, g) & kk) == 0;
+            const unsigned long long k0 = r[g], k1 = r[h];
+            const bool sw = (k0 > k1) == up;
+            r[g] = sw ? k1 : k0;
+            r[h] = sw ? k0 : k1;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(CO_BLOCK) k_co_local(const int64_t *colptr, int64_t ncols, const int32_t *v,
                                                       int64_t nnz, const int64_t *first, int64_t nwin, int64_t *z,
                                                       uint32_t *vs) {
     // keys: counting path, the values with the sign bit flipped (unsigned
-    // order); sorting path, the bitonic keys, then the slots
-    __shared__ unsigned long long keys[CO_WIN];
+    // order); sorting path, the keys between layouts, then the slots
+    __shared__ unsigned long long keys[CO_WIN + CO_WIN / 16];
     uint32_t *kv = (uint32_t *)keys;
     __shared__ uint16_t segid[CO_WIN];  // first the segment-start flags
     __shared__ uint16_t segstart[CO_WIN + 2];
@@ -164,87 +216,60 @@ __global__ void __launch_bounds__(CO_BLOCK) k_co_local(const int64_t *colptr, in
         return;
     }
 
-    // bitonic sort of (segment, value, position), built from the values in
-    // registers since the keys overwrite them in LDS; pads sort last
+    // Bitonic sort of the keys (segment, value, position); pads sort last.
+    // Every compare-exchange happens in registers: a thread holds 16 keys in
+    // one of three layouts, each owning four bits of the position (C: bits
+    // 0-3, position 16t + g; S: bits 4-7, 256(t/16) + 16g + t%16; L: bits
+    // 8-11, 256g + t), and the keys move between layouts through LDS.  The
+    // keys start in layout L, which is how the values were loaded.
+    unsigned long long r[CO_PER];
 #pragma unroll
-    for (int m = 0; m < CO_PER; m++) {
-        const int p = t + m * CO_BLOCK;
-        const unsigned long long u = (uint32_t)x[m] ^ 0x80000000u;
-        keys[p] = p < cnt ? ((unsigned long long)segid[p] << 44) | (u << 12) | (unsigned)p : ~0ull;
+    for (int g = 0; g < CO_PER; g++) {
+        const int p = t + g * CO_BLOCK;
+        const unsigned long long u = (uint32_t)x[g] ^ 0x80000000u;
+        r[g] = p < cnt ? ((unsigned long long)segid[p] << 44) | (u << 12) | (unsigned)p : ~0ull;
     }
-    __syncthreads();
-    // a wave's pairs at distance j <= 64 lie in its own 128-key blocks: only
-    // longer distances need the work-group barrier; within a wave LDS
-    // accesses stay in order
-    for (int kk = 2; kk <= CO_WIN; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= 2 * CO_WAVE) __syncthreads();
-#pragma unroll 4
-            for (int i = t; i < CO_WIN / 2; i += CO_BLOCK) {
-                const int lo = 2 * i - (i & (j - 1)), hi = lo + j;
-                const unsigned long long k0 = keys[lo], k1 = keys[hi];
-                if ((k0 > k1) == ((lo & kk) == 0)) {
-                    keys[lo] = k1;
-                    keys[hi] = k0;
-                }
-            }
-            if (j >= 2 * CO_WAVE) __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+    int cur = 2;
+    for (int lk = 1; lk <= 12; lk++) {  // merge width 2^lk: stages on bits lk-1 .. 0
+        const int kk = 1 << lk;
+        if (lk - 1 >= 8) {
+            co_to<2>(r, cur, t, keys);
+            co_stages<2>(r, t, kk, lk - 1);
         }
+        if (lk - 1 >= 4) {
+            co_to<1>(r, cur, t, keys);
+            co_stages<1>(r, t, kk, lk - 1);
+        }
+        co_to<0>(r, cur, t, keys);
+        co_stages<0>(r, t, kk, lk - 1);
     }
-    __syncthreads();
-    unsigned long long ky[CO_PER];
+    __syncthreads();  // every thread's last layout read is done
 #pragma unroll
-    for (int m = 0; m < CO_PER; m++) ky[m] = keys[t + m * CO_BLOCK];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < CO_PER; m++) {
-        const int y = t + m * CO_BLOCK;  // sorted position
+    for (int g = 0; g < CO_PER; g++) {
+        const int y = CO_PER * t + g;  // sorted position
         if (y < cnt) {
-            const int s = (int)(ky[m] >> 44), idx = (int)(ky[m] & 0xFFFu);
-            keys[idx] = (unsigned long long)(base_of(s) + (y - segstart[s]));
-            if (spans(s)) vs[a + y] = (uint32_t)(ky[m] >> 12);
+            const int s = (int)(r[g] >> 44), idx = (int)(r[g] & 0xFFFu);
+            keys[co_phys(idx)] = (unsigned long long)(base_of(s) + (y - segstart[s]));
+            if (spans(s)) vs[a + y] = (uint32_t)(r[g] >> 12);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < CO_PER; m++) {
         const int p = t + m * CO_BLOCK;
-        if (p < cnt) z[a + p] = (int64_t)keys[p];
+        if (p < cnt) z[a + p] = (int64_t)keys[co_phys(p)];
     }
 }
 
-// entries of column [cs, ce) in window w' come first when their value is
-// smaller, or equal and w' < w
-static __device__ int64_t co_before(const uint32_t *vs, int64_t cs, int64_t ce, int64_t w, uint32_t xv) {
-    int64_t add = 0;
-    const int64_t w0 = cs / CO_WIN, w1 = (ce - 1) / CO_WIN;
-    for (int64_t u = w0; u <= w1; u++) {
-        if (u == w) continue;
-        int64_t lo = max(cs, u * CO_WIN), hi = min(ce, (u + 1) * CO_WIN);
-        const int64_t r0 = lo;
-        if (u < w) {
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (vs[mid] <= xv) lo = mid + 1;
-                else hi = mid;
-            }
-        } else {
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (vs[mid] < xv) lo = mid + 1;
-                else hi = mid;
-            }
-        }
-        add += lo - r0;
-    }
-    return add;
-}
-
+// Per window, for the (at most two) columns that leave it: every other
+// window u the column meets holds a sorted run of the column's values; its
+// entries come first when their value is smaller, or equal and u < w.  The
+// run is staged in LDS, then each entry of this window binary-searches it.
 __global__ void __launch_bounds__(CO_BLOCK) k_co_merge(const int64_t *colptr, int64_t ncols, const int32_t *v,
                                                       int64_t nnz, const int64_t *first, int64_t nwin, int64_t *z,
                                                       const uint32_t *vs) {
+    __shared__ uint32_t run[CO_WIN];
+    const int t = threadIdx.x;
     const int64_t w = blockIdx.x;
     const CoWindow W = co_window(colptr, ncols, nnz, first, nwin, w);
     const int64_t a = W.a, b = a + W.cnt;
@@ -254,15 +279,56 @@ __global__ void __launch_bounds__(CO_BLOCK) k_co_merge(const int64_t *colptr, in
     const bool r = W.cl >= 0 && W.cl != W.c0 && colptr[W.cl] < b;
     if (!l && !r) return;
     for (int side = 0; side < 2; side++) {
-        if (side == 0 ? !l : !r) continue;
+        if (side == 0 ? !l : !r) continue;  // uniform over the work-group
         const int64_t c = side == 0 ? W.c0 : W.cl;
         const int64_t cs = side == 0 ? W.cs0 : clampi(colptr[c], a, b);
         const int64_t ce = side == 0 ? ce0 : clampi(colptr[c + 1], b, nnz);
         const int64_t ps = max(cs, a), pe = min(ce, b);
-        for (int64_t p = ps + threadIdx.x; p < pe; p += CO_BLOCK) {
-            const uint32_t xv = (uint32_t)v[p] ^ 0x80000000u;
-            z[p] += co_before(vs, cs, ce, w, xv);
+        if (pe <= ps) continue;  // only for a colptr that breaks the rules
+        uint32_t xv[CO_PER];
+        int64_t add[CO_PER];
+#pragma unroll
+        for (int m = 0; m < CO_PER; m++) {
+            const int64_t p = ps + t + m * CO_BLOCK;
+            xv[m] = (uint32_t)v[min(p, pe - 1)] ^ 0x80000000u;
+            add[m] = 0;
         }
+        const int nm = (int)((pe - ps + CO_BLOCK - 1) / CO_BLOCK);  // entries per thread, at most
+        const int64_t w0 = cs / CO_WIN, w1 = (ce - 1) / CO_WIN;
+        for (int64_t u = w0; u <= w1; u++) {
+            if (u == w) continue;
+            const int64_t rs = max(cs, u * CO_WIN);
+            const int len = (int)(min(ce, (u + 1) * CO_WIN) - rs);
+            if (len <= 0) continue;  // only for a colptr that breaks the rules
+            __syncthreads();
+            for (int i = t; i < len; i += CO_BLOCK) run[i] = vs[rs + i];
+            __syncthreads();
+            const bool before = u < w;
+            // branchless search, steps outermost so that the entries' LDS
+            // reads of one step are in flight together: pos = the run's
+            // entries that come first (a prefix, since the run is sorted)
+            int pos[CO_PER];
+#pragma unroll
+            for (int m = 0; m < CO_PER; m++) pos[m] = 0;
+            for (int step = CO_WIN; step > 0; step >>= 1) {
+#pragma unroll
+                for (int m = 0; m < CO_PER; m++) {
+                    if (m >= nm) break;
+                    const int at = pos[m] + step;
+                    const uint32_t y = run[min(at, len) - 1];
+                    const bool first_ = y < xv[m] || (before && y == xv[m]);
+                    pos[m] += (at <= len && first_) ? step : 0;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < CO_PER; m++) add[m] += pos[m];
+        }
+#pragma unroll
+        for (int m = 0; m < CO_PER; m++) {
+            const int64_t p = ps + t + m * CO_BLOCK;
+            if (p < pe) z[p] += add[m];
+        }
+        __syncthreads();  // the next side reuses the run buffer
     }
 }
 
