@@ -307,7 +307,7 @@ def _schedule(vr, args, pts, thr):
     return vr.autotune(pts, thr) if not args.no_tune else None
 
 
-def _hamming(vr, torch, tune=True, steps=5, warmup=2):
+def _hamming(vr, torch, tune=True, steps=5, warmup=2, sched=None):
     """Dissimilarity-matrix input: pairwise Hamming distances of 1088 synthetic
     binary sequences (the shape of the paper's sequence example), every pair
     kept: C(1088, 3) = 214 million triangles per build."""
@@ -315,7 +315,11 @@ def _hamming(vr, torch, tune=True, steps=5, warmup=2):
 
     M = torch.from_numpy(workloads.hamming_matrix(1088, 1088)).to("cuda:0")
     thr = ("full", 0, 1)
-    sch = vr.autotune(M, thr, matrix=True) if tune else None
+    if sched:
+        vr.set_schedule(M, thr, sched, matrix=True)
+        sch = sched
+    else:
+        sch = vr.autotune(M, thr, matrix=True) if tune else None
     el, cnt, tw = _time_builds(vr, torch, M, thr, steps, warmup, build=vr.build_matrix)
     a = _alg_bytes(cnt[0], cnt[1], cnt[2], cnt[0] ** 2)
     del M
@@ -397,6 +401,13 @@ def main():
         _copy_calibration(torch)
     if args.workload == "batched512":
         _main_batched(vr, torch, args)
+        return
+    if args.workload == "hamming1088":  # the matrix-input workload alone (profiling)
+        print(json.dumps({"workload": "hamming1088_full_matrix",
+                          **_hamming(vr, torch, tune=not args.no_tune, steps=args.steps, warmup=args.warmup,
+                                     sched=tuple(int(x) for x in args.schedule.split(",")) if args.schedule
+                                     else None)}),
+              flush=True)
         return
     if args.workload == "colorder2000":  # the per-column order alone (profiling)
         print(json.dumps({"workload": "column_order_2000x1999", **_column_order(vr, torch, reps=args.steps)}),
