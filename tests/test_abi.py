@@ -186,3 +186,14 @@ def test_column_order_argument_checks():
     assert L.vr_column_order(None, 0, None, -1, None, None) == vr.VR_EINVAL
     assert L.vr_column_order(None, 3, None, 0, None, None) == vr.VR_EINVAL  # colptr missing
     assert L.vr_column_order(None, 0, None, 0, None, None) == vr.VR_OK      # nothing to do
+
+
+def test_matrix_batches_hold_one_matrix():
+    """A dissimilarity matrix takes all 32 bits of the sort key, so a batch
+    holds one matrix of two or more points (VR_E2BIG otherwise)."""
+    L = vr.lib()
+    arr = (vr.VrRequest * 2)(_req(n=50, d=50, dtype=vr.VR_DIST), _req(n=50, d=50, dtype=vr.VR_DIST))
+    assert L.vr_batch_workspace_bytes(arr, 2) == vr.VR_E2BIG
+    assert L.vr_batch_workspace_bytes(arr, 1) > 0
+    arr2 = (vr.VrRequest * 2)(_req(n=50, d=50, dtype=vr.VR_DIST), _req(n=1, d=50, dtype=vr.VR_DIST))
+    assert L.vr_batch_workspace_bytes(arr2, 2) == -1  # a one-point request must say d = 1
