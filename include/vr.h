@@ -252,7 +252,7 @@ VR_API int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t 
  *         its column is sorted stably by value.
  * Enqueued on `stream`; scratch of 4 bytes per entry comes from the
  * library's cache.  VR_EINVAL for negative sizes, a null pointer, or
- * entries without columns; nnz = 0 does nothing.  A colptr that breaks the
+ * entries without columns; VR_E2BIG for nnz >= 2^43; nnz = 0 does nothing.  A colptr that breaks the
  * rules above gives unspecified z but no access outside the arrays. */
 VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz, int64_t *z,
                            void *stream);
