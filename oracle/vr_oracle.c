@@ -424,8 +424,10 @@ void or_reduce_cohomology(int64_t n, int64_t K, const int64_t *ei, const int64_t
     }
 
     /* dimension 1: columns = edges K-1..0 (cleared when already paired with a
-       vertex), rows = triangles in reversed order (row of triangle t is T-1-t). */
-    {
+       vertex), rows = triangles in reversed order (row of triangle t is T-1-t).
+       A filtration without triangles (built up to dimension 1) has empty
+       coboundaries here: nothing to reduce. */
+    if (T > 0) {
         int64_t *R = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n * n > 0 ? n * n : 1));
         for (int64_t x = 0; x < n * n; x++) R[x] = -1;
         for (int64_t r = 0; r < K; r++) { R[ei[r] * n + ej[r]] = r; R[ej[r] * n + ei[r]] = r; }

@@ -420,3 +420,15 @@ def test_column_order_special_cases(orc):
         orc.column_order_original([0, 2], [1, 5], maxvalue=4)
     with pytest.raises(ValueError):
         orc.column_order([0, 3], [1, 2])
+
+
+def test_reductions_without_triangles(orc):
+    """Up to dimension 1 the complex is a graph: both reductions pair the
+    spanning-forest edges with vertices and leave every other edge unpaired."""
+    c = workloads.noisy_circle(seed=30, n=150)
+    f1 = orc.build(c.points, c.thr, maxdim=1)
+    f2 = orc.build(c.points, c.thr)
+    for m in ("homology", "cohomology"):
+        p1, p2 = orc.reduce(f1, m), orc.reduce(f2, m)
+        assert np.array_equal(p1.e_low, p2.e_low)
+        assert len(p1.t_low) == 0
