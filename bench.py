@@ -359,6 +359,34 @@ def _column_order(vr, torch, reps=20):
             "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def _pairs_dim0(vr, torch, reps=20):
+    """Dimension-0 persistence pairs of the circle1000 build: a (min, max)
+    closure of the padded n x n rank matrix (2 * ld^3 integer min/max
+    operations, ld = 64 * ceil(n / 64)), timed with HIP events on the current
+    stream around each call.  The ALU peak counts one 32-bit integer
+    operation per lane per cycle: 256 CUs x 64 lanes x 2.4 GHz."""
+    c = _workload("circle1000")
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    r = vr.build(pts, c.thr)
+    for _ in range(2):
+        vr.pairs_dim0(r)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        vr.pairs_dim0(r)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
+    n, K, _ = r.counts
+    r.free()
+    ld = 64 * ((n + 63) // 64)
+    ops = 2 * ld ** 3
+    peak = 256 * 64 * 2.4e9
+    return {"ms_per_call": round(ms, 5), "n": n, "K": K, "minmax_ops": ops,
+            "alu_frac": round(ops / (ms * 1e-3) / peak, 4)}
+
+
 def _alg_bytes(n, K, T, n2):
     """Algorithmic bytes of the triangle writer: triangle keys out (8 T), kept
     ranks in (8 K), the adjacency once (n^2/8 over the clouds), and the fused
@@ -409,6 +437,10 @@ def main():
                                      else None)}),
               flush=True)
         return
+    if args.workload == "pairs0":  # dimension-0 pairs of circle1000 alone (profiling)
+        print(json.dumps({"workload": "pairs_dim0_circle1000", **_pairs_dim0(vr, torch, reps=args.steps)}),
+              flush=True)
+        return
     if args.workload == "colorder2000":  # the per-column order alone (profiling)
         print(json.dumps({"workload": "column_order_2000x1999", **_column_order(vr, torch, reps=args.steps)}),
               flush=True)
@@ -453,6 +485,7 @@ def main():
     if not args.no_extra and args.workload == "circle1000":
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
         extra["column_order_2000x1999"] = _column_order(vr, torch)
+        extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
 
     if not args.no_batch and args.workload == "circle1000":
         extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)

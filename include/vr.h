@@ -257,6 +257,21 @@ VR_API int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t 
 VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz, int64_t *z,
                            void *stream);
 
+/* Persistence pairs in dimension 0 of a build's filtration (Section 2.2.1:
+ * Alg. 1 on the edge columns of the boundary matrix; vertices share one
+ * value and are ordered by index).  Edge r is paired with the vertex that
+ * is the smallest of its component just before r joins that component to
+ * one holding a smaller vertex; every other edge is unpaired (it creates a
+ * cycle).
+ * res:    a single build's result (edges on the device, rank order).
+ * e_low:  device, K int32, caller-owned: the vertex paired with edge r, or -1.
+ * death:  device, n int32, caller-owned: the edge rank that pairs vertex v,
+ *         or -1 for the smallest vertex of each final component (an
+ *         infinite bar).
+ * Enqueued on `stream`; scratch of 4 (64 ceil(n / 64))^2 bytes comes from
+ * the library's cache.  VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
+VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, void *stream);
+
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from
  * the driver once and reused by later builds of any stream (a reuse on

@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -115,6 +115,8 @@ def lib():
         L.vr_column_order.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_void_p]
         L.vr_column_order.restype = ctypes.c_int
+        L.vr_pairs_dim0.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_pairs_dim0.restype = ctypes.c_int
         L.vr_trim.argtypes = []
         L.vr_trim.restype = ctypes.c_int64
         L.vr_status_string.argtypes = [ctypes.c_int]
@@ -560,3 +562,24 @@ def column_order(colptr, v, out=None):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return z
+
+
+def pairs_dim0(result):
+    """Persistence pairs in dimension 0 of a build (Section 2.2.1): returns
+    (e_low, death) as int32 device tensors; e_low[r] = the vertex paired with
+    edge r or -1, death[v] = the edge rank pairing vertex v or -1."""
+    import torch
+
+    L = lib()
+    n, K, T = result.counts
+    dev = result._device
+    e_low = torch.empty(K, dtype=torch.int32, device=dev)
+    death = torch.empty(n, dtype=torch.int32, device=dev)
+    r = VrResult(n, K, T, result._p_ij, result._p_q, result._p_tri)
+    stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = L.vr_pairs_dim0(ctypes.byref(r), ctypes.c_void_p(e_low.data_ptr() if K else 0),
+                             ctypes.c_void_p(death.data_ptr() if n else 0), ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return e_low, death

@@ -1,0 +1,226 @@
+// k_pairs.hip -- persistence pairs in dimension 0 (Section 2.2.1, Alg. 1 on
+// the edge columns of the boundary matrix) on the device.
+//
+// With every vertex at the same value and vertices ordered by index, the
+// column algorithm pairs edge r with vertex v exactly when v is the smallest
+// vertex of its component just before r joins it to a component holding a
+// smaller vertex (the younger component dies).  So vertex v dies at
+//     death(v) = min over u < v of  minimax(v, u),
+// where minimax(v, u) is the least, over the paths from v to u, of the
+// largest edge rank on the path (+inf when no path exists); v with no
+// finite death is the oldest vertex of its component and never dies.
+//
+// minimax over all pairs is the closure of the rank matrix in the (min, max)
+// semiring: a blocked Floyd-Warshall in 64 x 64 tiles.
+//   k_pd_fill     D = +inf off the diagonal, -1 on it
+//   k_pd_edges    D[i][j] = D[j][i] = r per kept edge
+//   k_pd_diag     phase 1: the diagonal tile, pivots in order
+//   k_pd_cross    phase 2: the tiles in the pivot's row and column, each a
+//                 (min, max) product with the closed diagonal tile
+//   k_pd_rest     phase 3: every other tile, the product of a column tile
+//                 and a row tile
+//   k_pd_death    death(v): a wave takes the minimum of row v left of v
+//   k_pd_clear, k_pd_emit   e_low[r] = v for death(v) = r, else -1
+// D is (nb * 64)^2 with the padding vertices isolated, so the tile kernels
+// need no bounds tests.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vr.h"
+#include "vr_cache.h"
+
+#define PD_T 64      // tile edge
+#define PD_BLOCK 256  // 16 x 16 threads, 4 x 4 entries each
+#define PD_INF 0x7FFFFFFF
+
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_fill(int32_t *D, int64_t m) {
+    const int64_t ld = m;
+    for (int64_t x = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < ld * ld; x += (int64_t)gridDim.x * PD_BLOCK)
+        D[x] = (x / ld == x % ld) ? -1 : PD_INF;
+}
+
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_edges(int32_t *D, int64_t ld, const int32_t *ij, int64_t K,
+                                                      int64_t n) {
+    for (int64_t r = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; r < K; r += (int64_t)gridDim.x * PD_BLOCK) {
+        const int64_t i = ij[2 * r], j = ij[2 * r + 1];
+        if (i < 0 || j < 0 || i >= n || j >= n) continue;  // never for a library result
+        D[i * ld + j] = (int32_t)r;
+        D[j * ld + i] = (int32_t)r;
+    }
+}
+
+// In the tile kernels thread (ty, tx) owns rows 4ty..4ty+3 and columns
+// 4tx..4tx+3 of a tile.
+
+// phase 1: D_kk closed over its own 64 pivots, in order.  Each thread keeps
+// its 16 entries in registers; after pivot k the owners of row k+1 and
+// column k+1 publish them to LDS for the next pivot.  Row k and column k do
+// not change at pivot k (D[k][k] = -1), and the entries written after pivot
+// k are not the ones read at pivot k, so one barrier per pivot suffices.
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_diag(int32_t *D, int64_t ld, int64_t kb) {
+    __shared__ __align__(16) int32_t s[PD_T][PD_T + 4];
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    int32_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int4 v = *(const int4 *)(D + (kb * PD_T + 4 * ty + a) * ld + kb * PD_T + 4 * tx);
+        acc[a][0] = v.x;
+        acc[a][1] = v.y;
+        acc[a][2] = v.z;
+        acc[a][3] = v.w;
+        *(int4 *)&s[4 * ty + a][4 * tx] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < PD_T; k++) {
+        int32_t ck[4], rk[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) ck[a] = s[4 * ty + a][k];
+#pragma unroll
+        for (int b = 0; b < 4; b++) rk[b] = s[k][4 * tx + b];
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) acc[a][b] = min(acc[a][b], max(ck[a], rk[b]));
+        const int k1 = k + 1;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+            if (4 * ty + a == k1)
+#pragma unroll
+                for (int b = 0; b < 4; b++) s[k1][4 * tx + b] = acc[a][b];
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if (4 * tx + b == k1)
+#pragma unroll
+                for (int a = 0; a < 4; a++) s[4 * ty + a][k1] = acc[a][b];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+        *(int4 *)(D + (kb * PD_T + 4 * ty + a) * ld + kb * PD_T + 4 * tx) =
+            make_int4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
+}
+
+// out = min(out, A (min,max) B) for 64 x 64 tiles A = (ai, aj), B = (bi, bj),
+// out = (oi, oj); out may be A or B (all reads precede the writes)
+static __device__ __forceinline__ void pd_product(int32_t *D, int64_t ld, int64_t ai, int64_t aj, int64_t bi,
+                                                  int64_t bj, int64_t oi, int64_t oj) {
+    __shared__ __align__(16) int32_t at[PD_T][PD_T + 4];  // A transposed: at[m][i]
+    __shared__ __align__(16) int32_t bt[PD_T][PD_T + 4];  // B: bt[m][j]
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int4 v = *(const int4 *)(D + (ai * PD_T + 4 * ty + a) * ld + aj * PD_T + 4 * tx);
+        at[4 * tx + 0][4 * ty + a] = v.x;
+        at[4 * tx + 1][4 * ty + a] = v.y;
+        at[4 * tx + 2][4 * ty + a] = v.z;
+        at[4 * tx + 3][4 * ty + a] = v.w;
+        *(int4 *)&bt[4 * ty + a][4 * tx] = *(const int4 *)(D + (bi * PD_T + 4 * ty + a) * ld + bj * PD_T + 4 * tx);
+    }
+    int32_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int4 v = *(const int4 *)(D + (oi * PD_T + 4 * ty + a) * ld + oj * PD_T + 4 * tx);
+        acc[a][0] = v.x;
+        acc[a][1] = v.y;
+        acc[a][2] = v.z;
+        acc[a][3] = v.w;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int m = 0; m < PD_T; m++) {
+        const int4 c = *(const int4 *)&at[m][4 * ty];
+        const int4 r = *(const int4 *)&bt[m][4 * tx];
+        const int32_t cv[4] = {c.x, c.y, c.z, c.w}, rv[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) acc[a][b] = min(acc[a][b], max(cv[a], rv[b]));
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+        *(int4 *)(D + (oi * PD_T + 4 * ty + a) * ld + oj * PD_T + 4 * tx) =
+            make_int4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
+}
+
+// phase 2: with D_kk closed, the tiles of the pivot's row and column need
+// one product each: row tile (kb, o) = D_kk (min,max) itself, column tile
+// (o, kb) = itself (min,max) D_kk.  Work-group g < nb: row tile (kb, g);
+// nb <= g < 2 nb: column tile (g - nb, kb).
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_cross(int32_t *D, int64_t ld, int64_t kb, int64_t nb) {
+    const int64_t g = blockIdx.x;
+    const bool row = g < nb;
+    const int64_t o = row ? g : g - nb;
+    if (o == kb) return;
+    if (row) pd_product(D, ld, kb, kb, kb, o, kb, o);
+    else pd_product(D, ld, o, kb, kb, kb, o, kb);
+}
+
+// phase 3: tile (bi, bj) off the pivot's row and column takes the product
+// of column tile (bi, kb) and row tile (kb, bj)
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_rest(int32_t *D, int64_t ld, int64_t kb, int64_t nb) {
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bi == kb || bj == kb) return;
+    pd_product(D, ld, bi, kb, kb, bj, bi, bj);
+}
+
+// death(v) = min over u < v of D[v][u]; -1 when none is finite
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_death(const int32_t *D, int64_t ld, int64_t n, int32_t *death) {
+    const int lane = threadIdx.x & 63;
+    const int64_t v = blockIdx.x * (int64_t)(PD_BLOCK / 64) + (threadIdx.x >> 6);
+    if (v >= n) return;
+    int32_t m = PD_INF;
+    for (int64_t u = lane; u < v; u += 64) m = min(m, D[v * ld + u]);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = min(m, __shfl_xor(m, d, 64));
+    if (lane == 0) death[v] = m == PD_INF ? -1 : m;
+}
+
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_clear(int32_t *e_low, int64_t K) {
+    for (int64_t r = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; r < K; r += (int64_t)gridDim.x * PD_BLOCK)
+        e_low[r] = -1;
+}
+
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_emit(const int32_t *death, int64_t n, int32_t *e_low, int64_t K) {
+    const int64_t v = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x;
+    if (v >= n) return;
+    const int32_t r = death[v];
+    if (r >= 0 && r < K) e_low[r] = (int32_t)v;
+}
+
+static unsigned grid_for(int64_t items) {
+    const int64_t g = (items + PD_BLOCK - 1) / PD_BLOCK;
+    return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+extern "C" VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, void *stream) {
+    if (!res) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges;
+    if (n < 0 || K < 0 || n > VR_MAX_POINTS) return VR_EINVAL;
+    if ((K > 0 && (!e_low || !res->edge_ij)) || (n > 0 && !death)) return VR_EINVAL;
+    if (n == 0) return VR_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = (n + PD_T - 1) / PD_T, ld = nb * PD_T;
+    int32_t *D = (int32_t *)cache_get((size_t)ld * (size_t)ld * 4, s);
+    if (!D) return VR_ENOMEM;
+    hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(ld * ld)), dim3(PD_BLOCK), 0, s, D, ld);
+    if (K > 0)
+        hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, D, ld,
+                           (const int32_t *)res->edge_ij, K, n);
+    if (K > 0)
+        for (int64_t kb = 0; kb < nb; kb++) {
+            hipLaunchKernelGGL(k_pd_diag, dim3(1), dim3(PD_BLOCK), 0, s, D, ld, kb);
+            if (nb > 1) {
+                hipLaunchKernelGGL(k_pd_cross, dim3((unsigned)(2 * nb)), dim3(PD_BLOCK), 0, s, D, ld, kb, nb);
+                hipLaunchKernelGGL(k_pd_rest, dim3((unsigned)nb, (unsigned)nb), dim3(PD_BLOCK), 0, s, D, ld, kb, nb);
+            }
+        }
+    hipLaunchKernelGGL(k_pd_death, dim3((unsigned)((n + PD_BLOCK / 64 - 1) / (PD_BLOCK / 64))), dim3(PD_BLOCK), 0, s,
+                       (const int32_t *)D, ld, n, death);
+    if (K > 0) {
+        hipLaunchKernelGGL(k_pd_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, e_low, K);
+        hipLaunchKernelGGL(k_pd_emit, dim3(grid_for(n)), dim3(PD_BLOCK), 0, s, (const int32_t *)death, n, e_low, K);
+    }
+    const hipError_t e = hipGetLastError();
+    cache_put(D, s);
+    return e == hipSuccess ? VR_OK : VR_EHIP;
+}

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "vr.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(vr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(vr_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_binding_symbols():
@@ -197,3 +197,14 @@ def test_matrix_batches_hold_one_matrix():
     assert L.vr_batch_workspace_bytes(arr, 1) > 0
     arr2 = (vr.VrRequest * 2)(_req(n=50, d=50, dtype=vr.VR_DIST), _req(n=1, d=50, dtype=vr.VR_DIST))
     assert L.vr_batch_workspace_bytes(arr2, 2) == -1  # a one-point request must say d = 1
+
+
+def test_pairs_dim0_argument_checks():
+    L = vr.lib()
+    assert L.vr_pairs_dim0(None, None, None, None) == vr.VR_EINVAL
+    r = vr.VrResult(0, 0, 0, None, None, None)
+    assert L.vr_pairs_dim0(ctypes.byref(r), None, None, None) == vr.VR_OK  # empty: nothing to do
+    r = vr.VrResult(10, 5, 0, None, None, None)
+    assert L.vr_pairs_dim0(ctypes.byref(r), None, None, None) == vr.VR_EINVAL  # edges but no arrays
+    r = vr.VrResult(9000, 0, 0, None, None, None)
+    assert L.vr_pairs_dim0(ctypes.byref(r), None, None, None) == vr.VR_EINVAL

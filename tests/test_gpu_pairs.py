@@ -1,0 +1,78 @@
+"""Dimension-0 persistence pairs on the device (vr_pairs_dim0) against the
+oracle's column reductions, bit-exact."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1809_04424_amd as vr
+
+    vr.lib()
+    yield
+
+
+def _gpu_pairs(points, thr):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    r = vr.build(torch.from_numpy(np.ascontiguousarray(points)).to("cuda:0"), thr)
+    e_low, death = vr.pairs_dim0(r)
+    torch.cuda.synchronize()
+    out = e_low.cpu().numpy().astype(np.int64), death.cpu().numpy().astype(np.int64), r.counts
+    r.free()
+    return out
+
+
+def _check(orc, points, thr, label):
+    print(f"[gpu] pairs_dim0 {label} n={len(points)} thr={thr}", flush=True)
+    f = orc.build(points, thr, maxdim=1)  # dimension 0 needs no triangles
+    ref = orc.reduce(f, "cohomology").e_low
+    e_low, death, counts = _gpu_pairs(points, thr)
+    assert counts[0] == f.n and counts[1] == f.K
+    assert np.array_equal(e_low, ref)
+    # death is the inverse of e_low; the unpaired vertices are one per component
+    want = np.full(f.n, -1, np.int64)
+    for r in np.nonzero(ref >= 0)[0]:
+        want[ref[r]] = r
+    assert np.array_equal(death, want)
+    assert death[0] == -1 if f.n else True
+
+
+CASES = [
+    ("circle150_p10", lambda: workloads.noisy_circle(seed=40, n=150).points, ("fraction", 10, 100)),
+    ("circle300_sparse", lambda: workloads.noisy_circle(seed=41, n=300).points, ("count", 250, 1)),
+    ("circle1000_p20", lambda: workloads.noisy_circle().points, ("fraction", 20, 100)),
+    ("lattice_ties", lambda: workloads.lattice_cloud(3, 90, side=3).points, ("fraction", 30, 100)),
+    ("mixture_d16", lambda: workloads.uniform_cloud(42, 260, 16).points, ("fraction", 5, 100)),
+    ("plain64_full", lambda: workloads.plain64().points, ("full", 0, 1)),
+    ("n65", lambda: workloads.uniform_cloud(43, 65, 3).points, ("fraction", 50, 100)),
+    ("n128_sqdist", lambda: workloads.uniform_cloud(44, 128, 2).points, ("sqdist", 900, 0)),
+    ("n2000", lambda: workloads.noisy_circle(seed=45, n=2000).points, ("fraction", 2, 100)),
+]
+
+
+@pytest.mark.parametrize("name,gen,thr", CASES, ids=[c[0] for c in CASES])
+def test_pairs_dim0(orc, name, gen, thr):
+    _check(orc, gen(), thr, name)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_pairs_dim0_tiny(orc, n):
+    pts = np.array([[0, 0], [3, 0], [0, 4]][:n], np.int32)
+    _check(orc, pts, ("full", 0, 1), f"tiny{n}")
+
+
+def test_pairs_dim0_no_edges(orc):
+    pts = workloads.uniform_cloud(46, 50, 3).points
+    e_low, death, counts = _gpu_pairs(pts, ("count", 0, 1))
+    assert counts[1] == 0 and len(e_low) == 0 and np.all(death == -1)
