@@ -52,52 +52,48 @@ __global__ void __launch_bounds__(PD_BLOCK) k_pd_edges(int32_t *D, int64_t ld, c
 // In the tile kernels thread (ty, tx) owns rows 4ty..4ty+3 and columns
 // 4tx..4tx+3 of a tile.
 
-// phase 1: D_kk closed over its own 64 pivots, in order.  Each thread keeps
-// its 16 entries in registers; after pivot k the owners of row k+1 and
-// column k+1 publish them to LDS for the next pivot.  Row k and column k do
-// not change at pivot k (D[k][k] = -1), and the entries written after pivot
-// k are not the ones read at pivot k, so one barrier per pivot suffices.
-__global__ void __launch_bounds__(PD_BLOCK) k_pd_diag(int32_t *D, int64_t ld, int64_t kb) {
+// phase 1: D_kk closed over its own 64 pivots, in order, by 1024 threads of
+// 2 x 2 entries each (thread (ty, tx) of 32 x 32: rows 2ty, 2ty+1, columns
+// 2tx, 2tx+1), which keeps the work between two pivots short.  The entries
+// stay in registers; after pivot k the owners of row k+1 and column k+1
+// publish them to LDS for the next pivot.  Row k and column k do not change
+// at pivot k (D[k][k] = -1), and the entries written after pivot k are not
+// the ones read at pivot k, so one barrier per pivot suffices.
+#define PD_DIAG_BLOCK 1024
+__global__ void __launch_bounds__(PD_DIAG_BLOCK) k_pd_diag(int32_t *D, int64_t ld, int64_t kb) {
     __shared__ __align__(16) int32_t s[PD_T][PD_T + 4];
-    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-    int32_t acc[4][4];
+    const int ty = threadIdx.x >> 5, tx = threadIdx.x & 31;
+    int32_t acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-        const int4 v = *(const int4 *)(D + (kb * PD_T + 4 * ty + a) * ld + kb * PD_T + 4 * tx);
+    for (int a = 0; a < 2; a++) {
+        const int2 v = *(const int2 *)(D + (kb * PD_T + 2 * ty + a) * ld + kb * PD_T + 2 * tx);
         acc[a][0] = v.x;
         acc[a][1] = v.y;
-        acc[a][2] = v.z;
-        acc[a][3] = v.w;
-        *(int4 *)&s[4 * ty + a][4 * tx] = v;
+        *(int2 *)&s[2 * ty + a][2 * tx] = v;
     }
     __syncthreads();
     for (int k = 0; k < PD_T; k++) {
-        int32_t ck[4], rk[4];
-#pragma unroll
-        for (int a = 0; a < 4; a++) ck[a] = s[4 * ty + a][k];
-#pragma unroll
-        for (int b = 0; b < 4; b++) rk[b] = s[k][4 * tx + b];
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int b = 0; b < 4; b++) acc[a][b] = min(acc[a][b], max(ck[a], rk[b]));
+        const int32_t c0 = s[2 * ty][k], c1 = s[2 * ty + 1][k];
+        const int2 r = *(const int2 *)&s[k][2 * tx];
+        acc[0][0] = min(acc[0][0], max(c0, r.x));
+        acc[0][1] = min(acc[0][1], max(c0, r.y));
+        acc[1][0] = min(acc[1][0], max(c1, r.x));
+        acc[1][1] = min(acc[1][1], max(c1, r.y));
         const int k1 = k + 1;
 #pragma unroll
-        for (int a = 0; a < 4; a++)
-            if (4 * ty + a == k1)
+        for (int a = 0; a < 2; a++)
+            if (2 * ty + a == k1) *(int2 *)&s[k1][2 * tx] = make_int2(acc[a][0], acc[a][1]);
 #pragma unroll
-                for (int b = 0; b < 4; b++) s[k1][4 * tx + b] = acc[a][b];
-#pragma unroll
-        for (int b = 0; b < 4; b++)
-            if (4 * tx + b == k1)
-#pragma unroll
-                for (int a = 0; a < 4; a++) s[4 * ty + a][k1] = acc[a][b];
+        for (int b = 0; b < 2; b++)
+            if (2 * tx + b == k1) {
+                s[2 * ty][k1] = acc[0][b];
+                s[2 * ty + 1][k1] = acc[1][b];
+            }
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 4; a++)
-        *(int4 *)(D + (kb * PD_T + 4 * ty + a) * ld + kb * PD_T + 4 * tx) =
-            make_int4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
+    for (int a = 0; a < 2; a++)
+        *(int2 *)(D + (kb * PD_T + 2 * ty + a) * ld + kb * PD_T + 2 * tx) = make_int2(acc[a][0], acc[a][1]);
 }
 
 // out = min(out, A (min,max) B) for 64 x 64 tiles A = (ai, aj), B = (bi, bj),
@@ -208,7 +204,7 @@ extern "C" VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_
                            (const int32_t *)res->edge_ij, K, n);
     if (K > 0)
         for (int64_t kb = 0; kb < nb; kb++) {
-            hipLaunchKernelGGL(k_pd_diag, dim3(1), dim3(PD_BLOCK), 0, s, D, ld, kb);
+            hipLaunchKernelGGL(k_pd_diag, dim3(1), dim3(PD_DIAG_BLOCK), 0, s, D, ld, kb);
             if (nb > 1) {
                 hipLaunchKernelGGL(k_pd_cross, dim3((unsigned)(2 * nb)), dim3(PD_BLOCK), 0, s, D, ld, kb, nb);
                 hipLaunchKernelGGL(k_pd_rest, dim3((unsigned)nb, (unsigned)nb), dim3(PD_BLOCK), 0, s, D, ld, kb, nb);
