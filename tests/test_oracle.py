@@ -432,3 +432,27 @@ def test_reductions_without_triangles(orc):
         p1, p2 = orc.reduce(f1, m), orc.reduce(f2, m)
         assert np.array_equal(p1.e_low, p2.e_low)
         assert len(p1.t_low) == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dim0_pairs_follow_elder_rule(orc, seed):
+    """With vertices ordered by index, the column reduction pairs edge r with
+    the younger of the two components it joins, named by its smallest vertex
+    (a union-find that keeps each component's smallest vertex as its root)."""
+    c = workloads.noisy_circle(seed=50 + seed, n=120)
+    f = orc.build(c.points, [("fraction", 8, 100), ("count", 90, 1), ("full", 0, 1), ("sqdist", 300, 0)][seed])
+    root = list(range(f.n))
+
+    def find(x):
+        while root[x] != x:
+            x = root[x]
+        return x
+
+    want = np.full(f.K, -1)
+    for r, (a, b) in enumerate(zip(f.ei, f.ej)):
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            want[r] = max(ra, rb)
+            root[max(ra, rb)] = min(ra, rb)
+    for m in ("homology", "cohomology"):
+        assert np.array_equal(orc.reduce(f, m).e_low, want)
