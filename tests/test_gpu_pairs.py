@@ -76,3 +76,28 @@ def test_pairs_dim0_no_edges(orc):
     pts = workloads.uniform_cloud(46, 50, 3).points
     e_low, death, counts = _gpu_pairs(pts, ("count", 0, 1))
     assert counts[1] == 0 and len(e_low) == 0 and np.all(death == -1)
+
+
+def test_pairs_dim0_largest_point_count(orc):
+    """n = 8192, the largest point count (a 268 MB closure in 128 pivot
+    blocks), at a sparse threshold that leaves several components."""
+    import time
+
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.uniform_cloud(47, 8192, 3)
+    thr = ("fraction", 1, 1000)
+    print("[gpu] pairs_dim0 n=8192", flush=True)
+    f = orc.build(c.points, thr, maxdim=1)
+    ref = orc.reduce(f, "cohomology").e_low
+    r = vr.build(torch.from_numpy(c.points).to("cuda:0"), thr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_low, death = vr.pairs_dim0(r)
+    torch.cuda.synchronize()
+    print(f"[gpu] pairs_dim0 n=8192 K={r.counts[1]}: {1e3 * (time.perf_counter() - t0):.1f} ms", flush=True)
+    assert np.array_equal(e_low.cpu().numpy().astype(np.int64), ref)
+    assert int((death.cpu().numpy() < 0).sum()) == f.n - int((ref >= 0).sum())
+    r.free()
