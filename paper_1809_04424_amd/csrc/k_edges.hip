@@ -108,11 +108,22 @@ __global__ __launch_bounds__(VR_BLOCK) void k_dist(VrDev D) {
     for (int c0 = 0; c0 < d; c0 += DIST_CC) {
         const int cc = min(DIST_CC, d - c0);
         __syncthreads();
-        for (int x = threadIdx.x; x < DIST_TB * DIST_CC; x += VR_BLOCK) {
-            int r = x / DIST_CC, cx = x % DIST_CC;
-            int gi = bi * DIST_TB + r, gj = bj * DIST_TB + r;
-            xi[r][cx] = (gi < n && cx < cc) ? (int32_t)pts[(size_t)gi * d + c0 + cx] : 0;
-            xj[r][cx] = (gj < n && cx < cc) ? (int32_t)pts[(size_t)gj * d + c0 + cx] : 0;
+        if (cc == DIST_CC) {
+            for (int x = threadIdx.x; x < DIST_TB * DIST_CC; x += VR_BLOCK) {
+                const int r = x / DIST_CC, cx = x % DIST_CC;
+                const int gi = bi * DIST_TB + r, gj = bj * DIST_TB + r;
+                xi[r][cx] = gi < n ? (int32_t)pts[(size_t)gi * d + c0 + cx] : 0;
+                xj[r][cx] = gj < n ? (int32_t)pts[(size_t)gj * d + c0 + cx] : 0;
+            }
+        } else {
+            // a partial chunk (every chunk when d < 64): stage only the cc
+            // coordinates the loop below reads
+            for (int x = threadIdx.x; x < DIST_TB * cc; x += VR_BLOCK) {
+                const int r = x / cc, cx = x - r * cc;
+                const int gi = bi * DIST_TB + r, gj = bj * DIST_TB + r;
+                xi[r][cx] = gi < n ? (int32_t)pts[(size_t)gi * d + c0 + cx] : 0;
+                xj[r][cx] = gj < n ? (int32_t)pts[(size_t)gj * d + c0 + cx] : 0;
+            }
         }
         __syncthreads();
         for (int cx = 0; cx < cc; cx++) {
