@@ -399,7 +399,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="circle1000")
+    ap.add_argument("--workload", default="circle1000",
+                    choices=["circle1000", "mixture4000", "plain64", "batched512", "hamming1088", "colorder2000",
+                             "pairs0"],
+                    help="circle1000 (the benchmark line, with side measurements), mixture4000, plain64, "
+                         "batched512 (one batched build of 512 clouds), or one side measurement alone: "
+                         "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cloud batched side measurement")
@@ -416,8 +421,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU split is a design note, not an implementation)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(splitting a build over several GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
