@@ -101,3 +101,27 @@ def test_pairs_dim0_largest_point_count(orc):
     assert np.array_equal(e_low.cpu().numpy().astype(np.int64), ref)
     assert int((death.cpu().numpy() < 0).sum()) == f.n - int((ref >= 0).sum())
     r.free()
+
+
+def test_pairs_dim0_of_batch_items_and_matrix_builds(orc):
+    """Any result works: the clouds of a batch, and a dissimilarity-matrix build."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    clouds = [workloads.noisy_circle(seed=60 + i, n=n).points for i, n in enumerate((40, 150, 3, 260))]
+    thr = ("fraction", 15, 100)
+    b = vr.build_batch([torch.from_numpy(p).to("cuda:0") for p in clouds], thr)
+    for p, item in zip(clouds, b):
+        e_low, death = vr.pairs_dim0(item)
+        torch.cuda.synchronize()
+        f = orc.build(p, thr, maxdim=1)
+        assert np.array_equal(e_low.cpu().numpy().astype(np.int64), orc.reduce(f, "cohomology").e_low)
+    b.free()
+    M = workloads.hamming_matrix(61, 300)
+    r = vr.build_matrix(torch.from_numpy(M).to("cuda:0"), ("fraction", 5, 100))
+    e_low, _ = vr.pairs_dim0(r)
+    torch.cuda.synchronize()
+    f = orc.build_matrix(M, ("fraction", 5, 100), maxdim=1)
+    assert np.array_equal(e_low.cpu().numpy().astype(np.int64), orc.reduce(f, "cohomology").e_low)
+    r.free()
