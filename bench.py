@@ -359,6 +359,39 @@ def _column_order(vr, torch, reps=20):
             "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def _with_d2h(vr, torch, pts, thr, steps=20, warmup=3):
+    """End to end with the outputs copied to the host: each step builds, then
+    copies the edge endpoints, edge lengths and triangle keys into pinned
+    host buffers (allocated once, before timing) and waits for the copies.
+    The library's boundary keeps outputs on the device; this is the rate a
+    caller that needs them on the host sees over PCIe."""
+    r = vr.build(pts, thr)
+    torch.cuda.synchronize()
+    n, K, T = r.counts
+    r.free()
+    h_ij = torch.empty((K, 2), dtype=torch.int32, pin_memory=True)
+    h_q = torch.empty(K, dtype=torch.int64, pin_memory=True)
+    h_tri = torch.empty(T, dtype=torch.int64, pin_memory=True)
+
+    def step():
+        r = vr.build(pts, thr)
+        h_ij.copy_(r.edge_ij(), non_blocking=True)
+        h_q.copy_(r.edge_q(), non_blocking=True)
+        h_tri.copy_(r.tri_key(), non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        r.free()
+
+    for _ in range(warmup):
+        step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    el = time.perf_counter() - t0
+    out_bytes = 8 * K + 8 * K + 8 * T
+    return {"value": (n + K + T) * steps / el, "unit": "simplices/s", "ms_per_step": 1e3 * el / steps,
+            "output_bytes_per_step": out_bytes, "d2h_GBps": out_bytes * steps / el / 1e9}
+
+
 def _pairs_dim0(vr, torch, reps=20):
     """Dimension-0 persistence pairs of the circle1000 build: a (min, max)
     closure of the padded n x n rank matrix (2 * ld^3 integer min/max
@@ -491,6 +524,7 @@ def main():
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
+        extra["circle1000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr)
 
     if not args.no_batch and args.workload == "circle1000":
         extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)
