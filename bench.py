@@ -359,6 +359,28 @@ def _column_order(vr, torch, reps=20):
             "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def _event_median(vr, torch, pts, thr, reps=20, warmup=3):
+    """Median over `reps` builds of the time between HIP events recorded on
+    the torch stream just before and just after each vr.build call (the call
+    enqueues every kernel of the build on that stream), after `warmup`
+    builds."""
+    for _ in range(warmup):
+        vr.build(pts, thr).free()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = vr.build(pts, thr)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+        r.free()
+    ts.sort()
+    return {"median_ms": round(ts[reps // 2], 5), "min_ms": round(ts[0], 5), "max_ms": round(ts[-1], 5),
+            "reps": reps, "warmup": warmup}
+
+
 def _with_d2h(vr, torch, pts, thr, steps=20, warmup=3):
     """End to end with the outputs copied to the host: each step builds, then
     copies the edge endpoints, edge lengths and triangle keys into pinned
@@ -525,6 +547,7 @@ def main():
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
         extra["circle1000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr)
+        extra["circle1000_event_timed"] = _event_median(vr, torch, pts, cloud.thr)
 
     if not args.no_batch and args.workload == "circle1000":
         extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)
