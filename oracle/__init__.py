@@ -22,6 +22,9 @@ passage of arXiv:1809.04424 it follows:
 * per-column ordering of a compressed-sparse-column array: the slot of every
   entry when its column is sorted stably by value, by the original and by the
   modified counting sort of Section 4.3;
+* the F2 sparse product and sum S = D + C E of the Schur complement step,
+  whole and partitioned by columns as the paper's workers compute it
+  (Section 4.6);
 * persistence pairs: Algorithm 1 over F2 on the boundary matrix, and the same
   algorithm on the anti-transpose with clearing (Sections 2.2.1, 2.2.2).
 """
@@ -335,3 +338,89 @@ def column_order(colptr, v) -> np.ndarray:
     cp, vv = _csc(colptr, v)
     _, dense = np.unique(vv, return_inverse=True)
     return column_order_modified(cp, dense.astype(np.int64).reshape(-1))
+
+
+# --- F2 sparse product and sum (Section 4.6) -------------------------------
+
+def _csc_check(colptr, rows, nrows):
+    cp = np.ascontiguousarray(colptr, dtype=np.int64)
+    rw = np.ascontiguousarray(rows, dtype=np.int64)
+    if cp.ndim != 1 or len(cp) < 1 or cp[0] != 0 or np.any(np.diff(cp) < 0) or cp[-1] != len(rw):
+        raise ValueError("colptr must start at 0, not decrease, and end at len(rows)")
+    if len(rw) and (rw.min() < 0 or rw.max() >= nrows):
+        raise ValueError("row index out of range")
+    return cp, rw
+
+
+def _dense_f2(colptr, rows, nrows):
+    """Dense 0/1 matrix of a CSC pattern; a row listed twice in a column
+    cancels (entries are added mod 2)."""
+    ncols = len(colptr) - 1
+    M = np.zeros((nrows, ncols), np.int64)
+    for j in range(ncols):
+        for r in rows[colptr[j]:colptr[j + 1]]:
+            M[r, j] ^= 1
+    return M
+
+
+def _csc_of_dense(M):
+    """CSC of a 0/1 matrix, rows ascending in each column."""
+    colptr = np.zeros(M.shape[1] + 1, np.int64)
+    rows = []
+    for j in range(M.shape[1]):
+        nz = np.nonzero(M[:, j])[0]
+        rows.append(nz)
+        colptr[j + 1] = colptr[j] + len(nz)
+    return colptr, (np.concatenate(rows).astype(np.int64) if rows else np.zeros(0, np.int64))
+
+
+def blockprodsum(m, C, E, D):
+    """S = D + C E over F2 (Section 4.6: the Schur complement's D + C A^-1 B
+    once E = A^-1 B is known), for CSC matrices given as (colptr, rows):
+    C is m x k, E is k x n, D is m x n.  Dense integer product, then mod 2.
+    Returns S as (colptr, rows) with rows ascending in each column."""
+    cpC, rC = C
+    k = len(cpC) - 1
+    cpE, rE = _csc_check(*E, k)
+    n = len(cpE) - 1
+    cpC, rC = _csc_check(cpC, rC, m)
+    cpD, rD = _csc_check(*D, m)
+    if len(cpD) - 1 != n:
+        raise ValueError("D must have as many columns as E")
+    S = (_dense_f2(cpD, rD, m) + _dense_f2(cpC, rC, m) @ _dense_f2(cpE, rE, k)) % 2
+    return _csc_of_dense(S)
+
+
+def blockprodsum_by_workers(m, C, E, D, workers):
+    """The same product computed as the paper partitions it: the columns of D
+    and E are split into `workers` contiguous blocks, each block i computes
+    S_i = D_i + C E_i on its own, and the column pointers of the blocks are
+    then shifted one after the other to join them."""
+    cpE, rE = np.asarray(E[0], np.int64), np.asarray(E[1], np.int64)
+    cpD, rD = np.asarray(D[0], np.int64), np.asarray(D[1], np.int64)
+    n = len(cpE) - 1
+    cuts = [n * i // workers for i in range(workers + 1)]
+    colptr, rows = [np.zeros(1, np.int64)], []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        Ei = (cpE[a:b + 1] - cpE[a], rE[cpE[a]:cpE[b]])
+        Di = (cpD[a:b + 1] - cpD[a], rD[cpD[a]:cpD[b]])
+        cp, rw = blockprodsum(m, C, Ei, Di)
+        colptr.append(cp[1:] + colptr[-1][-1])  # the master's adjustment
+        rows.append(rw)
+    return np.concatenate(colptr), (np.concatenate(rows) if rows else np.zeros(0, np.int64))
+
+
+def blockprodsum_column(m, C, E, D, j):
+    """Column j of S = D + C E by the definition, one column at a time: the
+    symmetric difference of column j of D and the columns of C that column j
+    of E selects (a row selected twice cancels).  Rows ascending."""
+    cpC, rC = np.asarray(C[0], np.int64), np.asarray(C[1], np.int64)
+    cpE, rE = np.asarray(E[0], np.int64), np.asarray(E[1], np.int64)
+    cpD, rD = np.asarray(D[0], np.int64), np.asarray(D[1], np.int64)
+    odd = set()
+    for r in rD[cpD[j]:cpD[j + 1]]:
+        odd ^= {int(r)}
+    for kk in rE[cpE[j]:cpE[j + 1]]:
+        for r in rC[cpC[kk]:cpC[kk + 1]]:
+            odd ^= {int(r)}
+    return np.array(sorted(odd), np.int64)

@@ -456,3 +456,72 @@ def test_dim0_pairs_follow_elder_rule(orc, seed):
             root[max(ra, rb)] = min(ra, rb)
     for m in ("homology", "cohomology"):
         assert np.array_equal(orc.reduce(f, m).e_low, want)
+
+
+# --- F2 sparse product and sum (Section 4.6) --------------------------------
+
+def _f2(seed, m, n, L, dup=0.2):
+    return workloads.f2_csc(seed, m, n, L, dup=dup)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_blockprodsum_dense_equals_columnwise_and_scipy(orc, seed):
+    import scipy.sparse as sp
+
+    m, k, n = [(30, 20, 25), (64, 64, 64), (97, 13, 40), (5, 50, 7), (200, 150, 120)][seed]
+    C, E, D = _f2(seed, m, k, 3), _f2(seed + 10, k, n, 2), _f2(seed + 20, m, n, 2)
+    cp, rw = orc.blockprodsum(m, C, E, D)
+    for j in range(n):
+        assert np.array_equal(rw[cp[j]:cp[j + 1]], orc.blockprodsum_column(m, C, E, D, j))
+
+    def mat(x, rows):
+        c, r = x
+        return sp.csc_matrix((np.ones(len(r), np.int64), r.astype(np.int64), c), shape=(rows, len(c) - 1))
+
+    S = (mat(D, m) + mat(C, m) @ mat(E, k)).toarray() % 2
+    cps, rws = orc._csc_of_dense(S)
+    assert np.array_equal(cp, cps) and np.array_equal(rw, rws)
+
+
+def test_blockprodsum_special_cases(orc):
+    m, n = 40, 30
+    C, D = _f2(1, m, n, 4, dup=0), _f2(2, m, n, 3, dup=0)
+    eye = (np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32))
+    zero = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32))
+    # E = I: S = D + C
+    cp, rw = orc.blockprodsum(m, C, eye, D)
+    want = (orc._dense_f2(D[0], D[1].astype(np.int64), m) + orc._dense_f2(C[0], C[1].astype(np.int64), m)) % 2
+    assert np.array_equal(orc._dense_f2(cp, rw, m), want)
+    # E = 0: S = D;  D = 0 and C = I: S = E
+    cp, rw = orc.blockprodsum(m, C, zero, D)
+    assert np.array_equal(orc._dense_f2(cp, rw, m), orc._dense_f2(D[0], D[1].astype(np.int64), m))
+    E = _f2(3, n, 25, 3)
+    cp, rw = orc.blockprodsum(n, eye, E, (np.zeros(26, np.int64), np.zeros(0, np.int32)))
+    assert np.array_equal(orc._dense_f2(cp, rw, n), orc._dense_f2(E[0], E[1].astype(np.int64), n))
+
+
+def test_blockprodsum_is_linear(orc):
+    """S(C, E1 + E2, D1 + D2) = S(C, E1, D1) + S(C, E2, D2) over F2."""
+    m, k, n = 50, 40, 30
+    C = _f2(4, m, k, 5)
+    E1, E2, D1, D2 = _f2(5, k, n, 3), _f2(6, k, n, 3), _f2(7, m, n, 2), _f2(8, m, n, 2)
+
+    def add(A, B, rows):
+        return orc._csc_of_dense((orc._dense_f2(A[0], np.asarray(A[1], np.int64), rows)
+                                  + orc._dense_f2(B[0], np.asarray(B[1], np.int64), rows)) % 2)
+
+    lhs = orc.blockprodsum(m, C, add(E1, E2, k), add(D1, D2, m))
+    s1, s2 = orc.blockprodsum(m, C, E1, D1), orc.blockprodsum(m, C, E2, D2)
+    rhs = add(s1, s2, m)
+    assert np.array_equal(lhs[0], rhs[0]) and np.array_equal(lhs[1], rhs[1])
+
+
+@pytest.mark.parametrize("workers", [1, 2, 3, 4, 7])
+def test_blockprodsum_by_workers_equals_whole(orc, workers):
+    """The paper's partition by columns, with the column pointers shifted
+    block after block, gives the whole product."""
+    m, k, n = 60, 45, 33
+    C, E, D = _f2(9, m, k, 4), _f2(10, k, n, 3), _f2(11, m, n, 2)
+    a = orc.blockprodsum(m, C, E, D)
+    b = orc.blockprodsum_by_workers(m, C, E, D, workers)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -222,3 +222,25 @@ CONFIGS = {
 
 def config(name: str) -> Cloud:
     return CONFIGS[name]()
+
+
+def f2_csc(seed: int, nrows: int, ncols: int, mean_len: float, empty: float = 0.1, dup: float = 0.0):
+    """A random sparse 0/1 pattern in CSC (colptr int64, rows int32): column
+    lengths geometric with the given mean, a fraction `empty` of the columns
+    empty, rows uniform in 0..nrows-1 and distinct within a column (with
+    probability `dup` a column repeats one of its rows, which over F2
+    cancels it), rows in random order within a column."""
+    rng = np.random.default_rng(seed)
+    lens = rng.geometric(1.0 / max(mean_len, 1.0), ncols).astype(np.int64) if ncols else np.zeros(0, np.int64)
+    lens = np.minimum(lens, nrows)
+    lens[rng.random(ncols) < empty] = 0
+    cols = []
+    for L in lens:
+        r = rng.choice(nrows, int(L), replace=False) if L else np.zeros(0, np.int64)
+        if L and rng.random() < dup:
+            r = np.concatenate([r, r[:1]])
+        cols.append(r)
+    colptr = np.zeros(ncols + 1, np.int64)
+    np.cumsum([len(c) for c in cols], out=colptr[1:])
+    rows = (np.concatenate(cols) if cols else np.zeros(0)).astype(np.int32)
+    return colptr, rows
