@@ -272,6 +272,29 @@ VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *
  * the library's cache.  VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
 VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, void *stream);
 
+/* The F2 sparse product and sum of the Schur complement step (Section 4.6):
+ * S = D + C E mod 2, where C is m x k, E is k x n and D is m x n, all in
+ * compressed sparse columns on the device: colptr (ncols + 1 int64, from 0,
+ * non-decreasing, ending at the entry count) and rows (int32 row indices;
+ * NULL only for a matrix without entries).  Rows within a column may come
+ * in any order, and a row listed twice in a column cancels.  Two calls:
+ *   vr_blockprodsum_count writes S's column pointers into s_colptr (n + 1
+ *     int64, caller-owned device memory);
+ *   vr_blockprodsum_write then writes S's rows into s_rows (s_colptr[n]
+ *     int32, caller-owned), ascending within each column; it takes the
+ *     s_colptr of a count call on the same inputs.
+ * Both are enqueued on `stream` and allocate nothing.  VR_EINVAL for
+ * negative sizes or missing column pointers, VR_E2BIG for m > 262144 (the
+ * rows of one column of S are gathered in a bitmap in LDS).  Malformed
+ * column pointers or row indices give an unspecified S but no access
+ * outside the arrays they describe. */
+VR_API int vr_blockprodsum_count(int64_t m, int64_t k, int64_t n, const int64_t *c_colptr, const int32_t *c_rows,
+                                 const int64_t *e_colptr, const int32_t *e_rows, const int64_t *d_colptr,
+                                 const int32_t *d_rows, int64_t *s_colptr, void *stream);
+VR_API int vr_blockprodsum_write(int64_t m, int64_t k, int64_t n, const int64_t *c_colptr, const int32_t *c_rows,
+                                 const int64_t *e_colptr, const int32_t *e_rows, const int64_t *d_colptr,
+                                 const int32_t *d_rows, const int64_t *s_colptr, int32_t *s_rows, void *stream);
+
 /* Device memory.  Without a caller allocator, workspaces and output blocks
  * come from a stream-ordered cache inside the library: blocks are taken from
  * the driver once and reused by later builds of any stream (a reuse on

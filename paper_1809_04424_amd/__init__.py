@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -117,6 +117,11 @@ def lib():
         L.vr_column_order.restype = ctypes.c_int
         L.vr_pairs_dim0.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.vr_pairs_dim0.restype = ctypes.c_int
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.vr_blockprodsum_count.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.vr_blockprodsum_count.restype = ctypes.c_int
+        L.vr_blockprodsum_write.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.vr_blockprodsum_write.restype = ctypes.c_int
         L.vr_trim.argtypes = []
         L.vr_trim.restype = ctypes.c_int64
         L.vr_status_string.argtypes = [ctypes.c_int]
@@ -583,3 +588,39 @@ def pairs_dim0(result):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return e_low, death
+
+
+def blockprodsum(m, C, E, D):
+    """S = D + C E over F2 (Section 4.6) for device CSC matrices given as
+    (colptr int64, rows int32) tensors: C is m x k, E is k x n, D is m x n.
+    Returns S as (colptr, rows), rows ascending in each column."""
+    import torch
+
+    L = lib()
+    mats = []
+    for name, (cp, rw) in (("C", C), ("E", E), ("D", D)):
+        if cp.dtype != torch.int64 or rw.dtype != torch.int32 or cp.device.type != "cuda" or rw.device != cp.device:
+            raise TypeError(f"{name} must be (int64 colptr, int32 rows) tensors on a HIP device")
+        mats.append((cp.contiguous(), rw.contiguous()))
+    for name, (cp, rw) in zip("CED", mats):
+        if cp.numel() < 1 or int(cp[-1].item()) != rw.numel():
+            raise ValueError(f"{name}: colptr must end at the number of rows listed")
+    (cpc, rc), (cpe, re_), (cpd, rd) = mats
+    k, n = cpc.numel() - 1, cpe.numel() - 1
+    if cpd.numel() - 1 != n:
+        raise ValueError("D must have as many columns as E")
+    dev = cpc.device
+    stream = torch.cuda.current_stream(dev)
+    s_colptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+    args = (int(m), k, n, ptr(cpc), ptr(rc), ptr(cpe), ptr(re_), ptr(cpd), ptr(rd))
+    with torch.cuda.device(dev):
+        rc_ = L.vr_blockprodsum_count(*args, ptr(s_colptr), ctypes.c_void_p(stream.cuda_stream))
+        if rc_ != VR_OK:
+            raise VrError(rc_, status_string(rc_))
+        nnz = int(s_colptr[-1].item())
+        s_rows = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        rc_ = L.vr_blockprodsum_write(*args, ptr(s_colptr), ptr(s_rows), ctypes.c_void_p(stream.cuda_stream))
+        if rc_ != VR_OK:
+            raise VrError(rc_, status_string(rc_))
+    return s_colptr, s_rows[:nnz]

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvrhip.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["vr_api.hip", "vr_cache.hip", "k_edges.hip", "k_triangles.hip", "k_gram.hip", "k_colsort.hip", "k_pairs.hip"]
+SOURCES = ["vr_api.hip", "vr_cache.hip", "k_edges.hip", "k_triangles.hip", "k_gram.hip", "k_colsort.hip", "k_pairs.hip", "k_schur.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -208,3 +208,12 @@ def test_pairs_dim0_argument_checks():
     assert L.vr_pairs_dim0(ctypes.byref(r), None, None, None) == vr.VR_EINVAL  # edges but no arrays
     r = vr.VrResult(9000, 0, 0, None, None, None)
     assert L.vr_pairs_dim0(ctypes.byref(r), None, None, None) == vr.VR_EINVAL
+
+
+def test_blockprodsum_argument_checks():
+    L = vr.lib()
+    p = ctypes.c_void_p(8)  # never dereferenced: every call below is refused first
+    assert L.vr_blockprodsum_count(-1, 1, 1, p, p, p, p, p, p, p, None) == vr.VR_EINVAL
+    assert L.vr_blockprodsum_count(1, 1, 1, None, p, p, p, p, p, p, None) == vr.VR_EINVAL
+    assert L.vr_blockprodsum_count(300000, 1, 1, p, p, p, p, p, p, p, None) == vr.VR_E2BIG
+    assert L.vr_blockprodsum_write(1, 1, 1, p, p, p, p, p, p, None, p, None) == vr.VR_EINVAL
