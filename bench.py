@@ -414,6 +414,41 @@ def _with_d2h(vr, torch, pts, thr, steps=20, warmup=3):
             "output_bytes_per_step": out_bytes, "d2h_GBps": out_bytes * steps / el / 1e9}
 
 
+def _schur(vr, torch, reps=10):
+    """S = D + C E over F2 (the Schur complement step) for 16384 x 16384
+    sparse matrices in compressed columns: C with 32 entries per column on
+    average, E and D with 8, seeded.  HIP events on the current stream around
+    each whole call (count, scan, the host's read of the entry count, write).
+    `xors` counts the row additions: every entry of D plus, for every entry
+    (k, j) of E, the entries of column k of C."""
+    import numpy as np
+
+    import workloads
+
+    m = k = n = 16384
+    C = workloads.f2_csc(101, m, k, 32, empty=0.0)
+    E = workloads.f2_csc(102, k, n, 8, empty=0.0)
+    D = workloads.f2_csc(103, m, n, 8, empty=0.0)
+    lens_c = np.diff(C[0])
+    xors = int(len(D[1]) + lens_c[E[1]].sum())
+    dev = lambda x: (torch.from_numpy(x[0]).to("cuda:0"), torch.from_numpy(x[1]).to("cuda:0"))
+    Cd, Ed, Dd = dev(C), dev(E), dev(D)
+    for _ in range(2):
+        vr.blockprodsum(m, Cd, Ed, Dd)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cp, _ = vr.blockprodsum(m, Cd, Ed, Dd)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[reps // 2]
+    return {"ms_per_call": round(ms, 5), "m": m, "k": k, "n": n, "xors": xors, "nnz_S": int(cp[-1].item()),
+            "xors_per_s": xors / (ms * 1e-3)}
+
+
 def _pairs_dim0(vr, torch, reps=20):
     """Dimension-0 persistence pairs of the circle1000 build: a (min, max)
     closure of the padded n x n rank matrix (2 * ld^3 integer min/max
@@ -456,10 +491,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="circle1000",
                     choices=["circle1000", "mixture4000", "plain64", "batched512", "hamming1088", "colorder2000",
-                             "pairs0"],
+                             "pairs0", "schur16384"],
                     help="circle1000 (the benchmark line, with side measurements), mixture4000, plain64, "
                          "batched512 (one batched build of 512 clouds), or one side measurement alone: "
-                         "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs)")
+                         "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs), "
+                         "schur16384 (F2 product and sum)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cloud batched side measurement")
@@ -500,6 +536,9 @@ def main():
     if args.workload == "pairs0":  # dimension-0 pairs of circle1000 alone (profiling)
         print(json.dumps({"workload": "pairs_dim0_circle1000", **_pairs_dim0(vr, torch, reps=args.steps)}),
               flush=True)
+        return
+    if args.workload == "schur16384":  # the F2 product and sum alone (profiling)
+        print(json.dumps({"workload": "schur_f2_16384", **_schur(vr, torch, reps=args.steps)}), flush=True)
         return
     if args.workload == "colorder2000":  # the per-column order alone (profiling)
         print(json.dumps({"workload": "column_order_2000x1999", **_column_order(vr, torch, reps=args.steps)}),
@@ -546,6 +585,7 @@ def main():
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
+        extra["schur_f2_16384"] = _schur(vr, torch)
         extra["circle1000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr)
         extra["circle1000_event_timed"] = _event_median(vr, torch, pts, cloud.thr)
 
