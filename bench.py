@@ -449,6 +449,34 @@ def _schur(vr, torch, reps=10):
             "xors_per_s": xors / (ms * 1e-3)}
 
 
+def _apparent(vr, torch, reps=20):
+    """Apparent pairs of dimension 1 on the circle1000 build: one pass over
+    the triangle keys (8 T bytes in, 4 K out), timed with HIP events on the
+    current stream.  Also counts the edges left to a column-serial stage:
+    neither paired with a vertex (dimension 0) nor apparent."""
+    c = _workload("circle1000")
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    r = vr.build(pts, c.thr)
+    for _ in range(2):
+        vr.pairs_dim1_apparent(r)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        app = vr.pairs_dim1_apparent(r)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
+    e_low, _ = vr.pairs_dim0(r)
+    n, K, T = r.counts
+    n_app = int((app >= 0).sum().item())
+    n_neg = int((e_low >= 0).sum().item())
+    r.free()
+    alg = 8 * T + 4 * K
+    return {"ms_per_call": round(ms, 5), "apparent_pairs": n_app, "edges_paired_dim0": n_neg,
+            "edges_left": K - n_app - n_neg, "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def _pairs_dim0(vr, torch, reps=20):
     """Dimension-0 persistence pairs of the circle1000 build: a (min, max)
     closure of the padded n x n rank matrix (2 * ld^3 integer min/max
@@ -494,7 +522,7 @@ def main():
                              "pairs0", "schur16384"],
                     help="circle1000 (the benchmark line, with side measurements), mixture4000, plain64, "
                          "batched512 (one batched build of 512 clouds), or one side measurement alone: "
-                         "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs), "
+                         "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs and dimension-1 apparent pairs), "
                          "schur16384 (F2 product and sum)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
@@ -533,9 +561,9 @@ def main():
                                      else None)}),
               flush=True)
         return
-    if args.workload == "pairs0":  # dimension-0 pairs of circle1000 alone (profiling)
-        print(json.dumps({"workload": "pairs_dim0_circle1000", **_pairs_dim0(vr, torch, reps=args.steps)}),
-              flush=True)
+    if args.workload == "pairs0":  # pairs of circle1000 alone (profiling)
+        print(json.dumps({"workload": "pairs_dim0_circle1000", **_pairs_dim0(vr, torch, reps=args.steps),
+                          "apparent_dim1": _apparent(vr, torch, reps=args.steps)}), flush=True)
         return
     if args.workload == "schur16384":  # the F2 product and sum alone (profiling)
         print(json.dumps({"workload": "schur_f2_16384", **_schur(vr, torch, reps=args.steps)}), flush=True)
@@ -585,6 +613,7 @@ def main():
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
+        extra["pairs_dim1_apparent_circle1000"] = _apparent(vr, torch)
         extra["schur_f2_16384"] = _schur(vr, torch)
         extra["circle1000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr)
         extra["circle1000_event_timed"] = _event_median(vr, torch, pts, cloud.thr)

@@ -272,6 +272,21 @@ VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *
  * the library's cache.  VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
 VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, void *stream);
 
+/* Apparent persistence pairs in dimension 1 (Section 2.2.1, Alg. 1 on the
+ * triangle columns).  The triangles of value r are the cofacets of edge r
+ * whose other edges are older; the first of them in filtration order is
+ * the oldest cofacet of edge r and has edge r as its youngest facet, and
+ * the column algorithm pairs the two (edge r becomes a cycle that this
+ * triangle fills at once: a bar of length zero).  The other pairs of
+ * dimension 1, the bars of positive length among them, need column
+ * additions and are not computed here.
+ * res:          a single build's result with triangle keys (not count-only).
+ * tri_of_edge:  device, K int32, caller-owned: the index in tri_key of the
+ *               triangle paired with edge r, or -1.
+ * Enqueued on `stream`; allocates nothing.  VR_EINVAL for a null argument,
+ * a result without keys, or T >= 2^31. */
+VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, void *stream);
+
 /* The F2 sparse product and sum of the Schur complement step (Section 4.6):
  * S = D + C E mod 2, where C is m x k, E is k x n and D is m x n, all in
  * compressed sparse columns on the device: colptr (ncols + 1 int64, from 0,

@@ -183,6 +183,22 @@ __global__ void __launch_bounds__(PD_BLOCK) k_pd_emit(const int32_t *death, int6
     if (r >= 0 && r < K) e_low[r] = (int32_t)v;
 }
 
+// Dimension 1, apparent pairs.  Triangles of value r are the cofacets of
+// edge r whose other two edges are older, and the writer emits them
+// together in lexicographic order, so the first of them is the oldest
+// cofacet of edge r, and edge r (the largest edge) is its youngest facet:
+// the two form an apparent pair, which the column algorithm always pairs.
+// The first triangle of each value is where the value changes along the
+// keys.
+__global__ void __launch_bounds__(PD_BLOCK) k_pd_apparent(const unsigned long long *key, int64_t T, int32_t *first,
+                                                         int64_t K) {
+    for (int64_t t = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; t < T; t += (int64_t)gridDim.x * PD_BLOCK) {
+        const unsigned long long v = key[t] >> 39;
+        const unsigned long long u = t > 0 ? key[t - 1] >> 39 : ~0ull;
+        if (v != u && (int64_t)v < K) first[v] = (int32_t)t;
+    }
+}
+
 static unsigned grid_for(int64_t items) {
     const int64_t g = (items + PD_BLOCK - 1) / PD_BLOCK;
     return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
@@ -219,4 +235,18 @@ extern "C" VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_
     const hipError_t e = hipGetLastError();
     cache_put(D, s);
     return e == hipSuccess ? VR_OK : VR_EHIP;
+}
+
+extern "C" VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, void *stream) {
+    if (!res) return VR_EINVAL;
+    const int64_t K = res->n_edges, T = res->n_triangles;
+    if (K < 0 || T < 0 || T > 0x7FFFFFFF) return VR_EINVAL;
+    if (K == 0) return VR_OK;
+    if (!tri_of_edge || (T > 0 && !res->tri_key)) return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_pd_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K);
+    if (T > 0)
+        hipLaunchKernelGGL(k_pd_apparent, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key,
+                           T, tri_of_edge, K);
+    return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
 }

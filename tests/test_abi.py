@@ -217,3 +217,12 @@ def test_blockprodsum_argument_checks():
     assert L.vr_blockprodsum_count(1, 1, 1, None, p, p, p, p, p, p, None) == vr.VR_EINVAL
     assert L.vr_blockprodsum_count(300000, 1, 1, p, p, p, p, p, p, p, None) == vr.VR_E2BIG
     assert L.vr_blockprodsum_write(1, 1, 1, p, p, p, p, p, p, None, p, None) == vr.VR_EINVAL
+
+
+def test_pairs_dim1_apparent_argument_checks():
+    L = vr.lib()
+    assert L.vr_pairs_dim1_apparent(None, None, None) == vr.VR_EINVAL
+    r = vr.VrResult(10, 0, 0, None, None, None)
+    assert L.vr_pairs_dim1_apparent(ctypes.byref(r), None, None) == vr.VR_OK  # no edges
+    r = vr.VrResult(10, 5, 3, None, None, None)
+    assert L.vr_pairs_dim1_apparent(ctypes.byref(r), ctypes.c_void_p(8), None) == vr.VR_EINVAL  # no keys

@@ -125,3 +125,40 @@ def test_pairs_dim0_of_batch_items_and_matrix_builds(orc):
     f = orc.build_matrix(M, ("fraction", 5, 100), maxdim=1)
     assert np.array_equal(e_low.cpu().numpy().astype(np.int64), orc.reduce(f, "cohomology").e_low)
     r.free()
+
+
+@pytest.mark.parametrize("name,gen,thr", CASES[:6], ids=[c[0] for c in CASES[:6]])
+def test_pairs_dim1_apparent(orc, name, gen, thr):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    pts = gen()
+    print(f"[gpu] pairs_dim1_apparent {name}", flush=True)
+    f = orc.build(pts, thr)
+    r = vr.build(torch.from_numpy(np.ascontiguousarray(pts)).to("cuda:0"), thr)
+    got = vr.pairs_dim1_apparent(r).cpu().numpy().astype(np.int64)
+    torch.cuda.synchronize()
+    r.free()
+    v = f.tris[:, 0]
+    want = np.full(f.K, -1, np.int64)
+    if f.T:
+        first = np.nonzero(np.r_[True, v[1:] != v[:-1]])[0]
+        want[v[first]] = first
+    assert np.array_equal(got, want)
+    if f.K <= 5000:  # each is a pair of the column reduction
+        t_low = orc.reduce(f, "cohomology").t_low
+        assert np.all(t_low[got[got >= 0]] == np.nonzero(got >= 0)[0])
+
+
+def test_pairs_dim1_apparent_needs_keys():
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.noisy_circle(seed=81, n=100)
+    r = vr.build(torch.from_numpy(c.points).to("cuda:0"), c.thr, count_only=True)
+    with pytest.raises(vr.VrError) as e:
+        vr.pairs_dim1_apparent(r)
+    assert e.value.code == vr.VR_EINVAL
+    r.free()

@@ -525,3 +525,20 @@ def test_blockprodsum_by_workers_equals_whole(orc, workers):
     a = orc.blockprodsum(m, C, E, D)
     b = orc.blockprodsum_by_workers(m, C, E, D, workers)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_apparent_pairs_are_persistence_pairs(orc, case):
+    """The first triangle of each value (the oldest cofacet of that value's
+    edge, which is the triangle's youngest facet) is always paired with that
+    edge by the column algorithm, in both reductions."""
+    c, thr = [(workloads.noisy_circle(seed=80, n=200), ("fraction", 20, 100)),
+              (workloads.lattice_cloud(4, 60, side=3), ("fraction", 40, 100)),
+              (workloads.plain64(), ("full", 0, 1)),
+              (workloads.uniform_cloud(6, 100, 3), ("sqdist", 4000, 0))][case]
+    f = orc.build(c.points, thr)
+    v = f.tris[:, 0]
+    first = np.nonzero(np.r_[True, v[1:] != v[:-1]])[0] if f.T else np.zeros(0, np.int64)
+    for m in ("homology", "cohomology"):
+        t_low = orc.reduce(f, m).t_low
+        assert np.array_equal(t_low[first], v[first])
