@@ -22,6 +22,8 @@ passage of arXiv:1809.04424 it follows:
 * per-column ordering of a compressed-sparse-column array: the slot of every
   entry when its column is sorted stably by value, by the original and by the
   modified counting sort of Section 4.3;
+* tetrahedra: for every kept edge, the number whose largest edge it is
+  (dimension 3, Section 2.1's rule one dimension up);
 * the F2 sparse product and sum S = D + C E of the Schur complement step,
   whole and partitioned by columns as the paper's workers compute it
   (Section 4.6);
@@ -424,3 +426,23 @@ def blockprodsum_column(m, C, E, D, j):
         for r in rC[cpC[kk]:cpC[kk + 1]]:
             odd ^= {int(r)}
     return np.array(sorted(odd), np.int64)
+
+
+# --- tetrahedra (dimension 3): counts per value -------------------------------
+
+def tetra_counts(f: Filtration) -> np.ndarray:
+    """For every kept edge r, the number of tetrahedra whose largest edge is
+    r (a tetrahedron exists once its six edges are kept; its value is its
+    largest edge rank, as for triangles in Section 2.1).  Per edge (i, j):
+    the vertices joined to both by older edges, then the pairs of them
+    joined by an older edge.  int64, K entries."""
+    R = np.asarray(f.R, np.int64)
+    out = np.zeros(f.K, np.int64)
+    for r in range(f.K):
+        i, j = int(f.ei[r]), int(f.ej[r])
+        low = np.nonzero((R[i] >= 0) & (R[i] < r) & (R[j] >= 0) & (R[j] < r))[0]
+        if len(low) < 2:
+            continue
+        sub = R[np.ix_(low, low)]
+        out[r] = int(np.count_nonzero(np.triu((sub >= 0) & (sub < r), 1)))
+    return out

@@ -151,3 +151,16 @@ def column_order(colptr, v):
         for i in range(a, b):
             z.append(a + sum(1 for t in range(a, b) if v[t] < v[i] or (v[t] == v[i] and t < i)))
     return z
+
+
+def tetra_counts(points, K_of):
+    """Per kept edge rank, the tetrahedra {a<b<c<d} with all six edges kept
+    whose largest edge rank is that edge's (by definition, itertools)."""
+    kept, rank, _, _ = filtration(points, K_of)
+    out = [0] * len(kept)
+    n = len(points)
+    for quad in itertools.combinations(range(n), 4):
+        rs = [rank.get(e) for e in itertools.combinations(quad, 2)]
+        if all(x is not None for x in rs):
+            out[max(rs)] += 1
+    return out

@@ -542,3 +542,20 @@ def test_apparent_pairs_are_persistence_pairs(orc, case):
     for m in ("homology", "cohomology"):
         t_low = orc.reduce(f, m).t_low
         assert np.array_equal(t_low[first], v[first])
+
+
+# --- tetrahedra counts (dimension 3) ----------------------------------------
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c.name for c in CASES])
+def test_tetra_counts_match_bruteforce(orc, case):
+    c = CASES[case]
+    f = orc.build(c.points, c.thr, list_triangles=False)
+    assert list(orc.tetra_counts(f)) == bf.tetra_counts(c.points, _K_of(c.thr))
+
+
+@pytest.mark.parametrize("n", [4, 5, 17, 40])
+def test_tetra_counts_full_threshold_closed_form(orc, n):
+    """Every 4-subset is a tetrahedron, counted at its largest edge once."""
+    c = workloads.uniform_cloud(20 + n, n, 3)
+    f = orc.build(c.points, ("full", 0, 1), list_triangles=False)
+    assert int(orc.tetra_counts(f).sum()) == math.comb(n, 4)
