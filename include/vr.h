@@ -287,6 +287,17 @@ VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, v
  * a result without keys, or T >= 2^31. */
 VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, void *stream);
 
+/* Tetrahedra (dimension 3) of a build's filtration, counted per largest
+ * edge: a tetrahedron exists once its six edges are kept, and its value is
+ * its largest edge rank (Section 2.1's rule one dimension up).  The
+ * tetrahedra themselves are not listed.
+ * res:     a single build's result (edges on the device, rank order).
+ * counts:  device, K int64, caller-owned: the tetrahedra whose largest
+ *          edge is edge r.
+ * Enqueued on `stream`; scratch of 4 n^2 bytes from the library's cache.
+ * VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
+VR_API int vr_tetra_counts(const vr_result *res, long long *counts, void *stream);
+
 /* The F2 sparse product and sum of the Schur complement step (Section 4.6):
  * S = D + C E mod 2, where C is m x k, E is k x n and D is m x n, all in
  * compressed sparse columns on the device: colptr (ncols + 1 int64, from 0,

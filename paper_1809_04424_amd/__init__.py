@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_blockprodsum_count", "vr_blockprodsum_write",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_tetra_counts", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -119,6 +119,8 @@ def lib():
         L.vr_pairs_dim0.restype = ctypes.c_int
         L.vr_pairs_dim1_apparent.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
         L.vr_pairs_dim1_apparent.restype = ctypes.c_int
+        L.vr_tetra_counts.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_tetra_counts.restype = ctypes.c_int
         vp, i64 = ctypes.c_void_p, ctypes.c_int64
         L.vr_blockprodsum_count.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.vr_blockprodsum_count.restype = ctypes.c_int
@@ -642,6 +644,24 @@ def pairs_dim1_apparent(result):
     with torch.cuda.device(result._device):
         rc = L.vr_pairs_dim1_apparent(ctypes.byref(r), ctypes.c_void_p(out.data_ptr() if K else 0),
                                       ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return out
+
+
+def tetra_counts(result):
+    """Tetrahedra per largest edge (dimension 3): an int64 device tensor of
+    K entries."""
+    import torch
+
+    L = lib()
+    n, K, T = result.counts
+    out = torch.empty(K, dtype=torch.int64, device=result._device)
+    r = VrResult(n, K, T, result._p_ij, result._p_q, result._p_tri)
+    stream = torch.cuda.current_stream(result._device)
+    with torch.cuda.device(result._device):
+        rc = L.vr_tetra_counts(ctypes.byref(r), ctypes.c_void_p(out.data_ptr() if K else 0),
+                               ctypes.c_void_p(stream.cuda_stream))
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return out

@@ -250,3 +250,67 @@ extern "C" VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_
                            T, tri_of_edge, K);
     return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
 }
+
+// Tetrahedra (dimension 3) per largest edge.  Work-group g takes edge r:
+// the vertices x joined to both ends by older edges (D[i][x] < r and
+// D[j][x] < r; the ends themselves fail one test, D[i][j] = r), compacted
+// into LDS, then the pairs of them joined by an older edge.  D as for the
+// pairs of dimension 0 (ranks, +inf off the edges, -1 on the diagonal).
+__global__ void __launch_bounds__(PD_BLOCK) k_tet_count(const int32_t *D, int64_t ld, int64_t n, const int32_t *ij,
+                                                       int64_t K, long long *counts) {
+    __shared__ uint16_t L[VR_MAX_POINTS];
+    __shared__ uint32_t m_s;
+    __shared__ unsigned long long tot[PD_BLOCK / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int64_t r = blockIdx.x; r < K; r += gridDim.x) {
+        const int64_t i = ij[2 * r], j = ij[2 * r + 1];
+        if (t == 0) m_s = 0;
+        __syncthreads();
+        if (i >= 0 && j >= 0 && i < n && j < n)
+            for (int64_t x0 = 0; x0 < n; x0 += PD_BLOCK) {
+                const int64_t x = x0 + t;
+                const bool in = x < n && D[i * ld + x] < r && D[j * ld + x] < r;
+                const unsigned long long b = __ballot(in);
+                uint32_t base = 0;
+                if (lane == 0 && b) base = atomicAdd(&m_s, (uint32_t)__popcll(b));
+                base = __shfl(base, 0, 64);
+                if (in) L[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] =
+                    (uint16_t)x;
+            }
+        __syncthreads();
+        const uint32_t m = m_s;
+        unsigned long long c = 0;
+        for (uint32_t a = t; a < m; a += PD_BLOCK) {
+            const int32_t *row = D + (int64_t)L[a] * ld;
+            for (uint32_t b2 = a + 1; b2 < m; b2++) c += row[L[b2]] < r ? 1ull : 0ull;
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+        if (lane == 0) tot[wv] = c;
+        __syncthreads();
+        if (t == 0) {
+            unsigned long long s = 0;
+            for (int w = 0; w < PD_BLOCK / 64; w++) s += tot[w];
+            counts[r] = (long long)s;
+        }
+        __syncthreads();  // m_s, L and tot are reused by the next edge
+    }
+}
+
+extern "C" VR_API int vr_tetra_counts(const vr_result *res, long long *counts, void *stream) {
+    if (!res) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges;
+    if (n < 0 || K < 0 || n > VR_MAX_POINTS) return VR_EINVAL;
+    if (K == 0) return VR_OK;
+    if (!counts || !res->edge_ij) return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    int32_t *D = (int32_t *)cache_get((size_t)n * (size_t)n * 4, s);
+    if (!D) return VR_ENOMEM;
+    hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, D, n);
+    hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, D, n, (const int32_t *)res->edge_ij, K, n);
+    hipLaunchKernelGGL(k_tet_count, dim3((unsigned)(K < 65536 ? K : 65536)), dim3(PD_BLOCK), 0, s, (const int32_t *)D,
+                       n, n, (const int32_t *)res->edge_ij, K, counts);
+    const hipError_t e = hipGetLastError();
+    cache_put(D, s);
+    return e == hipSuccess ? VR_OK : VR_EHIP;
+}

@@ -226,3 +226,12 @@ def test_pairs_dim1_apparent_argument_checks():
     assert L.vr_pairs_dim1_apparent(ctypes.byref(r), None, None) == vr.VR_OK  # no edges
     r = vr.VrResult(10, 5, 3, None, None, None)
     assert L.vr_pairs_dim1_apparent(ctypes.byref(r), ctypes.c_void_p(8), None) == vr.VR_EINVAL  # no keys
+
+
+def test_tetra_counts_argument_checks():
+    L = vr.lib()
+    assert L.vr_tetra_counts(None, None, None) == vr.VR_EINVAL
+    r = vr.VrResult(10, 0, 0, None, None, None)
+    assert L.vr_tetra_counts(ctypes.byref(r), None, None) == vr.VR_OK
+    r = vr.VrResult(10, 4, 0, None, None, None)
+    assert L.vr_tetra_counts(ctypes.byref(r), None, None) == vr.VR_EINVAL

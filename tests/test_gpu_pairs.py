@@ -162,3 +162,45 @@ def test_pairs_dim1_apparent_needs_keys():
         vr.pairs_dim1_apparent(r)
     assert e.value.code == vr.VR_EINVAL
     r.free()
+
+
+TET_CASES = [
+    ("circle150_p20", lambda: workloads.noisy_circle(seed=90, n=150).points, ("fraction", 20, 100)),
+    ("lattice_ties", lambda: workloads.lattice_cloud(5, 80, side=3).points, ("fraction", 40, 100)),
+    ("uniform_d4_sqdist", lambda: workloads.uniform_cloud(91, 120, 4).points, ("sqdist", 30000, 0)),
+    ("plain64_full", lambda: workloads.plain64().points, ("full", 0, 1)),
+    ("n3", lambda: workloads.uniform_cloud(92, 3, 2).points, ("full", 0, 1)),
+    ("n4", lambda: workloads.uniform_cloud(93, 4, 2).points, ("full", 0, 1)),
+]
+
+
+@pytest.mark.parametrize("name,gen,thr", TET_CASES, ids=[c[0] for c in TET_CASES])
+def test_tetra_counts(orc, name, gen, thr):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    pts = gen()
+    print(f"[gpu] tetra_counts {name}", flush=True)
+    f = orc.build(pts, thr, list_triangles=False)
+    r = vr.build(torch.from_numpy(np.ascontiguousarray(pts)).to("cuda:0"), thr)
+    got = vr.tetra_counts(r).cpu().numpy()
+    r.free()
+    assert np.array_equal(got, orc.tetra_counts(f))
+
+
+@pytest.mark.parametrize("n", [100, 300])
+def test_tetra_counts_full_threshold(n):
+    """Every 4-subset once: the counts sum to C(n, 4)."""
+    import math
+
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.uniform_cloud(94 + n, n, 3)
+    r = vr.build(torch.from_numpy(c.points).to("cuda:0"), ("full", 0, 1))
+    got = vr.tetra_counts(r)
+    assert int(got.sum().item()) == math.comb(n, 4)
+    assert int(got[:3].sum().item()) == 0  # the first three edges close no tetrahedron
+    r.free()
