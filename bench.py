@@ -477,6 +477,27 @@ def _apparent(vr, torch, reps=20):
             "edges_left": K - n_app - n_neg, "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def _tetra(vr, torch, reps=10):
+    """Tetrahedra per largest edge of the circle1000 build (dimension 3),
+    timed with HIP events on the current stream."""
+    c = _workload("circle1000")
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    r = vr.build(pts, c.thr)
+    for _ in range(2):
+        vr.tetra_counts(r)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        cnt = vr.tetra_counts(r)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
+    total = int(cnt.sum().item())
+    r.free()
+    return {"ms_per_call": round(ms, 5), "tetrahedra": total, "tetrahedra_per_s": total / (ms * 1e-3)}
+
+
 def _pairs_dim0(vr, torch, reps=20):
     """Dimension-0 persistence pairs of the circle1000 build: a (min, max)
     closure of the padded n x n rank matrix (2 * ld^3 integer min/max
@@ -563,7 +584,8 @@ def main():
         return
     if args.workload == "pairs0":  # pairs of circle1000 alone (profiling)
         print(json.dumps({"workload": "pairs_dim0_circle1000", **_pairs_dim0(vr, torch, reps=args.steps),
-                          "apparent_dim1": _apparent(vr, torch, reps=args.steps)}), flush=True)
+                          "apparent_dim1": _apparent(vr, torch, reps=args.steps),
+                          "tetra_counts": _tetra(vr, torch, reps=args.steps)}), flush=True)
         return
     if args.workload == "schur16384":  # the F2 product and sum alone (profiling)
         print(json.dumps({"workload": "schur_f2_16384", **_schur(vr, torch, reps=args.steps)}), flush=True)
@@ -614,6 +636,7 @@ def main():
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
         extra["pairs_dim1_apparent_circle1000"] = _apparent(vr, torch)
+        extra["tetra_counts_circle1000"] = _tetra(vr, torch)
         extra["schur_f2_16384"] = _schur(vr, torch)
         extra["circle1000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr)
         extra["circle1000_event_timed"] = _event_median(vr, torch, pts, cloud.thr)
