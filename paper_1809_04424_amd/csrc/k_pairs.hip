@@ -254,46 +254,53 @@ extern "C" VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_
 // Tetrahedra (dimension 3) per largest edge.  Work-group g takes edge r:
 // the vertices x joined to both ends by older edges (D[i][x] < r and
 // D[j][x] < r; the ends themselves fail one test, D[i][j] = r), compacted
-// into LDS, then the pairs of them joined by an older edge.  D as for the
-// pairs of dimension 0 (ranks, +inf off the edges, -1 on the diagonal).
+// into LDS in ascending order, then the pairs of them joined by an older
+// edge: wave w takes the vertices a = w, w+4, ... and its lanes read the
+// entries of row L[a] for the later vertices together (ascending, so nearby
+// addresses).  D as for the pairs of dimension 0 (ranks, +inf off the
+// edges, -1 on the diagonal).
 __global__ void __launch_bounds__(PD_BLOCK) k_tet_count(const int32_t *D, int64_t ld, int64_t n, const int32_t *ij,
                                                        int64_t K, long long *counts) {
     __shared__ uint16_t L[VR_MAX_POINTS];
-    __shared__ uint32_t m_s;
+    __shared__ uint32_t wc[PD_BLOCK / 64];
     __shared__ unsigned long long tot[PD_BLOCK / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int64_t r = blockIdx.x; r < K; r += gridDim.x) {
         const int64_t i = ij[2 * r], j = ij[2 * r + 1];
-        if (t == 0) m_s = 0;
-        __syncthreads();
-        if (i >= 0 && j >= 0 && i < n && j < n)
-            for (int64_t x0 = 0; x0 < n; x0 += PD_BLOCK) {
-                const int64_t x = x0 + t;
-                const bool in = x < n && D[i * ld + x] < r && D[j * ld + x] < r;
-                const unsigned long long b = __ballot(in);
-                uint32_t base = 0;
-                if (lane == 0 && b) base = atomicAdd(&m_s, (uint32_t)__popcll(b));
-                base = __shfl(base, 0, 64);
-                if (in) L[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] =
-                    (uint16_t)x;
+        const bool ok = i >= 0 && j >= 0 && i < n && j < n;  // always for a library result
+        uint32_t m = 0;
+        for (int64_t x0 = 0; x0 < n; x0 += PD_BLOCK) {
+            const int64_t x = x0 + t;
+            const bool in = ok && x < n && D[i * ld + x] < r && D[j * ld + x] < r;
+            const unsigned long long b = __ballot(in);
+            if (lane == 0) wc[wv] = (uint32_t)__popcll(b);
+            __syncthreads();
+            uint32_t base = m, chunk = 0;
+#pragma unroll
+            for (int w = 0; w < PD_BLOCK / 64; w++) {
+                if (w < wv) base += wc[w];
+                chunk += wc[w];
             }
-        __syncthreads();
-        const uint32_t m = m_s;
+            if (in) L[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] =
+                (uint16_t)x;
+            m += chunk;
+            __syncthreads();  // wc is rewritten by the next chunk
+        }
         unsigned long long c = 0;
-        for (uint32_t a = t; a < m; a += PD_BLOCK) {
+        for (uint32_t a = wv; a + 1 < m; a += PD_BLOCK / 64) {
             const int32_t *row = D + (int64_t)L[a] * ld;
-            for (uint32_t b2 = a + 1; b2 < m; b2++) c += row[L[b2]] < r ? 1ull : 0ull;
+            for (uint32_t b2 = a + 1 + lane; b2 < m; b2 += 64) c += row[L[b2]] < r ? 1ull : 0ull;
         }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
         if (lane == 0) tot[wv] = c;
         __syncthreads();
         if (t == 0) {
-            unsigned long long s = 0;
-            for (int w = 0; w < PD_BLOCK / 64; w++) s += tot[w];
-            counts[r] = (long long)s;
+            unsigned long long s2 = 0;
+            for (int w = 0; w < PD_BLOCK / 64; w++) s2 += tot[w];
+            counts[r] = (long long)s2;
         }
-        __syncthreads();  // m_s, L and tot are reused by the next edge
+        __syncthreads();  // L and tot are reused by the next edge
     }
 }
 
