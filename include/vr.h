@@ -296,7 +296,7 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  *          edge is edge r.
  * Enqueued on `stream`; scratch of 4 n^2 bytes from the library's cache.
  * VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
-VR_API int vr_tetra_counts(const vr_result *res, long long *counts, void *stream);
+VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream);
 
 /* The F2 sparse product and sum of the Schur complement step (Section 4.6):
  * S = D + C E mod 2, where C is m x k, E is k x n and D is m x n, all in
@@ -334,7 +334,7 @@ VR_API int64_t vr_trim(void);
 /* Static description of a status code. */
 VR_API const char *vr_status_string(int status);
 
-/* Library version, e.g. 120 for 0.1.2. */
+/* Library version, e.g. 130 for 0.1.3. */
 VR_API int vr_version(void);
 
 #ifdef __cplusplus

@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(PD_BLOCK) k_tet_count(const int32_t *D, int64_
     }
 }
 
-extern "C" VR_API int vr_tetra_counts(const vr_result *res, long long *counts, void *stream) {
+extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream) {
     if (!res) return VR_EINVAL;
     const int64_t n = res->n_vertices, K = res->n_edges;
     if (n < 0 || K < 0 || n > VR_MAX_POINTS) return VR_EINVAL;
@@ -316,7 +316,7 @@ extern "C" VR_API int vr_tetra_counts(const vr_result *res, long long *counts, v
     hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, D, n);
     hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, D, n, (const int32_t *)res->edge_ij, K, n);
     hipLaunchKernelGGL(k_tet_count, dim3((unsigned)(K < 65536 ? K : 65536)), dim3(PD_BLOCK), 0, s, (const int32_t *)D,
-                       n, n, (const int32_t *)res->edge_ij, K, counts);
+                       n, n, (const int32_t *)res->edge_ij, K, (long long *)counts);
     const hipError_t e = hipGetLastError();
     cache_put(D, s);
     return e == hipSuccess ? VR_OK : VR_EHIP;

@@ -958,7 +958,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
 
 extern "C" {
 
-int vr_version(void) { return 120; }
+int vr_version(void) { return 130; }
 
 const char *vr_status_string(int status) {
     switch (status) {
