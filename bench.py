@@ -7,7 +7,14 @@ output) of the headline workload: 1000 points on a noisy circle in R^3
 Inputs are resident in HBM before the timed region; outputs stay on the
 device.  The metric is filtered simplices per second, n + K + T per build.
 
-Prints ONE JSON line.  Only N = 1 GPU is supported.
+Prints ONE JSON line.  Only N = 1 GPU is supported.  Under "extra" the
+line also carries side measurements: the 4000-point R^64 mixture, the
+512-cloud batch, a Poisson request stream, a 1088 x 1088 Hamming matrix
+(dissimilarity input), the per-column order of a 2000 x 1999 array, the
+pairs of dimension 0 and the apparent pairs of dimension 1, tetrahedra
+counts, the F2 product and sum of 16384 x 16384 sparse matrices, one
+end-to-end figure with the outputs copied to the host, and event-timed
+single builds.  --workload runs one of them alone.
 """
 from __future__ import annotations
 
