@@ -104,7 +104,8 @@ def test_pairs_dim0_largest_point_count(orc):
 
 
 def test_pairs_dim0_of_batch_items_and_matrix_builds(orc):
-    """Any result works: the clouds of a batch, and a dissimilarity-matrix build."""
+    """Any result works: the clouds of a batch (pairs of both dimensions and
+    tetrahedra), and a dissimilarity-matrix build."""
     import torch
 
     import paper_1809_04424_amd as vr
@@ -114,9 +115,18 @@ def test_pairs_dim0_of_batch_items_and_matrix_builds(orc):
     b = vr.build_batch([torch.from_numpy(p).to("cuda:0") for p in clouds], thr)
     for p, item in zip(clouds, b):
         e_low, death = vr.pairs_dim0(item)
+        tet = vr.tetra_counts(item)
+        app = vr.pairs_dim1_apparent(item)
         torch.cuda.synchronize()
-        f = orc.build(p, thr, maxdim=1)
+        f = orc.build(p, thr)
         assert np.array_equal(e_low.cpu().numpy().astype(np.int64), orc.reduce(f, "cohomology").e_low)
+        assert np.array_equal(tet.cpu().numpy(), orc.tetra_counts(f))
+        want = np.full(f.K, -1, np.int64)
+        if f.T:
+            v = f.tris[:, 0]
+            first = np.nonzero(np.r_[True, v[1:] != v[:-1]])[0]
+            want[v[first]] = first
+        assert np.array_equal(app.cpu().numpy().astype(np.int64), want)
     b.free()
     M = workloads.hamming_matrix(61, 300)
     r = vr.build_matrix(torch.from_numpy(M).to("cuda:0"), ("fraction", 5, 100))
