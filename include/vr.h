@@ -294,6 +294,9 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  * res:     a single build's result (edges on the device, rank order).
  * counts:  device, K int64, caller-owned: the tetrahedra whose largest
  *          edge is edge r.
+ * Work: two rank rows per edge (K n reads), then, per edge, the pairs of
+ * its m common older neighbours (m^2 / 2): milliseconds for a thousand
+ * points, far longer near the largest n and K.
  * Enqueued on `stream`; scratch of 4 n^2 bytes from the library's cache.
  * VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
 VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream);
