@@ -446,3 +446,21 @@ def tetra_counts(f: Filtration) -> np.ndarray:
         sub = R[np.ix_(low, low)]
         out[r] = int(np.count_nonzero(np.triu((sub >= 0) & (sub < r), 1)))
     return out
+
+
+def tetra_list(f: Filtration) -> np.ndarray:
+    """Every tetrahedron as a row (value, a, b, c, d), a < b < c < d, value =
+    its largest edge rank, sorted by (value, a, b, c, d): the filtration
+    order one dimension up."""
+    R = np.asarray(f.R, np.int64)
+    rows = []
+    for r in range(f.K):
+        i, j = int(f.ei[r]), int(f.ej[r])
+        low = np.nonzero((R[i] >= 0) & (R[i] < r) & (R[j] >= 0) & (R[j] < r))[0]
+        for x in range(len(low)):
+            for y in range(x + 1, len(low)):
+                k, l = int(low[x]), int(low[y])
+                if 0 <= R[k, l] < r:
+                    rows.append((r,) + tuple(sorted((i, j, k, l))))
+    out = np.array(sorted(rows), np.int64).reshape(-1, 5)
+    return out

@@ -559,3 +559,23 @@ def test_tetra_counts_full_threshold_closed_form(orc, n):
     c = workloads.uniform_cloud(20 + n, n, 3)
     f = orc.build(c.points, ("full", 0, 1), list_triangles=False)
     assert int(orc.tetra_counts(f).sum()) == math.comb(n, 4)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c.name for c in CASES])
+def test_tetra_list_matches_bruteforce(orc, case):
+    """The listed tetrahedra are exactly the 4-subsets with six kept edges,
+    valued at their largest edge, in (value, vertices) order."""
+    import itertools
+
+    c = CASES[case]
+    f = orc.build(c.points, c.thr, list_triangles=False)
+    got = orc.tetra_list(f)
+    kept, rank, _, _ = bf.filtration(c.points, _K_of(c.thr))
+    want = []
+    for quad in itertools.combinations(range(len(c.points)), 4):
+        rs = [rank.get(e) for e in itertools.combinations(quad, 2)]
+        if all(x is not None for x in rs):
+            want.append((max(rs),) + quad)
+    assert [tuple(r) for r in got] == sorted(want)
+    assert np.array_equal(np.bincount(got[:, 0], minlength=f.K)[: f.K] if len(got) else np.zeros(f.K, int),
+                          orc.tetra_counts(f))
