@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_tetra_counts", "vr_blockprodsum_count", "vr_blockprodsum_write",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -121,6 +121,11 @@ def lib():
         L.vr_pairs_dim1_apparent.restype = ctypes.c_int
         L.vr_tetra_counts.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
         L.vr_tetra_counts.restype = ctypes.c_int
+        L.vr_tetra_offsets.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_tetra_offsets.restype = ctypes.c_int
+        L.vr_tetra_write.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        L.vr_tetra_write.restype = ctypes.c_int
         vp, i64 = ctypes.c_void_p, ctypes.c_int64
         L.vr_blockprodsum_count.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.vr_blockprodsum_count.restype = ctypes.c_int
@@ -665,3 +670,28 @@ def tetra_counts(result):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return out
+
+
+def tetrahedra(result):
+    """The tetrahedra of a build in filtration order: (offsets, keys) device
+    tensors; offsets int64 (K + 1,) (offsets[r] = the first of value r),
+    keys int64 (T3, 2) rows (value, a<<39 | b<<26 | c<<13 | d), a<b<c<d."""
+    import torch
+
+    L = lib()
+    n, K, T = result.counts
+    dev = result._device
+    off = torch.empty(K + 1, dtype=torch.int64, device=dev)
+    r = VrResult(n, K, T, result._p_ij, result._p_q, result._p_tri)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    with torch.cuda.device(dev):
+        rc = L.vr_tetra_offsets(ctypes.byref(r), ctypes.c_void_p(off.data_ptr()), stream)
+        if rc != VR_OK:
+            raise VrError(rc, status_string(rc))
+        total = int(off[-1].item())
+        keys = torch.empty((max(total, 1), 2), dtype=torch.int64, device=dev)
+        rc = L.vr_tetra_write(ctypes.byref(r), ctypes.c_void_p(off.data_ptr()), total,
+                              ctypes.c_void_p(keys.data_ptr()), stream)
+        if rc != VR_OK:
+            raise VrError(rc, status_string(rc))
+    return off, keys[:total]

@@ -304,6 +304,183 @@ __global__ void __launch_bounds__(PD_BLOCK) k_tet_count(const int32_t *D, int64_
     }
 }
 
+extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream);
+
+// Tetrahedra written in filtration order.  The group of edge r starts at
+// off[r] (an exclusive scan of the counts).  Within it the tetrahedra
+// {i, j, k, l} run in lexicographic order of their sorted vertices, which
+// for a fixed pair i < j is the lexicographic order of (k, l), k < l: row
+// a of the common neighbours L (ascending) holds the pairs (L[a], L[b]),
+// b > a, so the rows are counted, scanned in LDS, and each wave writes its
+// rows' pairs in order through a ballot.  Key of a tetrahedron: two words,
+// its value r and a<<39 | b<<26 | c<<13 | d.
+__global__ void __launch_bounds__(PD_BLOCK) k_tet_write(const int32_t *D, int64_t ld, int64_t n, const int32_t *ij,
+                                                       int64_t K, const long long *off, long long total,
+                                                       unsigned long long *keys) {
+    __shared__ uint16_t L[VR_MAX_POINTS];
+    __shared__ uint32_t rowc[VR_MAX_POINTS];
+    __shared__ uint32_t wc[PD_BLOCK / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int64_t r = blockIdx.x; r < K; r += gridDim.x) {
+        const int64_t i = ij[2 * r], j = ij[2 * r + 1];
+        const bool ok = i >= 0 && j >= 0 && i < n && j < n;
+        uint32_t m = 0;
+        for (int64_t x0 = 0; x0 < n; x0 += PD_BLOCK) {
+            const int64_t x = x0 + t;
+            const bool in = ok && x < n && D[i * ld + x] < r && D[j * ld + x] < r;
+            const unsigned long long b = __ballot(in);
+            if (lane == 0) wc[wv] = (uint32_t)__popcll(b);
+            __syncthreads();
+            uint32_t base = m, chunk = 0;
+#pragma unroll
+            for (int w = 0; w < PD_BLOCK / 64; w++) {
+                if (w < wv) base += wc[w];
+                chunk += wc[w];
+            }
+            if (in) L[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] =
+                (uint16_t)x;
+            m += chunk;
+            __syncthreads();
+        }
+        // pairs per row a
+        for (uint32_t a = wv; a < m; a += PD_BLOCK / 64) {
+            uint32_t c = 0;
+            const int32_t *row = D + (int64_t)L[a] * ld;
+            for (uint32_t b2 = a + 1 + lane; b2 < m; b2 += 64) c += row[L[b2]] < r ? 1u : 0u;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+            if (lane == 0) rowc[a] = c;
+        }
+        __syncthreads();
+        // exclusive scan of rowc[0..m) in place: thread t takes the rows
+        // [t*per, t*per + per), the work-group scans the threads' sums
+        {
+            const uint32_t per = (m + PD_BLOCK - 1) / PD_BLOCK;
+            const uint32_t a0 = min((uint32_t)t * per, m), a1 = min(a0 + per, m);
+            uint32_t own = 0;
+            for (uint32_t a = a0; a < a1; a++) own += rowc[a];
+            uint32_t incl = own;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            if (lane == 63) wc[wv] = incl;
+            __syncthreads();
+            uint32_t run = incl - own;
+#pragma unroll
+            for (int w = 0; w < PD_BLOCK / 64; w++)
+                if (w < wv) run += wc[w];
+            for (uint32_t a = a0; a < a1; a++) {
+                const uint32_t c = rowc[a];
+                rowc[a] = run;
+                run += c;
+            }
+            __syncthreads();
+        }
+        const long long g0 = off[r];
+        const uint32_t vi = (uint32_t)i, vj = (uint32_t)j;
+        for (uint32_t a = wv; a < m; a += PD_BLOCK / 64) {
+            const uint32_t k = L[a];
+            const int32_t *row = D + (int64_t)k * ld;
+            uint32_t pos = rowc[a];
+            for (uint32_t b0 = a + 1; b0 < m; b0 += 64) {
+                const uint32_t b2 = b0 + lane;
+                const bool in = b2 < m && row[L[b2]] < r;
+                const unsigned long long bm = __ballot(in);
+                if (in) {
+                    const uint32_t l = L[b2];
+                    // sorted merge of {i < j} and {k < l}
+                    uint32_t q[4];
+                    uint32_t x = 0, y = 0;
+                    const uint32_t s1[2] = {vi, vj}, s2[2] = {k, l};
+#pragma unroll
+                    for (int z = 0; z < 4; z++) {
+                        const bool take1 = y >= 2 || (x < 2 && s1[x < 2 ? x : 1] < s2[y < 2 ? y : 1]);
+                        q[z] = take1 ? s1[x < 2 ? x : 1] : s2[y < 2 ? y : 1];
+                        x += take1 ? 1 : 0;
+                        y += take1 ? 0 : 1;
+                    }
+                    const long long at = g0 + pos +
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0));
+                    if (at < total) {
+                        keys[2 * at] = (unsigned long long)r;
+                        keys[2 * at + 1] = ((unsigned long long)q[0] << 39) | ((unsigned long long)q[1] << 26) |
+                                           ((unsigned long long)q[2] << 13) | q[3];
+                    }
+                }
+                pos += (uint32_t)__popcll(bm);
+            }
+        }
+        __syncthreads();  // L and rowc are reused by the next edge
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_tet_scan(long long *v, int64_t K) {
+    // exclusive scan of v[0..K) into v[0..K], v[K] = total; one work-group
+    __shared__ long long wt[16];
+    __shared__ long long carry;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < K; base += 1024) {
+        const int64_t x = base + t;
+        const long long own = x < K ? v[x] : 0;
+        long long incl = own;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const long long y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        if (lane == 63) wt[wv] = incl;
+        __syncthreads();
+        long long pre = carry + incl - own, tot = 0;
+        for (int w = 0; w < 16; w++) {
+            if (w < wv) pre += wt[w];
+            tot += wt[w];
+        }
+        if (x < K) v[x] = pre;
+        __syncthreads();
+        if (t == 0) carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) v[K] = carry;
+}
+
+// offsets[0..K]: the first tetrahedron of each edge's group, offsets[K] = the
+// number of tetrahedra
+extern "C" VR_API int vr_tetra_offsets(const vr_result *res, int64_t *offsets, void *stream) {
+    if (!res || !offsets) return VR_EINVAL;
+    const int64_t K = res->n_edges;
+    const hipStream_t s = (hipStream_t)stream;
+    if (K > 0) {
+        const int st = vr_tetra_counts(res, offsets, stream);
+        if (st != VR_OK) return st;
+    }
+    hipLaunchKernelGGL(k_tet_scan, dim3(1), dim3(1024), 0, s, (long long *)offsets, K);
+    return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
+}
+
+extern "C" VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t total, uint64_t *keys,
+                                     void *stream) {
+    if (!res || !offsets || total < 0 || (total > 0 && !keys)) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges;
+    if (n < 0 || K < 0 || n > VR_MAX_POINTS) return VR_EINVAL;
+    if (K == 0 || total == 0) return VR_OK;
+    if (!res->edge_ij) return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    int32_t *D = (int32_t *)cache_get((size_t)n * (size_t)n * 4, s);
+    if (!D) return VR_ENOMEM;
+    hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, D, n);
+    hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, D, n, (const int32_t *)res->edge_ij, K, n);
+    hipLaunchKernelGGL(k_tet_write, dim3((unsigned)(K < 65536 ? K : 65536)), dim3(PD_BLOCK), 0, s, (const int32_t *)D,
+                       n, n, (const int32_t *)res->edge_ij, K, (const long long *)offsets, (long long)total,
+                       (unsigned long long *)keys);
+    const hipError_t e = hipGetLastError();
+    cache_put(D, s);
+    return e == hipSuccess ? VR_OK : VR_EHIP;
+}
+
 extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream) {
     if (!res) return VR_EINVAL;
     const int64_t n = res->n_vertices, K = res->n_edges;

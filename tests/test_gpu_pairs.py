@@ -214,3 +214,37 @@ def test_tetra_counts_full_threshold(n):
     assert int(got.sum().item()) == math.comb(n, 4)
     assert int(got[:3].sum().item()) == 0  # the first three edges close no tetrahedron
     r.free()
+
+
+LIST_CASES = [
+    ("circle120_p20", lambda: workloads.noisy_circle(seed=95, n=120).points, ("fraction", 20, 100)),
+    ("lattice_ties", lambda: workloads.lattice_cloud(6, 50, side=3).points, ("fraction", 40, 100)),
+    ("uniform_full40", lambda: workloads.uniform_cloud(96, 40, 3).points, ("full", 0, 1)),
+    ("uniform_sqdist", lambda: workloads.uniform_cloud(97, 90, 4).points, ("sqdist", 25000, 0)),
+    ("n4", lambda: workloads.uniform_cloud(98, 4, 2).points, ("full", 0, 1)),
+    ("n3", lambda: workloads.uniform_cloud(99, 3, 2).points, ("full", 0, 1)),
+]
+
+
+@pytest.mark.parametrize("name,gen,thr", LIST_CASES, ids=[c[0] for c in LIST_CASES])
+def test_tetrahedra_listed_in_order(orc, name, gen, thr):
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    pts = gen()
+    print(f"[gpu] tetrahedra {name}", flush=True)
+    f = orc.build(pts, thr, list_triangles=False)
+    r = vr.build(torch.from_numpy(np.ascontiguousarray(pts)).to("cuda:0"), thr)
+    off, keys = vr.tetrahedra(r)
+    off, keys = off.cpu().numpy(), keys.cpu().numpy().view(np.uint64)
+    r.free()
+    want = orc.tetra_list(f)
+    counts = orc.tetra_counts(f)
+    assert np.array_equal(off, np.r_[0, np.cumsum(counts)])
+    assert len(keys) == len(want)
+    if len(want):
+        m = np.uint64(0x1FFF)
+        got = np.stack([keys[:, 0], keys[:, 1] >> np.uint64(39), (keys[:, 1] >> np.uint64(26)) & m,
+                        (keys[:, 1] >> np.uint64(13)) & m, keys[:, 1] & m], axis=1).astype(np.int64)
+        assert np.array_equal(got, want)
