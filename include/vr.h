@@ -306,13 +306,15 @@ VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream);
  *   vr_tetra_offsets writes offsets (K + 1 int64, caller-owned device
  *     memory): offsets[r] = the first tetrahedron of value r, offsets[K] =
  *     their number T3;
- *   vr_tetra_write writes keys (2 T3 uint64, caller-owned): for the t-th
+ *   vr_tetra_write writes keys (2 T3 uint64, caller-owned, 16-byte
+ *     aligned): for the t-th
  *     tetrahedron keys[2t] = its value and keys[2t+1] = a<<39 | b<<26 |
  *     c<<13 | d with a < b < c < d.  `total` is offsets[K] as read back by
  *     the caller (nothing is written past it).
  * Both enqueued on `stream`, with scratch of 4 n^2 bytes from the library's
  * cache; the work is that of vr_tetra_counts, twice for the write.
- * VR_EINVAL for a null argument, total < 0, or n > VR_MAX_POINTS. */
+ * VR_EINVAL for a null argument, total < 0, misaligned keys, or
+ * n > VR_MAX_POINTS. */
 VR_API int vr_tetra_offsets(const vr_result *res, int64_t *offsets, void *stream);
 VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t total, uint64_t *keys, void *stream);
 

@@ -403,11 +403,11 @@ __global__ void __launch_bounds__(PD_BLOCK) k_tet_write(const int32_t *D, int64_
                     }
                     const long long at = g0 + pos +
                         __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0));
-                    if (at < total) {
-                        keys[2 * at] = (unsigned long long)r;
-                        keys[2 * at + 1] = ((unsigned long long)q[0] << 39) | ((unsigned long long)q[1] << 26) |
-                                           ((unsigned long long)q[2] << 13) | q[3];
-                    }
+                    if (at < total)  // one 16-byte store per tetrahedron
+                        *(ulonglong2 *)(keys + 2 * at) =
+                            make_ulonglong2((unsigned long long)r, ((unsigned long long)q[0] << 39) |
+                                                                       ((unsigned long long)q[1] << 26) |
+                                                                       ((unsigned long long)q[2] << 13) | q[3]);
                 }
                 pos += (uint32_t)__popcll(bm);
             }
@@ -423,9 +423,14 @@ __global__ void __launch_bounds__(1024) k_tet_scan(long long *v, int64_t K) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0) carry = 0;
     __syncthreads();
-    for (int64_t base = 0; base < K; base += 1024) {
-        const int64_t x = base + t;
-        const long long own = x < K ? v[x] : 0;
+    for (int64_t base = 0; base < K; base += 4096) {  // 4 consecutive values per thread
+        long long e[4], own = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t x = base + 4 * t + u;
+            e[u] = x < K ? v[x] : 0;
+            own += e[u];
+        }
         long long incl = own;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -439,7 +444,12 @@ __global__ void __launch_bounds__(1024) k_tet_scan(long long *v, int64_t K) {
             if (w < wv) pre += wt[w];
             tot += wt[w];
         }
-        if (x < K) v[x] = pre;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t x = base + 4 * t + u;
+            if (x < K) v[x] = pre;
+            pre += e[u];
+        }
         __syncthreads();
         if (t == 0) carry += tot;
         __syncthreads();
@@ -464,6 +474,7 @@ extern "C" VR_API int vr_tetra_offsets(const vr_result *res, int64_t *offsets, v
 extern "C" VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t total, uint64_t *keys,
                                      void *stream) {
     if (!res || !offsets || total < 0 || (total > 0 && !keys)) return VR_EINVAL;
+    if ((uintptr_t)keys % 16) return VR_EINVAL;  // keys are stored 16 bytes at a time
     const int64_t n = res->n_vertices, K = res->n_edges;
     if (n < 0 || K < 0 || n > VR_MAX_POINTS) return VR_EINVAL;
     if (K == 0 || total == 0) return VR_OK;
