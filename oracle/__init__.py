@@ -20,8 +20,8 @@ passage of arXiv:1809.04424 it follows:
 * triangles: every triple whose three edges are kept, valued at its largest
   edge rank, sorted by (value, i, j, k) (Section 2.1);
 * per-column ordering of a compressed-sparse-column array: the slot of every
-  entry when its column is sorted stably by value, by the original and by the
-  modified counting sort of Section 4.3;
+  entry when its column is sorted stably by value (Section 4.3), by sorting
+  each column's (value, entry) pairs;
 * tetrahedra: for every kept edge, the number whose largest edge it is
   (dimension 3, Section 2.1's rule one dimension up);
 * the F2 sparse product and sum S = D + C E of the Schur complement step,
@@ -72,8 +72,6 @@ def lib():
     L.or_kept_edges.restype = None
     L.or_count_triangles.argtypes = [i64, _I64P]
     L.or_count_triangles.restype = i64
-    L.or_count_triangles_full.argtypes = [i64]
-    L.or_count_triangles_full.restype = i64
     L.or_triangles.argtypes = [i64, _I64P, i64, _I64P]
     L.or_triangles.restype = i64
     L.or_triangles_per_value.argtypes = [i64, _I64P, i64, _I64P, _I64P, _I64P]
@@ -84,10 +82,14 @@ def lib():
     L.or_reduce_homology.restype = None
     L.or_reduce_cohomology.argtypes = [i64, i64, _I64P, _I64P, i64, _I64P, _I64P, _I64P]
     L.or_reduce_cohomology.restype = None
-    L.or_colorder_original.argtypes = [i64, _I64P, _I64P, i64, _I64P]
-    L.or_colorder_original.restype = ctypes.c_int
-    L.or_colorder_modified.argtypes = [i64, _I64P, _I64P, i64, _I64P]
-    L.or_colorder_modified.restype = ctypes.c_int
+    L.or_column_order.argtypes = [i64, _I64P, _I64P, _I64P]
+    L.or_column_order.restype = None
+    L.or_sqdist_mt.argtypes = [vp, i64, i64, ctypes.c_int, _I64P, ctypes.c_int]
+    L.or_sqdist_mt.restype = ctypes.c_int
+    L.or_triangles_by_value_count.argtypes = [i64, _I64P, _I64P, _I64P, i64, i64, _I64P, ctypes.c_int]
+    L.or_triangles_by_value_count.restype = i64
+    L.or_triangles_by_value_write.argtypes = [i64, _I64P, _I64P, _I64P, i64, i64, _I64P, _I64P, ctypes.c_int]
+    L.or_triangles_by_value_write.restype = None
     _LIB = L
     return L
 
@@ -177,7 +179,7 @@ def build_matrix(M, thr, maxdim: int = 2, list_triangles: bool = True) -> Filtra
     return _build_from_pairs(np.asarray(M).shape[0], matrix_pairs(M), thr, maxdim, list_triangles)
 
 
-def _build_from_pairs(n, q, thr, maxdim, list_triangles) -> Filtration:
+def _build_from_pairs(n, q, thr, maxdim, list_triangles, triangles=True) -> Filtration:
     L = lib()
     E = len(q)
     order = sortperm(q)
@@ -194,7 +196,7 @@ def _build_from_pairs(n, q, thr, maxdim, list_triangles) -> Filtration:
         L.or_rank_matrix(n, order if E else np.zeros(1, np.int64), K, R)
     T = 0
     tris = np.zeros((0, 4), np.int64)
-    if maxdim >= 2 and n >= 3:
+    if maxdim >= 2 and n >= 3 and triangles:
         if list_triangles:
             T = L.or_count_triangles(n, R)
             buf = np.zeros((max(T, 1), 4), np.int64)
@@ -208,8 +210,47 @@ def _build_from_pairs(n, q, thr, maxdim, list_triangles) -> Filtration:
                       R=R[: n * n].reshape(n, n) if n else R[:0].reshape(0, 0), tris=tris, T=int(T))
 
 
-def count_triangles_full(n: int) -> int:
-    return int(lib().or_count_triangles_full(n))
+def sqdist_mt(points, threads: int) -> np.ndarray:
+    """As sqdist, the rows of pairs split over `threads` host threads."""
+    p = _pts(points)
+    n, d = p.shape
+    E = n * (n - 1) // 2
+    q = np.zeros(max(E, 1), np.int64)
+    if lib().or_sqdist_mt(p.ctypes.data, n, d, DTYPE_CODE[p.dtype], q, int(threads)) < 0:
+        raise OverflowError("a squared distance does not fit in 63 bits")
+    return q[:E]
+
+
+def triangles_by_value(f: Filtration, r0: int = 0, r1: int | None = None, threads: int = 1) -> np.ndarray:
+    """(m, 4) rows (v, i, j, k) of the triangles whose value (largest edge
+    rank) v lies in [r0, r1), sorted by (v, i, j, k): for each value r, the
+    vertices joined to both ends of edge r by edges ranked below r (Section
+    2.1), sorted within the value; values split over `threads` host threads."""
+    r1 = f.K if r1 is None else r1
+    if not (0 <= r0 <= r1 <= f.K):
+        raise ValueError("value range outside [0, K]")
+    if r1 == r0 or f.n < 3:
+        return np.zeros((0, 4), np.int64)
+    L = lib()
+    R = np.ascontiguousarray(f.R.reshape(-1), dtype=np.int64)
+    cnt = np.zeros(r1 - r0, np.int64)
+    T = L.or_triangles_by_value_count(f.n, R, f.ei, f.ej, r0, r1, cnt, int(threads))
+    off = np.zeros(r1 - r0, np.int64)
+    np.cumsum(cnt[:-1], out=off[1:])
+    out = np.zeros((max(T, 1), 4), np.int64)
+    L.or_triangles_by_value_write(f.n, R, f.ei, f.ej, r0, r1, off, out.reshape(-1), int(threads))
+    return out[:T]
+
+
+def build_mt(points, thr, threads: int) -> Filtration:
+    """The whole front end as build(), with the distances (by rows of pairs)
+    and the triangles (by values) computed on `threads` host threads; the
+    outputs are identical to build()'s."""
+    p = _pts(points)
+    f = _build_from_pairs(p.shape[0], sqdist_mt(p, threads), thr, 2, False, triangles=False)
+    f.tris = triangles_by_value(f, threads=threads)
+    f.T = len(f.tris)
+    return f
 
 
 def triangles_per_value(f: Filtration) -> np.ndarray:
@@ -309,37 +350,16 @@ def _csc(colptr, v):
     return cp, vv
 
 
-def _colorder(fn, colptr, v, maxvalue):
-    cp, vv = _csc(colptr, v)
-    if maxvalue is None:
-        maxvalue = int(vv.max()) if len(vv) else 0
-    z = np.zeros(max(len(vv), 1), np.int64)
-    rc = fn(len(cp) - 1, cp, vv if len(vv) else np.zeros(1, np.int64), int(maxvalue), z)
-    if rc != 0:
-        raise ValueError("values must lie in 0..maxvalue")
-    return z[: len(vv)]
-
-
-def column_order_original(colptr, v, maxvalue=None) -> np.ndarray:
-    """Section 4.3, original version: z[i] = slot of entry i in its column
-    sorted stably by value (0-based), values in 0..maxvalue."""
-    return _colorder(lib().or_colorder_original, colptr, v, maxvalue)
-
-
-def column_order_modified(colptr, v, maxvalue=None) -> np.ndarray:
-    """Section 4.3, modified version (prefix sums over each column's own value
-    range only, counts cleared per range); same result as the original."""
-    return _colorder(lib().or_colorder_modified, colptr, v, maxvalue)
-
-
 def column_order(colptr, v) -> np.ndarray:
-    """The per-column order for any integer values: the modified counting
-    sort after replacing each value by its position among the distinct
-    values (an order-preserving relabelling keeps every comparison, hence
-    the order, and bounds the count array by the number of entries)."""
+    """Section 4.3, the per-column ordering: z[e] = the slot of entry e when
+    its column is sorted by value, equal values keeping their entry order
+    (column start + smaller entries + earlier equal entries).  Any integer
+    values; computed in the C library by sorting each column's (value, entry)
+    pairs."""
     cp, vv = _csc(colptr, v)
-    _, dense = np.unique(vv, return_inverse=True)
-    return column_order_modified(cp, dense.astype(np.int64).reshape(-1))
+    z = np.zeros(max(len(vv), 1), np.int64)
+    lib().or_column_order(len(cp) - 1, cp, vv if len(vv) else np.zeros(1, np.int64), z)
+    return z[: len(vv)]
 
 
 # --- F2 sparse product and sum (Section 4.6) -------------------------------

@@ -24,6 +24,7 @@
  *     columns known to be zero may be skipped.
  */
 #define _GNU_SOURCE
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -161,15 +162,6 @@ int64_t or_count_triangles(int64_t n, const int64_t *R) {
     return t;
 }
 
-/* Full-threshold triangle count C(n,3) without any rank matrix (for the
- * paper's "size of complex" figures): every triple is a triangle. */
-int64_t or_count_triangles_full(int64_t n) {
-    int64_t t = 0;
-    for (int64_t i = 0; i < n; i++)
-        for (int64_t j = i + 1; j < n; j++) t += n - 1 - j;
-    return t;
-}
-
 typedef struct { int64_t v, i, j, k; } tri_t;
 
 static int cmp_tri(const void *a, const void *b) {
@@ -240,6 +232,158 @@ int64_t or_triangles_of_value(int64_t n, const int64_t *R, int64_t a, int64_t b,
     }
     if (t <= cap) qsort(buf, (size_t)t, sizeof(tri_t), cmp_tri);
     return t;
+}
+
+static void sort3(int64_t *a, int64_t *b, int64_t *c) {
+    int64_t t;
+    if (*a > *b) { t = *a; *a = *b; *b = t; }
+    if (*b > *c) { t = *b; *b = *c; *c = t; }
+    if (*a > *b) { t = *a; *a = *b; *b = t; }
+}
+
+/* ================= the same steps on several host threads ================= */
+/*
+ * Threads here only split independent units of work whose results have a
+ * fixed place in the output (a row of pairs, the triangles of one value), so
+ * every output is byte-identical to the single-threaded routine above.  Work
+ * is handed out in blocks from a shared counter, so threads that draw cheap
+ * blocks take more of them.
+ */
+typedef struct {
+    int64_t next;          /* next unclaimed unit */
+    pthread_mutex_t lock;
+} or_queue_t;
+
+static int64_t queue_take(or_queue_t *qu, int64_t block, int64_t end, int64_t *stop) {
+    pthread_mutex_lock(&qu->lock);
+    int64_t a = qu->next;
+    qu->next = a + block < end ? a + block : end;
+    *stop = qu->next;
+    pthread_mutex_unlock(&qu->lock);
+    return a;
+}
+
+static void run_threads(int nthreads, void *(*fn)(void *), void *arg) {
+    if (nthreads < 1) nthreads = 1;
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, fn, arg);
+    fn(arg);
+    for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
+    free(th);
+}
+
+/* Squared distances of all pairs, as or_sqdist, rows i split over threads:
+ * the pairs (i, j > i) of row i start at i n - i (i + 1) / 2. */
+typedef struct {
+    or_queue_t qu;
+    const void *pts;
+    int64_t n, d;
+    int dtype;
+    int64_t *q;
+    int bad;
+} sqdist_job_t;
+
+static void *sqdist_worker(void *arg) {
+    sqdist_job_t *J = (sqdist_job_t *)arg;
+    int bad = 0;
+    for (;;) {
+        int64_t stop, i0 = queue_take(&J->qu, 8, J->n, &stop);
+        if (i0 >= J->n) break;
+        for (int64_t i = i0; i < stop; i++) {
+            int64_t e = i * J->n - i * (i + 1) / 2;
+            for (int64_t j = i + 1; j < J->n; j++) {
+                __int128 s = 0;
+                for (int64_t c = 0; c < J->d; c++) {
+                    __int128 diff = (__int128)coord(J->pts, J->dtype, i * J->d + c) -
+                                    coord(J->pts, J->dtype, j * J->d + c);
+                    s += diff * diff;
+                }
+                if (s > (__int128)INT64_MAX) { bad = 1; s = INT64_MAX; }
+                J->q[e++] = (int64_t)s;
+            }
+        }
+    }
+    if (bad) {
+        pthread_mutex_lock(&J->qu.lock);
+        J->bad = 1;
+        pthread_mutex_unlock(&J->qu.lock);
+    }
+    return NULL;
+}
+
+/* Returns 0, or -1 if some q does not fit in 63 bits (as or_sqdist). */
+int or_sqdist_mt(const void *pts, int64_t n, int64_t d, int dtype, int64_t *q, int nthreads) {
+    sqdist_job_t J = {{0, PTHREAD_MUTEX_INITIALIZER}, pts, n, d, dtype, q, 0};
+    run_threads(nthreads, sqdist_worker, &J);
+    return J.bad ? -1 : 0;
+}
+
+/*
+ * Triangles by value (Section 2.1: a triangle enters with its largest edge).
+ * The triangles of value r are the {a, b, k} with edge r = {a, b} and both
+ * {a, k} and {b, k} kept with ranks below r.  For the values r0 <= r < r1:
+ * count[r - r0] = how many (pass 1), then, at the offsets the caller derives
+ * from those counts, the rows (r, i, j, k), i < j < k, of each value sorted
+ * by (i, j, k) with qsort (pass 2).  Concatenated over the values in order,
+ * this is the whole triangle list sorted by (value, i, j, k).
+ */
+typedef struct {
+    or_queue_t qu;
+    int64_t n;
+    const int64_t *R, *ei, *ej;
+    int64_t r0, r1;
+    int64_t *count;        /* pass 1 output, or pass 2 input (offsets) */
+    const int64_t *offset; /* NULL in pass 1 */
+    int64_t *out;
+} byvalue_job_t;
+
+static void *byvalue_worker(void *arg) {
+    byvalue_job_t *J = (byvalue_job_t *)arg;
+    const int64_t n = J->n, *R = J->R;
+    for (;;) {
+        int64_t stop, v0 = queue_take(&J->qu, 256, J->r1, &stop);
+        if (v0 >= J->r1) break;
+        for (int64_t r = v0; r < stop; r++) {
+            const int64_t a = J->ei[r], b = J->ej[r];
+            const int64_t *Ra = R + a * n, *Rb = R + b * n;
+            if (!J->offset) {
+                int64_t c = 0;
+                for (int64_t k = 0; k < n; k++)
+                    if (k != a && k != b && Ra[k] >= 0 && Ra[k] < r && Rb[k] >= 0 && Rb[k] < r) c++;
+                J->count[r - J->r0] = c;
+                continue;
+            }
+            tri_t *dst = (tri_t *)J->out + J->offset[r - J->r0];
+            int64_t m = 0;
+            for (int64_t k = 0; k < n; k++) {
+                if (k == a || k == b || Ra[k] < 0 || Ra[k] >= r || Rb[k] < 0 || Rb[k] >= r) continue;
+                int64_t s0 = a, s1 = b, s2 = k;
+                sort3(&s0, &s1, &s2);
+                dst[m].v = r; dst[m].i = s0; dst[m].j = s1; dst[m].k = s2;
+                m++;
+            }
+            qsort(dst, (size_t)m, sizeof(tri_t), cmp_tri);
+        }
+    }
+    return NULL;
+}
+
+/* Pass 1: count[r - r0] for r0 <= r < r1.  Returns their sum. */
+int64_t or_triangles_by_value_count(int64_t n, const int64_t *R, const int64_t *ei, const int64_t *ej, int64_t r0,
+                                    int64_t r1, int64_t *count, int nthreads) {
+    byvalue_job_t J = {{r0, PTHREAD_MUTEX_INITIALIZER}, n, R, ei, ej, r0, r1, count, NULL, NULL};
+    run_threads(nthreads, byvalue_worker, &J);
+    int64_t t = 0;
+    for (int64_t r = r0; r < r1; r++) t += count[r - r0];
+    return t;
+}
+
+/* Pass 2: rows (v, i, j, k) into out, value r's at out row offset[r - r0]
+ * (offset = exclusive prefix sums of pass 1's counts). */
+void or_triangles_by_value_write(int64_t n, const int64_t *R, const int64_t *ei, const int64_t *ej, int64_t r0,
+                                 int64_t r1, const int64_t *offset, int64_t *out, int nthreads) {
+    byvalue_job_t J = {{r0, PTHREAD_MUTEX_INITIALIZER}, n, R, ei, ej, r0, r1, NULL, offset, out};
+    run_threads(nthreads, byvalue_worker, &J);
 }
 
 /* ======================= F2 column reduction ======================= */
@@ -330,13 +474,6 @@ static int64_t tri_index(const tri_t *tris, int64_t T, int64_t v, int64_t i, int
         if (c < 0) lo = mid + 1; else hi = mid;
     }
     return -1;
-}
-
-static void sort3(int64_t *a, int64_t *b, int64_t *c) {
-    int64_t t;
-    if (*a > *b) { t = *a; *a = *b; *b = t; }
-    if (*b > *c) { t = *b; *b = *c; *c = t; }
-    if (*a > *b) { t = *a; *a = *b; *b = t; }
 }
 
 /*
@@ -465,79 +602,40 @@ void or_reduce_cohomology(int64_t n, int64_t K, const int64_t *ei, const int64_t
 }
 
 /*
- * Section 4.3 (redundant calculations): the per-column ordering of integers
- * of a compressed-sparse-column array.  Column j holds the entries
- * colptr[j] .. colptr[j+1]-1 with integer values v in 0..maxvalue; z[i] is
- * the slot entry i takes when its column is sorted by value, equal values
- * keeping their order (a stable counting sort per column).  Indices here are
- * 0-based where the paper's are 1-based.
+ * Section 4.3 (redundant calculations): the per-column ordering of the
+ * integers of a compressed-sparse-column array.  Column c holds the entries
+ * colptr[c] .. colptr[c+1]-1.  By definition entry e of column c goes to
+ * slot colptr[c] + (the entries of c with a smaller value) + (the entries of
+ * c before e with the same value): its place once the column is sorted by
+ * value with equal values kept in entry order.
  *
- * The original version clears one count per possible value for every column,
- * counts the column's values, takes prefix sums over the whole value range
- * into a second array starting at the column's first slot, and hands out the
- * slots in entry order.
- *
- * The modified version keeps a single count array, cleared once: it counts
- * the column's values, finds the column's smallest and largest value, turns
- * the counts of that range into starting slots in place, hands out the
- * slots, and clears only that range again.  The paper's version reads the
- * first value of a column without checking that the column has entries; an
- * empty column is skipped here.
- *
- * Both return 0, or -1 when a value lies outside 0..maxvalue (the modified
- * version takes maxvalue only to size its count array).
+ * Computed as exactly that sort: the column's (value, entry index) pairs
+ * are sorted with the C library's qsort under the order value first, entry
+ * index second (no two pairs compare equal, so qsort's lack of stability
+ * does not matter), and the pair sorted to position t gives its entry the
+ * slot colptr[c] + t.  Any integer values are accepted.
  */
-static int values_in_range(int64_t n, const int64_t *v, int64_t maxvalue) {
-    for (int64_t i = 0; i < n; i++)
-        if (v[i] < 0 || v[i] > maxvalue) return 0;
-    return 1;
+typedef struct { int64_t value, entry; } ventry_t;
+
+static int cmp_value_then_entry(const void *a, const void *b) {
+    const ventry_t *x = (const ventry_t *)a, *y = (const ventry_t *)b;
+    if (x->value != y->value) return x->value < y->value ? -1 : 1;
+    return (x->entry > y->entry) - (x->entry < y->entry);
 }
 
-int or_colorder_original(int64_t ncols, const int64_t *colptr, const int64_t *v, int64_t maxvalue,
-                         int64_t *z) {
-    if (!values_in_range(colptr[ncols], v, maxvalue)) return -1;
-    int64_t *x = (int64_t *)malloc(sizeof(int64_t) * (size_t)(maxvalue + 1));
-    int64_t *y = (int64_t *)malloc(sizeof(int64_t) * (size_t)(maxvalue + 2));
-    for (int64_t j = 0; j < ncols; j++) {
-        for (int64_t u = 0; u <= maxvalue; u++) x[u] = 0;
-        for (int64_t i = colptr[j]; i < colptr[j + 1]; i++) x[v[i]] += 1;
-        y[0] = colptr[j];
-        for (int64_t u = 0; u <= maxvalue; u++) y[u + 1] = y[u] + x[u];
-        for (int64_t i = colptr[j]; i < colptr[j + 1]; i++) {
-            z[i] = y[v[i]];
-            y[v[i]] += 1;
+void or_column_order(int64_t ncols, const int64_t *colptr, const int64_t *v, int64_t *z) {
+    int64_t longest = 0;
+    for (int64_t c = 0; c < ncols; c++)
+        if (colptr[c + 1] - colptr[c] > longest) longest = colptr[c + 1] - colptr[c];
+    ventry_t *col = (ventry_t *)malloc(sizeof(ventry_t) * (size_t)(longest > 0 ? longest : 1));
+    for (int64_t c = 0; c < ncols; c++) {
+        const int64_t start = colptr[c], len = colptr[c + 1] - colptr[c];
+        for (int64_t t = 0; t < len; t++) {
+            col[t].value = v[start + t];
+            col[t].entry = start + t;
         }
+        qsort(col, (size_t)len, sizeof(ventry_t), cmp_value_then_entry);
+        for (int64_t t = 0; t < len; t++) z[col[t].entry] = start + t;
     }
-    free(y);
-    free(x);
-    return 0;
-}
-
-int or_colorder_modified(int64_t ncols, const int64_t *colptr, const int64_t *v, int64_t maxvalue,
-                         int64_t *z) {
-    if (!values_in_range(colptr[ncols], v, maxvalue)) return -1;
-    int64_t *x = (int64_t *)calloc((size_t)(maxvalue + 1), sizeof(int64_t));
-    for (int64_t j = 0; j < ncols; j++) {
-        int64_t first = colptr[j], end = colptr[j + 1];
-        if (first == end) continue;
-        for (int64_t i = first; i < end; i++) x[v[i]] += 1;
-        int64_t lo = v[first], hi = v[first];
-        for (int64_t i = first + 1; i < end; i++) {
-            if (v[i] > hi) hi = v[i];
-            else if (v[i] < lo) lo = v[i];
-        }
-        int64_t next = first;
-        for (int64_t u = lo; u <= hi; u++) {
-            int64_t c = x[u];
-            x[u] = next;
-            next += c;
-        }
-        for (int64_t i = first; i < end; i++) {
-            z[i] = x[v[i]];
-            x[v[i]] += 1;
-        }
-        for (int64_t u = lo; u <= hi; u++) x[u] = 0;
-    }
-    free(x);
-    return 0;
+    free(col);
 }

@@ -228,6 +228,45 @@ def test_reduction_matches_bruteforce_persistent_betti(orc, case, method):
         assert got[k] == beta[k], f"dimension {k}"
 
 
+@pytest.mark.parametrize("case", [
+    workloads.uniform_cloud(21, 6, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(22, 7, 2, thr=("fraction", 70, 100)),
+    workloads.lattice_cloud(23, 7, side=3, thr=("fraction", 60, 100)),
+    workloads.uniform_cloud(24, 6, 3, thr=("count", 9, 1)),
+    workloads.uniform_cloud(25, 8, 2, thr=("fraction", 45, 100)),
+], ids=lambda c: c.name)
+def test_barcode_reproduces_persistent_betti_by_value(orc, case):
+    """The barcode in filtration values (vertices -1, edge r at r, a triangle
+    at its largest edge rank): for every pair of values s <= t, the bars of
+    dimension k with birth <= s and death > t number rank(H_k(X_s) -> H_k(X_t)),
+    X_s being every simplex of value <= s (brute force from F2 ranks).  A
+    bar read backwards (birth after death) is never counted, so a swapped
+    orientation fails; zero-length bars are absent and every bar is
+    born strictly before it dies."""
+    f = orc.build(case.points, case.thr)
+    bars = orc.barcode(f, orc.reduce(f, "cohomology"))
+    assert all(b < d for _, b, d in bars)
+    kept = list(zip(f.ei.tolist(), f.ej.tolist()))
+    tris = [tuple(t) for t in f.tris.tolist()]
+    order, beta = bf.persistent_betti(f.n, kept, tris)
+    # last total-order index of a simplex of value <= s
+    value_of = {("e", e): r for r, e in enumerate(kept)}
+    value_of.update({("t", tuple(t[1:])): t[0] for t in tris})
+    last = {-1: f.n - 1}
+    for p_, (kind, verts) in enumerate(order):
+        if kind != "v":
+            last[value_of[(kind, verts)]] = p_
+    values = sorted(last)
+    assert values == list(range(-1, f.K))
+    for k in (0, 1, 2):
+        for s in values:
+            for t in values:
+                if t < s:
+                    continue
+                alive = sum(1 for dim, b, d in bars if dim == k and b <= s and d > t)
+                assert alive == beta[k][(last[s], last[t])], (k, s, t)
+
+
 @pytest.mark.parametrize("seed,thr", [(31, ("fraction", 15, 100)), (32, ("full", 0, 1)), (33, ("fraction", 40, 100))])
 def test_homology_and_cohomology_give_same_pivots(orc, seed, thr):
     """Section 2.2.2: the anti-transpose yields the same pivot pairs."""
@@ -362,18 +401,15 @@ def test_column_order_matches_paper_sortperm_example(orc):
     for slot, e in enumerate(perm):
         inv[e] = slot
     v = rows["v"]
-    for fn in (orc.column_order_original, orc.column_order_modified):
-        assert list(fn([0, len(v)], v)) == inv
+    assert list(orc.column_order([0, len(v)], v)) == inv
 
 
 @pytest.mark.parametrize("seed", range(8))
-def test_column_order_versions_agree_and_match_bruteforce(orc, seed):
-    """Original vs modified (the paper's differential pair) and the
-    definition by counting, on ragged columns with empties and ties."""
+def test_column_order_matches_bruteforce(orc, seed):
+    """The definition by counting (smaller entries plus earlier equal
+    entries), in pure Python, on ragged columns with empties and ties."""
     colptr, v = workloads.csc_columns(seed, ncols=40, mean_len=6, maxvalue=[1, 3, 9, 50][seed % 4])
-    a = orc.column_order_original(colptr, v)
-    b = orc.column_order_modified(colptr, v)
-    assert np.array_equal(a, b)
+    a = orc.column_order(colptr, v)
     assert list(a) == bf.column_order(colptr, [int(x) for x in v])
 
 
@@ -382,13 +418,12 @@ def test_column_order_equals_stable_library_sort(orc, seed):
     """Per column, the inverse of numpy's stable argsort."""
     colptr, v = workloads.csc_columns(100 + seed, ncols=300, mean_len=40, maxvalue=[0, 5, 1000, 2**20][seed],
                                       long_cols=2, long_len=3000)
-    z = orc.column_order_modified(colptr, v)
+    z = orc.column_order(colptr, v)
     ref = np.empty_like(z)
     for j in range(len(colptr) - 1):
         a, b = colptr[j], colptr[j + 1]
         ref[a + np.argsort(v[a:b], kind="stable")] = np.arange(a, b)
     assert np.array_equal(z, ref)
-    assert np.array_equal(orc.column_order_original(colptr, v), ref)
 
 
 def test_column_order_invariants(orc):
@@ -416,8 +451,6 @@ def test_column_order_special_cases(orc):
     assert list(orc.column_order([0, 0, 4, 4], [3, 3, 3, 3])) == [0, 1, 2, 3]
     assert list(orc.column_order([0, 3, 6], [1, 2, 3, 9, 8, 7])) == [0, 1, 2, 5, 4, 3]
     assert list(orc.column_order([0, 4], [-5, 2**31 - 1, -2**31, 0])) == [1, 3, 0, 2]
-    with pytest.raises(ValueError):
-        orc.column_order_original([0, 2], [1, 5], maxvalue=4)
     with pytest.raises(ValueError):
         orc.column_order([0, 3], [1, 2])
 
@@ -579,3 +612,39 @@ def test_tetra_list_matches_bruteforce(orc, case):
     assert [tuple(r) for r in got] == sorted(want)
     assert np.array_equal(np.bincount(got[:, 0], minlength=f.K)[: f.K] if len(got) else np.zeros(f.K, int),
                           orc.tetra_counts(f))
+
+
+# --- the oracle on several host threads ------------------------------------
+
+@pytest.mark.parametrize("case", [
+    workloads.noisy_circle(seed=61, n=300),
+    workloads.lattice_cloud(62, 90, side=4, thr=("fraction", 30, 100)),  # ties
+    workloads.uniform_cloud(63, 70, 4, thr=("full", 0, 1)),
+    workloads.uniform_cloud(64, 120, 16, thr=("sqdist", 60000, 0)),
+    workloads.uniform_cloud(65, 3, 2, thr=("full", 0, 1)),
+    workloads.uniform_cloud(66, 2, 2, thr=("full", 0, 1)),
+], ids=lambda c: c.name)
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_threaded_build_equals_plain_build(orc, case, threads):
+    """Distances split by rows and triangles split by values give exactly
+    the single-threaded triple loop's sorted list, whatever the thread count."""
+    f = orc.build(case.points, case.thr)
+    g = orc.build_mt(case.points, case.thr, threads)
+    assert np.array_equal(f.q, g.q)
+    assert (f.K, f.T) == (g.K, g.T)
+    assert np.array_equal(f.tris.reshape(-1, 4), g.tris.reshape(-1, 4))
+
+
+def test_triangles_by_value_ranges_concatenate(orc):
+    """Listing values [0, a), [a, b), [b, K) separately and concatenating
+    gives the whole list; an empty range gives nothing."""
+    c = workloads.noisy_circle(seed=67, n=250)
+    f = orc.build(c.points, c.thr)
+    a, b = f.K // 3, 2 * f.K // 3
+    parts = [orc.triangles_by_value(f, 0, a, 2), orc.triangles_by_value(f, a, b, 5),
+             orc.triangles_by_value(f, b, f.K, 1)]
+    assert np.array_equal(np.concatenate(parts), f.tris)
+    assert len(orc.triangles_by_value(f, a, a, 4)) == 0
+    assert all((p[:, 0] >= lo).all() and (p[:, 0] < hi).all() for p, lo, hi in zip(parts, (0, a, b), (a, b, f.K)))
+    with pytest.raises(ValueError):
+        orc.triangles_by_value(f, 0, f.K + 1)
