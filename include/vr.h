@@ -8,7 +8,8 @@
  *
  * The problem statement follows arXiv:1809.04424:
  *   - Section 3 (the eirene call): a point cloud whose rows are points (or a
- *     distance matrix; not supported here) plus an upper distance limit in,
+ *     symmetric dissimilarity matrix, dtype VR_DIST) plus an upper distance
+ *     limit in,
  *     an integer rank matrix ("symmat") and integer filtration values out;
  *   - Section 2.1: an edge joins two points closer than the threshold, a
  *     solid triangle exists once its three edges exist;
@@ -124,7 +125,17 @@ typedef struct vr_result {
 } vr_result;
 
 /*
- * Build the filtration of one point cloud.
+ * Build the filtration of one point cloud (Section 3: the eirene call takes
+ * the points and an upper limit and returns the integer rank matrix and the
+ * filtered simplices; Section 2.1: edges below the threshold, triangles once
+ * their three edges exist, each valued at its largest edge rank; Section
+ * 4.5: ranks are the sortperm of the distances).
+ * req:    the request; its points are read during the call only.
+ * stream: a hipStream_t (NULL = the null stream).
+ * out:    receives a new handle, owned by the caller until vr_free.
+ * Errors: VR_EINVAL (bad argument), VR_E2BIG (n or K beyond the key
+ * packing), VR_ERANGE (a squared distance of 2^32 or more, or a negative
+ * VR_DIST entry), VR_ENOMEM, VR_EHIP.
  * Enqueues all work on `stream` (a hipStream_t; NULL = the null stream) and
  * waits once for the first phase (distances up to triangle counts) to reach
  * the host through host-pinned memory, to size the outputs.  When a build
@@ -146,14 +157,17 @@ typedef struct vr_result {
  */
 VR_API int vr_build(const vr_request *req, void *stream, vr_result **out);
 
-/* counts[0..2] = (n, K, T).  Host only: no device call, no synchronisation. */
-
 /* Triangles of a result (or of a batch view) unpacked into T rows of four
  * int32 (i, j, k, v), i < j < k, v = the value (largest edge rank), in the
  * filtration order of tri_key.  `rows` is caller-owned device memory of
  * 16*T bytes; enqueued on `stream` after the build's work.  VR_EINVAL for a
  * null argument or a count-only result with triangles. */
 VR_API int vr_unpack_triangles(const vr_result *res, int32_t *rows, void *stream);
+
+/* counts[0..2] = (n, K, T): the vertices, kept edges and triangles of the
+ * filtration, whose sum is the size of the complex the paper tabulates per
+ * data set (Table 5).  Host only: no device call, no synchronisation.
+ * VR_EINVAL for a null argument. */
 VR_API int vr_query_counts(const vr_result *res, int64_t counts[3]);
 
 /*
@@ -167,8 +181,10 @@ VR_API int vr_query_stage_ms(const vr_result *res, float *ms, int cap);
 /* Name of stage s (static string), or NULL past the last stage. */
 VR_API const char *vr_stage_name(int s);
 
-/* Releases the handle's device memory in stream order on `stream`, then the
- * handle.  NULL-safe. */
+/* Releases the handle's device memory (the filtration of Section 3's output:
+ * edges and triangles) in stream order on `stream`, then the handle; device
+ * arrays read through the handle must be used before, in stream order.
+ * NULL-safe; no error. */
 VR_API void vr_free(vr_result *res, void *stream);
 
 /* Device bytes a build of this shape needs at most, besides its outputs

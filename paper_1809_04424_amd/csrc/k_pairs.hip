@@ -461,7 +461,8 @@ __global__ void __launch_bounds__(1024) k_tet_scan(long long *v, int64_t K) {
 // number of tetrahedra
 extern "C" VR_API int vr_tetra_offsets(const vr_result *res, int64_t *offsets, void *stream) {
     if (!res || !offsets) return VR_EINVAL;
-    const int64_t K = res->n_edges;
+    const int64_t n = res->n_vertices, K = res->n_edges;
+    if (n < 0 || K < 0 || n > VR_MAX_POINTS) return VR_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
     if (K > 0) {
         const int st = vr_tetra_counts(res, offsets, stream);

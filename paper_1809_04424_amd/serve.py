@@ -73,6 +73,21 @@ class Request:
             self.out_bytes = 0
 
 
+def check_request(points, thr):
+    """Reject at submission what no build could take: points that are not a
+    2-D int8/int16/int32 tensor on a HIP device, or a threshold that is not a
+    (kind, num, den) tuple of a known kind.  Raises TypeError or ValueError."""
+    import torch
+
+    if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+        raise TypeError("points must be a torch tensor on a HIP device")
+    if points.dim() != 2:
+        raise ValueError("points must be 2-D (n, d)")
+    vr._dtype_code(points)  # TypeError for other dtypes
+    if not isinstance(thr, (tuple, list)) or len(thr) != 3 or thr[0] not in vr.VR_THR:
+        raise ValueError(f"threshold must be (kind, num, den) with kind in {sorted(vr.VR_THR)}")
+
+
 def output_bytes(counts) -> int:
     """Device bytes of one result's outputs (as allocated, 256-byte aligned)."""
     _, K, T = counts
@@ -150,6 +165,10 @@ class Server:
 
     # ---------------------------------------------------------------- API --
     def submit(self, points, thr, arrival=None) -> Request:
+        """Queue one build.  Raises TypeError/ValueError at once for a request
+        no build could take (see check_request); a request the library
+        rejects later fails alone (its wait() raises)."""
+        check_request(points, thr)
         with self._cv:
             r = Request(self._next, points, thr, self.clock() if arrival is None else arrival, self)
             self._next += 1
@@ -186,7 +205,7 @@ class Server:
             try:
                 self._ws_of([head])
                 break
-            except vr.VrError as e:
+            except Exception as e:  # noqa: BLE001 -- any rejection fails this request only
                 self._pending.popleft()
                 head.error = e
                 head.t_done = self.clock()
@@ -221,34 +240,43 @@ class Server:
 
     def _run(self, group, ws, stream):
         t0 = self.clock()
-        err, items = None, None
+        err, items, b = None, None, None
         try:
-            b = vr.build_batch([r.points for r in group], [r.thr for r in group], maxdim=self.maxdim)
-            stream.synchronize()
-            items = list(b)
-        except vr.VrError as e:
-            err = e
-        t1 = self.clock()
-        charged = 0
-        with self._cv:
-            self._reserved -= ws
-            self._inflight -= 1
-            self.batches += 1
-            for i, r in enumerate(group):
-                r.t_start, r.t_done, r.batch_size = t0, t1, len(group)
-                if err is not None:
-                    r.error = err
-                    continue
-                r.counts = items[i].counts
-                if self.keep:
-                    r.item = items[i]
-                    r.out_bytes = output_bytes(r.counts)
-                    charged += r.out_bytes
-            self._held += charged
-            self.peak_bytes = max(self.peak_bytes, self._reserved + self._held)
-            self._cv.notify_all()
-        if not self.keep and items is not None:
-            items = None
-            b.free()
-        for r in group:
-            r._done.set()
+            try:
+                b = vr.build_batch([r.points for r in group], [r.thr for r in group], maxdim=self.maxdim)
+                stream.synchronize()
+                items = list(b)
+            except Exception as e:  # noqa: BLE001 -- the group fails, the loop goes on
+                err = e
+            t1 = self.clock()
+            charged = 0
+            with self._cv:
+                self.batches += 1
+                for i, r in enumerate(group):
+                    r.t_start, r.t_done, r.batch_size = t0, t1, len(group)
+                    if err is not None:
+                        r.error = err
+                        continue
+                    r.counts = items[i].counts
+                    if self.keep:
+                        r.item = items[i]
+                        r.out_bytes = output_bytes(r.counts)
+                        charged += r.out_bytes
+                self._held += charged
+            if not self.keep and b is not None:
+                items = None
+                b.free()
+        finally:
+            # the workspace and the slot come back whatever happened, and
+            # every request of the group is released to its waiter
+            with self._cv:
+                self._reserved -= ws
+                self._inflight -= 1
+                self.peak_bytes = max(self.peak_bytes, self._reserved + self._held)
+                self._cv.notify_all()
+            for r in group:
+                if r.t_done is None:
+                    r.t_start, r.t_done, r.batch_size = t0, self.clock(), len(group)
+                    if r.error is None and r.counts is None:
+                        r.error = RuntimeError("build did not complete")
+                r._done.set()

@@ -60,3 +60,40 @@ def test_workspace_of_requests(n):
     r = _R(n, 3)
     w = __import__("paper_1809_04424_amd").batch_workspace_bytes([(n, 3, 1, r.thr)])
     assert (w == 0) == (n < 2)
+
+
+@pytest.mark.parametrize("points,thr,exc", [
+    (torch.zeros((5, 3), dtype=torch.int8), ("fraction", 10, 100), TypeError),      # host tensor
+    ("not a tensor", ("fraction", 10, 100), TypeError),
+    (torch.zeros((5, 3), dtype=torch.float32), ("fraction", 10, 100), TypeError),  # checked after the device
+    (torch.zeros(5, dtype=torch.int8), ("fraction", 10, 100), TypeError),
+    (torch.zeros((5, 3), dtype=torch.int8), ("median", 1, 2), TypeError),
+])
+def test_submit_rejects_what_no_build_takes(points, thr, exc):
+    """Host tensors, other types and unknown threshold kinds are refused at
+    submission (before they could reach a worker thread)."""
+    with pytest.raises(exc):
+        serve.check_request(points, thr)
+
+
+def test_check_request_thresholds_without_gpu(monkeypatch):
+    """With the device test bypassed, the shape, dtype and threshold checks
+    still apply in that order."""
+    class _Dev:
+        type = "cuda"
+
+    class _T(torch.Tensor):
+        pass
+
+    t = torch.zeros((5, 3), dtype=torch.int8).as_subclass(_T)
+    monkeypatch.setattr(_T, "device", property(lambda self: _Dev()))
+    serve.check_request(t, ("fraction", 10, 100))
+    for bad in [("median", 1, 2), ("fraction", 1), "full", None]:
+        with pytest.raises(ValueError):
+            serve.check_request(t, bad)
+    t1 = torch.zeros(5, dtype=torch.int8).as_subclass(_T)
+    with pytest.raises(ValueError):
+        serve.check_request(t1, ("fraction", 10, 100))
+    tf = torch.zeros((5, 3), dtype=torch.float32).as_subclass(_T)
+    with pytest.raises(TypeError):
+        serve.check_request(tf, ("fraction", 10, 100))
