@@ -2,13 +2,19 @@
 """Benchmark of the gfx950 Vietoris-Rips filtration front end (dim <= 2).
 
 One step = one whole build (distances, ranks, threshold, triangles, ordered
-output) of the headline workload: 1000 points on a noisy circle in R^3
-(radius 100, sigma 5, int8), thresholded at the 20th-percentile edge rank.
-Inputs are resident in HBM before the timed region; outputs stay on the
-device.  The metric is filtered simplices per second, n + K + T per build.
+output) of the headline workload: 4000 points of an 8-component Gaussian
+mixture in R^64 (int8, int8 MFMA Gram), thresholded at the 10th-percentile
+edge rank (799800 edges, 94017474 triangles).  Inputs are resident in HBM
+before the timed region; outputs stay on the device.  The metric is filtered
+simplices per second, n + K + T per build.
+
+Before the line is printed, the last timed build's edges and every triangle
+key are compared with the CPU oracle's (built on the host's threads, which is
+also the CPU baseline); the line carries "parity": "bit-exact" only if every
+element matches, and the run fails otherwise.
 
 Prints ONE JSON line.  Only N = 1 GPU is supported.  Under "extra" the
-line also carries side measurements: the 4000-point R^64 mixture, the
+line also carries side measurements: the 1000-point noisy circle, the
 512-cloud batch, a Poisson request stream, a 1088 x 1088 Hamming matrix
 (dissimilarity input), the per-column order of a 2000 x 1999 array, the
 pairs of dimension 0 and the apparent pairs of dimension 1, tetrahedra
@@ -68,11 +74,12 @@ def _workload(name):
             "plain64": workloads.plain64}[name]()
 
 
-def _time_builds(vr, torch, pts, thr, steps, warmup, build=None):
+def _time_builds(vr, torch, pts, thr, steps, warmup, build=None, keep_last=False):
     """Time `steps` whole builds; HIP events bracket only the triangle write
     (on the build's stream), so its average launch duration is measured live.
     Each result is freed once the next build has been issued, as a caller
-    consuming results would; its events have completed by then."""
+    consuming results would; its events have completed by then.  With
+    keep_last the last result is returned too (for the parity gate)."""
     build = build or vr.build
     prev = None
     for _ in range(max(warmup, 2)):  # two results alive at once, as in the timed loop
@@ -96,6 +103,8 @@ def _time_builds(vr, torch, pts, thr, steps, warmup, build=None):
     t1 = time.perf_counter()
     tw.append(prev.stage_ms()["tri_write"])
     counts = prev.counts
+    if keep_last:
+        return (t1 - t0), counts, sum(tw) / len(tw), prev
     prev.free()
     torch.cuda.synchronize()
     return (t1 - t0), counts, sum(tw) / len(tw)
@@ -113,22 +122,52 @@ def _stage_breakdown(vr, torch, pts, thr, reps=10):
     return {k: round(sum(v) / len(v), 5) for k, v in acc.items()}
 
 
-def _cpu_baseline(cloud, budget_s=12.0):
+def _host_threads():
+    """Threads for the oracle: the host's CPU share for one GPU (16), or fewer
+    where the host has fewer cores."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _cpu_baseline(cloud, threads):
+    """The oracle's whole build of the headline cloud (distances, ranks,
+    threshold, every triangle in filtration order), timed on `threads` host
+    threads and on one; returns the baseline and the threaded build, which
+    the parity gate then compares with the device's output."""
     import oracle
 
     oracle.lib()
-    reps, t0 = 0, time.perf_counter()
-    simp = 0
-    while True:
-        f = oracle.build(cloud.points, cloud.thr)
-        simp += f.n + f.K + f.T
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 50:
-            break
-    return {"value": simp / el, "unit": "simplices/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} complete builds of {cloud.name} by the single-threaded C oracle "
-                      f"(distances, sortperm, rank matrix, triangle triple loop, qsort); {el:.1f} s"}
+    t0 = time.perf_counter()
+    f = oracle.build_mt(cloud.points, cloud.thr, threads)
+    tn = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    f1 = oracle.build_mt(cloud.points, cloud.thr, 1)
+    t1 = time.perf_counter() - t0
+    simp = f.n + f.K + f.T
+    assert (f1.K, f1.T) == (f.K, f.T)
+    del f1
+    return {"value": simp / tn, "unit": "simplices/s", "cores": threads, "kind": "oracle",
+            "sample": f"one complete build of {cloud.name} by the C oracle (distances by rows of pairs, sortperm, "
+                      f"rank matrix, the triangles of each value sorted; distances and triangles split over "
+                      f"{threads} threads): {tn:.2f} s; host reports {os.cpu_count()} cores",
+            "single_thread": {"value": simp / t1, "seconds": round(t1, 3)}}, f
+
+
+def _parity_gate(res, f):
+    """Every kept edge (endpoints, squared length) and every triangle key of
+    the device's result against the oracle's filtration; True when all match."""
+    import numpy as np
+
+    n, K, T = res.counts
+    if (n, K, T) != (f.n, f.K, f.T):
+        return False
+    ij = res.edge_ij().cpu().numpy()
+    if not (np.array_equal(ij[:, 0], f.ei) and np.array_equal(ij[:, 1], f.ej)
+            and np.array_equal(res.edge_q().cpu().numpy(), f.eq)):
+        return False
+    keys = res.tri_key().cpu().numpy().view(np.uint64)
+    t = f.tris.astype(np.uint64)
+    want = (t[:, 0] << np.uint64(39)) | (t[:, 1] << np.uint64(26)) | (t[:, 2] << np.uint64(13)) | t[:, 3]
+    return bool(np.array_equal(keys, want))
 
 
 def _batched(vr, torch, reps=3, tune=True):
@@ -289,7 +328,7 @@ def _main_batched(vr, torch, args):
     n, K, T = (sum(c[i] for c in counts) for i in range(3))
     simp = n + K + T
     tri_ms = sum(tw) / len(tw)
-    alg = _alg_bytes(n, K, T, sum(c[0] ** 2 for c in counts))
+    alg = _enum_bytes(n, K, T, sum(c[0] ** 2 for c in counts))
     achieved = alg / (tri_ms * 1e-3) / 1e9
     print(json.dumps({
         "metric": "filtered simplices/sec (VR dim<=2, bit-exact)", "value": simp * args.steps / el,
@@ -301,7 +340,8 @@ def _main_batched(vr, torch, args):
                    "schedule": list(tuned) if tuned else "default"},
         "roofline": {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic("batched512"),
-                     "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}}), flush=True)
+                     "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5),
+                     "fused_edge_bytes": int(_edge_bytes(K))}}), flush=True)
 
 
 def _schedule(vr, args, pts, thr):
@@ -328,7 +368,7 @@ def _hamming(vr, torch, tune=True, steps=5, warmup=2, sched=None):
     else:
         sch = vr.autotune(M, thr, matrix=True) if tune else None
     el, cnt, tw = _time_builds(vr, torch, M, thr, steps, warmup, build=vr.build_matrix)
-    a = _alg_bytes(cnt[0], cnt[1], cnt[2], cnt[0] ** 2)
+    a = _enum_bytes(cnt[0], cnt[1], cnt[2], cnt[0] ** 2)
     del M
     return {"value": sum(cnt) * steps / el, "unit": "simplices/s", "ms_per_step": 1e3 * el / steps,
             "steps": steps, "counts": list(cnt), "schedule": list(sch) if sch else "default",
@@ -549,11 +589,16 @@ def _pairs_dim0(vr, torch, reps=20):
             "alu_frac": round(ops / (ms * 1e-3) / peak, 4)}
 
 
-def _alg_bytes(n, K, T, n2):
-    """Algorithmic bytes of the triangle writer: triangle keys out (8 T), kept
-    ranks in (8 K), the adjacency once (n^2/8 over the clouds), and the fused
-    public edge arrays (8 K in, 16 K out)."""
-    return 8 * T + 8 * K + n2 / 8.0 + 24 * K
+def _enum_bytes(n, K, T, n2):
+    """Algorithmic bytes of the triangle enumeration: triangle keys out (8 T),
+    kept ranks in (8 K), the adjacency once (n^2/8 over the clouds)."""
+    return 8 * T + 8 * K + n2 / 8.0
+
+
+def _edge_bytes(K):
+    """Bytes of the public edge arrays the writer's grid also emits: 8 K in
+    (packed endpoints and length), 16 K out (endpoints, int64 length)."""
+    return 24 * K
 
 
 def main():
@@ -561,15 +606,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="circle1000",
+    ap.add_argument("--workload", default="mixture4000",
                     choices=["circle1000", "mixture4000", "plain64", "batched512", "hamming1088", "colorder2000",
                              "pairs0", "schur16384"],
-                    help="circle1000 (the benchmark line, with side measurements), mixture4000, plain64, "
+                    help="mixture4000 (the benchmark line, with side measurements), circle1000, plain64, "
                          "batched512 (one batched build of 512 clouds), or one side measurement alone: "
                          "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs and dimension-1 apparent pairs), "
                          "schur16384 (F2 product and sum)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 4000 x R^64 side measurement")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and the parity gate")
+    ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cloud batched side measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (Poisson stream) side measurement")
     ap.add_argument("--qps", type=float, default=SERVE_QPS,
@@ -622,51 +667,63 @@ def main():
     torch.cuda.synchronize()
 
     tuned = _schedule(vr, args, pts, cloud.thr)  # one-time, untimed
-    el, counts, tri_ms = _time_builds(vr, torch, pts, cloud.thr, args.steps, args.warmup)
+    el, counts, tri_ms, last = _time_builds(vr, torch, pts, cloud.thr, args.steps, args.warmup, keep_last=True)
     n, K, T = counts
     simplices = n + K + T
     value = simplices * args.steps / el
     ms_step = 1e3 * el / args.steps
+    # the CPU baseline's build doubles as the reference of the parity gate
+    cpu, parity = None, None
+    if not args.no_cpu:
+        cpu, f = _cpu_baseline(cloud, _host_threads())
+        ok = _parity_gate(last, f)
+        del f
+        if not ok:
+            last.free()
+            print(f"bench.py: the device's build of {cloud.name} differs from the oracle's", file=sys.stderr)
+            sys.exit(1)
+        parity = "bit-exact"
+    last.free()
+    torch.cuda.synchronize()
     st = _stage_breakdown(vr, torch, pts, cloud.thr, args.breakdown_reps) if args.breakdown_reps > 0 else {}
     if args.stages:
         print(json.dumps({"stages_ms": st}), file=sys.stderr, flush=True)
 
-    alg = _alg_bytes(n, K, T, n * n)
-    achieved = alg / (tri_ms * 1e-3) / 1e9 if tri_ms > 0 else 0.0
-    traffic = _traffic(args.workload)
+    enum = _enum_bytes(n, K, T, n * n)
+    achieved = enum / (tri_ms * 1e-3) / 1e9 if tri_ms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": "k_tri_write", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes": int(alg), "avg_ms": round(tri_ms, 5)}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(args.workload),
+                "algorithmic_bytes": int(enum), "avg_ms": round(tri_ms, 5),
+                "fused_edge_bytes": int(_edge_bytes(K)),
+                "frac_with_edges": round((enum + _edge_bytes(K)) / (tri_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                if tri_ms > 0 else None}
 
     extra = {}
-    if not args.no_extra and args.workload == "circle1000":
-        c3 = _workload("mixture4000")
-        p3 = torch.from_numpy(c3.points).to("cuda:0")
-        t3s = vr.autotune(p3, c3.thr) if not args.no_tune else None
-        e3, cnt3, t3 = _time_builds(vr, torch, p3, c3.thr, 10, 2)
-        s3 = sum(cnt3)
-        a3 = _alg_bytes(cnt3[0], cnt3[1], cnt3[2], cnt3[0] ** 2)
-        extra["mixture4000_r64_p10"] = {
-            "value": s3 * 10 / e3, "unit": "simplices/s", "ms_per_step": 1e3 * e3 / 10,
-            "counts": list(cnt3), "schedule": list(t3s) if t3s else "default",
-            "tri_write_ms": round(t3, 5), "tri_write_traffic": _traffic("mixture4000"),
-            "tri_write_frac_hbm": round(a3 / (t3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t3 > 0 else None,
-            "stages_ms": _stage_breakdown(vr, torch, p3, c3.thr, reps=3) if args.breakdown_reps > 0 else {}}
-        del p3
-
-    if not args.no_extra and args.workload == "circle1000":
+    if not args.no_extra and args.workload == "mixture4000":
+        c2 = _workload("circle1000")
+        p2 = torch.from_numpy(c2.points).to("cuda:0")
+        t2s = vr.autotune(p2, c2.thr) if not args.no_tune else None
+        e2, cnt2, t2 = _time_builds(vr, torch, p2, c2.thr, 20, 3)
+        a2 = _enum_bytes(cnt2[0], cnt2[1], cnt2[2], cnt2[0] ** 2)
+        extra["circle1000_r3_p20"] = {
+            "value": sum(cnt2) * 20 / e2, "unit": "simplices/s", "ms_per_step": 1e3 * e2 / 20,
+            "counts": list(cnt2), "schedule": list(t2s) if t2s else "default",
+            "tri_write_ms": round(t2, 5), "tri_write_traffic": _traffic("circle1000"),
+            "tri_write_frac_hbm": round(a2 / (t2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t2 > 0 else None,
+            "stages_ms": _stage_breakdown(vr, torch, p2, c2.thr, reps=3) if args.breakdown_reps > 0 else {}}
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
         extra["pairs_dim1_apparent_circle1000"] = _apparent(vr, torch)
         extra["tetra_counts_circle1000"] = _tetra(vr, torch)
         extra["schur_f2_16384"] = _schur(vr, torch)
-        extra["circle1000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr)
-        extra["circle1000_event_timed"] = _event_median(vr, torch, pts, cloud.thr)
+        extra["mixture4000_outputs_to_host"] = _with_d2h(vr, torch, pts, cloud.thr, steps=5, warmup=1)
+        extra["mixture4000_event_timed"] = _event_median(vr, torch, pts, cloud.thr)
+        del p2
 
-    if not args.no_batch and args.workload == "circle1000":
+    if not args.no_batch and args.workload == "mixture4000":
         extra["batched512_r3"] = _batched(vr, torch, tune=not args.no_tune)
-    if not args.no_serve and args.workload == "circle1000":
+    if not args.no_serve and args.workload == "mixture4000":
         extra["serving_poisson"] = _serving(vr, torch, qps=args.qps)
 
     line = {
@@ -685,14 +742,18 @@ def main():
         "config": {"workload": cloud.name, "n": n, "d": cloud.d, "coords": str(cloud.points.dtype),
                    "threshold": f"{cloud.thr[0]} {cloud.thr[1]}/{cloud.thr[2]}", "kept_edges": K,
                    "triangles": T, "simplices_per_build": simplices,
-                   "schedule": list(tuned) if tuned else "default"},
+                   "schedule": list(tuned) if tuned else "default",
+                   "timed_loop": "repeat builds of one shape: after the first, each build enqueues its "
+                                 "triangle write before the host reads the counts"},
         "roofline": roofline,
         "stages_ms": st,
     }
+    if parity:
+        line["parity"] = parity
     if extra:
         line["extra"] = extra
-    if not args.no_cpu:
-        line["cpu_baseline"] = _cpu_baseline(cloud)
+    if cpu:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

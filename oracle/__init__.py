@@ -242,14 +242,28 @@ def triangles_by_value(f: Filtration, r0: int = 0, r1: int | None = None, thread
     return out[:T]
 
 
-def build_mt(points, thr, threads: int) -> Filtration:
+def triangle_counts_by_value(f: Filtration, threads: int = 1) -> np.ndarray:
+    """count[r] = the triangles whose value is r (the first pass of
+    triangles_by_value), for every kept edge; T = count.sum()."""
+    cnt = np.zeros(max(f.K, 1), np.int64)
+    if f.K and f.n >= 3:
+        R = np.ascontiguousarray(f.R.reshape(-1), dtype=np.int64)
+        lib().or_triangles_by_value_count(f.n, R, f.ei, f.ej, 0, f.K, cnt, int(threads))
+    return cnt[: f.K]
+
+
+def build_mt(points, thr, threads: int, list_triangles: bool = True) -> Filtration:
     """The whole front end as build(), with the distances (by rows of pairs)
     and the triangles (by values) computed on `threads` host threads; the
     outputs are identical to build()'s."""
     p = _pts(points)
     f = _build_from_pairs(p.shape[0], sqdist_mt(p, threads), thr, 2, False, triangles=False)
-    f.tris = triangles_by_value(f, threads=threads)
-    f.T = len(f.tris)
+    if list_triangles:
+        f.tris = triangles_by_value(f, threads=threads)
+        f.T = len(f.tris)
+    else:
+        f.tris = None
+        f.T = int(triangle_counts_by_value(f, threads).sum())
     return f
 
 
