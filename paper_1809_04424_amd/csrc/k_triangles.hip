@@ -294,7 +294,15 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 
 // Compact the edges a owns among star entries [p0, p0+EB) and split
 // them by piece count: `parts` work-groups share a vertex (part = this one's
-// index), each taking a contiguous slice, cut again into one run per wave.  WRITE: an edge is written at the
+// index), each taking a contiguous slice, cut again into one run per wave.
+// When `parts` is a multiple of 8, the work-groups of a vertex are split
+// by the partner instead: work-group `part` takes only the edges whose
+// partner lies in the (part mod 8)-th eighth of the cloud's vertices, and
+// the parts / 8 work-groups of that eighth share them as above.  Work-groups
+// are handed to the chip's 8 dies (XCDs, each with its own L2) in turn, so
+// block index mod 8 names the die, and with parts a multiple of 8 it equals
+// part mod 8: each die then reads the stars of one eighth of the vertices,
+// which its L2 can hold, instead of all of them.  WRITE: an edge is written at the
 // endpoint whose partner has the shorter star (candidates = the partner's
 // whole neighbour-ordered star).  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
@@ -308,6 +316,12 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
     bool owned = false;
     uint32_t r = 0, b = 0, pb = 0, sb = 0, len = 0;
     const uint32_t x = p - s0;
+    const bool by_partner = (parts & 7) == 0;
+    const uint32_t eighth = (uint32_t)(part & 7);
+    if (by_partner) {
+        part >>= 3;
+        parts >>= 3;
+    }
     if (p < s1) {
         r = kb + (p0 == s0 ? r0 : D.star_r[p]);  // global kept-edge index
         b = p0 == s0 ? b0 : D.star_nbr[p];
@@ -322,6 +336,7 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
             owned = pb < x || (pb == x && (uint32_t)a < b);
             len = pb;
         }
+        if (by_partner) owned = owned && (b * 8u) / (uint32_t)n == eighth;
     }
     uint32_t m, C;
     const uint32_t idx = enum_excl_scan<EB>(owned ? 1u : 0u, L.scan, &m);
