@@ -273,6 +273,23 @@ VR_API int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t 
 VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz, int64_t *z,
                            void *stream);
 
+/* vr_column_order for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and errors, but the scratch lives in
+ * an array of VR_COLORDER_NOALLOC_BYTES that the library holds on every GPU
+ * it runs on until the process ends, so the call allocates nothing (its
+ * device address is looked up on the first call on each GPU).  Limit: the
+ * scratch of one call, 8 ceil(nnz / 4096) bytes rounded up to 256, plus 4
+ * nnz bytes (about 8.3 million entries), must fit, else VR_E2BIG and
+ * nothing is enqueued.  `stream` must belong to the calling thread's
+ * current device.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (different streams or threads without ordering
+ * between them) race, and the caller must order them.  VR_EHIP if the
+ * array's address cannot be found. */
+#define VR_COLORDER_NOALLOC_BYTES (32u << 20)
+VR_API int vr_column_order_noalloc(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz,
+                                   int64_t *z, void *stream);
+
 /* Persistence pairs in dimension 0 of a build's filtration (Section 2.2.1:
  * Alg. 1 on the edge columns of the boundary matrix; vertices share one
  * value and are ordered by index).  Edge r is paired with the vertex that

@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_blockprodsum_count", "vr_blockprodsum_write",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -115,6 +115,8 @@ def lib():
         L.vr_column_order.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_void_p]
         L.vr_column_order.restype = ctypes.c_int
+        L.vr_column_order_noalloc.argtypes = L.vr_column_order.argtypes
+        L.vr_column_order_noalloc.restype = ctypes.c_int
         L.vr_pairs_dim0.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.vr_pairs_dim0.restype = ctypes.c_int
         L.vr_pairs_dim1_apparent.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
@@ -549,13 +551,16 @@ def build_batch(points, thr, maxdim: int = 2, count_only: bool = False, timing=F
     return Batch(out, alloc, ctypes.c_void_p(stream.cuda_stream), dev, len(pts))
 
 
-def column_order(colptr, v, out=None):
+def column_order(colptr, v, out=None, noalloc=False):
     """Per-column stable order of a compressed-sparse-column array (Section
     4.3): z[e] = the slot of entry e when its column is sorted by value,
     equal values keeping their order.
 
     colptr: int64 (ncols + 1,) device tensor (0, ..., nnz); v: int32 (nnz,)
     device tensor; out: optional int64 (nnz,) device tensor.  Returns z.
+    noalloc=True calls vr_column_order_noalloc (scratch in the library's
+    per-GPU array, nothing allocated; pass `out` to allocate nothing here
+    either).
     """
     import torch
 
@@ -569,10 +574,10 @@ def column_order(colptr, v, out=None):
     if z.dtype != torch.int64 or z.numel() != nnz or not z.is_contiguous():
         raise ValueError("out must be a contiguous int64 tensor of nnz entries")
     stream = torch.cuda.current_stream(v.device)
+    fn = L.vr_column_order_noalloc if noalloc else L.vr_column_order
     with torch.cuda.device(v.device):
-        rc = L.vr_column_order(ctypes.c_void_p(colptr.data_ptr()), colptr.numel() - 1,
-                               ctypes.c_void_p(v.data_ptr() if nnz else 0), nnz,
-                               ctypes.c_void_p(z.data_ptr() if nnz else 0), ctypes.c_void_p(stream.cuda_stream))
+        rc = fn(ctypes.c_void_p(colptr.data_ptr()), colptr.numel() - 1, ctypes.c_void_p(v.data_ptr() if nnz else 0),
+                nnz, ctypes.c_void_p(z.data_ptr() if nnz else 0), ctypes.c_void_p(stream.cuda_stream))
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return z

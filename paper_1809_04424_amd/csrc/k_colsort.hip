@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "vr.h"
 #include "vr_cache.h"
 
@@ -332,19 +334,14 @@ __global__ void __launch_bounds__(CO_BLOCK) k_co_merge(const int64_t *colptr, in
     }
 }
 
-extern "C" VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz,
-                                      int64_t *z, void *stream) {
-    if (ncols < 0 || nnz < 0 || (ncols > 0 && !colptr)) return VR_EINVAL;
-    if (nnz == 0) return VR_OK;
-    if (ncols == 0 || !v || !z) return VR_EINVAL;
-    const hipStream_t s = (hipStream_t)stream;
-    const int64_t nwin = (nnz + CO_WIN - 1) / CO_WIN;
-    if (nwin > 0x7FFFFFFF) return VR_E2BIG;
-    const size_t off_vs = ((size_t)nwin * 8 + 255) & ~(size_t)255;
-    char *ws = (char *)cache_get(off_vs + (size_t)nnz * 4, s);
-    if (!ws) return VR_ENOMEM;
+// Scratch of one call: the first column of every window (nwin int64), then
+// the sorted runs of the windows (nnz uint32) at off_vs.
+static size_t co_scratch_off(int64_t nwin) { return ((size_t)nwin * 8 + 255) & ~(size_t)255; }
+
+static int co_launch(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz, int64_t *z, char *ws,
+                     int64_t nwin, hipStream_t s) {
     int64_t *first = (int64_t *)ws;
-    uint32_t *vs = (uint32_t *)(ws + off_vs);
+    uint32_t *vs = (uint32_t *)(ws + co_scratch_off(nwin));
     const int64_t gb = (ncols + CO_BLOCK - 1) / CO_BLOCK;
     hipLaunchKernelGGL(k_co_first, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(CO_BLOCK), 0, s, colptr, ncols,
                        nnz, first);
@@ -352,7 +349,67 @@ extern "C" VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, cons
                        (const int64_t *)first, nwin, z, vs);
     hipLaunchKernelGGL(k_co_merge, dim3((unsigned)nwin), dim3(CO_BLOCK), 0, s, colptr, ncols, v, nnz,
                        (const int64_t *)first, nwin, z, (const uint32_t *)vs);
-    const hipError_t e = hipGetLastError();
+    return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
+}
+
+// Checks shared by both entry points; *nwin = the windows of nnz entries.
+static int co_check(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz, const int64_t *z,
+                    int64_t *nwin) {
+    if (ncols < 0 || nnz < 0 || (ncols > 0 && !colptr)) return VR_EINVAL;
+    *nwin = (nnz + CO_WIN - 1) / CO_WIN;
+    if (nnz == 0) return VR_OK;
+    if (ncols == 0 || !v || !z) return VR_EINVAL;
+    if (*nwin > 0x7FFFFFFF) return VR_E2BIG;
+    return VR_OK;
+}
+
+extern "C" VR_API int vr_column_order(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz,
+                                      int64_t *z, void *stream) {
+    int64_t nwin = 0;
+    const int st = co_check(colptr, ncols, v, nnz, z, &nwin);
+    if (st != VR_OK || nnz == 0) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)cache_get(co_scratch_off(nwin) + (size_t)nnz * 4, s);
+    if (!ws) return VR_ENOMEM;
+    const int rc = co_launch(colptr, ncols, v, nnz, z, ws, nwin, s);
     cache_put(ws, s);
-    return e == hipSuccess ? VR_OK : VR_EHIP;
+    return rc;
+}
+
+// ------------------------------------------------- without allocation ----
+// The scratch of vr_column_order_noalloc: one array per GPU, loaded with the
+// code object and held until the process ends.  In host code its name only
+// stands in for the array, so each GPU's device address is looked up once
+// (hipGetSymbolAddress, with that GPU current) and used from then on.
+static __device__ __align__(256) unsigned char scratch[VR_COLORDER_NOALLOC_BYTES];
+
+namespace {
+constexpr int CO_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[CO_MAX_DEVICES];
+
+// Device address of the current GPU's scratch array; nullptr when the
+// lookup fails.
+char *scratch_here() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= CO_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch[dev] = (char *)p;
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
+extern "C" VR_API int vr_column_order_noalloc(const int64_t *colptr, int64_t ncols, const int32_t *v, int64_t nnz,
+                                              int64_t *z, void *stream) {
+    int64_t nwin = 0;
+    const int st = co_check(colptr, ncols, v, nnz, z, &nwin);
+    if (st != VR_OK || nnz == 0) return st;
+    if (co_scratch_off(nwin) + (size_t)nnz * 4 > (size_t)VR_COLORDER_NOALLOC_BYTES) return VR_E2BIG;
+    char *ws = scratch_here();
+    if (!ws) return VR_EHIP;
+    return co_launch(colptr, ncols, v, nnz, z, ws, nwin, (hipStream_t)stream);
 }

@@ -188,6 +188,27 @@ def test_column_order_argument_checks():
     assert L.vr_column_order(None, 0, None, 0, None, None) == vr.VR_OK      # nothing to do
 
 
+def test_column_order_noalloc_argument_checks():
+    """The same argument errors, plus VR_E2BIG once one call's scratch would
+    not fit the library's per-GPU array; all before any device work (the
+    pointers below are never read)."""
+    L = vr.lib()
+    f = L.vr_column_order_noalloc
+    assert f(None, -1, None, 0, None, None) == vr.VR_EINVAL
+    assert f(None, 0, None, -1, None, None) == vr.VR_EINVAL
+    assert f(None, 3, None, 0, None, None) == vr.VR_EINVAL
+    assert f(None, 0, None, 0, None, None) == vr.VR_OK
+    fake = ctypes.c_void_p(0x1000)
+    limit = 32 << 20  # VR_COLORDER_NOALLOC_BYTES
+    nnz_over = limit // 4  # 4 bytes per entry alone fill the array
+    assert f(fake, 1, fake, nnz_over, fake, None) == vr.VR_E2BIG
+    # the largest nnz whose scratch fits, and one more
+    fits = lambda m: ((8 * ((m + 4095) // 4096) + 255) // 256) * 256 + 4 * m <= limit  # noqa: E731
+    m = max(x for x in range(nnz_over - 20000, nnz_over) if fits(x))
+    assert not fits(m + 1)
+    assert f(fake, 1, fake, m + 1, fake, None) == vr.VR_E2BIG
+
+
 def test_matrix_batches_hold_one_matrix():
     """A dissimilarity matrix takes all 32 bits of the sort key, so a batch
     holds one matrix of two or more points (VR_E2BIG otherwise)."""
