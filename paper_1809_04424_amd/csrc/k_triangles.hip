@@ -20,7 +20,8 @@
 //   k_scan        exclusive scan of the counts (decoupled look-back); the
 //                 last tile stores (flags, K, T) into the host-pinned mailbox
 //   k_tri_write   per vertex a: for each edge a owns, walk the partner's
-//                 neighbour-ordered star; hits are compacted with ballot and
+//                 shortest neighbour-ordered prefix list that holds the
+//                 partner's entries before the edge; hits are compacted with ballot and
 //                 mbcnt (the ballot/popc compaction of the paper's init_supp,
 //                 Section 4.4, on 64-wide waves) and stored contiguously
 //   k_emit_edges  public edge arrays
@@ -37,11 +38,35 @@ __device__ __forceinline__ int vertex_cloud(const VrDev &D, long long v) {
 
 // --------------------------------------------------------------- k_rows ----
 // Star slots: vertex v of a cloud with n points owns n entries of star_r
-// and star_nbr at star_slot(mbase, n, v), and of star_k 64 entries further
-// per preceding vertex, which leaves room for its 64 sentinels.
+// and star_nbr at star_slot(mbase, n, v).
 #define STAR_SENTINEL 0xFFFF0000u  // neighbour 0, position 0xFFFF
 __device__ __forceinline__ uint32_t star_slot(uint32_t mbase, int n, int v) { return mbase + (uint32_t)v * (uint32_t)n; }
-__device__ __forceinline__ uint32_t star_k_base(uint32_t s0, long long v) { return s0 + 64u * (uint32_t)v; }
+
+// Prefix lists: for a star of deg entries, list j (j = 1..VR_PLISTS) holds
+// the entries whose position in the rank-ordered star is below
+// plist_len(j) = ceil(j deg / VR_PLISTS), in neighbour order, each packing
+// (neighbour | position << 16), and is followed by 64 sentinels; the last
+// list is the whole star.  An edge's triangles lie among its partner's
+// first pb entries, which the partner's list plist_pick(pb) holds: walking
+// that list instead of the whole star leaves the walk in neighbour order
+// (so hits still come out in k order) while cutting the candidates to about
+// half on average.  Vertex v of a cloud owns 3n + 65 VR_PLISTS entries of
+// star_k from plist_region (sum over the lists: at most 2.5 deg + 4 + 256).
+#define VR_PLISTS 4
+__device__ __forceinline__ uint32_t plist_len(uint32_t j, uint32_t deg) { return (j * deg + VR_PLISTS - 1) / VR_PLISTS; }
+__device__ __forceinline__ uint32_t plist_off(uint32_t j, uint32_t deg) {
+    uint32_t o = 0;
+    for (uint32_t i = 1; i < j; i++) o += plist_len(i, deg) + VR_WAVE;
+    return o;
+}
+// smallest j with plist_len(j) >= p; 0 for p = 0 (no candidates)
+__device__ __forceinline__ uint32_t plist_pick(uint32_t p, uint32_t deg) {
+    return p == 0 ? 0u : (p * VR_PLISTS + deg - 1) / deg;
+}
+__device__ __forceinline__ uint32_t plist_region(uint32_t mbase, uint32_t vbase, int n, int v) {
+    const uint32_t per = 3u * (uint32_t)n + (VR_WAVE + 1) * VR_PLISTS;
+    return 3u * mbase + (uint32_t)(VR_WAVE + 1) * VR_PLISTS * vbase + (uint32_t)v * per;
+}
 
 // One work-group per vertex v reads row v of the rank matrix that k_edges
 // scattered into v's star_r slot (entry k = this build's tag << 24 | rank
@@ -55,8 +80,9 @@ __device__ __forceinline__ uint32_t star_k_base(uint32_t s0, long long v) { retu
 // by rank in LDS (bitonic), which orders v's edges the way the paper's
 // per-column ordering of the distance matrix does (Section 4.3).  Outputs:
 // v's star in rank order (rank within the cloud, written over the row, and
-// the neighbour), each edge's position in it (pos), the star in neighbour
-// order with those positions (star_k, then 64 sentinels) and its size.
+// the neighbour), each edge's position in it (pos), the prefix lists (the
+// star in neighbour order with those positions, whole and cut at each
+// quarter of the rank order) and its size.
 //
 // Wave w reads the row's entries [64 S w, 64 S (w+1)) in S steps of 64, so
 // the neighbour order is the order of (wave, step, lane); S * 256 >= n.
@@ -65,9 +91,10 @@ __device__ __forceinline__ uint32_t star_k_base(uint32_t s0, long long v) { retu
 // Counting rank of a star of 1 <= deg <= NK * 256 entries: keys[x] = rank of the
 // x-th neighbour (padded to a multiple of 4 with ~0), nbr[x] = that
 // neighbour.  Writes the star in rank order over the row, its neighbours,
-// the edges' positions, and the neighbour-ordered star.
+// the edges' positions, and the neighbour-ordered star (sk, and keys[x]
+// once every key is read).
 template <int NK>
-__device__ __forceinline__ void rows_count_rank(const VrDev &D, const uint32_t *keys, const uint16_t *nbr, uint32_t deg,
+__device__ __forceinline__ void rows_count_rank(const VrDev &D, uint32_t *keys, const uint16_t *nbr, uint32_t deg,
                                                 uint32_t *__restrict__ row, uint32_t s0, uint32_t *__restrict__ sk,
                                                 int v, long long kb) {
     uint32_t own[NK], y[NK];
@@ -84,15 +111,20 @@ __device__ __forceinline__ void rows_count_rank(const VrDev &D, const uint32_t *
         for (int i = 0; i < NK; i++)
             y[i] += (uint32_t)(e.x < own[i]) + (uint32_t)(e.y < own[i]) + (uint32_t)(e.z < own[i]) + (uint32_t)(e.w < own[i]);
     }
+    uint32_t kx[NK];
+#pragma unroll
+    for (int i = 0; i < NK; i++) kx[i] = nbr[min(threadIdx.x + VR_BLOCK * i, deg - 1)];
+    __syncthreads();  // every key is read: keys[] takes the packed entries
 #pragma unroll
     for (int i = 0; i < NK; i++) {
         const uint32_t x = threadIdx.x + VR_BLOCK * i;
         if (x < deg) {
-            const uint32_t k = nbr[x], lr = own[i];
+            const uint32_t k = kx[i], lr = own[i];
             row[y[i]] = lr;
             D.star_nbr[s0 + y[i]] = (uint16_t)k;
             D.pos[s0 + k] = (uint16_t)y[i];
             sk[x] = k | (y[i] << 16);
+            keys[x] = k | (y[i] << 16);
         }
     }
 }
@@ -101,6 +133,7 @@ template <int S>
 __global__ __launch_bounds__(VR_BLOCK) void k_rows(VrDev D) {
     extern __shared__ uint32_t lds[];  // P sort keys, then the position of each neighbour (u16)
     __shared__ uint32_t sh_w[VR_WAVES];
+    __shared__ uint32_t sh_l[VR_PLISTS - 1][VR_WAVES];
     const long long vg = blockIdx.x;
     const int c = vertex_cloud(D, vg);
     const int v = (int)(vg - D.cl[c].vbase), n = D.cl[c].n;
@@ -160,7 +193,8 @@ __global__ __launch_bounds__(VR_BLOCK) void k_rows(VrDev D) {
         }
     }
     __syncthreads();
-    uint32_t *sk = D.star_k + star_k_base(s0, vg);
+    uint32_t *lb = D.star_k + plist_region((uint32_t)D.cl[c].mbase, (uint32_t)D.cl[c].vbase, n, v);
+    uint32_t *sk = lb + plist_off(VR_PLISTS, deg);  // the last list: the whole star
     if (by_count) {
         // rank-order position of entry x = number of smaller keys (ranks
         // are distinct); every lane reads the same keys, which LDS
@@ -218,13 +252,56 @@ __global__ __launch_bounds__(VR_BLOCK) void k_rows(VrDev D) {
         for (int s = 0; s < S; s++) {
             const uint32_t k = (uint32_t)((w * per + s) * VR_WAVE + lane);
             const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk[s] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[s], x));
-            if ((mk[s] >> lane) & 1ull) sk[at] = k | ((uint32_t)pk[k] << 16);
+            if ((mk[s] >> lane) & 1ull) {
+                const uint32_t e = k | ((uint32_t)pk[k] << 16);
+                sk[at] = e;
+                lds[at] = e;
+            }
             x += (uint32_t)__popcll(mk[s]);
         }
     }
-    // 64 sentinels after the star: position 0xFFFF fails every prefix test,
-    // so a piece may run past the star's end without a bounds test
-    if (threadIdx.x < VR_WAVE) sk[deg + threadIdx.x] = STAR_SENTINEL;
+    // lds[0, deg) holds the star in neighbour order (packed); the shorter
+    // lists are its entries below each cut, compacted in order
+    __syncthreads();
+    {
+        uint32_t cut[VR_PLISTS - 1], off[VR_PLISTS - 1], run[VR_PLISTS - 1];
+#pragma unroll
+        for (int j = 0; j < VR_PLISTS - 1; j++) {
+            cut[j] = plist_len((uint32_t)j + 1, deg);
+            off[j] = plist_off((uint32_t)j + 1, deg);
+            run[j] = 0;
+        }
+        for (uint32_t x0 = 0; x0 < deg; x0 += VR_BLOCK) {
+            const uint32_t x = x0 + threadIdx.x;
+            const uint32_t e = x < deg ? lds[x] : 0xFFFFFFFFu;
+            unsigned long long m[VR_PLISTS - 1];
+#pragma unroll
+            for (int j = 0; j < VR_PLISTS - 1; j++) {
+                m[j] = __builtin_amdgcn_ballot_w64((e >> 16) < cut[j]);
+                if (lane == 0) sh_l[j][w] = (uint32_t)__popcll(m[j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < VR_PLISTS - 1; j++) {
+                uint32_t before = 0, tot = 0;
+#pragma unroll
+                for (int i = 0; i < VR_WAVES; i++) {
+                    const uint32_t t = sh_l[j][i];
+                    if (i < w) before += t;
+                    tot += t;
+                }
+                if ((m[j] >> lane) & 1ull)
+                    lb[off[j] + run[j] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m[j] >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m[j], before))] = e;
+                run[j] += tot;
+            }
+            __syncthreads();  // sh_l is rewritten by the next chunk
+        }
+    }
+    // 64 sentinels after each list: position 0xFFFF fails every prefix test,
+    // so a piece may run past a list's end without a bounds test
+    if (threadIdx.x < VR_WAVE)
+        for (uint32_t j = 1; j <= VR_PLISTS; j++) lb[plist_off(j, deg) + plist_len(j, deg) + threadIdx.x] = STAR_SENTINEL;
     if (threadIdx.x == 0) D.deg[vg] = deg;
 }
 
@@ -303,8 +380,9 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 // block index mod 8 names the die, and with parts a multiple of 8 it equals
 // part mod 8: each die then reads the stars of one eighth of the vertices,
 // which its L2 can hold, instead of all of them.  WRITE: an edge is written at the
-// endpoint whose partner has the shorter star (candidates = the partner's
-// whole neighbour-ordered star).  Otherwise it is counted at the endpoint
+// endpoint whose partner's prefix list (the shortest holding the partner's
+// entries before the edge) is shorter; candidates = that list, in
+// neighbour order.  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
 // The first chunk's star entries come preloaded (r0, b0: see stage_pos).
 template <bool WRITE, int EB>
@@ -328,10 +406,14 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
         pb = D.pos[star_slot(mb, n, (int)b) + (uint32_t)a];  // edge {b,a} in b's star
         sb = star_slot(mb, n, (int)b);
         if (WRITE) {
+            // a walks b's shortest list holding b's first pb entries, or b
+            // walks a's holding a's first x: the shorter walk wins
             const uint32_t db = D.deg[vb + b], da = s1 - s0;
-            owned = db < da || (db == da && (uint32_t)a < b);
-            len = db;
-            sb = star_k_base(sb, vb + b);
+            const uint32_t jb = plist_pick(pb, db), ja = plist_pick(x, da);
+            const uint32_t cb = jb ? plist_len(jb, db) : 0u, ca = ja ? plist_len(ja, da) : 0u;
+            owned = cb < ca || (cb == ca && (uint32_t)a < b);
+            len = cb;
+            sb = plist_region(mb, vb, n, (int)b) + plist_off(jb ? jb : 1u, db);
         } else {
             owned = pb < x || (pb == x && (uint32_t)a < b);
             len = pb;
@@ -657,8 +739,8 @@ void launch_cloud_publish(const VrDev &D, hipStream_t s) {
 }
 
 // ----------------------------------------------------------- k_tri_write ----
-// Edge r = {a, b}: walk b's neighbour-ordered star; entry (k, position pk in
-// b's rank-ordered star) is a triangle of value r when pk < pb and Pa[k] < xa.
+// Edge r = {a, b}: walk b's prefix list; entry (k, position pk in b's
+// rank-ordered star) is a triangle of value r when pk < pb and Pa[k] < xa.
 // The sorted vertex triple is (k, lo, hi), (lo, k, hi) or (lo, hi, k) as k
 // falls below, between or above the endpoints, so a key is a per-edge base
 // plus k shifted into place.  Hits of a piece are compacted with ballot and

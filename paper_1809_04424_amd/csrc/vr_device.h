@@ -434,14 +434,14 @@ struct VrDev {
     uint32_t *se_ij;        // K sorted kept edges (i<<16|j, local)
     uint32_t *se_q;         // K
     // Star slots: vertex v of a cloud with n points owns entries
-    // [mbase + v n, mbase + v n + n) of star_r and star_nbr, and the same
-    // entries shifted by 64 (global vertex) of star_k, which leaves room
-    // for the 64 sentinels after each star.
+    // [mbase + v n, mbase + v n + n) of star_r, star_nbr and pos, and
+    // 3 n + 260 entries of star_k from 3 mbase + 260 vbase + v (3 n + 260).
     uint32_t *star_r;       // sum n^2: first the rank matrix (tag << 24 | local rank at [v][k]),
                             // then each row's star in rank order (local rank, tag 0)
     uint16_t *star_nbr;     // sum n^2: the other endpoint (local), rank order
-    uint32_t *star_k;       // sum n^2 + 64V: stars in neighbour order (neighbour | rank-order position << 16),
-                            // each followed by 64 sentinels
+    uint32_t *star_k;       // 3 sum n^2 + 260 V: per vertex, its prefix lists (the star in neighbour
+                            // order, entries neighbour | rank-order position << 16, whole and cut at
+                            // each quarter of the rank order), each followed by 64 sentinels
     uint32_t *deg;          // V: star sizes
     uint16_t *pos;          // sum n^2, in the star slots: entry k of v's slot = position of edge {v,k}
                             // in v's rank-ordered star (set for v's neighbours only)
