@@ -561,13 +561,12 @@ def _tetra(vr, torch, reps=10):
             "list_ms_per_call": round(lms, 5), "list_GBps": 16 * total / (lms * 1e-3) / 1e9}
 
 
-def _pairs_dim0(vr, torch, reps=20):
-    """Dimension-0 persistence pairs of the circle1000 build: a (min, max)
-    closure of the padded n x n rank matrix (2 * ld^3 integer min/max
-    operations, ld = 64 * ceil(n / 64)), timed with HIP events on the current
-    stream around each call.  The ALU peak counts one 32-bit integer
-    operation per lane per cycle: 256 CUs x 64 lanes x 2.4 GHz."""
-    c = _workload("circle1000")
+def _pairs_dim0(vr, torch, reps=20, workload="circle1000"):
+    """Dimension-0 persistence pairs of a build: above 512 points a spanning
+    forest in rank order (one work-group: every edge's roots found in
+    parallel, at most n - 1 serial unions), timed with HIP events on the
+    current stream around each call; the rate is kept edges per second."""
+    c = _workload(workload)
     pts = torch.from_numpy(c.points).to("cuda:0")
     r = vr.build(pts, c.thr)
     for _ in range(2):
@@ -582,11 +581,40 @@ def _pairs_dim0(vr, torch, reps=20):
     ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
     n, K, _ = r.counts
     r.free()
-    ld = 64 * ((n + 63) // 64)
-    ops = 2 * ld ** 3
-    peak = 256 * 64 * 2.4e9
-    return {"ms_per_call": round(ms, 5), "n": n, "K": K, "minmax_ops": ops,
-            "alu_frac": round(ops / (ms * 1e-3) / peak, 4)}
+    return {"ms_per_call": round(ms, 5), "n": n, "K": K, "edges_per_s": K / (ms * 1e-3)}
+
+
+def _pairs_dim1(vr, torch, reps=5, workload="circle1000"):
+    """All persistence pairs of dimension 1 and the barcode of dimensions 0
+    and 1 of a build (dimension-0 pairs first, as the clearing needs them):
+    the apparent pairs in one pass over the keys, then the remaining edge
+    columns reduced youngest first by one work-group.  Wall time of the
+    three calls (each synchronises for its status), median of reps."""
+    c = _workload(workload)
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    r = vr.build(pts, c.thr)
+    torch.cuda.synchronize()
+    ts = []
+    for i in range(reps + 1):
+        t0 = time.perf_counter()
+        e_low, _ = vr.pairs_dim0(r)
+        toe = vr.pairs_dim1(r, e_low)
+        bars, ess2 = vr.barcode(r, e_low, toe)
+        torch.cuda.synchronize()
+        if i:
+            ts.append(time.perf_counter() - t0)
+    n, K, T = r.counts
+    app = vr.pairs_dim1_apparent(r)
+    n_app = int((app >= 0).sum().item())
+    n_dim0 = int((e_low >= 0).sum().item())
+    n_pair1 = int((toe >= 0).sum().item())
+    b = bars.cpu()
+    inf = 2 ** 63 - 1
+    betti = [int(((b[:, 0] == 0) & (b[:, 2] == inf)).sum()), int(((b[:, 0] == 1) & (b[:, 2] == inf)).sum()), ess2]
+    r.free()
+    return {"ms_per_call": round(1e3 * sorted(ts)[len(ts) // 2], 4), "n": n, "K": K, "T": T,
+            "apparent_pairs": n_app, "columns_reduced": K - n_app - n_dim0, "pairs_dim1": n_pair1,
+            "positive_bars_dim1": int(((b[:, 0] == 1) & (b[:, 2] != inf)).sum()), "betti": betti}
 
 
 def _enum_bytes(n, K, T, n2):
@@ -652,6 +680,7 @@ def main():
         return
     if args.workload == "pairs0":  # pairs of circle1000 alone (profiling)
         print(json.dumps({"workload": "pairs_dim0_circle1000", **_pairs_dim0(vr, torch, reps=args.steps),
+                          "pairs_dim1_barcode": _pairs_dim1(vr, torch),
                           "apparent_dim1": _apparent(vr, torch, reps=args.steps),
                           "tetra_counts": _tetra(vr, torch, reps=args.steps)}), flush=True)
         return
@@ -714,6 +743,9 @@ def main():
         extra["hamming1088_full_matrix"] = _hamming(vr, torch, tune=not args.no_tune)
         extra["column_order_2000x1999"] = _column_order(vr, torch)
         extra["pairs_dim0_circle1000"] = _pairs_dim0(vr, torch)
+        extra["pairs_dim0_mixture4000"] = _pairs_dim0(vr, torch, workload="mixture4000")
+        extra["pairs_dim1_barcode_circle1000"] = _pairs_dim1(vr, torch)
+        extra["pairs_dim1_barcode_mixture4000"] = _pairs_dim1(vr, torch, reps=3, workload="mixture4000")
         extra["pairs_dim1_apparent_circle1000"] = _apparent(vr, torch)
         extra["tetra_counts_circle1000"] = _tetra(vr, torch)
         extra["schur_f2_16384"] = _schur(vr, torch)

@@ -301,8 +301,11 @@ VR_API int vr_column_order_noalloc(const int64_t *colptr, int64_t ncols, const i
  * death:  device, n int32, caller-owned: the edge rank that pairs vertex v,
  *         or -1 for the smallest vertex of each final component (an
  *         infinite bar).
- * Enqueued on `stream`; scratch of 4 (64 ceil(n / 64))^2 bytes comes from
- * the library's cache.  VR_EINVAL for a null argument or n > VR_MAX_POINTS. */
+ * Enqueued on `stream`.  Up to 512 points the pairs come from the (min, max)
+ * closure of the rank matrix, with scratch of 4 (64 ceil(n / 64))^2 bytes
+ * from the library's cache; larger clouds use a spanning forest in rank
+ * order (K finds and at most n - 1 unions, no scratch).  VR_EINVAL for a
+ * null argument or n > VR_MAX_POINTS. */
 VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, void *stream);
 
 /* Apparent persistence pairs in dimension 1 (Section 2.2.1, Alg. 1 on the
@@ -319,6 +322,53 @@ VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_t *death, v
  * Enqueued on `stream`; allocates nothing.  VR_EINVAL for a null argument,
  * a result without keys, or T >= 2^31. */
 VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, void *stream);
+
+/* All persistence pairs in dimension 1 (Section 2.2.1, Alg. 1, run as in
+ * Section 2.2.2 on the anti-transpose of the boundary matrix with
+ * clearing): the edge columns go from the youngest edge to the oldest, and
+ * the pivot of an edge's column is its oldest cofacet (the smallest
+ * triangle key).  Edges paired with a vertex are cleared (their columns
+ * reduce to zero); an edge with triangles of its own value pairs with the
+ * first of them (as in vr_pairs_dim1_apparent); every other edge's column is
+ * reduced, youngest first, by one work-group.  The pairs equal those of the
+ * column algorithm on the whole boundary matrix (Section 2.2.2).
+ * res:          a single build's result with its triangle keys (maxdim 2,
+ *               not count-only).
+ * e_low:        device, K int32: vr_pairs_dim0's e_low for this result.
+ * tri_of_edge:  device, K int32, caller-owned output: the index in tri_key
+ *               of the triangle paired with edge r (bar [r, its value); of
+ *               length zero when its value is r), or -1: edge r is paired
+ *               with a vertex (e_low[r] >= 0), or else starts a class of
+ *               dimension 1 that never dies.
+ * The working column is a base list in device memory plus a short sorted
+ * delta in LDS that takes the additions and is folded into the base when
+ * full.  Synchronises `stream` (a status word is read back).  Scratch from
+ * the library's cache: 4 n^2 + 24 K + 12 H bytes (H = 2K rounded up to a
+ * power of two) plus 224 MiB (the reduced columns, 2^24 keys, and three
+ * working lists of 2^22 keys).  VR_ENOMEM when the columns outgrow that.
+ * VR_EINVAL for a null argument, n > VR_MAX_POINTS or T >= 2^31.  With no
+ * triangles (T = 0) no edge dies. */
+VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, int32_t *tri_of_edge, void *stream);
+
+/* The barcode of dimensions 0 and 1 from the pairs (Section 2.2.1: a pair
+ * (sigma, tau) is the bar [value of sigma, value of tau); a simplex paired
+ * with nothing that kills nothing starts a bar that never ends).  Values:
+ * -1 for vertices, the rank for edges, the value for triangles; a bar that
+ * never ends has death INT64_MAX.  Bars of length zero are left out.
+ * e_low, tri_of_edge: vr_pairs_dim0's and vr_pairs_dim1's outputs.
+ * bars:    device, 3 (n + K) int64, caller-owned: (dimension, birth, death)
+ *          triples.  bars[0, n): dimension 0, first [-1, r) for every edge
+ *          r paired with a vertex, in edge order, then [-1, inf) for each
+ *          vertex no edge pairs; from bars[n]: dimension 1 in edge order,
+ *          [r, value) for edge r paired with a later triangle, [r, inf) for
+ *          an edge paired with nothing.
+ * counts:  host, 3 int64: n, the bars of dimension 1 written, and the
+ *          triangles paired with nothing (bars [value, inf) of dimension 2,
+ *          not listed).
+ * Synchronises `stream`.  VR_EINVAL for a null argument, n > VR_MAX_POINTS
+ * or T >= 2^31. */
+VR_API int vr_barcode(const vr_result *res, const int32_t *e_low, const int32_t *tri_of_edge, int64_t *bars,
+                      int64_t counts[3], void *stream);
 
 /* Tetrahedra (dimension 3) of a build's filtration, counted per largest
  * edge: a tetrahedron exists once its six edges are kept, and its value is

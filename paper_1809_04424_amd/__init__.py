@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_blockprodsum_count", "vr_blockprodsum_write",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_pairs_dim1", "vr_barcode", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -121,6 +121,11 @@ def lib():
         L.vr_pairs_dim0.restype = ctypes.c_int
         L.vr_pairs_dim1_apparent.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
         L.vr_pairs_dim1_apparent.restype = ctypes.c_int
+        L.vr_pairs_dim1.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_pairs_dim1.restype = ctypes.c_int
+        L.vr_barcode.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.vr_barcode.restype = ctypes.c_int
         L.vr_tetra_counts.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
         L.vr_tetra_counts.restype = ctypes.c_int
         L.vr_tetra_offsets.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p]
@@ -657,6 +662,52 @@ def pairs_dim1_apparent(result):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return out
+
+
+def pairs_dim1(result, e_low):
+    """All persistence pairs of dimension 1 (Section 2.2.1, reduced as in
+    Section 2.2.2): an int32 device tensor of K entries, the index in tri_key
+    of the triangle paired with edge r, or -1.  e_low is pairs_dim0's."""
+    import torch
+
+    L = lib()
+    n, K, T = result.counts
+    dev = result._device
+    if not isinstance(e_low, torch.Tensor) or e_low.dtype != torch.int32 or e_low.numel() != K or e_low.device != dev:
+        raise TypeError("e_low must be pairs_dim0's int32 tensor of K entries on the result's device")
+    e_low = e_low.contiguous()
+    out = torch.empty(K, dtype=torch.int32, device=dev)
+    r = VrResult(n, K, T, result._p_ij, result._p_q, result._p_tri)
+    stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = L.vr_pairs_dim1(ctypes.byref(r), ctypes.c_void_p(e_low.data_ptr() if K else 0),
+                             ctypes.c_void_p(out.data_ptr() if K else 0), ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return out
+
+
+def barcode(result, e_low, tri_of_edge):
+    """Bars of dimensions 0 and 1: an (m, 3) int64 device tensor of
+    (dimension, birth, death) rows (death 2^63 - 1 for a bar that never
+    ends; bars of length zero left out), and the number of triangles paired
+    with nothing (bars of dimension 2 that never end, not listed)."""
+    import torch
+
+    L = lib()
+    n, K, T = result.counts
+    dev = result._device
+    bars = torch.empty((n + K, 3), dtype=torch.int64, device=dev)
+    counts = (ctypes.c_int64 * 3)()
+    r = VrResult(n, K, T, result._p_ij, result._p_q, result._p_tri)
+    stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = L.vr_barcode(ctypes.byref(r), ctypes.c_void_p(e_low.data_ptr() if K else 0),
+                          ctypes.c_void_p(tri_of_edge.data_ptr() if K else 0),
+                          ctypes.c_void_p(bars.data_ptr() if n + K else 0), counts, ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return bars[: counts[0] + counts[1]], int(counts[2])
 
 
 def tetra_counts(result):

@@ -32,6 +32,9 @@
 #define PD_T 64      // tile edge
 #define PD_BLOCK 256  // 16 x 16 threads, 4 x 4 entries each
 #define PD_INF 0x7FFFFFFF
+// Largest point count whose dimension-0 pairs come from the (min, max)
+// closure; larger clouds use the spanning forest.
+#define PD_CLOSURE_MAX 512
 
 __global__ void __launch_bounds__(PD_BLOCK) k_pd_fill(int32_t *D, int64_t m) {
     const int64_t ld = m;
@@ -183,6 +186,84 @@ __global__ void __launch_bounds__(PD_BLOCK) k_pd_emit(const int32_t *death, int6
     if (r >= 0 && r < K) e_low[r] = (int32_t)v;
 }
 
+// Dimension 0 by a spanning forest (Kruskal's order): the edges in rank
+// order, a union-find whose roots are the smallest vertex of each component
+// (the larger root is linked under the smaller), so the column algorithm's
+// pair for an edge joining two components is the larger of the two roots.
+// One work-group takes the edges 1024 at a time: every thread finds the
+// roots of its edge's ends without writing, and only the edges whose ends
+// lie in different components (the candidates) go, in rank order, through
+// the serial union by one thread, which finds again (an earlier candidate
+// of the chunk may have joined the two).  Work: K reads and finds, plus the
+// serial step for at most n - 1 unions and the candidates that lost to an
+// earlier one; it stops once n - 1 unions are made.
+#define PF_BLOCK 1024
+__global__ void __launch_bounds__(PF_BLOCK) k_pd_forest(const int32_t *ij, int64_t K, int64_t n, int32_t *e_low,
+                                                       int32_t *death) {
+    __shared__ int32_t par[VR_MAX_POINTS];
+    __shared__ int32_t cand[PF_BLOCK], ca[PF_BLOCK], cb[PF_BLOCK];
+    __shared__ uint32_t wc[PF_BLOCK / 64];
+    __shared__ int32_t s_unions;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int64_t v = t; v < n; v += PF_BLOCK) par[v] = (int32_t)v;
+    if (t == 0) s_unions = 0;
+    __syncthreads();
+    for (int64_t e0 = 0; e0 < K && s_unions < n - 1; e0 += PF_BLOCK) {
+        const int64_t e = e0 + t;
+        bool c = false;
+        int32_t ea = 0, eb = 0;
+        if (e < K) {
+            ea = ij[2 * e];
+            eb = ij[2 * e + 1];
+            if (ea >= 0 && eb >= 0 && ea < n && eb < n) {  // always for a library result
+                int32_t a = ea, b = eb;
+                while (par[a] != a) a = par[a];
+                while (par[b] != b) b = par[b];
+                c = a != b;
+            }
+        }
+        const unsigned long long m = __ballot(c);
+        if (lane == 0) wc[wv] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int w = 0; w < PF_BLOCK / 64; w++) {
+            if (w < wv) before += wc[w];
+            tot += wc[w];
+        }
+        if (c) {
+            const uint32_t at = before + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            cand[at] = (int32_t)(e - e0);
+            ca[at] = ea;
+            cb[at] = eb;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int32_t u = s_unions;
+            for (uint32_t i = 0; i < tot; i++) {
+                const int64_t f = e0 + cand[i];
+                int32_t a = ca[i], b = cb[i];
+                while (par[a] != a) {
+                    par[a] = par[par[a]];
+                    a = par[a];
+                }
+                while (par[b] != b) {
+                    par[b] = par[par[b]];
+                    b = par[b];
+                }
+                if (a != b) {
+                    const int32_t lo = min(a, b), hi = max(a, b);
+                    par[hi] = lo;
+                    e_low[f] = hi;
+                    death[hi] = (int32_t)f;
+                    u++;
+                }
+            }
+            s_unions = u;
+        }
+        __syncthreads();
+    }
+}
+
 // Dimension 1, apparent pairs.  Triangles of value r are the cofacets of
 // edge r whose other two edges are older, and the writer emits them
 // together in lexicographic order, so the first of them is the oldest
@@ -211,6 +292,16 @@ extern "C" VR_API int vr_pairs_dim0(const vr_result *res, int32_t *e_low, int32_
     if ((K > 0 && (!e_low || !res->edge_ij)) || (n > 0 && !death)) return VR_EINVAL;
     if (n == 0) return VR_OK;
     const hipStream_t s = (hipStream_t)stream;
+    if (n > PD_CLOSURE_MAX) {
+        // the spanning forest: K finds and at most n - 1 serial unions
+        hipLaunchKernelGGL(k_pd_clear, dim3(grid_for(n)), dim3(PD_BLOCK), 0, s, death, n);
+        if (K > 0) {
+            hipLaunchKernelGGL(k_pd_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, e_low, K);
+            hipLaunchKernelGGL(k_pd_forest, dim3(1), dim3(PF_BLOCK), 0, s, (const int32_t *)res->edge_ij, K, n, e_low,
+                               death);
+        }
+        return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
+    }
     const int64_t nb = (n + PD_T - 1) / PD_T, ld = nb * PD_T;
     int32_t *D = (int32_t *)cache_get((size_t)ld * (size_t)ld * 4, s);
     if (!D) return VR_ENOMEM;
@@ -509,4 +600,723 @@ extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, voi
     const hipError_t e = hipGetLastError();
     cache_put(D, s);
     return e == hipSuccess ? VR_OK : VR_EHIP;
+}
+
+// ------------------------------------------------ dimension 1, reduction ----
+// Persistence pairs of dimension 1: Algorithm 1 (Section 2.2.1) on the
+// anti-transpose of the boundary matrix, with clearing (Section 2.2.2), the
+// edge columns taken from the youngest edge to the oldest.  In
+// anti-transposed coordinates the column of edge r holds its cofacets (the
+// triangles containing it) and its pivot is its oldest cofacet: the
+// smallest key, since triangle keys (value << 39 | i << 26 | j << 13 | k)
+// sort in filtration order.  Three kinds of column:
+//   - cleared: an edge paired with a vertex (dimension 0) reduces to zero;
+//   - apparent: an edge with triangles of its own value keeps its
+//     coboundary, whose pivot is the first of them (a younger column holds
+//     only triangles of larger values), so the two pair at once;
+//   - the rest, reduced here by one work-group, youngest first: while the
+//     working column (sorted keys) is not empty, its pivot p is looked up;
+//     an apparent pivot adds that edge's coboundary, the pivot of a column
+//     reduced before adds that column, and a new pivot pairs the edge with
+//     p (a bar [r, value of p)) and stores the column under p.  A column
+//     that empties is a class born at r that never dies.
+// Additions are over F2: the symmetric difference of two sorted lists, a
+// merge that drops the keys present in both.  Every addition removes the
+// pivot and adds only larger keys, so the pivot grows and the loop ends.
+#define RD_BLOCK 1024
+#define RD_WAVES (RD_BLOCK / 64)
+#define RD_GEN_MAX 8192                    // coboundary of one edge: at most n - 2 triangles
+#define RD_POOL_ENTRIES (1ll << 24)        // stored reduced columns (keys)
+#define RD_WORK_ENTRIES (1ll << 22)        // one working column (keys)
+#define RD_EMPTY 0ull                      // no triangle key is 0 (its largest vertex is >= 2)
+
+struct RdCtl {
+    int32_t m;        // columns to reduce
+    int32_t err;      // 1: stored columns outgrew the pool, 2: a working column outgrew its buffer
+};
+
+struct RdBufs {
+    const int32_t *R;               // n x n ranks (+inf off the edges, -1 on the diagonal)
+    const int32_t *ij;              // K edges (i, j)
+    const unsigned long long *key;  // T triangle keys, filtration order
+    const int32_t *first;           // K: first triangle of value r, or -1 (the apparent pairs)
+    const int32_t *rem;             // the columns to reduce, youngest first
+    unsigned long long *tkey;       // table of pivots: key (RD_EMPTY: free slot)
+    int32_t *tcol;                  //   and the column holding it
+    long long hmask;                // table slots - 1 (a power of two, at least twice the columns)
+    unsigned long long *pool;       // reduced columns, back to back
+    long long *cstart;              // column ci: its keys start here in the pool
+    int32_t *clen;                  //   and number this many
+    unsigned long long *w[2];       // working column, ping-pong
+    unsigned long long *mrg;        // merged keys before the cancellation
+    unsigned long long *rkey;       // per column: its pivot, or RD_EMPTY for a class that never dies
+    RdCtl *ctl;
+    int64_t n, K;
+};
+
+// Columns to reduce: edges with neither a vertex (e_low) nor an apparent
+// triangle (first), from the youngest down.  One work-group.
+__global__ void __launch_bounds__(RD_BLOCK) k_rd_list(const int32_t *first, const int32_t *e_low, int64_t K,
+                                                     int32_t *rem, RdCtl *ctl) {
+    __shared__ uint32_t wc[RD_WAVES];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t run = 0;
+    for (int64_t base = K - 1; base >= 0; base -= RD_BLOCK) {
+        const int64_t r = base - t;
+        const bool keep = r >= 0 && first[r] < 0 && e_low[r] < 0;
+        const unsigned long long b = __ballot(keep);
+        if (lane == 0) wc[wv] = (uint32_t)__popcll(b);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int w = 0; w < RD_WAVES; w++) {
+            if (w < wv) before += wc[w];
+            tot += wc[w];
+        }
+        if (keep) rem[run + before + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] = (int32_t)r;
+        run += tot;
+        __syncthreads();
+    }
+    if (t == 0) {
+        ctl->m = (int32_t)run;
+        ctl->err = 0;
+    }
+}
+
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_zero(unsigned long long *p, int64_t m) {
+    for (int64_t x = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < m; x += (int64_t)gridDim.x * PD_BLOCK) p[x] = 0ull;
+}
+
+// Exclusive scan of one value per thread over the work-group; *total gets the sum.
+static __device__ __forceinline__ uint32_t rd_scan(uint32_t x, uint32_t *sh, uint32_t *total) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int w = 0; w < RD_WAVES; w++) {
+        const uint32_t v = sh[w];
+        if (w < wv) before += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
+}
+
+static __device__ __forceinline__ unsigned long long rd_tri_key(uint32_t v, uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t lo = min(a, min(b, c)), hi = max(a, max(b, c)), mid = a + b + c - lo - hi;
+    return ((unsigned long long)v << 39) | ((unsigned long long)lo << 26) | ((unsigned long long)mid << 13) | hi;
+}
+
+// The coboundary of edge e, sorted, into g (LDS); returns its length.
+static __device__ uint32_t rd_gen(const RdBufs &B, int64_t e, unsigned long long *g, uint32_t *sh) {
+    const int t = threadIdx.x;
+    const int32_t a = B.ij[2 * e], b = B.ij[2 * e + 1];
+    const int32_t *Ra = B.R + (int64_t)a * B.n, *Rb = B.R + (int64_t)b * B.n;
+    uint32_t run = 0;
+    for (int64_t k0 = 0; k0 < B.n; k0 += RD_BLOCK) {
+        const int64_t k = k0 + t;
+        const int64_t kc = k < B.n ? k : B.n - 1;
+        const int32_t x = Ra[kc], y = Rb[kc];
+        const bool ok = k < B.n && k != a && k != b && x != PD_INF && y != PD_INF;
+        uint32_t tot;
+        const uint32_t at = rd_scan(ok ? 1u : 0u, sh, &tot);
+        if (ok) g[run + at] = rd_tri_key((uint32_t)max((int32_t)e, max(x, y)), (uint32_t)a, (uint32_t)b, (uint32_t)k);
+        run += tot;
+    }
+    // bitonic sort of the keys, padded to a power of two with the largest key
+    uint32_t P = 1;
+    while (P < run) P <<= 1;
+    for (uint32_t x = run + t; x < P; x += RD_BLOCK) g[x] = ~0ull;
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= P; kk <<= 1)
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = t; i < P / 2; i += RD_BLOCK) {
+                const uint32_t lo = 2 * i - (i & (j - 1)), hi = lo + j;
+                const unsigned long long x0 = g[lo], x1 = g[hi];
+                if ((x0 > x1) == ((lo & kk) == 0)) {
+                    g[lo] = x1;
+                    g[hi] = x0;
+                }
+            }
+            __syncthreads();
+        }
+    return run;
+}
+
+// dst = a + b over F2 (a, b sorted, without repeats); returns dst's length,
+// or ~0u when it would not fit.  mrg holds the plain merge.
+static __device__ uint32_t rd_add(const unsigned long long *a, uint32_t na, const unsigned long long *b, uint32_t nb,
+                                  unsigned long long *mrg, unsigned long long *dst, uint32_t *sh) {
+    const int t = threadIdx.x;
+    const uint32_t L = na + nb;
+    if ((long long)L > RD_WORK_ENTRIES) return ~0u;
+    const uint32_t S = (L + RD_BLOCK - 1) / RD_BLOCK;
+    const uint32_t d0 = min(L, (uint32_t)t * S), d1 = min(L, d0 + S);
+    // merge path: a[i] goes before b[d - i] when a[i] <= b[d - i]
+    uint32_t lo = d0 > nb ? d0 - nb : 0u, hi = min(d0, na);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= b[d0 - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t i = lo, j = d0 - lo;
+    for (uint32_t d = d0; d < d1; d++) {
+        const bool take_a = j >= nb || (i < na && a[i] <= b[j]);
+        mrg[d] = take_a ? a[i++] : b[j++];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // a key in both lists sits twice in a row: drop both
+    uint32_t c = 0;
+    for (uint32_t d = d0; d < d1; d++) {
+        const unsigned long long x = mrg[d];
+        c += ((d == 0 || mrg[d - 1] != x) && (d + 1 == L || mrg[d + 1] != x)) ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t o = rd_scan(c, sh, &tot);
+    for (uint32_t d = d0; d < d1; d++) {
+        const unsigned long long x = mrg[d];
+        if ((d == 0 || mrg[d - 1] != x) && (d + 1 == L || mrg[d + 1] != x)) dst[o++] = x;
+    }
+    __threadfence_block();
+    __syncthreads();
+    return tot;
+}
+
+static __device__ __forceinline__ long long rd_slot(unsigned long long p, long long hmask) {
+    return (long long)((p * 0x9E3779B97F4A7C15ull) >> 20) & hmask;
+}
+
+// The working column is kept in two parts whose sum (over F2) it is: a base
+// list in global memory, of which the entries before a head index are gone,
+// and a short delta list in LDS (at most RD_DCAP keys), also with a head.
+// Additions go into the delta by a merge in LDS; only when the delta would
+// overflow is it folded into the base, one pass over the base.  The pivot
+// is the smallest key of the sum: the two heads, skipping keys present in
+// both (they cancel).  A column of the essential class of the noisy circle
+// takes 3537 additions and grows to 90 thousand keys, so re-merging the
+// whole column at every addition would dominate.
+#define RD_DCAP 4096
+
+static __device__ __forceinline__ uint32_t rd_lower_bound(const unsigned long long *a, uint32_t n, unsigned long long x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// dst = a + b over F2 for a sorted base a (global, na keys) and a sorted
+// delta b (LDS, nb <= RD_DCAP keys); sc: LDS scratch of 2 RD_DCAP uint32.
+// Returns the length.  A delta key is matched when the base holds it
+// (both vanish); an unmatched delta key b_j lands at pos_j + j - 2 M_j
+// (pos_j: base keys below it, M_j: matched delta keys before it), an
+// unmatched base key a_i at i + r - 2 M_r (r: delta keys below it).
+static __device__ uint32_t rd_fold(const unsigned long long *a, uint32_t na, const unsigned long long *b, uint32_t nb,
+                                   unsigned long long *dst, uint32_t *sc, uint32_t *sh) {
+    const int t = threadIdx.x;
+    uint32_t *pos = sc, *minc = sc + RD_DCAP;  // minc[j]: matched delta keys in [0, j]
+    uint32_t mloc[RD_DCAP / RD_BLOCK], cnt = 0;
+#pragma unroll
+    for (int u = 0; u < RD_DCAP / RD_BLOCK; u++) {
+        const uint32_t j = (uint32_t)t * (RD_DCAP / RD_BLOCK) + u;
+        mloc[u] = 0;
+        if (j < nb) {
+            const unsigned long long x = b[j];
+            const uint32_t q = rd_lower_bound(a, na, x);
+            pos[j] = q;
+            mloc[u] = (q < na && a[q] == x) ? 1u : 0u;
+        }
+        cnt += mloc[u];
+    }
+    uint32_t tot;
+    uint32_t run = rd_scan(cnt, sh, &tot);
+#pragma unroll
+    for (int u = 0; u < RD_DCAP / RD_BLOCK; u++) {
+        const uint32_t j = (uint32_t)t * (RD_DCAP / RD_BLOCK) + u;
+        run += mloc[u];
+        if (j < nb) minc[j] = run;
+    }
+    __syncthreads();
+    for (uint32_t j = t; j < nb; j += RD_BLOCK) {
+        const uint32_t mex = j ? minc[j - 1] : 0u;
+        if (minc[j] == mex) dst[pos[j] + j - 2 * mex] = b[j];
+    }
+    for (uint32_t i = t; i < na; i += RD_BLOCK) {
+        const unsigned long long y = a[i];
+        uint32_t lo = 0, hi = nb;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (b[mid] < y) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < nb && b[lo] == y) continue;
+        const uint32_t mex = lo ? minc[lo - 1] : 0u;
+        dst[i + lo - 2 * mex] = y;
+    }
+    __threadfence_block();
+    __syncthreads();
+    return na + nb - 2 * tot;
+}
+
+// o = d + x over F2 in LDS (d: nd keys in LDS, x: nx keys, LDS or global;
+// nd + nx <= RD_DCAP); returns the length.  Merge path, then the keys in
+// both lists (adjacent after the merge) are dropped in place.
+static __device__ uint32_t rd_delta_add(const unsigned long long *d, uint32_t nd, const unsigned long long *x, uint32_t nx,
+                                        unsigned long long *o, uint32_t *sh) {
+    const int t = threadIdx.x;
+    constexpr uint32_t S = RD_DCAP / RD_BLOCK;
+    const uint32_t L = nd + nx;
+    const uint32_t d0 = min(L, (uint32_t)t * S), d1 = min(L, d0 + S);
+    uint32_t lo = d0 > nx ? d0 - nx : 0u, hi = min(d0, nd);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (d[mid] <= x[d0 - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t i = lo, j = d0 - lo;
+    for (uint32_t q = d0; q < d1; q++) {
+        const bool take_d = j >= nx || (i < nd && d[i] <= x[j]);
+        o[q] = take_d ? d[i++] : x[j++];
+    }
+    __syncthreads();
+    unsigned long long v[S];
+    bool keep[S];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < S; u++) {
+        const uint32_t q = d0 + u;
+        keep[u] = false;
+        v[u] = 0;
+        if (q < d1) {
+            v[u] = o[q];
+            keep[u] = (q == 0 || o[q - 1] != v[u]) && (q + 1 == L || o[q + 1] != v[u]);
+        }
+        c += keep[u] ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t at = rd_scan(c, sh, &tot);  // its barriers also end every read of o above
+#pragma unroll
+    for (uint32_t u = 0; u < S; u++)
+        if (keep[u]) o[at++] = v[u];
+    __syncthreads();
+    return tot;
+}
+
+__global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
+    __shared__ unsigned long long g[RD_GEN_MAX];
+    __shared__ unsigned long long dl[2][RD_DCAP];
+    __shared__ uint32_t sh[RD_WAVES];
+    __shared__ int32_t s_act, s_arg;
+    __shared__ uint32_t s_h, s_dh;
+    __shared__ unsigned long long s_piv;
+    const int t = threadIdx.x;
+    const int32_t m = B.ctl->m;
+    int cur = 0, dc = 0;  // base buffer, delta buffer
+    long long top = 0;    // pool entries used (every thread keeps the same count)
+    for (int32_t ci = 0; ci < m; ci++) {
+        const int64_t r = B.rem[ci];
+        // base: empty; delta: the coboundary (or the base, when it is longer)
+        uint32_t nw = 0, h = 0, nd = 0, dh = 0;
+        {
+            const uint32_t len = rd_gen(B, r, g, sh);
+            if (len <= RD_DCAP) {
+                for (uint32_t x = t; x < len; x += RD_BLOCK) dl[dc][x] = g[x];
+                nd = len;
+            } else {
+                for (uint32_t x = t; x < len; x += RD_BLOCK) B.w[cur][x] = g[x];
+                nw = len;
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+        for (;;) {
+            if (t == 0) {
+                // the pivot: the smaller head, keys in both heads cancelling
+                unsigned long long p = 0;
+                bool any = false;
+                for (;;) {
+                    const bool ha = h < nw, hb = dh < nd;
+                    if (!ha && !hb) break;
+                    const unsigned long long ya = ha ? B.w[cur][h] : ~0ull, yb = hb ? dl[dc][dh] : ~0ull;
+                    if (ha && hb && ya == yb) {
+                        h++;
+                        dh++;
+                        continue;
+                    }
+                    p = min(ya, yb);
+                    any = true;
+                    break;
+                }
+                // 0: never dies; 1: add the coboundary of edge s_arg; 2: add
+                // stored column s_arg; 3: new pivot
+                int32_t act = 0, arg = -1;
+                if (any) {
+                    const int64_t v = (int64_t)(p >> 39);
+                    const int32_t f = v < B.K ? B.first[v] : -1;
+                    if (f >= 0 && B.key[f] == p) {
+                        act = 1;
+                        arg = (int32_t)v;
+                    } else {
+                        act = 3;
+                        for (long long s = rd_slot(p, B.hmask);; s = (s + 1) & B.hmask) {
+                            const unsigned long long q = B.tkey[s];
+                            if (q == RD_EMPTY) break;
+                            if (q == p) {
+                                act = 2;
+                                arg = B.tcol[s];
+                                break;
+                            }
+                        }
+                    }
+                }
+                s_act = act;
+                s_arg = arg;
+                s_piv = p;
+                s_h = h;
+                s_dh = dh;
+            }
+            __syncthreads();
+            const int32_t act = s_act, arg = s_arg;
+            const unsigned long long p = s_piv;
+            h = s_h;
+            dh = s_dh;
+            __syncthreads();
+            if (act == 0 || act == 3) {
+                if (act == 3) {
+                    // store the column (base + delta) in the pool under p
+                    const uint32_t len_max = (nw - h) + (nd - dh);
+                    if (top + len_max > RD_POOL_ENTRIES) {
+                        if (t == 0) B.ctl->err = 1;
+                        return;
+                    }
+                    const uint32_t len = rd_fold(B.w[cur] + h, nw - h, dl[dc] + dh, nd - dh, B.pool + top,
+                                                 (uint32_t *)dl[dc ^ 1], sh);
+                    if (t == 0) {
+                        B.cstart[ci] = top;
+                        B.clen[ci] = (int32_t)len;
+                        long long s = rd_slot(p, B.hmask);
+                        while (B.tkey[s] != RD_EMPTY) s = (s + 1) & B.hmask;
+                        B.tkey[s] = p;
+                        B.tcol[s] = ci;
+                    }
+                    top += len;
+                }
+                if (t == 0) B.rkey[ci] = act == 3 ? p : RD_EMPTY;
+                __threadfence_block();
+                __syncthreads();
+                break;
+            }
+            // the column to add: a coboundary (in g) or a stored column
+            const unsigned long long *x;
+            uint32_t nx;
+            if (act == 1) {
+                nx = rd_gen(B, arg, g, sh);
+                x = g;
+            } else {
+                x = B.pool + B.cstart[arg];
+                nx = (uint32_t)B.clen[arg];
+            }
+            if ((nd - dh) + nx > RD_DCAP) {
+                // fold the delta into the base first
+                if ((long long)(nw - h) + (nd - dh) > RD_WORK_ENTRIES) {
+                    if (t == 0) B.ctl->err = 2;
+                    return;
+                }
+                nw = rd_fold(B.w[cur] + h, nw - h, dl[dc] + dh, nd - dh, B.w[cur ^ 1], (uint32_t *)dl[dc ^ 1], sh);
+                cur ^= 1;
+                h = 0;
+                nd = dh = 0;
+            }
+            if (nx <= RD_DCAP) {
+                nd = rd_delta_add(dl[dc] + dh, nd - dh, x, nx, dl[dc ^ 1], sh);
+                dc ^= 1;
+                dh = 0;
+            } else {
+                // a column longer than the delta goes straight into the base
+                const uint32_t nl = rd_add(B.w[cur] + h, nw - h, x, nx, B.mrg, B.w[cur ^ 1], sh);
+                if (nl == ~0u) {
+                    if (t == 0) B.ctl->err = 2;
+                    return;
+                }
+                cur ^= 1;
+                nw = nl;
+                h = 0;
+            }
+        }
+    }
+}
+
+// tri_of_edge[rem[ci]] = the index of column ci's pivot among the keys
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_emit(const unsigned long long *key, int64_t T, const int32_t *rem,
+                                                     const unsigned long long *rkey, const RdCtl *ctl,
+                                                     int32_t *tri_of_edge) {
+    const int32_t m = ctl->m;
+    for (int64_t ci = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; ci < m; ci += (int64_t)gridDim.x * PD_BLOCK) {
+        const unsigned long long p = rkey[ci];
+        if (p == RD_EMPTY) continue;
+        int64_t lo = 0, hi = T;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (key[mid] < p) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < T && key[lo] == p) tri_of_edge[rem[ci]] = (int32_t)lo;
+    }
+}
+
+extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, int32_t *tri_of_edge, void *stream) {
+    if (!res) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges, T = res->n_triangles;
+    if (n < 0 || K < 0 || T < 0 || n > VR_MAX_POINTS || T > 0x7FFFFFFF) return VR_EINVAL;
+    if (K == 0) return VR_OK;
+    if (!tri_of_edge || !e_low || !res->edge_ij || (T > 0 && !res->tri_key)) return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_pd_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K);
+    if (T == 0) return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;  // no triangles: nothing dies
+    hipLaunchKernelGGL(k_pd_apparent, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key,
+                       T, tri_of_edge, K);
+    // scratch, from the library's cache
+    long long H = 2;
+    while (H < 2 * K) H <<= 1;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t o = 0;
+    const size_t o_R = o; o = up(o + 4 * (size_t)n * (size_t)n);
+    const size_t o_rem = o; o = up(o + 4 * (size_t)K);
+    const size_t o_tkey = o; o = up(o + 8 * (size_t)H);
+    const size_t o_tcol = o; o = up(o + 4 * (size_t)H);
+    const size_t o_pool = o; o = up(o + 8 * (size_t)RD_POOL_ENTRIES);
+    const size_t o_cst = o; o = up(o + 8 * (size_t)K);
+    const size_t o_cln = o; o = up(o + 4 * (size_t)K);
+    const size_t o_w0 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
+    const size_t o_w1 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
+    const size_t o_mrg = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
+    const size_t o_rkey = o; o = up(o + 8 * (size_t)K);
+    const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
+    char *ws = (char *)cache_get(o, s);
+    if (!ws) return VR_ENOMEM;
+    RdBufs B;
+    B.R = (const int32_t *)(ws + o_R);
+    B.ij = (const int32_t *)res->edge_ij;
+    B.key = (const unsigned long long *)res->tri_key;
+    B.first = tri_of_edge;
+    B.rem = (const int32_t *)(ws + o_rem);
+    B.tkey = (unsigned long long *)(ws + o_tkey);
+    B.tcol = (int32_t *)(ws + o_tcol);
+    B.hmask = H - 1;
+    B.pool = (unsigned long long *)(ws + o_pool);
+    B.cstart = (long long *)(ws + o_cst);
+    B.clen = (int32_t *)(ws + o_cln);
+    B.w[0] = (unsigned long long *)(ws + o_w0);
+    B.w[1] = (unsigned long long *)(ws + o_w1);
+    B.mrg = (unsigned long long *)(ws + o_mrg);
+    B.rkey = (unsigned long long *)(ws + o_rkey);
+    B.ctl = (RdCtl *)(ws + o_ctl);
+    B.n = n;
+    B.K = K;
+    hipLaunchKernelGGL(k_rd_list, dim3(1), dim3(RD_BLOCK), 0, s, (const int32_t *)tri_of_edge, e_low, K,
+                       (int32_t *)(ws + o_rem), B.ctl);
+    hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n);
+    hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n,
+                       (const int32_t *)res->edge_ij, K, n);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(H)), dim3(PD_BLOCK), 0, s, B.tkey, H);
+    hipLaunchKernelGGL(k_rd_reduce, dim3(1), dim3(RD_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_rd_emit, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key, T,
+                       (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
+                       tri_of_edge);
+    int32_t err = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, &B.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cache_put(ws, s);
+    if (e != hipSuccess) return VR_EHIP;
+    return err ? VR_ENOMEM : VR_OK;
+}
+
+// ------------------------------------------------------------ barcode ----
+// Bars of dimensions 0 and 1 from the pairs (birth, death in filtration
+// values: -1 for vertices, the rank for edges, the value for triangles;
+// death INT64_MAX for a class that never dies), as (dimension, birth,
+// death) int64 triples: bars[0, n) = dimension 0 (an edge r paired with a
+// vertex gives [-1, r), in edge order, then the vertices no edge pairs
+// give [-1, inf)); from n, dimension 1 in edge order (edge r paired with a
+// triangle of larger value t gives [r, t); an edge paired with nothing
+// gives [r, inf); zero-length pairs give no bar).  Per 1024-edge chunk the
+// two kinds are counted, the counts scanned, then the bars written.
+#define BC_CHUNK 1024
+__device__ __forceinline__ bool bc_dim0(const int32_t *e_low, int64_t r) { return e_low[r] >= 0; }
+__device__ __forceinline__ bool bc_dim1(const int32_t *e_low, const int32_t *toe, const unsigned long long *key,
+                                        int64_t r) {
+    const int32_t t = toe[r];
+    if (t >= 0) return (int64_t)(key[t] >> 39) > r;
+    return e_low[r] < 0;
+}
+
+__global__ void __launch_bounds__(BC_CHUNK) k_bc_count(const int32_t *e_low, const int32_t *toe,
+                                                      const unsigned long long *key, int64_t K, int32_t *cnt) {
+    __shared__ uint32_t sh[BC_CHUNK / 64][2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t r = (int64_t)blockIdx.x * BC_CHUNK + t;
+    const bool d0 = r < K && bc_dim0(e_low, r), d1 = r < K && bc_dim1(e_low, toe, key, r);
+    const unsigned long long b0 = __ballot(d0), b1 = __ballot(d1);
+    if (lane == 0) {
+        sh[wv][0] = (uint32_t)__popcll(b0);
+        sh[wv][1] = (uint32_t)__popcll(b1);
+    }
+    __syncthreads();
+    if (t < 2) {
+        uint32_t s = 0;
+        for (int w = 0; w < BC_CHUNK / 64; w++) s += sh[w][t];
+        cnt[2 * (int64_t)blockIdx.x + t] = (int32_t)s;
+    }
+}
+
+// exclusive scan of the per-chunk counts (two interleaved series) into off
+// (int64); off[2 nch] / off[2 nch + 1] get the totals.  One work-group.
+__global__ void __launch_bounds__(BC_CHUNK) k_bc_scan(const int32_t *cnt, int64_t nch, long long *off) {
+    __shared__ long long sh[BC_CHUNK / 64][2];
+    __shared__ long long carry[2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t < 2) carry[t] = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nch; c0 += BC_CHUNK) {
+        const int64_t c = c0 + t;
+        long long x[2];
+        for (int s = 0; s < 2; s++) {
+            x[s] = c < nch ? cnt[2 * c + s] : 0;
+            long long inc = x[s];
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long y = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += y;
+            }
+            if (lane == 63) sh[wv][s] = inc;
+            x[s] = inc - x[s];
+        }
+        __syncthreads();
+        long long tot[2] = {0, 0};
+        for (int s = 0; s < 2; s++) {
+            long long before = 0;
+            for (int w = 0; w < BC_CHUNK / 64; w++) {
+                if (w < wv) before += sh[w][s];
+                tot[s] += sh[w][s];
+            }
+            if (c < nch) off[2 * c + s] = carry[s] + before + x[s];
+        }
+        __syncthreads();
+        if (t < 2) carry[t] += tot[t];
+        __syncthreads();
+    }
+    if (t < 2) off[2 * nch + t] = carry[t];
+}
+
+__global__ void __launch_bounds__(BC_CHUNK) k_bc_write(const int32_t *e_low, const int32_t *toe,
+                                                      const unsigned long long *key, int64_t n, int64_t K,
+                                                      const long long *off, long long *bars) {
+    __shared__ uint32_t sh[BC_CHUNK / 64][2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t r = (int64_t)blockIdx.x * BC_CHUNK + t;
+    const bool d0 = r < K && bc_dim0(e_low, r), d1 = r < K && bc_dim1(e_low, toe, key, r);
+    const unsigned long long b0 = __ballot(d0), b1 = __ballot(d1);
+    if (lane == 0) {
+        sh[wv][0] = (uint32_t)__popcll(b0);
+        sh[wv][1] = (uint32_t)__popcll(b1);
+    }
+    __syncthreads();
+    uint32_t before0 = 0, before1 = 0;
+    for (int w = 0; w < wv; w++) {
+        before0 += sh[w][0];
+        before1 += sh[w][1];
+    }
+    const long long INF = 0x7FFFFFFFFFFFFFFFll;
+    if (d0) {
+        const long long at = off[2 * (int64_t)blockIdx.x] + before0 +
+                             __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0));
+        bars[3 * at] = 0;
+        bars[3 * at + 1] = -1;
+        bars[3 * at + 2] = r;
+    }
+    if (d1) {
+        const long long at = n + off[2 * (int64_t)blockIdx.x + 1] + before1 +
+                             __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0));
+        const int32_t tt = toe[r];
+        bars[3 * at] = 1;
+        bars[3 * at + 1] = r;
+        bars[3 * at + 2] = tt >= 0 ? (long long)(key[tt] >> 39) : INF;
+    }
+}
+
+// the vertices no edge pairs: [-1, inf) at bars [f0, n), f0 = finite bars of dimension 0
+__global__ void __launch_bounds__(PD_BLOCK) k_bc_ess0(const long long *f0p, int64_t n, long long *bars) {
+    const long long f0 = *f0p;
+    for (int64_t x = f0 + blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < n; x += (int64_t)gridDim.x * PD_BLOCK) {
+        bars[3 * x] = 0;
+        bars[3 * x + 1] = -1;
+        bars[3 * x + 2] = 0x7FFFFFFFFFFFFFFFll;
+    }
+}
+
+// paired triangles (for the essential classes of dimension 2)
+__global__ void __launch_bounds__(PD_BLOCK) k_bc_paired(const int32_t *toe, int64_t K, unsigned long long *cnt) {
+    __shared__ unsigned long long s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    unsigned long long c = 0;
+    for (int64_t r = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; r < K; r += (int64_t)gridDim.x * PD_BLOCK)
+        c += toe[r] >= 0 ? 1ull : 0ull;
+    atomicAdd(&s, c);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(cnt, s);
+}
+
+extern "C" VR_API int vr_barcode(const vr_result *res, const int32_t *e_low, const int32_t *tri_of_edge,
+                                 int64_t *bars, int64_t counts[3], void *stream) {
+    if (!res || !counts) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges, T = res->n_triangles;
+    if (n < 0 || K < 0 || T < 0 || n > VR_MAX_POINTS || T > 0x7FFFFFFF) return VR_EINVAL;
+    if ((n + K > 0 && !bars) || (K > 0 && (!e_low || !tri_of_edge)) || (T > 0 && !res->tri_key)) return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    const int64_t nch = (K + BC_CHUNK - 1) / BC_CHUNK;
+    // off: 2 nch + 2 int64 (chunk offsets, then the two totals), the paired
+    // triangle count, then cnt: 2 nch int32
+    char *ws = (char *)cache_get(8 * (size_t)(2 * nch + 3) + 4 * (size_t)(2 * nch + 2) + 64, s);
+    if (!ws) return VR_ENOMEM;
+    long long *off = (long long *)ws;
+    unsigned long long *paired = (unsigned long long *)(off + 2 * nch + 2);
+    int32_t *cnt = (int32_t *)(ws + 8 * (size_t)(2 * nch + 3));
+    const unsigned long long *key = (const unsigned long long *)res->tri_key;
+    if (nch > 0) {
+        hipLaunchKernelGGL(k_bc_count, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, e_low, tri_of_edge, key, K, cnt);
+    }
+    hipLaunchKernelGGL(k_bc_scan, dim3(1), dim3(BC_CHUNK), 0, s, (const int32_t *)cnt, nch, off);
+    if (nch > 0)
+        hipLaunchKernelGGL(k_bc_write, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, e_low, tri_of_edge, key, n, K,
+                           (const long long *)off, (long long *)bars);
+    if (n > 0)
+        hipLaunchKernelGGL(k_bc_ess0, dim3(grid_for(n)), dim3(PD_BLOCK), 0, s, (const long long *)(off + 2 * nch), n,
+                           (long long *)bars);
+    long long tot[2] = {0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(tot, off + 2 * nch, sizeof(tot), hipMemcpyDeviceToHost, s);
+    unsigned long long np = 0;
+    if (K > 0 && e == hipSuccess) {
+        hipLaunchKernelGGL(k_rd_zero, dim3(1), dim3(PD_BLOCK), 0, s, paired, (int64_t)1);
+        hipLaunchKernelGGL(k_bc_paired, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K, paired);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&np, paired, sizeof(np), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cache_put(ws, s);
+    if (e != hipSuccess) return VR_EHIP;
+    counts[0] = n;
+    counts[1] = tot[1];
+    counts[2] = T - (int64_t)np;
+    return VR_OK;
 }
