@@ -547,14 +547,15 @@ __global__ __launch_bounds__(EB) void k_tri_count(VrDev D, int parts) {
                 for (int j = 0; j < NP; j++) {
                     if ((uint32_t)(j * VR_WAVE) < len) {  // whole pieces past len are skipped
                         const uint32_t y = (uint32_t)(j * VR_WAVE + lane);
-                        const bool hit = (y < len) & ((uint32_t)Pa[kk[j]] < xa);
-                        c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+                        // lane masks straight from the comparisons (unsigned less-than: 36)
+                        c += (uint32_t)__popcll(__builtin_amdgcn_uicmp(y, len, 36) &
+                                                __builtin_amdgcn_uicmp((uint32_t)Pa[kk[j]], xa, 36));
                     }
                 }
                 for (uint32_t y0 = NP * VR_WAVE; y0 < len; y0 += VR_WAVE) {
                     const uint32_t y = y0 + (uint32_t)lane;
                     const uint32_t k = D.star_nbr[rl(vsb, el) + (y < len ? y : len - 1u)];
-                    c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((y < len) & ((uint32_t)Pa[k] < xa)));
+                    c += (uint32_t)__popcll(__builtin_amdgcn_uicmp(y, len, 36) & __builtin_amdgcn_uicmp((uint32_t)Pa[k], xa, 36));
                 }
                 if (lane == el) mycnt = c;
             };
@@ -816,16 +817,21 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
                 // one 64-entry piece of the partner's neighbour-ordered star, with
                 // the position of each entry's neighbour in a's star (lanes past
                 // the star read sentinels, which never hit)
+                const unsigned long long kbase = (unsigned long long)rh << 32;
                 auto piece = [&](uint32_t v, uint32_t pa) {
                     const uint32_t k = v & 0xFFFFu, pk = v >> 16;
-                    const bool hit = (pk < pb) & (pa < xa);
-                    const unsigned long long m = __builtin_amdgcn_ballot_w64(hit);
-                    const uint32_t x0 = min(lo, k), x2 = max(hi, k), x1 = max(lo, min(hi, k));
-                    const uint32_t klo = (x0 << 26) | (x1 << 13) | x2;
-                    const uint32_t khi = rh | (x0 >> 6);
-                    const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, run));
-                    // streaming store: keeps the stars, not the output, in L2
-                    if (hit) __builtin_nontemporal_store(((unsigned long long)khi << 32) | klo, dst + at);
+                    // lane masks of the two tests straight from the comparisons
+                    // (unsigned less-than is predicate 36)
+                    const unsigned long long m = __builtin_amdgcn_uicmp(pk, pb, 36) & __builtin_amdgcn_uicmp(pa, xa, 36);
+                    if ((pk < pb) & (pa < xa)) {
+                        // x1 = k clamped to [lo, hi] is the median; x0 << 26 spans both
+                        // words, added to the edge's base with the low bits of x1, x2
+                        const uint32_t x0 = min(lo, k), x2 = max(hi, k), x1 = min(max(k, lo), hi);
+                        const unsigned long long key = (((unsigned long long)x0 << 26) + kbase) | ((x1 << 13) | x2);
+                        const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, run));
+                        // streaming store: keeps the stars, not the output, in L2
+                        __builtin_nontemporal_store(key, dst + at);
+                    }
                     run += (uint32_t)__popcll(m);
                 };
                 // pieces in groups of four: a group past len is skipped whole
