@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 # SHA-256 prefix of the writer's sources the counters were taken on, and the
 # figure is dropped (null) once those sources change.
 TRAFFIC = {
-    "circle1000": {"bytes": 92580165, "src": "a504010f66a4d24d"},
-    "mixture4000": {"bytes": 2066402023, "src": "a504010f66a4d24d"},
-    "batched512": {"bytes": 36513805632, "src": "a504010f66a4d24d"},
+    "circle1000": {"bytes": 88201693, "src": "30755776c5182e42"},
+    "mixture4000": {"bytes": 1880250023, "src": "30755776c5182e42"},
+    "batched512": {"bytes": 30799856988, "src": "30755776c5182e42"},
 }
 WRITER_SOURCES = ("k_triangles.hip", "vr_device.h")
 
@@ -272,10 +272,25 @@ def _serving(vr, torch, qps=None, requests=2000, warm=100, slots=4, max_batch=32
     span_srv = max(r.t_done for r in reqs[warm:]) - reqs[warm].arrival
     assert all(sum(r.counts) == n for r, n in zip(reqs, simp)), "served counts differ from plain builds"
     print("[bench] serving: request loop done", file=sys.stderr, flush=True)
+    # saturation: every request waiting at once, so the loop batches as far
+    # as its byte budget and batch limit allow; capacity = requests / span
+    with Server(slots=slots, max_batch=max_batch, keep_results=False) as srv2:
+        t0 = time.perf_counter()
+        sreqs = [srv2.submit(p, c.thr, arrival=t0) for p, c in zip(pts, clouds)]
+        for r in sreqs:
+            r.wait(timeout=300)
+        t_sat = max(r.t_done for r in sreqs) - t0
+    assert all(sum(r.counts) == n for r, n in zip(sreqs, simp)), "served counts differ from plain builds"
+    sat_sizes = [r.batch_size for r in sreqs]
+    print("[bench] serving: saturation done", file=sys.stderr, flush=True)
     total = sum(simp[warm:])
     sizes = [r.batch_size for r in reqs]
     return {"qps": qps, "plain_capacity_rps": round(mu, 2), "requests": requests, "warmup_requests": warm,
             "simplices": total,
+            "capacity": {"plain_rps": round(mu, 2), "plain_simplices_per_s": sum(simp) * mu / requests,
+                         "served_rps": round(requests / t_sat, 2), "served_simplices_per_s": sum(simp) / t_sat,
+                         "served_mean_batch": round(sum(sat_sizes) / len(sat_sizes), 3),
+                         "served_over_plain": round(requests / t_sat / mu, 3)},
             "plain_fifo": dict(_pcts(lat_plain[warm:]), simplices_per_s=total / span_plain),
             "served": dict(_pcts(lat_srv[warm:]), simplices_per_s=total / span_srv, slots=slots,
                            max_batch=max_batch, batches=srv.batches,
