@@ -342,14 +342,44 @@ extern "C" VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_
     return hipGetLastError() == hipSuccess ? VR_OK : VR_EHIP;
 }
 
+// Index pairs (a, b), a < b < m, numbered row-major: p = S(a) + b - a - 1,
+// S(a) = a (2m - a - 1) / 2 the pairs of the rows before a.
+static __device__ __forceinline__ long long tet_row_start(long long a, long long m) { return a * (2 * m - a - 1) / 2; }
+
+// Index pair of pair number p among the pairs of m entries: a from the
+// closed form in single precision, then corrected with exact integers.
+static __device__ __forceinline__ void tet_pair(long long p, long long m, uint32_t &a, uint32_t &b) {
+    const float c = (float)(2 * m - 1);
+    float disc = c * c - 8.0f * (float)p;
+    disc = disc > 0.0f ? disc : 0.0f;
+    long long x = (long long)((c - sqrtf(disc)) * 0.5f);
+    x = x < 0 ? 0 : (x > m - 2 ? m - 2 : x);
+    while (x > 0 && tet_row_start(x, m) > p) x--;
+    while (x < m - 2 && tet_row_start(x + 1, m) <= p) x++;
+    a = (uint32_t)x;
+    b = (uint32_t)(p - tet_row_start(x, m) + x + 1);
+}
+
+// Move pair (a, b) d places on in row-major order (row a holds b = a+1 ..
+// m-1): b grows by d, and each time it leaves its row it continues in the
+// next, shorter one.  Past the last pair it stops at a = m - 1 (no pair).
+static __device__ __forceinline__ void tet_advance(uint32_t &a, uint32_t &b, uint32_t d, uint32_t m) {
+    b += d;
+    while (b >= m && a + 2 < m) {
+        a++;
+        b = b - m + a + 1;
+    }
+    if (b >= m) a = m - 1;
+}
+
 // Tetrahedra (dimension 3) per largest edge.  Work-group g takes edge r:
 // the vertices x joined to both ends by older edges (D[i][x] < r and
 // D[j][x] < r; the ends themselves fail one test, D[i][j] = r), compacted
 // into LDS in ascending order, then the pairs of them joined by an older
-// edge: wave w takes the vertices a = w, w+4, ... and its lanes read the
-// entries of row L[a] for the later vertices together (ascending, so nearby
-// addresses).  D as for the pairs of dimension 0 (ranks, +inf off the
-// edges, -1 on the diagonal).
+// edge, a wave per row of the pairs (rows are long, so lanes stay busy; the
+// writer, which must also order its stores, numbers the pairs instead).  D
+// as for the pairs of dimension 0 (ranks, +inf off the edges, -1 on the
+// diagonal).
 __global__ void __launch_bounds__(PD_BLOCK) k_tet_count(const int32_t *D, int64_t ld, int64_t n, const int32_t *ij,
                                                        int64_t K, long long *counts) {
     __shared__ uint16_t L[VR_MAX_POINTS];
@@ -377,6 +407,9 @@ __global__ void __launch_bounds__(PD_BLOCK) k_tet_count(const int32_t *D, int64_
             m += chunk;
             __syncthreads();  // wc is rewritten by the next chunk
         }
+        // the pairs of the common neighbours joined by an older edge: wave w
+        // takes the rows a = w, w + 4, ..., its lanes the later entries b of
+        // row a together (ascending, so nearby addresses)
         unsigned long long c = 0;
         for (uint32_t a = wv; a + 1 < m; a += PD_BLOCK / 64) {
             const int32_t *row = D + (int64_t)L[a] * ld;
@@ -400,17 +433,21 @@ extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, voi
 // Tetrahedra written in filtration order.  The group of edge r starts at
 // off[r] (an exclusive scan of the counts).  Within it the tetrahedra
 // {i, j, k, l} run in lexicographic order of their sorted vertices, which
-// for a fixed pair i < j is the lexicographic order of (k, l), k < l: row
-// a of the common neighbours L (ascending) holds the pairs (L[a], L[b]),
-// b > a, so the rows are counted, scanned in LDS, and each wave writes its
-// rows' pairs in order through a ballot.  Key of a tetrahedron: two words,
-// its value r and a<<39 | b<<26 | c<<13 | d.
+// for a fixed pair i < j is the lexicographic order of (k, l), k < l.  With
+// the common neighbours L ascending, that is the row-major order of the
+// index pairs (a, b), a < b, numbered p = S(a) + b - a - 1 with
+// S(a) = a (2m - a - 1) / 2 the pairs of the rows before a.  Each wave
+// takes a contiguous quarter of the m (m - 1) / 2 pairs, 64 at a time (one
+// pair per lane, so no lane idles on short rows): it counts its hits, the
+// four counts are scanned, and it walks its pairs again, writing each hit
+// through a ballot at its place.  Key of a tetrahedron: two words, its value
+// r and a<<39 | b<<26 | c<<13 | d.
 __global__ void __launch_bounds__(PD_BLOCK) k_tet_write(const int32_t *D, int64_t ld, int64_t n, const int32_t *ij,
                                                        int64_t K, const long long *off, long long total,
                                                        unsigned long long *keys) {
     __shared__ uint16_t L[VR_MAX_POINTS];
-    __shared__ uint32_t rowc[VR_MAX_POINTS];
     __shared__ uint32_t wc[PD_BLOCK / 64];
+    __shared__ unsigned long long wh[PD_BLOCK / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int64_t r = blockIdx.x; r < K; r += gridDim.x) {
         const int64_t i = ij[2 * r], j = ij[2 * r + 1];
@@ -433,77 +470,48 @@ __global__ void __launch_bounds__(PD_BLOCK) k_tet_write(const int32_t *D, int64_
             m += chunk;
             __syncthreads();
         }
-        // pairs per row a
-        for (uint32_t a = wv; a < m; a += PD_BLOCK / 64) {
-            uint32_t c = 0;
-            const int32_t *row = D + (int64_t)L[a] * ld;
-            for (uint32_t b2 = a + 1 + lane; b2 < m; b2 += 64) c += row[L[b2]] < r ? 1u : 0u;
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-            if (lane == 0) rowc[a] = c;
+        // this wave's pairs [p0, p1)
+        const long long P = (long long)m * (m - 1) / 2;
+        const long long p0 = P * wv / (PD_BLOCK / 64), p1 = P * (wv + 1) / (PD_BLOCK / 64);
+        unsigned long long c = 0;
+        uint32_t a0 = 0, b0 = 1;
+        if (p0 + lane < p1) tet_pair(p0 + lane, m, a0, b0);  // once; then 64 places per step
+        uint32_t a = a0, b = b0;
+        for (long long q0 = p0; q0 < p1; q0 += 64) {
+            const bool in = q0 + lane < p1 && D[(int64_t)L[a] * ld + L[b]] < r;
+            c += (unsigned long long)__popcll(__ballot(in));
+            tet_advance(a, b, 64, m);
         }
+        if (lane == 0) wh[wv] = c;
         __syncthreads();
-        // exclusive scan of rowc[0..m) in place: thread t takes the rows
-        // [t*per, t*per + per), the work-group scans the threads' sums
-        {
-            const uint32_t per = (m + PD_BLOCK - 1) / PD_BLOCK;
-            const uint32_t a0 = min((uint32_t)t * per, m), a1 = min(a0 + per, m);
-            uint32_t own = 0;
-            for (uint32_t a = a0; a < a1; a++) own += rowc[a];
-            uint32_t incl = own;
+        unsigned long long pos = 0;
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t y = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += y;
-            }
-            if (lane == 63) wc[wv] = incl;
-            __syncthreads();
-            uint32_t run = incl - own;
-#pragma unroll
-            for (int w = 0; w < PD_BLOCK / 64; w++)
-                if (w < wv) run += wc[w];
-            for (uint32_t a = a0; a < a1; a++) {
-                const uint32_t c = rowc[a];
-                rowc[a] = run;
-                run += c;
-            }
-            __syncthreads();
-        }
+        for (int w = 0; w < PD_BLOCK / 64; w++)
+            if (w < wv) pos += wh[w];
         const long long g0 = off[r];
         const uint32_t vi = (uint32_t)i, vj = (uint32_t)j;
-        for (uint32_t a = wv; a < m; a += PD_BLOCK / 64) {
-            const uint32_t k = L[a];
-            const int32_t *row = D + (int64_t)k * ld;
-            uint32_t pos = rowc[a];
-            for (uint32_t b0 = a + 1; b0 < m; b0 += 64) {
-                const uint32_t b2 = b0 + lane;
-                const bool in = b2 < m && row[L[b2]] < r;
-                const unsigned long long bm = __ballot(in);
-                if (in) {
-                    const uint32_t l = L[b2];
-                    // sorted merge of {i < j} and {k < l}
-                    uint32_t q[4];
-                    uint32_t x = 0, y = 0;
-                    const uint32_t s1[2] = {vi, vj}, s2[2] = {k, l};
-#pragma unroll
-                    for (int z = 0; z < 4; z++) {
-                        const bool take1 = y >= 2 || (x < 2 && s1[x < 2 ? x : 1] < s2[y < 2 ? y : 1]);
-                        q[z] = take1 ? s1[x < 2 ? x : 1] : s2[y < 2 ? y : 1];
-                        x += take1 ? 1 : 0;
-                        y += take1 ? 0 : 1;
-                    }
-                    const long long at = g0 + pos +
-                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0));
-                    if (at < total)  // one 16-byte store per tetrahedron
-                        *(ulonglong2 *)(keys + 2 * at) =
-                            make_ulonglong2((unsigned long long)r, ((unsigned long long)q[0] << 39) |
-                                                                       ((unsigned long long)q[1] << 26) |
-                                                                       ((unsigned long long)q[2] << 13) | q[3]);
-                }
-                pos += (uint32_t)__popcll(bm);
+        a = a0;
+        b = b0;
+        for (long long q0 = p0; q0 < p1; q0 += 64) {
+            const bool live = q0 + lane < p1;  // a < b < m exactly then
+            const uint32_t k = live ? L[a] : 0u, l = live ? L[b] : 0u;
+            const bool in = live && D[(int64_t)k * ld + l] < r;
+            tet_advance(a, b, 64, m);
+            const unsigned long long bm = __ballot(in);
+            if (in) {
+                // sorted {i < j} and {k < l}: ends by min and max, the middle
+                // two sorted between themselves
+                const uint32_t lo = min(vi, k), hi = max(vj, l), u = max(vi, k), v = min(vj, l);
+                const unsigned long long packed = ((unsigned long long)lo << 39) | ((unsigned long long)min(u, v) << 26) |
+                                                  ((unsigned long long)max(u, v) << 13) | hi;
+                const long long at = g0 + (long long)pos +
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0));
+                if (at < total)  // one 16-byte store per tetrahedron
+                    *(ulonglong2 *)(keys + 2 * at) = make_ulonglong2((unsigned long long)r, packed);
             }
+            pos += (unsigned long long)__popcll(bm);
         }
-        __syncthreads();  // L and rowc are reused by the next edge
+        __syncthreads();  // L and wh are reused by the next edge
     }
 }
 
