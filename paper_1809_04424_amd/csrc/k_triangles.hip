@@ -50,9 +50,10 @@ __device__ __forceinline__ uint32_t star_slot(uint32_t mbase, int n, int v) { re
 // first pb entries, which the partner's list plist_pick(pb) holds: walking
 // that list instead of the whole star leaves the walk in neighbour order
 // (so hits still come out in k order) while cutting the candidates to about
-// half on average.  Vertex v of a cloud owns 3n + 65 VR_PLISTS entries of
-// star_k from plist_region (sum over the lists: at most 2.5 deg + 4 + 256).
-#define VR_PLISTS 4
+// half on average (cutting at each eighth instead left the writer's time
+// unchanged and slowed the star stage).  Vertex v of a cloud owns
+// VR_PLIST_PER n + 65 VR_PLISTS entries of star_k from plist_region (sum
+// over the lists: at most (VR_PLISTS + 1) deg / 2 + VR_PLISTS + 64 VR_PLISTS).
 __device__ __forceinline__ uint32_t plist_len(uint32_t j, uint32_t deg) { return (j * deg + VR_PLISTS - 1) / VR_PLISTS; }
 __device__ __forceinline__ uint32_t plist_off(uint32_t j, uint32_t deg) {
     uint32_t o = 0;
@@ -64,8 +65,8 @@ __device__ __forceinline__ uint32_t plist_pick(uint32_t p, uint32_t deg) {
     return p == 0 ? 0u : (p * VR_PLISTS + deg - 1) / deg;
 }
 __device__ __forceinline__ uint32_t plist_region(uint32_t mbase, uint32_t vbase, int n, int v) {
-    const uint32_t per = 3u * (uint32_t)n + (VR_WAVE + 1) * VR_PLISTS;
-    return 3u * mbase + (uint32_t)(VR_WAVE + 1) * VR_PLISTS * vbase + (uint32_t)v * per;
+    const uint32_t per = VR_PLIST_PER * (uint32_t)n + (VR_WAVE + 1) * VR_PLISTS;
+    return VR_PLIST_PER * mbase + (uint32_t)(VR_WAVE + 1) * VR_PLISTS * vbase + (uint32_t)v * per;
 }
 
 // One work-group per vertex v reads row v of the rank matrix that k_edges
@@ -82,7 +83,7 @@ __device__ __forceinline__ uint32_t plist_region(uint32_t mbase, uint32_t vbase,
 // v's star in rank order (rank within the cloud, written over the row, and
 // the neighbour), each edge's position in it (pos), the prefix lists (the
 // star in neighbour order with those positions, whole and cut at each
-// quarter of the rank order) and its size.
+// 1/VR_PLISTS of the rank order) and its size.
 //
 // Wave w reads the row's entries [64 S w, 64 S (w+1)) in S steps of 64, so
 // the neighbour order is the order of (wave, step, lane); S * 256 >= n.

@@ -285,7 +285,7 @@ Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax
         // star slots: n entries per vertex (the rank matrix, then the stars)
         P.off_star_r = o; o = align_up(o + 4 * (size_t)N2);
         P.off_star_nbr = o; o = align_up(o + 2 * (size_t)N2);
-        P.off_star_k = o; o = align_up(o + 4 * (3 * (size_t)N2 + 260 * (size_t)V));  // prefix lists
+        P.off_star_k = o; o = align_up(o + 4 * (VR_PLIST_PER * (size_t)N2 + 65 * VR_PLISTS * (size_t)V));  // prefix lists
         P.off_deg = o; o = align_up(o + 4 * (size_t)V);
         P.off_pos = o; o = align_up(o + 2 * (size_t)N2);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
@@ -400,9 +400,9 @@ int shape_of(const vr_request *reqs, long long count, Shape &S) {
     S.Kmax = (S.Khost >= 0) ? S.Khost : S.E;
     // sort keys (cloud, q) in 32 bits; candidate counts in the 30-bit
     // look-back statuses; vertices in 24 bits; kept-edge index + 1 in 32
-    // bits; prefix-list indices (3 sum n^2 + 260 V) in 32 bits.
+    // bits; prefix-list indices (VR_PLIST_PER sum n^2 + 65 VR_PLISTS V) in 32 bits.
     if (S.qbits + S.cbits > 32 || S.E >= (1ll << 30) || S.V >= (1ll << 24) || S.Kmax > 0x7FFFFFFFll ||
-        3 * S.N2 + 260 * S.V >= (1ll << 32))
+        VR_PLIST_PER * S.N2 + 65 * VR_PLISTS * S.V >= (1ll << 32))
         return VR_E2BIG;
     return VR_OK;
 }

@@ -16,6 +16,11 @@
 #define VR_MAX_PASSES 4
 #define VR_NBUCKET 1728              // log-linear buckets of a 32-bit key
 #define VR_NOT_KEPT 0xFFFFFFFFu
+// Prefix lists of the triangle writer: each star in neighbour order, whole
+// and cut at every (1 / VR_PLISTS)-th of its rank order; VR_PLIST_PER n +
+// 65 VR_PLISTS entries per vertex hold them with their sentinels.
+#define VR_PLISTS 4
+#define VR_PLIST_PER ((VR_PLISTS + 2) / 2)
 
 // Look-back status words: 2-bit state in the top bits, value below.
 #define VR_ST_NONE 0u
@@ -435,13 +440,15 @@ struct VrDev {
     uint32_t *se_q;         // K
     // Star slots: vertex v of a cloud with n points owns entries
     // [mbase + v n, mbase + v n + n) of star_r, star_nbr and pos, and
-    // 3 n + 260 entries of star_k from 3 mbase + 260 vbase + v (3 n + 260).
+    // P n + 65 VR_PLISTS entries of star_k from P mbase + 65 VR_PLISTS vbase +
+    // v (P n + 65 VR_PLISTS), P = VR_PLIST_PER.
     uint32_t *star_r;       // sum n^2: first the rank matrix (tag << 24 | local rank at [v][k]),
                             // then each row's star in rank order (local rank, tag 0)
     uint16_t *star_nbr;     // sum n^2: the other endpoint (local), rank order
-    uint32_t *star_k;       // 3 sum n^2 + 260 V: per vertex, its prefix lists (the star in neighbour
-                            // order, entries neighbour | rank-order position << 16, whole and cut at
-                            // each quarter of the rank order), each followed by 64 sentinels
+    uint32_t *star_k;       // VR_PLIST_PER sum n^2 + 65 VR_PLISTS V: per vertex, its prefix lists (the
+                            // star in neighbour order, entries neighbour | rank-order position << 16,
+                            // whole and cut at each 1/VR_PLISTS of the rank order), each followed by
+                            // 64 sentinels
     uint32_t *deg;          // V: star sizes
     uint16_t *pos;          // sum n^2, in the star slots: entry k of v's slot = position of edge {v,k}
                             // in v's rank-ordered star (set for v's neighbours only)
