@@ -22,7 +22,11 @@ __device__ __forceinline__ long long gram_tile_row_start(long long bi, long long
     return bi * nb - bi * (bi - 1) / 2;
 }
 
-__global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(VrDev D, int dpad) {
+// DPAD: d rounded up to a multiple of 64 (64, 128, 192 or 256), a
+// compile-time constant so that staging indexes rows without divisions.
+template <int DPAD>
+__global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(VrDev D) {
+    constexpr int dpad = DPAD;
     const long long tg = blockIdx.x;
     const int c = (D.C == 1) ? 0 : (int)D.tcloud[tg];
     const VrCloud cl = D.cl[c];
@@ -47,20 +51,46 @@ __global__ __launch_bounds__(VR_BLOCK) void k_gram_i8(VrDev D, int dpad) {
     uint32_t *hist = (uint32_t *)(nj + GRAM_TB);  // VR_NBUCKET
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
-    // stage both blocks (zero rows past n and coordinates past d)
-    for (int x = t; x < GRAM_TB * dpad; x += VR_BLOCK) {
-        const int r = x / dpad, c = x % dpad;
-        const int gi = bi * GRAM_TB + r, gj = bj * GRAM_TB + r;
-        xi[x] = (gi < n && c < d) ? pts[(size_t)gi * d + c] : (int8_t)0;
-        xj[x] = (gj < n && c < d) ? pts[(size_t)gj * d + c] : (int8_t)0;
+    // stage both blocks (zero rows past n and coordinates past d): 16 bytes
+    // at a time when every row starts on a 16-byte boundary, else bytewise
+    if ((d & 15) == 0 && ((uintptr_t)pts & 15) == 0) {
+        constexpr int CPR = DPAD / 16;  // 16-byte chunks per staged row
+        const int cd = d / 16;          // chunks holding coordinates
+        for (int x = t; x < GRAM_TB * CPR; x += VR_BLOCK) {
+            const int r = x / CPR, ch = x % CPR;
+            const int gi = bi * GRAM_TB + r, gj = bj * GRAM_TB + r;
+            int4 vi = make_int4(0, 0, 0, 0), vj = make_int4(0, 0, 0, 0);
+            if (ch < cd) {
+                if (gi < n) vi = *(const int4 *)(pts + (size_t)gi * d + 16 * ch);
+                if (gj < n) vj = *(const int4 *)(pts + (size_t)gj * d + 16 * ch);
+            }
+            ((int4 *)xi)[x] = vi;
+            ((int4 *)xj)[x] = vj;
+        }
+    } else {
+        for (int x = t; x < GRAM_TB * dpad; x += VR_BLOCK) {
+            const int r = x / dpad, c = x % dpad;
+            const int gi = bi * GRAM_TB + r, gj = bj * GRAM_TB + r;
+            xi[x] = (gi < n && c < d) ? pts[(size_t)gi * d + c] : (int8_t)0;
+            xj[x] = (gj < n && c < d) ? pts[(size_t)gj * d + c] : (int8_t)0;
+        }
     }
     if (need_hist)
         for (int b = t; b < VR_NBUCKET; b += VR_BLOCK) hist[b] = 0u;
     __syncthreads();
     if (t < 2 * GRAM_TB) {
-        const int8_t *row = (t < GRAM_TB) ? xi + t * dpad : xj + (t - GRAM_TB) * dpad;
+        // squared norm of one staged row, 4 coordinates per 32-bit word
+        const int *row = (const int *)((t < GRAM_TB) ? xi + t * dpad : xj + (t - GRAM_TB) * dpad);
         int32_t s = 0;
-        for (int c = 0; c < dpad; c++) s += (int32_t)row[c] * (int32_t)row[c];
+#pragma unroll 4
+        for (int c = 0; c < dpad / 4; c++) {
+            const int v = row[c];
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const int x = (int)(int8_t)(v >> (8 * b));  // signed byte b
+                s += x * x;
+            }
+        }
         if (t < GRAM_TB) ni[t] = s;
         else nj[t - GRAM_TB] = s;
     }
@@ -111,6 +141,12 @@ bool gram_applies(const VrDev &D) { return D.dtype == 1 && D.d >= 16 && D.d <= 2
 
 void launch_gram(const VrDev &D, const void *points, hipStream_t s) {
     (void)points;
-    const int dpad = (D.d + GRAM_KC - 1) / GRAM_KC * GRAM_KC;
-    hipLaunchKernelGGL(k_gram_i8, dim3((unsigned)D.tiles), dim3(VR_BLOCK), gram_lds(dpad), s, D, dpad);
+    const int dpad = (D.d + GRAM_KC - 1) / GRAM_KC * GRAM_KC;  // gram_applies: 64 .. 256
+    const dim3 grid((unsigned)D.tiles), block(VR_BLOCK);
+    switch (dpad) {
+    case 64: hipLaunchKernelGGL(k_gram_i8<64>, grid, block, gram_lds(64), s, D); break;
+    case 128: hipLaunchKernelGGL(k_gram_i8<128>, grid, block, gram_lds(128), s, D); break;
+    case 192: hipLaunchKernelGGL(k_gram_i8<192>, grid, block, gram_lds(192), s, D); break;
+    default: hipLaunchKernelGGL(k_gram_i8<256>, grid, block, gram_lds(256), s, D); break;
+    }
 }

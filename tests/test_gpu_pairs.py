@@ -181,6 +181,7 @@ TET_CASES = [
     ("plain64_full", lambda: workloads.plain64().points, ("full", 0, 1)),
     ("n3", lambda: workloads.uniform_cloud(92, 3, 2).points, ("full", 0, 1)),
     ("n4", lambda: workloads.uniform_cloud(93, 4, 2).points, ("full", 0, 1)),
+    ("hub_pair_m300", lambda: workloads.hub_pair(), ("sqdist", 7000, 0)),
 ]
 
 
@@ -223,6 +224,9 @@ LIST_CASES = [
     ("uniform_sqdist", lambda: workloads.uniform_cloud(97, 90, 4).points, ("sqdist", 25000, 0)),
     ("n4", lambda: workloads.uniform_cloud(98, 4, 2).points, ("full", 0, 1)),
     ("n3", lambda: workloads.uniform_cloud(99, 3, 2).points, ("full", 0, 1)),
+    # the hub edge has 300 common older neighbours: several 256-vertex chunks
+    # per row scan, rows of up to 299 later neighbours, 44850 pairs of them
+    ("hub_pair_m300", lambda: workloads.hub_pair(), ("sqdist", 7000, 0)),
 ]
 
 

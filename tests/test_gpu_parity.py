@@ -59,6 +59,8 @@ SMALL = [
     workloads.uniform_cloud(24, 100, 256, thr=("fraction", 30, 100)),  # deepest matrix-core input
     workloads.uniform_cloud(25, 90, 257, thr=("fraction", 30, 100)),   # vector path past it
     workloads.uniform_cloud(26, 150, 64, lo=-128, hi=-100, thr=("count", 4000, 1)),  # -128 extremes
+    workloads.uniform_cloud(27, 170, 96, thr=("fraction", 20, 100)),   # matrix cores, 128-deep staging, 16-byte rows
+    workloads.uniform_cloud(28, 140, 100, thr=("fraction", 20, 100)),  # 128-deep staging, rows staged bytewise
 ]
 
 

@@ -206,6 +206,22 @@ def full_columns(seed: int, ncols: int, length: int, maxvalue: int):
     return colptr, v
 
 
+def hub_pair(seed: int = 101, m: int = 300, d: int = 64, h: float = 40.0, s: float = 66.8) -> np.ndarray:
+    """Two hub points (-h, 0, ...) and (h, 0, ...) and m points at radius s in
+    the hyperplane between them (random directions in R^(d-1)), int8.  Under
+    a squared-distance threshold between 4h^2 and the typical distance of two
+    hyperplane points, every hyperplane point joins both hubs by an edge
+    shorter than the hub edge, while few hyperplane points join each other:
+    the hub edge has m common older neighbours, with few tetrahedra."""
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((m, d - 1))
+    y *= s / np.linalg.norm(y, axis=1, keepdims=True)
+    pts = np.zeros((m + 2, d))
+    pts[0, 0], pts[1, 0] = -h, h
+    pts[2:, 1:] = y
+    return quantize_i8(pts)
+
+
 def lattice_cloud(seed: int, n: int, side: int = 4, d: int = 2, thr=("full", 0, 1)) -> Cloud:
     """Points drawn from the lattice {0..side-1}^d: many exact distance ties and duplicates."""
     rng = np.random.default_rng(seed)
