@@ -42,9 +42,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 # SHA-256 prefix of the writer's sources the counters were taken on, and the
 # figure is dropped (null) once those sources change.
 TRAFFIC = {
-    "circle1000": {"bytes": 88201693, "src": "30755776c5182e42"},
-    "mixture4000": {"bytes": 1880250023, "src": "30755776c5182e42"},
-    "batched512": {"bytes": 30799856988, "src": "30755776c5182e42"},
+    "mixture4000": {"bytes": 1623778713, "src": "f6e4d208cdc283fb"},
 }
 WRITER_SOURCES = ("k_triangles.hip", "vr_device.h")
 

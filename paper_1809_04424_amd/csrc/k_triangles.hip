@@ -404,7 +404,15 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
     if (p < s1) {
         r = kb + (p0 == s0 ? r0 : D.star_r[p]);  // global kept-edge index
         b = p0 == s0 ? b0 : D.star_nbr[p];
-        pb = D.pos[star_slot(mb, n, (int)b) + (uint32_t)a];  // edge {b,a} in b's star
+        // edge {b,a} in b's star: the count reads it from b's positions (one
+        // scattered read per entry) and stores it beside the entry, where the
+        // write reads it in order
+        if (WRITE) {
+            pb = D.ppos[p];
+        } else {
+            pb = D.pos[star_slot(mb, n, (int)b) + (uint32_t)a];
+            D.ppos[p] = (uint16_t)pb;
+        }
         sb = star_slot(mb, n, (int)b);
         if (WRITE) {
             // a walks b's shortest list holding b's first pb entries, or b

@@ -452,6 +452,8 @@ struct VrDev {
     uint32_t *deg;          // V: star sizes
     uint16_t *pos;          // sum n^2, in the star slots: entry k of v's slot = position of edge {v,k}
                             // in v's rank-ordered star (set for v's neighbours only)
+    uint16_t *ppos;         // sum n^2, in the star slots: entry x of v's star = the position of that
+                            // edge in the partner's star (written by the count, read by the write)
     uint32_t *cnt;          // K triangles per kept edge
     unsigned long long *off;     // K exclusive offsets
     unsigned long long *st_scan; // ceil(K/TILE)
