@@ -601,7 +601,8 @@ def _pairs_dim1(vr, torch, reps=5, workload="circle1000"):
     """All persistence pairs of dimension 1 and the barcode of dimensions 0
     and 1 of a build (dimension-0 pairs first, as the clearing needs them):
     the apparent pairs in one pass over the keys, then the remaining edge
-    columns reduced youngest first by one work-group.  Wall time of the
+    columns: their apparent additions all at once, the rest youngest first
+    by one work-group.  Wall time of the
     three calls (each synchronises for its status), median of reps."""
     c = _workload(workload)
     pts = torch.from_numpy(c.points).to("cuda:0")
@@ -649,10 +650,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="mixture4000",
                     choices=["circle1000", "mixture4000", "plain64", "batched512", "hamming1088", "colorder2000",
-                             "pairs0", "schur16384"],
+                             "pairs0", "pairs1", "schur16384"],
                     help="mixture4000 (the benchmark line, with side measurements), circle1000, plain64, "
                          "batched512 (one batched build of 512 clouds), or one side measurement alone: "
                          "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs and dimension-1 apparent pairs), "
+                         "pairs1 (dimension-1 reduction and barcode), "
                          "schur16384 (F2 product and sum)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and the parity gate")
     ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
@@ -696,6 +698,11 @@ def main():
                           "pairs_dim1_barcode": _pairs_dim1(vr, torch),
                           "apparent_dim1": _apparent(vr, torch, reps=args.steps),
                           "tetra_counts": _tetra(vr, torch, reps=args.steps)}), flush=True)
+        return
+    if args.workload == "pairs1":  # the dimension-1 reduction and barcode alone (profiling)
+        print(json.dumps({"workload": "pairs_dim1_barcode",
+                          "circle1000": _pairs_dim1(vr, torch, reps=args.steps),
+                          "mixture4000": _pairs_dim1(vr, torch, reps=args.steps, workload="mixture4000")}), flush=True)
         return
     if args.workload == "schur16384":  # the F2 product and sum alone (profiling)
         print(json.dumps({"workload": "schur_f2_16384", **_schur(vr, torch, reps=args.steps)}), flush=True)

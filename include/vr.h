@@ -329,9 +329,12 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  * the pivot of an edge's column is its oldest cofacet (the smallest
  * triangle key).  Edges paired with a vertex are cleared (their columns
  * reduce to zero); an edge with triangles of its own value pairs with the
- * first of them (as in vr_pairs_dim1_apparent); every other edge's column is
- * reduced, youngest first, by one work-group.  The pairs equal those of the
- * column algorithm on the whole boundary matrix (Section 2.2.2).
+ * first of them (as in vr_pairs_dim1_apparent); every other edge's column
+ * first takes, all columns at once, the coboundaries of the apparent pairs
+ * its pivot meets, up to its first pivot that is not apparent (these
+ * additions depend on no other column), and is then reduced, youngest first,
+ * by one work-group.  The pairs equal those of the column algorithm on the
+ * whole boundary matrix (Section 2.2.2).
  * res:          a single build's result with its triangle keys (maxdim 2,
  *               not count-only).
  * e_low:        device, K int32: vr_pairs_dim0's e_low for this result.
@@ -343,8 +346,8 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  * The working column is a base list in device memory plus a short sorted
  * delta in LDS that takes the additions and is folded into the base when
  * full.  Synchronises `stream` (a status word is read back).  Scratch from
- * the library's cache: 4 n^2 + 24 K + 12 H bytes (H = 2K rounded up to a
- * power of two) plus 224 MiB (the reduced columns, 2^24 keys, and three
+ * the library's cache: 4 n^2 + 36 K + 16 H bytes (H = 2K rounded up to a
+ * power of two) plus 608 MiB (the stored columns, 2^26 keys, and three
  * working lists of 2^22 keys).  VR_ENOMEM when the columns outgrow that.
  * VR_EINVAL for a null argument, n > VR_MAX_POINTS or T >= 2^31.  With no
  * triangles (T = 0) no edge dies. */

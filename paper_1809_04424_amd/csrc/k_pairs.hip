@@ -622,35 +622,50 @@ extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, voi
 //   - apparent: an edge with triangles of its own value keeps its
 //     coboundary, whose pivot is the first of them (a younger column holds
 //     only triangles of larger values), so the two pair at once;
-//   - the rest, reduced here by one work-group, youngest first: while the
-//     working column (sorted keys) is not empty, its pivot p is looked up;
-//     an apparent pivot adds that edge's coboundary, the pivot of a column
-//     reduced before adds that column, and a new pivot pairs the edge with
-//     p (a bar [r, value of p)) and stores the column under p.  A column
-//     that empties is a class born at r that never dies.
+//   - the rest, reduced youngest first: while the working column (sorted
+//     keys) is not empty, its pivot p is looked up; an apparent pivot adds
+//     that edge's coboundary, the pivot of a column reduced before adds
+//     that column, and a new pivot pairs the edge with p (a bar [r, value
+//     of p)) and stores the column under p.  A column that empties is a
+//     class born at r that never dies.  The additions of apparent
+//     coboundaries up to the first other pivot are made for all columns at
+//     once (k_rd_pre); one work-group then finishes the columns in order
+//     (k_rd_reduce).
 // Additions are over F2: the symmetric difference of two sorted lists, a
 // merge that drops the keys present in both.  Every addition removes the
 // pivot and adds only larger keys, so the pivot grows and the loop ends.
 #define RD_BLOCK 1024
 #define RD_WAVES (RD_BLOCK / 64)
 #define RD_GEN_MAX 8192                    // coboundary of one edge: at most n - 2 triangles
-#define RD_POOL_ENTRIES (1ll << 24)        // stored reduced columns (keys)
+#define RD_POOL_ENTRIES (1ll << 26)        // stored columns (keys)
 #define RD_WORK_ENTRIES (1ll << 22)        // one working column (keys)
 #define RD_EMPTY 0ull                      // no triangle key is 0 (its largest vertex is >= 2)
 
 struct RdCtl {
     int32_t m;        // columns to reduce
     int32_t err;      // 1: stored columns outgrew the pool, 2: a working column outgrew its buffer
+    long long ptop;   // pool entries the first pass took
+    int32_t next;     // the first pass's next column
+};
+
+// What the first pass left of a column (RdBufs::pst)
+#define RD_ST_EMPTY 0  // reduced to zero: a class that never dies
+#define RD_ST_PIVOT 1  // stored in the pool, pivot in rkey: new unless a column before holds it
+#define RD_ST_REDO 2   // outgrew the first pass's buffers: reduced from the start
+
+// A slot of the table of pivots: the key (RD_EMPTY: a free slot) and where
+// the stored column holding it lies in the pool.
+struct __attribute__((aligned(16))) RdSlot {
+    unsigned long long key;
+    uint32_t start, len;
 };
 
 struct RdBufs {
     const int32_t *R;               // n x n ranks (+inf off the edges, -1 on the diagonal)
     const int32_t *ij;              // K edges (i, j)
-    const unsigned long long *key;  // T triangle keys, filtration order
-    const int32_t *first;           // K: first triangle of value r, or -1 (the apparent pairs)
+    const unsigned long long *app;  // K: the key of edge r's apparent pivot, or RD_EMPTY
     const int32_t *rem;             // the columns to reduce, youngest first
-    unsigned long long *tkey;       // table of pivots: key (RD_EMPTY: free slot)
-    int32_t *tcol;                  //   and the column holding it
+    RdSlot *tab;                    // table of pivots
     long long hmask;                // table slots - 1 (a power of two, at least twice the columns)
     unsigned long long *pool;       // reduced columns, back to back
     long long *cstart;              // column ci: its keys start here in the pool
@@ -658,6 +673,7 @@ struct RdBufs {
     unsigned long long *w[2];       // working column, ping-pong
     unsigned long long *mrg;        // merged keys before the cancellation
     unsigned long long *rkey;       // per column: its pivot, or RD_EMPTY for a class that never dies
+    int32_t *pst;                   // per column: what the first pass left (RD_ST_*)
     RdCtl *ctl;
     int64_t n, K;
 };
@@ -687,6 +703,19 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_list(const int32_t *first, cons
     if (t == 0) {
         ctl->m = (int32_t)run;
         ctl->err = 0;
+        ctl->ptop = 0;
+        ctl->next = 0;
+    }
+}
+
+// app[r] = the key of the first triangle of value r when it pairs with edge
+// r (an apparent pair), else RD_EMPTY: one load tells whether a pivot is
+// apparent.
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_app(const int32_t *first, const unsigned long long *key, int64_t K,
+                                                    unsigned long long *app) {
+    for (int64_t r = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; r < K; r += (int64_t)gridDim.x * PD_BLOCK) {
+        const int32_t f = first[r];
+        app[r] = f >= 0 ? key[f] : RD_EMPTY;
     }
 }
 
@@ -721,23 +750,48 @@ static __device__ __forceinline__ unsigned long long rd_tri_key(uint32_t v, uint
     return ((unsigned long long)v << 39) | ((unsigned long long)lo << 26) | ((unsigned long long)mid << 13) | hi;
 }
 
-// The coboundary of edge e, sorted, into g (LDS); returns its length.
-static __device__ uint32_t rd_gen(const RdBufs &B, int64_t e, unsigned long long *g, uint32_t *sh) {
+// Order the LDS accesses of one wave (a bitonic stage whose partners lie
+// within the wave's own elements needs no work-group barrier).
+static __device__ __forceinline__ void rd_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+#define RD_SEG (VR_MAX_POINTS / RD_BLOCK)  // vertices per thread in rd_gen
+
+// The coboundary of edge e, sorted, into g (LDS); returns its length.  Each
+// thread takes a run of at most RD_SEG consecutive vertices k (its loads
+// all in flight at once), one scan places the keys.  Bitonic sort: in a
+// stage of partner distance j <= 64 every wave reads and writes only its
+// own 128-element blocks, so consecutive such stages need only the wave's
+// own ordering.
+static __device__ uint32_t rd_gen_ab(const RdBufs &B, int64_t e, int32_t a, int32_t b, unsigned long long *g,
+                                     uint32_t *sh) {
     const int t = threadIdx.x;
-    const int32_t a = B.ij[2 * e], b = B.ij[2 * e + 1];
     const int32_t *Ra = B.R + (int64_t)a * B.n, *Rb = B.R + (int64_t)b * B.n;
-    uint32_t run = 0;
-    for (int64_t k0 = 0; k0 < B.n; k0 += RD_BLOCK) {
-        const int64_t k = k0 + t;
-        const int64_t kc = k < B.n ? k : B.n - 1;
-        const int32_t x = Ra[kc], y = Rb[kc];
-        const bool ok = k < B.n && k != a && k != b && x != PD_INF && y != PD_INF;
-        uint32_t tot;
-        const uint32_t at = rd_scan(ok ? 1u : 0u, sh, &tot);
-        if (ok) g[run + at] = rd_tri_key((uint32_t)max((int32_t)e, max(x, y)), (uint32_t)a, (uint32_t)b, (uint32_t)k);
-        run += tot;
+    const int S = (int)((B.n + RD_BLOCK - 1) / RD_BLOCK);
+    const int k0 = t * S;
+    int32_t val[RD_SEG];
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < RD_SEG; u++) {
+        const int k = k0 + u;
+        val[u] = -1;
+        if (u < S && k < B.n) {
+            const int32_t x = Ra[k], y = Rb[k];
+            if (k != a && k != b && x != PD_INF && y != PD_INF) {
+                val[u] = max((int32_t)e, max(x, y));
+                c++;
+            }
+        }
     }
-    // bitonic sort of the keys, padded to a power of two with the largest key
+    uint32_t run;
+    uint32_t at = rd_scan(c, sh, &run);
+#pragma unroll
+    for (int u = 0; u < RD_SEG; u++)
+        if (val[u] >= 0) g[at++] = rd_tri_key((uint32_t)val[u], (uint32_t)a, (uint32_t)b, (uint32_t)(k0 + u));
+    // padded to a power of two with the largest key
     uint32_t P = 1;
     while (P < run) P <<= 1;
     for (uint32_t x = run + t; x < P; x += RD_BLOCK) g[x] = ~0ull;
@@ -752,9 +806,15 @@ static __device__ uint32_t rd_gen(const RdBufs &B, int64_t e, unsigned long long
                     g[hi] = x0;
                 }
             }
-            __syncthreads();
+            const uint32_t jn = j > 1 ? j >> 1 : kk;  // the next stage's distance
+            if (j > 64 || jn > 64 || (j == 1 && kk == P)) __syncthreads();
+            else rd_wave_sync();
         }
     return run;
+}
+
+static __device__ uint32_t rd_gen(const RdBufs &B, int64_t e, unsigned long long *g, uint32_t *sh) {
+    return rd_gen_ab(B, e, B.ij[2 * e], B.ij[2 * e + 1], g, sh);
 }
 
 // dst = a + b over F2 (a, b sorted, without repeats); returns dst's length,
@@ -822,16 +882,26 @@ static __device__ __forceinline__ uint32_t rd_lower_bound(const unsigned long lo
     return lo;
 }
 
+#define RD_SMP 2048  // keys of the base's sample in LDS
+
 // dst = a + b over F2 for a sorted base a (global, na keys) and a sorted
-// delta b (LDS, nb <= RD_DCAP keys); sc: LDS scratch of 2 RD_DCAP uint32.
-// Returns the length.  A delta key is matched when the base holds it
-// (both vanish); an unmatched delta key b_j lands at pos_j + j - 2 M_j
-// (pos_j: base keys below it, M_j: matched delta keys before it), an
-// unmatched base key a_i at i + r - 2 M_r (r: delta keys below it).
+// delta b (LDS, nb <= RD_DCAP keys); sc: LDS scratch of 2 RD_DCAP uint32,
+// smp: LDS for RD_SMP keys.  Returns the length.  A delta key is matched
+// when the base holds it (both vanish); an unmatched delta key b_j lands at
+// pos_j + j - 2 M_j (pos_j: base keys below it, M_j: matched delta keys
+// before it), an unmatched base key a_i at i + r - 2 M_r (r: delta keys
+// below it).  The base's every 2^sh-th key is staged in LDS first (the
+// whole base when it fits), so a delta key's place takes a search in LDS
+// and at most sh steps in device memory.
 static __device__ uint32_t rd_fold(const unsigned long long *a, uint32_t na, const unsigned long long *b, uint32_t nb,
-                                   unsigned long long *dst, uint32_t *sc, uint32_t *sh) {
+                                   unsigned long long *dst, uint32_t *sc, unsigned long long *smp, uint32_t *sh) {
     const int t = threadIdx.x;
     uint32_t *pos = sc, *minc = sc + RD_DCAP;  // minc[j]: matched delta keys in [0, j]
+    uint32_t lg = 0;
+    while (((size_t)RD_SMP << lg) < na) lg++;
+    const uint32_t ns = (na + (1u << lg) - 1) >> lg;  // <= RD_SMP
+    for (uint32_t q = t; q < ns; q += RD_BLOCK) smp[q] = a[(size_t)q << lg];
+    __syncthreads();
     uint32_t mloc[RD_DCAP / RD_BLOCK], cnt = 0;
 #pragma unroll
     for (int u = 0; u < RD_DCAP / RD_BLOCK; u++) {
@@ -839,9 +909,17 @@ static __device__ uint32_t rd_fold(const unsigned long long *a, uint32_t na, con
         mloc[u] = 0;
         if (j < nb) {
             const unsigned long long x = b[j];
-            const uint32_t q = rd_lower_bound(a, na, x);
-            pos[j] = q;
-            mloc[u] = (q < na && a[q] == x) ? 1u : 0u;
+            // first sample >= x, then the keys between it and the sample before
+            const uint32_t qs = rd_lower_bound(smp, ns, x);
+            uint32_t lo = qs ? ((qs - 1) << lg) + 1 : 0u, hi = qs < ns ? qs << lg : na;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            pos[j] = lo;
+            const bool on = lo < na && ((lo & ((1u << lg) - 1)) ? a[lo] : smp[lo >> lg]) == x;
+            mloc[u] = on ? 1u : 0u;
         }
         cnt += mloc[u];
     }
@@ -859,7 +937,7 @@ static __device__ uint32_t rd_fold(const unsigned long long *a, uint32_t na, con
         if (minc[j] == mex) dst[pos[j] + j - 2 * mex] = b[j];
     }
     for (uint32_t i = t; i < na; i += RD_BLOCK) {
-        const unsigned long long y = a[i];
+        const unsigned long long y = lg ? a[i] : smp[i];
         uint32_t lo = 0, hi = nb;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -919,81 +997,252 @@ static __device__ uint32_t rd_delta_add(const unsigned long long *d, uint32_t nd
     return tot;
 }
 
-__global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
+// First pass, one work-group per column at a time, columns in any order:
+// adding the coboundary of an apparent pair's edge depends on no other
+// column, so every column can take these additions at once, up to its
+// first pivot that is not apparent.  The serial pass below then meets the
+// same working column it would have built itself.  A column kept whole in
+// LDS (at most RD_DCAP keys) is stored in the pool with its pivot; one
+// that outgrows LDS is left for the serial pass to reduce from the start.
+__global__ void __launch_bounds__(RD_BLOCK) k_rd_pre(RdBufs B) {
     __shared__ unsigned long long g[RD_GEN_MAX];
     __shared__ unsigned long long dl[2][RD_DCAP];
     __shared__ uint32_t sh[RD_WAVES];
-    __shared__ int32_t s_act, s_arg;
-    __shared__ uint32_t s_h, s_dh;
+    __shared__ int32_t s_ci, s_arg, s_a, s_b;
+    __shared__ long long s_off;
+    const int t = threadIdx.x;
+    const int32_t m = B.ctl->m;
+    for (;;) {
+        if (t == 0) s_ci = atomicAdd(&B.ctl->next, 1);
+        __syncthreads();
+        const int32_t ci = s_ci;
+        __syncthreads();
+        if (ci >= m) break;
+        uint32_t nd = rd_gen(B, B.rem[ci], g, sh);
+        int dc = 0;
+        int32_t st = RD_ST_REDO;
+        if (nd <= RD_DCAP) {
+            for (uint32_t x = t; x < nd; x += RD_BLOCK) dl[0][x] = g[x];
+            __syncthreads();
+            for (;;) {
+                if (t == 0) {
+                    // -1: the pivot is not apparent (or the column is empty)
+                    int32_t arg = -1;
+                    if (nd > 0) {
+                        const unsigned long long p = dl[dc][0];
+                        const int64_t v = (int64_t)(p >> 39);
+                        if (v < B.K) {
+                            const unsigned long long ap = B.app[v];
+                            const int32_t ea = B.ij[2 * v], eb = B.ij[2 * v + 1];
+                            if (ap == p) {
+                                arg = (int32_t)v;
+                                s_a = ea;
+                                s_b = eb;
+                            }
+                        }
+                    }
+                    s_arg = arg;
+                }
+                __syncthreads();
+                const int32_t arg = s_arg;
+                if (arg < 0) {
+                    st = nd ? RD_ST_PIVOT : RD_ST_EMPTY;
+                    break;
+                }
+                const uint32_t nx = rd_gen_ab(B, arg, s_a, s_b, g, sh);  // its barriers end every read of s_*
+                if (nd + nx > RD_DCAP) break;
+                nd = rd_delta_add(dl[dc], nd, g, nx, dl[dc ^ 1], sh);
+                dc ^= 1;
+            }
+        }
+        if (st == RD_ST_PIVOT) {
+            if (t == 0) s_off = (long long)atomicAdd((unsigned long long *)&B.ctl->ptop, (unsigned long long)nd);
+            __syncthreads();
+            const long long off = s_off;
+            if (off + nd <= RD_POOL_ENTRIES) {
+                for (uint32_t x = t; x < nd; x += RD_BLOCK) B.pool[off + x] = dl[dc][x];
+                if (t == 0) {
+                    B.cstart[ci] = off;
+                    B.clen[ci] = (int32_t)nd;
+                    B.rkey[ci] = dl[dc][0];
+                }
+            } else {
+                st = RD_ST_REDO;
+            }
+        }
+        if (t == 0) {
+            B.pst[ci] = st;
+            if (st == RD_ST_EMPTY) B.rkey[ci] = RD_EMPTY;
+        }
+        __syncthreads();
+    }
+}
+
+// The serial pass, one work-group, columns youngest first.  Wave 0 walks
+// over the columns the first pass finished, 64 at a time: an empty one, or
+// a pivot that neither the table nor a column before it in the batch holds
+// (these go into the table), up to the next column with work left: a
+// pivot already held (the column continues from its stored keys) or a
+// column to reduce from the start.  Thread 0 looks up each pivot (its
+// apparent key and its table slot, two independent loads) and the work-
+// group makes the addition; a stored column is staged in LDS first.
+__global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
+    __shared__ unsigned long long g[RD_GEN_MAX];
+    __shared__ unsigned long long dl[2][RD_DCAP];
+    __shared__ unsigned long long smp[RD_SMP];
+    __shared__ uint32_t sh[RD_WAVES];
+    __shared__ int32_t s_act, s_ci;
+    __shared__ uint32_t s_h, s_dh, s_a0, s_a1, s_a2;
     __shared__ unsigned long long s_piv;
     const int t = threadIdx.x;
     const int32_t m = B.ctl->m;
-    int cur = 0, dc = 0;  // base buffer, delta buffer
-    long long top = 0;    // pool entries used (every thread keeps the same count)
-    for (int32_t ci = 0; ci < m; ci++) {
-        const int64_t r = B.rem[ci];
-        // base: empty; delta: the coboundary (or the base, when it is longer)
+    long long top = min(B.ctl->ptop, RD_POOL_ENTRIES);  // pool entries used (every thread keeps the same count)
+    int32_t ci = 0;
+    for (;; ci++) {
+        if (t < 64) {
+            for (;;) {
+                const int32_t c = ci + t;
+                int32_t st = RD_ST_REDO;
+                unsigned long long p = RD_EMPTY;
+                uint32_t start = 0, len = 0;
+                if (c < m) {
+                    st = B.pst[c];
+                    p = B.rkey[c];
+                    start = (uint32_t)B.cstart[c];
+                    len = (uint32_t)B.clen[c];
+                }
+                const bool piv = c < m && st == RD_ST_PIVOT;
+                bool stop = !(c < m && (st == RD_ST_EMPTY || piv));
+                long long sl = rd_slot(p, B.hmask);
+                if (piv)
+                    for (;; sl = (sl + 1) & B.hmask) {
+                        const unsigned long long q = B.tab[sl].key;
+                        if (q == RD_EMPTY) break;
+                        if (q == p) {
+                            stop = true;
+                            break;
+                        }
+                    }
+                for (int j = 0; j < 63; j++) {
+                    const unsigned long long pj = __shfl(p, j, 64);
+                    const int32_t sj = __shfl(st, j, 64);
+                    if (j < t && piv && sj == RD_ST_PIVOT && pj == p) stop = true;
+                }
+                const unsigned long long bal = __ballot(stop);
+                const int f = bal ? __builtin_ctzll(bal) : 64;
+                if (t < f && piv) {
+                    // a new pivot (distinct within the batch): claim a slot
+                    for (;; sl = (sl + 1) & B.hmask)
+                        if (atomicCAS((unsigned long long *)&B.tab[sl].key, RD_EMPTY, p) == RD_EMPTY) break;
+                    B.tab[sl].start = start;
+                    B.tab[sl].len = len;
+                }
+                ci += f;
+                if (f < 64) break;
+            }
+            if (t == 0) s_ci = ci;
+        }
+        __syncthreads();
+        ci = s_ci;
+        __syncthreads();
+        if (ci >= m) break;
+        // the base (global, entries before h gone) and the delta (LDS); bp
+        // is the base, w[wn] the buffer the next rewrite of the base goes to
+        const unsigned long long *bp = B.w[0];
+        int wn = 1, dc = 0;
         uint32_t nw = 0, h = 0, nd = 0, dh = 0;
-        {
-            const uint32_t len = rd_gen(B, r, g, sh);
+        if (B.pst[ci] == RD_ST_PIVOT) {
+            bp = B.pool + B.cstart[ci];
+            nw = (uint32_t)B.clen[ci];
+            wn = 0;
+        } else {
+            // delta: the coboundary (or the base, when it is longer)
+            const uint32_t len = rd_gen(B, B.rem[ci], g, sh);
             if (len <= RD_DCAP) {
                 for (uint32_t x = t; x < len; x += RD_BLOCK) dl[dc][x] = g[x];
                 nd = len;
             } else {
-                for (uint32_t x = t; x < len; x += RD_BLOCK) B.w[cur][x] = g[x];
+                for (uint32_t x = t; x < len; x += RD_BLOCK) B.w[0][x] = g[x];
                 nw = len;
             }
             __threadfence_block();
             __syncthreads();
         }
         for (;;) {
-            if (t == 0) {
+            if (t < 64) {
                 // the pivot: the smaller head, keys in both heads cancelling
+                // (64 head pairs compared at a time)
+                const int lane = t;
                 unsigned long long p = 0;
                 bool any = false;
                 for (;;) {
-                    const bool ha = h < nw, hb = dh < nd;
-                    if (!ha && !hb) break;
-                    const unsigned long long ya = ha ? B.w[cur][h] : ~0ull, yb = hb ? dl[dc][dh] : ~0ull;
-                    if (ha && hb && ya == yb) {
-                        h++;
-                        dh++;
+                    const bool ha = h + lane < nw, hb = dh + lane < nd;
+                    const unsigned long long ya = ha ? bp[h + lane] : ~0ull, yb = hb ? dl[dc][dh + lane] : ~0ull;
+                    const unsigned long long diff = __ballot(!(ha && hb && ya == yb));
+                    if (!diff) {
+                        h += 64;
+                        dh += 64;
                         continue;
                     }
-                    p = min(ya, yb);
-                    any = true;
+                    const int f = __builtin_ctzll(diff);
+                    h += f;
+                    dh += f;
+                    p = min(__shfl(ya, f, 64), __shfl(yb, f, 64));
+                    any = h < nw || dh < nd;
                     break;
                 }
-                // 0: never dies; 1: add the coboundary of edge s_arg; 2: add
-                // stored column s_arg; 3: new pivot
-                int32_t act = 0, arg = -1;
+                // 0: never dies; 1: add the coboundary of edge a0 = {a1, a2};
+                // 2: add the stored column of a1 keys at a0; 3: new pivot.
+                // The apparent key, the edge's endpoints and 64 table slots
+                // are loaded at once.
+                int32_t act = 0;
+                uint32_t a0 = 0, a1 = 0, a2 = 0;
                 if (any) {
                     const int64_t v = (int64_t)(p >> 39);
-                    const int32_t f = v < B.K ? B.first[v] : -1;
-                    if (f >= 0 && B.key[f] == p) {
-                        act = 1;
-                        arg = (int32_t)v;
-                    } else {
-                        act = 3;
-                        for (long long s = rd_slot(p, B.hmask);; s = (s + 1) & B.hmask) {
-                            const unsigned long long q = B.tkey[s];
-                            if (q == RD_EMPTY) break;
-                            if (q == p) {
-                                act = 2;
-                                arg = B.tcol[s];
-                                break;
-                            }
+                    unsigned long long ap = RD_EMPTY;
+                    int32_t ea = 0, eb = 0;
+                    if (lane == 0 && v < B.K) {
+                        ap = B.app[v];
+                        ea = B.ij[2 * v];
+                        eb = B.ij[2 * v + 1];
+                    }
+                    long long sl = rd_slot(p, B.hmask);
+                    act = 3;
+                    for (;;) {
+                        const RdSlot q = B.tab[(sl + lane) & B.hmask];
+                        const unsigned long long stop = __ballot(q.key == p || q.key == RD_EMPTY);
+                        if (!stop) {
+                            sl += 64;
+                            continue;
                         }
+                        const int f = __builtin_ctzll(stop);
+                        if (__shfl(q.key, f, 64) == p) {
+                            act = 2;
+                            a0 = __shfl(q.start, f, 64);
+                            a1 = __shfl(q.len, f, 64);
+                        }
+                        break;
+                    }
+                    if (__shfl(ap, 0, 64) == p) {
+                        act = 1;
+                        a0 = (uint32_t)v;
+                        a1 = (uint32_t)__shfl(ea, 0, 64);
+                        a2 = (uint32_t)__shfl(eb, 0, 64);
                     }
                 }
-                s_act = act;
-                s_arg = arg;
-                s_piv = p;
-                s_h = h;
-                s_dh = dh;
+                if (lane == 0) {
+                    s_act = act;
+                    s_a0 = a0;
+                    s_a1 = a1;
+                    s_a2 = a2;
+                    s_piv = p;
+                    s_h = h;
+                    s_dh = dh;
+                }
             }
             __syncthreads();
-            const int32_t act = s_act, arg = s_arg;
+            const int32_t act = s_act;
+            const uint32_t a0 = s_a0, a1 = s_a1, a2 = s_a2;
             const unsigned long long p = s_piv;
             h = s_h;
             dh = s_dh;
@@ -1006,15 +1255,12 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                         if (t == 0) B.ctl->err = 1;
                         return;
                     }
-                    const uint32_t len = rd_fold(B.w[cur] + h, nw - h, dl[dc] + dh, nd - dh, B.pool + top,
-                                                 (uint32_t *)dl[dc ^ 1], sh);
+                    const uint32_t len =
+                        rd_fold(bp + h, nw - h, dl[dc] + dh, nd - dh, B.pool + top, (uint32_t *)dl[dc ^ 1], smp, sh);
                     if (t == 0) {
-                        B.cstart[ci] = top;
-                        B.clen[ci] = (int32_t)len;
-                        long long s = rd_slot(p, B.hmask);
-                        while (B.tkey[s] != RD_EMPTY) s = (s + 1) & B.hmask;
-                        B.tkey[s] = p;
-                        B.tcol[s] = ci;
+                        long long sl = rd_slot(p, B.hmask);
+                        while (B.tab[sl].key != RD_EMPTY) sl = (sl + 1) & B.hmask;
+                        B.tab[sl] = RdSlot{p, (uint32_t)top, len};
                     }
                     top += len;
                 }
@@ -1023,15 +1269,19 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                 __syncthreads();
                 break;
             }
-            // the column to add: a coboundary (in g) or a stored column
-            const unsigned long long *x;
+            // the column to add: a coboundary or a stored column, in g
+            const unsigned long long *x = g;
             uint32_t nx;
             if (act == 1) {
-                nx = rd_gen(B, arg, g, sh);
-                x = g;
+                nx = rd_gen_ab(B, a0, (int32_t)a1, (int32_t)a2, g, sh);
             } else {
-                x = B.pool + B.cstart[arg];
-                nx = (uint32_t)B.clen[arg];
+                nx = a1;
+                if (nx <= RD_DCAP) {
+                    for (uint32_t y = t; y < nx; y += RD_BLOCK) g[y] = B.pool[a0 + y];
+                    __syncthreads();
+                } else {
+                    x = B.pool + a0;
+                }
             }
             if ((nd - dh) + nx > RD_DCAP) {
                 // fold the delta into the base first
@@ -1039,8 +1289,9 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                     if (t == 0) B.ctl->err = 2;
                     return;
                 }
-                nw = rd_fold(B.w[cur] + h, nw - h, dl[dc] + dh, nd - dh, B.w[cur ^ 1], (uint32_t *)dl[dc ^ 1], sh);
-                cur ^= 1;
+                nw = rd_fold(bp + h, nw - h, dl[dc] + dh, nd - dh, B.w[wn], (uint32_t *)dl[dc ^ 1], smp, sh);
+                bp = B.w[wn];
+                wn ^= 1;
                 h = 0;
                 nd = dh = 0;
             }
@@ -1050,12 +1301,13 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                 dh = 0;
             } else {
                 // a column longer than the delta goes straight into the base
-                const uint32_t nl = rd_add(B.w[cur] + h, nw - h, x, nx, B.mrg, B.w[cur ^ 1], sh);
+                const uint32_t nl = rd_add(bp + h, nw - h, x, nx, B.mrg, B.w[wn], sh);
                 if (nl == ~0u) {
                     if (t == 0) B.ctl->err = 2;
                     return;
                 }
-                cur ^= 1;
+                bp = B.w[wn];
+                wn ^= 1;
                 nw = nl;
                 h = 0;
             }
@@ -1099,8 +1351,8 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     size_t o = 0;
     const size_t o_R = o; o = up(o + 4 * (size_t)n * (size_t)n);
     const size_t o_rem = o; o = up(o + 4 * (size_t)K);
-    const size_t o_tkey = o; o = up(o + 8 * (size_t)H);
-    const size_t o_tcol = o; o = up(o + 4 * (size_t)H);
+    const size_t o_tab = o; o = up(o + sizeof(RdSlot) * (size_t)H);
+    const size_t o_app = o; o = up(o + 8 * (size_t)K);
     const size_t o_pool = o; o = up(o + 8 * (size_t)RD_POOL_ENTRIES);
     const size_t o_cst = o; o = up(o + 8 * (size_t)K);
     const size_t o_cln = o; o = up(o + 4 * (size_t)K);
@@ -1108,17 +1360,16 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     const size_t o_w1 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
     const size_t o_mrg = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
     const size_t o_rkey = o; o = up(o + 8 * (size_t)K);
+    const size_t o_pst = o; o = up(o + 4 * (size_t)K);
     const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
     char *ws = (char *)cache_get(o, s);
     if (!ws) return VR_ENOMEM;
     RdBufs B;
     B.R = (const int32_t *)(ws + o_R);
     B.ij = (const int32_t *)res->edge_ij;
-    B.key = (const unsigned long long *)res->tri_key;
-    B.first = tri_of_edge;
+    B.app = (const unsigned long long *)(ws + o_app);
     B.rem = (const int32_t *)(ws + o_rem);
-    B.tkey = (unsigned long long *)(ws + o_tkey);
-    B.tcol = (int32_t *)(ws + o_tcol);
+    B.tab = (RdSlot *)(ws + o_tab);
     B.hmask = H - 1;
     B.pool = (unsigned long long *)(ws + o_pool);
     B.cstart = (long long *)(ws + o_cst);
@@ -1127,6 +1378,7 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     B.w[1] = (unsigned long long *)(ws + o_w1);
     B.mrg = (unsigned long long *)(ws + o_mrg);
     B.rkey = (unsigned long long *)(ws + o_rkey);
+    B.pst = (int32_t *)(ws + o_pst);
     B.ctl = (RdCtl *)(ws + o_ctl);
     B.n = n;
     B.K = K;
@@ -1135,7 +1387,17 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n);
     hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n,
                        (const int32_t *)res->edge_ij, K, n);
-    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(H)), dim3(PD_BLOCK), 0, s, B.tkey, H);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(2 * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab, 2 * H);
+    hipLaunchKernelGGL(k_rd_app, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const int32_t *)tri_of_edge,
+                       (const unsigned long long *)res->tri_key, K, (unsigned long long *)(ws + o_app));
+    // the first pass: one work-group per compute unit (its LDS takes most of one)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        cache_put(ws, s);
+        return VR_EHIP;
+    }
+    hipLaunchKernelGGL(k_rd_pre, dim3((unsigned)(K < cus ? K : cus)), dim3(RD_BLOCK), 0, s, B);
     hipLaunchKernelGGL(k_rd_reduce, dim3(1), dim3(RD_BLOCK), 0, s, B);
     hipLaunchKernelGGL(k_rd_emit, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key, T,
                        (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
