@@ -105,7 +105,8 @@ typedef struct vr_request {
     int32_t dtype;      /* VR_I8, VR_I16, VR_I32, or VR_DIST (a dissimilarity matrix) */
     int32_t thr_kind;   /* VR_THR_* */
     int64_t thr_num, thr_den;
-    int32_t maxdim;     /* 0: vertices only, 1: up to edges, 2: up to triangles */
+    int32_t maxdim;     /* 0: vertices only, 1: up to edges, 2: up to triangles,
+                           3: also tetrahedra (vr_build only) */
     uint32_t flags;     /* VR_COUNT_ONLY | VR_TIMING | VR_TIMING_WRITE */
     const vr_allocator *alloc; /* NULL: the library's stream-ordered cache */
 } vr_request;
@@ -122,6 +123,15 @@ typedef struct vr_result {
     /* device, T: triangle keys v<<39 | i<<26 | j<<13 | k, i<j<k, v = largest
      * edge rank; ascending, which is filtration order (NULL with VR_COUNT_ONLY) */
     const uint64_t *tri_key;
+    /* maxdim 3 only (else 0 and NULL): the tetrahedra, T3 of them, in
+     * filtration order (by value, the largest edge rank, then by vertices).
+     * tet_off: device, K + 1: tet_off[r] = the first tetrahedron of value r,
+     * tet_off[K] = T3.  tet_key: device, 2 T3: tetrahedron t has value
+     * tet_key[2t] and vertices tet_key[2t+1] = a<<39 | b<<26 | c<<13 | d,
+     * a<b<c<d (NULL with VR_COUNT_ONLY). */
+    int64_t n_tetrahedra;
+    const int64_t *tet_off;
+    const uint64_t *tet_key;
 } vr_result;
 
 /*
@@ -154,6 +164,11 @@ typedef struct vr_result {
  * receives a new handle whose device arrays are complete once `stream`
  * reaches the end of this call's work (stream order).  On error *out is
  * not written and nothing is leaked.
+ * maxdim 3 (dimension 3 of Section 3's bettimax = 2: tetrahedra, so that
+ * classes of dimension 2 can die): after the triangles the tetrahedra are
+ * counted per value, their offsets scanned and read back (a second wait),
+ * and listed into a second output block, as by vr_tetra_offsets and
+ * vr_tetra_write (not combined with VR_GRAPH).
  */
 VR_API int vr_build(const vr_request *req, void *stream, vr_result **out);
 
@@ -209,6 +224,7 @@ VR_API int64_t vr_workspace_bytes(int64_t n, int64_t d, int32_t dtype, int32_t t
  * Other limits of the whole batch: fewer than 2^24 vertices, fewer than 2^30
  * pairs and 2^31 kept edges (VR_E2BIG).  Each request keeps the per-cloud
  * limits of vr_build.  Same stream semantics and error behaviour as vr_build.
+ * maxdim 3 is vr_build's alone (VR_EINVAL here).
  */
 typedef struct vr_batch vr_batch;
 

@@ -28,7 +28,10 @@ passage of arXiv:1809.04424 it follows:
   whole and partitioned by columns as the paper's workers compute it
   (Section 4.6);
 * persistence pairs: Algorithm 1 over F2 on the boundary matrix, and the same
-  algorithm on the anti-transpose with clearing (Sections 2.2.1, 2.2.2).
+  algorithm on the anti-transpose with clearing (Sections 2.2.1, 2.2.2);
+  one dimension up, the pairs of triangles with tetrahedra by both (the
+  boundary block of the tetrahedra; the triangles' coboundaries with the
+  triangles paired with edges cleared).
 """
 from __future__ import annotations
 
@@ -82,6 +85,10 @@ def lib():
     L.or_reduce_homology.restype = None
     L.or_reduce_cohomology.argtypes = [i64, i64, _I64P, _I64P, i64, _I64P, _I64P, _I64P]
     L.or_reduce_cohomology.restype = None
+    L.or_reduce_dim2_homology.argtypes = [i64, i64, _I64P, _I64P, i64, _I64P, i64, _I64P, _I64P]
+    L.or_reduce_dim2_homology.restype = None
+    L.or_reduce_dim2_cohomology.argtypes = [i64, i64, _I64P, _I64P, i64, _I64P, _I64P, i64, _I64P, _I64P]
+    L.or_reduce_dim2_cohomology.restype = None
     L.or_column_order.argtypes = [i64, _I64P, _I64P, _I64P]
     L.or_column_order.restype = None
     L.or_sqdist_mt.argtypes = [vp, i64, i64, ctypes.c_int, _I64P, ctypes.c_int]
@@ -286,10 +293,12 @@ def triangles_of_value(f: Filtration, r: int) -> np.ndarray:
 
 @dataclass
 class Pairs:
-    """Persistence pairs and essential simplices of a dim<=2 filtration.
+    """Persistence pairs and essential simplices of a dim<=2 filtration
+    (dim<=3 once q_low is set by with_dim2).
 
     e_low[r]: vertex paired with edge r (an H0 death at edge r) or -1.
     t_low[t]: edge paired with triangle t (an H1 death at triangle t) or -1.
+    q_low[s]: triangle paired with tetrahedron s (an H2 death at s) or -1.
     """
 
     e_low: np.ndarray
@@ -297,9 +306,12 @@ class Pairs:
     n: int
     K: int
     T: int
+    q_low: np.ndarray | None = None
+    T3: int = 0
 
     def essential(self):
-        """Essential simplices per dimension: never paired as birth or death."""
+        """Essential simplices per dimension: never paired as birth or death
+        (three dimensions, four once the tetrahedra are paired)."""
         v_paired = np.zeros(self.n, bool)
         v_paired[self.e_low[self.e_low >= 0]] = True
         e_paired = self.e_low >= 0
@@ -308,12 +320,16 @@ class Pairs:
         t_paired = self.t_low >= 0
         ess0 = np.nonzero(~v_paired)[0]
         ess1 = np.nonzero(~(e_paired | e_birth))[0]
-        ess2 = np.nonzero(~t_paired)[0]
-        return ess0, ess1, ess2
+        if self.q_low is None:
+            return ess0, ess1, np.nonzero(~t_paired)[0]
+        t_birth = np.zeros(self.T, bool)
+        t_birth[self.q_low[self.q_low >= 0]] = True
+        ess2 = np.nonzero(~(t_paired | t_birth))[0]
+        ess3 = np.nonzero(self.q_low < 0)[0]
+        return ess0, ess1, ess2, ess3
 
     def betti(self):
-        a, b, c = self.essential()
-        return len(a), len(b), len(c)
+        return tuple(len(x) for x in self.essential())
 
 
 def reduce(f: Filtration, method: str = "cohomology", clear: bool = True) -> Pairs:
@@ -336,10 +352,44 @@ def reduce(f: Filtration, method: str = "cohomology", clear: bool = True) -> Pai
     return Pairs(e_low=e_low[: f.K], t_low=t_low[:T], n=f.n, K=f.K, T=T)
 
 
-def barcode(f: Filtration, pairs: Pairs):
+def reduce_dim2(f: Filtration, tets: np.ndarray, method: str = "cohomology", t_low=None) -> np.ndarray:
+    """Pairs of triangles with tetrahedra: q_low[s] = the triangle paired
+    with tetrahedron s (row s of tets, as tetra_list gives them), or -1.
+    method="homology": Algorithm 1 on the tetrahedra's boundary block;
+    "cohomology": on the anti-transpose, triangles from last to first, those
+    paired with an edge (t_low, from reduce) cleared (Section 2.2.2)."""
+    L = lib()
+    tris = f.tris if f.tris is not None else np.zeros((0, 4), np.int64)
+    T, T3 = len(tris), len(tets)
+    q_low = np.full(max(T3, 1), -1, np.int64)
+    flat = np.ascontiguousarray(tris.reshape(-1)) if T else np.zeros(4, np.int64)
+    tflat = np.ascontiguousarray(np.asarray(tets, np.int64).reshape(-1)) if T3 else np.zeros(5, np.int64)
+    ei = f.ei if f.K else np.zeros(1, np.int64)
+    ej = f.ej if f.K else np.zeros(1, np.int64)
+    if method == "homology":
+        L.or_reduce_dim2_homology(f.n, f.K, ei, ej, T, flat, T3, tflat, q_low)
+    elif method == "cohomology":
+        if t_low is None:
+            t_low = reduce(f, "cohomology").t_low
+        tl = np.ascontiguousarray(np.asarray(t_low, np.int64)) if T else np.zeros(1, np.int64)
+        L.or_reduce_dim2_cohomology(f.n, f.K, ei, ej, T, flat, tl, T3, tflat, q_low)
+    else:
+        raise ValueError(method)
+    return q_low[:T3]
+
+
+def with_dim2(f: Filtration, pairs: Pairs, tets: np.ndarray, method: str = "cohomology") -> Pairs:
+    """The pairs extended by the triangle-tetrahedron pairs (reduce_dim2)."""
+    q = reduce_dim2(f, tets, method, pairs.t_low)
+    return Pairs(e_low=pairs.e_low, t_low=pairs.t_low, n=pairs.n, K=pairs.K, T=pairs.T, q_low=q, T3=len(tets))
+
+
+def barcode(f: Filtration, pairs: Pairs, tets: np.ndarray | None = None):
     """Bars (dim, birth_value, death_value); vertices have value -1, edges their
-    rank, triangles their value.  Essential bars die at +inf (INT64_MAX).
-    Zero-length bars (birth == death) are dropped."""
+    rank, triangles and tetrahedra their value (largest edge rank).  Essential
+    bars die at +inf (INT64_MAX).  Zero-length bars (birth == death) are
+    dropped.  With the tetrahedra (pairs from with_dim2, tets their rows) the
+    bars of dimension 2 die at tetrahedra and dimension 3 appears."""
     INF = np.iinfo(np.int64).max
     bars = []
     for r in np.nonzero(pairs.e_low >= 0)[0]:
@@ -349,10 +399,18 @@ def barcode(f: Filtration, pairs: Pairs):
         b, d = int(pairs.t_low[t]), int(tv[t])
         if b != d:
             bars.append((1, b, d))
-    a, b_, c = pairs.essential()
+    ess = pairs.essential()
+    a, b_, c = ess[0], ess[1], ess[2]
     bars += [(0, -1, INF)] * len(a)
     bars += [(1, int(r), INF) for r in b_]
     bars += [(2, int(tv[t]), INF) for t in c]
+    if pairs.q_low is not None:
+        qv = np.asarray(tets, np.int64)[:, 0] if pairs.T3 else np.zeros(0, np.int64)
+        for s in np.nonzero(pairs.q_low >= 0)[0]:
+            b, d = int(tv[pairs.q_low[s]]), int(qv[s])
+            if b != d:
+                bars.append((2, b, d))
+        bars += [(3, int(qv[s]), INF) for s in ess[3]]
     return sorted(bars)
 
 

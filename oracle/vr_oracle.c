@@ -22,6 +22,9 @@
  *   Section 2.2.2 (persistent cohomology; clear and compress): the same
  *     column algorithm run on the anti-transpose returns the same pivots;
  *     columns known to be zero may be skipped.
+ *   One dimension up (Section 3's bettimax = 2): tetrahedra once their six
+ *     edges exist, valued at their largest edge rank, and the pairs of
+ *     triangles with tetrahedra by both reductions.
  */
 #define _GNU_SOURCE
 #include <pthread.h>
@@ -599,6 +602,125 @@ void or_reduce_cohomology(int64_t n, int64_t K, const int64_t *ei, const int64_t
             if (piv[c] >= 0) t_low[T - 1 - piv[c]] = K - 1 - c;
         free(piv); free(skip); free(cr); free(cp); free(cnt); free(R);
     }
+}
+
+/* ================= dimension 2: triangles and tetrahedra ================= */
+
+/* A tetrahedron (value, a, b, c, d), a < b < c < d; rows of five int64. */
+typedef struct { int64_t v, a, b, c, d; } tet_t;
+
+static int cmp_tet(const tet_t *x, const tet_t *y) {
+    const int64_t p[5] = {x->v, x->a, x->b, x->c, x->d}, q[5] = {y->v, y->a, y->b, y->c, y->d};
+    for (int u = 0; u < 5; u++)
+        if (p[u] != q[u]) return p[u] < q[u] ? -1 : 1;
+    return 0;
+}
+
+/* index of a tetrahedron in the sorted list, or -1 */
+static int64_t tet_index(const tet_t *tets, int64_t T3, const tet_t *key) {
+    int64_t lo = 0, hi = T3;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        int c = cmp_tet(&tets[mid], key);
+        if (c == 0) return mid;
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+static int64_t *rank_matrix_of(int64_t n, int64_t K, const int64_t *ei, const int64_t *ej) {
+    int64_t *R = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n * n > 0 ? n * n : 1));
+    for (int64_t x = 0; x < n * n; x++) R[x] = -1;
+    for (int64_t r = 0; r < K; r++) { R[ei[r] * n + ej[r]] = r; R[ej[r] * n + ei[r]] = r; }
+    return R;
+}
+
+/* index of the triangle {x<y<z} (valued at its largest edge rank), or -1 */
+static int64_t facet_index(const tri_t *tris, int64_t T, const int64_t *R, int64_t n, int64_t x, int64_t y, int64_t z) {
+    int64_t v = max3(R[x * n + y], R[x * n + z], R[y * n + z]);
+    return tri_index(tris, T, v, x, y, z);
+}
+
+/*
+ * Persistence pairs of dimension 2 by Algorithm 1 on the boundary block of
+ * the tetrahedra (homology): columns are the tetrahedra in filtration order
+ * (value, then vertices), rows the indices of their four facets in the
+ * triangle list.  As for the lower blocks, column additions stay within the
+ * block, so its pivots are those of the whole boundary matrix.
+ * q_low[s] = the triangle paired with tetrahedron s (its low), or -1.
+ */
+void or_reduce_dim2_homology(int64_t n, int64_t K, const int64_t *ei, const int64_t *ej, int64_t T,
+                             const int64_t *tris4, int64_t T3, const int64_t *tets5, int64_t *q_low) {
+    const tri_t *tris = (const tri_t *)tris4;
+    const tet_t *tets = (const tet_t *)tets5;
+    int64_t *R = rank_matrix_of(n, K, ei, ej);
+    int64_t *cp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T3 + 1));
+    int64_t *cr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(4 * T3 + 1));
+    for (int64_t s = 0; s < T3; s++) {
+        const tet_t *q = &tets[s];
+        cp[s] = 4 * s;
+        cr[4 * s + 0] = facet_index(tris, T, R, n, q->a, q->b, q->c);
+        cr[4 * s + 1] = facet_index(tris, T, R, n, q->a, q->b, q->d);
+        cr[4 * s + 2] = facet_index(tris, T, R, n, q->a, q->c, q->d);
+        cr[4 * s + 3] = facet_index(tris, T, R, n, q->b, q->c, q->d);
+    }
+    cp[T3] = 4 * T3;
+    reduce_block(T3, cp, cr, T, NULL, q_low);
+    free(cp); free(cr); free(R);
+}
+
+/*
+ * The same pairs from the anti-transpose (persistent cohomology) with
+ * clearing (Section 2.2.2): columns are the triangles from last to first,
+ * rows the tetrahedra from last to first, so a column's low is its earliest
+ * cofacet.  A triangle paired with an edge (t_low[t] >= 0, the dimension-1
+ * pairs) has a coboundary that reduces to zero and is skipped.
+ * Output in the convention of or_reduce_dim2_homology.
+ */
+void or_reduce_dim2_cohomology(int64_t n, int64_t K, const int64_t *ei, const int64_t *ej, int64_t T,
+                               const int64_t *tris4, const int64_t *t_low, int64_t T3, const int64_t *tets5,
+                               int64_t *q_low) {
+    const tri_t *tris = (const tri_t *)tris4;
+    const tet_t *tets = (const tet_t *)tets5;
+    for (int64_t s = 0; s < T3; s++) q_low[s] = -1;
+    if (T == 0 || T3 == 0) return;
+    int64_t *R = rank_matrix_of(n, K, ei, ej);
+    /* cofacets of each triangle: the vertices l joined to all three */
+    int64_t *cp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T + 1));
+    cp[0] = 0;
+    for (int64_t c = 0; c < T; c++) {
+        const tri_t *t = &tris[T - 1 - c];
+        int64_t m = 0;
+        for (int64_t l = 0; l < n; l++)
+            if (l != t->i && l != t->j && l != t->k && R[t->i * n + l] >= 0 && R[t->j * n + l] >= 0 &&
+                R[t->k * n + l] >= 0)
+                m++;
+        cp[c + 1] = cp[c] + m;
+    }
+    int64_t *cr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cp[T] + 1));
+    unsigned char *skip = (unsigned char *)calloc((size_t)T, 1);
+    for (int64_t c = 0; c < T; c++) {
+        const int64_t ti = T - 1 - c;
+        const tri_t *t = &tris[ti];
+        if (t_low[ti] >= 0) skip[c] = 1;
+        int64_t o = cp[c];
+        for (int64_t l = 0; l < n; l++) {
+            if (l == t->i || l == t->j || l == t->k) continue;
+            const int64_t x = R[t->i * n + l], y = R[t->j * n + l], z = R[t->k * n + l];
+            if (x < 0 || y < 0 || z < 0) continue;
+            int64_t w = max3(x, y, z);
+            if (t->v > w) w = t->v;
+            int64_t u[4] = {t->i, t->j, t->k, l};
+            for (int p = 3; p > 0 && u[p] < u[p - 1]; p--) { int64_t h = u[p]; u[p] = u[p - 1]; u[p - 1] = h; }
+            const tet_t key = {w, u[0], u[1], u[2], u[3]};
+            cr[o++] = T3 - 1 - tet_index(tets, T3, &key);
+        }
+    }
+    int64_t *piv = (int64_t *)malloc(sizeof(int64_t) * (size_t)T);
+    reduce_block(T, cp, cr, T3, skip, piv);
+    for (int64_t c = 0; c < T; c++)
+        if (piv[c] >= 0) q_low[T3 - 1 - piv[c]] = T - 1 - c;
+    free(piv); free(skip); free(cr); free(cp); free(R);
 }
 
 /*

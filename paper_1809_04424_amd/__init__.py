@@ -58,6 +58,9 @@ class VrResult(ctypes.Structure):
         ("edge_ij", ctypes.c_void_p),
         ("edge_q", ctypes.c_void_p),
         ("tri_key", ctypes.c_void_p),
+        ("n_tetrahedra", ctypes.c_int64),
+        ("tet_off", ctypes.c_void_p),
+        ("tet_key", ctypes.c_void_p),
     ]
 
 
@@ -244,11 +247,19 @@ class _DeviceArray:
 class _Arrays:
     """Counts and device arrays of one cloud's filtration (a vr_result view)."""
 
-    def _init_arrays(self, r, device, block=None, block_ptr=0):
+    def _init_arrays(self, r, device, block=None, block_ptr=0, alloc=None):
         self._device = device
         self.n, self.K, self.T = int(r.n_vertices), int(r.n_edges), int(r.n_triangles)
         self._p_q, self._p_ij, self._p_tri = r.edge_q, r.edge_ij, r.tri_key
         self._block, self._block_ptr = block, block_ptr
+        # maxdim 3: the tetrahedra, in blocks of their own
+        self.T3 = int(r.n_tetrahedra)
+        self._p_toff, self._p_tkey = r.tet_off, r.tet_key
+        self._tet_blocks = {}
+        if alloc is not None:
+            for p in (r.tet_off, r.tet_key):
+                if p and p in alloc.live:
+                    self._tet_blocks[p] = alloc.live[p]
 
     @property
     def counts(self):
@@ -281,6 +292,26 @@ class _Arrays:
         import torch
 
         return self._tensor(self._p_tri, self.T, torch.int64, "<i8", 8, (self.T,))
+
+    def _tet_tensor(self, ptr, count, shape):
+        import torch
+
+        if not ptr or count == 0:
+            return torch.empty((0,) + tuple(shape[1:]), dtype=torch.int64, device=self._device)
+        blk = self._tet_blocks.get(ptr)
+        if blk is not None:  # torch-allocated block
+            return blk[: count * 8].view(torch.int64).view(shape)
+        return torch.as_tensor(_DeviceArray(self, ptr, shape, "<i8"), device=self._device)
+
+    def tet_off(self):
+        """int64 (K + 1,) of a maxdim-3 build: tet_off[r] = the first
+        tetrahedron of value r, tet_off[K] = T3 (empty otherwise)."""
+        return self._tet_tensor(self._p_toff, self.K + 1 if self._p_toff else 0, (self.K + 1,))
+
+    def tet_key(self):
+        """int64 (T3, 2) of a maxdim-3 build: rows (value, a<<39 | b<<26 |
+        c<<13 | d), a<b<c<d, in filtration order (empty otherwise)."""
+        return self._tet_tensor(self._p_tkey, 2 * self.T3, (self.T3, 2))
 
     def triangles(self):
         """int32 (T, 4) rows (i, j, k, v) in filtration order, unpacked on the device."""
@@ -316,7 +347,7 @@ class Result(_Arrays):
         self._stream = stream
         r = ptr.contents
         blk = alloc.live.get(r.edge_q) if (alloc is not None and r.edge_q) else None
-        self._init_arrays(r, device, blk, r.edge_q or 0)
+        self._init_arrays(r, device, blk, r.edge_q or 0, alloc)
 
     def stage_ms(self):
         """{stage: ms} of a build made with timing=True."""
@@ -470,6 +501,7 @@ def batch_limit(dtype: int, d: int) -> int:
 def build(points, thr=("full", 0, 1), maxdim: int = 2, count_only: bool = False, timing=False,
           allocator: str = "library", graph: bool = False) -> Result:
     """Build the Vietoris-Rips filtration (dim <= maxdim) of a device point cloud.
+    maxdim 3 also lists the tetrahedra (Result.tet_off, Result.tet_key).
 
     points:    torch tensor on a HIP device, (n, d) int8/int16/int32, rows are points.
     thr:       ("full", 0, 1) | ("count", K, 1) | ("fraction", num, den) | ("sqdist", tau, 0).

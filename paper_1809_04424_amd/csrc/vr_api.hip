@@ -88,6 +88,8 @@ EventPool &event_pool() {
 struct Owner {
     void *block = nullptr;
     size_t block_bytes = 0;
+    void *tet_block[2] = {nullptr, nullptr};  // maxdim 3: tetrahedron offsets, keys
+    size_t tet_bytes[2] = {0, 0};
     vr_allocator alloc{};
     bool has_alloc = false;
     bool timing = false;
@@ -99,6 +101,10 @@ struct Owner {
         Alloc A{has_alloc ? &alloc : nullptr, s};
         A.put(block, block_bytes);
         block = nullptr;
+        for (int i = 0; i < 2; i++) {
+            A.put(tet_block[i], tet_bytes[i]);
+            tet_block[i] = nullptr;
+        }
         for (int i = 0; i <= ST_N; i++) {
             if (ev[i]) event_pool().put(dev, ev[i]);
             ev[i] = nullptr;
@@ -323,7 +329,7 @@ int check_request(const vr_request *req, long long *E_out, long long *K_out) {
     if (req->n < 0 || req->d < 1) return VR_EINVAL;
     if (req->dtype != VR_I8 && req->dtype != VR_I16 && req->dtype != VR_I32 && req->dtype != VR_DIST) return VR_EINVAL;
     if (req->dtype == VR_DIST && req->d != (req->n > 0 ? req->n : 1)) return VR_EINVAL;  // an n x n matrix
-    if (req->maxdim < 0 || req->maxdim > 2) return VR_EINVAL;
+    if (req->maxdim < 0 || req->maxdim > 3) return VR_EINVAL;
     if (req->n > 0 && !req->points) return VR_EINVAL;
     if (req->n > VR_MAX_POINTS) return VR_E2BIG;
     const long long n = req->n;
@@ -1007,8 +1013,41 @@ void vr_free(vr_result *res_, void *stream) {
     delete res;
 }
 
+// maxdim 3: the tetrahedra of a finished build, into blocks the result owns.
+static int add_tetrahedra(Result *res, const vr_request *req, hipStream_t s) {
+    const int64_t K = res->n_edges;
+    Owner &own = res->own;
+    Alloc A{own.has_alloc ? &own.alloc : nullptr, s};
+    own.tet_bytes[0] = 8 * (size_t)(K + 1);
+    own.tet_block[0] = A.get(own.tet_bytes[0]);
+    if (!own.tet_block[0]) return VR_ENOMEM;
+    int64_t *off = (int64_t *)own.tet_block[0];
+    int64_t T3 = 0;
+    if (K == 0) {
+        if (hipMemsetAsync(off, 0, 8, s) != hipSuccess) return VR_EHIP;
+    } else {
+        int st = vr_tetra_offsets(res, off, s);
+        if (st != VR_OK) return st;
+        if (hipMemcpyAsync(&T3, off + K, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return VR_EHIP;
+    }
+    res->n_tetrahedra = T3;
+    res->tet_off = off;
+    if (T3 > 0 && !(req->flags & VR_COUNT_ONLY)) {
+        own.tet_bytes[1] = 16 * (size_t)T3;
+        own.tet_block[1] = A.get(own.tet_bytes[1]);
+        if (!own.tet_block[1]) return VR_ENOMEM;
+        const int st = vr_tetra_write(res, off, T3, (uint64_t *)own.tet_block[1], s);
+        if (st != VR_OK) return st;
+        res->tet_key = (const uint64_t *)own.tet_block[1];
+    }
+    return VR_OK;
+}
+
 int vr_build(const vr_request *req, void *stream, vr_result **out) {
     if (!out || !req) return VR_EINVAL;
+    if (req->maxdim == 3 && (req->flags & VR_GRAPH)) return VR_EINVAL;
     Result *res = new (std::nothrow) Result();
     if (!res) return VR_ENOMEM;
     std::vector<vr_result> views;
@@ -1018,6 +1057,14 @@ int vr_build(const vr_request *req, void *stream, vr_result **out) {
         return st;
     }
     static_cast<vr_result &>(*res) = views[0];
+    if (req->maxdim == 3) {
+        const int st3 = add_tetrahedra(res, req, (hipStream_t)stream);
+        if (st3 != VR_OK) {
+            res->own.release((hipStream_t)stream);
+            delete res;
+            return st3;
+        }
+    }
     *out = res;
     return VR_OK;
 }
@@ -1065,6 +1112,8 @@ int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t sched[6
 
 int vr_build_batch(const vr_request *reqs, int64_t count, void *stream, vr_batch **out) {
     if (!out || !reqs || count < 1) return VR_EINVAL;
+    for (int64_t i = 0; i < count; i++)
+        if (reqs[i].maxdim == 3) return VR_EINVAL;
     vr_batch *b = new (std::nothrow) vr_batch();
     if (!b) return VR_ENOMEM;
     const int st = build_impl(reqs, count, (hipStream_t)stream, b->own, b->views);

@@ -36,17 +36,22 @@ def filtration(points, K_of):
     return kept, rank, tris, q
 
 
-def total_order(n, kept, tris):
+def total_order(n, kept, tris, tets=()):
     """Simplices in filtration order (value, dim, lex): vertices (value -1),
-    then for each rank r the edge r followed by the triangles of value r."""
-    by_value = {}
-    for t in tris:
+    then for each rank r the edge r followed by the triangles of value r and
+    the tetrahedra of value r (rows (value, a, b, c, d))."""
+    by_value, tet_by_value = {}, {}
+    for t in sorted(tris):
         by_value.setdefault(t[0], []).append(t)
+    for q in sorted(tuple(x) for x in tets):
+        tet_by_value.setdefault(q[0], []).append(q)
     order = [("v", (i,)) for i in range(n)]
     for r, e in enumerate(kept):
         order.append(("e", e))
         for t in by_value.get(r, []):
             order.append(("t", t[1:]))
+        for q in tet_by_value.get(r, []):
+            order.append(("q", q[1:]))
     return order
 
 
@@ -65,7 +70,7 @@ def _f2_rank(vectors):
     return rank
 
 
-def persistent_betti(n, kept, tris):
+def persistent_betti(n, kept, tris, tets=()):
     """beta[k][(s, t)] for all s <= t indices into the total order: the rank of
     H_k(X_s) -> H_k(X_t), from F2 ranks of boundary matrices.
 
@@ -73,10 +78,11 @@ def persistent_betti(n, kept, tris):
     dim(B_k(X_t) cap C_k(X_s)) = rank d_{k+1}(X_t) - rank(P d_{k+1}(X_t)),
     with P the projection onto the k-simplices of X_t that are not in X_s.
     """
-    order = total_order(n, kept, tris)
+    order = total_order(n, kept, tris, tets)
     N = len(order)
     pos = {s: p for p, s in enumerate(order)}
-    dim = [{"v": 0, "e": 1, "t": 2}[s[0]] for s in order]
+    dim = [{"v": 0, "e": 1, "t": 2, "q": 3}[s[0]] for s in order]
+    top = max(dim) if dim else 0
 
     def boundary(p):
         kind, verts = order[p]
@@ -84,13 +90,19 @@ def persistent_betti(n, kept, tris):
             return 0
         if kind == "e":
             return (1 << pos[("v", (verts[0],))]) | (1 << pos[("v", (verts[1],))])
-        i, j, k = verts
-        return (1 << pos[("e", (i, j))]) | (1 << pos[("e", (i, k))]) | (1 << pos[("e", (j, k))])
+        if kind == "t":
+            i, j, k = verts
+            return (1 << pos[("e", (i, j))]) | (1 << pos[("e", (i, k))]) | (1 << pos[("e", (j, k))])
+        out = 0
+        for f in itertools.combinations(verts, 3):
+            out |= 1 << pos[("t", f)]
+        return out
 
     bnd = [boundary(p) for p in range(N)]
-    beta = {0: {}, 1: {}, 2: {}}
+    dims = tuple(range(max(3, top + 1)))
+    beta = {k: {} for k in dims}
     for s in range(N):
-        for k in (0, 1, 2):
+        for k in dims:
             nk = sum(1 for p in range(s + 1) if dim[p] == k)
             rk = _f2_rank([bnd[p] for p in range(s + 1) if dim[p] == k])
             zk = nk - rk
@@ -109,11 +121,11 @@ def persistent_betti(n, kept, tris):
     return order, beta
 
 
-def betti_from_pairs(N, pairs_by_dim, essential_by_dim):
+def betti_from_pairs(N, pairs_by_dim, essential_by_dim, dims=(0, 1, 2)):
     """Same quantity from a pairing: bars (b, d) in total-order indices with
     b <= s and d > t, plus essential births b <= s."""
-    beta = {0: {}, 1: {}, 2: {}}
-    for k in (0, 1, 2):
+    beta = {k: {} for k in dims}
+    for k in dims:
         for s in range(N):
             for t in range(s, N):
                 c = sum(1 for b, d in pairs_by_dim.get(k, []) if b <= s and d > t)

@@ -648,3 +648,125 @@ def test_triangles_by_value_ranges_concatenate(orc):
     assert all((p[:, 0] >= lo).all() and (p[:, 0] < hi).all() for p, lo, hi in zip(parts, (0, a, b), (a, b, f.K)))
     with pytest.raises(ValueError):
         orc.triangles_by_value(f, 0, f.K + 1)
+
+
+# --- pairs of dimension 2 (triangles with tetrahedra) ------------------------
+
+def _pairs3_in_total_order(f, p, tets):
+    """(birth, death) pairs of dimensions 0..2 and essential births of
+    dimensions 0..3 as total-order indices, tetrahedra included."""
+    order = bf.total_order(f.n, list(zip(f.ei.tolist(), f.ej.tolist())), [tuple(t) for t in f.tris.tolist()],
+                           [tuple(q) for q in tets.tolist()])
+    pos = {s: i for i, s in enumerate(order)}
+    vid = lambda v: pos[("v", (v,))]
+    eid = lambda r: pos[("e", (int(f.ei[r]), int(f.ej[r])))]
+    tid = lambda t: pos[("t", tuple(int(x) for x in f.tris[t, 1:]))]
+    qid = lambda s: pos[("q", tuple(int(x) for x in tets[s, 1:]))]
+    pairs = {0: [], 1: [], 2: []}
+    for r in np.nonzero(p.e_low >= 0)[0]:
+        pairs[0].append((vid(int(p.e_low[r])), eid(r)))
+    for t in np.nonzero(p.t_low >= 0)[0]:
+        pairs[1].append((eid(int(p.t_low[t])), tid(t)))
+    for s in np.nonzero(p.q_low >= 0)[0]:
+        pairs[2].append((tid(int(p.q_low[s])), qid(s)))
+    e0, e1, e2, e3 = p.essential()
+    ess = {0: [vid(v) for v in e0], 1: [eid(r) for r in e1], 2: [tid(t) for t in e2], 3: [qid(s) for s in e3]}
+    return len(order), pairs, ess
+
+
+DIM2_TINY = [
+    workloads.uniform_cloud(121, 6, 3, thr=("full", 0, 1)),
+    workloads.uniform_cloud(122, 7, 3, thr=("fraction", 75, 100)),
+    workloads.lattice_cloud(123, 7, side=3, thr=("fraction", 65, 100)),
+    workloads.uniform_cloud(124, 7, 2, thr=("count", 16, 1)),
+]
+
+
+@pytest.mark.parametrize("case", DIM2_TINY, ids=lambda c: c.name)
+@pytest.mark.parametrize("method", ["homology", "cohomology"])
+def test_dim2_pairs_match_bruteforce_persistent_betti(orc, case, method):
+    """With the tetrahedra, the pairs of every dimension reproduce every
+    persistent Betti number rank(H_k(X_s) -> H_k(X_t)), k = 0..3, brute
+    force from F2 ranks of the boundary matrices."""
+    f = orc.build(case.points, case.thr)
+    tets = orc.tetra_list(f)
+    assert len(tets) > 0
+    p = orc.with_dim2(f, orc.reduce(f, method), tets, method)
+    N, pairs, ess = _pairs3_in_total_order(f, p, tets)
+    _, beta = bf.persistent_betti(f.n, list(zip(f.ei.tolist(), f.ej.tolist())), [tuple(t) for t in f.tris.tolist()],
+                                  [tuple(q) for q in tets.tolist()])
+    got = bf.betti_from_pairs(N, pairs, ess, dims=(0, 1, 2, 3))
+    for k in (0, 1, 2, 3):
+        assert got[k] == beta[k], f"dimension {k}"
+
+
+@pytest.mark.parametrize("seed,n,thr", [(131, 30, ("fraction", 30, 100)), (132, 24, ("full", 0, 1)),
+                                        (133, 40, ("fraction", 15, 100)), (134, 36, ("sqdist", 2500, 0))])
+def test_dim2_homology_and_cohomology_give_same_pairs(orc, seed, n, thr):
+    """Section 2.2.2 one dimension up: the tetrahedra's boundary block and
+    the triangles' coboundaries with clearing pair the same simplices."""
+    c = workloads.uniform_cloud(seed, n, 3, thr=thr)
+    f = orc.build(c.points, c.thr)
+    tets = orc.tetra_list(f)
+    h = orc.reduce_dim2(f, tets, "homology")
+    co = orc.reduce_dim2(f, tets, "cohomology", orc.reduce(f, "cohomology").t_low)
+    assert np.array_equal(h, co)
+    # a triangle pairs at most once, never with an older tetrahedron (its
+    # column's low is a row above the column), and a triangle paired with an
+    # edge is never paired with a tetrahedron
+    paired = h[h >= 0]
+    assert len(set(paired.tolist())) == len(paired)
+    assert all(f.tris[h[s], 0] <= tets[s, 0] for s in np.nonzero(h >= 0)[0])
+    t_low = orc.reduce(f, "homology").t_low
+    assert not np.any(t_low[paired] >= 0)
+
+
+@pytest.mark.parametrize("seed,thr", [(141, ("fraction", 12, 100)), (142, ("fraction", 35, 100)),
+                                      (143, ("sqdist", 900, 0))])
+def test_euler_characteristic_dim3(orc, seed, thr):
+    """n - K + T - T3 = beta0 - beta1 + beta2 - beta3 of the 3-skeleton."""
+    c = workloads.uniform_cloud(seed, 45, 2, thr=thr)
+    f = orc.build(c.points, c.thr)
+    tets = orc.tetra_list(f)
+    b = orc.with_dim2(f, orc.reduce(f, "cohomology"), tets).betti()
+    assert f.n - f.K + f.T - len(tets) == b[0] - b[1] + b[2] - b[3]
+
+
+@pytest.mark.parametrize("n", [5, 9, 14])
+def test_full_simplex_dim3_betti(orc, n):
+    """The 3-skeleton of a full simplex on n vertices: beta = (1, 0, 0,
+    C(n-1, 4)) (it is 2-connected; its cycles of dimension 3 are the
+    boundaries of the C(n-1, 4) 4-simplices through one vertex)."""
+    c = workloads.uniform_cloud(150 + n, n, 3)
+    f = orc.build(c.points, ("full", 0, 1))
+    tets = orc.tetra_list(f)
+    assert len(tets) == math.comb(n, 4)
+    assert orc.with_dim2(f, orc.reduce(f, "cohomology"), tets).betti() == (1, 0, 0, math.comb(n - 1, 4))
+
+
+@pytest.mark.parametrize("case", DIM2_TINY[1:], ids=lambda c: c.name)
+def test_dim2_barcode_reproduces_persistent_betti_by_value(orc, case):
+    """The barcode with the tetrahedra, in filtration values: for every pair
+    of values s <= t the bars of dimension k (k = 0..3) with birth <= s and
+    death > t number rank(H_k(X_s) -> H_k(X_t)), X_s the simplices of value
+    <= s; no bar is born after it dies."""
+    f = orc.build(case.points, case.thr)
+    tets = orc.tetra_list(f)
+    bars = orc.barcode(f, orc.with_dim2(f, orc.reduce(f, "cohomology"), tets), tets)
+    assert all(b < d for _, b, d in bars)
+    kept = list(zip(f.ei.tolist(), f.ej.tolist()))
+    tris = [tuple(t) for t in f.tris.tolist()]
+    order, beta = bf.persistent_betti(f.n, kept, tris, [tuple(q) for q in tets.tolist()])
+    value_of = {("e", e): r for r, e in enumerate(kept)}
+    value_of.update({("t", tuple(t[1:])): t[0] for t in tris})
+    value_of.update({("q", tuple(q[1:])): q[0] for q in tets.tolist()})
+    last = {-1: f.n - 1}
+    for p_, (kind, verts) in enumerate(order):
+        if kind != "v":
+            last[value_of[(kind, verts)]] = p_
+    for k in (0, 1, 2, 3):
+        for s in sorted(last):
+            for t in sorted(last):
+                if t >= s:
+                    alive = sum(1 for dim, b, d in bars if dim == k and b <= s and d > t)
+                    assert alive == beta[k][(last[s], last[t])], (k, s, t)
