@@ -631,6 +631,40 @@ def _pairs_dim1(vr, torch, reps=5, workload="circle1000"):
             "positive_bars_dim1": int(((b[:, 0] == 1) & (b[:, 2] != inf)).sum()), "betti": betti}
 
 
+def _dim3(vr, torch, reps=3, workload="circle1000"):
+    """Dimension 3 (Section 3's bettimax = 2): a maxdim-3 build (the
+    triangles, then the tetrahedra counted, scanned, read back and listed)
+    and the pairs of dimension 2 (triangles with tetrahedra: apparent pairs
+    one wave per triangle, the rest reduced as in dimension 1).  Wall times,
+    median of reps; the pairs of dimensions 0 and 1 come first (clearing)."""
+    c = _workload(workload)
+    pts = torch.from_numpy(c.points).to("cuda:0")
+    tb, tp = [], []
+    for i in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = vr.build(pts, c.thr, maxdim=3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e_low, _ = vr.pairs_dim0(r)
+        toe = vr.pairs_dim1(r, e_low)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tt = vr.pairs_dim2(r, toe)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if i:
+            tb.append(t1 - t0)
+            tp.append(t3 - t2)
+        n, K, T = r.counts
+        T3 = r.T3
+        paired = int((tt >= 0).sum().item())
+        r.free()
+    mb, mp = sorted(tb)[len(tb) // 2], sorted(tp)[len(tp) // 2]
+    return {"build_ms": round(1e3 * mb, 3), "n": n, "K": K, "T": T, "T3": T3,
+            "simplices_per_s": (n + K + T + T3) / mb, "pairs_dim2_ms": round(1e3 * mp, 3), "pairs_dim2": paired}
+
+
 def _enum_bytes(n, K, T, n2):
     """Algorithmic bytes of the triangle enumeration: triangle keys out (8 T),
     kept ranks in (8 K), the adjacency once (n^2/8 over the clouds)."""
@@ -654,7 +688,7 @@ def main():
                     help="mixture4000 (the benchmark line, with side measurements), circle1000, plain64, "
                          "batched512 (one batched build of 512 clouds), or one side measurement alone: "
                          "hamming1088 (matrix input), colorder2000 (column order), pairs0 (dimension-0 pairs and dimension-1 apparent pairs), "
-                         "pairs1 (dimension-1 reduction and barcode), "
+                         "pairs1 (dimension-1 reduction and barcode; dimension 3 and its pairs), "
                          "schur16384 (F2 product and sum)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and the parity gate")
     ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
@@ -702,7 +736,8 @@ def main():
     if args.workload == "pairs1":  # the dimension-1 reduction and barcode alone (profiling)
         print(json.dumps({"workload": "pairs_dim1_barcode",
                           "circle1000": _pairs_dim1(vr, torch, reps=args.steps),
-                          "mixture4000": _pairs_dim1(vr, torch, reps=args.steps, workload="mixture4000")}), flush=True)
+                          "mixture4000": _pairs_dim1(vr, torch, reps=args.steps, workload="mixture4000"),
+                          "dim3_circle1000": _dim3(vr, torch, reps=args.steps)}), flush=True)
         return
     if args.workload == "schur16384":  # the F2 product and sum alone (profiling)
         print(json.dumps({"workload": "schur_f2_16384", **_schur(vr, torch, reps=args.steps)}), flush=True)
@@ -766,6 +801,7 @@ def main():
         extra["pairs_dim0_mixture4000"] = _pairs_dim0(vr, torch, workload="mixture4000")
         extra["pairs_dim1_barcode_circle1000"] = _pairs_dim1(vr, torch)
         extra["pairs_dim1_barcode_mixture4000"] = _pairs_dim1(vr, torch, reps=3, workload="mixture4000")
+        extra["dim3_circle1000"] = _dim3(vr, torch)
         extra["pairs_dim1_apparent_circle1000"] = _apparent(vr, torch)
         extra["tetra_counts_circle1000"] = _tetra(vr, torch)
         extra["schur_f2_16384"] = _schur(vr, torch)

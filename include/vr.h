@@ -420,6 +420,31 @@ VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, void *stream);
 VR_API int vr_tetra_offsets(const vr_result *res, int64_t *offsets, void *stream);
 VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t total, uint64_t *keys, void *stream);
 
+/* Persistence pairs of dimension 2: triangles with tetrahedra (Section
+ * 2.2.1, Alg. 1, run as in Section 2.2.2 on the anti-transpose with
+ * clearing, one dimension above vr_pairs_dim1; Section 3's bettimax = 2).
+ * The triangle columns go from the youngest triangle to the oldest, and a
+ * column's pivot is its oldest cofacet.  Triangles paired with an edge are
+ * cleared; a triangle whose oldest cofacet has it as its youngest facet
+ * pairs with it at once (an apparent pair: one wave per triangle finds its
+ * oldest cofacet); the other columns first take, all at once, the
+ * coboundaries of the apparent pairs their pivots meet, then are reduced,
+ * youngest first, by one work-group.  The pairs equal those of the column
+ * algorithm on the tetrahedra's boundary block.
+ * res:          a maxdim-3 build's result with its triangle and tetrahedron
+ *               keys (not count-only).
+ * tri_of_edge:  device, K int32: vr_pairs_dim1's output for this result.
+ * tri_tet:      device, T int64, caller-owned output: the index (in
+ *               tet_key's order) of the tetrahedron paired with triangle t,
+ *               or -1: t is paired with an edge, or else starts a class of
+ *               dimension 2 that never dies.
+ * Synchronises `stream`.  Scratch from the library's cache: 4 n^2 + 40 T +
+ * 16 H bytes (H = 2T rounded up to a power of two) plus 608 MiB, as
+ * vr_pairs_dim1.  VR_ENOMEM when the columns outgrow it; VR_EINVAL for a
+ * null argument, a result without tetrahedron keys, n > VR_MAX_POINTS or
+ * T >= 2^31.  With no triangles nothing is written. */
+VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_edge, int64_t *tri_tet, void *stream);
+
 /* The F2 sparse product and sum of the Schur complement step (Section 4.6):
  * S = D + C E mod 2, where C is m x k, E is k x n and D is m x n, all in
  * compressed sparse columns on the device: colptr (ncols + 1 int64, from 0,

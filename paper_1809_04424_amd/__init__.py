@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_pairs_dim1", "vr_barcode", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_blockprodsum_count", "vr_blockprodsum_write",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_pairs_dim1", "vr_barcode", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_pairs_dim2", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -126,6 +126,8 @@ def lib():
         L.vr_pairs_dim1_apparent.restype = ctypes.c_int
         L.vr_pairs_dim1.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.vr_pairs_dim1.restype = ctypes.c_int
+        L.vr_pairs_dim2.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vr_pairs_dim2.restype = ctypes.c_int
         L.vr_barcode.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.vr_barcode.restype = ctypes.c_int
@@ -292,6 +294,11 @@ class _Arrays:
         import torch
 
         return self._tensor(self._p_tri, self.T, torch.int64, "<i8", 8, (self.T,))
+
+    def _c_result(self):
+        """This view as a vr_result (for calls that take one)."""
+        return VrResult(self.n, self.K, self.T, self._p_ij, self._p_q, self._p_tri, self.T3, self._p_toff,
+                        self._p_tkey)
 
     def _tet_tensor(self, ptr, count, shape):
         import torch
@@ -740,6 +747,26 @@ def barcode(result, e_low, tri_of_edge):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return bars[: counts[0] + counts[1]], int(counts[2])
+
+
+def pairs_dim2(result, tri_of_edge):
+    """Persistence pairs of dimension 2 of a maxdim-3 build (Section 2.2.1,
+    Alg. 1 on the anti-transpose with clearing, Section 2.2.2): an int64
+    device tensor of T entries, the index in tet_key of the tetrahedron
+    paired with triangle t, or -1.  tri_of_edge: pairs_dim1's output."""
+    import torch
+
+    L = lib()
+    dev = result._device
+    out = torch.empty(max(result.T, 1), dtype=torch.int64, device=dev)
+    r = result._c_result()
+    stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = L.vr_pairs_dim2(ctypes.byref(r), ctypes.c_void_p(tri_of_edge.data_ptr() if result.K else 0),
+                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return out[: result.T]
 
 
 def tetra_counts(result):

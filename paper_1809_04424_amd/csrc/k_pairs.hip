@@ -676,7 +676,13 @@ struct RdBufs {
     int32_t *pst;                   // per column: what the first pass left (RD_ST_*)
     RdCtl *ctl;
     int64_t n, K;
+    const unsigned long long *tri;  // dimension 2: the T triangle keys (the columns' simplices)
+    int64_t T;
 };
+
+// A table slot of dimension 2 whose length is RD_APP holds an apparent pair:
+// its start is the triangle whose coboundary has that pivot.
+#define RD_APP 0xFFFFFFFFu
 
 // Columns to reduce: edges with neither a vertex (e_low) nor an apparent
 // triangle (first), from the youngest down.  One work-group.
@@ -760,12 +766,11 @@ static __device__ __forceinline__ void rd_wave_sync() {
 
 #define RD_SEG (VR_MAX_POINTS / RD_BLOCK)  // vertices per thread in rd_gen
 
+static __device__ uint32_t rd_sort(unsigned long long *g, uint32_t run);
+
 // The coboundary of edge e, sorted, into g (LDS); returns its length.  Each
 // thread takes a run of at most RD_SEG consecutive vertices k (its loads
-// all in flight at once), one scan places the keys.  Bitonic sort: in a
-// stage of partner distance j <= 64 every wave reads and writes only its
-// own 128-element blocks, so consecutive such stages need only the wave's
-// own ordering.
+// all in flight at once), one scan places the keys, rd_sort sorts them.
 static __device__ uint32_t rd_gen_ab(const RdBufs &B, int64_t e, int32_t a, int32_t b, unsigned long long *g,
                                      uint32_t *sh) {
     const int t = threadIdx.x;
@@ -791,6 +796,15 @@ static __device__ uint32_t rd_gen_ab(const RdBufs &B, int64_t e, int32_t a, int3
 #pragma unroll
     for (int u = 0; u < RD_SEG; u++)
         if (val[u] >= 0) g[at++] = rd_tri_key((uint32_t)val[u], (uint32_t)a, (uint32_t)b, (uint32_t)(k0 + u));
+    return rd_sort(g, run);
+}
+
+// Sort the first run keys of g (LDS) in place; returns run.  Bitonic: in a
+// stage of partner distance j <= 64 every wave reads and writes only its
+// own 128-element blocks, so consecutive such stages need only the wave's
+// own ordering.
+static __device__ uint32_t rd_sort(unsigned long long *g, uint32_t run) {
+    const int t = threadIdx.x;
     // padded to a power of two with the largest key
     uint32_t P = 1;
     while (P < run) P <<= 1;
@@ -815,6 +829,63 @@ static __device__ uint32_t rd_gen_ab(const RdBufs &B, int64_t e, int32_t a, int3
 
 static __device__ uint32_t rd_gen(const RdBufs &B, int64_t e, unsigned long long *g, uint32_t *sh) {
     return rd_gen_ab(B, e, B.ij[2 * e], B.ij[2 * e + 1], g, sh);
+}
+
+// Dimension 2.  A tetrahedron as a key of the reduction: w << 26 | c << 13
+// | d, w its value (largest edge rank) and c < d its two vertices off edge
+// w.  The tetrahedra of one value share that edge, and two 4-sets with two
+// common vertices compare (sorted, lexicographically) as their other two
+// vertices do, so these keys sort in filtration order.
+static __device__ __forceinline__ unsigned long long rd_tet_key(int32_t w, uint32_t c, uint32_t d) {
+    return ((unsigned long long)(uint32_t)w << 26) | ((unsigned long long)c << 13) | d;
+}
+
+// The cofacet t + {l} of triangle t = {i, j, k} (value v, m its vertex off
+// its largest edge), given the ranks x, y, z of the edges il, jl, kl.
+static __device__ __forceinline__ unsigned long long rd_cofacet(int32_t v, uint32_t i, uint32_t j, uint32_t k,
+                                                                uint32_t m, uint32_t l, int32_t x, int32_t y,
+                                                                int32_t z) {
+    const int32_t w = max(v, max(x, max(y, z)));
+    if (w == v) return rd_tet_key(w, min(m, l), max(m, l));  // the triangle's own largest edge
+    if (w == x) return rd_tet_key(w, j, k);                  // edge il
+    if (w == y) return rd_tet_key(w, i, k);                  // edge jl
+    return rd_tet_key(w, i, j);                              // edge kl
+}
+
+// The coboundary of triangle tix (its cofacets t + {l}), sorted, into g.
+static __device__ uint32_t rd_gen_tri(const RdBufs &B, int64_t tix, unsigned long long *g, uint32_t *sh) {
+    const int t = threadIdx.x;
+    const unsigned long long key = B.tri[tix];
+    const int32_t v = (int32_t)(key >> 39);
+    const uint32_t i = (uint32_t)(key >> 26) & 0x1FFFu, j = (uint32_t)(key >> 13) & 0x1FFFu, k = (uint32_t)key & 0x1FFFu;
+    const int32_t *Ri = B.R + (int64_t)i * B.n, *Rj = B.R + (int64_t)j * B.n, *Rk = B.R + (int64_t)k * B.n;
+    const uint32_t m = Ri[j] == v ? k : (Ri[k] == v ? j : i);
+    const int S = (int)((B.n + RD_BLOCK - 1) / RD_BLOCK);
+    const int l0 = t * S;
+    unsigned long long kv[RD_SEG];
+    bool ok[RD_SEG];
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < RD_SEG; u++) {
+        const int l = l0 + u;
+        ok[u] = false;
+        kv[u] = 0;
+        if (u < S && l < B.n) {
+            const int32_t x = Ri[l], y = Rj[l], z = Rk[l];
+            if ((uint32_t)l != i && (uint32_t)l != j && (uint32_t)l != k && x != PD_INF && y != PD_INF &&
+                z != PD_INF) {
+                kv[u] = rd_cofacet(v, i, j, k, m, (uint32_t)l, x, y, z);
+                ok[u] = true;
+                c++;
+            }
+        }
+    }
+    uint32_t run;
+    uint32_t at = rd_scan(c, sh, &run);
+#pragma unroll
+    for (int u = 0; u < RD_SEG; u++)
+        if (ok[u]) g[at++] = kv[u];
+    return rd_sort(g, run);
 }
 
 // dst = a + b over F2 (a, b sorted, without repeats); returns dst's length,
@@ -997,6 +1068,33 @@ static __device__ uint32_t rd_delta_add(const unsigned long long *d, uint32_t nd
     return tot;
 }
 
+// The coboundary of column simplex id: an edge (DIM 1) or a triangle (DIM 2).
+template <int DIM>
+static __device__ __forceinline__ uint32_t rd_gen_col(const RdBufs &B, int64_t id, unsigned long long *g,
+                                                      uint32_t *sh) {
+    if constexpr (DIM == 1) return rd_gen(B, id, g, sh);
+    else return rd_gen_tri(B, id, g, sh);
+}
+
+// Dimension 2: the apparent partner of pivot p, from 64 table slots read at
+// once by the calling wave (every lane gets it); -1 when p is no apparent
+// pivot.
+static __device__ __forceinline__ int32_t rd_app2(const RdBufs &B, unsigned long long p) {
+    const int lane = threadIdx.x & 63;
+    long long sl = rd_slot(p, B.hmask);
+    for (;;) {
+        const RdSlot q = B.tab[(sl + lane) & B.hmask];
+        const unsigned long long stop = __ballot(q.key == p || q.key == RD_EMPTY);
+        if (!stop) {
+            sl += 64;
+            continue;
+        }
+        const int f = __builtin_ctzll(stop);
+        const bool hit = __shfl(q.key, f, 64) == p && __shfl(q.len, f, 64) == RD_APP;
+        return hit ? (int32_t)__shfl(q.start, f, 64) : -1;
+    }
+}
+
 // First pass, one work-group per column at a time, columns in any order:
 // adding the coboundary of an apparent pair's edge depends on no other
 // column, so every column can take these additions at once, up to its
@@ -1004,6 +1102,7 @@ static __device__ uint32_t rd_delta_add(const unsigned long long *d, uint32_t nd
 // same working column it would have built itself.  A column kept whole in
 // LDS (at most RD_DCAP keys) is stored in the pool with its pivot; one
 // that outgrows LDS is left for the serial pass to reduce from the start.
+template <int DIM>
 __global__ void __launch_bounds__(RD_BLOCK) k_rd_pre(RdBufs B) {
     __shared__ unsigned long long g[RD_GEN_MAX];
     __shared__ unsigned long long dl[2][RD_DCAP];
@@ -1018,30 +1117,37 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_pre(RdBufs B) {
         const int32_t ci = s_ci;
         __syncthreads();
         if (ci >= m) break;
-        uint32_t nd = rd_gen(B, B.rem[ci], g, sh);
+        uint32_t nd = rd_gen_col<DIM>(B, B.rem[ci], g, sh);
         int dc = 0;
         int32_t st = RD_ST_REDO;
         if (nd <= RD_DCAP) {
             for (uint32_t x = t; x < nd; x += RD_BLOCK) dl[0][x] = g[x];
             __syncthreads();
             for (;;) {
-                if (t == 0) {
-                    // -1: the pivot is not apparent (or the column is empty)
-                    int32_t arg = -1;
-                    if (nd > 0) {
-                        const unsigned long long p = dl[dc][0];
-                        const int64_t v = (int64_t)(p >> 39);
-                        if (v < B.K) {
-                            const unsigned long long ap = B.app[v];
-                            const int32_t ea = B.ij[2 * v], eb = B.ij[2 * v + 1];
-                            if (ap == p) {
-                                arg = (int32_t)v;
-                                s_a = ea;
-                                s_b = eb;
+                if constexpr (DIM == 1) {
+                    if (t == 0) {
+                        // -1: the pivot is not apparent (or the column is empty)
+                        int32_t arg = -1;
+                        if (nd > 0) {
+                            const unsigned long long p = dl[dc][0];
+                            const int64_t v = (int64_t)(p >> 39);
+                            if (v < B.K) {
+                                const unsigned long long ap = B.app[v];
+                                const int32_t ea = B.ij[2 * v], eb = B.ij[2 * v + 1];
+                                if (ap == p) {
+                                    arg = (int32_t)v;
+                                    s_a = ea;
+                                    s_b = eb;
+                                }
                             }
                         }
+                        s_arg = arg;
                     }
-                    s_arg = arg;
+                } else {
+                    if (t < 64) {
+                        const int32_t arg = nd > 0 ? rd_app2(B, dl[dc][0]) : -1;
+                        if (t == 0) s_arg = arg;
+                    }
                 }
                 __syncthreads();
                 const int32_t arg = s_arg;
@@ -1049,7 +1155,9 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_pre(RdBufs B) {
                     st = nd ? RD_ST_PIVOT : RD_ST_EMPTY;
                     break;
                 }
-                const uint32_t nx = rd_gen_ab(B, arg, s_a, s_b, g, sh);  // its barriers end every read of s_*
+                uint32_t nx;  // the generator's barriers end every read of s_*
+                if constexpr (DIM == 1) nx = rd_gen_ab(B, arg, s_a, s_b, g, sh);
+                else nx = rd_gen_tri(B, arg, g, sh);
                 if (nd + nx > RD_DCAP) break;
                 nd = rd_delta_add(dl[dc], nd, g, nx, dl[dc ^ 1], sh);
                 dc ^= 1;
@@ -1086,6 +1194,7 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_pre(RdBufs B) {
 // column to reduce from the start.  Thread 0 looks up each pivot (its
 // apparent key and its table slot, two independent loads) and the work-
 // group makes the addition; a stored column is staged in LDS first.
+template <int DIM>
 __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
     __shared__ unsigned long long g[RD_GEN_MAX];
     __shared__ unsigned long long dl[2][RD_DCAP];
@@ -1157,7 +1266,7 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
             wn = 0;
         } else {
             // delta: the coboundary (or the base, when it is longer)
-            const uint32_t len = rd_gen(B, B.rem[ci], g, sh);
+            const uint32_t len = rd_gen_col<DIM>(B, B.rem[ci], g, sh);
             if (len <= RD_DCAP) {
                 for (uint32_t x = t; x < len; x += RD_BLOCK) dl[dc][x] = g[x];
                 nd = len;
@@ -1201,7 +1310,7 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                     const int64_t v = (int64_t)(p >> 39);
                     unsigned long long ap = RD_EMPTY;
                     int32_t ea = 0, eb = 0;
-                    if (lane == 0 && v < B.K) {
+                    if (DIM == 1 && lane == 0 && v < B.K) {
                         ap = B.app[v];
                         ea = B.ij[2 * v];
                         eb = B.ij[2 * v + 1];
@@ -1220,10 +1329,11 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                             act = 2;
                             a0 = __shfl(q.start, f, 64);
                             a1 = __shfl(q.len, f, 64);
+                            if (DIM == 2 && a1 == RD_APP) act = 1;  // an apparent pair's triangle a0
                         }
                         break;
                     }
-                    if (__shfl(ap, 0, 64) == p) {
+                    if (DIM == 1 && __shfl(ap, 0, 64) == p) {
                         act = 1;
                         a0 = (uint32_t)v;
                         a1 = (uint32_t)__shfl(ea, 0, 64);
@@ -1273,7 +1383,8 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
             const unsigned long long *x = g;
             uint32_t nx;
             if (act == 1) {
-                nx = rd_gen_ab(B, a0, (int32_t)a1, (int32_t)a2, g, sh);
+                if constexpr (DIM == 1) nx = rd_gen_ab(B, a0, (int32_t)a1, (int32_t)a2, g, sh);
+                else nx = rd_gen_tri(B, a0, g, sh);
             } else {
                 nx = a1;
                 if (nx <= RD_DCAP) {
@@ -1364,7 +1475,7 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
     char *ws = (char *)cache_get(o, s);
     if (!ws) return VR_ENOMEM;
-    RdBufs B;
+    RdBufs B{};
     B.R = (const int32_t *)(ws + o_R);
     B.ij = (const int32_t *)res->edge_ij;
     B.app = (const unsigned long long *)(ws + o_app);
@@ -1397,8 +1508,8 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
         cache_put(ws, s);
         return VR_EHIP;
     }
-    hipLaunchKernelGGL(k_rd_pre, dim3((unsigned)(K < cus ? K : cus)), dim3(RD_BLOCK), 0, s, B);
-    hipLaunchKernelGGL(k_rd_reduce, dim3(1), dim3(RD_BLOCK), 0, s, B);
+    hipLaunchKernelGGL((k_rd_pre<1>), dim3((unsigned)(K < cus ? K : cus)), dim3(RD_BLOCK), 0, s, B);
+    hipLaunchKernelGGL((k_rd_reduce<1>), dim3(1), dim3(RD_BLOCK), 0, s, B);
     hipLaunchKernelGGL(k_rd_emit, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key, T,
                        (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
                        tri_of_edge);
@@ -1589,4 +1700,249 @@ extern "C" VR_API int vr_barcode(const vr_result *res, const int32_t *e_low, con
     counts[1] = tot[1];
     counts[2] = T - (int64_t)np;
     return VR_OK;
+}
+
+// ------------------------------------------------ dimension 2, reduction ----
+// Pairs of triangles with tetrahedra (maxdim 3 builds): the same reduction
+// one dimension up.  Columns are the triangles from the youngest to the
+// oldest, a column holds the triangle's cofacets (keys rd_tet_key, in
+// filtration order) and its pivot is its oldest cofacet.  Triangles paired
+// with an edge (dimension 1) are cleared.  Apparent pairs: a triangle t
+// whose oldest cofacet s has t as its youngest facet pairs with s at once
+// (no younger triangle is a facet of s, so no column before holds s).  The
+// youngest facet of s = {a, b, c, d} (value w, edge w = {a, b}, c < d) is
+// {a, b, d}: of the two facets of value w, the one holding the larger of
+// the two other vertices.  So t (value v, vertex m off its largest edge)
+// is apparent exactly when its oldest cofacet has value v and m as its
+// larger vertex off edge v.  The apparent pairs go into the pivot table
+// (length RD_APP, start = the triangle) before the two passes of the
+// reduction; a pivot found there adds that triangle's coboundary.
+
+// The index of the tetrahedron of reduction key (w, c, d) in the listed
+// tetrahedra (value w: tet_off[w] .. tet_off[w + 1], by vertex word), or -1.
+static __device__ long long rd_tet_index(const int32_t *ij, const long long *toff, const unsigned long long *tkey,
+                                         unsigned long long key) {
+    const int64_t w = (int64_t)(key >> 26);
+    const uint32_t c = (uint32_t)(key >> 13) & 0x1FFFu, d = (uint32_t)key & 0x1FFFu;
+    const uint32_t a = (uint32_t)ij[2 * w], b = (uint32_t)ij[2 * w + 1];
+    const uint32_t x0 = min(a, c), x3 = max(b, d), m1 = max(a, c), m2 = min(b, d);
+    const unsigned long long vk = ((unsigned long long)x0 << 39) | ((unsigned long long)min(m1, m2) << 26) |
+                                  ((unsigned long long)max(m1, m2) << 13) | x3;
+    long long lo = toff[w], hi = toff[w + 1];
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (tkey[2 * mid + 1] < vk) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < toff[w + 1] && tkey[2 * lo + 1] == vk) ? lo : -1;
+}
+
+// clr[t] = 1 for the triangles paired with an edge (clr zeroed before).
+__global__ void __launch_bounds__(PD_BLOCK) k_d2_clear(const int32_t *toe, int64_t K, int32_t *clr) {
+    for (int64_t r = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; r < K; r += (int64_t)gridDim.x * PD_BLOCK) {
+        const int32_t t = toe[r];
+        if (t >= 0) clr[t] = 1;
+    }
+}
+
+// Every triangle's oldest cofacet, one wave per triangle: a cleared
+// triangle or one without cofacets has no partner (tri_tet -1, no column);
+// an apparent one pairs at once (tri_tet, and its pivot into the table);
+// the rest are columns to reduce (col 1).
+#define D2_WAVES (PD_BLOCK / 64)
+__global__ void __launch_bounds__(PD_BLOCK) k_d2_first(RdBufs B, const int32_t *clr, const long long *toff,
+                                                      const unsigned long long *tkey, int32_t *col,
+                                                      long long *tri_tet) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t tix = blockIdx.x * (int64_t)D2_WAVES + wv; tix < B.T; tix += (int64_t)gridDim.x * D2_WAVES) {
+        if (clr[tix]) {
+            if (lane == 0) {
+                col[tix] = 0;
+                tri_tet[tix] = -1;
+            }
+            continue;
+        }
+        const unsigned long long key = B.tri[tix];
+        const int32_t v = (int32_t)(key >> 39);
+        const uint32_t i = (uint32_t)(key >> 26) & 0x1FFFu, j = (uint32_t)(key >> 13) & 0x1FFFu,
+                       k = (uint32_t)key & 0x1FFFu;
+        const int32_t *Ri = B.R + (int64_t)i * B.n, *Rj = B.R + (int64_t)j * B.n, *Rk = B.R + (int64_t)k * B.n;
+        const uint32_t m = Ri[j] == v ? k : (Ri[k] == v ? j : i);
+        unsigned long long best = ~0ull;
+        for (int64_t l0 = 0; l0 < B.n; l0 += 64) {
+            const uint32_t l = (uint32_t)(l0 + lane);
+            if (l < (uint32_t)B.n && l != i && l != j && l != k) {
+                const int32_t x = Ri[l], y = Rj[l], z = Rk[l];
+                if (x != PD_INF && y != PD_INF && z != PD_INF) best = min(best, rd_cofacet(v, i, j, k, m, l, x, y, z));
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) best = min(best, (unsigned long long)__shfl_xor(best, o, 64));
+        if (lane == 0) {
+            long long q = -1;
+            int32_t cc = 0;
+            if (best != ~0ull) {
+                const int32_t w = (int32_t)(best >> 26);
+                const uint32_t d = (uint32_t)best & 0x1FFFu;
+                if (w == v && d == m) {
+                    q = rd_tet_index(B.ij, toff, tkey, best);
+                    long long sl = rd_slot(best, B.hmask);
+                    for (;; sl = (sl + 1) & B.hmask)
+                        if (atomicCAS((unsigned long long *)&B.tab[sl].key, RD_EMPTY, best) == RD_EMPTY) break;
+                    B.tab[sl].start = (uint32_t)tix;
+                    B.tab[sl].len = RD_APP;
+                } else {
+                    cc = 1;
+                }
+            }
+            col[tix] = cc;
+            tri_tet[tix] = q;
+        }
+    }
+}
+
+// Columns to reduce per chunk of BC_CHUNK triangles (second series unused).
+__global__ void __launch_bounds__(BC_CHUNK) k_d2_count(const int32_t *col, int64_t T, int32_t *cnt) {
+    __shared__ uint32_t sh[BC_CHUNK / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t x = (int64_t)blockIdx.x * BC_CHUNK + t;
+    const unsigned long long b = __ballot(x < T && col[x]);
+    if (lane == 0) sh[wv] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < BC_CHUNK / 64; w++) s += sh[w];
+        cnt[2 * (int64_t)blockIdx.x] = (int32_t)s;
+        cnt[2 * (int64_t)blockIdx.x + 1] = 0;
+    }
+}
+
+__global__ void k_d2_ctl(const long long *off, int64_t nch, RdCtl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->m = (int32_t)off[2 * nch];
+        ctl->err = 0;
+        ctl->ptop = 0;
+        ctl->next = 0;
+    }
+}
+
+// rem: the columns youngest first (column x-th from the oldest at m - 1 - x).
+__global__ void __launch_bounds__(BC_CHUNK) k_d2_list(const int32_t *col, int64_t T, const long long *off,
+                                                     int64_t nch, int32_t *rem) {
+    __shared__ uint32_t sh[BC_CHUNK / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t x = (int64_t)blockIdx.x * BC_CHUNK + t;
+    const bool keep = x < T && col[x];
+    const unsigned long long b = __ballot(keep);
+    if (lane == 0) sh[wv] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wv; w++) before += sh[w];
+    if (keep) {
+        const long long at = off[2 * (int64_t)blockIdx.x] + before +
+                             __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
+        rem[off[2 * nch] - 1 - at] = (int32_t)x;
+    }
+}
+
+// tri_tet[rem[ci]] = the index of column ci's pivot among the tetrahedra
+__global__ void __launch_bounds__(PD_BLOCK) k_d2_emit(const int32_t *ij, const long long *toff,
+                                                     const unsigned long long *tkey, const int32_t *rem,
+                                                     const unsigned long long *rkey, const RdCtl *ctl,
+                                                     long long *tri_tet) {
+    const int32_t m = ctl->m;
+    for (int64_t ci = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; ci < m; ci += (int64_t)gridDim.x * PD_BLOCK) {
+        const unsigned long long p = rkey[ci];
+        if (p != RD_EMPTY) tri_tet[rem[ci]] = rd_tet_index(ij, toff, tkey, p);
+    }
+}
+
+extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_edge, int64_t *tri_tet, void *stream) {
+    if (!res) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges, T = res->n_triangles, T3 = res->n_tetrahedra;
+    if (n < 0 || K < 0 || T < 0 || T3 < 0 || n > VR_MAX_POINTS || T > 0x7FFFFFFF) return VR_EINVAL;
+    if (T == 0) return VR_OK;
+    if (!tri_tet || !tri_of_edge || !res->edge_ij || !res->tri_key || !res->tet_off || (T3 > 0 && !res->tet_key))
+        return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    long long H = 2;
+    while (H < 2 * T) H <<= 1;
+    const int64_t nch = (T + BC_CHUNK - 1) / BC_CHUNK;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t o = 0;
+    const size_t o_R = o; o = up(o + 4 * (size_t)n * (size_t)n);
+    const size_t o_clr = o; o = up(o + 8 * (size_t)((T + 1) / 2));
+    const size_t o_col = o; o = up(o + 4 * (size_t)T);
+    const size_t o_cnt = o; o = up(o + 8 * (size_t)nch);
+    const size_t o_off = o; o = up(o + 8 * (size_t)(2 * nch + 2));
+    const size_t o_rem = o; o = up(o + 4 * (size_t)T);
+    const size_t o_tab = o; o = up(o + sizeof(RdSlot) * (size_t)H);
+    const size_t o_pool = o; o = up(o + 8 * (size_t)RD_POOL_ENTRIES);
+    const size_t o_cst = o; o = up(o + 8 * (size_t)T);
+    const size_t o_cln = o; o = up(o + 4 * (size_t)T);
+    const size_t o_w0 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
+    const size_t o_w1 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
+    const size_t o_mrg = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
+    const size_t o_rkey = o; o = up(o + 8 * (size_t)T);
+    const size_t o_pst = o; o = up(o + 4 * (size_t)T);
+    const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
+    char *ws = (char *)cache_get(o, s);
+    if (!ws) return VR_ENOMEM;
+    RdBufs B{};
+    B.R = (const int32_t *)(ws + o_R);
+    B.ij = (const int32_t *)res->edge_ij;
+    B.app = nullptr;
+    B.rem = (const int32_t *)(ws + o_rem);
+    B.tab = (RdSlot *)(ws + o_tab);
+    B.hmask = H - 1;
+    B.pool = (unsigned long long *)(ws + o_pool);
+    B.cstart = (long long *)(ws + o_cst);
+    B.clen = (int32_t *)(ws + o_cln);
+    B.w[0] = (unsigned long long *)(ws + o_w0);
+    B.w[1] = (unsigned long long *)(ws + o_w1);
+    B.mrg = (unsigned long long *)(ws + o_mrg);
+    B.rkey = (unsigned long long *)(ws + o_rkey);
+    B.pst = (int32_t *)(ws + o_pst);
+    B.ctl = (RdCtl *)(ws + o_ctl);
+    B.n = n;
+    B.K = K;
+    B.tri = (const unsigned long long *)res->tri_key;
+    B.T = T;
+    const long long *toff = (const long long *)res->tet_off;
+    const unsigned long long *tkey = (const unsigned long long *)res->tet_key;
+    int32_t *clr = (int32_t *)(ws + o_clr), *col = (int32_t *)(ws + o_col), *cnt = (int32_t *)(ws + o_cnt);
+    long long *off = (long long *)(ws + o_off);
+    hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n);
+    hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n,
+                       (const int32_t *)res->edge_ij, K, n);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for((T + 1) / 2)), dim3(PD_BLOCK), 0, s, (unsigned long long *)clr,
+                       (T + 1) / 2);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(2 * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab, 2 * H);
+    hipLaunchKernelGGL(k_d2_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K, clr);
+    hipLaunchKernelGGL(k_d2_first, dim3((unsigned)((T + D2_WAVES - 1) / D2_WAVES < 65536 ? (T + D2_WAVES - 1) / D2_WAVES
+                                                                                       : 65536)),
+                       dim3(PD_BLOCK), 0, s, B, (const int32_t *)clr, toff, tkey, col, (long long *)tri_tet);
+    hipLaunchKernelGGL(k_d2_count, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, (const int32_t *)col, T, cnt);
+    hipLaunchKernelGGL(k_bc_scan, dim3(1), dim3(BC_CHUNK), 0, s, (const int32_t *)cnt, nch, off);
+    hipLaunchKernelGGL(k_d2_ctl, dim3(1), dim3(64), 0, s, (const long long *)off, nch, B.ctl);
+    hipLaunchKernelGGL(k_d2_list, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, (const int32_t *)col, T,
+                       (const long long *)off, nch, (int32_t *)(ws + o_rem));
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        cache_put(ws, s);
+        return VR_EHIP;
+    }
+    hipLaunchKernelGGL((k_rd_pre<2>), dim3((unsigned)(T < cus ? T : cus)), dim3(RD_BLOCK), 0, s, B);
+    hipLaunchKernelGGL((k_rd_reduce<2>), dim3(1), dim3(RD_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_d2_emit, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, (const int32_t *)res->edge_ij, toff, tkey,
+                       (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
+                       (long long *)tri_tet);
+    int32_t err = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, &B.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cache_put(ws, s);
+    if (e != hipSuccess) return VR_EHIP;
+    return err ? VR_ENOMEM : VR_OK;
 }

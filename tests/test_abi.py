@@ -53,7 +53,8 @@ def _req(**kw):
     (dict(n=-1), vr.VR_EINVAL),
     (dict(dtype=7), vr.VR_EINVAL),
     (dict(points=None), vr.VR_EINVAL),
-    (dict(maxdim=3), vr.VR_EINVAL),
+    (dict(maxdim=4), vr.VR_EINVAL),
+    (dict(maxdim=3, flags=vr.VR_GRAPH), vr.VR_EINVAL),  # tetrahedra are not captured
     (dict(thr_kind=9), vr.VR_EINVAL),
     (dict(thr_kind=1, thr_num=46), vr.VR_EINVAL),      # more than C(10,2) edges
     (dict(thr_kind=2, thr_num=3, thr_den=0), vr.VR_EINVAL),
@@ -67,6 +68,14 @@ def test_invalid_requests_rejected_before_device_work(kw, code):
     rc = vr.lib().vr_build(ctypes.byref(_req(**kw)), None, ctypes.byref(out))
     assert rc == code
     assert not out
+
+
+def test_batch_rejects_maxdim3():
+    """Tetrahedra are vr_build's alone: a batch asking for them is refused."""
+    reqs = (vr.VrRequest * 2)(_req(), _req(maxdim=3))
+    out = ctypes.c_void_p()
+    assert vr.lib().vr_build_batch(reqs, 2, None, ctypes.byref(out)) == vr.VR_EINVAL
+    assert not out.value
 
 
 def test_workspace_bytes():

@@ -160,6 +160,13 @@ def serving_stream(seed: int = 5, requests: int = 2000, qps: float = 100.0,
     return out
 
 
+def sphere_cloud(seed: int, n: int, thr=("fraction", 15, 100)) -> Cloud:
+    """n points near a sphere of radius 100 in R^3 (noise 3), int8: a cloud
+    whose complex holds a class of dimension 2."""
+    rng = np.random.default_rng(seed)
+    return Cloud(quantize_i8(_sphere(rng, n)), thr, name=f"sphere{n}_s{seed}")
+
+
 def uniform_cloud(seed: int, n: int, d: int, lo: int = -127, hi: int = 127,
                   dtype=np.int8, thr=("full", 0, 1)) -> Cloud:
     """Uniform integer points, for tests of arbitrary shapes and dtypes."""
