@@ -426,8 +426,9 @@ VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t 
  * The triangle columns go from the youngest triangle to the oldest, and a
  * column's pivot is its oldest cofacet.  Triangles paired with an edge are
  * cleared; a triangle whose oldest cofacet has it as its youngest facet
- * pairs with it at once (an apparent pair: one wave per triangle finds its
- * oldest cofacet); the other columns first take, all at once, the
+ * pairs with it at once (an apparent pair: per edge the vertices joined to
+ * both ends are listed once, and one wave per triangle of that value finds
+ * its oldest cofacet among them); the other columns first take, all at once, the
  * coboundaries of the apparent pairs their pivots meet, then are reduced,
  * youngest first, by one work-group.  The pairs equal those of the column
  * algorithm on the tetrahedra's boundary block.
@@ -438,12 +439,32 @@ VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t 
  *               tet_key's order) of the tetrahedron paired with triangle t,
  *               or -1: t is paired with an edge, or else starts a class of
  *               dimension 2 that never dies.
- * Synchronises `stream`.  Scratch from the library's cache: 4 n^2 + 40 T +
- * 16 H bytes (H = 2T rounded up to a power of two) plus 608 MiB, as
+ * Synchronises `stream`.  Scratch from the library's cache: 4 n^2 + 8 K +
+ * 48 T + 16 H bytes (H = 2T rounded up to a power of two) plus 608 MiB, as
  * vr_pairs_dim1.  VR_ENOMEM when the columns outgrow it; VR_EINVAL for a
  * null argument, a result without tetrahedron keys, n > VR_MAX_POINTS or
  * T >= 2^31.  With no triangles nothing is written. */
 VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_edge, int64_t *tri_tet, void *stream);
+
+/* The barcode of dimension 2 (and the classes of dimension 3) from the
+ * pairs (Section 2.2.1: a pair (sigma, tau) is the bar [value of sigma,
+ * value of tau)), as vr_barcode one dimension up.  Values are largest edge
+ * ranks; a bar that never ends has death INT64_MAX; bars of length zero are
+ * left out.
+ * res:          a maxdim-3 build's result with its triangle and tetrahedron
+ *               keys.
+ * tri_of_edge, tri_tet: vr_pairs_dim1's and vr_pairs_dim2's outputs.
+ * bars:    device, 3 T int64, caller-owned: (2, birth, death) triples in
+ *          triangle order: triangle t paired with a tetrahedron of larger
+ *          value w gives [value of t, w); a triangle paired with neither an
+ *          edge nor a tetrahedron gives [value of t, inf).
+ * counts:  host: counts[0] = the bars written, counts[1] = the tetrahedra
+ *          no triangle pairs with (classes of dimension 3 that never die;
+ *          counted, not listed).
+ * Synchronises `stream`.  VR_EINVAL for a null argument, a result without
+ * tetrahedron keys, n > VR_MAX_POINTS or T >= 2^31. */
+VR_API int vr_barcode_dim2(const vr_result *res, const int32_t *tri_of_edge, const int64_t *tri_tet, int64_t *bars,
+                           int64_t counts[2], void *stream);
 
 /* The F2 sparse product and sum of the Schur complement step (Section 4.6):
  * S = D + C E mod 2, where C is m x k, E is k x n and D is m x n, all in

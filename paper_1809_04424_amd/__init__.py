@@ -24,7 +24,7 @@ VR_MAX_EDGES = 1 << 24
 
 # C symbols declared in include/vr.h
 SYMBOLS = ("vr_build", "vr_query_counts", "vr_unpack_triangles", "vr_query_stage_ms", "vr_stage_name", "vr_free",
-           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_pairs_dim1", "vr_barcode", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_pairs_dim2", "vr_blockprodsum_count", "vr_blockprodsum_write",
+           "vr_workspace_bytes", "vr_batch_workspace_bytes", "vr_build_batch", "vr_batch_result", "vr_batch_stage_ms", "vr_batch_free", "vr_autotune", "vr_set_schedule", "vr_trim", "vr_column_order", "vr_column_order_noalloc", "vr_pairs_dim0", "vr_pairs_dim1_apparent", "vr_pairs_dim1", "vr_barcode", "vr_tetra_counts", "vr_tetra_offsets", "vr_tetra_write", "vr_pairs_dim2", "vr_barcode_dim2", "vr_blockprodsum_count", "vr_blockprodsum_write",
            "vr_status_string", "vr_version")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -128,6 +128,9 @@ def lib():
         L.vr_pairs_dim1.restype = ctypes.c_int
         L.vr_pairs_dim2.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.vr_pairs_dim2.restype = ctypes.c_int
+        L.vr_barcode_dim2.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.vr_barcode_dim2.restype = ctypes.c_int
         L.vr_barcode.argtypes = [ctypes.POINTER(VrResult), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.vr_barcode.restype = ctypes.c_int
@@ -767,6 +770,29 @@ def pairs_dim2(result, tri_of_edge):
     if rc != VR_OK:
         raise VrError(rc, status_string(rc))
     return out[: result.T]
+
+
+def barcode_dim2(result, tri_of_edge, tri_tet):
+    """Bars of dimension 2 of a maxdim-3 build from the pairs of dimensions
+    1 and 2 (Section 2.2.1), computed on the device: (bars, ess3) with bars
+    an int64 (m, 3) device tensor of (2, birth, death) rows in triangle
+    order (death INT64_MAX for a class that never dies; no zero-length
+    bars) and ess3 the number of tetrahedra no triangle pairs with."""
+    import torch
+
+    L = lib()
+    dev = result._device
+    bars = torch.empty((max(result.T, 1), 3), dtype=torch.int64, device=dev)
+    counts = (ctypes.c_int64 * 2)()
+    r = result._c_result()
+    stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = L.vr_barcode_dim2(ctypes.byref(r), ctypes.c_void_p(tri_of_edge.data_ptr() if result.K else 0),
+                               ctypes.c_void_p(tri_tet.data_ptr() if result.T else 0), ctypes.c_void_p(bars.data_ptr()),
+                               counts, ctypes.c_void_p(stream.cuda_stream))
+    if rc != VR_OK:
+        raise VrError(rc, status_string(rc))
+    return bars[: counts[0]], int(counts[1])
 
 
 def tetra_counts(result):

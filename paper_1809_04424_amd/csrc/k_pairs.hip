@@ -1745,59 +1745,128 @@ __global__ void __launch_bounds__(PD_BLOCK) k_d2_clear(const int32_t *toe, int64
     }
 }
 
-// Every triangle's oldest cofacet, one wave per triangle: a cleared
-// triangle or one without cofacets has no partner (tri_tet -1, no column);
-// an apparent one pairs at once (tri_tet, and its pivot into the table);
-// the rest are columns to reduce (col 1).
-#define D2_WAVES (PD_BLOCK / 64)
-__global__ void __launch_bounds__(PD_BLOCK) k_d2_first(RdBufs B, const int32_t *clr, const long long *toff,
-                                                      const unsigned long long *tkey, int32_t *col,
-                                                      long long *tri_tet) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int64_t tix = blockIdx.x * (int64_t)D2_WAVES + wv; tix < B.T; tix += (int64_t)gridDim.x * D2_WAVES) {
-        if (clr[tix]) {
-            if (lane == 0) {
-                col[tix] = 0;
-                tri_tet[tix] = -1;
+// Every triangle's oldest cofacet: a cleared triangle or one without
+// cofacets has no partner (tri_tet -1, no column); an apparent one pairs at
+// once (tri_tet, and its pivot into the table); the rest are columns to
+// reduce (col 1).  One work-group per edge r = {a, b}: the triangles of
+// value r are {a, b, m} for the vertices m older-joined to both, and all
+// their cofacets {a, b, m, l} have l joined to both a and b.  The
+// work-group lists those l once (with the larger of the ranks of al and
+// bl, and which of the two it is), then one wave per triangle takes the
+// least cofacet key over them, reading only row m of the rank matrix.
+#define D2_BLOCK 256
+#define D2_WAVES (D2_BLOCK / 64)
+
+// rng[2r], rng[2r + 1] = the first and one past the last triangle of value r
+// (both 0 when there is none; rng zeroed before).
+__global__ void __launch_bounds__(PD_BLOCK) k_d2_range(const unsigned long long *tri, int64_t T, int32_t *rng) {
+    for (int64_t t = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; t < T; t += (int64_t)gridDim.x * PD_BLOCK) {
+        const unsigned long long v = tri[t] >> 39;
+        if (t == 0 || (tri[t - 1] >> 39) != v) rng[2 * v] = (int32_t)t;
+        if (t == T - 1 || (tri[t + 1] >> 39) != v) rng[2 * v + 1] = (int32_t)(t + 1);
+    }
+}
+
+__global__ void __launch_bounds__(D2_BLOCK) k_d2_first(RdBufs B, const int32_t *rng, const int32_t *clr,
+                                                      unsigned long long *piv, int32_t *col) {
+    __shared__ uint16_t Ll[VR_MAX_POINTS];  // the vertices joined to both a and b
+    __shared__ uint32_t Lx[VR_MAX_POINTS];  // max(rank al, rank bl), bit 31 set when bl is the larger
+    __shared__ uint32_t sh[D2_WAVES];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t n = B.n;
+    for (int64_t r = blockIdx.x; r < B.K; r += gridDim.x) {
+        const long long lo = rng[2 * r], hi = rng[2 * r + 1];  // the triangles of value r
+        if (lo == hi) continue;
+        const uint32_t a = (uint32_t)B.ij[2 * r], b = (uint32_t)B.ij[2 * r + 1];
+        const int32_t *Ra = B.R + (int64_t)a * n, *Rb = B.R + (int64_t)b * n;
+        // list the common neighbours of a and b, in vertex order
+        uint32_t nl = 0;
+        for (int64_t l0 = 0; l0 < n; l0 += D2_BLOCK) {
+            const int64_t l = l0 + t;
+            int32_t x = PD_INF, y = PD_INF;
+            if (l < n) {
+                x = Ra[l];
+                y = Rb[l];
             }
-            continue;
-        }
-        const unsigned long long key = B.tri[tix];
-        const int32_t v = (int32_t)(key >> 39);
-        const uint32_t i = (uint32_t)(key >> 26) & 0x1FFFu, j = (uint32_t)(key >> 13) & 0x1FFFu,
-                       k = (uint32_t)key & 0x1FFFu;
-        const int32_t *Ri = B.R + (int64_t)i * B.n, *Rj = B.R + (int64_t)j * B.n, *Rk = B.R + (int64_t)k * B.n;
-        const uint32_t m = Ri[j] == v ? k : (Ri[k] == v ? j : i);
-        unsigned long long best = ~0ull;
-        for (int64_t l0 = 0; l0 < B.n; l0 += 64) {
-            const uint32_t l = (uint32_t)(l0 + lane);
-            if (l < (uint32_t)B.n && l != i && l != j && l != k) {
-                const int32_t x = Ri[l], y = Rj[l], z = Rk[l];
-                if (x != PD_INF && y != PD_INF && z != PD_INF) best = min(best, rd_cofacet(v, i, j, k, m, l, x, y, z));
+            const bool ok = l < n && (uint32_t)l != a && (uint32_t)l != b && x != PD_INF && y != PD_INF;
+            const unsigned long long bl = __ballot(ok);
+            if (lane == 0) sh[wv] = (uint32_t)__popcll(bl);
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
+            for (int w = 0; w < D2_WAVES; w++) {
+                if (w < wv) before += sh[w];
+                tot += sh[w];
             }
+            if (ok) {
+                const uint32_t at = nl + before + __builtin_amdgcn_mbcnt_hi((uint32_t)(bl >> 32),
+                                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bl, 0));
+                Ll[at] = (uint16_t)l;
+                Lx[at] = y > x ? ((uint32_t)y | 0x80000000u) : (uint32_t)x;
+            }
+            nl += tot;
+            __syncthreads();
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) best = min(best, (unsigned long long)__shfl_xor(best, o, 64));
-        if (lane == 0) {
-            long long q = -1;
-            int32_t cc = 0;
-            if (best != ~0ull) {
-                const int32_t w = (int32_t)(best >> 26);
-                const uint32_t d = (uint32_t)best & 0x1FFFu;
-                if (w == v && d == m) {
-                    q = rd_tet_index(B.ij, toff, tkey, best);
-                    long long sl = rd_slot(best, B.hmask);
-                    for (;; sl = (sl + 1) & B.hmask)
-                        if (atomicCAS((unsigned long long *)&B.tab[sl].key, RD_EMPTY, best) == RD_EMPTY) break;
-                    B.tab[sl].start = (uint32_t)tix;
-                    B.tab[sl].len = RD_APP;
-                } else {
-                    cc = 1;
+        const int32_t v = (int32_t)r;
+        for (long long tix = lo + wv; tix < hi; tix += D2_WAVES) {
+            if (clr[tix]) {
+                if (lane == 0) {
+                    col[tix] = 0;
+                    piv[tix] = ~0ull;
                 }
+                continue;
             }
-            col[tix] = cc;
-            tri_tet[tix] = q;
+            const unsigned long long key = B.tri[tix];
+            const uint32_t i = (uint32_t)(key >> 26) & 0x1FFFu, j = (uint32_t)(key >> 13) & 0x1FFFu,
+                           k = (uint32_t)key & 0x1FFFu;
+            const uint32_t m = (i != a && i != b) ? i : ((j != a && j != b) ? j : k);  // off edge r
+            const int32_t *Rm = B.R + (int64_t)m * n;
+            unsigned long long best = ~0ull;
+            for (uint32_t p = lane; p < nl; p += 64) {
+                const uint32_t l = Ll[p];
+                if (l == m) continue;
+                const int32_t z = Rm[l];
+                if (z == PD_INF) continue;
+                const uint32_t lx = Lx[p];
+                const int32_t x = (int32_t)(lx & 0x7FFFFFFFu);
+                const int32_t w = max(v, max(x, z));
+                unsigned long long kk;
+                if (w == v) kk = rd_tet_key(w, min(m, l), max(m, l));                // edge r itself
+                else if (w == x) kk = (lx >> 31) ? rd_tet_key(w, min(a, m), max(a, m))  // edge bl
+                                                 : rd_tet_key(w, min(b, m), max(b, m)); // edge al
+                else kk = rd_tet_key(w, a, b);                                          // edge ml
+                best = min(best, kk);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) best = min(best, (unsigned long long)__shfl_xor(best, o, 64));
+            if (lane == 0) {
+                // apparent: the oldest cofacet has value v and m as its larger vertex off edge v
+                const bool app = best != ~0ull && (int32_t)(best >> 26) == v && ((uint32_t)best & 0x1FFFu) == m;
+                col[tix] = best != ~0ull && !app;
+                piv[tix] = app ? best : ~0ull;
+            }
         }
+        __syncthreads();
+    }
+}
+
+// The apparent pairs found by k_d2_first: into the pivot table (flagged,
+// with their triangle) and tri_tet; every other triangle's tri_tet is -1
+// (the reduction writes the pairs of its columns).  One thread per triangle.
+__global__ void __launch_bounds__(PD_BLOCK) k_d2_app(RdBufs B, const unsigned long long *piv, const long long *toff,
+                                                    const unsigned long long *tkey, long long *tri_tet) {
+    for (int64_t tix = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; tix < B.T;
+         tix += (int64_t)gridDim.x * PD_BLOCK) {
+        const unsigned long long p = piv[tix];
+        long long q = -1;
+        if (p != ~0ull) {
+            q = rd_tet_index(B.ij, toff, tkey, p);
+            long long sl = rd_slot(p, B.hmask);
+            for (;; sl = (sl + 1) & B.hmask)
+                if (atomicCAS((unsigned long long *)&B.tab[sl].key, RD_EMPTY, p) == RD_EMPTY) break;
+            B.tab[sl].start = (uint32_t)tix;
+            B.tab[sl].len = RD_APP;
+        }
+        tri_tet[tix] = q;
     }
 }
 
@@ -1873,6 +1942,8 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
     const size_t o_R = o; o = up(o + 4 * (size_t)n * (size_t)n);
     const size_t o_clr = o; o = up(o + 8 * (size_t)((T + 1) / 2));
     const size_t o_col = o; o = up(o + 4 * (size_t)T);
+    const size_t o_piv = o; o = up(o + 8 * (size_t)T);
+    const size_t o_rng = o; o = up(o + 8 * (size_t)K);
     const size_t o_cnt = o; o = up(o + 8 * (size_t)nch);
     const size_t o_off = o; o = up(o + 8 * (size_t)(2 * nch + 2));
     const size_t o_rem = o; o = up(o + 4 * (size_t)T);
@@ -1919,9 +1990,14 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
                        (T + 1) / 2);
     hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(2 * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab, 2 * H);
     hipLaunchKernelGGL(k_d2_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K, clr);
-    hipLaunchKernelGGL(k_d2_first, dim3((unsigned)((T + D2_WAVES - 1) / D2_WAVES < 65536 ? (T + D2_WAVES - 1) / D2_WAVES
-                                                                                       : 65536)),
-                       dim3(PD_BLOCK), 0, s, B, (const int32_t *)clr, toff, tkey, col, (long long *)tri_tet);
+    int32_t *rng = (int32_t *)(ws + o_rng);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (unsigned long long *)rng, K);
+    hipLaunchKernelGGL(k_d2_range, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, B.tri, T, rng);
+    unsigned long long *piv = (unsigned long long *)(ws + o_piv);
+    hipLaunchKernelGGL(k_d2_first, dim3((unsigned)(K < 65536 ? K : 65536)), dim3(D2_BLOCK), 0, s, B,
+                       (const int32_t *)rng, (const int32_t *)clr, piv, col);
+    hipLaunchKernelGGL(k_d2_app, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, B, (const unsigned long long *)piv, toff,
+                       tkey, (long long *)tri_tet);
     hipLaunchKernelGGL(k_d2_count, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, (const int32_t *)col, T, cnt);
     hipLaunchKernelGGL(k_bc_scan, dim3(1), dim3(BC_CHUNK), 0, s, (const int32_t *)cnt, nch, off);
     hipLaunchKernelGGL(k_d2_ctl, dim3(1), dim3(64), 0, s, (const long long *)off, nch, B.ctl);
@@ -1945,4 +2021,102 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
     cache_put(ws, s);
     if (e != hipSuccess) return VR_EHIP;
     return err ? VR_ENOMEM : VR_OK;
+}
+
+// ------------------------------------------------- barcode, dimension 2 ----
+// Bars of dimension 2 from the pairs of dimensions 1 and 2, in triangle
+// order: triangle t paired with a tetrahedron of larger value w gives
+// [value of t, w); a triangle paired with neither an edge nor a tetrahedron
+// gives [value of t, inf).  The tetrahedra no triangle pairs with are the
+// classes of dimension 3 (counted).  Per chunk of BC_CHUNK triangles the
+// bars and the pairs are counted, the counts scanned, the bars written.
+__device__ __forceinline__ bool b2_bar(const int32_t *clr, const long long *tt, const unsigned long long *tri,
+                                       const unsigned long long *tkey, int64_t t) {
+    const long long q = tt[t];
+    if (q >= 0) return (long long)tkey[2 * q] > (long long)(tri[t] >> 39);
+    return !clr[t];
+}
+
+__global__ void __launch_bounds__(BC_CHUNK) k_b2_count(const int32_t *clr, const long long *tt,
+                                                      const unsigned long long *tri, const unsigned long long *tkey,
+                                                      int64_t T, int32_t *cnt) {
+    __shared__ uint32_t sh[BC_CHUNK / 64][2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t x = (int64_t)blockIdx.x * BC_CHUNK + t;
+    const bool bar = x < T && b2_bar(clr, tt, tri, tkey, x), paired = x < T && tt[x] >= 0;
+    const unsigned long long b0 = __ballot(bar), b1 = __ballot(paired);
+    if (lane == 0) {
+        sh[wv][0] = (uint32_t)__popcll(b0);
+        sh[wv][1] = (uint32_t)__popcll(b1);
+    }
+    __syncthreads();
+    if (t < 2) {
+        uint32_t s = 0;
+        for (int w = 0; w < BC_CHUNK / 64; w++) s += sh[w][t];
+        cnt[2 * (int64_t)blockIdx.x + t] = (int32_t)s;
+    }
+}
+
+__global__ void __launch_bounds__(BC_CHUNK) k_b2_write(const int32_t *clr, const long long *tt,
+                                                      const unsigned long long *tri, const unsigned long long *tkey,
+                                                      int64_t T, const long long *off, long long *bars) {
+    __shared__ uint32_t sh[BC_CHUNK / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t x = (int64_t)blockIdx.x * BC_CHUNK + t;
+    const bool bar = x < T && b2_bar(clr, tt, tri, tkey, x);
+    const unsigned long long b = __ballot(bar);
+    if (lane == 0) sh[wv] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wv; w++) before += sh[w];
+    if (bar) {
+        const long long at = off[2 * (int64_t)blockIdx.x] + before +
+                             __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
+        const long long q = tt[x];
+        bars[3 * at] = 2;
+        bars[3 * at + 1] = (long long)(tri[x] >> 39);
+        bars[3 * at + 2] = q >= 0 ? (long long)tkey[2 * q] : 0x7FFFFFFFFFFFFFFFll;
+    }
+}
+
+extern "C" VR_API int vr_barcode_dim2(const vr_result *res, const int32_t *tri_of_edge, const int64_t *tri_tet,
+                                      int64_t *bars, int64_t counts[2], void *stream) {
+    if (!res || !counts) return VR_EINVAL;
+    const int64_t n = res->n_vertices, K = res->n_edges, T = res->n_triangles, T3 = res->n_tetrahedra;
+    if (n < 0 || K < 0 || T < 0 || T3 < 0 || n > VR_MAX_POINTS || T > 0x7FFFFFFF) return VR_EINVAL;
+    counts[0] = 0;
+    counts[1] = T3;
+    if (T == 0) return VR_OK;
+    if (!tri_of_edge || !tri_tet || !bars || !res->tri_key || !res->tet_off || (T3 > 0 && !res->tet_key))
+        return VR_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    const int64_t nch = (T + BC_CHUNK - 1) / BC_CHUNK;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t o = 0;
+    const size_t o_clr = o; o = up(o + 8 * (size_t)((T + 1) / 2));
+    const size_t o_cnt = o; o = up(o + 8 * (size_t)nch);
+    const size_t o_off = o; o = up(o + 8 * (size_t)(2 * nch + 2));
+    char *ws = (char *)cache_get(o, s);
+    if (!ws) return VR_ENOMEM;
+    int32_t *clr = (int32_t *)(ws + o_clr), *cnt = (int32_t *)(ws + o_cnt);
+    long long *off = (long long *)(ws + o_off);
+    const unsigned long long *tri = (const unsigned long long *)res->tri_key;
+    const unsigned long long *tkey = (const unsigned long long *)res->tet_key;
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for((T + 1) / 2)), dim3(PD_BLOCK), 0, s, (unsigned long long *)clr,
+                       (T + 1) / 2);
+    hipLaunchKernelGGL(k_d2_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K, clr);
+    hipLaunchKernelGGL(k_b2_count, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, (const int32_t *)clr,
+                       (const long long *)tri_tet, tri, tkey, T, cnt);
+    hipLaunchKernelGGL(k_bc_scan, dim3(1), dim3(BC_CHUNK), 0, s, (const int32_t *)cnt, nch, off);
+    hipLaunchKernelGGL(k_b2_write, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, (const int32_t *)clr,
+                       (const long long *)tri_tet, tri, tkey, T, (const long long *)off, (long long *)bars);
+    long long tot[2] = {0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(tot, off + 2 * nch, sizeof(tot), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cache_put(ws, s);
+    if (e != hipSuccess) return VR_EHIP;
+    counts[0] = tot[0];
+    counts[1] = T3 - tot[1];
+    return VR_OK;
 }

@@ -77,10 +77,16 @@ def test_maxdim3_build_and_dim2_pairs(orc, name, gen, thr):
     tt = vr.pairs_dim2(r, toe)
     torch.cuda.synchronize()
     got = tt.cpu().numpy()
-    q_low = orc.reduce_dim2(f, tets, "cohomology", orc.reduce(f, "cohomology").t_low)
+    p1 = orc.reduce(f, "cohomology")
+    q_low = orc.reduce_dim2(f, tets, "cohomology", p1.t_low)
     want = np.full(f.T, -1, np.int64)
     want[q_low[q_low >= 0]] = np.nonzero(q_low >= 0)[0]
     assert np.array_equal(got, want)
+    # the barcode of dimension 2 and the classes of dimension 3
+    bars, ess3 = vr.barcode_dim2(r, toe, tt)
+    wb = orc.barcode(f, orc.with_dim2(f, p1, tets), tets)
+    assert sorted(tuple(int(x) for x in b) for b in bars.cpu().numpy()) == sorted(b for b in wb if b[0] == 2)
+    assert ess3 == sum(1 for b in wb if b[0] == 3)
     r.free()
 
 
@@ -199,6 +205,14 @@ def test_circle1000_dim2_properties(orc):
         idx = lo + int(torch.searchsorted(tkey[lo:hi, 1].contiguous(), torch.tensor([vk], device=tkey.device)).item())
         assert tt_h[t] == idx, (t, s)
     assert apparent > 0
-    print(f"[gpu] circle1000 dimension 2: {int(paired_t.sum())} pairs, {apparent} of 3000 sampled apparent",
-          flush=True)
+    # the barcode: a bar per pair of positive length and per triangle paired
+    # with nothing; the tetrahedra left unpaired are the classes of dimension 3
+    bars, ess3 = vr.barcode_dim2(r, toe, tt)
+    b = bars.cpu().numpy()
+    assert ess3 == r.T3 - int(paired_t.sum())
+    assert np.all(b[:, 0] == 2) and np.all(b[:, 1] < b[:, 2])
+    positive = int(np.count_nonzero(tval > tri_val[paired_t]))
+    assert len(b) == positive + int(np.count_nonzero(~paired_t & ~dead_t))
+    print(f"[gpu] circle1000 dimension 2: {int(paired_t.sum())} pairs, {apparent} of 3000 sampled apparent, "
+          f"{len(b)} bars, {ess3} classes of dimension 3", flush=True)
     r.free()
