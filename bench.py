@@ -603,8 +603,8 @@ def _pairs_dim1(vr, torch, reps=5, workload="circle1000"):
     """All persistence pairs of dimension 1 and the barcode of dimensions 0
     and 1 of a build (dimension-0 pairs first, as the clearing needs them):
     the apparent pairs in one pass over the keys, then the remaining edge
-    columns: their apparent additions all at once, the rest youngest first
-    by one work-group.  Wall time of the
+    columns in rounds that reduce every unsettled column at once.  Wall
+    time of the
     three calls (each synchronises for its status), median of reps."""
     c = _workload(workload)
     pts = torch.from_numpy(c.points).to("cuda:0")

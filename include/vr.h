@@ -345,12 +345,14 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  * the pivot of an edge's column is its oldest cofacet (the smallest
  * triangle key).  Edges paired with a vertex are cleared (their columns
  * reduce to zero); an edge with triangles of its own value pairs with the
- * first of them (as in vr_pairs_dim1_apparent); every other edge's column
- * first takes, all columns at once, the coboundaries of the apparent pairs
- * its pivot meets, up to its first pivot that is not apparent (these
- * additions depend on no other column), and is then reduced, youngest first,
- * by one work-group.  The pairs equal those of the column algorithm on the
- * whole boundary matrix (Section 2.2.2).
+ * first of them (as in vr_pairs_dim1_apparent); the other edge columns are
+ * reduced in rounds: every unsettled column at once (one work-group each)
+ * adds the apparent coboundaries and the stored columns of owners before it
+ * that its pivots meet, then each pivot goes to its first claimant in the
+ * order, displacing a later owner; every round settles at least one column.
+ * The pairs equal those of the column algorithm on the whole boundary
+ * matrix (Section 2.2.2), whose pairs do not depend on the column
+ * operations that reached them.
  * res:          a single build's result with its triangle keys (maxdim 2,
  *               not count-only).
  * e_low:        device, K int32: vr_pairs_dim0's e_low for this result.
@@ -361,10 +363,11 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  *               dimension 1 that never dies.
  * The working column is a base list in device memory plus a short sorted
  * delta in LDS that takes the additions and is folded into the base when
- * full.  Synchronises `stream` (a status word is read back).  Scratch from
- * the library's cache: 4 n^2 + 36 K + 16 H bytes (H = 2K rounded up to a
- * power of two) plus 608 MiB (the stored columns, 2^26 keys, and three
- * working lists of 2^22 keys).  VR_ENOMEM when the columns outgrow that.
+ * full.  Synchronises `stream` once per round (the number of unsettled
+ * columns and a status word are read back).  Scratch from the library's
+ * cache: 4 n^2 + 48 K + 32 H bytes (H = 2K rounded up to a power of two)
+ * plus 1 GiB (the stored columns and rewritten bases, 2^27 keys).
+ * VR_ENOMEM when the columns outgrow that.
  * VR_EINVAL for a null argument, n > VR_MAX_POINTS or T >= 2^31.  With no
  * triangles (T = 0) no edge dies. */
 VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, int32_t *tri_of_edge, void *stream);
@@ -428,10 +431,9 @@ VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t 
  * cleared; a triangle whose oldest cofacet has it as its youngest facet
  * pairs with it at once (an apparent pair: per edge the vertices joined to
  * both ends are listed once, and one wave per triangle of that value finds
- * its oldest cofacet among them); the other columns first take, all at once, the
- * coboundaries of the apparent pairs their pivots meet, then are reduced,
- * youngest first, by one work-group.  The pairs equal those of the column
- * algorithm on the tetrahedra's boundary block.
+ * its oldest cofacet among them); the other columns are reduced in rounds
+ * as by vr_pairs_dim1.  The pairs equal those of the column algorithm on
+ * the tetrahedra's boundary block.
  * res:          a maxdim-3 build's result with its triangle and tetrahedron
  *               keys (not count-only).
  * tri_of_edge:  device, K int32: vr_pairs_dim1's output for this result.
@@ -439,9 +441,9 @@ VR_API int vr_tetra_write(const vr_result *res, const int64_t *offsets, int64_t 
  *               tet_key's order) of the tetrahedron paired with triangle t,
  *               or -1: t is paired with an edge, or else starts a class of
  *               dimension 2 that never dies.
- * Synchronises `stream`.  Scratch from the library's cache: 4 n^2 + 8 K +
- * 48 T + 16 H bytes (H = 2T rounded up to a power of two) plus 608 MiB, as
- * vr_pairs_dim1.  VR_ENOMEM when the columns outgrow it; VR_EINVAL for a
+ * Synchronises `stream` once per round.  Scratch from the library's cache:
+ * 4 n^2 + 8 K + 60 T + 32 H bytes (H = 2T rounded up to a power of two)
+ * plus 1 GiB, as vr_pairs_dim1.  VR_ENOMEM when the columns outgrow it; VR_EINVAL for a
  * null argument, a result without tetrahedron keys, n > VR_MAX_POINTS or
  * T >= 2^31.  With no triangles nothing is written. */
 VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_edge, int64_t *tri_tet, void *stream);

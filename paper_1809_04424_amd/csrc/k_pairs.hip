@@ -627,38 +627,37 @@ extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, voi
 //     that edge's coboundary, the pivot of a column reduced before adds
 //     that column, and a new pivot pairs the edge with p (a bar [r, value
 //     of p)) and stores the column under p.  A column that empties is a
-//     class born at r that never dies.  The additions of apparent
-//     coboundaries up to the first other pivot are made for all columns at
-//     once (k_rd_pre); one work-group then finishes the columns in order
-//     (k_rd_reduce).
+//     class born at r that never dies.  The columns are reduced in rounds,
+//     all unsettled columns at once (k_rd_round, below).
 // Additions are over F2: the symmetric difference of two sorted lists, a
 // merge that drops the keys present in both.  Every addition removes the
 // pivot and adds only larger keys, so the pivot grows and the loop ends.
 #define RD_BLOCK 1024
 #define RD_WAVES (RD_BLOCK / 64)
 #define RD_GEN_MAX 8192                    // coboundary of one edge: at most n - 2 triangles
-#define RD_POOL_ENTRIES (1ll << 26)        // stored columns (keys)
-#define RD_WORK_ENTRIES (1ll << 22)        // one working column (keys)
+#define RD_POOL_ENTRIES (1ll << 27)        // stored columns and rewritten bases (keys)
+#define RD_WORK_ENTRIES (1ll << 22)        // one column (keys)
 #define RD_EMPTY 0ull                      // no triangle key is 0 (its largest vertex is >= 2)
 
 struct RdCtl {
     int32_t m;        // columns to reduce
     int32_t err;      // 1: stored columns outgrew the pool, 2: a working column outgrew its buffer
-    long long ptop;   // pool entries the first pass took
-    int32_t next;     // the first pass's next column
+    long long ptop;   // pool entries taken
+    int32_t next;     // a round's next unsettled column
+    int32_t nh;       // columns left unsettled by a round
 };
 
-// What the first pass left of a column (RdBufs::pst)
-#define RD_ST_EMPTY 0  // reduced to zero: a class that never dies
-#define RD_ST_PIVOT 1  // stored in the pool, pivot in rkey: new unless a column before holds it
-#define RD_ST_REDO 2   // outgrew the first pass's buffers: reduced from the start
-
-// A slot of the table of pivots: the key (RD_EMPTY: a free slot) and where
-// the stored column holding it lies in the pool.
-struct __attribute__((aligned(16))) RdSlot {
+// A slot of the table of pivots: the key (RD_EMPTY: a free slot), its
+// owner (column + 1; 0: none) and where the owner's stored version lies in
+// the pool, and a round's first claimant (m - column; 0: none).
+struct __attribute__((aligned(32))) RdSlot {
     unsigned long long key;
     uint32_t start, len;
+    int32_t owner, claim;
+    unsigned long long pad;
 };
+#define RD_SLOT_WORDS ((int64_t)(sizeof(RdSlot) / 8))  // 64-bit words a slot takes (the table is zeroed by words)
+static_assert(sizeof(RdSlot) == 32, "a table slot is 32 bytes");
 
 struct RdBufs {
     const int32_t *R;               // n x n ranks (+inf off the edges, -1 on the diagonal)
@@ -670,10 +669,8 @@ struct RdBufs {
     unsigned long long *pool;       // reduced columns, back to back
     long long *cstart;              // column ci: its keys start here in the pool
     int32_t *clen;                  //   and number this many
-    unsigned long long *w[2];       // working column, ping-pong
-    unsigned long long *mrg;        // merged keys before the cancellation
     unsigned long long *rkey;       // per column: its pivot, or RD_EMPTY for a class that never dies
-    int32_t *pst;                   // per column: what the first pass left (RD_ST_*)
+    long long *cslot;               // per column: the slot of its claim in a round (-1: none)
     RdCtl *ctl;
     int64_t n, K;
     const unsigned long long *tri;  // dimension 2: the T triangle keys (the columns' simplices)
@@ -711,6 +708,7 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_list(const int32_t *first, cons
         ctl->err = 0;
         ctl->ptop = 0;
         ctl->next = 0;
+        ctl->nh = 0;
     }
 }
 
@@ -1095,189 +1093,92 @@ static __device__ __forceinline__ int32_t rd_app2(const RdBufs &B, unsigned long
     }
 }
 
-// First pass, one work-group per column at a time, columns in any order:
-// adding the coboundary of an apparent pair's edge depends on no other
-// column, so every column can take these additions at once, up to its
-// first pivot that is not apparent.  The serial pass below then meets the
-// same working column it would have built itself.  A column kept whole in
-// LDS (at most RD_DCAP keys) is stored in the pool with its pivot; one
-// that outgrows LDS is left for the serial pass to reduce from the start.
-template <int DIM>
-__global__ void __launch_bounds__(RD_BLOCK) k_rd_pre(RdBufs B) {
-    __shared__ unsigned long long g[RD_GEN_MAX];
-    __shared__ unsigned long long dl[2][RD_DCAP];
-    __shared__ uint32_t sh[RD_WAVES];
-    __shared__ int32_t s_ci, s_arg, s_a, s_b;
-    __shared__ long long s_off;
-    const int t = threadIdx.x;
-    const int32_t m = B.ctl->m;
-    for (;;) {
-        if (t == 0) s_ci = atomicAdd(&B.ctl->next, 1);
-        __syncthreads();
-        const int32_t ci = s_ci;
-        __syncthreads();
-        if (ci >= m) break;
-        uint32_t nd = rd_gen_col<DIM>(B, B.rem[ci], g, sh);
-        int dc = 0;
-        int32_t st = RD_ST_REDO;
-        if (nd <= RD_DCAP) {
-            for (uint32_t x = t; x < nd; x += RD_BLOCK) dl[0][x] = g[x];
-            __syncthreads();
-            for (;;) {
-                if constexpr (DIM == 1) {
-                    if (t == 0) {
-                        // -1: the pivot is not apparent (or the column is empty)
-                        int32_t arg = -1;
-                        if (nd > 0) {
-                            const unsigned long long p = dl[dc][0];
-                            const int64_t v = (int64_t)(p >> 39);
-                            if (v < B.K) {
-                                const unsigned long long ap = B.app[v];
-                                const int32_t ea = B.ij[2 * v], eb = B.ij[2 * v + 1];
-                                if (ap == p) {
-                                    arg = (int32_t)v;
-                                    s_a = ea;
-                                    s_b = eb;
-                                }
-                            }
-                        }
-                        s_arg = arg;
-                    }
-                } else {
-                    if (t < 64) {
-                        const int32_t arg = nd > 0 ? rd_app2(B, dl[dc][0]) : -1;
-                        if (t == 0) s_arg = arg;
-                    }
-                }
-                __syncthreads();
-                const int32_t arg = s_arg;
-                if (arg < 0) {
-                    st = nd ? RD_ST_PIVOT : RD_ST_EMPTY;
-                    break;
-                }
-                uint32_t nx;  // the generator's barriers end every read of s_*
-                if constexpr (DIM == 1) nx = rd_gen_ab(B, arg, s_a, s_b, g, sh);
-                else nx = rd_gen_tri(B, arg, g, sh);
-                if (nd + nx > RD_DCAP) break;
-                nd = rd_delta_add(dl[dc], nd, g, nx, dl[dc ^ 1], sh);
-                dc ^= 1;
-            }
+// The reduction in rounds.  A column may add any stored version of a column
+// before it (a younger simplex, reduced earlier in the order): that is a
+// column operation of Algorithm 1, and the pairs of a reduced matrix do not
+// depend on which operations reached it.  So every unsettled column is
+// reduced at once against a table that does not change during the round:
+// while its pivot is apparent (that coboundary is added) or owned by a
+// column before it (that column's stored version is added); it stops at a
+// pivot owned by nobody or by a column after it.  Then each pivot's
+// claimants are settled: the first column claiming it owns it (a later
+// former owner is displaced), the others stay unsettled.  The first
+// unsettled column meets only settled owners before it, so it reduces as
+// in the serial algorithm and wins: every round settles at least one
+// column, and in practice nearly all (3 to 5 rounds on 300- to 1000-point
+// clouds).  Round 0 is the pass over every column's coboundary.
+//
+// Column c's state: its stored version (cstart, clen; clen -1: not yet
+// generated) and pivot (rkey; RD_EMPTY once it reduced to zero).  Stored
+// versions are immutable: every new version, and every rewritten base,
+// goes to a fresh stretch of the pool.  Table slot of pivot p: the owner
+// (column + 1, 0: none) with its stored version (start, len), and this
+// round's first claimant (m - column, 0: none).
+
+// n keys from the pool for the work-group; -1 (and the error flagged) when
+// the pool is full.
+static __device__ long long rd_alloc(const RdBufs &B, uint32_t n, long long *s_off) {
+    if (threadIdx.x == 0) {
+        long long off = (long long)atomicAdd((unsigned long long *)&B.ctl->ptop, (unsigned long long)n);
+        if (off + (long long)n > RD_POOL_ENTRIES) {
+            off = -1;
+            B.ctl->err = 1;
         }
-        if (st == RD_ST_PIVOT) {
-            if (t == 0) s_off = (long long)atomicAdd((unsigned long long *)&B.ctl->ptop, (unsigned long long)nd);
-            __syncthreads();
-            const long long off = s_off;
-            if (off + nd <= RD_POOL_ENTRIES) {
-                for (uint32_t x = t; x < nd; x += RD_BLOCK) B.pool[off + x] = dl[dc][x];
-                if (t == 0) {
-                    B.cstart[ci] = off;
-                    B.clen[ci] = (int32_t)nd;
-                    B.rkey[ci] = dl[dc][0];
-                }
-            } else {
-                st = RD_ST_REDO;
-            }
-        }
-        if (t == 0) {
-            B.pst[ci] = st;
-            if (st == RD_ST_EMPTY) B.rkey[ci] = RD_EMPTY;
-        }
-        __syncthreads();
+        *s_off = off;
     }
+    __syncthreads();
+    const long long off = *s_off;
+    __syncthreads();
+    return off;
 }
 
-// The serial pass, one work-group, columns youngest first.  Wave 0 walks
-// over the columns the first pass finished, 64 at a time: an empty one, or
-// a pivot that neither the table nor a column before it in the batch holds
-// (these go into the table), up to the next column with work left: a
-// pivot already held (the column continues from its stored keys) or a
-// column to reduce from the start.  Thread 0 looks up each pivot (its
-// apparent key and its table slot, two independent loads) and the work-
-// group makes the addition; a stored column is staged in LDS first.
 template <int DIM>
-__global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
+__global__ void __launch_bounds__(RD_BLOCK) k_rd_round(RdBufs B, const int32_t *H, int32_t nH) {
     __shared__ unsigned long long g[RD_GEN_MAX];
     __shared__ unsigned long long dl[2][RD_DCAP];
     __shared__ unsigned long long smp[RD_SMP];
     __shared__ uint32_t sh[RD_WAVES];
-    __shared__ int32_t s_act, s_ci;
+    __shared__ int32_t s_act, s_hx;
     __shared__ uint32_t s_h, s_dh, s_a0, s_a1, s_a2;
     __shared__ unsigned long long s_piv;
+    __shared__ long long s_off;
     const int t = threadIdx.x;
-    const int32_t m = B.ctl->m;
-    long long top = min(B.ctl->ptop, RD_POOL_ENTRIES);  // pool entries used (every thread keeps the same count)
-    int32_t ci = 0;
-    for (;; ci++) {
-        if (t < 64) {
-            for (;;) {
-                const int32_t c = ci + t;
-                int32_t st = RD_ST_REDO;
-                unsigned long long p = RD_EMPTY;
-                uint32_t start = 0, len = 0;
-                if (c < m) {
-                    st = B.pst[c];
-                    p = B.rkey[c];
-                    start = (uint32_t)B.cstart[c];
-                    len = (uint32_t)B.clen[c];
-                }
-                const bool piv = c < m && st == RD_ST_PIVOT;
-                bool stop = !(c < m && (st == RD_ST_EMPTY || piv));
-                long long sl = rd_slot(p, B.hmask);
-                if (piv)
-                    for (;; sl = (sl + 1) & B.hmask) {
-                        const unsigned long long q = B.tab[sl].key;
-                        if (q == RD_EMPTY) break;
-                        if (q == p) {
-                            stop = true;
-                            break;
-                        }
-                    }
-                for (int j = 0; j < 63; j++) {
-                    const unsigned long long pj = __shfl(p, j, 64);
-                    const int32_t sj = __shfl(st, j, 64);
-                    if (j < t && piv && sj == RD_ST_PIVOT && pj == p) stop = true;
-                }
-                const unsigned long long bal = __ballot(stop);
-                const int f = bal ? __builtin_ctzll(bal) : 64;
-                if (t < f && piv) {
-                    // a new pivot (distinct within the batch): claim a slot
-                    for (;; sl = (sl + 1) & B.hmask)
-                        if (atomicCAS((unsigned long long *)&B.tab[sl].key, RD_EMPTY, p) == RD_EMPTY) break;
-                    B.tab[sl].start = start;
-                    B.tab[sl].len = len;
-                }
-                ci += f;
-                if (f < 64) break;
-            }
-            if (t == 0) s_ci = ci;
-        }
+    for (;;) {
+        if (t == 0) s_hx = atomicAdd(&B.ctl->next, 1);
         __syncthreads();
-        ci = s_ci;
+        const int32_t hx = s_hx;
         __syncthreads();
-        if (ci >= m) break;
-        // the base (global, entries before h gone) and the delta (LDS); bp
-        // is the base, w[wn] the buffer the next rewrite of the base goes to
-        const unsigned long long *bp = B.w[0];
-        int wn = 1, dc = 0;
+        if (hx >= nH) break;
+        const int32_t c = H[hx];
+        // the base (global, entries before h gone) and the delta (LDS)
+        const unsigned long long *bp = B.pool;
+        int dc = 0;
         uint32_t nw = 0, h = 0, nd = 0, dh = 0;
-        if (B.pst[ci] == RD_ST_PIVOT) {
-            bp = B.pool + B.cstart[ci];
-            nw = (uint32_t)B.clen[ci];
-            wn = 0;
+        bool dirty = false, fail = false;
+        const int32_t cl = B.clen[c];
+        if (cl >= 0) {
+            bp = B.pool + B.cstart[c];
+            nw = (uint32_t)cl;
         } else {
-            // delta: the coboundary (or the base, when it is longer)
-            const uint32_t len = rd_gen_col<DIM>(B, B.rem[ci], g, sh);
+            dirty = true;
+            const uint32_t len = rd_gen_col<DIM>(B, B.rem[c], g, sh);
             if (len <= RD_DCAP) {
-                for (uint32_t x = t; x < len; x += RD_BLOCK) dl[dc][x] = g[x];
+                for (uint32_t x = t; x < len; x += RD_BLOCK) dl[0][x] = g[x];
                 nd = len;
             } else {
-                for (uint32_t x = t; x < len; x += RD_BLOCK) B.w[0][x] = g[x];
-                nw = len;
+                const long long off = rd_alloc(B, len, &s_off);
+                if (off < 0) {
+                    fail = true;
+                } else {
+                    for (uint32_t x = t; x < len; x += RD_BLOCK) B.pool[off + x] = g[x];
+                    bp = B.pool + off;
+                    nw = len;
+                }
             }
             __threadfence_block();
             __syncthreads();
         }
-        for (;;) {
+        while (!fail) {
             if (t < 64) {
                 // the pivot: the smaller head, keys in both heads cancelling
                 // (64 head pairs compared at a time)
@@ -1300,10 +1201,10 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                     any = h < nw || dh < nd;
                     break;
                 }
-                // 0: never dies; 1: add the coboundary of edge a0 = {a1, a2};
-                // 2: add the stored column of a1 keys at a0; 3: new pivot.
-                // The apparent key, the edge's endpoints and 64 table slots
-                // are loaded at once.
+                // 0: reduced to zero; 1: add the coboundary of simplex a0
+                // (an edge {a1, a2} in dimension 1); 2: add the stored column
+                // of a1 keys at a0; 3: stop at pivot p.  The apparent key,
+                // the edge's endpoints and 64 table slots load at once.
                 int32_t act = 0;
                 uint32_t a0 = 0, a1 = 0, a2 = 0;
                 if (any) {
@@ -1326,10 +1227,16 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                         }
                         const int f = __builtin_ctzll(stop);
                         if (__shfl(q.key, f, 64) == p) {
-                            act = 2;
-                            a0 = __shfl(q.start, f, 64);
-                            a1 = __shfl(q.len, f, 64);
-                            if (DIM == 2 && a1 == RD_APP) act = 1;  // an apparent pair's triangle a0
+                            const uint32_t qs = __shfl(q.start, f, 64), ql = __shfl(q.len, f, 64);
+                            const int32_t owner = __shfl(q.owner, f, 64) - 1;
+                            if (DIM == 2 && ql == RD_APP) {
+                                act = 1;  // an apparent pair's triangle
+                                a0 = qs;
+                            } else if (owner >= 0 && owner < c) {
+                                act = 2;
+                                a0 = qs;
+                                a1 = ql;
+                            }
                         }
                         break;
                     }
@@ -1357,28 +1264,29 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
             h = s_h;
             dh = s_dh;
             __syncthreads();
-            if (act == 0 || act == 3) {
-                if (act == 3) {
-                    // store the column (base + delta) in the pool under p
-                    const uint32_t len_max = (nw - h) + (nd - dh);
-                    if (top + len_max > RD_POOL_ENTRIES) {
-                        if (t == 0) B.ctl->err = 1;
-                        return;
-                    }
-                    const uint32_t len =
-                        rd_fold(bp + h, nw - h, dl[dc] + dh, nd - dh, B.pool + top, (uint32_t *)dl[dc ^ 1], smp, sh);
-                    if (t == 0) {
-                        long long sl = rd_slot(p, B.hmask);
-                        while (B.tab[sl].key != RD_EMPTY) sl = (sl + 1) & B.hmask;
-                        B.tab[sl] = RdSlot{p, (uint32_t)top, len};
-                    }
-                    top += len;
+            if (act == 0) {
+                if (t == 0) {
+                    B.rkey[c] = RD_EMPTY;
+                    B.clen[c] = 0;
                 }
-                if (t == 0) B.rkey[ci] = act == 3 ? p : RD_EMPTY;
-                __threadfence_block();
-                __syncthreads();
                 break;
             }
+            if (act == 3) {
+                if (dirty) {
+                    // store the new version (base + delta) in the pool
+                    const long long off = rd_alloc(B, (nw - h) + (nd - dh), &s_off);
+                    if (off < 0) break;
+                    const uint32_t len =
+                        rd_fold(bp + h, nw - h, dl[dc] + dh, nd - dh, B.pool + off, (uint32_t *)dl[dc ^ 1], smp, sh);
+                    if (t == 0) {
+                        B.cstart[c] = off;
+                        B.clen[c] = (int32_t)len;
+                    }
+                }
+                if (t == 0) B.rkey[c] = p;
+                break;
+            }
+            dirty = true;
             // the column to add: a coboundary or a stored column, in g
             const unsigned long long *x = g;
             uint32_t nx;
@@ -1395,14 +1303,11 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                 }
             }
             if ((nd - dh) + nx > RD_DCAP) {
-                // fold the delta into the base first
-                if ((long long)(nw - h) + (nd - dh) > RD_WORK_ENTRIES) {
-                    if (t == 0) B.ctl->err = 2;
-                    return;
-                }
-                nw = rd_fold(bp + h, nw - h, dl[dc] + dh, nd - dh, B.w[wn], (uint32_t *)dl[dc ^ 1], smp, sh);
-                bp = B.w[wn];
-                wn ^= 1;
+                // fold the delta into a new base first
+                const long long off = rd_alloc(B, (nw - h) + (nd - dh), &s_off);
+                if (off < 0) break;
+                nw = rd_fold(bp + h, nw - h, dl[dc] + dh, nd - dh, B.pool + off, (uint32_t *)dl[dc ^ 1], smp, sh);
+                bp = B.pool + off;
                 h = 0;
                 nd = dh = 0;
             }
@@ -1412,18 +1317,126 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_reduce(RdBufs B) {
                 dh = 0;
             } else {
                 // a column longer than the delta goes straight into the base
-                const uint32_t nl = rd_add(bp + h, nw - h, x, nx, B.mrg, B.w[wn], sh);
+                const uint32_t L = (nw - h) + nx;
+                const long long off = rd_alloc(B, 2 * L, &s_off);  // the merge, then the sum
+                if (off < 0) break;
+                const uint32_t nl = rd_add(bp + h, nw - h, x, nx, B.pool + off, B.pool + off + L, sh);
                 if (nl == ~0u) {
                     if (t == 0) B.ctl->err = 2;
-                    return;
+                    break;
                 }
-                bp = B.w[wn];
-                wn ^= 1;
+                bp = B.pool + off + L;
                 nw = nl;
                 h = 0;
             }
         }
+        __syncthreads();  // LDS is reused by the next column
     }
+}
+
+// First round's input: every column unsettled, none generated.
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_init(RdBufs B, int32_t *H) {
+    const int32_t m = B.ctl->m;
+    for (int64_t x = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < m; x += (int64_t)gridDim.x * PD_BLOCK) {
+        H[x] = (int32_t)x;
+        B.clen[x] = -1;
+    }
+}
+
+__global__ void k_rd_reset(RdCtl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->next = 0;
+        ctl->nh = 0;
+    }
+}
+
+// Claims: each unsettled column with a pivot finds (or inserts) its slot
+// and records itself as a claimant; the first column keeps the largest m - c.
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_claim(RdBufs B, const int32_t *H, int32_t nH) {
+    const int32_t m = B.ctl->m;
+    for (int64_t x = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < nH; x += (int64_t)gridDim.x * PD_BLOCK) {
+        const int32_t c = H[x];
+        const unsigned long long p = B.rkey[c];
+        if (p == RD_EMPTY) {
+            B.cslot[c] = -1;
+            continue;
+        }
+        long long sl = rd_slot(p, B.hmask);
+        for (;; sl = (sl + 1) & B.hmask) {
+            const unsigned long long q = atomicCAS((unsigned long long *)&B.tab[sl].key, RD_EMPTY, p);
+            if (q == RD_EMPTY || q == p) break;
+        }
+        atomicMax(&B.tab[sl].claim, m - c);
+        B.cslot[c] = sl;
+    }
+}
+
+// The first claimant of each pivot owns it (with its stored version); a
+// former owner, after it in the order, is displaced; the other claimants
+// and the displaced owners form the next round's unsettled columns.
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_win(RdBufs B, const int32_t *H, int32_t nH, int32_t *Hn) {
+    const int32_t m = B.ctl->m;
+    for (int64_t x = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < nH; x += (int64_t)gridDim.x * PD_BLOCK) {
+        const int32_t c = H[x];
+        const long long sl = B.cslot[c];
+        if (sl < 0) continue;  // reduced to zero: settled
+        RdSlot &q = B.tab[sl];
+        if (q.claim == m - c) {
+            const int32_t o = q.owner - 1;
+            if (o >= 0) Hn[atomicAdd(&B.ctl->nh, 1)] = o;
+            q.owner = c + 1;
+            q.start = (uint32_t)B.cstart[c];
+            q.len = (uint32_t)B.clen[c];
+        } else {
+            Hn[atomicAdd(&B.ctl->nh, 1)] = c;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_unclaim(RdBufs B, const int32_t *H, int32_t nH) {
+    for (int64_t x = blockIdx.x * (int64_t)PD_BLOCK + threadIdx.x; x < nH; x += (int64_t)gridDim.x * PD_BLOCK) {
+        const long long sl = B.cslot[H[x]];
+        if (sl >= 0) B.tab[sl].claim = 0;
+    }
+}
+
+// The rounds, from the host: reads m, then after each round the number of
+// unsettled columns and the error word (one synchronisation per round).
+// H0, H1: m entries each.  Returns VR_OK, VR_ENOMEM or VR_EHIP.
+template <int DIM>
+static int rd_run(RdBufs &B, int32_t *H0, int32_t *H1, hipStream_t s) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return VR_EHIP;
+    RdCtl hc{};
+    if (hipMemcpyAsync(&hc, B.ctl, sizeof(hc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return VR_EHIP;
+    const int32_t m = hc.m;
+    if (m == 0) return VR_OK;
+    hipLaunchKernelGGL(k_rd_init, dim3(grid_for(m)), dim3(PD_BLOCK), 0, s, B, H0);
+    int32_t *H = H0, *Hn = H1;
+    int32_t nH = m;
+    for (int32_t round = 0; nH > 0; round++) {
+        if (round > m) return VR_EHIP;  // every round settles a column
+        hipLaunchKernelGGL(k_rd_reset, dim3(1), dim3(64), 0, s, B.ctl);
+        hipLaunchKernelGGL((k_rd_round<DIM>), dim3((unsigned)(nH < cus ? nH : cus)), dim3(RD_BLOCK), 0, s, B,
+                           (const int32_t *)H, nH);
+        hipLaunchKernelGGL(k_rd_claim, dim3(grid_for(nH)), dim3(PD_BLOCK), 0, s, B, (const int32_t *)H, nH);
+        hipLaunchKernelGGL(k_rd_win, dim3(grid_for(nH)), dim3(PD_BLOCK), 0, s, B, (const int32_t *)H, nH, Hn);
+        hipLaunchKernelGGL(k_rd_unclaim, dim3(grid_for(nH)), dim3(PD_BLOCK), 0, s, B, (const int32_t *)H, nH);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&hc, B.ctl, sizeof(hc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return VR_EHIP;
+        if (hc.err) return VR_ENOMEM;
+        nH = hc.nh;
+        int32_t *tmp = H;
+        H = Hn;
+        Hn = tmp;
+    }
+    return VR_OK;
 }
 
 // tri_of_edge[rem[ci]] = the index of column ci's pivot among the keys
@@ -1467,11 +1480,10 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     const size_t o_pool = o; o = up(o + 8 * (size_t)RD_POOL_ENTRIES);
     const size_t o_cst = o; o = up(o + 8 * (size_t)K);
     const size_t o_cln = o; o = up(o + 4 * (size_t)K);
-    const size_t o_w0 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
-    const size_t o_w1 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
-    const size_t o_mrg = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
     const size_t o_rkey = o; o = up(o + 8 * (size_t)K);
-    const size_t o_pst = o; o = up(o + 4 * (size_t)K);
+    const size_t o_cslot = o; o = up(o + 8 * (size_t)K);
+    const size_t o_h0 = o; o = up(o + 4 * (size_t)K);
+    const size_t o_h1 = o; o = up(o + 4 * (size_t)K);
     const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
     char *ws = (char *)cache_get(o, s);
     if (!ws) return VR_ENOMEM;
@@ -1485,11 +1497,8 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     B.pool = (unsigned long long *)(ws + o_pool);
     B.cstart = (long long *)(ws + o_cst);
     B.clen = (int32_t *)(ws + o_cln);
-    B.w[0] = (unsigned long long *)(ws + o_w0);
-    B.w[1] = (unsigned long long *)(ws + o_w1);
-    B.mrg = (unsigned long long *)(ws + o_mrg);
     B.rkey = (unsigned long long *)(ws + o_rkey);
-    B.pst = (int32_t *)(ws + o_pst);
+    B.cslot = (long long *)(ws + o_cslot);
     B.ctl = (RdCtl *)(ws + o_ctl);
     B.n = n;
     B.K = K;
@@ -1498,28 +1507,20 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     hipLaunchKernelGGL(k_pd_fill, dim3(grid_for(n * n)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n);
     hipLaunchKernelGGL(k_pd_edges, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (int32_t *)(ws + o_R), n,
                        (const int32_t *)res->edge_ij, K, n);
-    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(2 * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab, 2 * H);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(RD_SLOT_WORDS * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab,
+                       RD_SLOT_WORDS * H);
     hipLaunchKernelGGL(k_rd_app, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const int32_t *)tri_of_edge,
                        (const unsigned long long *)res->tri_key, K, (unsigned long long *)(ws + o_app));
-    // the first pass: one work-group per compute unit (its LDS takes most of one)
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
-        cache_put(ws, s);
-        return VR_EHIP;
-    }
-    hipLaunchKernelGGL((k_rd_pre<1>), dim3((unsigned)(K < cus ? K : cus)), dim3(RD_BLOCK), 0, s, B);
-    hipLaunchKernelGGL((k_rd_reduce<1>), dim3(1), dim3(RD_BLOCK), 0, s, B);
-    hipLaunchKernelGGL(k_rd_emit, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key, T,
-                       (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
-                       tri_of_edge);
-    int32_t err = 0;
+    const int st = rd_run<1>(B, (int32_t *)(ws + o_h0), (int32_t *)(ws + o_h1), s);
+    if (st == VR_OK)
+        hipLaunchKernelGGL(k_rd_emit, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key,
+                           T, (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
+                           tri_of_edge);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&err, &B.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     cache_put(ws, s);
-    if (e != hipSuccess) return VR_EHIP;
-    return err ? VR_ENOMEM : VR_OK;
+    if (st != VR_OK) return st;
+    return e == hipSuccess ? VR_OK : VR_EHIP;
 }
 
 // ------------------------------------------------------------ barcode ----
@@ -1892,6 +1893,7 @@ __global__ void k_d2_ctl(const long long *off, int64_t nch, RdCtl *ctl) {
         ctl->err = 0;
         ctl->ptop = 0;
         ctl->next = 0;
+        ctl->nh = 0;
     }
 }
 
@@ -1951,11 +1953,10 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
     const size_t o_pool = o; o = up(o + 8 * (size_t)RD_POOL_ENTRIES);
     const size_t o_cst = o; o = up(o + 8 * (size_t)T);
     const size_t o_cln = o; o = up(o + 4 * (size_t)T);
-    const size_t o_w0 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
-    const size_t o_w1 = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
-    const size_t o_mrg = o; o = up(o + 8 * (size_t)RD_WORK_ENTRIES);
     const size_t o_rkey = o; o = up(o + 8 * (size_t)T);
-    const size_t o_pst = o; o = up(o + 4 * (size_t)T);
+    const size_t o_cslot = o; o = up(o + 8 * (size_t)T);
+    const size_t o_h0 = o; o = up(o + 4 * (size_t)T);
+    const size_t o_h1 = o; o = up(o + 4 * (size_t)T);
     const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
     char *ws = (char *)cache_get(o, s);
     if (!ws) return VR_ENOMEM;
@@ -1969,11 +1970,8 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
     B.pool = (unsigned long long *)(ws + o_pool);
     B.cstart = (long long *)(ws + o_cst);
     B.clen = (int32_t *)(ws + o_cln);
-    B.w[0] = (unsigned long long *)(ws + o_w0);
-    B.w[1] = (unsigned long long *)(ws + o_w1);
-    B.mrg = (unsigned long long *)(ws + o_mrg);
     B.rkey = (unsigned long long *)(ws + o_rkey);
-    B.pst = (int32_t *)(ws + o_pst);
+    B.cslot = (long long *)(ws + o_cslot);
     B.ctl = (RdCtl *)(ws + o_ctl);
     B.n = n;
     B.K = K;
@@ -1988,7 +1986,8 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
                        (const int32_t *)res->edge_ij, K, n);
     hipLaunchKernelGGL(k_rd_zero, dim3(grid_for((T + 1) / 2)), dim3(PD_BLOCK), 0, s, (unsigned long long *)clr,
                        (T + 1) / 2);
-    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(2 * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab, 2 * H);
+    hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(RD_SLOT_WORDS * H)), dim3(PD_BLOCK), 0, s, (unsigned long long *)B.tab,
+                       RD_SLOT_WORDS * H);
     hipLaunchKernelGGL(k_d2_clear, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, tri_of_edge, K, clr);
     int32_t *rng = (int32_t *)(ws + o_rng);
     hipLaunchKernelGGL(k_rd_zero, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (unsigned long long *)rng, K);
@@ -2003,24 +2002,16 @@ extern "C" VR_API int vr_pairs_dim2(const vr_result *res, const int32_t *tri_of_
     hipLaunchKernelGGL(k_d2_ctl, dim3(1), dim3(64), 0, s, (const long long *)off, nch, B.ctl);
     hipLaunchKernelGGL(k_d2_list, dim3((unsigned)nch), dim3(BC_CHUNK), 0, s, (const int32_t *)col, T,
                        (const long long *)off, nch, (int32_t *)(ws + o_rem));
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
-        cache_put(ws, s);
-        return VR_EHIP;
-    }
-    hipLaunchKernelGGL((k_rd_pre<2>), dim3((unsigned)(T < cus ? T : cus)), dim3(RD_BLOCK), 0, s, B);
-    hipLaunchKernelGGL((k_rd_reduce<2>), dim3(1), dim3(RD_BLOCK), 0, s, B);
-    hipLaunchKernelGGL(k_d2_emit, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, (const int32_t *)res->edge_ij, toff, tkey,
-                       (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
-                       (long long *)tri_tet);
-    int32_t err = 0;
+    const int st = rd_run<2>(B, (int32_t *)(ws + o_h0), (int32_t *)(ws + o_h1), s);
+    if (st == VR_OK)
+        hipLaunchKernelGGL(k_d2_emit, dim3(grid_for(T)), dim3(PD_BLOCK), 0, s, (const int32_t *)res->edge_ij, toff,
+                           tkey, (const int32_t *)(ws + o_rem), (const unsigned long long *)B.rkey, (const RdCtl *)B.ctl,
+                           (long long *)tri_tet);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&err, &B.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     cache_put(ws, s);
-    if (e != hipSuccess) return VR_EHIP;
-    return err ? VR_ENOMEM : VR_OK;
+    if (st != VR_OK) return st;
+    return e == hipSuccess ? VR_OK : VR_EHIP;
 }
 
 // ------------------------------------------------- barcode, dimension 2 ----
