@@ -77,6 +77,10 @@ CASES = [
     ("torus300", lambda: workloads.batched(seed=4, clouds=3, nmin=300, nmax=300)[2].points,
      ("fraction", 12, 100)),
     ("mixture_d64_600", lambda: workloads.mixture(seed=49, n=600).points, ("fraction", 10, 100)),
+    # an edge column with 4202 cofacets, more than the 4096 a work-group's
+    # LDS holds: reduced from a base in device memory
+    ("hub_cycle_m4200", lambda: workloads.hub_cycle(), ("sqdist", 6000, 0)),
+    ("hub_cycle_m4200_denser", lambda: workloads.hub_cycle(), ("sqdist", 6500, 0)),
 ]
 
 

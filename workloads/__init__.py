@@ -229,6 +229,26 @@ def hub_pair(seed: int = 101, m: int = 300, d: int = 64, h: float = 40.0, s: flo
     return quantize_i8(pts)
 
 
+def hub_cycle(seed: int = 111, m: int = 4200, d: int = 64, h: float = 30.0, s: float = 66.8) -> np.ndarray:
+    """Two hubs a = (-h, 0, ...), b = (h, 0, ...), two points x = (-h, 40),
+    y = (h - 5, 40) and m points at radius s in the hyperplane between the
+    hubs (random directions in R^(d-1)), int8.  The path a-x-y-b is shorter
+    than the hub edge and no point is nearer both hubs than they are to each
+    other, so the hub edge closes a cycle without a triangle of its own
+    value: its column is neither cleared nor apparent, and its cofacets are
+    the m hyperplane points (more than one work-group's LDS holds when m
+    exceeds 4096)."""
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((m, d - 1))
+    y *= s / np.linalg.norm(y, axis=1, keepdims=True)
+    pts = np.zeros((m + 4, d))
+    pts[0, 0], pts[1, 0] = -h, h
+    pts[2, 0], pts[2, 1] = -h, 40.0
+    pts[3, 0], pts[3, 1] = h - 5.0, 40.0
+    pts[4:, 1:] = y
+    return quantize_i8(pts)
+
+
 def lattice_cloud(seed: int, n: int, side: int = 4, d: int = 2, thr=("full", 0, 1)) -> Cloud:
     """Points drawn from the lattice {0..side-1}^d: many exact distance ties and duplicates."""
     rng = np.random.default_rng(seed)
