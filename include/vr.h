@@ -366,8 +366,11 @@ VR_API int vr_pairs_dim1_apparent(const vr_result *res, int32_t *tri_of_edge, vo
  * full.  Synchronises `stream` once per round (the number of unsettled
  * columns and a status word are read back).  Scratch from the library's
  * cache: 4 n^2 + 48 K + 32 H bytes (H = 2K rounded up to a power of two)
- * plus 1 GiB (the stored columns and rewritten bases, 2^27 keys).
- * VR_ENOMEM when the columns outgrow that.
+ * plus 1 GiB (the stored columns and rewritten bases, 2^27 keys), and when
+ * 3 T <= 2^25 another 8 K + 24 T bytes: the apparent edges' coboundaries,
+ * generated once, all at once, so that a long chain of additions copies
+ * them instead of generating each.  VR_ENOMEM when the columns outgrow
+ * that.
  * VR_EINVAL for a null argument, n > VR_MAX_POINTS or T >= 2^31.  With no
  * triangles (T = 0) no edge dies. */
 VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, int32_t *tri_of_edge, void *stream);

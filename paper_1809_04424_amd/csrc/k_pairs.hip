@@ -636,6 +636,7 @@ extern "C" VR_API int vr_tetra_counts(const vr_result *res, int64_t *counts, voi
 #define RD_WAVES (RD_BLOCK / 64)
 #define RD_GEN_MAX 8192                    // coboundary of one edge: at most n - 2 triangles
 #define RD_POOL_ENTRIES (1ll << 27)        // stored columns and rewritten bases (keys)
+#define RD_ACACHE_KEYS (1ll << 25)         // largest cache of apparent coboundaries (keys)
 #define RD_WORK_ENTRIES (1ll << 22)        // one column (keys)
 #define RD_EMPTY 0ull                      // no triangle key is 0 (its largest vertex is >= 2)
 
@@ -675,6 +676,11 @@ struct RdBufs {
     int64_t n, K;
     const unsigned long long *tri;  // dimension 2: the T triangle keys (the columns' simplices)
     int64_t T;
+    // dimension 1, when the coboundaries are few enough: every apparent
+    // edge's sorted coboundary, generated once (acache + astart[v], up to
+    // astart[v + 1]); null otherwise
+    const unsigned long long *acache;
+    const long long *astart;
 };
 
 // A table slot of dimension 2 whose length is RD_APP holds an apparent pair:
@@ -1290,16 +1296,23 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_round(RdBufs B, const int32_t *
             // the column to add: a coboundary or a stored column, in g
             const unsigned long long *x = g;
             uint32_t nx;
-            if (act == 1) {
+            if (act == 1 && (DIM == 2 || !B.acache)) {
                 if constexpr (DIM == 1) nx = rd_gen_ab(B, a0, (int32_t)a1, (int32_t)a2, g, sh);
                 else nx = rd_gen_tri(B, a0, g, sh);
             } else {
+                // a stored column, or an apparent edge's cached coboundary
+                const unsigned long long *src = B.pool + a0;
                 nx = a1;
+                if (act == 1) {
+                    const long long o = B.astart[a0];
+                    src = B.acache + o;
+                    nx = (uint32_t)(B.astart[a0 + 1] - o);
+                }
                 if (nx <= RD_DCAP) {
-                    for (uint32_t y = t; y < nx; y += RD_BLOCK) g[y] = B.pool[a0 + y];
+                    for (uint32_t y = t; y < nx; y += RD_BLOCK) g[y] = src[y];
                     __syncthreads();
                 } else {
-                    x = B.pool + a0;
+                    x = src;
                 }
             }
             if ((nd - dh) + nx > RD_DCAP) {
@@ -1331,6 +1344,45 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_round(RdBufs B, const int32_t *
             }
         }
         __syncthreads();  // LDS is reused by the next column
+    }
+}
+
+// Dimension 1, coboundaries of the apparent edges generated ahead, all at
+// once: a chain of additions (the essential class of a noisy circle takes
+// thousands, one after the other) then copies each from device memory
+// instead of generating and sorting it.  alen[v] = the size of apparent edge
+// v's coboundary (its common neighbours), 0 for the other edges; one wave
+// per edge.
+__global__ void __launch_bounds__(PD_BLOCK) k_rd_acount(RdBufs B, long long *alen) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t v = blockIdx.x * (int64_t)(PD_BLOCK / 64) + wv; v < B.K; v += (int64_t)gridDim.x * (PD_BLOCK / 64)) {
+        if (B.app[v] == RD_EMPTY) {
+            if (lane == 0) alen[v] = 0;
+            continue;
+        }
+        const int32_t a = B.ij[2 * v], b = B.ij[2 * v + 1];
+        const int32_t *Ra = B.R + (int64_t)a * B.n, *Rb = B.R + (int64_t)b * B.n;
+        uint32_t cnt = 0;
+        for (int64_t k0 = 0; k0 < B.n; k0 += 64) {
+            const int64_t k = k0 + lane;
+            const bool ok = k < B.n && k != a && k != b && Ra[k] != PD_INF && Rb[k] != PD_INF;
+            cnt += (uint32_t)__popcll(__ballot(ok));
+        }
+        if (lane == 0) alen[v] = cnt;
+    }
+}
+
+// The apparent edges' coboundaries into the cache (astart: the scanned
+// sizes), one work-group per edge at a time.
+__global__ void __launch_bounds__(RD_BLOCK) k_rd_agen(RdBufs B, unsigned long long *cache) {
+    __shared__ unsigned long long g[RD_GEN_MAX];
+    __shared__ uint32_t sh[RD_WAVES];
+    for (int64_t v = blockIdx.x; v < B.K; v += gridDim.x) {
+        const long long o = B.astart[v], len = B.astart[v + 1] - o;
+        if (len == 0) continue;
+        const uint32_t nx = rd_gen(B, v, g, sh);
+        for (uint32_t x = threadIdx.x; x < nx; x += RD_BLOCK) cache[o + x] = g[x];
+        __syncthreads();  // g is rewritten by the next edge
     }
 }
 
@@ -1485,6 +1537,11 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     const size_t o_h0 = o; o = up(o + 4 * (size_t)K);
     const size_t o_h1 = o; o = up(o + 4 * (size_t)K);
     const size_t o_ctl = o; o = up(o + sizeof(RdCtl));
+    // the apparent edges' coboundaries hold at most 3 T keys (a triangle
+    // lies in three edges' coboundaries): generated ahead when that fits
+    const bool acache = 3 * T <= RD_ACACHE_KEYS;
+    const size_t o_alen = o; o = up(o + (acache ? 8 * (size_t)(K + 1) : 0));
+    const size_t o_acache = o; o = up(o + (acache ? 8 * (size_t)(3 * T) : 0));
     char *ws = (char *)cache_get(o, s);
     if (!ws) return VR_ENOMEM;
     RdBufs B{};
@@ -1511,6 +1568,17 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
                        RD_SLOT_WORDS * H);
     hipLaunchKernelGGL(k_rd_app, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const int32_t *)tri_of_edge,
                        (const unsigned long long *)res->tri_key, K, (unsigned long long *)(ws + o_app));
+    if (acache) {
+        long long *alen = (long long *)(ws + o_alen);
+        const int64_t wblocks = (K + PD_BLOCK / 64 - 1) / (PD_BLOCK / 64);
+        hipLaunchKernelGGL(k_rd_acount, dim3((unsigned)(wblocks < 65536 ? wblocks : 65536)), dim3(PD_BLOCK), 0, s, B,
+                           alen);
+        hipLaunchKernelGGL(k_tet_scan, dim3(1), dim3(1024), 0, s, alen, K);  // sizes -> starts, alen[K] = total
+        B.astart = alen;
+        B.acache = (const unsigned long long *)(ws + o_acache);
+        hipLaunchKernelGGL(k_rd_agen, dim3((unsigned)(K < 2048 ? K : 2048)), dim3(RD_BLOCK), 0, s, B,
+                           (unsigned long long *)(ws + o_acache));
+    }
     const int st = rd_run<1>(B, (int32_t *)(ws + o_h0), (int32_t *)(ws + o_h1), s);
     if (st == VR_OK)
         hipLaunchKernelGGL(k_rd_emit, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const unsigned long long *)res->tri_key,
