@@ -123,7 +123,7 @@ __device__ __forceinline__ void rows_count_rank(const VrDev &D, uint32_t *keys, 
             const uint32_t k = kx[i], lr = own[i];
             row[y[i]] = lr;
             D.star_nbr[s0 + y[i]] = (uint16_t)k;
-            D.pos[s0 + k] = (uint16_t)y[i];
+            D.epos[2 * (kb + lr) + ((uint32_t)v < k ? 0 : 1)] = (uint16_t)y[i];
             sk[x] = k | (y[i] << 16);
             keys[x] = k | (y[i] << 16);
         }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(VR_BLOCK) void k_rows(VrDev D) {
                 const uint32_t k = ((ij[i] >> 16) == (uint32_t)v) ? (ij[i] & 0xFFFFu) : (ij[i] >> 16);
                 row[y] = lr;
                 D.star_nbr[s0 + y] = (uint16_t)k;
-                D.pos[s0 + k] = (uint16_t)y;
+                D.epos[2 * (kb + lr) + ((uint32_t)v < k ? 0 : 1)] = (uint16_t)y;
                 pk[k] = (uint16_t)y;
             }
         }
@@ -404,13 +404,13 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
     if (p < s1) {
         r = kb + (p0 == s0 ? r0 : D.star_r[p]);  // global kept-edge index
         b = p0 == s0 ? b0 : D.star_nbr[p];
-        // edge {b,a} in b's star: the count reads it from b's positions (one
-        // scattered read per entry) and stores it beside the entry, where the
-        // write reads it in order
+        // edge {b,a} in b's star: the count reads it from the per-edge
+        // positions (4 bytes per kept edge, written by the star stage) and
+        // stores it beside the entry, where the write reads it in order
         if (WRITE) {
             pb = D.ppos[p];
         } else {
-            pb = D.pos[star_slot(mb, n, (int)b) + (uint32_t)a];
+            pb = D.epos[2 * r + (b < (uint32_t)a ? 0u : 1u)];
             D.ppos[p] = (uint16_t)pb;
         }
         sb = star_slot(mb, n, (int)b);

@@ -249,7 +249,7 @@ struct Plan {
     size_t off_cl, off_cs;
     size_t off_q, off_key0, off_key1, off_val0, off_val1, off_st0, off_st1;
     size_t off_seij, off_seq;
-    size_t off_star_r, off_star_nbr, off_star_k, off_deg, off_pos, off_ppos, off_cnt, off_off;
+    size_t off_star_r, off_star_nbr, off_star_k, off_deg, off_epos, off_ppos, off_cnt, off_off;
     size_t off_vcloud, off_tcloud, off_scloud, off_kcloud;
     size_t total;
 };
@@ -293,7 +293,7 @@ Plan plan(long long C, long long V, long long E, long long tiles, long long Kmax
         P.off_star_nbr = o; o = align_up(o + 2 * (size_t)N2);
         P.off_star_k = o; o = align_up(o + 4 * (VR_PLIST_PER * (size_t)N2 + 65 * VR_PLISTS * (size_t)V));  // prefix lists
         P.off_deg = o; o = align_up(o + 4 * (size_t)V);
-        P.off_pos = o; o = align_up(o + 2 * (size_t)N2);
+        P.off_epos = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_ppos = o; o = align_up(o + 2 * (size_t)N2);
         P.off_cnt = o; o = align_up(o + 4 * (size_t)Kmax);
         P.off_off = o; o = align_up(o + 8 * (size_t)Kmax);
@@ -694,7 +694,7 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
         D.star_nbr = (uint16_t *)(ws + P.off_star_nbr);
         D.star_k = (uint32_t *)(ws + P.off_star_k);
         D.deg = (uint32_t *)(ws + P.off_deg);
-        D.pos = (uint16_t *)(ws + P.off_pos);
+        D.epos = (uint16_t *)(ws + P.off_epos);
         D.ppos = (uint16_t *)(ws + P.off_ppos);
         D.cnt = (uint32_t *)(ws + P.off_cnt);
         D.off = (unsigned long long *)(ws + P.off_off);

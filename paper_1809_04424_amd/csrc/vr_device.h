@@ -450,7 +450,8 @@ struct VrDev {
                             // whole and cut at each 1/VR_PLISTS of the rank order), each followed by
                             // 64 sentinels
     uint32_t *deg;          // V: star sizes
-    uint16_t *pos;          // sum n^2, in the star slots: entry k of v's slot = position of edge {v,k}
+    uint16_t *epos;         // 2 Kmax: entry 2r + s = position of kept edge r in the rank-ordered star of its
+                            // lower (s = 0) or upper (s = 1) endpoint
                             // in v's rank-ordered star (set for v's neighbours only)
     uint16_t *ppos;         // sum n^2, in the star slots: entry x of v's star = the position of that
                             // edge in the partner's star (written by the count, read by the write)
