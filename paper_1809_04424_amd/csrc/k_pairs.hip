@@ -681,6 +681,13 @@ struct RdBufs {
     // astart[v + 1]); null otherwise
     const unsigned long long *acache;
     const long long *astart;
+    // dimension 1: every vertex's kept edges as (rank << 16 | neighbour)
+    // words, in neighbour order (nv) and in rank order (sr), from soff[v] to
+    // soff[v + 1]; epos[2r + s] = the place of edge r in the rank order of
+    // its lower (s = 0) or upper (s = 1) endpoint
+    const unsigned long long *nv, *sr;
+    const uint32_t *epos;
+    const long long *soff;
 };
 
 // A table slot of dimension 2 whose length is RD_APP holds an apparent pair:
@@ -772,35 +779,106 @@ static __device__ __forceinline__ void rd_wave_sync() {
 
 static __device__ uint32_t rd_sort(unsigned long long *g, uint32_t run);
 
+static __device__ __forceinline__ uint32_t rd_lower_bound(const unsigned long long *a, uint32_t n, unsigned long long x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+
 // The coboundary of edge e, sorted, into g (LDS); returns its length.  Each
 // thread takes a run of at most RD_SEG consecutive vertices k (its loads
 // all in flight at once), one scan places the keys, rd_sort sorts them.
+// The keys of one stream of n0 items compacted in order into dst (LDS):
+// key(x) is item x's key, or ~0 for none.  Each thread takes a run of at
+// most RD_SEG consecutive items (n0 < VR_MAX_POINTS), so one scan places
+// them.  Returns the count.
+template <typename F>
+static __device__ uint32_t rd_compact(uint32_t n0, unsigned long long *dst, uint32_t *sh, F key) {
+    const uint32_t S = (n0 + RD_BLOCK - 1) / RD_BLOCK;
+    const uint32_t x0 = (uint32_t)threadIdx.x * S;
+    unsigned long long kv[RD_SEG];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < RD_SEG; u++) {
+        kv[u] = ~0ull;
+        if (u < S && x0 + u < n0) kv[u] = key(x0 + u);
+        c += kv[u] != ~0ull ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t at = rd_scan(c, sh, &tot);
+#pragma unroll
+    for (uint32_t u = 0; u < RD_SEG; u++)
+        if (kv[u] != ~0ull) dst[at++] = kv[u];
+    return tot;
+}
+
+// The coboundary of edge e = {a, b}, sorted, into g (LDS); returns its
+// length.  No sort: the cofacets {a, b, k} of value e (both other edges
+// older) come from a's edges in neighbour order, which is their order; a
+// cofacet of larger value takes the value of its youngest edge, ak or bk,
+// so the cofacets whose youngest edge is ak follow a's edges after e in
+// rank order, those whose youngest edge is bk follow b's, and the two
+// sorted runs are merged (each key placed by a binary search in the other
+// run).
 static __device__ uint32_t rd_gen_ab(const RdBufs &B, int64_t e, int32_t a, int32_t b, unsigned long long *g,
                                      uint32_t *sh) {
     const int t = threadIdx.x;
     const int32_t *Ra = B.R + (int64_t)a * B.n, *Rb = B.R + (int64_t)b * B.n;
-    const int S = (int)((B.n + RD_BLOCK - 1) / RD_BLOCK);
-    const int k0 = t * S;
-    int32_t val[RD_SEG];
-    uint32_t c = 0;
+    const long long oa = B.soff[a], ob = B.soff[b];
+    const uint32_t da = (uint32_t)(B.soff[a + 1] - oa), db = (uint32_t)(B.soff[b + 1] - ob);
+    const bool alo = a < b;
+    const uint32_t pa = B.epos[2 * e + (alo ? 0 : 1)], pb = B.epos[2 * e + (alo ? 1 : 0)];
+    const unsigned long long *nva = B.nv + oa, *sra = B.sr + oa + pa + 1, *srb = B.sr + ob + pb + 1;
+    const int32_t E = (int32_t)e;
+    // value e: ak and bk both older than e, in neighbour order
+    const uint32_t c1 = rd_compact(da, g, sh, [&](uint32_t x) -> unsigned long long {
+        const unsigned long long w = nva[x];
+        const uint32_t k = (uint32_t)w & 0xFFFFu;
+        if ((int32_t)(w >> 16) >= E) return ~0ull;
+        return Rb[k] < E ? rd_tri_key((uint32_t)E, (uint32_t)a, (uint32_t)b, k) : ~0ull;
+    });
+    // youngest edge ak (after e in a's rank order), then youngest edge bk
+    const uint32_t ca = rd_compact(da - pa - 1, g + c1, sh, [&](uint32_t x) -> unsigned long long {
+        const unsigned long long w = sra[x];
+        const uint32_t k = (uint32_t)w & 0xFFFFu;
+        const int32_t r = (int32_t)(w >> 16), y = Rb[k];
+        return (y != PD_INF && y < r) ? rd_tri_key((uint32_t)r, (uint32_t)a, (uint32_t)b, k) : ~0ull;
+    });
+    const uint32_t cb = rd_compact(db - pb - 1, g + c1 + ca, sh, [&](uint32_t x) -> unsigned long long {
+        const unsigned long long w = srb[x];
+        const uint32_t k = (uint32_t)w & 0xFFFFu;
+        const int32_t r = (int32_t)(w >> 16), y = Ra[k];
+        return (y != PD_INF && y < r) ? rd_tri_key((uint32_t)r, (uint32_t)a, (uint32_t)b, k) : ~0ull;
+    });
+    // merge the runs g[c1, c1 + ca) and g[c1 + ca, c1 + ca + cb) in place:
+    // every key is read before any is written
+    __syncthreads();
+    const unsigned long long *A = g + c1, *Bq = g + c1 + ca;
+    unsigned long long mv[RD_SEG];
+    uint32_t md[RD_SEG];
+    const uint32_t nm = ca + cb;
 #pragma unroll
-    for (int u = 0; u < RD_SEG; u++) {
-        const int k = k0 + u;
-        val[u] = -1;
-        if (u < S && k < B.n) {
-            const int32_t x = Ra[k], y = Rb[k];
-            if (k != a && k != b && x != PD_INF && y != PD_INF) {
-                val[u] = max((int32_t)e, max(x, y));
-                c++;
-            }
+    for (uint32_t u = 0; u < RD_SEG; u++) {
+        const uint32_t x = (uint32_t)t + u * RD_BLOCK;
+        md[u] = ~0u;
+        mv[u] = 0;
+        if (x < nm) {
+            const unsigned long long v = g[c1 + x];
+            mv[u] = v;
+            md[u] = x < ca ? x + rd_lower_bound(Bq, cb, v) : (x - ca) + rd_lower_bound(A, ca, v);
         }
     }
-    uint32_t run;
-    uint32_t at = rd_scan(c, sh, &run);
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < RD_SEG; u++)
-        if (val[u] >= 0) g[at++] = rd_tri_key((uint32_t)val[u], (uint32_t)a, (uint32_t)b, (uint32_t)(k0 + u));
-    return rd_sort(g, run);
+    for (uint32_t u = 0; u < RD_SEG; u++)
+        if (md[u] != ~0u) g[c1 + md[u]] = mv[u];
+    __syncthreads();
+    return c1 + nm;
 }
 
 // Sort the first run keys of g (LDS) in place; returns run.  Bitonic: in a
@@ -947,15 +1025,6 @@ static __device__ __forceinline__ long long rd_slot(unsigned long long p, long l
 // whole column at every addition would dominate.
 #define RD_DCAP 4096
 
-static __device__ __forceinline__ uint32_t rd_lower_bound(const unsigned long long *a, uint32_t n, unsigned long long x) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
 
 #define RD_SMP 2048  // keys of the base's sample in LDS
 
@@ -1347,6 +1416,49 @@ __global__ void __launch_bounds__(RD_BLOCK) k_rd_round(RdBufs B, const int32_t *
     }
 }
 
+// Dimension 1: each vertex's kept edges from its row of the rank matrix,
+// in neighbour order (nv) and, sorted, in rank order (sr), with every
+// edge's places in its endpoints' rank orders (epos).  soff[v] = the
+// vertex's degree first (k_st_deg), then its start (after a scan).
+__global__ void __launch_bounds__(PD_BLOCK) k_st_deg(const int32_t *R, int64_t n, long long *soff) {
+    __shared__ uint32_t sw[PD_BLOCK / 64];
+    const int t = threadIdx.x;
+    const int32_t *row = R + (int64_t)blockIdx.x * n;
+    uint32_t c = 0;
+    for (int64_t k = t; k < n; k += PD_BLOCK) c += (k != (int64_t)blockIdx.x && row[k] != PD_INF) ? 1u : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((t & 63) == 0) sw[t >> 6] = c;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t d = 0;
+        for (int w = 0; w < PD_BLOCK / 64; w++) d += sw[w];
+        soff[blockIdx.x] = d;
+    }
+}
+
+__global__ void __launch_bounds__(RD_BLOCK) k_st_fill(RdBufs B, unsigned long long *nv, unsigned long long *sr,
+                                                     uint32_t *epos) {
+    __shared__ unsigned long long g[RD_GEN_MAX];
+    __shared__ uint32_t sh[RD_WAVES];
+    const int64_t v = blockIdx.x;
+    const int32_t *row = B.R + v * B.n;
+    const long long o = B.soff[v];
+    const uint32_t deg = rd_compact((uint32_t)B.n, g, sh, [&](uint32_t k) -> unsigned long long {
+        const int32_t r = row[k];
+        return ((int64_t)k != v && r != PD_INF) ? (((unsigned long long)(uint32_t)r << 16) | k) : ~0ull;
+    });
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < deg; x += RD_BLOCK) nv[o + x] = g[x];
+    rd_sort(g, deg);  // its first barrier ends the reads above
+    for (uint32_t x = threadIdx.x; x < deg; x += RD_BLOCK) {
+        const unsigned long long w = g[x];
+        const uint32_t k = (uint32_t)w & 0xFFFFu;
+        sr[o + x] = w;
+        epos[2 * (w >> 16) + ((int64_t)k > v ? 0 : 1)] = x;
+    }
+}
+
 // Dimension 1, coboundaries of the apparent edges generated ahead, all at
 // once: a chain of additions (the essential class of a noisy circle takes
 // thousands, one after the other) then copies each from device memory
@@ -1542,6 +1654,11 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
     const bool acache = 3 * T <= RD_ACACHE_KEYS;
     const size_t o_alen = o; o = up(o + (acache ? 8 * (size_t)(K + 1) : 0));
     const size_t o_acache = o; o = up(o + (acache ? 8 * (size_t)(3 * T) : 0));
+    // every vertex's edges in neighbour and in rank order, for the generator
+    const size_t o_soff = o; o = up(o + 8 * (size_t)(n + 1));
+    const size_t o_nv = o; o = up(o + 16 * (size_t)K);
+    const size_t o_sr = o; o = up(o + 16 * (size_t)K);
+    const size_t o_epos = o; o = up(o + 8 * (size_t)K);
     char *ws = (char *)cache_get(o, s);
     if (!ws) return VR_ENOMEM;
     RdBufs B{};
@@ -1568,6 +1685,17 @@ extern "C" VR_API int vr_pairs_dim1(const vr_result *res, const int32_t *e_low, 
                        RD_SLOT_WORDS * H);
     hipLaunchKernelGGL(k_rd_app, dim3(grid_for(K)), dim3(PD_BLOCK), 0, s, (const int32_t *)tri_of_edge,
                        (const unsigned long long *)res->tri_key, K, (unsigned long long *)(ws + o_app));
+    {
+        long long *soff = (long long *)(ws + o_soff);
+        hipLaunchKernelGGL(k_st_deg, dim3((unsigned)n), dim3(PD_BLOCK), 0, s, B.R, n, soff);
+        hipLaunchKernelGGL(k_tet_scan, dim3(1), dim3(1024), 0, s, soff, n);  // degrees -> starts
+        B.soff = soff;
+        hipLaunchKernelGGL(k_st_fill, dim3((unsigned)n), dim3(RD_BLOCK), 0, s, B, (unsigned long long *)(ws + o_nv),
+                           (unsigned long long *)(ws + o_sr), (uint32_t *)(ws + o_epos));
+        B.nv = (const unsigned long long *)(ws + o_nv);
+        B.sr = (const unsigned long long *)(ws + o_sr);
+        B.epos = (const uint32_t *)(ws + o_epos);
+    }
     if (acache) {
         long long *alen = (long long *)(ws + o_alen);
         const int64_t wblocks = (K + PD_BLOCK / 64 - 1) / (PD_BLOCK / 64);
