@@ -81,6 +81,10 @@ CASES = [
     # LDS holds: reduced from a base in device memory
     ("hub_cycle_m4200", lambda: workloads.hub_cycle(), ("sqdist", 6000, 0)),
     ("hub_cycle_m4200_denser", lambda: workloads.hub_cycle(), ("sqdist", 6500, 0)),
+    # the largest point count: every vertex's edge lists built from rows of
+    # 8192 ranks (eight per thread)
+    ("n8192_sparse", lambda: workloads.uniform_cloud(77, 8192, 2, dtype=np.int32, lo=0, hi=6000).points,
+     ("count", 200000, 1)),
 ]
 
 
