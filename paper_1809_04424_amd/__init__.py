@@ -795,6 +795,41 @@ def barcode_dim2(result, tri_of_edge, tri_tet):
     return bars[: counts[0]], int(counts[1])
 
 
+def persistence(points, thr=("full", 0, 1), maxdim: int = 2):
+    """The whole device path, from points to barcodes (Section 3: the
+    package's main call takes a cloud, an upper limit on the scale and how
+    many dimensions to compute, and returns their persistence): the build,
+    then the pairs of
+    dimensions 0 and 1 and their barcode; with maxdim 3 also the
+    tetrahedra, the pairs of dimension 2 and their barcode.  Returns a dict:
+    "bars" an (m, 3) int64 device tensor of (dimension, birth, death) rows
+    (values are largest edge ranks, -1 for vertices; death 2^63 - 1 for a
+    class that never dies; no zero-length bars), "essential_top" the
+    classes of the top dimension that never die (counted, not listed:
+    dimension 2 for maxdim 2, 3 for maxdim 3), and "counts" (n, K, T[,
+    T3]).  Every step runs in the library's kernels; this only chains the
+    calls."""
+    import torch
+
+    if maxdim not in (2, 3):
+        raise ValueError("maxdim must be 2 or 3")
+    r = build(points, thr, maxdim=maxdim)
+    try:
+        e_low, _ = pairs_dim0(r)
+        toe = pairs_dim1(r, e_low)
+        bars, ess2 = barcode(r, e_low, toe)
+        counts = r.counts
+        if maxdim == 3:
+            tt = pairs_dim2(r, toe)
+            bars2, ess3 = barcode_dim2(r, toe, tt)
+            bars = torch.cat([bars, bars2])
+            return {"bars": bars, "essential_top": ess3, "counts": counts + (r.T3,)}
+        return {"bars": bars, "essential_top": ess2, "counts": counts}
+    finally:
+        torch.cuda.current_stream(r._device).synchronize()
+        r.free()
+
+
 def tetra_counts(result):
     """Tetrahedra per largest edge (dimension 3): an int64 device tensor of
     K entries."""

@@ -216,3 +216,29 @@ def test_circle1000_dim2_properties(orc):
     print(f"[gpu] circle1000 dimension 2: {int(paired_t.sum())} pairs, {apparent} of 3000 sampled apparent, "
           f"{len(b)} bars, {ess3} classes of dimension 3", flush=True)
     r.free()
+
+
+@pytest.mark.parametrize("maxdim", [2, 3])
+def test_persistence_chain_matches_oracle_barcode(orc, maxdim):
+    """vr.persistence, the build, pairs and barcodes chained on the device,
+    gives the oracle's barcode: every bar of dimensions 0..maxdim-1 and the
+    count of classes of the top dimension."""
+    import paper_1809_04424_amd as vr
+
+    c = workloads.noisy_circle(seed=220, n=160)
+    thr = ("fraction", 25, 100)
+    import torch
+
+    out = vr.persistence(torch.from_numpy(np.ascontiguousarray(c.points)).to("cuda:0"), thr, maxdim=maxdim)
+    f = orc.build(c.points, thr)
+    p = orc.reduce(f, "cohomology")
+    if maxdim == 3:
+        tets = orc.tetra_list(f)
+        want = orc.barcode(f, orc.with_dim2(f, p, tets), tets)
+        assert out["counts"] == f.counts + (len(tets),)
+    else:
+        want = orc.barcode(f, p)
+        assert out["counts"] == f.counts
+    got = sorted(tuple(int(x) for x in b) for b in out["bars"].cpu().numpy())
+    assert got == sorted(b for b in want if b[0] < maxdim)
+    assert out["essential_top"] == sum(1 for b in want if b[0] == maxdim)
