@@ -252,7 +252,11 @@ VR_API void vr_batch_free(vr_batch *batch, void *stream);
 /*
  * Autotuning of the triangle kernels' schedule (work-group size 128, 256 or 512,
  * work-groups per vertex 1, 2, 4, 8 or 16, and candidate pieces of 64 loaded
- * at a time: 2, 4 or 8 for the count, 4 or 8 for the write) for the size
+ * at a time: 2, 4 or 8 for the count, 4 or 8 for the write; the write also
+ * takes 0 work-groups per vertex: one wave per vertex and eighth of its
+ * partners, each die of the chip taking one eighth, with the work-group
+ * size halved while its waves' LDS, 2 maxn + 2048 bytes each, would pass
+ * 64 KiB) for the size
  * class of these requests (bits of their total vertex count and of their
  * mean degree).  Runs one build of the requests (as vr_build_batch), then
  * times the count and the write kernel at every schedule, keeps the fastest

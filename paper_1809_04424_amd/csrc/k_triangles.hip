@@ -386,6 +386,23 @@ __device__ __forceinline__ uint32_t enum_excl_scan(uint32_t x, uint32_t *sh, uin
 // neighbour order.  Otherwise it is counted at the endpoint
 // whose partner has the shorter rank prefix (candidates = that prefix).
 // The first chunk's star entries come preloaded (r0, b0: see stage_pos).
+// Which endpoint writes edge {a, b}: a walks b's shortest prefix list
+// holding b's first pb entries, or b walks a's holding a's first xa; the
+// shorter walk wins, the smaller vertex on a tie (so exactly one endpoint
+// owns the edge).  xa, da: the edge's position in a's star and a's degree;
+// pb: its position in b's star.  For a's side: len = the list's length and
+// sb = where it starts in star_k.
+__device__ __forceinline__ bool write_side(const VrDev &D, uint32_t a, uint32_t b, uint32_t xa, uint32_t da,
+                                           uint32_t pb, uint32_t vb, uint32_t mb, int n, uint32_t &len,
+                                           uint32_t &sb) {
+    const uint32_t db = D.deg[vb + b];
+    const uint32_t jb = plist_pick(pb, db), ja = plist_pick(xa, da);
+    const uint32_t cb = jb ? plist_len(jb, db) : 0u, ca = ja ? plist_len(ja, da) : 0u;
+    len = cb;
+    sb = plist_region(mb, vb, n, (int)b) + plist_off(jb ? jb : 1u, db);
+    return cb < ca || (cb == ca && a < b);
+}
+
 template <bool WRITE, int EB>
 __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, uint32_t mb, int n, uint32_t kb,
                                           uint32_t s0, uint32_t s1, uint32_t p0, EnumLds<EB> &L, int part,
@@ -415,14 +432,7 @@ __device__ __forceinline__ int load_chunk(const VrDev &D, int a, uint32_t vb, ui
         }
         sb = star_slot(mb, n, (int)b);
         if (WRITE) {
-            // a walks b's shortest list holding b's first pb entries, or b
-            // walks a's holding a's first x: the shorter walk wins
-            const uint32_t db = D.deg[vb + b], da = s1 - s0;
-            const uint32_t jb = plist_pick(pb, db), ja = plist_pick(x, da);
-            const uint32_t cb = jb ? plist_len(jb, db) : 0u, ca = ja ? plist_len(ja, da) : 0u;
-            owned = cb < ca || (cb == ca && (uint32_t)a < b);
-            len = cb;
-            sb = plist_region(mb, vb, n, (int)b) + plist_off(jb ? jb : 1u, db);
+            owned = write_side(D, (uint32_t)a, b, x, s1 - s0, pb, vb, mb, n, len, sb);
         } else {
             owned = pb < x || (pb == x && (uint32_t)a < b);
             len = pb;
@@ -765,6 +775,80 @@ __device__ __forceinline__ void emit_edges_range(const VrDev &D, long long K, ui
     }
 }
 
+// The triangles of up to 64 edges that vertex a (local index) writes, one
+// edge's parameters per lane (lanes >= ne unused): global rank vr, start
+// vsb and length vlen of the partner's prefix list in star_k, the edge's
+// positions vxa in a's star and vpb in the partner's, the partner vb, and
+// the edge's first output slot voff.  Pa = a's position table.  Each edge's
+// list is walked in neighbour order, so its hits come out in k order.
+template <int NP>
+__device__ __forceinline__ void write_run(const VrDev &D, unsigned long long *__restrict__ out, uint32_t a,
+                                          uint32_t kb, const uint16_t *Pa, int ne, uint32_t vr, uint32_t vsb,
+                                          uint32_t vlen, uint32_t vxa, uint32_t vpb, uint32_t vb,
+                                          unsigned long long voff) {
+    const int lane = threadIdx.x & 63;
+    // write the triangles of edge el from its prefetched pieces
+    auto write_edge = [&](int el, const uint32_t (&kk)[NP]) {
+        const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
+        const uint32_t r = rl(vr, el) - kb;  // local rank within the cloud
+        unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
+                                         rl((uint32_t)voff, el));
+        uint32_t run = 0;  // keys of this edge written so far
+        // key = (r << 39) | (x0 << 26) | (x1 << 13) | x2 with x0 < x1 < x2 the
+        // sorted triple {lo, hi, k}; k differs from both endpoints
+        const uint32_t lo = min(a, b), hi = max(a, b);
+        const uint32_t rh = r << 7;  // bits 39.. of the key, in the high word
+        // one 64-entry piece of the partner's neighbour-ordered star, with
+        // the position of each entry's neighbour in a's star (lanes past
+        // the star read sentinels, which never hit)
+        const unsigned long long kbase = (unsigned long long)rh << 32;
+        auto piece = [&](uint32_t v, uint32_t pa) {
+            const uint32_t k = v & 0xFFFFu, pk = v >> 16;
+            // lane masks of the two tests straight from the comparisons
+            // (unsigned less-than is predicate 36)
+            const unsigned long long m = __builtin_amdgcn_uicmp(pk, pb, 36) & __builtin_amdgcn_uicmp(pa, xa, 36);
+            if ((pk < pb) & (pa < xa)) {
+                // x1 = k clamped to [lo, hi] is the median; x0 << 26 spans both
+                // words, added to the edge's base with the low bits of x1, x2
+                const uint32_t x0 = min(lo, k), x2 = max(hi, k), x1 = min(max(k, lo), hi);
+                const unsigned long long key = (((unsigned long long)x0 << 26) + kbase) | ((x1 << 13) | x2);
+                const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, run));
+                // streaming store: keeps the stars, not the output, in L2
+                __builtin_nontemporal_store(key, dst + at);
+            }
+            run += (uint32_t)__popcll(m);
+        };
+        // pieces in groups of four: a group past len is skipped whole
+        // (pieces past len inside a group read sentinels), and the four
+        // position lookups of a group are issued together
+#pragma unroll
+        for (int g = 0; g < NP; g += 4) {
+            if ((uint32_t)(g * VR_WAVE) < len) {
+                uint32_t pa[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) pa[j] = Pa[kk[g + j] & 0xFFFFu];
+#pragma unroll
+                for (int j = 0; j < 4; j++) piece(kk[g + j], pa[j]);
+            }
+        }
+        for (uint32_t y0 = NP * VR_WAVE; y0 < len; y0 += VR_WAVE) {
+            const uint32_t v = D.star_k[rl(vsb, el) + y0 + (uint32_t)lane];
+            piece(v, Pa[v & 0xFFFFu]);
+        }
+    };
+    // ping-pong prefetch one edge ahead; past the last edge the loads
+    // repeat the last edge's (never consumed)
+    uint32_t kA[NP], kB[NP];
+    issue_padded(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
+    for (int el = 0; el < ne; el += 2) {
+        const int e1 = min(el + 1, ne - 1), e2 = min(el + 2, ne - 1);
+        issue_padded(D.star_k + rl(vsb, e1), rl(vlen, e1), kB);
+        write_edge(el, kA);
+        issue_padded(D.star_k + rl(vsb, e2), rl(vlen, e2), kA);
+        if (el + 1 < ne) write_edge(el + 1, kB);
+    }
+}
+
 // Blocks [0, n*parts) write triangles; the blocks after them write the
 // public edge arrays.
 template <int EB, int NP>
@@ -812,68 +896,136 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
                 vb = L.b[eb + lane];
                 voff = D.off[vr];
             }
-            // write the triangles of edge el from its prefetched pieces
-            auto write_edge = [&](int el, const uint32_t (&kk)[NP]) {
-                const uint32_t xa = rl(vxa, el), pb = rl(vpb, el), len = rl(vlen, el), b = rl(vb, el);
-                const uint32_t r = rl(vr, el) - kb;  // local rank within the cloud
-                unsigned long long *dst = out + (((unsigned long long)rl((uint32_t)(voff >> 32), el) << 32) |
-                                                 rl((uint32_t)voff, el));
-                uint32_t run = 0;  // keys of this edge written so far
-                // key = (r << 39) | (x0 << 26) | (x1 << 13) | x2 with x0 < x1 < x2 the
-                // sorted triple {lo, hi, k}; k differs from both endpoints
-                const uint32_t lo = min((uint32_t)a, b), hi = max((uint32_t)a, b);
-                const uint32_t rh = r << 7;  // bits 39.. of the key, in the high word
-                // one 64-entry piece of the partner's neighbour-ordered star, with
-                // the position of each entry's neighbour in a's star (lanes past
-                // the star read sentinels, which never hit)
-                const unsigned long long kbase = (unsigned long long)rh << 32;
-                auto piece = [&](uint32_t v, uint32_t pa) {
-                    const uint32_t k = v & 0xFFFFu, pk = v >> 16;
-                    // lane masks of the two tests straight from the comparisons
-                    // (unsigned less-than is predicate 36)
-                    const unsigned long long m = __builtin_amdgcn_uicmp(pk, pb, 36) & __builtin_amdgcn_uicmp(pa, xa, 36);
-                    if ((pk < pb) & (pa < xa)) {
-                        // x1 = k clamped to [lo, hi] is the median; x0 << 26 spans both
-                        // words, added to the edge's base with the low bits of x1, x2
-                        const uint32_t x0 = min(lo, k), x2 = max(hi, k), x1 = min(max(k, lo), hi);
-                        const unsigned long long key = (((unsigned long long)x0 << 26) + kbase) | ((x1 << 13) | x2);
-                        const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, run));
-                        // streaming store: keeps the stars, not the output, in L2
-                        __builtin_nontemporal_store(key, dst + at);
-                    }
-                    run += (uint32_t)__popcll(m);
-                };
-                // pieces in groups of four: a group past len is skipped whole
-                // (pieces past len inside a group read sentinels), and the four
-                // position lookups of a group are issued together
-#pragma unroll
-                for (int g = 0; g < NP; g += 4) {
-                    if ((uint32_t)(g * VR_WAVE) < len) {
-                        uint32_t pa[4];
-#pragma unroll
-                        for (int j = 0; j < 4; j++) pa[j] = Pa[kk[g + j] & 0xFFFFu];
-#pragma unroll
-                        for (int j = 0; j < 4; j++) piece(kk[g + j], pa[j]);
-                    }
-                }
-                for (uint32_t y0 = NP * VR_WAVE; y0 < len; y0 += VR_WAVE) {
-                    const uint32_t v = D.star_k[rl(vsb, el) + y0 + (uint32_t)lane];
-                    piece(v, Pa[v & 0xFFFFu]);
-                }
-            };
-            // ping-pong prefetch one edge ahead; past the last edge the loads
-            // repeat the last edge's (never consumed)
-            uint32_t kA[NP], kB[NP];
-            issue_padded(D.star_k + rl(vsb, 0), rl(vlen, 0), kA);
-            for (int el = 0; el < ne; el += 2) {
-                const int e1 = min(el + 1, ne - 1), e2 = min(el + 2, ne - 1);
-                issue_padded(D.star_k + rl(vsb, e1), rl(vlen, e1), kB);
-                write_edge(el, kA);
-                issue_padded(D.star_k + rl(vsb, e2), rl(vlen, e2), kA);
-                if (el + 1 < ne) write_edge(el + 1, kB);
-            }
+            write_run<NP>(D, out, (uint32_t)a, kb, Pa, ne, vr, vsb, vlen, vxa, vpb, vb, voff);
         }
         __syncthreads();
+    }
+}
+
+// LDS of one wave of k_tri_write_x: a's position table (maxn entries,
+// rounded up to 8) and a ring of 128 staged edges.
+#define VR_XRING 128
+__host__ __device__ __forceinline__ uint32_t xwave_lds(int maxn) {
+    return 2u * (((uint32_t)maxn + 7u) & ~7u) + VR_XRING * (uint32_t)sizeof(uint4);
+}
+
+// Orders a wave's LDS stores before its later LDS loads of other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The write with 0 work-groups per vertex: one wave per (vertex a, eighth
+// of its cloud's vertices), taking the edges a writes (write_side) whose
+// partner lies in that eighth.  Work-group g holds the waves of vertices
+// [W (g / 8), W (g / 8) + W) for eighth g mod 8.  Work-groups go to the
+// chip's 8 dies (XCDs, each with its own L2) in turn, so block index mod 8
+// names the die: each die reads the prefix lists of one eighth of the
+// vertices, about an eighth of them all, which its L2 can hold.  Each wave
+// runs on its own, with a's position table and a ring of staged edges in
+// the wave's own LDS and no work-group barrier: the table is filled from
+// a's rank-ordered star while counting a's neighbours below the eighth's
+// bounds, which locates a's edges to the eighth as one run of its
+// neighbour-ordered star; those a writes are staged in the ring and
+// written 64 at a time (write_run).  Blocks past the vertices' write the
+// public edge arrays.
+template <int EB, int NP>
+__global__ __launch_bounds__(EB) void k_tri_write_x(VrDev D, unsigned long long *__restrict__ out, long long cap_k,
+                                                    unsigned long long cap_t, uint32_t *__restrict__ edge_ij,
+                                                    long long *__restrict__ edge_q) {
+    constexpr int W = EB / VR_WAVE;
+    extern __shared__ uint32_t lds[];
+    const long long K = (long long)D.ctl->n_kept;
+    if (K > cap_k || D.ctl->n_tri > cap_t) return;
+    const long long nb = (D.V + W - 1) / W * 8;
+    if ((long long)blockIdx.x >= nb) {
+        emit_edges_range(D, K, edge_ij, edge_q, (long long)(blockIdx.x - nb) * EB + threadIdx.x,
+                         (long long)(gridDim.x - nb) * EB);
+        return;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t x8 = blockIdx.x & 7u;
+    const long long ag = (long long)(blockIdx.x >> 3) * W + w;
+    if (ag >= D.V) return;  // the whole wave: nothing below waits on other waves
+    const uint32_t deg = D.deg[ag];
+    if (deg == 0) return;
+    const int c = vertex_cloud(D, ag);
+    const uint32_t vb = (uint32_t)D.cl[c].vbase;
+    const uint32_t kb = (uint32_t)kept_base(D, c);
+    const int n = D.cl[c].n;
+    const uint32_t a = (uint32_t)(ag - vb);
+    const uint32_t mb = (uint32_t)D.cl[c].mbase;
+    const uint32_t pa_n = ((uint32_t)D.maxn + 7u) & ~7u;
+    uint16_t *Pa = (uint16_t *)((char *)lds + (size_t)w * xwave_lds(D.maxn));
+    uint4 *ring = (uint4 *)(Pa + pa_n);
+    const uint32_t s0 = star_slot(mb, n, (int)a), s1 = s0 + deg;
+    // partners b with (8 b) / n == x8
+    const uint32_t blo = (x8 * (uint32_t)n + 7u) / 8u, bhi = ((x8 + 1u) * (uint32_t)n + 7u) / 8u;
+    for (uint32_t i = (uint32_t)lane; i < pa_n / 8u; i += VR_WAVE) ((uint4 *)Pa)[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    wave_lds_sync();
+    // position table; y0, y1 = a's neighbours below blo, below bhi
+    uint32_t y0 = 0, y1 = 0;
+    for (uint32_t base = s0; base < s1; base += 4 * VR_WAVE) {
+        uint32_t k[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) k[j] = D.star_nbr[min(base + (uint32_t)(j * VR_WAVE + lane), s1 - 1u)];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t p = base + (uint32_t)(j * VR_WAVE + lane);
+            const bool in = p < s1;
+            if (in) Pa[k[j]] = (uint16_t)(p - s0);
+            y0 += (uint32_t)__popcll(ballot64(in && k[j] < blo));
+            y1 += (uint32_t)__popcll(ballot64(in && k[j] < bhi));
+        }
+    }
+    wave_lds_sync();
+    // a's neighbour-ordered star (the last prefix list): entries [y0, y1)
+    // are its edges to the eighth
+    const uint32_t *sk = D.star_k + plist_region(mb, vb, n, (int)a) + plist_off(VR_PLISTS, deg);
+    uint32_t head = 0, cnt = 0;  // staged edges: ring slots [head, head + cnt)
+    auto flush = [&](int ne) {
+        uint32_t vr = 0, vsb = 0, vlen = 0, vxa = 0, vpb = 0, vbp = 0;
+        unsigned long long voff = 0;
+        if (lane < ne) {
+            const uint4 e = ring[(head + (uint32_t)lane) & (VR_XRING - 1)];
+            vr = e.x;
+            vsb = e.y;
+            vbp = e.z & 0xFFFFu;
+            vxa = e.z >> 16;
+            vpb = e.w & 0xFFFFu;
+            vlen = e.w >> 16;
+            voff = D.off[vr];
+        }
+        write_run<NP>(D, out, a, kb, Pa, ne, vr, vsb, vlen, vxa, vpb, vbp, voff);
+    };
+    for (uint32_t y = y0; y < y1; y += VR_WAVE) {
+        const uint32_t yy = y + (uint32_t)lane;
+        const bool in = yy < y1;
+        const uint32_t e = sk[in ? yy : y1 - 1u];
+        const uint32_t b = e & 0xFFFFu, xa = e >> 16;
+        const uint32_t r = kb + D.star_r[s0 + xa];
+        const uint32_t pb = D.ppos[s0 + xa];
+        uint32_t len = 0, sb = 0;
+        const bool mine = write_side(D, a, b, xa, deg, pb, vb, mb, n, len, sb);
+        const bool own = in && mine && len > 0;  // len 0: the edge has no triangles
+        const unsigned long long m = ballot64(own);
+        if (own) {
+            const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            ring[(head + cnt + at) & (VR_XRING - 1)] = make_uint4(r, sb, b | (xa << 16), pb | (len << 16));
+        }
+        cnt += (uint32_t)__popcll(m);
+        if (cnt >= VR_WAVE) {  // cnt < 128: the ring never overflows
+            wave_lds_sync();
+            flush(VR_WAVE);
+            head = (head + VR_WAVE) & (VR_XRING - 1);
+            cnt -= VR_WAVE;
+            wave_lds_sync();
+        }
+    }
+    if (cnt > 0) {
+        wave_lds_sync();
+        flush((int)cnt);
     }
 }
 
@@ -882,14 +1034,30 @@ __global__ __launch_bounds__(EB) void k_tri_write(VrDev D, unsigned long long *_
 // they take the dispatch's own start and end times (no separate markers).
 void launch_tri_write(const VrDev &D, unsigned long long *tri_out, long long cap_k, unsigned long long cap_t,
                       uint32_t *edge_ij, long long *edge_q, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    const int parts = D.parts_write, EB = D.eb_write;
+    const int parts = D.parts_write;
+    int EB = D.eb_write;
+    // one wave per (vertex, eighth): fewer waves per work-group while their
+    // LDS would pass 64 KiB
+    if (parts == 0)
+        while (EB > 128 && (size_t)(EB / VR_WAVE) * xwave_lds(D.maxn) > 65536) EB /= 2;
     const long long K = cap_k;
     long long eb = (K + EB - 1) / EB;  // extra work-groups that write the edge arrays
     if (eb > 256) eb = 256;
     if (eb < 1) eb = 1;
-    const dim3 grid((unsigned)(D.V * parts + eb));
+    const long long W = EB / VR_WAVE;
+    const dim3 grid((unsigned)((parts == 0 ? (D.V + W - 1) / W * 8 : D.V * parts) + eb));
     auto go = [&](auto eb_c, auto np_c) {
         constexpr int E = decltype(eb_c)::value, N = decltype(np_c)::value;
+        if (parts == 0) {
+            const size_t lb = (size_t)(E / VR_WAVE) * xwave_lds(D.maxn);
+            if (ev0 && ev1)
+                hipExtLaunchKernelGGL((k_tri_write_x<E, N>), grid, dim3(E), lb, s, ev0, ev1, 0u, D, tri_out, cap_k,
+                                      cap_t, edge_ij, edge_q);
+            else
+                hipLaunchKernelGGL((k_tri_write_x<E, N>), grid, dim3(E), lb, s, D, tri_out, cap_k, cap_t, edge_ij,
+                                   edge_q);
+            return;
+        }
         if (ev0 && ev1)
             hipExtLaunchKernelGGL((k_tri_write<E, N>), grid, dim3(E), enum_lds<E>(D.maxn), s, ev0, ev1, 0u, D, tri_out,
                                   parts, cap_k, cap_t, edge_ij, edge_q);

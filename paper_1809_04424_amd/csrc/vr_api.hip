@@ -917,8 +917,19 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
             if (hipEventSynchronize(e[1]) == hipSuccess) (void)hipEventElapsedTime(&t, e[0], e[1]);
             return t;
         };
+        auto time_write = [&](VrDev &Dp, int eb, int p) {
+            Dp.eb_write = eb;
+            Dp.parts_write = p;
+            for (int nw : cand_nw) {
+                Dp.pieces_write = nw;
+                const float t = timed([&] {
+                    launch_tri_write(Dp, (unsigned long long *)tri_key, K, T, (uint32_t *)edge_ij, (long long *)edge_q, s);
+                });
+                if (t < best_w) { best_w = t; best.eb_write = eb; best.parts_write = p; best.pieces_write = nw; }
+            }
+        };
         for (int rep = 0; rep < 3; rep++)
-            for (int eb : cand_eb)
+            for (int eb : cand_eb) {
                 for (int p : cand_p) {
                     if (V * p > (1ll << 30)) continue;
                     VrDev Dp = D;
@@ -929,16 +940,13 @@ int build_impl(const vr_request *reqs, long long count, hipStream_t s, Owner &ow
                         const float t = timed([&] { launch_tri_count(Dp, s); });
                         if (t < best_c) { best_c = t; best.eb_count = eb; best.parts_count = p; best.pieces_count = nc; }
                     }
-                    if (write_tri)
-                        for (int nw : cand_nw) {
-                            Dp.pieces_write = nw;
-                            const float t = timed([&] {
-                                launch_tri_write(Dp, (unsigned long long *)tri_key, K, T, (uint32_t *)edge_ij,
-                                                 (long long *)edge_q, s);
-                            });
-                            if (t < best_w) { best_w = t; best.eb_write = eb; best.parts_write = p; best.pieces_write = nw; }
-                        }
+                    if (write_tri) time_write(Dp, eb, p);
                 }
+                if (write_tri) {  // one wave per (vertex, eighth of the partners)
+                    VrDev Dp = D;
+                    time_write(Dp, eb, 0);
+                }
+            }
         for (int i = 0; i < 2; i++) (void)hipEventDestroy(e[i]);
         if (hipGetLastError() != hipSuccess) return failw(VR_EHIP);
         {
@@ -1099,7 +1107,7 @@ int vr_set_schedule(const vr_request *reqs, int64_t count, const int32_t sched[6
         return false;
     };
     if (!in(sched[0], {128, 256, 512}) || !in(sched[1], {1, 2, 4, 8, 16}) || !in(sched[2], {2, 4, 8}) ||
-        !in(sched[3], {128, 256, 512}) || !in(sched[4], {1, 2, 4, 8, 16}) || !in(sched[5], {4, 8}))
+        !in(sched[3], {128, 256, 512}) || !in(sched[4], {0, 1, 2, 4, 8, 16}) || !in(sched[5], {4, 8}))
         return VR_EINVAL;
     Shape S;
     const int st = shape_of(reqs, count, S);

@@ -168,8 +168,10 @@ def test_set_schedule_validates():
     arr = (vr.VrRequest * 1)(_req())
     good = (ctypes.c_int32 * 6)(256, 1, 4, 256, 2, 8)
     assert L.vr_set_schedule(arr, 1, good) == vr.VR_OK
+    # 0 work-groups per vertex: the write's one-wave-per-eighth form (not the count's)
+    assert L.vr_set_schedule(arr, 1, (ctypes.c_int32 * 6)(256, 1, 4, 512, 0, 8)) == vr.VR_OK
     for bad in [(64, 1, 4, 256, 2, 8), (256, 3, 4, 256, 2, 8), (256, 1, 5, 256, 2, 8), (256, 1, 4, 256, 2, 2),
-                (256, 1, 4, 1024, 2, 8), (256, 1, 4, 256, 32, 8)]:
+                (256, 1, 4, 1024, 2, 8), (256, 1, 4, 256, 32, 8), (256, 0, 4, 256, 2, 8), (256, 1, 4, 256, -1, 8)]:
         assert L.vr_set_schedule(arr, 1, (ctypes.c_int32 * 6)(*bad)) == vr.VR_EINVAL
     assert L.vr_set_schedule(None, 1, good) == vr.VR_EINVAL
     assert L.vr_set_schedule(arr, 0, good) == vr.VR_EINVAL
