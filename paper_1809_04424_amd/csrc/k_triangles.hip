@@ -24,6 +24,9 @@
 //                 partner's entries before the edge; hits are compacted with ballot and
 //                 mbcnt (the ballot/popc compaction of the paper's init_supp,
 //                 Section 4.4, on 64-wide waves) and stored contiguously
+//   k_tri_write_x the same writes, one wave per (vertex, eighth of its
+//                 partners), each die of the chip reading one eighth of the
+//                 prefix lists (a schedule the tuner may pick)
 //   k_emit_edges  public edge arrays
 #include "vr_device.h"
 

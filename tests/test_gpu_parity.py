@@ -115,15 +115,29 @@ def test_repeat_builds_identical():
     assert np.array_equal(a["edge_ij"], b["edge_ij"])
 
 
-def test_mixture4000_complete(orc):
+_MIX_ORACLE = {}
+
+
+@pytest.mark.parametrize("sched", [None, (512, 1, 4, 512, 2, 8), (512, 1, 4, 256, 0, 8)],
+                         ids=["default", "bench_tuned", "wave_per_eighth"])
+def test_mixture4000_complete(orc, sched):
     """Full-size 4000 x R^64 mixture at the 10th percentile (the headline
-    workload, in the launch configuration the benchmark times): every kept
-    edge and all 94,017,474 triangle keys equal the oracle's, element by
-    element."""
+    workload): every kept edge and all 94,017,474 triangle keys equal the
+    oracle's, element by element, with the default schedule, the one the
+    benchmark's tuning picks (two work-groups per vertex in the write), and
+    the write with one wave per vertex and eighth of its partners."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
     c = workloads.mixture()
-    _say("[gpu] mixture4000 oracle (threaded)")
-    f = orc.build_mt(c.points, c.thr, host_threads(), list_triangles=False)
-    _say("[gpu] mixture4000 build")
+    if "f" not in _MIX_ORACLE:
+        _say("[gpu] mixture4000 oracle (threaded)")
+        _MIX_ORACLE["f"] = orc.build_mt(c.points, c.thr, host_threads(), list_triangles=False)
+    f = _MIX_ORACLE["f"]
+    if sched is not None:
+        vr.set_schedule(torch.from_numpy(np.ascontiguousarray(c.points)).to("cuda:0"), c.thr, sched)
+    _say(f"[gpu] mixture4000 build, schedule {sched}")
     res, out = gpu_build(c)
     assert out["counts"] == (4000, 799800, f.T)
     assert np.array_equal(out["edge_ij"][:, 0], f.ei)
