@@ -498,7 +498,7 @@ void or_reduce_homology(int64_t n, int64_t K, const int64_t *ei, const int64_t *
     /* triangle block: rows are edge ranks */
     int64_t *R = NULL;
     int64_t *cp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T + 1));
-    int64_t *cr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(3 * T + 1));
+    int64_t *cr = (int64_t *)calloc((size_t)(3 * T + 1), sizeof(int64_t));
     R = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n * n > 0 ? n * n : 1));
     for (int64_t x = 0; x < n * n; x++) R[x] = -1;
     for (int64_t r = 0; r < K; r++) { R[ei[r] * n + ej[r]] = r; R[ej[r] * n + ei[r]] = r; }
