@@ -1037,6 +1037,7 @@ static __device__ __forceinline__ long long rd_slot(unsigned long long p, long l
 // below it).  The base's every 2^sh-th key is staged in LDS first (the
 // whole base when it fits), so a delta key's place takes a search in LDS
 // and at most sh steps in device memory.
+#define RD_FOLD_U 4  // base keys per thread in flight in a fold
 static __device__ uint32_t rd_fold(const unsigned long long *a, uint32_t na, const unsigned long long *b, uint32_t nb,
                                    unsigned long long *dst, uint32_t *sc, unsigned long long *smp, uint32_t *sh) {
     const int t = threadIdx.x;
@@ -1080,17 +1081,34 @@ static __device__ uint32_t rd_fold(const unsigned long long *a, uint32_t na, con
         const uint32_t mex = j ? minc[j - 1] : 0u;
         if (minc[j] == mex) dst[pos[j] + j - 2 * mex] = b[j];
     }
-    for (uint32_t i = t; i < na; i += RD_BLOCK) {
-        const unsigned long long y = lg ? a[i] : smp[i];
-        uint32_t lo = 0, hi = nb;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (b[mid] < y) lo = mid + 1;
-            else hi = mid;
+    // the base's keys, RD_FOLD_U per thread at a time: their loads issued
+    // together, then their places in the delta found in lockstep (a
+    // fixed-step lower bound, the U searches' LDS reads interleaved)
+    uint32_t pw = 1;
+    while (pw <= nb) pw <<= 1;
+    for (uint32_t i0 = t; i0 < na; i0 += RD_BLOCK * RD_FOLD_U) {
+        unsigned long long y[RD_FOLD_U];
+        uint32_t lo[RD_FOLD_U];
+#pragma unroll
+        for (int u = 0; u < RD_FOLD_U; u++) {
+            const uint32_t i = i0 + (uint32_t)u * RD_BLOCK;
+            y[u] = i < na ? (lg ? a[i] : smp[i]) : 0ull;
+            lo[u] = 0;
         }
-        if (lo < nb && b[lo] == y) continue;
-        const uint32_t mex = lo ? minc[lo - 1] : 0u;
-        dst[i + lo - 2 * mex] = y;
+        for (uint32_t step = pw >> 1; step > 0; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < RD_FOLD_U; u++) {
+                const uint32_t c = lo[u] + step;  // lo[u] = keys of b below y[u] so far
+                if (c <= nb && b[c - 1] < y[u]) lo[u] = c;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RD_FOLD_U; u++) {
+            const uint32_t i = i0 + (uint32_t)u * RD_BLOCK;
+            if (i >= na || (lo[u] < nb && b[lo[u]] == y[u])) continue;
+            const uint32_t mex = lo[u] ? minc[lo[u] - 1] : 0u;
+            dst[i + lo[u] - 2 * mex] = y[u];
+        }
     }
     __threadfence_block();
     __syncthreads();
