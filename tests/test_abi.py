@@ -267,3 +267,14 @@ def test_tetra_counts_argument_checks():
     assert L.vr_tetra_counts(ctypes.byref(r), None, None) == vr.VR_OK
     r = vr.VrResult(10, 4, 0, None, None, None)
     assert L.vr_tetra_counts(ctypes.byref(r), None, None) == vr.VR_EINVAL
+
+
+def test_persistence_rejects_other_dimensions():
+    """The chained call takes maxdim 2 or 3 and refuses others before any
+    device work."""
+    import torch
+
+    pts = torch.zeros((4, 2), dtype=torch.int32)
+    for bad in (1, 4):
+        with pytest.raises(ValueError):
+            vr.persistence(pts, ("full", 0, 1), maxdim=bad)
