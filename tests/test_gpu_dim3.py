@@ -242,3 +242,29 @@ def test_persistence_chain_matches_oracle_barcode(orc, maxdim):
     got = sorted(tuple(int(x) for x in b) for b in out["bars"].cpu().numpy())
     assert got == sorted(b for b in want if b[0] < maxdim)
     assert out["essential_top"] == sum(1 for b in want if b[0] == maxdim)
+
+
+@pytest.mark.parametrize("maxdim", [2, 3])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 6])
+def test_persistence_tiny_clouds(orc, n, maxdim):
+    """The chained call on clouds with no edge, no triangle or no
+    tetrahedron (full threshold): the oracle's barcode, and the counts."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    c = workloads.uniform_cloud(400 + n, n, 3, thr=("full", 0, 1))
+    print(f"[gpu] persistence n={n} maxdim={maxdim}", flush=True)
+    out = vr.persistence(torch.from_numpy(np.ascontiguousarray(c.points)).to("cuda:0"), c.thr, maxdim=maxdim)
+    f = orc.build(c.points, c.thr)
+    p = orc.reduce(f, "cohomology")
+    if maxdim == 3:
+        tets = orc.tetra_list(f)
+        want = orc.barcode(f, orc.with_dim2(f, p, tets), tets)
+        assert out["counts"] == f.counts + (len(tets),)
+    else:
+        want = orc.barcode(f, p)
+        assert out["counts"] == f.counts
+    got = sorted(tuple(int(x) for x in b) for b in out["bars"].cpu().numpy())
+    assert got == sorted(b for b in want if b[0] < maxdim)
+    assert out["essential_top"] == sum(1 for b in want if b[0] == maxdim)
