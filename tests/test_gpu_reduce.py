@@ -130,6 +130,29 @@ def test_pairs_dim1_of_batch_items(orc):
     b.free()
 
 
+@pytest.mark.parametrize("n,thr", [(120, ("fraction", 20, 100)), (300, ("fraction", 6, 100))])
+def test_pairs_dim1_of_a_matrix_build(orc, n, thr):
+    """The pairs and barcode of a build from a Hamming dissimilarity matrix
+    (ties everywhere: the edge order falls back to (i, j)) equal the
+    oracle's."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    M = workloads.hamming_matrix(90 + n, n)
+    print(f"[gpu] pairs_dim1 hamming matrix n={n} thr={thr}", flush=True)
+    r = vr.build_matrix(torch.from_numpy(M).to("cuda:0"), thr)
+    e_low, toe, bars, ess2 = _device_pairs(r)
+    f = orc.build_matrix(M, thr)
+    p = orc.reduce(f, "cohomology")
+    assert np.array_equal(e_low, p.e_low)
+    assert np.array_equal(toe, _oracle_tri_of_edge(p, f.K))
+    want = orc.barcode(f, p)
+    assert sorted(tuple(int(x) for x in b) for b in bars) == sorted(b for b in want if b[0] < 2)
+    assert ess2 == sum(1 for b in want if b[0] == 2)
+    r.free()
+
+
 def test_mixture4000_reduction_properties(orc):
     """The 4000-point mixture (94 million triangles, beyond the oracle's
     reduction): H0 pairs equal the oracle's spanning-forest edges, every
