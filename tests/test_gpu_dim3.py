@@ -90,6 +90,38 @@ def test_maxdim3_build_and_dim2_pairs(orc, name, gen, thr):
     r.free()
 
 
+def test_maxdim3_matrix_build_and_dim2_pairs(orc):
+    """A maxdim-3 build from a Hamming dissimilarity matrix (ties broken by
+    index throughout): the tetrahedra and the pairs and barcode of
+    dimension 2 equal the oracle's."""
+    import torch
+
+    import paper_1809_04424_amd as vr
+
+    M = workloads.hamming_matrix(211, 90)
+    thr = ("fraction", 12, 100)
+    print("[gpu] maxdim-3 matrix build n=90", flush=True)
+    r = vr.build_matrix(torch.from_numpy(M).to("cuda:0"), thr, maxdim=3)
+    f = orc.build_matrix(M, thr)
+    tets = orc.tetra_list(f)
+    assert r.counts == f.counts and r.T3 == len(tets)
+    assert np.array_equal(r.tet_key().cpu().numpy(), _tet_rows_as_keys(tets))
+    e_low, _ = vr.pairs_dim0(r)
+    toe = vr.pairs_dim1(r, e_low)
+    tt = vr.pairs_dim2(r, toe)
+    bars, ess3 = vr.barcode_dim2(r, toe, tt)
+    torch.cuda.synchronize()
+    p1 = orc.reduce(f, "cohomology")
+    q_low = orc.reduce_dim2(f, tets, "cohomology", p1.t_low)
+    want = np.full(f.T, -1, np.int64)
+    want[q_low[q_low >= 0]] = np.nonzero(q_low >= 0)[0]
+    assert np.array_equal(tt.cpu().numpy(), want)
+    wb = orc.barcode(f, orc.with_dim2(f, p1, tets), tets)
+    assert sorted(tuple(int(x) for x in b) for b in bars.cpu().numpy()) == sorted(b for b in wb if b[0] == 2)
+    assert ess3 == sum(1 for b in wb if b[0] == 3)
+    r.free()
+
+
 def test_maxdim3_count_only_and_torch_allocator(orc):
     """Count-only lists no tetrahedra but still gives their offsets; the
     torch allocator's blocks hold the same arrays as the library's cache."""
